@@ -1,0 +1,243 @@
+/*
+ * mhs.h -- C ABI of libmhs, a gfx950 (MI355X) multigrid solver for the
+ * poloidal potential P of the NR99 linear magnetohydrostatic model, as
+ * reduced to scalar elliptic problems in Section 2.2 of MacTaggart et al.,
+ * "Non-symmetric magnetohydrostatic equilibria: a multigrid approach".
+ *
+ * Problems solved (second-order central differences, uniform grid):
+ *   lower boundary, equation (11):  P_xx + P_yy = -Bz0(x, y) on z = 0,
+ *                                   P = 0 on the edges of the base;
+ *   interior, equation (8):  (1 - xi(z)) (P_xx + P_yy) + P_zz + alpha^2 P = 0,
+ *                            P(z=0) from (11), P = 0 on top and side faces;
+ * then B from equation (5) with T = alpha P (6), p from (9), rho from (10).
+ *
+ * Conventions shared by every entry point
+ *   Grid.     nx, ny, nz nodes per axis, each 2^L + 1 with L >= 2; node
+ *             spacing d = l / (n - 1); nodes run from 0 to l inclusive.
+ *   Layout.   every 3D array is contiguous, x fastest:
+ *             idx = i + nx * (j + ny * k)  (a torch tensor of shape
+ *             (nz, ny, nx)); 2D arrays are (ny, nx), x fastest.
+ *   Memory.   "d_" pointers are device pointers on the plan's device,
+ *             owned by the caller.  Model arrays (xi, dxi, pb, rhob) are
+ *             host pointers of length nz, copied during the call.
+ *   Streams.  `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *             stream-ordered.  The solve entry points return once the
+ *             stopping rule has been decided (they read back an 8-byte
+ *             status); mhs_fields and the stage entry points are
+ *             asynchronous.  A plan must not be used by two calls at once.
+ *   Errors.   every function returns 0 (MHS_OK) or a positive MHS_ERR_*
+ *             code; nothing throws across the ABI.  mhs_last_error()
+ *             returns a thread-local message for the last failure.
+ *
+ * The library allocates no device memory: the caller passes a workspace
+ * of mhs_workspace_bytes() bytes to mhs_plan_create(), and the plan owns
+ * that memory's contents until mhs_plan_destroy().  Host-side plan
+ * structures and a small pinned status buffer are allocated by
+ * mhs_plan_create().
+ */
+#ifndef MHS_H
+#define MHS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define MHS_OK 0
+#define MHS_ERR_INVALID_ARG 1    /* null pointer, bad option value          */
+#define MHS_ERR_GRID 2           /* an axis is not 2^L+1 nodes, or too small */
+#define MHS_ERR_NOT_ELLIPTIC 3   /* xi(z_k) >= 1 at an interior plane (8)   */
+#define MHS_ERR_INDEFINITE 4     /* alpha^2 too close to the spectrum of (8) */
+#define MHS_ERR_NO_CONVERGENCE 5 /* max_cycles reached; P holds last iterate */
+#define MHS_ERR_DIVERGED 6       /* residual non-finite or grew tenfold     */
+#define MHS_ERR_BUDGET 7         /* serving: no slot or workspace too small */
+#define MHS_ERR_WORKSPACE 8      /* workspace too small or misaligned       */
+#define MHS_ERR_HIP 9            /* a HIP runtime call failed               */
+#define MHS_ERR_UNSUPPORTED 10   /* option combination not built            */
+
+/* ---- precisions (bit mask for plans, single value for a solve) -------- */
+#define MHS_PREC_FP64 1  /* FP64 V(nu1,nu2) cycles                          */
+#define MHS_PREC_MIXED 2 /* FP32 V-cycles inside FP64 iterative refinement  */
+
+typedef struct mhs_grid {
+    int32_t nx, ny, nz; /* nodes per axis, each 2^L + 1, L >= 2            */
+    double lx, ly, lz;  /* box lengths (> 0)                               */
+} mhs_grid;
+
+typedef struct mhs_model {
+    double alpha;      /* the constant of the field-aligned current (4)    */
+    const double *xi;  /* host, nz values: xi(z_k), cross-field profile    */
+    const double *dxi; /* host, nz values: dxi/dz at z_k (for (10))        */
+    const double *pb;  /* host, nz values: background pressure p_b(z_k)    */
+    const double *rhob;/* host, nz values: background density rho_b(z_k)   */
+    double mu0;        /* permeability in the units of the model (> 0)     */
+    double g;          /* gravitational acceleration (> 0)                 */
+} mhs_model;
+
+typedef struct mhs_opts {
+    int32_t precision;    /* MHS_PREC_FP64 or MHS_PREC_MIXED (interior only) */
+    int32_t max_cycles;   /* cap on V-cycles (FP64) or refinement steps     */
+    double rtol;          /* stop when ||r||_2 / ||r_0||_2 <= rtol          */
+    int32_t nu1, nu2;     /* pre/post red-black Gauss-Seidel sweeps (>= 1)  */
+    int32_t inner_cycles; /* FP32 V-cycles per refinement step (mixed)      */
+    int32_t warm_start;   /* 1: use P's interior as the initial guess       */
+    int32_t check_every;  /* cycles launched between host status reads; 0 = adaptive */
+    int32_t reserved;
+} mhs_opts;
+
+typedef struct mhs_info {
+    int32_t status;       /* MHS_OK or an MHS_ERR_* code                    */
+    int32_t cycles;       /* V-cycles (FP64) / refinement steps (mixed)     */
+    int32_t inner_cycles; /* total FP32 V-cycles (mixed path)               */
+    int32_t host_syncs;   /* status read-backs performed                    */
+    double rel_residual;  /* final ||r||_2 / ||r_0||_2                      */
+    double r0;            /* ||r_0||_2                                      */
+    double seconds;       /* wall time of the call                          */
+} mhs_info;
+
+typedef struct mhs_plan mhs_plan;
+
+/* Fill *opts with defaults: FP64, V(2,2), rtol 1e-10, max_cycles 100,
+ * inner_cycles 1, check_every 0 (adaptive). */
+void mhs_default_opts(mhs_opts *opts);
+
+/* Library version as 10000*major + 100*minor + patch. */
+int32_t mhs_version(void);
+
+/* Message describing the last failure on this thread ("" if none). */
+const char *mhs_last_error(void);
+
+/* Bytes of device workspace a plan for `grid` needs.  `precisions` is a
+ * bit mask of MHS_PREC_* paths the plan must support.  Validates the grid
+ * (MHS_ERR_GRID for a bad axis). */
+int mhs_workspace_bytes(const mhs_grid *grid, int32_t precisions, size_t *bytes);
+
+/* Create a plan on the current HIP device over the caller's workspace
+ * (d_workspace: device pointer, 256-byte aligned, >= mhs_workspace_bytes).
+ * Clears the workspace (synchronously).  The hierarchy coarsens every axis
+ * together while all axes exceed 3 nodes; the coarsest grid is solved
+ * exactly. */
+int mhs_plan_create(const mhs_grid *grid, int32_t precisions, void *d_workspace,
+                    size_t workspace_bytes, mhs_plan **plan);
+
+/* Release the plan's host resources (not the caller's workspace). */
+int mhs_plan_destroy(mhs_plan *plan);
+
+/* Number of 3D (space = 3) or 2D (space = 2) multigrid levels of the plan,
+ * and the node counts of level `level` (0 = finest). */
+int mhs_plan_levels(const mhs_plan *plan, int32_t space, int32_t *nlevels);
+int mhs_plan_level_dims(const mhs_plan *plan, int32_t space, int32_t level, int32_t *nx,
+                        int32_t *ny, int32_t *nz);
+
+/* First level (0 = finest) handled by the single-workgroup bottom solver,
+ * which runs whole V-cycles from that level down to the coarsest grid. */
+int mhs_plan_bottom_level(const mhs_plan *plan, int32_t space, int32_t *level);
+
+/* Step 2 of the procedure of Section 2.2: multigrid solve of equation (11).
+ * d_bz0: device, nx*ny doubles (edge values are not read).  d_P: device,
+ * nx*ny*nz doubles; plane k = 0 (its first nx*ny doubles) receives P0 with
+ * zero edges; the other planes are not touched.  Initial guess 0 unless
+ * opts->warm_start.  Always FP64.  On MHS_ERR_NO_CONVERGENCE plane 0 holds
+ * the last iterate and *info is filled. */
+int mhs_solve_boundary(mhs_plan *plan, const double *d_bz0, double *d_P, const mhs_opts *opts,
+                       mhs_info *info, void *stream);
+
+/* Step 3 of the procedure: multigrid solve of equation (8) in place.  Plane
+ * k = 0 of d_P is the Dirichlet data from mhs_solve_boundary; the side and
+ * top faces are set to 0; the interior starts from 0 (step 1) unless
+ * opts->warm_start.  opts->precision selects plain FP64 V-cycles or FP32
+ * V-cycles inside FP64 iterative refinement (fine residual, update and the
+ * coarsest solve in FP64).  Validates xi < 1 on interior planes
+ * (MHS_ERR_NOT_ELLIPTIC) and definiteness (MHS_ERR_INDEFINITE) first. */
+int mhs_solve_interior(mhs_plan *plan, const mhs_model *model, double *d_P, const mhs_opts *opts,
+                       mhs_info *info, void *stream);
+
+/* Field recovery (Section 2.2, equations (5), (6), (9), (10)) by central
+ * differences: Bx = alpha P_y + P_xz, By = -alpha P_x + P_yz,
+ * Bz = -(P_xx + P_yy), p = p_b - xi Bz^2/(2 mu0),
+ * rho = rho_b + (xi' Bz^2/(2 mu0) + xi B.grad(Bz)/mu0)/g.
+ * Faces: B = 0 on the side and top faces (so p = p_b, rho = rho_b there);
+ * on the base the z-derivatives are one-sided second order.  All outputs
+ * nx*ny*nz doubles on the device.  Asynchronous. */
+int mhs_fields(mhs_plan *plan, const mhs_model *model, const double *d_P, double *d_Bx,
+               double *d_By, double *d_Bz, double *d_p, double *d_rho, void *stream);
+
+/* ---- stage entry points (kernel-level checks; asynchronous) ----------- *
+ * `space` is 3 (equation (8) at 3D level `level`) or 2 (equation (11) at
+ * 2D level `level`); `precision` is MHS_PREC_FP64 (double arrays) or
+ * MHS_PREC_MIXED (float arrays, the inner solver's storage).  Arrays have
+ * the level's shape; boundary nodes of u are its Dirichlet values.  For
+ * space 3 the model supplies xi and alpha; for space 2 it may be NULL.
+ * The coarse coefficients use xi sampled at the coarse nodes.  These run
+ * the same kernels as the solves. */
+
+/* u <- nsweeps red-black Gauss-Seidel sweeps on A u = f (f may be NULL:
+ * zero).  Red = (i+j+k) even, updated first. */
+int mhs_stage_smooth(mhs_plan *plan, const mhs_model *model, int32_t space, int32_t level,
+                     int32_t precision, void *d_u, const void *d_f, int32_t nsweeps,
+                     void *stream);
+
+/* f_c <- full weighting of r = f - A u (r = 0 on boundary nodes) onto the
+ * interior nodes of level+1; boundary nodes of f_c are not written. */
+int mhs_stage_restrict(mhs_plan *plan, const mhs_model *model, int32_t space, int32_t level,
+                       int32_t precision, const void *d_u, const void *d_f, void *d_fc,
+                       void *stream);
+
+/* u <- one red-black sweep applied to u + I(e_c), where I is trilinear
+ * (bilinear in 2D) interpolation from level+1, added on interior nodes only. */
+int mhs_stage_correct_smooth(mhs_plan *plan, const mhs_model *model, int32_t space,
+                             int32_t level, int32_t precision, void *d_u, const void *d_f,
+                             const void *d_ec, void *stream);
+
+/* u <- one V(nu1,nu2) cycle, starting from u = 0, on A u = f over the
+ * plan's bottom levels (from level mhs_plan_bottom_level() to the coarsest,
+ * which is solved exactly).  u and f must have the shape of that level;
+ * *bottom_level (may be NULL) receives it.  Computed in FP64 whatever the
+ * storage precision. */
+int mhs_stage_bottom(mhs_plan *plan, const mhs_model *model, int32_t space, int32_t precision,
+                     void *d_u, const void *d_f, int32_t nu1, int32_t nu2,
+                     int32_t *bottom_level, void *stream);
+
+/* *norm <- ||f - A u||_2 over interior nodes of the level (synchronous). */
+int mhs_stage_residual_norm(mhs_plan *plan, const mhs_model *model, int32_t space,
+                            int32_t level, int32_t precision, const void *d_u, const void *d_f,
+                            double *norm, void *stream);
+
+/* ---- continuous batching (serving) ------------------------------------ *
+ * A batch advances many independent solves together: each tick runs, for
+ * every active slot, one V-cycle of its current phase (boundary solve, then
+ * interior solve, then fields), and launches each stage of the tick once
+ * for all slots (descriptor-driven kernels).  Slots hold a plan, device
+ * buffers and options; admission policy (memory budget, queueing) belongs
+ * to the caller. */
+typedef struct mhs_batch mhs_batch;
+
+int mhs_batch_create(int32_t max_slots, mhs_batch **batch);
+int mhs_batch_destroy(mhs_batch *batch);
+
+/* Admit one request into a free slot (MHS_ERR_BUDGET if none).  The plan
+ * (exclusive to this slot while it is active), d_bz0, d_P and the five
+ * field outputs must stay valid until the slot is released.  Model arrays
+ * are copied.  opts->precision selects the interior path. */
+int mhs_batch_admit(mhs_batch *batch, mhs_plan *plan, const mhs_model *model,
+                    const double *d_bz0, double *d_P, double *d_Bx, double *d_By, double *d_Bz,
+                    double *d_p, double *d_rho, const mhs_opts *opts, int32_t *slot);
+
+/* One tick on `stream`; blocks until the tick's status read-back.
+ * *active receives the number of slots still running after the tick. */
+int mhs_batch_step(mhs_batch *batch, void *stream, int32_t *active);
+
+/* Status of a slot: *done = 1 once its fields are written (info filled). */
+int mhs_batch_poll(mhs_batch *batch, int32_t slot, int32_t *done, mhs_info *info);
+
+/* Free a slot (finished or not) for reuse. */
+int mhs_batch_release(mhs_batch *batch, int32_t slot);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MHS_H */

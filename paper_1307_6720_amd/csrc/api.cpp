@@ -1,0 +1,1234 @@
+// C-ABI of libmhs: plans, validation, coefficient tables, the coarsest-grid
+// inverse, V-cycle programs and the solve drivers.
+//
+// The procedure follows Section 2.2: P = 0 everywhere (step 1), multigrid on
+// the lower-boundary equation (11) (step 2), multigrid on the interior
+// equation (8) with the base plane as Dirichlet data (step 3), then the field
+// recovery of equations (5), (6), (9), (10).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "plan.h"
+
+using namespace mhs;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail(MHS_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr size_t kStagingBytes = 1 << 20;
+constexpr size_t kBottomMax3 = 5000; // 3D levels this small go to the single-workgroup solver
+constexpr size_t kBottomMax2 = 4300; // 2D likewise (65 x 65)
+
+struct Carver {
+    char *base;
+    size_t off = 0;
+    template <typename T>
+    T *take(size_t count)
+    {
+        off = (off + kAlign - 1) & ~(kAlign - 1);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+bool valid_axis(int n)
+{
+    if (n < 5) return false;
+    const int m = n - 1;
+    return (m & (m - 1)) == 0;
+}
+
+int check_grid(const mhs_grid *g)
+{
+    if (!g) return fail(MHS_ERR_INVALID_ARG, "grid is NULL");
+    if (!valid_axis(g->nx) || !valid_axis(g->ny) || !valid_axis(g->nz))
+        return fail(MHS_ERR_GRID, "every axis needs 2^L+1 nodes with L >= 2 (got %d x %d x %d)", g->nx, g->ny,
+                    g->nz);
+    if (!(g->lx > 0 && g->ly > 0 && g->lz > 0) || !std::isfinite(g->lx) || !std::isfinite(g->ly) ||
+        !std::isfinite(g->lz))
+        return fail(MHS_ERR_INVALID_ARG, "box lengths must be positive and finite");
+    const double npts = (double)g->nx * g->ny * g->nz;
+    if (npts > 2.0e9) return fail(MHS_ERR_GRID, "grid too large (%g nodes)", npts);
+    return MHS_OK;
+}
+
+// Geometry of a hierarchy (no buffers): coarsen every axis together while all
+// axes exceed 3 nodes.
+int build_geometry(Hierarchy &h, const int n0[3], const double len[3], bool planar)
+{
+    h = Hierarchy();
+    h.planar = planar;
+    int n[3] = {n0[0], n0[1], planar ? 1 : n0[2]};
+    int L = 0;
+    for (;;) {
+        if (L >= kMaxLevels) return fail(MHS_ERR_GRID, "too many levels");
+        Level &lv = h.lv[L];
+        for (int a = 0; a < 3; ++a) lv.n[a] = n[a];
+        lv.h[0] = len[0] / (n[0] - 1);
+        lv.h[1] = len[1] / (n[1] - 1);
+        lv.h[2] = planar ? 1.0 : len[2] / (n[2] - 1);
+        lv.N = (size_t)n[0] * n[1] * n[2];
+        ++L;
+        const bool more = planar ? (n[0] > 3 && n[1] > 3) : (n[0] > 3 && n[1] > 3 && n[2] > 3);
+        if (!more) break;
+        n[0] = (n[0] - 1) / 2 + 1;
+        n[1] = (n[1] - 1) / 2 + 1;
+        if (!planar) n[2] = (n[2] - 1) / 2 + 1;
+    }
+    h.L = L;
+    if (L < 2) return fail(MHS_ERR_GRID, "grid too small for multigrid");
+    const Level &c = h.lv[L - 1];
+    h.m = (c.n[0] - 2) * (c.n[1] - 2) * (planar ? 1 : c.n[2] - 2);
+    if (h.m > kMaxCoarse)
+        return fail(MHS_ERR_GRID, "coarsest grid has %d unknowns (max %d): axes too unequal", h.m, kMaxCoarse);
+    const size_t bmax = planar ? kBottomMax2 : kBottomMax3;
+    h.b = L - 1;
+    for (int l = 1; l < L; ++l)
+        if (h.lv[l].N <= bmax) {
+            h.b = l;
+            break;
+        }
+    for (int l = 0; l < L; ++l) {
+        Level &lv = h.lv[l];
+        if (planar) {
+            lv.st[0] = ceil_div(lv.n[0] - 2, kTX);
+            lv.st[1] = ceil_div(lv.n[1] - 2, kTY2);
+            lv.st[2] = 1;
+        } else {
+            lv.st[0] = ceil_div(lv.n[0] - 2, kTX);
+            lv.st[1] = ceil_div(lv.n[1] - 2, kTY);
+            lv.st[2] = ceil_div(lv.n[2] - 2, kKZ);
+        }
+        if (l + 1 < L) {
+            const Level &c2 = h.lv[l + 1];
+            lv.rt[0] = ceil_div(c2.n[0] - 2, kCX);
+            lv.rt[1] = ceil_div(c2.n[1] - 2, kCY);
+            lv.rt[2] = planar ? 1 : ceil_div(c2.n[2] - 2, kKC);
+        }
+    }
+    return MHS_OK;
+}
+
+// Lay out the buffers of a hierarchy.  paths: bit 0 = FP64 cycles, bit 1 =
+// FP32 inner cycles.  Level 0's iterate is the caller's array (set per call);
+// its twin is allocated whenever any path exists.
+void carve_hierarchy(Hierarchy &h, Carver &cv, int paths)
+{
+    const int L = h.L, b = h.b;
+    Level &l0 = h.lv[0];
+    l0.t[kF64] = cv.take<double>(l0.N);
+    if (h.planar) l0.f[kF64] = cv.take<double>(l0.N);
+    for (int p = 0; p < 2; ++p) {
+        if (!(paths & (1 << p))) continue;
+        const size_t es = p == kF64 ? sizeof(double) : sizeof(float);
+        if (p == kF32) {
+            l0.u[kF32] = cv.take<char>(l0.N * es);
+            l0.t[kF32] = cv.take<char>(l0.N * es);
+            l0.f[kF32] = cv.take<char>(l0.N * es);
+        }
+        for (int l = 1; l <= b; ++l) {
+            Level &lv = h.lv[l];
+            lv.u[p] = cv.take<char>(lv.N * es);
+            lv.f[p] = cv.take<char>(lv.N * es);
+            if (l < b) lv.t[p] = cv.take<char>(lv.N * es);
+        }
+    }
+    for (int l = 0; l < L; ++l) {
+        Level &lv = h.lv[l];
+        lv.coef64 = cv.take<double>(4 * (size_t)lv.n[2]);
+        if (paths & 2) lv.coef32 = cv.take<float>(4 * (size_t)lv.n[2]);
+    }
+    for (int l = b; l < L; ++l) {
+        h.bu[l] = cv.take<double>(h.lv[l].N);
+        h.bf[l] = cv.take<double>(h.lv[l].N);
+    }
+    h.br = cv.take<double>(h.lv[b].N);
+    h.minv = cv.take<double>((size_t)h.m * h.m);
+    h.npart = l0.sweep_tiles();
+    h.partials = cv.take<double>(h.npart);
+}
+
+size_t carve_plan(mhs_plan *p, char *base, int precisions)
+{
+    Carver cv{base};
+    int paths = 0;
+    if (precisions & MHS_PREC_FP64) paths |= 1;
+    if (precisions & MHS_PREC_MIXED) paths |= 2;
+    carve_hierarchy(p->h3, cv, paths);
+    carve_hierarchy(p->h2, cv, 1);
+    p->d_fields_tab = cv.take<double>(4 * (size_t)p->grid.nz);
+    p->scratch_npart = std::max(p->h3.npart, p->h2.npart);
+    p->d_scratch_norm = cv.take<double>(p->scratch_npart);
+    p->stage.dev = cv.take<char>(kStagingBytes);
+    p->stage.cap = kStagingBytes;
+    return cv.off + kAlign;
+}
+
+int geometry(mhs_plan *p, const mhs_grid *g)
+{
+    p->grid = *g;
+    const int n0[3] = {g->nx, g->ny, g->nz};
+    const double len[3] = {g->lx, g->ly, g->lz};
+    int st = build_geometry(p->h3, n0, len, false);
+    if (st) return st;
+    return build_geometry(p->h2, n0, len, true);
+}
+
+// ---- coefficient tables and the coarsest-grid inverse --------------------------
+
+// cx_k = (1 - xi_k)/dx^2, cy_k = (1 - xi_k)/dy^2, d_k = alpha^2 - 2cx - 2cy - 2cz
+// (equation (8) at level l, xi sampled at the level's nodes: xi_l[k] = xi[k 2^l]).
+void level_coef(const Hierarchy &h, int l, double alpha, const double *xi, std::vector<double> &out,
+                double &cz)
+{
+    const Level &lv = h.lv[l];
+    const int nz = lv.n[2];
+    out.assign(4 * (size_t)nz, 0.0);
+    const double ix2 = 1.0 / (lv.h[0] * lv.h[0]), iy2 = 1.0 / (lv.h[1] * lv.h[1]);
+    cz = h.planar ? 0.0 : 1.0 / (lv.h[2] * lv.h[2]);
+    for (int k = 0; k < nz; ++k) {
+        const double x = h.planar ? 0.0 : xi[(size_t)k << l];
+        const double cx = (1.0 - x) * ix2, cy = (1.0 - x) * iy2;
+        const double a2 = h.planar ? 0.0 : alpha * alpha;
+        const double d = a2 - 2.0 * cx - 2.0 * cy - 2.0 * cz;
+        out[4 * k] = cx;
+        out[4 * k + 1] = cy;
+        out[4 * k + 2] = d;
+        out[4 * k + 3] = 1.0 / d;
+    }
+}
+
+// Inverse of the coarsest operator A (m x m, interior nodes x fastest) by
+// Cholesky of -A (which is symmetric positive definite when (8) is definite
+// on that grid) followed by triangular solves against the identity.
+int coarse_inverse(const Hierarchy &h, const std::vector<double> &coef, double cz, std::vector<double> &minv)
+{
+    const Level &c = h.lv[h.L - 1];
+    const int mx = c.n[0] - 2, my = c.n[1] - 2, mz = h.planar ? 1 : c.n[2] - 2;
+    const int m = mx * my * mz;
+    std::vector<double> M((size_t)m * m, 0.0); // -A
+    for (int kk = 0; kk < mz; ++kk)
+        for (int jj = 0; jj < my; ++jj)
+            for (int ii = 0; ii < mx; ++ii) {
+                const int r = ii + mx * (jj + my * kk);
+                const int k = h.planar ? 0 : kk + 1;
+                const double cx = coef[4 * k], cy = coef[4 * k + 1], d = coef[4 * k + 2];
+                M[(size_t)r * m + r] = -d;
+                if (ii > 0) M[(size_t)r * m + r - 1] = -cx;
+                if (ii + 1 < mx) M[(size_t)r * m + r + 1] = -cx;
+                if (jj > 0) M[(size_t)r * m + r - mx] = -cy;
+                if (jj + 1 < my) M[(size_t)r * m + r + mx] = -cy;
+                if (kk > 0) M[(size_t)r * m + r - mx * my] = -cz;
+                if (kk + 1 < mz) M[(size_t)r * m + r + mx * my] = -cz;
+            }
+    // Cholesky M = G G^T (lower G stored in M)
+    for (int j = 0; j < m; ++j) {
+        double s = M[(size_t)j * m + j];
+        for (int q = 0; q < j; ++q) s -= M[(size_t)j * m + q] * M[(size_t)j * m + q];
+        if (!(s > 0.0))
+            return fail(MHS_ERR_INDEFINITE, "coarsest operator is not definite: alpha^2 too large for this box");
+        const double g = std::sqrt(s);
+        M[(size_t)j * m + j] = g;
+        for (int i = j + 1; i < m; ++i) {
+            double t = M[(size_t)i * m + j];
+            for (int q = 0; q < j; ++q) t -= M[(size_t)i * m + q] * M[(size_t)j * m + q];
+            M[(size_t)i * m + j] = t / g;
+        }
+    }
+    minv.assign((size_t)m * m, 0.0);
+    std::vector<double> y(m);
+    for (int col = 0; col < m; ++col) {
+        for (int i = 0; i < m; ++i) {
+            double s = (i == col) ? 1.0 : 0.0;
+            for (int q = 0; q < i; ++q) s -= M[(size_t)i * m + q] * y[q];
+            y[i] = s / M[(size_t)i * m + i];
+        }
+        for (int i = m - 1; i >= 0; --i) {
+            double s = y[i];
+            for (int q = i + 1; q < m; ++q) s -= M[(size_t)q * m + i] * y[q];
+            y[i] = s / M[(size_t)i * m + i];
+        }
+        // A^{-1} = -(-A)^{-1}
+        for (int i = 0; i < m; ++i) minv[(size_t)i * m + col] = -y[i];
+    }
+    return MHS_OK;
+}
+
+// Lower bound of the smallest eigenvalue of -[(1 - xi)(d2x + d2y) + d2z] on
+// level l: min_k (1 - xi_k) * lam_h + lam_z, each term the smallest Dirichlet
+// eigenvalue of its one-dimensional operator.
+double definite_bound(const Hierarchy &h, int l, const double *xi, const double len[3])
+{
+    const Level &lv = h.lv[l];
+    auto lam1 = [](int n, double hh, double length) {
+        const double s = std::sin(3.14159265358979323846 * hh / (2.0 * length));
+        return 4.0 / (hh * hh) * s * s;
+    };
+    const double lh = lam1(lv.n[0], lv.h[0], len[0]) + lam1(lv.n[1], lv.h[1], len[1]);
+    const double lz = lam1(lv.n[2], lv.h[2], len[2]);
+    double mn = 1.0;
+    for (int k = 1; k < lv.n[2] - 1; ++k) mn = std::min(mn, 1.0 - xi[(size_t)k << l]);
+    return mn * lh + lz;
+}
+
+int upload_model(mhs_plan *p, const mhs_model *model, hipStream_t s)
+{
+    const int nz = p->grid.nz;
+    Hierarchy &h = p->h3;
+    const bool same = p->cache.valid && p->cache.alpha == model->alpha &&
+                      std::equal(p->cache.xi.begin(), p->cache.xi.end(), model->xi);
+    if (same) return MHS_OK;
+    const double len[3] = {p->grid.lx, p->grid.ly, p->grid.lz};
+    for (int l = 0; l < h.L; ++l) {
+        const double bound = definite_bound(h, l, model->xi, len);
+        if (!(model->alpha * model->alpha < bound))
+            return fail(MHS_ERR_INDEFINITE, "alpha^2 = %g is not below the spectral bound %g of level %d", model->alpha * model->alpha,
+                        bound, l);
+    }
+    std::vector<double> tab, minv;
+    std::vector<float> t32;
+    for (int l = 0; l < h.L; ++l) {
+        double cz = 0.0;
+        level_coef(h, l, model->alpha, model->xi, tab, cz);
+        h.lv[l].cz = cz;
+        HIPCHK(hipMemcpyAsync(h.lv[l].coef64, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        if (h.lv[l].coef32) {
+            t32.assign(tab.begin(), tab.end());
+            HIPCHK(hipMemcpyAsync(h.lv[l].coef32, t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice, s));
+        }
+        if (l == h.L - 1) {
+            int st = coarse_inverse(h, tab, cz, minv);
+            if (st) return st;
+            HIPCHK(hipMemcpyAsync(h.minv, minv.data(), minv.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        }
+    }
+    // pageable sources: make sure the copies have consumed them before return
+    HIPCHK(hipStreamSynchronize(s));
+    p->cache.valid = true;
+    p->cache.alpha = model->alpha;
+    p->cache.xi.assign(model->xi, model->xi + nz);
+    return MHS_OK;
+}
+
+int upload_planar(mhs_plan *p, hipStream_t s)
+{
+    Hierarchy &h = p->h2;
+    std::vector<double> tab, minv;
+    for (int l = 0; l < h.L; ++l) {
+        double cz = 0.0;
+        level_coef(h, l, 0.0, nullptr, tab, cz);
+        h.lv[l].cz = 0.0;
+        HIPCHK(hipMemcpyAsync(h.lv[l].coef64, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        if (l == h.L - 1) {
+            int st = coarse_inverse(h, tab, 0.0, minv);
+            if (st) return st;
+            HIPCHK(hipMemcpyAsync(h.minv, minv.data(), minv.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        }
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return MHS_OK;
+}
+
+int validate_model(const mhs_plan *p, const mhs_model *m, bool need_fields)
+{
+    if (!m || !m->xi) return fail(MHS_ERR_INVALID_ARG, "model or model->xi is NULL");
+    if (!std::isfinite(m->alpha)) return fail(MHS_ERR_INVALID_ARG, "alpha is not finite");
+    const int nz = p->grid.nz;
+    for (int k = 0; k < nz; ++k)
+        if (!std::isfinite(m->xi[k])) return fail(MHS_ERR_INVALID_ARG, "xi[%d] is not finite", k);
+    for (int k = 1; k < nz - 1; ++k)
+        if (!(m->xi[k] < 1.0))
+            return fail(MHS_ERR_NOT_ELLIPTIC, "xi(z_%d) = %g >= 1: equation (8) is not elliptic", k, m->xi[k]);
+    if (need_fields) {
+        if (!m->dxi || !m->pb || !m->rhob) return fail(MHS_ERR_INVALID_ARG, "dxi, pb and rhob are required");
+        if (!(m->mu0 > 0.0) || !(m->g > 0.0)) return fail(MHS_ERR_INVALID_ARG, "mu0 and g must be positive");
+        for (int k = 0; k < nz; ++k)
+            if (!std::isfinite(m->dxi[k]) || !std::isfinite(m->pb[k]) || !std::isfinite(m->rhob[k]))
+                return fail(MHS_ERR_INVALID_ARG, "non-finite model table entry at k = %d", k);
+    }
+    return MHS_OK;
+}
+
+int validate_opts(const mhs_opts *o)
+{
+    if (!o) return fail(MHS_ERR_INVALID_ARG, "opts is NULL");
+    if (o->precision != MHS_PREC_FP64 && o->precision != MHS_PREC_MIXED)
+        return fail(MHS_ERR_INVALID_ARG, "precision must be MHS_PREC_FP64 or MHS_PREC_MIXED");
+    if (o->nu1 < 1 || o->nu2 < 1 || o->nu1 > 16 || o->nu2 > 16)
+        return fail(MHS_ERR_INVALID_ARG, "nu1 and nu2 must be in 1..16");
+    if (o->max_cycles < 0) return fail(MHS_ERR_INVALID_ARG, "max_cycles must be >= 0");
+    if (!(o->rtol >= 0.0) || !std::isfinite(o->rtol)) return fail(MHS_ERR_INVALID_ARG, "rtol must be >= 0");
+    if (o->inner_cycles < 1 || o->inner_cycles > 16) return fail(MHS_ERR_INVALID_ARG, "inner_cycles must be in 1..16");
+    if (o->check_every < 0) return fail(MHS_ERR_INVALID_ARG, "check_every must be >= 0");
+    return MHS_OK;
+}
+
+// ---- programs -----------------------------------------------------------------
+
+struct Program {
+    std::vector<Launch> launches;
+    bool ok = true;
+};
+
+LevelItem level_item(const Hierarchy &h, int l, int path)
+{
+    const Level &lv = h.lv[l];
+    LevelItem it{};
+    it.coef = path == kF64 ? (const void *)lv.coef64 : (const void *)lv.coef32;
+    it.cz = lv.cz;
+    it.nx = lv.n[0];
+    it.ny = lv.n[1];
+    it.nz = lv.n[2];
+    if (l + 1 < h.L) {
+        it.ncx = h.lv[l + 1].n[0];
+        it.ncy = h.lv[l + 1].n[1];
+        it.ncz = h.lv[l + 1].n[2];
+    }
+    return it;
+}
+
+void add_sweep(Program &pg, Staging &st, const Hierarchy &h, int l, int path, const void *uin, void *uout,
+               const void *f, const void *ec, int flags, SolveState *state, double *partials)
+{
+    LevelItem it = level_item(h, l, path);
+    const Level &lv = h.lv[l];
+    it.u_in = uin;
+    it.u_out = uout;
+    it.f = f;
+    it.ec = ec;
+    it.state = state;
+    it.partials = partials;
+    it.ntx = lv.st[0];
+    it.nty = lv.st[1];
+    it.ntz = lv.st[2];
+    it.tile_base = 0;
+    const LevelItem *d = st.put(it);
+    if (!d) {
+        pg.ok = false;
+        return;
+    }
+    Launch L{};
+    L.kind = h.planar ? Launch::kSweep2 : Launch::kSweep3;
+    L.flags = flags | (f ? kHasF : 0);
+    L.dbl = path == kF64;
+    L.items = d;
+    L.nitems = 1;
+    L.ntiles = lv.sweep_tiles();
+    pg.launches.push_back(L);
+}
+
+void add_restrict(Program &pg, Staging &st, const Hierarchy &h, int l, int path, const void *u, const void *f,
+                  void *fc, SolveState *state)
+{
+    LevelItem it = level_item(h, l, path);
+    const Level &lv = h.lv[l];
+    it.u_in = u;
+    it.f = f;
+    it.u_out = fc;
+    it.state = state;
+    it.ntx = lv.rt[0];
+    it.nty = lv.rt[1];
+    it.ntz = lv.rt[2];
+    const LevelItem *d = st.put(it);
+    if (!d) {
+        pg.ok = false;
+        return;
+    }
+    Launch L{};
+    L.kind = h.planar ? Launch::kRestrict2 : Launch::kRestrict3;
+    L.flags = f ? 1 : 0;
+    L.dbl = path == kF64;
+    L.items = d;
+    L.ntiles = lv.restrict_tiles();
+    pg.launches.push_back(L);
+}
+
+BottomItem bottom_item(const Hierarchy &h, int path, const void *f_top, void *u_top, int nu1, int nu2,
+                       SolveState *state)
+{
+    BottomItem b{};
+    b.f_top = f_top;
+    b.u_top = u_top;
+    const int nl = h.L - h.b;
+    for (int q = 0; q < nl; ++q) {
+        const int l = h.b + q;
+        b.u[q] = h.bu[l];
+        b.f[q] = h.bf[l];
+        b.coef[q] = h.lv[l].coef64;
+        b.cz[q] = h.lv[l].cz;
+        for (int a = 0; a < 3; ++a) b.n[q][a] = h.lv[l].n[a];
+    }
+    b.r = h.br;
+    b.nlev = nl;
+    b.m = h.m;
+    b.nu1 = nu1;
+    b.nu2 = nu2;
+    b.planar = h.planar ? 1 : 0;
+    b.minv = h.minv;
+    b.state = state;
+    (void)path;
+    return b;
+}
+
+void add_bottom(Program &pg, Staging &st, const Hierarchy &h, int path, const void *f_top, void *u_top, int nu1,
+                int nu2, SolveState *state)
+{
+    const BottomItem *d = st.put(bottom_item(h, path, f_top, u_top, nu1, nu2, state));
+    if (!d) {
+        pg.ok = false;
+        return;
+    }
+    Launch L{};
+    L.kind = Launch::kBottom;
+    L.dbl = path == kF64;
+    L.items = d;
+    pg.launches.push_back(L);
+}
+
+void add_finalize(Program &pg, Staging &st, const double *partials, int n, SolveState *state)
+{
+    FinalizeItem fi{};
+    fi.partials = partials;
+    fi.n = n;
+    fi.state = state;
+    const FinalizeItem *d = st.put(fi);
+    if (!d) {
+        pg.ok = false;
+        return;
+    }
+    Launch L{};
+    L.kind = Launch::kFinalize;
+    L.items = d;
+    pg.launches.push_back(L);
+}
+
+// One V(nu1, nu2) cycle.  Level 0 ping-pongs between a0 (input) and b0; the
+// returned pointer is the buffer holding the level-0 result.  With
+// `first_norm`, the first sweep also sums the residual of the input iterate
+// and a finalize launch follows it (the convergence check of that iterate).
+void *add_cycle(Program &pg, Staging &st, const Hierarchy &h, int path, void *a0, void *b0, const void *f0,
+                bool first_zero, bool first_norm, int nu1, int nu2, SolveState *state)
+{
+    const int b = h.b;
+    void *cur = a0, *oth = b0;
+    for (int s = 0; s < nu1; ++s) {
+        int flags = 0;
+        if (s == 0 && first_zero) flags |= kZeroIn;
+        if (s == 0 && first_norm) flags |= kNorm;
+        add_sweep(pg, st, h, 0, path, cur, oth, f0, nullptr, flags, state, h.partials);
+        std::swap(cur, oth);
+        if (s == 0 && first_norm) add_finalize(pg, st, h.partials, h.npart, state);
+    }
+    add_restrict(pg, st, h, 0, path, cur, f0, h.lv[1].f[path], state);
+    void *lcur[kMaxLevels] = {};
+    for (int l = 1; l < b; ++l) {
+        const Level &lv = h.lv[l];
+        void *c = lv.u[path], *o = lv.t[path];
+        // first sweep from a zero guess writes lv.u
+        add_sweep(pg, st, h, l, path, nullptr, c, lv.f[path], nullptr, kZeroIn, state, nullptr);
+        for (int s = 1; s < nu1; ++s) {
+            add_sweep(pg, st, h, l, path, c, o, lv.f[path], nullptr, 0, state, nullptr);
+            std::swap(c, o);
+        }
+        lcur[l] = c;
+        add_restrict(pg, st, h, l, path, c, lv.f[path], h.lv[l + 1].f[path], state);
+    }
+    add_bottom(pg, st, h, path, h.lv[b].f[path], h.lv[b].u[path], nu1, nu2, state);
+    const void *ec = h.lv[b].u[path];
+    for (int l = b - 1; l >= 1; --l) {
+        const Level &lv = h.lv[l];
+        void *c = lcur[l];
+        void *o = (c == lv.u[path]) ? lv.t[path] : lv.u[path];
+        add_sweep(pg, st, h, l, path, c, o, lv.f[path], ec, kProlong, state, nullptr);
+        std::swap(c, o);
+        for (int s = 1; s < nu2; ++s) {
+            add_sweep(pg, st, h, l, path, c, o, lv.f[path], nullptr, 0, state, nullptr);
+            std::swap(c, o);
+        }
+        ec = c;
+    }
+    add_sweep(pg, st, h, 0, path, cur, oth, f0, ec, kProlong, state, nullptr);
+    std::swap(cur, oth);
+    for (int s = 1; s < nu2; ++s) {
+        add_sweep(pg, st, h, 0, path, cur, oth, f0, nullptr, 0, state, nullptr);
+        std::swap(cur, oth);
+    }
+    return cur;
+}
+
+int run_program(const Program &pg, hipStream_t s)
+{
+    for (const Launch &L : pg.launches) {
+        hipError_t e = hipSuccess;
+        switch (L.kind) {
+        case Launch::kSweep3:
+            e = launch_sweep3((const LevelItem *)L.items, L.nitems, L.ntiles, L.flags, L.dbl, s);
+            break;
+        case Launch::kSweep2:
+            e = launch_sweep2((const LevelItem *)L.items, L.nitems, L.ntiles, L.flags, L.dbl, s);
+            break;
+        case Launch::kRestrict3:
+            e = launch_restrict3((const LevelItem *)L.items, L.nitems, L.ntiles, L.flags != 0, L.dbl, s);
+            break;
+        case Launch::kRestrict2:
+            e = launch_restrict2((const LevelItem *)L.items, L.nitems, L.ntiles, L.dbl, s);
+            break;
+        case Launch::kIr3:
+            e = launch_ir3((const LevelItem *)L.items, L.nitems, L.ntiles, L.flags != 0, s);
+            break;
+        case Launch::kBottom:
+            e = launch_bottom((const BottomItem *)L.items, L.nitems, L.dbl, s);
+            break;
+        case Launch::kFinalize:
+            e = launch_finalize((const FinalizeItem *)L.items, L.nitems, s);
+            break;
+        case Launch::kCopy:
+            e = launch_copy(L.src, L.dst, L.n, L.gate, s);
+            break;
+        }
+        if (e != hipSuccess) return fail(MHS_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+    }
+    return MHS_OK;
+}
+
+int begin_staging(mhs_plan *p)
+{
+    if (p->stage.inflight) HIPCHK(hipEventSynchronize(p->stage.inflight));
+    p->stage.used = 0;
+    return MHS_OK;
+}
+
+int flush_staging(mhs_plan *p, hipStream_t s)
+{
+    if (p->stage.used == 0) return MHS_OK;
+    HIPCHK(hipMemcpyAsync(p->stage.dev, p->stage.host, p->stage.used, hipMemcpyHostToDevice, s));
+    HIPCHK(hipEventRecord(p->stage.inflight, s));
+    return MHS_OK;
+}
+
+SolveState initial_state(double rtol, int max_iter)
+{
+    SolveState s{};
+    s.rtol = rtol;
+    s.max_iter = max_iter;
+    return s;
+}
+
+int read_state(mhs_plan *p, const SolveState *d_state, SolveState *out, hipStream_t s)
+{
+    HIPCHK(hipMemcpyAsync(p->h_states, d_state, sizeof(SolveState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *out = p->h_states[0];
+    return MHS_OK;
+}
+
+// How many more cycles (including the one that only checks) to launch.
+int next_batch(const SolveState &ss, const mhs_opts *o, int launched)
+{
+    const int remaining = o->max_cycles + 1 - launched;
+    if (remaining <= 0) return 0;
+    if (o->check_every > 0) return std::min(o->check_every, remaining);
+    int want = 4;
+    if (ss.checks >= 2 && ss.r0 > 0.0 && ss.rnorm > 0.0) {
+        const double rel = ss.rnorm / ss.r0;
+        const double rate = std::pow(rel, 1.0 / (ss.checks - 1));
+        if (rate > 0.0 && rate < 0.95 && o->rtol > 0.0) {
+            const double need = std::log(o->rtol / rel) / std::log(rate);
+            want = std::max(1, (int)std::ceil(need + 1e-9)) + 1;
+        } else {
+            want = 8;
+        }
+    }
+    return std::max(1, std::min(want, remaining));
+}
+
+int status_of(int32_t done)
+{
+    switch (done) {
+    case kConverged:
+        return MHS_OK;
+    case kMaxed:
+        return MHS_ERR_NO_CONVERGENCE;
+    case kDiverged:
+        return MHS_ERR_DIVERGED;
+    default:
+        return MHS_ERR_NO_CONVERGENCE;
+    }
+}
+
+int set_device(const mhs_plan *p)
+{
+    int cur = -1;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != p->device) HIPCHK(hipSetDevice(p->device));
+    return MHS_OK;
+}
+
+// Drive cycles of `cycle` (each starts with the norm check of the current
+// iterate) until the device-side state is no longer running.
+int drive(mhs_plan *p, const Program &cycle, const SolveState *d_state, const mhs_opts *o, SolveState *out,
+          int *syncs, hipStream_t s)
+{
+    int launched = 0;
+    SolveState ss{};
+    for (;;) {
+        const int nb = next_batch(ss, o, launched);
+        if (nb <= 0) break;
+        for (int q = 0; q < nb; ++q) {
+            int st = run_program(cycle, s);
+            if (st) return st;
+        }
+        launched += nb;
+        int st = read_state(p, d_state, &ss, s);
+        if (st) return st;
+        ++*syncs;
+        if (ss.done != kRunning) break;
+    }
+    *out = ss;
+    return MHS_OK;
+}
+
+double seconds_since(std::chrono::steady_clock::time_point t0)
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+} // namespace
+
+// =================================================================================
+// C ABI
+// =================================================================================
+extern "C" {
+
+void mhs_default_opts(mhs_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->precision = MHS_PREC_FP64;
+    o->max_cycles = 100;
+    o->rtol = 1e-10;
+    o->nu1 = 2;
+    o->nu2 = 2;
+    o->inner_cycles = 1;
+    o->warm_start = 0;
+    o->check_every = 0;
+}
+
+int32_t mhs_version(void) { return 10000; }
+
+const char *mhs_last_error(void) { return g_err.c_str(); }
+
+int mhs_workspace_bytes(const mhs_grid *grid, int32_t precisions, size_t *bytes)
+{
+    if (!bytes) return fail(MHS_ERR_INVALID_ARG, "bytes is NULL");
+    int st = check_grid(grid);
+    if (st) return st;
+    if (precisions <= 0 || precisions > 3) return fail(MHS_ERR_INVALID_ARG, "precisions must be a mask of 1|2");
+    mhs_plan tmp;
+    st = geometry(&tmp, grid);
+    if (st) return st;
+    *bytes = carve_plan(&tmp, nullptr, precisions);
+    return MHS_OK;
+}
+
+int mhs_plan_create(const mhs_grid *grid, int32_t precisions, void *d_ws, size_t ws_bytes, mhs_plan **out)
+{
+    if (!out) return fail(MHS_ERR_INVALID_ARG, "plan output is NULL");
+    *out = nullptr;
+    size_t need = 0;
+    int st = mhs_workspace_bytes(grid, precisions, &need);
+    if (st) return st;
+    if (!d_ws || ((uintptr_t)d_ws % kAlign) != 0)
+        return fail(MHS_ERR_WORKSPACE, "workspace must be a 256-byte aligned device pointer");
+    if (ws_bytes < need) return fail(MHS_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    mhs_plan *p = new mhs_plan();
+    p->precisions = precisions;
+    HIPCHK(hipGetDevice(&p->device));
+    st = geometry(p, grid);
+    if (st) {
+        delete p;
+        return st;
+    }
+    p->ws = (char *)d_ws;
+    p->ws_bytes = ws_bytes;
+    carve_plan(p, p->ws, precisions);
+    if (hipHostMalloc((void **)&p->stage.host, kStagingBytes, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&p->h_states, 4 * sizeof(SolveState), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&p->stage.inflight, hipEventDisableTiming) != hipSuccess) {
+        mhs_plan_destroy(p);
+        return fail(MHS_ERR_HIP, "pinned host allocation failed");
+    }
+    // boundary nodes of every coarse array must read as zero
+    if (hipMemset(d_ws, 0, need - kAlign) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        mhs_plan_destroy(p);
+        return fail(MHS_ERR_HIP, "workspace clear failed");
+    }
+    hipStream_t s0 = nullptr;
+    st = upload_planar(p, s0);
+    if (st) {
+        mhs_plan_destroy(p);
+        return st;
+    }
+    *out = p;
+    return MHS_OK;
+}
+
+int mhs_plan_destroy(mhs_plan *p)
+{
+    if (!p) return MHS_OK;
+    if (p->stage.inflight) {
+        (void)hipEventSynchronize(p->stage.inflight);
+        (void)hipEventDestroy(p->stage.inflight);
+    }
+    if (p->stage.host) (void)hipHostFree(p->stage.host);
+    if (p->h_states) (void)hipHostFree(p->h_states);
+    delete p;
+    return MHS_OK;
+}
+
+int mhs_plan_levels(const mhs_plan *p, int32_t space, int32_t *nlevels)
+{
+    if (!p || !nlevels) return fail(MHS_ERR_INVALID_ARG, "NULL argument");
+    if (space != 2 && space != 3) return fail(MHS_ERR_INVALID_ARG, "space must be 2 or 3");
+    *nlevels = space == 3 ? p->h3.L : p->h2.L;
+    return MHS_OK;
+}
+
+int mhs_plan_level_dims(const mhs_plan *p, int32_t space, int32_t level, int32_t *nx, int32_t *ny, int32_t *nz)
+{
+    if (!p || !nx || !ny || !nz) return fail(MHS_ERR_INVALID_ARG, "NULL argument");
+    if (space != 2 && space != 3) return fail(MHS_ERR_INVALID_ARG, "space must be 2 or 3");
+    const Hierarchy &h = space == 3 ? p->h3 : p->h2;
+    if (level < 0 || level >= h.L) return fail(MHS_ERR_INVALID_ARG, "level out of range");
+    *nx = h.lv[level].n[0];
+    *ny = h.lv[level].n[1];
+    *nz = h.lv[level].n[2];
+    return MHS_OK;
+}
+
+int mhs_plan_bottom_level(const mhs_plan *p, int32_t space, int32_t *level)
+{
+    if (!p || !level) return fail(MHS_ERR_INVALID_ARG, "NULL argument");
+    if (space != 2 && space != 3) return fail(MHS_ERR_INVALID_ARG, "space must be 2 or 3");
+    *level = space == 3 ? p->h3.b : p->h2.b;
+    return MHS_OK;
+}
+
+int mhs_solve_boundary(mhs_plan *p, const double *d_bz0, double *d_P, const mhs_opts *o, mhs_info *info,
+                       void *stream)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!p || !d_bz0 || !d_P) return fail(MHS_ERR_INVALID_ARG, "NULL argument");
+    int st = validate_opts(o);
+    if (st) return st;
+    if ((st = set_device(p))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    Hierarchy &h = p->h2;
+    if ((st = begin_staging(p))) return st;
+    SolveState *d_state = (SolveState *)p->stage.put(initial_state(o->rtol, o->max_cycles));
+    PrepItem pi{};
+    pi.P = d_P;
+    pi.twin = (double *)h.lv[0].t[kF64];
+    pi.bz0 = d_bz0;
+    pi.f2 = (double *)h.lv[0].f[kF64];
+    pi.nx = p->grid.nx;
+    pi.ny = p->grid.ny;
+    pi.nz = 1;
+    pi.warm = o->warm_start;
+    pi.n = (int64_t)p->grid.nx * p->grid.ny;
+    pi.base = 0;
+    const PrepItem *d_prep = p->stage.put(pi);
+    Program cyc;
+    void *res = add_cycle(cyc, p->stage, h, kF64, d_P, h.lv[0].t[kF64], h.lv[0].f[kF64], false, true, o->nu1,
+                          o->nu2, d_state);
+    if (res != (void *)d_P) {
+        Launch c{};
+        c.kind = Launch::kCopy;
+        c.src = (const double *)res;
+        c.dst = d_P;
+        c.n = (int64_t)p->grid.nx * p->grid.ny;
+        c.gate = d_state;
+        cyc.launches.push_back(c);
+    }
+    if (!cyc.ok || !d_state || !d_prep) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
+    if ((st = flush_staging(p, s))) return st;
+    HIPCHK(launch_prep2(d_prep, 1, pi.n, s));
+    SolveState fin{};
+    int syncs = 0;
+    if ((st = drive(p, cyc, d_state, o, &fin, &syncs, s))) return st;
+    const int status = status_of(fin.done);
+    if (info) {
+        info->status = status;
+        info->cycles = std::max(0, fin.checks - 1);
+        info->inner_cycles = 0;
+        info->host_syncs = syncs;
+        info->r0 = fin.r0;
+        info->rel_residual = fin.r0 > 0 ? fin.rnorm / fin.r0 : 0.0;
+        info->seconds = seconds_since(t0);
+    }
+    if (status != MHS_OK)
+        return fail(status, "lower-boundary solve stopped after %d cycles (relative residual %g)", fin.checks - 1,
+                    fin.r0 > 0 ? fin.rnorm / fin.r0 : 0.0);
+    return MHS_OK;
+}
+
+int mhs_solve_interior(mhs_plan *p, const mhs_model *model, double *d_P, const mhs_opts *o, mhs_info *info,
+                       void *stream)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!p || !d_P) return fail(MHS_ERR_INVALID_ARG, "NULL argument");
+    int st = validate_opts(o);
+    if (st) return st;
+    if ((st = validate_model(p, model, false))) return st;
+    if (!(p->precisions & o->precision))
+        return fail(MHS_ERR_UNSUPPORTED, "plan was not created for precision %d", o->precision);
+    if ((st = set_device(p))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    Hierarchy &h = p->h3;
+    if ((st = upload_model(p, model, s))) return st;
+    if ((st = begin_staging(p))) return st;
+    const bool mixed = o->precision == MHS_PREC_MIXED;
+    SolveState *d_state = (SolveState *)p->stage.put(initial_state(o->rtol, o->max_cycles));
+    double *T0 = (double *)h.lv[0].t[kF64];
+    const int64_t N = (int64_t)h.lv[0].N;
+    PrepItem pi{};
+    pi.P = d_P;
+    pi.twin = T0;
+    pi.nx = p->grid.nx;
+    pi.ny = p->grid.ny;
+    pi.nz = p->grid.nz;
+    pi.warm = o->warm_start;
+    pi.n = N;
+    const PrepItem *d_prep = p->stage.put(pi);
+    SolveState fin{};
+    int syncs = 0;
+    int inner_total = 0;
+    if (!mixed) {
+        Program cyc;
+        void *res = add_cycle(cyc, p->stage, h, kF64, d_P, T0, nullptr, false, true, o->nu1, o->nu2, d_state);
+        if (res != (void *)d_P) {
+            Launch c{};
+            c.kind = Launch::kCopy;
+            c.src = (const double *)res;
+            c.dst = d_P;
+            c.n = N;
+            c.gate = d_state;
+            cyc.launches.push_back(c);
+        }
+        if (!cyc.ok || !d_state || !d_prep) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
+        if ((st = flush_staging(p, s))) return st;
+        HIPCHK(launch_prep3(d_prep, 1, N, s));
+        if ((st = drive(p, cyc, d_state, o, &fin, &syncs, s))) return st;
+    } else {
+        // FP64 iterative refinement around FP32 V-cycles.  Step 0 only
+        // computes r = -A P; step s >= 1 applies the previous correction
+        // (P -> T0 for odd s, T0 -> P for even s) and recomputes r.
+        const Level &l0 = h.lv[0];
+        float *r32 = (float *)l0.f[kF32];
+        // inner cycles: locate the final correction buffer
+        Program inner;
+        void *ebuf = nullptr;
+        for (int c = 0; c < o->inner_cycles; ++c) {
+            void *a = c == 0 ? l0.u[kF32] : ebuf;
+            void *bb = (a == l0.u[kF32]) ? l0.t[kF32] : l0.u[kF32];
+            ebuf = add_cycle(inner, p->stage, h, kF32, a, bb, r32, c == 0, false, o->nu1, o->nu2, d_state);
+        }
+        auto ir_step = [&](Program &pg, const double *uin, double *uout, bool has_e) {
+            LevelItem it = level_item(h, 0, kF64);
+            it.u_in = uin;
+            it.u_out = uout;
+            it.ec = has_e ? ebuf : nullptr;
+            it.r_out = r32;
+            it.state = d_state;
+            it.partials = h.partials;
+            it.ntx = l0.st[0];
+            it.nty = l0.st[1];
+            it.ntz = l0.st[2];
+            const LevelItem *d = p->stage.put(it);
+            if (!d) {
+                pg.ok = false;
+                return;
+            }
+            Launch L{};
+            L.kind = Launch::kIr3;
+            L.flags = has_e ? 1 : 0;
+            L.items = d;
+            L.ntiles = l0.sweep_tiles();
+            pg.launches.push_back(L);
+            add_finalize(pg, p->stage, h.partials, h.npart, d_state);
+            pg.launches.insert(pg.launches.end(), inner.launches.begin(), inner.launches.end());
+        };
+        Program first, odd, even;
+        ir_step(first, d_P, nullptr, false);
+        ir_step(odd, d_P, T0, true);
+        ir_step(even, T0, d_P, true);
+        if (!first.ok || !odd.ok || !even.ok || !inner.ok || !d_state || !d_prep)
+            return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
+        if ((st = flush_staging(p, s))) return st;
+        HIPCHK(launch_prep3(d_prep, 1, N, s));
+        int launched = 0;
+        SolveState ss{};
+        for (;;) {
+            const int nb = next_batch(ss, o, launched);
+            if (nb <= 0) break;
+            for (int q = 0; q < nb; ++q) {
+                const int step = launched + q;
+                const Program &pg = step == 0 ? first : ((step & 1) ? odd : even);
+                if ((st = run_program(pg, s))) return st;
+            }
+            launched += nb;
+            if ((st = read_state(p, d_state, &ss, s))) return st;
+            ++syncs;
+            if (ss.done != kRunning) break;
+        }
+        fin = ss;
+        const int steps = std::max(0, fin.checks - 1);
+        inner_total = steps * o->inner_cycles;
+        if (steps & 1) {
+            HIPCHK(launch_copy(T0, d_P, N, nullptr, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
+    }
+    const int status = status_of(fin.done);
+    if (info) {
+        info->status = status;
+        info->cycles = std::max(0, fin.checks - 1);
+        info->inner_cycles = inner_total;
+        info->host_syncs = syncs;
+        info->r0 = fin.r0;
+        info->rel_residual = fin.r0 > 0 ? fin.rnorm / fin.r0 : 0.0;
+        info->seconds = seconds_since(t0);
+    }
+    if (status != MHS_OK)
+        return fail(status, "interior solve stopped after %d cycles (relative residual %g)", fin.checks - 1,
+                    fin.r0 > 0 ? fin.rnorm / fin.r0 : 0.0);
+    return MHS_OK;
+}
+
+int mhs_fields(mhs_plan *p, const mhs_model *model, const double *d_P, double *d_Bx, double *d_By, double *d_Bz,
+               double *d_p, double *d_rho, void *stream)
+{
+    if (!p || !d_P || !d_Bx || !d_By || !d_Bz || !d_p || !d_rho) return fail(MHS_ERR_INVALID_ARG, "NULL argument");
+    int st = validate_model(p, model, true);
+    if (st) return st;
+    if ((st = set_device(p))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const int nx = p->grid.nx, ny = p->grid.ny, nz = p->grid.nz;
+    if ((st = begin_staging(p))) return st;
+    // the table goes through the staging buffer too (one transfer)
+    std::vector<double> tab(4 * (size_t)nz);
+    std::copy(model->xi, model->xi + nz, tab.begin());
+    std::copy(model->dxi, model->dxi + nz, tab.begin() + nz);
+    std::copy(model->pb, model->pb + nz, tab.begin() + 2 * nz);
+    std::copy(model->rhob, model->rhob + nz, tab.begin() + 3 * nz);
+    p->stage.used = (p->stage.used + 63) & ~size_t(63);
+    const size_t tab_off = p->stage.used;
+    if (tab_off + tab.size() * sizeof(double) > p->stage.cap) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
+    std::memcpy(p->stage.host + tab_off, tab.data(), tab.size() * sizeof(double));
+    p->stage.used += tab.size() * sizeof(double);
+    FieldsItem fi{};
+    fi.P = d_P;
+    fi.Bx = d_Bx;
+    fi.By = d_By;
+    fi.Bz = d_Bz;
+    fi.p = d_p;
+    fi.rho = d_rho;
+    fi.tab = (const double *)(p->stage.dev + tab_off);
+    fi.alpha = model->alpha;
+    fi.mu0 = model->mu0;
+    fi.g = model->g;
+    fi.dx = p->grid.lx / (nx - 1);
+    fi.dy = p->grid.ly / (ny - 1);
+    fi.dz = p->grid.lz / (nz - 1);
+    fi.nx = nx;
+    fi.ny = ny;
+    fi.nz = nz;
+    fi.ntx = ceil_div(nx, kTX);
+    fi.nty = ceil_div(ny, kFY);
+    fi.ntz = ceil_div(nz, kKZ);
+    fi.tile_base = 0;
+    const FieldsItem *d = p->stage.put(fi);
+    if (!d) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
+    if ((st = flush_staging(p, s))) return st;
+    HIPCHK(launch_fields(d, 1, fi.ntx * fi.nty * fi.ntz, s));
+    return MHS_OK;
+}
+
+} // extern "C"
+
+// ---- stage entry points -----------------------------------------------------------
+namespace {
+
+int stage_common(mhs_plan *p, const mhs_model *model, int space, int level, int precision, Hierarchy **hh,
+                 int *path, hipStream_t s)
+{
+    if (!p) return fail(MHS_ERR_INVALID_ARG, "plan is NULL");
+    if (space != 2 && space != 3) return fail(MHS_ERR_INVALID_ARG, "space must be 2 or 3");
+    if (precision != MHS_PREC_FP64 && precision != MHS_PREC_MIXED)
+        return fail(MHS_ERR_INVALID_ARG, "precision must be MHS_PREC_FP64 or MHS_PREC_MIXED");
+    Hierarchy &h = space == 3 ? p->h3 : p->h2;
+    if (level < 0 || level >= h.L) return fail(MHS_ERR_INVALID_ARG, "level out of range");
+    if (space == 2 && precision != MHS_PREC_FP64) return fail(MHS_ERR_UNSUPPORTED, "2D stages are FP64 only");
+    if (space == 3 && !(p->precisions & precision))
+        return fail(MHS_ERR_UNSUPPORTED, "plan was not created for precision %d", precision);
+    int st = set_device(p);
+    if (st) return st;
+    if (space == 3) {
+        if ((st = validate_model(p, model, false))) return st;
+        if ((st = upload_model(p, model, s))) return st;
+    }
+    *hh = &h;
+    *path = precision == MHS_PREC_FP64 ? kF64 : kF32;
+    return MHS_OK;
+}
+
+// the level's ping-pong twin for stage calls
+void *stage_twin(Hierarchy &h, int level, int path) { return h.lv[level].t[path]; }
+
+} // namespace
+
+extern "C" {
+
+int mhs_stage_smooth(mhs_plan *p, const mhs_model *model, int32_t space, int32_t level, int32_t precision,
+                     void *d_u, const void *d_f, int32_t nsweeps, void *stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    Hierarchy *h = nullptr;
+    int path = 0;
+    int st = stage_common(p, model, space, level, precision, &h, &path, s);
+    if (st) return st;
+    if (!d_u || nsweeps < 1) return fail(MHS_ERR_INVALID_ARG, "bad u or nsweeps");
+    void *tw = stage_twin(*h, level, path);
+    if (!tw || level >= h->b) return fail(MHS_ERR_UNSUPPORTED, "level %d is handled by the bottom solver", level);
+    if (path == kF32 && level == 0) tw = h->lv[0].t[kF32];
+    const size_t es = path == kF64 ? 8 : 4;
+    const size_t bytes = h->lv[level].N * es;
+    HIPCHK(hipMemcpyAsync(tw, d_u, bytes, hipMemcpyDeviceToDevice, s));
+    if ((st = begin_staging(p))) return st;
+    Program pg;
+    void *cur = d_u, *oth = tw;
+    for (int q = 0; q < nsweeps; ++q) {
+        add_sweep(pg, p->stage, *h, level, path, cur, oth, d_f, nullptr, 0, nullptr, nullptr);
+        std::swap(cur, oth);
+    }
+    if (!pg.ok) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
+    if ((st = flush_staging(p, s))) return st;
+    if ((st = run_program(pg, s))) return st;
+    if (cur != d_u) HIPCHK(hipMemcpyAsync(d_u, cur, bytes, hipMemcpyDeviceToDevice, s));
+    return MHS_OK;
+}
+
+int mhs_stage_restrict(mhs_plan *p, const mhs_model *model, int32_t space, int32_t level, int32_t precision,
+                       const void *d_u, const void *d_f, void *d_fc, void *stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    Hierarchy *h = nullptr;
+    int path = 0;
+    int st = stage_common(p, model, space, level, precision, &h, &path, s);
+    if (st) return st;
+    if (!d_u || !d_fc || level + 1 >= h->L) return fail(MHS_ERR_INVALID_ARG, "bad arrays or level");
+    if (space == 2 && !d_f) return fail(MHS_ERR_INVALID_ARG, "2D restriction needs f");
+    if ((st = begin_staging(p))) return st;
+    Program pg;
+    add_restrict(pg, p->stage, *h, level, path, d_u, d_f, d_fc, nullptr);
+    if (!pg.ok) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
+    if ((st = flush_staging(p, s))) return st;
+    return run_program(pg, s);
+}
+
+int mhs_stage_correct_smooth(mhs_plan *p, const mhs_model *model, int32_t space, int32_t level, int32_t precision,
+                             void *d_u, const void *d_f, const void *d_ec, void *stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    Hierarchy *h = nullptr;
+    int path = 0;
+    int st = stage_common(p, model, space, level, precision, &h, &path, s);
+    if (st) return st;
+    if (!d_u || !d_ec || level + 1 >= h->L) return fail(MHS_ERR_INVALID_ARG, "bad arrays or level");
+    void *tw = stage_twin(*h, level, path);
+    if (!tw || level >= h->b) return fail(MHS_ERR_UNSUPPORTED, "level %d is handled by the bottom solver", level);
+    const size_t bytes = h->lv[level].N * (path == kF64 ? 8 : 4);
+    HIPCHK(hipMemcpyAsync(tw, d_u, bytes, hipMemcpyDeviceToDevice, s));
+    if ((st = begin_staging(p))) return st;
+    Program pg;
+    add_sweep(pg, p->stage, *h, level, path, d_u, tw, d_f, d_ec, kProlong, nullptr, nullptr);
+    if (!pg.ok) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
+    if ((st = flush_staging(p, s))) return st;
+    if ((st = run_program(pg, s))) return st;
+    HIPCHK(hipMemcpyAsync(d_u, tw, bytes, hipMemcpyDeviceToDevice, s));
+    return MHS_OK;
+}
+
+int mhs_stage_bottom(mhs_plan *p, const mhs_model *model, int32_t space, int32_t precision, void *d_u,
+                     const void *d_f, int32_t nu1, int32_t nu2, int32_t *bottom_level, void *stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    Hierarchy *h = nullptr;
+    int path = 0;
+    int st = stage_common(p, model, space, 0, precision, &h, &path, s);
+    if (st) return st;
+    if (!d_u || !d_f || nu1 < 1 || nu2 < 1) return fail(MHS_ERR_INVALID_ARG, "bad arguments");
+    if (bottom_level) *bottom_level = h->b;
+    if ((st = begin_staging(p))) return st;
+    Program pg;
+    add_bottom(pg, p->stage, *h, path, d_f, d_u, nu1, nu2, nullptr);
+    if (!pg.ok) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
+    if ((st = flush_staging(p, s))) return st;
+    return run_program(pg, s);
+}
+
+int mhs_stage_residual_norm(mhs_plan *p, const mhs_model *model, int32_t space, int32_t level, int32_t precision,
+                            const void *d_u, const void *d_f, double *norm, void *stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    Hierarchy *h = nullptr;
+    int path = 0;
+    int st = stage_common(p, model, space, level, precision, &h, &path, s);
+    if (st) return st;
+    if (!d_u || !norm) return fail(MHS_ERR_INVALID_ARG, "bad arguments");
+    void *tw = stage_twin(*h, level, path);
+    if (!tw || level >= h->b) return fail(MHS_ERR_UNSUPPORTED, "level %d is handled by the bottom solver", level);
+    if (h->lv[level].sweep_tiles() > p->scratch_npart) return fail(MHS_ERR_WORKSPACE, "scratch too small");
+    if ((st = begin_staging(p))) return st;
+    SolveState *d_state = (SolveState *)p->stage.put(initial_state(0.0, 0));
+    Program pg;
+    add_sweep(pg, p->stage, *h, level, path, d_u, tw, d_f, nullptr, kNorm, nullptr, p->d_scratch_norm);
+    add_finalize(pg, p->stage, p->d_scratch_norm, h->lv[level].sweep_tiles(), d_state);
+    if (!pg.ok || !d_state) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
+    if ((st = flush_staging(p, s))) return st;
+    if ((st = run_program(pg, s))) return st;
+    SolveState ss{};
+    if ((st = read_state(p, d_state, &ss, s))) return st;
+    *norm = ss.rnorm;
+    return MHS_OK;
+}
+
+} // extern "C"

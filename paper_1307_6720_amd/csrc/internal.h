@@ -1,0 +1,149 @@
+// Internal declarations shared by the host library and the kernels.
+//
+// Every kernel is descriptor-driven: it receives a device array of work
+// items (one per request/level it serves) and maps its workgroups onto the
+// items' tiles through a prefix of tile counts.  A single solve launches
+// one item per stage; the batched (serving) path launches many.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace mhs {
+
+constexpr int kMaxLevels = 16;
+
+// ---- tile geometry ---------------------------------------------------------
+// 3D smoother / refinement residual: x-y tile of kTX x kTY interior nodes,
+// marching kKZ planes in z; 256 threads.
+constexpr int kTX = 64;
+constexpr int kTY = 8;
+constexpr int kKZ = 32;
+constexpr int kThreads = 256;
+// 3D residual + restriction: kCX x kCY coarse nodes per workgroup, marching
+// kKC coarse planes.
+constexpr int kCX = 32;
+constexpr int kCY = 8;
+constexpr int kKC = 16;
+// 2D smoother: kTX x kTY2 interior nodes per workgroup.
+constexpr int kTY2 = 16;
+// field recovery: kTX x kFY nodes per workgroup, marching kKZ planes.
+constexpr int kFY = 8;
+// bottom solver: one workgroup per item.
+constexpr int kBottomThreads = 1024;
+// largest coarsest-grid system solved by the dense inverse
+constexpr int kMaxCoarse = 1024;
+
+// Convergence state of one solve, updated only by the finalize kernel.
+struct SolveState {
+    double r0;        // ||r_0||_2
+    double rnorm;     // ||r_c||_2 of the last checked iterate
+    double rtol;      // stopping tolerance (relative)
+    int32_t checks;   // number of norms checked so far (iterate index + 1)
+    int32_t done;     // 0 running, 1 converged, 2 iteration cap, 3 diverged
+    int32_t max_iter; // iteration cap
+    int32_t pad;
+};
+
+enum DoneCode : int32_t { kRunning = 0, kConverged = 1, kMaxed = 2, kDiverged = 3 };
+
+// One (request, level) item of a stencil launch.
+struct LevelItem {
+    const void *u_in;   // iterate read by the stage
+    void *u_out;        // iterate written (smoother, refinement) / coarse rhs (restriction)
+    const void *f;      // right-hand side, nullptr = 0
+    const void *ec;     // coarse correction added before smoothing, or FP32 e (refinement)
+    void *r_out;        // refinement: FP32 residual output
+    const void *coef;   // per-plane {cx, cy, d, 1/d} in the stage's arithmetic type
+    double cz;          // z coupling 1/dz^2 (0 for the 2D problem)
+    SolveState *state;  // stage is skipped once state->done != 0 (may be null)
+    double *partials;   // per-tile sums of squared residuals (may be null)
+    int32_t nx, ny, nz; // nodes of this level (nz = 1 for the 2D problem)
+    int32_t ncx, ncy, ncz; // nodes of the next coarser level
+    int32_t ntx, nty, ntz; // tiles per axis
+    int32_t tile_base;     // first global tile of this item in its launch
+};
+
+// One request of the bottom solver: a full V-cycle from level `top` of the
+// bottom hierarchy to the coarsest grid, in FP64, by a single workgroup.
+struct BottomItem {
+    const void *f_top;            // right-hand side at the top bottom level (storage type)
+    void *u_top;                  // correction written back (storage type)
+    double *u[kMaxLevels];        // FP64 work arrays (levels of the bottom hierarchy)
+    double *f[kMaxLevels];
+    double *r;                    // residual scratch (size of the top level)
+    const double *coef[kMaxLevels];
+    double cz[kMaxLevels];
+    int32_t n[kMaxLevels][3];
+    int32_t nlev;
+    int32_t m;                    // unknowns of the coarsest grid
+    int32_t nu1, nu2;
+    int32_t planar;               // 1 = 2D problem
+    int32_t pad;
+    const double *minv;           // m x m inverse of the coarsest operator
+    SolveState *state;
+};
+
+struct FinalizeItem {
+    const double *partials;
+    int32_t n;
+    int32_t pad;
+    SolveState *state;
+};
+
+struct FieldsItem {
+    const double *P;
+    double *Bx, *By, *Bz, *p, *rho;
+    const double *tab; // 4 * nz: xi, dxi, pb, rhob
+    double alpha, mu0, g;
+    double dx, dy, dz;
+    int32_t nx, ny, nz;
+    int32_t ntx, nty, ntz;
+    int32_t tile_base;
+    int32_t pad;
+};
+
+// Whole-array preparation items.
+struct PrepItem {
+    double *P;          // 3D potential (or the base plane for 2D)
+    double *twin;       // ping-pong partner whose faces must match P
+    const double *bz0;  // 2D: magnetogram
+    double *f2;         // 2D: right-hand side -bz0
+    int32_t nx, ny, nz;
+    int32_t warm;
+    int64_t n;          // points covered
+    int64_t base;       // first global thread of this item
+};
+
+// ---- launchers (kernels.hip) ------------------------------------------------
+// `dbl` selects the arithmetic/storage type: true = double, false = float.
+enum SweepFlags : int {
+    kHasF = 1,      // read the right-hand side
+    kZeroIn = 2,    // input iterate is zero (first sweep from a zero guess)
+    kNorm = 4,      // also write per-tile ||f - A u_in||^2 partials
+    kProlong = 8,   // add the interpolated coarse correction to u_in first
+};
+
+hipError_t launch_sweep3(const LevelItem *items, int nitems, int ntiles, int flags, bool dbl,
+                         hipStream_t s);
+hipError_t launch_sweep2(const LevelItem *items, int nitems, int ntiles, int flags, bool dbl,
+                         hipStream_t s);
+hipError_t launch_restrict3(const LevelItem *items, int nitems, int ntiles, bool has_f, bool dbl,
+                            hipStream_t s);
+hipError_t launch_restrict2(const LevelItem *items, int nitems, int ntiles, bool dbl,
+                            hipStream_t s);
+hipError_t launch_ir3(const LevelItem *items, int nitems, int ntiles, bool has_e, hipStream_t s);
+hipError_t launch_bottom(const BottomItem *items, int nitems, bool dbl, hipStream_t s);
+hipError_t launch_finalize(const FinalizeItem *items, int nitems, hipStream_t s);
+hipError_t launch_fields(const FieldsItem *items, int nitems, int ntiles, hipStream_t s);
+hipError_t launch_prep3(const PrepItem *items, int nitems, int64_t nthreads, hipStream_t s);
+hipError_t launch_prep2(const PrepItem *items, int nitems, int64_t nthreads, hipStream_t s);
+hipError_t launch_copy(const double *src, double *dst, int64_t n, const SolveState *skip,
+                       hipStream_t s);
+
+// tile counts
+inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+} // namespace mhs

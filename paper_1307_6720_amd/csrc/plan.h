@@ -1,0 +1,103 @@
+// Host-side plan: the multigrid hierarchy laid out in the caller's
+// workspace, coefficient tables, launch programs and the C-ABI glue.
+#pragma once
+
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mhs.h"
+#include "internal.h"
+
+namespace mhs {
+
+enum Path : int { kF64 = 0, kF32 = 1 };
+
+struct Level {
+    int n[3] = {0, 0, 0}; // nx, ny, nz (nz = 1 for the 2D problem)
+    double h[3] = {0, 0, 0};
+    size_t N = 0;
+    void *u[2] = {nullptr, nullptr}; // per path: iterate / correction
+    void *t[2] = {nullptr, nullptr}; // per path: ping-pong twin
+    void *f[2] = {nullptr, nullptr}; // per path: right-hand side
+    double *coef64 = nullptr;        // device, 4 * nz
+    float *coef32 = nullptr;         // device, 4 * nz
+    double cz = 0.0;
+    int st[3] = {0, 0, 0}; // smoother tiles per axis
+    int rt[3] = {0, 0, 0}; // restriction tiles per axis (onto level+1)
+    int sweep_tiles() const { return st[0] * st[1] * st[2]; }
+    int restrict_tiles() const { return rt[0] * rt[1] * rt[2]; }
+};
+
+struct Hierarchy {
+    bool planar = false;
+    int L = 0; // levels
+    int b = 0; // first level handled by the bottom solver
+    Level lv[kMaxLevels];
+    double *bu[kMaxLevels] = {};
+    double *bf[kMaxLevels] = {};
+    double *br = nullptr;
+    double *minv = nullptr; // device m x m
+    int m = 0;              // coarsest unknowns
+    double *partials = nullptr;
+    int npart = 0;
+};
+
+// One kernel launch of a program (the device item table is in the workspace).
+struct Launch {
+    enum Kind { kSweep3, kSweep2, kRestrict3, kRestrict2, kIr3, kBottom, kFinalize, kCopy } kind;
+    int flags = 0;
+    bool dbl = true;
+    const void *items = nullptr; // device pointer
+    int nitems = 1;
+    int ntiles = 0;
+    // copy
+    const double *src = nullptr;
+    double *dst = nullptr;
+    int64_t n = 0;
+    const SolveState *gate = nullptr; // copy: skipped once this solve is done
+};
+
+// Host staging of item tables: items are appended in host memory and copied
+// to the device region in one transfer.
+struct Staging {
+    char *host = nullptr; // pinned
+    char *dev = nullptr;  // workspace region
+    size_t cap = 0, used = 0;
+    hipEvent_t inflight = nullptr;
+    template <typename T>
+    const T *put(const T &v)
+    {
+        used = (used + 63) & ~size_t(63);
+        if (used + sizeof(T) > cap) return nullptr;
+        std::memcpy(host + used, &v, sizeof(T));
+        const T *d = reinterpret_cast<const T *>(dev + used);
+        used += sizeof(T);
+        return d;
+    }
+};
+
+struct ModelCache {
+    bool valid = false;
+    double alpha = 0.0;
+    std::vector<double> xi;
+};
+
+} // namespace mhs
+
+struct mhs_plan {
+    mhs_grid grid{};
+    int precisions = 0;
+    int device = 0;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    mhs::Hierarchy h3, h2;
+    // the FP64 twin of the level-0 potential (3D) and the 2D base plane
+    mhs::SolveState *d_states = nullptr; // [0] 2D, [1] 3D, [2] stage
+    mhs::SolveState *h_states = nullptr; // pinned mirror
+    double *d_fields_tab = nullptr;      // 4 * nz
+    mhs::Staging stage;
+    mhs::ModelCache cache;
+    double *d_scratch_norm = nullptr;    // stage residual-norm partials
+    int scratch_npart = 0;
+};

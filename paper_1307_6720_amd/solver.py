@@ -1,0 +1,252 @@
+"""Torch-level interface to libmhs: plans, solves and field recovery.
+
+PyTorch provides device memory and streams only; every step of the solve runs
+in the HIP library through the C ABI declared in include/mhs.h.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import PREC_FP64, PREC_MIXED, MHSError, check
+
+
+def _stream(device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def make_opts(precision=PREC_FP64, rtol=1e-10, max_cycles=100, nu1=2, nu2=2, inner_cycles=1,
+              warm_start=False, check_every=0):
+    o = _lib.Opts()
+    _lib.lib().mhs_default_opts(C.byref(o))
+    o.precision = precision
+    o.rtol = rtol
+    o.max_cycles = max_cycles
+    o.nu1 = nu1
+    o.nu2 = nu2
+    o.inner_cycles = inner_cycles
+    o.warm_start = 1 if warm_start else 0
+    o.check_every = check_every
+    return o
+
+
+class _ModelArgs:
+    """Keeps the host arrays of a model alive while the C struct points at them."""
+
+    def __init__(self, alpha, xi, dxi=None, pb=None, rhob=None, mu0=1.0, g=1.0):
+        self.arrays = []
+
+        def arr(a):
+            if a is None:
+                return None
+            a = np.ascontiguousarray(a, dtype=np.float64)
+            self.arrays.append(a)
+            return a.ctypes.data_as(C.POINTER(C.c_double))
+
+        self.c = _lib.Model(float(alpha), arr(xi), arr(dxi), arr(pb), arr(rhob), float(mu0), float(g))
+
+    @classmethod
+    def of(cls, model):
+        if model is None:
+            return None
+        return cls(model.alpha, model.xi, model.dxi, model.pb, model.rhob, model.mu0, model.g)
+
+
+@dataclass
+class GridSpec:
+    nx: int
+    ny: int
+    nz: int
+    lx: float = 1.0
+    ly: float = 1.0
+    lz: float = 1.0
+
+    def c(self):
+        return _lib.Grid(self.nx, self.ny, self.nz, self.lx, self.ly, self.lz)
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+
+def workspace_bytes(grid, precisions=PREC_FP64 | PREC_MIXED):
+    g = _grid(grid)
+    n = C.c_size_t(0)
+    check(_lib.lib().mhs_workspace_bytes(C.byref(g), precisions, C.byref(n)))
+    return n.value
+
+
+def _grid(grid):
+    if isinstance(grid, _lib.Grid):
+        return grid
+    return _lib.Grid(int(grid.nx), int(grid.ny), int(grid.nz), float(grid.lx), float(grid.ly), float(grid.lz))
+
+
+class Plan:
+    """A multigrid plan over a torch-allocated workspace on one device."""
+
+    def __init__(self, grid, precisions=PREC_FP64 | PREC_MIXED, device="cuda:0", workspace=None):
+        self.grid = grid
+        self.cgrid = _grid(grid)
+        self.device = torch.device(device)
+        self.precisions = precisions
+        self.ws_bytes = workspace_bytes(grid, precisions)
+        with torch.cuda.device(self.device):
+            if workspace is None:
+                workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+            if workspace.numel() < self.ws_bytes:
+                raise ValueError("workspace too small")
+            self.ws = workspace
+            h = C.c_void_p()
+            check(_lib.lib().mhs_plan_create(C.byref(self.cgrid), precisions, C.c_void_p(workspace.data_ptr()),
+                                             workspace.numel(), C.byref(h)))
+        self.h = h
+
+    @property
+    def shape(self):
+        return (self.cgrid.nz, self.cgrid.ny, self.cgrid.nx)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.lib().mhs_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def levels(self, space=3):
+        n = C.c_int32()
+        check(_lib.lib().mhs_plan_levels(self.h, space, C.byref(n)))
+        return n.value
+
+    def bottom_level(self, space=3):
+        n = C.c_int32()
+        check(_lib.lib().mhs_plan_bottom_level(self.h, space, C.byref(n)))
+        return n.value
+
+    def level_shape(self, space, level):
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        check(_lib.lib().mhs_plan_level_dims(self.h, space, level, C.byref(a), C.byref(b), C.byref(c)))
+        return (c.value, b.value, a.value) if space == 3 else (b.value, a.value)
+
+    # ---- the three steps of the procedure ------------------------------------
+    def solve_boundary(self, bz0, P, opts=None, raise_on_error=True):
+        """Multigrid solve of equation (11); writes plane 0 of P."""
+        opts = opts or make_opts()
+        info = _lib.Info()
+        with torch.cuda.device(self.device):
+            code = _lib.lib().mhs_solve_boundary(self.h, _ptr(bz0), _ptr(P), C.byref(opts), C.byref(info),
+                                                 _stream(self.device))
+        if raise_on_error:
+            check(code)
+        return info
+
+    def solve_interior(self, model, P, opts=None, raise_on_error=True):
+        """Multigrid solve of equation (8) in place (FP64 or mixed)."""
+        opts = opts or make_opts()
+        m = _ModelArgs.of(model)
+        info = _lib.Info()
+        with torch.cuda.device(self.device):
+            code = _lib.lib().mhs_solve_interior(self.h, C.byref(m.c), _ptr(P), C.byref(opts), C.byref(info),
+                                                 _stream(self.device))
+        if raise_on_error:
+            check(code)
+        return info
+
+    def fields(self, model, P, out=None):
+        """B, p, rho by central differences; returns (Bx, By, Bz, p, rho)."""
+        if out is None:
+            out = tuple(torch.empty_like(P) for _ in range(5))
+        m = _ModelArgs.of(model)
+        with torch.cuda.device(self.device):
+            check(_lib.lib().mhs_fields(self.h, C.byref(m.c), _ptr(P), *[_ptr(t) for t in out],
+                                        _stream(self.device)))
+        return out
+
+    # ---- stage entry points (kernel-level checks) ----------------------------
+    def stage_smooth(self, model, space, level, u, f=None, nsweeps=1, precision=PREC_FP64):
+        m = _ModelArgs.of(model)
+        with torch.cuda.device(self.device):
+            check(_lib.lib().mhs_stage_smooth(self.h, C.byref(m.c) if m else None, space, level, precision,
+                                              _ptr(u), _ptr(f), nsweeps, _stream(self.device)))
+        return u
+
+    def stage_restrict(self, model, space, level, u, f, fc, precision=PREC_FP64):
+        m = _ModelArgs.of(model)
+        with torch.cuda.device(self.device):
+            check(_lib.lib().mhs_stage_restrict(self.h, C.byref(m.c) if m else None, space, level, precision,
+                                                _ptr(u), _ptr(f), _ptr(fc), _stream(self.device)))
+        return fc
+
+    def stage_correct_smooth(self, model, space, level, u, f, ec, precision=PREC_FP64):
+        m = _ModelArgs.of(model)
+        with torch.cuda.device(self.device):
+            check(_lib.lib().mhs_stage_correct_smooth(self.h, C.byref(m.c) if m else None, space, level,
+                                                      precision, _ptr(u), _ptr(f), _ptr(ec),
+                                                      _stream(self.device)))
+        return u
+
+    def stage_bottom(self, model, space, u, f, nu1=2, nu2=2, precision=PREC_FP64):
+        m = _ModelArgs.of(model)
+        lvl = C.c_int32()
+        with torch.cuda.device(self.device):
+            check(_lib.lib().mhs_stage_bottom(self.h, C.byref(m.c) if m else None, space, precision, _ptr(u),
+                                              _ptr(f), nu1, nu2, C.byref(lvl), _stream(self.device)))
+        return lvl.value
+
+    def stage_residual_norm(self, model, space, level, u, f=None, precision=PREC_FP64):
+        m = _ModelArgs.of(model)
+        out = C.c_double()
+        with torch.cuda.device(self.device):
+            check(_lib.lib().mhs_stage_residual_norm(self.h, C.byref(m.c) if m else None, space, level,
+                                                     precision, _ptr(u), _ptr(f), C.byref(out),
+                                                     _stream(self.device)))
+        return out.value
+
+
+@dataclass
+class SolveResult:
+    P: torch.Tensor
+    Bx: torch.Tensor
+    By: torch.Tensor
+    Bz: torch.Tensor
+    p: torch.Tensor
+    rho: torch.Tensor
+    info2d: dict
+    info3d: dict
+
+
+def solve(plan: Plan, bz0, model, precision=PREC_FP64, rtol=1e-10, rtol2d=None, max_cycles=100,
+          inner_cycles=1, fields=True, out=None):
+    """The whole path: (11) on the base, (8) in the interior, then B, p, rho.
+
+    bz0: torch float64 (ny, nx) on the plan's device; model: synth.Model-like.
+    """
+    dev = plan.device
+    shape = plan.shape
+    if out is None:
+        P = torch.empty(shape, dtype=torch.float64, device=dev)
+        F = tuple(torch.empty(shape, dtype=torch.float64, device=dev) for _ in range(5)) if fields else None
+    else:
+        P, F = out[0], tuple(out[1:]) if fields else None
+    o2 = make_opts(PREC_FP64, rtol if rtol2d is None else rtol2d, max_cycles)
+    i2 = plan.solve_boundary(bz0, P, o2)
+    o3 = make_opts(precision, rtol, max_cycles, inner_cycles=inner_cycles)
+    i3 = plan.solve_interior(model, P, o3)
+    if fields:
+        plan.fields(model, P, F)
+    else:
+        F = (None,) * 5
+    return SolveResult(P, *F, i2.as_dict(), i3.as_dict())

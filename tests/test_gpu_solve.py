@@ -1,0 +1,182 @@
+"""Solve-level parity of the HIP path against the oracle.
+
+* algorithm parity: the HIP V-cycles and the C twin (same method, same
+  stopping rule) produce the same iterates at a fixed number of cycles;
+* solution parity: at the stopping tolerance, P, B, p - p_b and rho - rho_b
+  match the exact discrete solution (sine transform + tridiagonal) within
+  1e-10 (FP64 path) and 1e-8 (FP32-in-FP64 refinement), relative max norm
+  per field;
+* error paths of the C ABI.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import exact, fields, ref
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1307_6720_amd import PREC_FP64, PREC_MIXED, MHSError  # noqa: E402
+from paper_1307_6720_amd import _lib  # noqa: E402
+from paper_1307_6720_amd.solver import Plan, make_opts, solve  # noqa: E402
+
+DEV = "cuda:0"
+NAMES = ("P", "Bx", "By", "Bz", "dp", "drho")
+
+
+def rel(a, b):
+    d = np.abs(b).max()
+    return float(np.abs(a - b).max() / (d if d > 0 else 1.0))
+
+
+def field_errors(res, want_P, m):
+    want = fields.fields(want_P, m.alpha, m.xi, m.dxi, m.pb, m.rhob, m.mu0, m.g)
+    pb = m.pb[:, None, None]
+    rb = m.rhob[:, None, None]
+    got = [res.P, res.Bx, res.By, res.Bz, res.p, res.rho]
+    got = [g.cpu().numpy() for g in got]
+    got[4] = got[4] - pb
+    got[5] = got[5] - rb
+    ref_ = [want_P, want[0], want[1], want[2], want[3] - pb, want[4] - rb]
+    return {n: rel(g, w) for n, g, w in zip(NAMES, got, ref_)}
+
+
+@pytest.fixture(scope="module")
+def plans():
+    cache = {}
+
+    def get(dims):
+        if dims not in cache:
+            nx, ny, nz = dims
+            cache[dims] = Plan(synth.make_grid(nx, ny, nz), PREC_FP64 | PREC_MIXED, device=DEV)
+        return cache[dims]
+
+    yield get
+    for p in cache.values():
+        p.close()
+
+
+@pytest.mark.parametrize("dims,cycles", [((33, 33, 33), 1), ((33, 33, 33), 3), ((65, 33, 17), 2),
+                                         ((129, 65, 65), 2)])
+def test_fixed_cycle_algorithm_parity(plans, dims, cycles):
+    """Same V(2,2) method as the oracle's C twin: equal iterates after a fixed
+    number of cycles (2D and 3D)."""
+    nx, ny, nz = dims
+    print(f"[solve] fixed cycles {dims} x{cycles}", flush=True)
+    w = synth.workload("mhs-129", dims=dims)
+    m = w.model
+    plan = plans(dims)
+    # 2D: oracle P0 after `cycles` cycles
+    P0_ref, st, c2, _ = ref.mg2(w.bz0, rtol=0.0, max_cycles=cycles)
+    assert c2 == cycles
+    P = torch.zeros((nz, ny, nx), dtype=torch.float64, device=DEV)
+    bz = torch.from_numpy(w.bz0).to(DEV)
+    info = plan.solve_boundary(bz, P, make_opts(rtol=0.0, max_cycles=cycles), raise_on_error=False)
+    assert info.status == _lib.ERR_NO_CONVERGENCE and info.cycles == cycles
+    assert rel(P[0].cpu().numpy(), P0_ref) < 1e-12
+    # 3D from the oracle's base plane
+    ubc = np.zeros((nz, ny, nx))
+    ubc[0] = P0_ref
+    P3_ref, st, c3, rr = ref.mg3(ubc, m.xi, m.alpha, rtol=0.0, max_cycles=cycles)
+    P.copy_(torch.from_numpy(ubc))
+    info = plan.solve_interior(m, P, make_opts(rtol=0.0, max_cycles=cycles), raise_on_error=False)
+    assert info.status == _lib.ERR_NO_CONVERGENCE and info.cycles == cycles
+    assert abs(info.rel_residual - rr) <= 1e-9 * rr
+    assert rel(P.cpu().numpy(), P3_ref) < 1e-12
+
+
+@pytest.mark.parametrize("name,dims,prec,rtol,tol", [
+    ("potential-33", (33, 33, 33), PREC_FP64, 1e-12, 1e-10),
+    ("potential-33", (33, 33, 33), PREC_MIXED, 1e-10, 1e-8),
+    ("mhs-129", (129, 129, 129), PREC_FP64, 1e-12, 1e-10),
+    ("mhs-129", (129, 129, 129), PREC_MIXED, 1e-10, 1e-8),
+    ("mhs-129", (65, 129, 33), PREC_MIXED, 1e-10, 1e-8),
+])
+def test_solution_parity(plans, name, dims, prec, rtol, tol):
+    print(f"[solve] parity {name} {dims} prec={prec}", flush=True)
+    w = synth.workload(name, dims=dims)
+    m = w.model
+    plan = plans(dims)
+    res = solve(plan, torch.from_numpy(w.bz0).to(DEV), m, precision=prec, rtol=rtol)
+    torch.cuda.synchronize()
+    want_P = exact.solve(w.bz0, dims[2], m.xi, m.alpha)
+    errs = field_errors(res, want_P, m)
+    print(errs, res.info2d, res.info3d)
+    for n, e in errs.items():
+        assert e < tol, (n, e)
+    if m.xi.max() == 0.0:
+        assert errs["dp"] == 0.0 and errs["drho"] == 0.0
+
+
+@pytest.mark.parametrize("run", [0, 3, 5])
+@pytest.mark.parametrize("prec", [PREC_FP64, PREC_MIXED])
+def test_full_size_257_parity(plans, run, prec):
+    """The headline size, in the launch configuration the benchmark uses:
+    every node of P, B, p, rho against the exact discrete solution."""
+    print(f"[solve] 257^3 run {run} prec={prec}", flush=True)
+    w = synth.workload("mhs-257", run=run)
+    m = w.model
+    plan = plans((257, 257, 257))
+    res = solve(plan, torch.from_numpy(w.bz0).to(DEV), m, precision=prec, rtol=1e-10)
+    torch.cuda.synchronize()
+    want_P = exact.solve(w.bz0, 257, m.xi, m.alpha)
+    errs = field_errors(res, want_P, m)
+    print(errs, res.info2d, res.info3d)
+    for n, e in errs.items():
+        assert e < 1e-8, (n, e)
+
+
+def test_repeat_is_bitwise_deterministic(plans):
+    w = synth.workload("mhs-129", dims=(65, 65, 65))
+    plan = plans((65, 65, 65))
+    bz = torch.from_numpy(w.bz0).to(DEV)
+    a = solve(plan, bz, w.model, precision=PREC_MIXED, rtol=1e-10)
+    a = [t.clone() for t in (a.P, a.Bx, a.rho)]
+    b = solve(plan, bz, w.model, precision=PREC_MIXED, rtol=1e-10)
+    for x, y in zip(a, (b.P, b.Bx, b.rho)):
+        assert torch.equal(x, y)
+
+
+def test_check_every_does_not_change_result(plans):
+    """Cycles launched past convergence are no-ops (device-side flag)."""
+    w = synth.workload("mhs-129", dims=(65, 65, 65))
+    m = w.model
+    plan = plans((65, 65, 65))
+    bz = torch.from_numpy(w.bz0).to(DEV)
+    out = []
+    for ce in (1, 3, 50):
+        P = torch.zeros((65, 65, 65), dtype=torch.float64, device=DEV)
+        plan.solve_boundary(bz, P, make_opts(rtol=1e-10, check_every=ce))
+        info = plan.solve_interior(m, P, make_opts(rtol=1e-10, check_every=ce))
+        out.append((P.clone(), info.cycles))
+    for P, c in out[1:]:
+        assert c == out[0][1]
+        assert torch.equal(P, out[0][0])
+
+
+def test_error_paths(plans):
+    w = synth.workload("mhs-129", dims=(33, 33, 33))
+    m = w.model
+    plan = plans((33, 33, 33))
+    P = torch.zeros((33, 33, 33), dtype=torch.float64, device=DEV)
+    bad = synth.Model(m.alpha, m.xi.copy(), m.dxi, m.pb, m.rhob)
+    bad.xi[5] = 1.0
+    with pytest.raises(MHSError) as e:
+        plan.solve_interior(bad, P)
+    assert e.value.code == _lib.ERR_NOT_ELLIPTIC
+    big = synth.Model(7.0, m.xi, m.dxi, m.pb, m.rhob)  # alpha^2 = 49 exceeds pi^2 (1 + 2 min(1 - xi))
+    with pytest.raises(MHSError) as e:
+        plan.solve_interior(big, P)
+    assert e.value.code == _lib.ERR_INDEFINITE
+    with pytest.raises(MHSError) as e:
+        plan.solve_interior(m, P, make_opts(nu1=0))
+    assert e.value.code == _lib.ERR_INVALID_ARG
+    bz = torch.from_numpy(w.bz0).to(DEV)
+    info = plan.solve_boundary(bz, P, make_opts(rtol=1e-14, max_cycles=2), raise_on_error=False)
+    assert info.status == _lib.ERR_NO_CONVERGENCE and info.cycles == 2 and info.rel_residual > 1e-14
+    nan_bz = bz.clone()
+    nan_bz[5, 5] = float("nan")
+    info = plan.solve_boundary(nan_bz, P, make_opts(), raise_on_error=False)
+    assert info.status == _lib.ERR_DIVERGED

@@ -1,0 +1,204 @@
+"""Kernel-level parity: each HIP stage against the oracle's same operation.
+
+Shapes span several tiles with ragged edges in every axis (tiles are 64 x 8
+x 32 nodes for the smoother, 32 x 8 x 16 coarse nodes for the restriction).
+Tolerances: FP64 stages agree to rounding (1e-13 relative); FP32 stages are
+compared with the FP64 oracle at 1e-5 relative.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ref
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1307_6720_amd import PREC_FP64, PREC_MIXED  # noqa: E402
+from paper_1307_6720_amd.solver import Plan  # noqa: E402
+
+DEV = "cuda:0"
+SHAPES = [(33, 33, 33), (17, 33, 129), (33, 65, 65)]  # (nz, ny, nx)
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    d = np.abs(b).max()
+    return float(np.abs(a - b).max() / (d if d > 0 else 1.0))
+
+
+def model_for(nz, alpha=0.7, a=0.6, h=0.2, lz=1.0):
+    z = np.arange(nz) * (lz / (nz - 1))
+    xi, dxi = synth.xi_exponential(z, a, h)
+    pb, rhob = synth.isothermal_background(z)
+    return synth.Model(alpha, xi, dxi, pb, rhob)
+
+
+def bottom_level(plan, model):
+    return plan.bottom_level(3)
+
+
+@pytest.fixture(scope="module", params=SHAPES, ids=lambda s: "x".join(map(str, s)))
+def setup(request):
+    nz, ny, nx = request.param
+    grid = synth.make_grid(nx, ny, nz, 1.0, 1.3, 0.8)
+    plan = Plan(grid, PREC_FP64 | PREC_MIXED, device=DEV)
+    model = model_for(nz, lz=0.8)
+    print(f"[stages] shape {request.param}", flush=True)
+    yield grid, plan, model
+    plan.close()
+
+
+def level_args(plan, model, grid, level):
+    if level >= bottom_level(plan, model):
+        pytest.skip("level handled by the bottom solver")
+    shape = plan.level_shape(3, level)
+    xi = model.xi[:: 2 ** level]
+    lengths = (grid.lx, grid.ly, grid.lz)
+    return shape, xi, lengths
+
+
+def tg(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype)
+
+
+@pytest.mark.parametrize("level", [0, 1])
+@pytest.mark.parametrize("with_f", [False, True])
+@pytest.mark.parametrize("nsweeps", [1, 2, 3])
+def test_smooth3_fp64(setup, level, with_f, nsweeps):
+    grid, plan, model = setup
+    shape, xi, lengths = level_args(plan, model, grid, level)
+    rng = np.random.default_rng(level * 10 + nsweeps)
+    u0 = rng.normal(size=shape)
+    f = rng.normal(size=shape) if with_f else None
+    want = ref.rbgs3(u0, f, xi, model.alpha, nsweeps, lengths)
+    u = tg(u0)
+    plan.stage_smooth(model, 3, level, u, None if f is None else tg(f), nsweeps)
+    assert rel(u.cpu().numpy(), want) < 1e-13
+
+
+def test_smooth3_fp32(setup):
+    grid, plan, model = setup
+    shape, xi, lengths = level_args(plan, model, grid, 0)
+    rng = np.random.default_rng(7)
+    u0 = rng.normal(size=shape).astype(np.float32).astype(np.float64)
+    f = rng.normal(size=shape).astype(np.float32).astype(np.float64)
+    want = ref.rbgs3(u0, f, xi, model.alpha, 2, lengths)
+    u = tg(u0, torch.float32)
+    plan.stage_smooth(model, 3, 0, u, tg(f, torch.float32), 2, precision=PREC_MIXED)
+    assert rel(u.double().cpu().numpy(), want) < 1e-5
+
+
+@pytest.mark.parametrize("level", [0, 1])
+def test_restrict3(setup, level):
+    grid, plan, model = setup
+    shape, xi, lengths = level_args(plan, model, grid, level)
+    cshape = plan.level_shape(3, level + 1)
+    rng = np.random.default_rng(level + 3)
+    u = rng.normal(size=shape)
+    f = rng.normal(size=shape) if level > 0 else None
+    want = ref.restrict3(ref.residual3(u, f, xi, model.alpha, lengths))
+    fc = torch.zeros(cshape, dtype=torch.float64, device=DEV)
+    plan.stage_restrict(model, 3, level, tg(u), None if f is None else tg(f), fc)
+    assert rel(fc.cpu().numpy(), want) < 1e-13
+
+
+def test_restrict3_fp32(setup):
+    grid, plan, model = setup
+    shape, xi, lengths = level_args(plan, model, grid, 0)
+    cshape = plan.level_shape(3, 1)
+    rng = np.random.default_rng(5)
+    u = rng.normal(size=shape).astype(np.float32).astype(np.float64)
+    f = rng.normal(size=shape).astype(np.float32).astype(np.float64)
+    want = ref.restrict3(ref.residual3(u, f, xi, model.alpha, lengths))
+    fc = torch.zeros(cshape, dtype=torch.float32, device=DEV)
+    plan.stage_restrict(model, 3, 0, tg(u, torch.float32), tg(f, torch.float32), fc, precision=PREC_MIXED)
+    assert rel(fc.double().cpu().numpy(), want) < 1e-5
+
+
+@pytest.mark.parametrize("level", [0, 1])
+def test_correct_smooth3(setup, level):
+    grid, plan, model = setup
+    shape, xi, lengths = level_args(plan, model, grid, level)
+    cshape = plan.level_shape(3, level + 1)
+    rng = np.random.default_rng(level + 11)
+    u0 = rng.normal(size=shape)
+    f = rng.normal(size=shape)
+    ec = rng.normal(size=cshape)
+    ec[0] = ec[-1] = 0
+    ec[:, 0] = ec[:, -1] = 0
+    ec[:, :, 0] = ec[:, :, -1] = 0
+    want = ref.rbgs3(ref.prolong3(ec, u0), f, xi, model.alpha, 1, lengths)
+    u = tg(u0)
+    plan.stage_correct_smooth(model, 3, level, u, tg(f), tg(ec))
+    assert rel(u.cpu().numpy(), want) < 1e-13
+
+
+def test_bottom3(setup):
+    """The bottom solver equals one oracle V-cycle from a zero guess on the
+    plan's bottom level (coarsest level solved exactly)."""
+    grid, plan, model = setup
+    b = bottom_level(plan, model)
+    shape = plan.level_shape(3, b)
+    rng = np.random.default_rng(1)
+    f = rng.normal(size=shape)
+    u = torch.zeros(shape, dtype=torch.float64, device=DEV)
+    assert plan.stage_bottom(model, 3, u, tg(f)) == b
+    xi = model.xi[:: 2 ** b]
+    lengths = (grid.lx, grid.ly, grid.lz)
+    want = ref.vcycle3_once(np.zeros(shape), f, xi, model.alpha, 2, 2, lengths)
+    assert rel(u.cpu().numpy(), want) < 1e-12
+    # FP32 storage, FP64 arithmetic inside
+    u32 = torch.zeros(shape, dtype=torch.float32, device=DEV)
+    f32 = f.astype(np.float32)
+    plan.stage_bottom(model, 3, u32, tg(f32, torch.float32), precision=PREC_MIXED)
+    want32 = ref.vcycle3_once(np.zeros(shape), f32.astype(np.float64), xi, model.alpha, 2, 2, lengths)
+    assert rel(u32.double().cpu().numpy(), want32) < 1e-6
+
+
+@pytest.mark.parametrize("level", [0, 1])
+def test_residual_norm3(setup, level):
+    grid, plan, model = setup
+    shape, xi, lengths = level_args(plan, model, grid, level)
+    rng = np.random.default_rng(level + 21)
+    u = rng.normal(size=shape)
+    f = rng.normal(size=shape)
+    want = ref.norm3_interior(ref.residual3(u, f, xi, model.alpha, lengths))
+    got = plan.stage_residual_norm(model, 3, level, tg(u), tg(f))
+    assert abs(got - want) / want < 1e-13
+
+
+# ---------------------------------------------------------------- 2D stages
+@pytest.mark.parametrize("nsweeps", [1, 2])
+def test_smooth2(setup, nsweeps):
+    grid, plan, model = setup
+    shape = plan.level_shape(2, 0)
+    rng = np.random.default_rng(nsweeps)
+    u0 = rng.normal(size=shape)
+    f = rng.normal(size=shape)
+    want = ref.rbgs2(u0, f, nsweeps, (grid.lx, grid.ly))
+    u = tg(u0)
+    plan.stage_smooth(None, 2, 0, u, tg(f), nsweeps)
+    assert rel(u.cpu().numpy(), want) < 1e-13
+
+
+def test_restrict2_correct2(setup):
+    grid, plan, model = setup
+    shape = plan.level_shape(2, 0)
+    cshape = plan.level_shape(2, 1)
+    rng = np.random.default_rng(4)
+    u = rng.normal(size=shape)
+    f = rng.normal(size=shape)
+    want = ref.restrict2(ref.residual2(u, f, (grid.lx, grid.ly)))
+    fc = torch.zeros(cshape, dtype=torch.float64, device=DEV)
+    plan.stage_restrict(None, 2, 0, tg(u), tg(f), fc)
+    assert rel(fc.cpu().numpy(), want) < 1e-13
+    ec = rng.normal(size=cshape)
+    ec[0] = ec[-1] = 0
+    ec[:, 0] = ec[:, -1] = 0
+    want = ref.rbgs2(ref.prolong2(ec, u), f, 1, (grid.lx, grid.ly))
+    ut = tg(u)
+    plan.stage_correct_smooth(None, 2, 0, ut, tg(f), tg(ec))
+    assert rel(ut.cpu().numpy(), want) < 1e-13
