@@ -43,8 +43,24 @@ int fail(int code, const char *fmt, ...)
 
 constexpr size_t kAlign = 256;
 constexpr size_t kStagingBytes = 1 << 20;
-constexpr size_t kBottomMax3 = 5000; // 3D levels this small go to the single-workgroup solver
-constexpr size_t kBottomMax2 = 4300; // 2D likewise (65 x 65)
+// Workgroups a stencil launch aims for: enough to keep every CU busy with
+// several resident groups while keeping each group's z-march short.
+constexpr int kTargetGroups = 2048;
+
+// LDS bytes of a bottom solver starting at level l: u and f of every level
+// from l down, plus a residual array of level l.
+size_t bottom_lds(const Hierarchy &h, int l)
+{
+    size_t n = 0;
+    for (int q = l; q < h.L; ++q) n += 2 * h.lv[q].N;
+    return 8 * (n + h.lv[l].N);
+}
+
+int chunk(int planes, int xy_tiles, int cap)
+{
+    const long want = ((long)planes * xy_tiles + kTargetGroups - 1) / kTargetGroups;
+    return (int)std::max(1L, std::min((long)cap, want));
+}
 
 struct Carver {
     char *base;
@@ -109,29 +125,38 @@ int build_geometry(Hierarchy &h, const int n0[3], const double len[3], bool plan
     h.m = (c.n[0] - 2) * (c.n[1] - 2) * (planar ? 1 : c.n[2] - 2);
     if (h.m > kMaxCoarse)
         return fail(MHS_ERR_GRID, "coarsest grid has %d unknowns (max %d): axes too unequal", h.m, kMaxCoarse);
-    const size_t bmax = planar ? kBottomMax2 : kBottomMax3;
-    h.b = L - 1;
+    h.b = -1;
     for (int l = 1; l < L; ++l)
-        if (h.lv[l].N <= bmax) {
+        if (bottom_lds(h, l) <= (size_t)kBottomLdsMax) {
             h.b = l;
             break;
         }
+    if (h.b < 0) return fail(MHS_ERR_GRID, "coarsest grid too large for the LDS bottom solver");
+    h.lds_bytes = (int)bottom_lds(h, h.b);
     for (int l = 0; l < L; ++l) {
         Level &lv = h.lv[l];
         if (planar) {
             lv.st[0] = ceil_div(lv.n[0] - 2, kTX);
             lv.st[1] = ceil_div(lv.n[1] - 2, kTY2);
             lv.st[2] = 1;
+            lv.kz = 1;
         } else {
             lv.st[0] = ceil_div(lv.n[0] - 2, kTX);
             lv.st[1] = ceil_div(lv.n[1] - 2, kTY);
-            lv.st[2] = ceil_div(lv.n[2] - 2, kKZ);
+            lv.kz = chunk(lv.n[2] - 2, lv.st[0] * lv.st[1], kKZ);
+            lv.st[2] = ceil_div(lv.n[2] - 2, lv.kz);
         }
         if (l + 1 < L) {
             const Level &c2 = h.lv[l + 1];
             lv.rt[0] = ceil_div(c2.n[0] - 2, kCX);
             lv.rt[1] = ceil_div(c2.n[1] - 2, kCY);
-            lv.rt[2] = planar ? 1 : ceil_div(c2.n[2] - 2, kKC);
+            if (planar) {
+                lv.rt[2] = 1;
+                lv.kc = 1;
+            } else {
+                lv.kc = chunk(c2.n[2] - 2, lv.rt[0] * lv.rt[1], kKC);
+                lv.rt[2] = ceil_div(c2.n[2] - 2, lv.kc);
+            }
         }
     }
     return MHS_OK;
@@ -166,11 +191,6 @@ void carve_hierarchy(Hierarchy &h, Carver &cv, int paths)
         lv.coef64 = cv.take<double>(4 * (size_t)lv.n[2]);
         if (paths & 2) lv.coef32 = cv.take<float>(4 * (size_t)lv.n[2]);
     }
-    for (int l = b; l < L; ++l) {
-        h.bu[l] = cv.take<double>(h.lv[l].N);
-        h.bf[l] = cv.take<double>(h.lv[l].N);
-    }
-    h.br = cv.take<double>(h.lv[b].N);
     h.minv = cv.take<double>((size_t)h.m * h.m);
     h.npart = l0.sweep_tiles();
     h.partials = cv.take<double>(h.npart);
@@ -429,6 +449,7 @@ void add_sweep(Program &pg, Staging &st, const Hierarchy &h, int l, int path, co
     it.ntx = lv.st[0];
     it.nty = lv.st[1];
     it.ntz = lv.st[2];
+    it.kz = lv.kz;
     it.tile_base = 0;
     const LevelItem *d = st.put(it);
     if (!d) {
@@ -457,6 +478,7 @@ void add_restrict(Program &pg, Staging &st, const Hierarchy &h, int l, int path,
     it.ntx = lv.rt[0];
     it.nty = lv.rt[1];
     it.ntz = lv.rt[2];
+    it.kz = lv.kc;
     const LevelItem *d = st.put(it);
     if (!d) {
         pg.ok = false;
@@ -478,15 +500,18 @@ BottomItem bottom_item(const Hierarchy &h, int path, const void *f_top, void *u_
     b.f_top = f_top;
     b.u_top = u_top;
     const int nl = h.L - h.b;
+    int off = 0;
     for (int q = 0; q < nl; ++q) {
         const int l = h.b + q;
-        b.u[q] = h.bu[l];
-        b.f[q] = h.bf[l];
         b.coef[q] = h.lv[l].coef64;
         b.cz[q] = h.lv[l].cz;
         for (int a = 0; a < 3; ++a) b.n[q][a] = h.lv[l].n[a];
+        b.off_u[q] = off;
+        off += (int)h.lv[l].N;
+        b.off_f[q] = off;
+        off += (int)h.lv[l].N;
     }
-    b.r = h.br;
+    b.off_r = off;
     b.nlev = nl;
     b.m = h.m;
     b.nu1 = nu1;
@@ -510,6 +535,7 @@ void add_bottom(Program &pg, Staging &st, const Hierarchy &h, int path, const vo
     L.kind = Launch::kBottom;
     L.dbl = path == kF64;
     L.items = d;
+    L.lds = h.lds_bytes;
     pg.launches.push_back(L);
 }
 
@@ -605,7 +631,7 @@ int run_program(const Program &pg, hipStream_t s)
             e = launch_ir3((const LevelItem *)L.items, L.nitems, L.ntiles, L.flags != 0, s);
             break;
         case Launch::kBottom:
-            e = launch_bottom((const BottomItem *)L.items, L.nitems, L.dbl, s);
+            e = launch_bottom((const BottomItem *)L.items, L.nitems, L.lds, L.dbl, s);
             break;
         case Launch::kFinalize:
             e = launch_finalize((const FinalizeItem *)L.items, L.nitems, s);
@@ -972,6 +998,7 @@ int mhs_solve_interior(mhs_plan *p, const mhs_model *model, double *d_P, const m
             it.ntx = l0.st[0];
             it.nty = l0.st[1];
             it.ntz = l0.st[2];
+            it.kz = l0.kz;
             const LevelItem *d = p->stage.put(it);
             if (!d) {
                 pg.ok = false;
@@ -1073,7 +1100,8 @@ int mhs_fields(mhs_plan *p, const mhs_model *model, const double *d_P, double *d
     fi.nz = nz;
     fi.ntx = ceil_div(nx, kTX);
     fi.nty = ceil_div(ny, kFY);
-    fi.ntz = ceil_div(nz, kKZ);
+    fi.kz = chunk(nz, fi.ntx * fi.nty, kKZ);
+    fi.ntz = ceil_div(nz, fi.kz);
     fi.tile_base = 0;
     const FieldsItem *d = p->stage.put(fi);
     if (!d) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
@@ -1113,6 +1141,16 @@ int stage_common(mhs_plan *p, const mhs_model *model, int space, int level, int 
 // the level's ping-pong twin for stage calls
 void *stage_twin(Hierarchy &h, int level, int path) { return h.lv[level].t[path]; }
 
+// Stage calls borrow a solver twin as scratch; the solver relies on the
+// boundary nodes of every twin being zero (the level-0 FP64 twin is reset by
+// each interior solve), so clear the borrowed buffer afterwards.
+int release_twin(Hierarchy &h, int level, int path, hipStream_t s)
+{
+    const size_t bytes = h.lv[level].N * (path == kF64 ? 8 : 4);
+    HIPCHK(hipMemsetAsync(h.lv[level].t[path], 0, bytes, s));
+    return MHS_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -1143,7 +1181,7 @@ int mhs_stage_smooth(mhs_plan *p, const mhs_model *model, int32_t space, int32_t
     if ((st = flush_staging(p, s))) return st;
     if ((st = run_program(pg, s))) return st;
     if (cur != d_u) HIPCHK(hipMemcpyAsync(d_u, cur, bytes, hipMemcpyDeviceToDevice, s));
-    return MHS_OK;
+    return release_twin(*h, level, path, s);
 }
 
 int mhs_stage_restrict(mhs_plan *p, const mhs_model *model, int32_t space, int32_t level, int32_t precision,
@@ -1184,7 +1222,7 @@ int mhs_stage_correct_smooth(mhs_plan *p, const mhs_model *model, int32_t space,
     if ((st = flush_staging(p, s))) return st;
     if ((st = run_program(pg, s))) return st;
     HIPCHK(hipMemcpyAsync(d_u, tw, bytes, hipMemcpyDeviceToDevice, s));
-    return MHS_OK;
+    return release_twin(*h, level, path, s);
 }
 
 int mhs_stage_bottom(mhs_plan *p, const mhs_model *model, int32_t space, int32_t precision, void *d_u,
@@ -1225,6 +1263,7 @@ int mhs_stage_residual_norm(mhs_plan *p, const mhs_model *model, int32_t space, 
     if (!pg.ok || !d_state) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
     if ((st = flush_staging(p, s))) return st;
     if ((st = run_program(pg, s))) return st;
+    if ((st = release_twin(*h, level, path, s))) return st;
     SolveState ss{};
     if ((st = read_state(p, d_state, &ss, s))) return st;
     *norm = ss.rnorm;

@@ -18,10 +18,18 @@ constexpr int kMaxLevels = 16;
 // ---- tile geometry ---------------------------------------------------------
 // 3D smoother / refinement residual: x-y tile of kTX x kTY interior nodes,
 // marching kKZ planes in z; 256 threads.
+#ifndef MHS_TILE_Y
+#define MHS_TILE_Y 8
+#endif
+#ifndef MHS_RING_DEPTH
+#define MHS_RING_DEPTH 4
+#endif
 constexpr int kTX = 64;
-constexpr int kTY = 8;
+constexpr int kTY = MHS_TILE_Y;
 constexpr int kKZ = 32;
 constexpr int kThreads = 256;
+// planes of HBM loads a marching kernel keeps in flight (register ring)
+constexpr int kDepth = MHS_RING_DEPTH;
 // 3D residual + restriction: kCX x kCY coarse nodes per workgroup, marching
 // kKC coarse planes.
 constexpr int kCX = 32;
@@ -64,27 +72,32 @@ struct LevelItem {
     int32_t ncx, ncy, ncz; // nodes of the next coarser level
     int32_t ntx, nty, ntz; // tiles per axis
     int32_t tile_base;     // first global tile of this item in its launch
+    int32_t kz;            // planes per workgroup (smoother: fine planes, restriction: coarse planes)
+    int32_t pad;
 };
 
 // One request of the bottom solver: a full V-cycle from level `top` of the
-// bottom hierarchy to the coarsest grid, in FP64, by a single workgroup.
+// bottom hierarchy to the coarsest grid, in FP64, by a single workgroup whose
+// work arrays all live in LDS (offsets in doubles into dynamic shared memory).
 struct BottomItem {
     const void *f_top;            // right-hand side at the top bottom level (storage type)
     void *u_top;                  // correction written back (storage type)
-    double *u[kMaxLevels];        // FP64 work arrays (levels of the bottom hierarchy)
-    double *f[kMaxLevels];
-    double *r;                    // residual scratch (size of the top level)
     const double *coef[kMaxLevels];
     double cz[kMaxLevels];
     int32_t n[kMaxLevels][3];
+    int32_t off_u[kMaxLevels];    // LDS offsets (doubles)
+    int32_t off_f[kMaxLevels];
+    int32_t off_r;
     int32_t nlev;
     int32_t m;                    // unknowns of the coarsest grid
     int32_t nu1, nu2;
     int32_t planar;               // 1 = 2D problem
-    int32_t pad;
     const double *minv;           // m x m inverse of the coarsest operator
     SolveState *state;
 };
+
+// LDS bytes a bottom hierarchy needs (u and f per level, r for the top level).
+constexpr int kBottomLdsMax = 160 * 1024;
 
 struct FinalizeItem {
     const double *partials;
@@ -102,7 +115,7 @@ struct FieldsItem {
     int32_t nx, ny, nz;
     int32_t ntx, nty, ntz;
     int32_t tile_base;
-    int32_t pad;
+    int32_t kz;
 };
 
 // Whole-array preparation items.
@@ -135,7 +148,7 @@ hipError_t launch_restrict3(const LevelItem *items, int nitems, int ntiles, bool
 hipError_t launch_restrict2(const LevelItem *items, int nitems, int ntiles, bool dbl,
                             hipStream_t s);
 hipError_t launch_ir3(const LevelItem *items, int nitems, int ntiles, bool has_e, hipStream_t s);
-hipError_t launch_bottom(const BottomItem *items, int nitems, bool dbl, hipStream_t s);
+hipError_t launch_bottom(const BottomItem *items, int nitems, int lds_bytes, bool dbl, hipStream_t s);
 hipError_t launch_finalize(const FinalizeItem *items, int nitems, hipStream_t s);
 hipError_t launch_fields(const FieldsItem *items, int nitems, int ntiles, hipStream_t s);
 hipError_t launch_prep3(const PrepItem *items, int nitems, int64_t nthreads, hipStream_t s);

@@ -16,6 +16,31 @@
 namespace mhs {
 namespace {
 
+// Descriptor pointers arrive without an address space, which would make every
+// access a FLAT instruction; FLAT counts against the LDS wait counter too, so
+// each LDS barrier would also wait for all outstanding HBM loads.  All
+// buffers are device (global) memory: say so.
+#define MHS_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const MHS_GLOBAL T *gin(const void *p)
+{
+    return (const MHS_GLOBAL T *)p;
+}
+template <typename T>
+__device__ __forceinline__ MHS_GLOBAL T *gout(void *p)
+{
+    return (MHS_GLOBAL T *)p;
+}
+// Small read-only tables indexed by workgroup-uniform values (per-plane
+// coefficients): the constant address space lets them use scalar loads,
+// which do not share the vector-memory wait counter with the plane prefetch.
+#define MHS_CONST __attribute__((address_space(4)))
+template <typename T>
+__device__ __forceinline__ const MHS_CONST T *gconst(const void *p)
+{
+    return (const MHS_CONST T *)p;
+}
+
 template <typename Item>
 __device__ __forceinline__ int find_item(const Item *items, int n, int tile)
 {
@@ -28,6 +53,30 @@ __device__ __forceinline__ int find_item(const Item *items, int n, int tile)
             hi = mid - 1;
     }
     return lo;
+}
+
+// Workgroup barrier that orders LDS traffic only.  The kernels share data
+// between threads exclusively through LDS, so the barrier must not wait for
+// outstanding global loads (a plain __syncthreads() would, which drains the
+// prefetch ring at every step) or stores.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b % 8), each with its own L2.  Remap so that each XCD receives one
+// contiguous range of tiles: neighbouring tiles, which re-read each other's
+// halo rows, then share an L2 and run at about the same time.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile()
+{
+    const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+    const int x = b % kXcds, q = b / kXcds;
+    const int per = nb / kXcds, rem = nb % kXcds;
+    return x * per + min(x, rem) + q;
 }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -44,7 +93,7 @@ __device__ __forceinline__ double block_sum(double v, double *red)
     v = wave_sum(v);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (lane == 0) red[w] = v;
-    __syncthreads();
+    lds_barrier();
     double s = 0.0;
     if (threadIdx.x == 0) {
 #pragma unroll
@@ -55,47 +104,73 @@ __device__ __forceinline__ double block_sum(double v, double *red)
 
 // Trilinear interpolation of the coarse correction at fine node (i, j, k):
 // coincident nodes copy, edge/face/cell midpoints average 2/4/8 values.
-template <typename T>
-__device__ __forceinline__ T interp3(const T *__restrict__ ec, int ncx, int ncy, int i, int j, int k)
+template <typename T, typename Ptr>
+__device__ __forceinline__ T interp3(Ptr ec, int ncx, int ncy, int i, int j, int k)
 {
     const size_t sy = (size_t)ncx, sz = (size_t)ncx * ncy;
-    const T *p = ec + (size_t)(i >> 1) + sy * (size_t)(j >> 1) + sz * (size_t)(k >> 1);
+    const Ptr p = ec + (size_t)(i >> 1) + sy * (size_t)(j >> 1) + sz * (size_t)(k >> 1);
     const int oi = i & 1, oj = j & 1, ok = k & 1;
     const T h = (T)0.5;
-    auto X = [&](const T *q) { return oi ? h * (q[0] + q[1]) : q[0]; };
-    auto Y = [&](const T *q) { return oj ? h * (X(q) + X(q + sy)) : X(q); };
+    auto X = [&](Ptr q) -> T { return oi ? h * (q[0] + q[1]) : (T)q[0]; };
+    auto Y = [&](Ptr q) -> T { return oj ? h * (X(q) + X(q + sy)) : X(q); };
     return ok ? h * (Y(p) + Y(p + sz)) : Y(p);
 }
 
-template <typename T>
-__device__ __forceinline__ T interp2(const T *__restrict__ ec, int ncx, int i, int j)
+template <typename T, typename Ptr>
+__device__ __forceinline__ T interp2(Ptr ec, int ncx, int i, int j)
 {
     const size_t sy = (size_t)ncx;
-    const T *p = ec + (size_t)(i >> 1) + sy * (size_t)(j >> 1);
+    const Ptr p = ec + (size_t)(i >> 1) + sy * (size_t)(j >> 1);
     const int oi = i & 1, oj = j & 1;
     const T h = (T)0.5;
-    auto X = [&](const T *q) { return oi ? h * (q[0] + q[1]) : q[0]; };
+    auto X = [&](Ptr q) -> T { return oi ? h * (q[0] + q[1]) : (T)q[0]; };
     return oj ? h * (X(p) + X(p + sy)) : X(p);
 }
 
 // ============================================================================
 // 3D red-black Gauss-Seidel sweep, ping-pong (u_in -> u_out).
 //
-// A workgroup owns kTX x kTY interior nodes of kKZ consecutive planes.  It
-// stages a (kTY+4) x (kTX+4) window of each plane in LDS (four planes in
-// flight) and marches up in z: at step s it updates the red nodes of plane
+// A workgroup owns kTX x kTY interior nodes of `kz` consecutive planes.  It
+// stages a (kTY+4) x (kTX+4) window of each plane in LDS (four planes
+// resident) and marches up in z: at step s it updates the red nodes of plane
 // s on the tile plus a one-node ring, then the black nodes of plane s-1 on
 // the tile, whose red neighbours (planes s-2, s-1, s) are all final by
 // then.  Red nodes of the ring are recomputed from u_in, so neighbouring
 // tiles never read each other's output and one pass is one complete sweep,
 // identical to updating all red nodes and then all black nodes.
+//
+// Loads run kDepth planes ahead of the stencil in a ring of register sets,
+// so kDepth planes of HBM traffic are in flight per workgroup.  With the
+// prolongation-fused variant each register set also carries the two coarse
+// planes the fine plane interpolates from; they are staged in LDS when the
+// fine plane is, and the trilinear correction is added there.
 // ============================================================================
 constexpr int kWX = kTX + 4;
 constexpr int kWY = kTY + 4;
+constexpr int kWCells = kWX * kWY;
+// LDS rows store even columns first, then odd columns, so the colour phases
+// (which touch every other column) read consecutive doubles: no bank conflicts
+constexpr int kHalf = kWX / 2;
+__device__ __forceinline__ int sx(int c) { return (c & 1) * kHalf + (c >> 1); }
+static_assert(kWX % 2 == 0, "window width must be even");
+constexpr int kWPer = (kWCells + kThreads - 1) / kThreads;
 constexpr int kRedPerRow = kTX / 2 + 1;
 constexpr int kBlackPerRow = kTX / 2;
 constexpr int kOwn = kTY * kTX / kThreads;
+constexpr int kCWX = kTX / 2 + 4;
+constexpr int kCWY = kTY / 2 + 4;
+constexpr int kCCells = 2 * kCWX * kCWY;
+constexpr int kCPer = (kCCells + kThreads - 1) / kThreads;
 static_assert(kTY * kTX % kThreads == 0, "tile must be a multiple of the block");
+
+// right-hand-side window: the tile plus a one-node ring, colour-split too
+constexpr int kFX = kTX + 2;
+constexpr int kFY3 = kTY + 2;
+constexpr int kFCells3 = kFX * kFY3;
+constexpr int kFPer3 = (kFCells3 + kThreads - 1) / kThreads;
+constexpr int kFHalf = kFX / 2;
+__device__ __forceinline__ int sxf(int c) { return (c & 1) * kFHalf + (c >> 1); }
+static_assert(kFX % 2 == 0, "rhs window width must be even");
 
 template <typename T, int FLAGS>
 __global__ __launch_bounds__(kThreads) void k_sweep3(const LevelItem *__restrict__ items, int nitems)
@@ -104,46 +179,131 @@ __global__ __launch_bounds__(kThreads) void k_sweep3(const LevelItem *__restrict
     constexpr bool ZERO_IN = (FLAGS & kZeroIn) != 0;
     constexpr bool NORM = (FLAGS & kNorm) != 0;
     constexpr bool PROLONG = (FLAGS & kProlong) != 0;
+    // register-ring depth (planes of loads in flight); shallower when every
+    // plane also carries right-hand-side or coarse-correction data
+    constexpr int D = (HAS_F || PROLONG) ? 3 : kDepth;
+    constexpr int kCWPlanes = PROLONG ? 2 : 1;
+    constexpr int kFSlots = HAS_F ? 4 : 1;
     __shared__ T S[4][kWY][kWX];
+    __shared__ T F[kFSlots][kFY3][kFX];
+    __shared__ T CW[kCWPlanes][kCWY][kCWX];
     __shared__ double red[kThreads / 64];
 
-    const int tile = blockIdx.x;
+    const int tile = xcd_tile();
     const LevelItem *it = items + find_item(items, nitems, tile);
-    if (it->state && it->state->done) return;
-    const T *__restrict__ uin = (const T *)it->u_in;
-    T *__restrict__ uout = (T *)it->u_out;
-    const T *__restrict__ f = (const T *)it->f;
-    const T *__restrict__ ec = (const T *)it->ec;
-    const T *__restrict__ coef = (const T *)it->coef;
+    if (it->state && gin<SolveState>(it->state)->done) return;
+    const MHS_GLOBAL T *__restrict__ uin = gin<T>(it->u_in);
+    MHS_GLOBAL T *__restrict__ uout = gout<T>(it->u_out);
+    const MHS_GLOBAL T *__restrict__ f = gin<T>(it->f);
+    const MHS_GLOBAL T *__restrict__ ec = gin<T>(it->ec);
+    const MHS_CONST T *__restrict__ coef = gconst<T>(it->coef);
     const T cz = (T)it->cz;
     const int nx = it->nx, ny = it->ny, nz = it->nz;
     const int ncx = it->ncx, ncy = it->ncy;
+    const int kz = it->kz;
     int local = tile - it->tile_base;
     const int tx = local % it->ntx;
     local /= it->ntx;
     const int ty = local % it->nty;
     const int tz = local / it->nty;
     const int i0 = 1 + tx * kTX, j0 = 1 + ty * kTY;
-    const int kb = 1 + tz * kKZ;
-    const int ke = min(kb + kKZ, nz - 1);
+    const int kb = 1 + tz * kz;
+    const int ke = min(kb + kz, nz - 1);
+    const int ptop = min(ke + 1, nz - 1); // highest plane read
     const size_t sxy = (size_t)nx * ny;
+    const size_t csxy = (size_t)ncx * ncy;
     const int tid = threadIdx.x;
+    const int I0 = (i0 - 2) >> 1, J0 = (j0 - 2) >> 1; // coarse window origin
 
-    auto load_plane = [&](int p) {
-        T(*dst)[kWX] = S[p & 3];
-        for (int e = tid; e < kWY * kWX; e += kThreads) {
-            const int w = e / kWX, c = e - w * kWX;
-            const int i = i0 - 2 + c, j = j0 - 2 + w;
-            T v = (T)0;
-            if (i >= 0 && i < nx && j >= 0 && j < ny) {
-                const size_t idx = (size_t)i + (size_t)nx * j + sxy * p;
-                if constexpr (!ZERO_IN) v = uin[idx];
-                if constexpr (PROLONG) {
-                    if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2 && p >= 1 && p <= nz - 2)
-                        v += interp3(ec, ncx, ncy, i, j, p);
+    T pre[D][kWPer];
+    T fpre[D][kFPer3];
+    T cpre[D][kCPer];
+    // Loads are unconditional, from clamped in-bounds addresses, straight
+    // into the ring registers; cells outside the array are zeroed when the
+    // plane is staged.  (A conditional load into a zero-initialised register
+    // forces the compiler to drain every outstanding load first.)
+    auto fetch = [&](int p, T(&dst)[kWPer], T(&fdst)[kFPer3], T(&cdst)[kCPer]) {
+        if constexpr (!ZERO_IN) {
+#pragma unroll
+            for (int r = 0; r < kWPer; ++r) {
+                const int e = min(tid + r * kThreads, kWCells - 1);
+                const int w = e / kWX, c = e - w * kWX;
+                const int i = min(max(i0 - 2 + c, 0), nx - 1), j = min(max(j0 - 2 + w, 0), ny - 1);
+                dst[r] = uin[(size_t)i + (size_t)nx * j + sxy * p];
+            }
+        }
+        if constexpr (HAS_F) {
+#pragma unroll
+            for (int r = 0; r < kFPer3; ++r) {
+                const int e = min(tid + r * kThreads, kFCells3 - 1);
+                const int w = e / kFX, c = e - w * kFX;
+                const int i = min(i0 - 1 + c, nx - 1), j = min(j0 - 1 + w, ny - 1);
+                fdst[r] = f[(size_t)i + (size_t)nx * j + sxy * p];
+            }
+        }
+        if constexpr (PROLONG) {
+            const int K0 = p >> 1, K1 = (p + 1) >> 1;
+#pragma unroll
+            for (int r = 0; r < kCPer; ++r) {
+                const int e = min(tid + r * kThreads, kCCells - 1);
+                const int pl = e / (kCWX * kCWY);
+                const int rem = e - pl * (kCWX * kCWY);
+                const int w = rem / kCWX, c = rem - w * kCWX;
+                const int I = min(max(I0 + c, 0), ncx - 1), J = min(max(J0 + w, 0), ncy - 1);
+                cdst[r] = ec[(size_t)I + (size_t)ncx * J + csxy * (pl ? K1 : K0)];
+            }
+        }
+    };
+    // coarse correction at fine node (i, j, p) from the LDS coarse window:
+    // coincident nodes copy, midpoints average 2/4/8 values (trilinear)
+    auto corr = [&](int i, int j, int p) {
+        const int lc = (i >> 1) - I0, lw = (j >> 1) - J0;
+        const int oi = i & 1, oj = j & 1, ok = p & 1;
+        const T h = (T)0.5;
+        auto X = [&](int pl, int w) { return oi ? h * (CW[pl][w][lc] + CW[pl][w][lc + 1]) : CW[pl][w][lc]; };
+        auto Y = [&](int pl) { return oj ? h * (X(pl, lw) + X(pl, lw + 1)) : X(pl, lw); };
+        return ok ? h * (Y(0) + Y(1)) : Y(0);
+    };
+    auto stash = [&](int p, const T(&src)[kWPer], const T(&fsrc)[kFPer3], const T(&csrc)[kCPer], bool sync_first) {
+        if constexpr (PROLONG) {
+            if (sync_first) lds_barrier();
+#pragma unroll
+            for (int r = 0; r < kCPer; ++r) {
+                const int e = tid + r * kThreads;
+                if (e < kCCells) {
+                    const int pl = e / (kCWX * kCWY);
+                    const int rem = e - pl * (kCWX * kCWY);
+                    const int w = rem / kCWX, c = rem - w * kCWX;
+                    CW[pl][w][c] = csrc[r];
                 }
             }
-            dst[w][c] = v;
+            lds_barrier();
+        }
+        T(*dst)[kWX] = S[p & 3];
+#pragma unroll
+        for (int r = 0; r < kWPer; ++r) {
+            const int e = tid + r * kThreads;
+            if (e < kWCells) {
+                const int w = e / kWX, c = e - w * kWX;
+                const int i = i0 - 2 + c, j = j0 - 2 + w;
+                T v = (T)0;
+                if (!ZERO_IN && i >= 0 && i < nx && j >= 0 && j < ny) v = src[r];
+                if constexpr (PROLONG) {
+                    if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2 && p >= 1 && p <= nz - 2) v += corr(i, j, p);
+                }
+                dst[w][sx(c)] = v;
+            }
+        }
+        if constexpr (HAS_F) {
+            T(*fd)[kFX] = F[p & 3];
+#pragma unroll
+            for (int r = 0; r < kFPer3; ++r) {
+                const int e = tid + r * kThreads;
+                if (e < kFCells3) {
+                    const int w = e / kFX, c = e - w * kFX;
+                    fd[w][sxf(c)] = fsrc[r];
+                }
+            }
         }
     };
 
@@ -152,97 +312,121 @@ __global__ __launch_bounds__(kThreads) void k_sweep3(const LevelItem *__restrict
 #pragma unroll
     for (int q = 0; q < kOwn; ++q) below[q] = (T)0;
 
-    if (kb - 2 >= 0) load_plane(kb - 2);
-    load_plane(kb - 1);
-    for (int s = kb - 1; s <= ke; ++s) {
-        if (s + 1 <= nz - 1) load_plane(s + 1);
-        __syncthreads();
-        if constexpr (NORM) {
-            // residual of the input iterate at plane s (all values still old);
-            // the old plane s-1 comes from registers captured one step earlier
-            T(*P)[kWX] = S[s & 3];
-            T(*Pp)[kWX] = S[(s + 1) & 3];
-            const bool do_res = (s >= kb && s < ke);
-            T cx = 0, cy = 0, d = 0;
-            if (do_res) {
-                cx = coef[4 * s];
-                cy = coef[4 * s + 1];
-                d = coef[4 * s + 2];
-            }
+    // plane p waits in register set (p - pbase) % D until it is staged
+    const int pbase = kb - 2;
 #pragma unroll
-            for (int q = 0; q < kOwn; ++q) {
-                const int e = tid + q * kThreads;
-                const int w = 2 + e / kTX, c = 2 + e % kTX;
-                const T uc = P[w][c];
+    for (int q = 0; q < D; ++q) {
+        const int p = pbase + q;
+        if (p >= 0 && p <= ptop) fetch(p, pre[q], fpre[q], cpre[q]);
+    }
+    if (pbase >= 0) stash(pbase, pre[0], fpre[0], cpre[0], false);
+    stash(kb - 1, pre[1], fpre[1], cpre[1], true);
+    if (pbase + D <= ptop) fetch(pbase + D, pre[0], fpre[0], cpre[0]);
+    if (pbase + D + 1 <= ptop) fetch(pbase + D + 1, pre[1], fpre[1], cpre[1]);
+
+    for (int s0 = kb - 1; s0 <= ke; s0 += D) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const int s = s0 + d;
+            if (s > ke) break;
+            // stage plane s+1 (slot of plane s-3, free since the last black
+            // phase) and refill its register set with plane s+1+D
+            const int ri = (d + 2) % D;
+            if (s + 1 <= ptop) stash(s + 1, pre[ri], fpre[ri], cpre[ri], false);
+            if (s + 1 + D <= ptop) fetch(s + 1 + D, pre[ri], fpre[ri], cpre[ri]);
+            lds_barrier();
+            if constexpr (NORM) {
+                // residual of the input iterate at plane s (all values still
+                // old); old plane s-1 comes from registers captured a step ago
+                T(*P)[kWX] = S[s & 3];
+                T(*Pp)[kWX] = S[(s + 1) & 3];
+                const bool do_res = (s >= kb && s < ke);
+                T cx = 0, cy = 0, dd = 0;
                 if (do_res) {
-                    const int i = i0 + c - 2, j = j0 + w - 2;
-                    if (i <= nx - 2 && j <= ny - 2) {
+                    cx = coef[4 * s];
+                    cy = coef[4 * s + 1];
+                    dd = coef[4 * s + 2];
+                }
+#pragma unroll
+                for (int q = 0; q < kOwn; ++q) {
+                    const int e = tid + q * kThreads;
+                    const int w = 2 + e / kTX, c = 2 + e % kTX;
+                    const T uc = P[w][sx(c)];
+                    if (do_res) {
+                        const int i = i0 + c - 2, j = j0 + w - 2;
+                        if (i <= nx - 2 && j <= ny - 2) {
+                            T fv = (T)0;
+                            if constexpr (HAS_F) fv = F[s & 3][w - 1][sxf(c - 1)];
+                            const T r = fv - (cx * (P[w][sx(c + 1)] + P[w][sx(c - 1)]) +
+                                              cy * (P[w + 1][sx(c)] + P[w - 1][sx(c)]) + cz * (Pp[w][sx(c)] + below[q]) +
+                                              dd * uc);
+                            acc += (double)r * (double)r;
+                        }
+                    }
+                    below[q] = uc;
+                }
+                lds_barrier();
+            }
+            // red nodes of plane s on the tile and its one-node ring
+            if (s >= 1 && s <= nz - 2) {
+                const T cx = coef[4 * s], cy = coef[4 * s + 1], invd = coef[4 * s + 3];
+                T(*P)[kWX] = S[s & 3];
+                T(*Pm)[kWX] = S[(s - 1) & 3];
+                T(*Pp)[kWX] = S[(s + 1) & 3];
+                T(*Fs)[kFX] = F[s & 3];
+                for (int e = tid; e < (kTY + 2) * kRedPerRow; e += kThreads) {
+                    const int w = 1 + e / kRedPerRow;
+                    const int q = e - (w - 1) * kRedPerRow;
+                    const int c = 1 + ((i0 + j0 + w + s + 1) & 1) + 2 * q;
+                    const int i = i0 - 2 + c, j = j0 - 2 + w;
+                    if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2) {
                         T fv = (T)0;
-                        if constexpr (HAS_F) fv = f[(size_t)i + (size_t)nx * j + sxy * s];
-                        const T r = fv - (cx * (P[w][c + 1] + P[w][c - 1]) + cy * (P[w + 1][c] + P[w - 1][c]) +
-                                          cz * (Pp[w][c] + below[q]) + d * uc);
-                        acc += (double)r * (double)r;
+                        if constexpr (HAS_F) fv = Fs[w - 1][sxf(c - 1)];
+                        P[w][sx(c)] = (fv - (cx * (P[w][sx(c + 1)] + P[w][sx(c - 1)]) +
+                                             cy * (P[w + 1][sx(c)] + P[w - 1][sx(c)]) +
+                                             cz * (Pp[w][sx(c)] + Pm[w][sx(c)]))) *
+                                      invd;
                     }
                 }
-                below[q] = uc;
             }
-            __syncthreads();
-        }
-        // red nodes of plane s on the tile and its one-node ring
-        if (s >= 1 && s <= nz - 2) {
-            const T cx = coef[4 * s], cy = coef[4 * s + 1], invd = coef[4 * s + 3];
-            T(*P)[kWX] = S[s & 3];
-            T(*Pm)[kWX] = S[(s - 1) & 3];
-            T(*Pp)[kWX] = S[(s + 1) & 3];
-            for (int e = tid; e < (kTY + 2) * kRedPerRow; e += kThreads) {
-                const int w = 1 + e / kRedPerRow;
-                const int q = e - (w - 1) * kRedPerRow;
-                const int c = 1 + ((i0 + j0 + w + s + 1) & 1) + 2 * q;
-                const int i = i0 - 2 + c, j = j0 - 2 + w;
-                if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2) {
-                    T fv = (T)0;
-                    if constexpr (HAS_F) fv = f[(size_t)i + (size_t)nx * j + sxy * s];
-                    P[w][c] = (fv - (cx * (P[w][c + 1] + P[w][c - 1]) + cy * (P[w + 1][c] + P[w - 1][c]) +
-                                     cz * (Pp[w][c] + Pm[w][c]))) *
-                              invd;
+            lds_barrier();
+            // black nodes of plane m = s - 1 on the tile
+            const int m = s - 1;
+            if (m >= kb && m < ke) {
+                const T cx = coef[4 * m], cy = coef[4 * m + 1], invd = coef[4 * m + 3];
+                T(*P)[kWX] = S[m & 3];
+                T(*Pm)[kWX] = S[(m - 1) & 3];
+                T(*Pp)[kWX] = S[(m + 1) & 3];
+                T(*Fm)[kFX] = F[m & 3];
+                for (int e = tid; e < kTY * kBlackPerRow; e += kThreads) {
+                    const int w = 2 + e / kBlackPerRow;
+                    const int q = e - (w - 2) * kBlackPerRow;
+                    const int c = 2 + ((i0 + j0 + w + m + 1) & 1) + 2 * q;
+                    const int i = i0 - 2 + c, j = j0 - 2 + w;
+                    if (i <= nx - 2 && j <= ny - 2) {
+                        T fv = (T)0;
+                        if constexpr (HAS_F) fv = Fm[w - 1][sxf(c - 1)];
+                        P[w][sx(c)] = (fv - (cx * (P[w][sx(c + 1)] + P[w][sx(c - 1)]) +
+                                             cy * (P[w + 1][sx(c)] + P[w - 1][sx(c)]) +
+                                             cz * (Pp[w][sx(c)] + Pm[w][sx(c)]))) *
+                                      invd;
+                    }
                 }
             }
-        }
-        __syncthreads();
-        // black nodes of plane m = s - 1 on the tile
-        const int m = s - 1;
-        if (m >= kb && m < ke) {
-            const T cx = coef[4 * m], cy = coef[4 * m + 1], invd = coef[4 * m + 3];
-            T(*P)[kWX] = S[m & 3];
-            T(*Pm)[kWX] = S[(m - 1) & 3];
-            T(*Pp)[kWX] = S[(m + 1) & 3];
-            for (int e = tid; e < kTY * kBlackPerRow; e += kThreads) {
-                const int w = 2 + e / kBlackPerRow;
-                const int q = e - (w - 2) * kBlackPerRow;
-                const int c = 2 + ((i0 + j0 + w + m + 1) & 1) + 2 * q;
-                const int i = i0 - 2 + c, j = j0 - 2 + w;
-                if (i <= nx - 2 && j <= ny - 2) {
-                    T fv = (T)0;
-                    if constexpr (HAS_F) fv = f[(size_t)i + (size_t)nx * j + sxy * m];
-                    P[w][c] = (fv - (cx * (P[w][c + 1] + P[w][c - 1]) + cy * (P[w + 1][c] + P[w - 1][c]) +
-                                     cz * (Pp[w][c] + Pm[w][c]))) *
-                              invd;
+            lds_barrier();
+            if (m >= kb && m < ke) {
+                T(*P)[kWX] = S[m & 3];
+                for (int e = tid; e < kTY * kTX; e += kThreads) {
+                    const int w = 2 + e / kTX, c = 2 + e % kTX;
+                    const int i = i0 + c - 2, j = j0 + w - 2;
+                    if (i <= nx - 2 && j <= ny - 2) uout[(size_t)i + (size_t)nx * j + sxy * m] = P[w][sx(c)];
                 }
-            }
-        }
-        __syncthreads();
-        if (m >= kb && m < ke) {
-            T(*P)[kWX] = S[m & 3];
-            for (int e = tid; e < kTY * kTX; e += kThreads) {
-                const int w = 2 + e / kTX, c = 2 + e % kTX;
-                const int i = i0 + c - 2, j = j0 + w - 2;
-                if (i <= nx - 2 && j <= ny - 2) uout[(size_t)i + (size_t)nx * j + sxy * m] = P[w][c];
             }
         }
     }
     if constexpr (NORM) {
         const double tot = block_sum<kThreads>(acc, red);
-        if (tid == 0) it->partials[tile - it->tile_base] = tot;
+        if (tid == 0) gout<double>(it->partials)[tile - it->tile_base] = tot;
     }
 }
 
@@ -264,14 +448,14 @@ __global__ __launch_bounds__(kThreads) void k_sweep2(const LevelItem *__restrict
     __shared__ T S[kW2Y][kW2X];
     __shared__ double red[kThreads / 64];
 
-    const int tile = blockIdx.x;
+    const int tile = xcd_tile();
     const LevelItem *it = items + find_item(items, nitems, tile);
-    if (it->state && it->state->done) return;
-    const T *__restrict__ uin = (const T *)it->u_in;
-    T *__restrict__ uout = (T *)it->u_out;
-    const T *__restrict__ f = (const T *)it->f;
-    const T *__restrict__ ec = (const T *)it->ec;
-    const T *__restrict__ coef = (const T *)it->coef;
+    if (it->state && gin<SolveState>(it->state)->done) return;
+    const MHS_GLOBAL T *__restrict__ uin = gin<T>(it->u_in);
+    MHS_GLOBAL T *__restrict__ uout = gout<T>(it->u_out);
+    const MHS_GLOBAL T *__restrict__ f = gin<T>(it->f);
+    const MHS_GLOBAL T *__restrict__ ec = gin<T>(it->ec);
+    const MHS_CONST T *__restrict__ coef = gconst<T>(it->coef);
     const int nx = it->nx, ny = it->ny;
     const int ncx = it->ncx;
     const int local = tile - it->tile_base;
@@ -287,12 +471,12 @@ __global__ __launch_bounds__(kThreads) void k_sweep2(const LevelItem *__restrict
         if (i >= 0 && i < nx && j >= 0 && j < ny) {
             if constexpr (!ZERO_IN) v = uin[(size_t)i + (size_t)nx * j];
             if constexpr (PROLONG) {
-                if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2) v += interp2(ec, ncx, i, j);
+                if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2) v += interp2<T>(ec, ncx, i, j);
             }
         }
         S[w][c] = v;
     }
-    __syncthreads();
+    lds_barrier();
     double acc = 0.0;
     if constexpr (NORM) {
 #pragma unroll
@@ -307,7 +491,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep2(const LevelItem *__restrict
                 acc += (double)r * (double)r;
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
     for (int e = tid; e < (kTY2 + 2) * kRedPerRow; e += kThreads) {
         const int w = 1 + e / kRedPerRow;
@@ -320,7 +504,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep2(const LevelItem *__restrict
             S[w][c] = (fv - (cx * (S[w][c + 1] + S[w][c - 1]) + cy * (S[w + 1][c] + S[w - 1][c]))) * invd;
         }
     }
-    __syncthreads();
+    lds_barrier();
     for (int e = tid; e < kTY2 * kBlackPerRow; e += kThreads) {
         const int w = 2 + e / kBlackPerRow;
         const int q = e - (w - 2) * kBlackPerRow;
@@ -332,7 +516,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep2(const LevelItem *__restrict
             S[w][c] = (fv - (cx * (S[w][c + 1] + S[w][c - 1]) + cy * (S[w + 1][c] + S[w - 1][c]))) * invd;
         }
     }
-    __syncthreads();
+    lds_barrier();
     for (int e = tid; e < kTY2 * kTX; e += kThreads) {
         const int w = 2 + e / kTX, c = 2 + e % kTX;
         const int i = i0 + c - 2, j = j0 + w - 2;
@@ -340,7 +524,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep2(const LevelItem *__restrict
     }
     if constexpr (NORM) {
         const double tot = block_sum<kThreads>(acc, red);
-        if (tid == 0) it->partials[tile - it->tile_base] = tot;
+        if (tid == 0) gout<double>(it->partials)[tile - it->tile_base] = tot;
     }
 }
 
@@ -361,27 +545,31 @@ static_assert(kCX * kCY == kThreads, "one coarse node per thread");
 template <typename T, bool HAS_F>
 __global__ __launch_bounds__(kThreads) void k_restrict3(const LevelItem *__restrict__ items, int nitems)
 {
-    __shared__ T U[3][kRWY][kRWX];
+    constexpr int kCells = kRWY * kRWX;
+    constexpr int kPer = (kCells + kThreads - 1) / kThreads;
+    constexpr int D = kDepth;
+    __shared__ T U[4][kRWY][kRWX];
     __shared__ T R[kRRY][kRRX];
 
-    const int tile = blockIdx.x;
+    const int tile = xcd_tile();
     const LevelItem *it = items + find_item(items, nitems, tile);
-    if (it->state && it->state->done) return;
-    const T *__restrict__ u = (const T *)it->u_in;
-    const T *__restrict__ f = (const T *)it->f;
-    T *__restrict__ fc = (T *)it->u_out;
-    const T *__restrict__ coef = (const T *)it->coef;
+    if (it->state && gin<SolveState>(it->state)->done) return;
+    const MHS_GLOBAL T *__restrict__ u = gin<T>(it->u_in);
+    const MHS_GLOBAL T *__restrict__ f = gin<T>(it->f);
+    MHS_GLOBAL T *__restrict__ fc = gout<T>(it->u_out);
+    const MHS_CONST T *__restrict__ coef = gconst<T>(it->coef);
     const T cz = (T)it->cz;
-    const int nx = it->nx, ny = it->ny, nz = it->nz;
+    const int nx = it->nx, ny = it->ny;
     const int ncx = it->ncx, ncy = it->ncy, ncz = it->ncz;
+    const int kc = it->kz;
     int local = tile - it->tile_base;
     const int tx = local % it->ntx;
     local /= it->ntx;
     const int ty = local % it->nty;
     const int tz = local / it->nty;
     const int I0 = 1 + tx * kCX, J0 = 1 + ty * kCY;
-    const int Kb = 1 + tz * kKC;
-    const int Ke = min(Kb + kKC, ncz - 1);
+    const int Kb = 1 + tz * kc;
+    const int Ke = min(Kb + kc, ncz - 1);
     const int fi0 = 2 * I0 - 1, fj0 = 2 * J0 - 1; // residual window origin
     const int ui0 = fi0 - 1, uj0 = fj0 - 1;       // u window origin
     const size_t sxy = (size_t)nx * ny;
@@ -390,60 +578,86 @@ __global__ __launch_bounds__(kThreads) void k_restrict3(const LevelItem *__restr
     const int I = I0 + tI, J = J0 + tJ;
     const bool valid = (I <= ncx - 2) && (J <= ncy - 2);
 
-    auto load_u = [&](int p) {
-        T(*dst)[kRWX] = U[p % 3];
-        for (int e = tid; e < kRWY * kRWX; e += kThreads) {
+    T pre[D][kPer];
+    // unconditional clamped loads; out-of-array cells zeroed when staged
+    auto fetch = [&](int p, T(&dst)[kPer]) {
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+            const int e = min(tid + r * kThreads, kCells - 1);
             const int w = e / kRWX, c = e - w * kRWX;
-            const int i = ui0 + c, j = uj0 + w;
-            T v = (T)0;
-            if (i >= 0 && i < nx && j >= 0 && j < ny) v = u[(size_t)i + (size_t)nx * j + sxy * p];
-            dst[w][c] = v;
+            const int i = min(max(ui0 + c, 0), nx - 1), j = min(max(uj0 + w, 0), ny - 1);
+            dst[r] = u[(size_t)i + (size_t)nx * j + sxy * p];
+        }
+    };
+    auto stash = [&](int p, const T(&src)[kPer]) {
+        T(*dst)[kRWX] = U[p & 3];
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+            const int e = tid + r * kThreads;
+            if (e < kCells) {
+                const int w = e / kRWX, c = e - w * kRWX;
+                const int i = ui0 + c, j = uj0 + w;
+                dst[w][c] = (i < nx && j < ny) ? src[r] : (T)0;
+            }
         }
     };
 
-    load_u(2 * Kb - 2);
-    load_u(2 * Kb - 1);
+    // u planes 2Kb-2 .. 2Ke are read; plane p waits in register set (p - pbase) % D
+    const int pbase = 2 * Kb - 2, ptop = 2 * Ke;
+#pragma unroll
+    for (int q = 0; q < D; ++q)
+        if (pbase + q <= ptop) fetch(pbase + q, pre[q]);
+    stash(pbase, pre[0]);
+    stash(pbase + 1, pre[1]);
+    if (pbase + D <= ptop) fetch(pbase + D, pre[0]);
+    if (pbase + D + 1 <= ptop) fetch(pbase + D + 1, pre[1]);
     T acc = (T)0;
     const T q4 = (T)0.25, h2 = (T)0.5;
-    for (int m = 2 * Kb - 1; m <= 2 * Ke - 1; ++m) {
-        load_u(m + 1);
-        __syncthreads();
-        {
-            const T cx = coef[4 * m], cy = coef[4 * m + 1], d = coef[4 * m + 2];
-            T(*P)[kRWX] = U[m % 3];
-            T(*Pm)[kRWX] = U[(m + 2) % 3];
-            T(*Pp)[kRWX] = U[(m + 1) % 3];
-            for (int e = tid; e < kRRY * kRRX; e += kThreads) {
-                const int w = e / kRRX, c = e - w * kRRX;
-                const int i = fi0 + c, j = fj0 + w;
-                T r = (T)0;
-                if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2) {
-                    const int uw = w + 1, uc = c + 1;
-                    T fv = (T)0;
-                    if constexpr (HAS_F) fv = f[(size_t)i + (size_t)nx * j + sxy * m];
-                    r = fv - (cx * (P[uw][uc + 1] + P[uw][uc - 1]) + cy * (P[uw + 1][uc] + P[uw - 1][uc]) +
-                              cz * (Pp[uw][uc] + Pm[uw][uc]) + d * P[uw][uc]);
+    for (int m0 = 2 * Kb - 1; m0 <= 2 * Ke - 1; m0 += D) {
+#pragma unroll
+        for (int dd = 0; dd < D; ++dd) {
+            const int m = m0 + dd;
+            if (m > 2 * Ke - 1) break;
+            // stage plane m+1 into the slot of plane m-3 (read two steps ago)
+            const int ri = (dd + 2) % D;
+            stash(m + 1, pre[ri]);
+            if (m + 1 + D <= ptop) fetch(m + 1 + D, pre[ri]);
+            lds_barrier();
+            {
+                const T cx = coef[4 * m], cy = coef[4 * m + 1], d = coef[4 * m + 2];
+                T(*P)[kRWX] = U[m & 3];
+                T(*Pm)[kRWX] = U[(m - 1) & 3];
+                T(*Pp)[kRWX] = U[(m + 1) & 3];
+                for (int e = tid; e < kRRY * kRRX; e += kThreads) {
+                    const int w = e / kRRX, c = e - w * kRRX;
+                    const int i = fi0 + c, j = fj0 + w;
+                    T r = (T)0;
+                    if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2) {
+                        const int uw = w + 1, uc = c + 1;
+                        T fv = (T)0;
+                        if constexpr (HAS_F) fv = f[(size_t)i + (size_t)nx * j + sxy * m];
+                        r = fv - (cx * (P[uw][uc + 1] + P[uw][uc - 1]) + cy * (P[uw + 1][uc] + P[uw - 1][uc]) +
+                                  cz * (Pp[uw][uc] + Pm[uw][uc]) + d * P[uw][uc]);
+                    }
+                    R[w][c] = r;
                 }
-                R[w][c] = r;
+            }
+            lds_barrier();
+            const int cw = 2 * tJ + 1, cc = 2 * tI + 1;
+            auto row = [&](int w) { return q4 * R[w][cc - 1] + h2 * R[w][cc] + q4 * R[w][cc + 1]; };
+            const T s2 = q4 * row(cw - 1) + h2 * row(cw) + q4 * row(cw + 1);
+            if (m & 1) {
+                const int Kend = (m - 1) >> 1;
+                if (Kend >= Kb) {
+                    acc += q4 * s2;
+                    if (valid) fc[(size_t)I + (size_t)ncx * J + (size_t)ncx * ncy * Kend] = acc;
+                }
+                acc = q4 * s2;
+            } else {
+                acc += h2 * s2;
             }
         }
-        __syncthreads();
-        const int cw = 2 * tJ + 1, cc = 2 * tI + 1;
-        auto row = [&](int w) { return q4 * R[w][cc - 1] + h2 * R[w][cc] + q4 * R[w][cc + 1]; };
-        const T s2 = q4 * row(cw - 1) + h2 * row(cw) + q4 * row(cw + 1);
-        if (m & 1) {
-            const int Kend = (m - 1) >> 1;
-            if (Kend >= Kb) {
-                acc += q4 * s2;
-                if (valid) fc[(size_t)I + (size_t)ncx * J + (size_t)ncx * ncy * Kend] = acc;
-            }
-            acc = q4 * s2;
-        } else {
-            acc += h2 * s2;
-        }
-        __syncthreads();
     }
-    (void)nz;
 }
 
 // 2D residual + nine-point full weighting.  One coarse node per thread,
@@ -453,13 +667,13 @@ __global__ __launch_bounds__(kThreads) void k_restrict2(const LevelItem *__restr
 {
     __shared__ T U[kRWY][kRWX];
     __shared__ T R[kRRY][kRRX];
-    const int tile = blockIdx.x;
+    const int tile = xcd_tile();
     const LevelItem *it = items + find_item(items, nitems, tile);
-    if (it->state && it->state->done) return;
-    const T *__restrict__ u = (const T *)it->u_in;
-    const T *__restrict__ f = (const T *)it->f;
-    T *__restrict__ fc = (T *)it->u_out;
-    const T *__restrict__ coef = (const T *)it->coef;
+    if (it->state && gin<SolveState>(it->state)->done) return;
+    const MHS_GLOBAL T *__restrict__ u = gin<T>(it->u_in);
+    const MHS_GLOBAL T *__restrict__ f = gin<T>(it->f);
+    MHS_GLOBAL T *__restrict__ fc = gout<T>(it->u_out);
+    const MHS_CONST T *__restrict__ coef = gconst<T>(it->coef);
     const int nx = it->nx, ny = it->ny;
     const int ncx = it->ncx, ncy = it->ncy;
     const int local = tile - it->tile_base;
@@ -476,7 +690,7 @@ __global__ __launch_bounds__(kThreads) void k_restrict2(const LevelItem *__restr
         const int i = ui0 + c, j = uj0 + w;
         U[w][c] = (i >= 0 && i < nx && j >= 0 && j < ny) ? u[(size_t)i + (size_t)nx * j] : (T)0;
     }
-    __syncthreads();
+    lds_barrier();
     for (int e = tid; e < kRRY * kRRX; e += kThreads) {
         const int w = e / kRRX, c = e - w * kRRX;
         const int i = fi0 + c, j = fj0 + w;
@@ -488,7 +702,7 @@ __global__ __launch_bounds__(kThreads) void k_restrict2(const LevelItem *__restr
         }
         R[w][c] = r;
     }
-    __syncthreads();
+    lds_barrier();
     if (I <= ncx - 2 && J <= ncy - 2) {
         const T q4 = (T)0.25, h2 = (T)0.5;
         const int cw = 2 * tJ + 1, cc = 2 * tI + 1;
@@ -505,97 +719,132 @@ __global__ __launch_bounds__(kThreads) void k_restrict2(const LevelItem *__restr
 // ============================================================================
 constexpr int kIWX = kTX + 2;
 constexpr int kIWY = kTY + 2;
+constexpr int kICells = kIWX * kIWY;
+constexpr int kIPer = (kICells + kThreads - 1) / kThreads;
 
 template <bool HAS_E>
 __global__ __launch_bounds__(kThreads) void k_ir3(const LevelItem *__restrict__ items, int nitems)
 {
-    __shared__ double S[3][kIWY][kIWX];
+    constexpr int D = kDepth;
+    __shared__ double S[4][kIWY][kIWX];
     __shared__ double red[kThreads / 64];
-    const int tile = blockIdx.x;
+    const int tile = xcd_tile();
     const LevelItem *it = items + find_item(items, nitems, tile);
-    if (it->state && it->state->done) return;
-    const double *__restrict__ uin = (const double *)it->u_in;
-    double *__restrict__ uout = (double *)it->u_out;
-    const float *__restrict__ e32 = (const float *)it->ec;
-    float *__restrict__ r32 = (float *)it->r_out;
-    const double *__restrict__ coef = (const double *)it->coef;
+    if (it->state && gin<SolveState>(it->state)->done) return;
+    const MHS_GLOBAL double *__restrict__ uin = gin<double>(it->u_in);
+    MHS_GLOBAL double *__restrict__ uout = gout<double>(it->u_out);
+    const MHS_GLOBAL float *__restrict__ e32 = gin<float>(it->ec);
+    MHS_GLOBAL float *__restrict__ r32 = gout<float>(it->r_out);
+    const MHS_CONST double *__restrict__ coef = gconst<double>(it->coef);
     const double cz = it->cz;
     const int nx = it->nx, ny = it->ny, nz = it->nz;
+    const int kz = it->kz;
     int local = tile - it->tile_base;
     const int tx = local % it->ntx;
     local /= it->ntx;
     const int ty = local % it->nty;
     const int tz = local / it->nty;
     const int i0 = 1 + tx * kTX, j0 = 1 + ty * kTY;
-    const int kb = 1 + tz * kKZ;
-    const int ke = min(kb + kKZ, nz - 1);
+    const int kb = 1 + tz * kz;
+    const int ke = min(kb + kz, nz - 1);
     const size_t sxy = (size_t)nx * ny;
     const int tid = threadIdx.x;
 
-    auto load_plane = [&](int p) {
-        double(*dst)[kIWX] = S[p % 3];
-        for (int e = tid; e < kIWY * kIWX; e += kThreads) {
+    double pre[D][kIPer];
+    float epre[D][kIPer];
+    // unconditional clamped loads; the correction is added and out-of-array
+    // cells are zeroed when the plane is staged
+    auto fetch = [&](int p, double(&dst)[kIPer], float(&edst)[kIPer]) {
+#pragma unroll
+        for (int r = 0; r < kIPer; ++r) {
+            const int e = min(tid + r * kThreads, kICells - 1);
             const int w = e / kIWX, c = e - w * kIWX;
-            const int i = i0 - 1 + c, j = j0 - 1 + w;
-            double v = 0.0;
-            if (i >= 0 && i < nx && j >= 0 && j < ny) {
-                const size_t idx = (size_t)i + (size_t)nx * j + sxy * p;
-                v = uin[idx];
-                if constexpr (HAS_E) {
-                    if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2 && p >= 1 && p <= nz - 2)
-                        v += (double)e32[idx];
+            const int i = min(max(i0 - 1 + c, 0), nx - 1), j = min(max(j0 - 1 + w, 0), ny - 1);
+            const size_t idx = (size_t)i + (size_t)nx * j + sxy * p;
+            dst[r] = uin[idx];
+            if constexpr (HAS_E) edst[r] = e32[idx];
+        }
+    };
+    auto stash = [&](int p, const double(&src)[kIPer], const float(&esrc)[kIPer]) {
+        double(*dst)[kIWX] = S[p & 3];
+#pragma unroll
+        for (int r = 0; r < kIPer; ++r) {
+            const int e = tid + r * kThreads;
+            if (e < kICells) {
+                const int w = e / kIWX, c = e - w * kIWX;
+                const int i = i0 - 1 + c, j = j0 - 1 + w;
+                double v = 0.0;
+                if (i < nx && j < ny) {
+                    v = src[r];
+                    if constexpr (HAS_E) {
+                        if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2 && p >= 1 && p <= nz - 2)
+                            v += (double)esrc[r];
+                    }
                 }
+                dst[w][c] = v;
             }
-            dst[w][c] = v;
         }
     };
     double acc = 0.0;
-    load_plane(kb - 1);
-    load_plane(kb);
-    for (int m = kb; m < ke; ++m) {
-        load_plane(m + 1);
-        __syncthreads();
-        const double cx = coef[4 * m], cy = coef[4 * m + 1], d = coef[4 * m + 2];
-        double(*P)[kIWX] = S[m % 3];
-        double(*Pm)[kIWX] = S[(m + 2) % 3];
-        double(*Pp)[kIWX] = S[(m + 1) % 3];
-        for (int e = tid; e < kTY * kTX; e += kThreads) {
-            const int w = 1 + e / kTX, c = 1 + e % kTX;
-            const int i = i0 + c - 1, j = j0 + w - 1;
-            if (i <= nx - 2 && j <= ny - 2) {
-                const size_t idx = (size_t)i + (size_t)nx * j + sxy * m;
-                const double uc = P[w][c];
-                const double r = -(cx * (P[w][c + 1] + P[w][c - 1]) + cy * (P[w + 1][c] + P[w - 1][c]) +
-                                   cz * (Pp[w][c] + Pm[w][c]) + d * uc);
-                if constexpr (HAS_E) uout[idx] = uc;
-                r32[idx] = (float)r;
-                acc += r * r;
+    // planes kb-1 .. ke are read; plane p waits in register set (p - pbase) % D
+    const int pbase = kb - 1, ptop = ke;
+#pragma unroll
+    for (int q = 0; q < D; ++q)
+        if (pbase + q <= ptop) fetch(pbase + q, pre[q], epre[q]);
+    stash(pbase, pre[0], epre[0]);
+    stash(pbase + 1, pre[1], epre[1]);
+    if (pbase + D <= ptop) fetch(pbase + D, pre[0], epre[0]);
+    if (pbase + D + 1 <= ptop) fetch(pbase + D + 1, pre[1], epre[1]);
+    for (int m0 = kb; m0 < ke; m0 += D) {
+#pragma unroll
+        for (int dd = 0; dd < D; ++dd) {
+            const int m = m0 + dd;
+            if (m >= ke) break;
+            // plane m+1 goes into the slot of plane m-3 (read two steps ago)
+            const int ri = (dd + 2) % D;
+            stash(m + 1, pre[ri], epre[ri]);
+            if (m + 1 + D <= ptop) fetch(m + 1 + D, pre[ri], epre[ri]);
+            lds_barrier();
+            const double cx = coef[4 * m], cy = coef[4 * m + 1], d = coef[4 * m + 2];
+            double(*P)[kIWX] = S[m & 3];
+            double(*Pm)[kIWX] = S[(m - 1) & 3];
+            double(*Pp)[kIWX] = S[(m + 1) & 3];
+            for (int e = tid; e < kTY * kTX; e += kThreads) {
+                const int w = 1 + e / kTX, c = 1 + e % kTX;
+                const int i = i0 + c - 1, j = j0 + w - 1;
+                if (i <= nx - 2 && j <= ny - 2) {
+                    const size_t idx = (size_t)i + (size_t)nx * j + sxy * m;
+                    const double uc = P[w][c];
+                    const double r = -(cx * (P[w][c + 1] + P[w][c - 1]) + cy * (P[w + 1][c] + P[w - 1][c]) +
+                                       cz * (Pp[w][c] + Pm[w][c]) + d * uc);
+                    if constexpr (HAS_E) uout[idx] = uc;
+                    r32[idx] = (float)r;
+                    acc += r * r;
+                }
             }
         }
-        __syncthreads();
     }
     const double tot = block_sum<kThreads>(acc, red);
-    if (tid == 0) it->partials[tile - it->tile_base] = tot;
+    if (tid == 0) gout<double>(it->partials)[tile - it->tile_base] = tot;
 }
 
 // ============================================================================
 // Bottom solver: one workgroup runs a whole V(nu1,nu2) cycle over the small
 // levels of one request, from a zero initial guess, in FP64, with exact
-// red-black Gauss-Seidel ordering (barrier between colours) and an exact
-// dense solve on the coarsest grid.  Work arrays live in the workspace and
-// stay cache resident.
+// red-black Gauss-Seidel ordering (a barrier between colours) and an exact
+// dense solve on the coarsest grid.  Every work array lives in LDS (up to
+// 160 KB on gfx950), so each phase costs LDS latency, not HBM latency.
 // ============================================================================
-__device__ __forceinline__ void bottom_smooth(const BottomItem &b, int l, int nsweeps)
+__device__ __forceinline__ void bottom_smooth(double *smem, const BottomItem &b, int l, bool planar, int nsweeps)
 {
     const int nx = b.n[l][0], ny = b.n[l][1], nz = b.n[l][2];
-    const bool planar = b.planar != 0;
     const int mx = nx - 2, my = ny - 2, mz = planar ? 1 : nz - 2;
     const int nint = mx * my * mz;
-    double *__restrict__ u = b.u[l];
-    const double *__restrict__ f = b.f[l];
-    const double *__restrict__ coef = b.coef[l];
+    double *u = smem + b.off_u[l];
+    const double *f = smem + b.off_f[l];
+    const MHS_GLOBAL double *coef = gin<double>(b.coef[l]);
     const double cz = b.cz[l];
-    const size_t sxy = (size_t)nx * ny;
+    const int sxy = nx * ny;
     for (int s = 0; s < nsweeps; ++s) {
         for (int colour = 0; colour < 2; ++colour) {
             for (int e = threadIdx.x; e < nint; e += kBottomThreads) {
@@ -603,14 +852,13 @@ __device__ __forceinline__ void bottom_smooth(const BottomItem &b, int l, int ns
                 const int jj = rest % my, kk = rest / my;
                 const int i = ii + 1, j = jj + 1, k = planar ? 0 : kk + 1;
                 if (((i + j + k) & 1) != colour) continue;
-                const size_t idx = (size_t)i + (size_t)nx * j + sxy * k;
-                const int kc = planar ? 0 : k;
-                const double cx = coef[4 * kc], cy = coef[4 * kc + 1], invd = coef[4 * kc + 3];
+                const int idx = i + nx * j + sxy * k;
+                const double cx = coef[4 * k], cy = coef[4 * k + 1], invd = coef[4 * k + 3];
                 double off = cx * (u[idx + 1] + u[idx - 1]) + cy * (u[idx + nx] + u[idx - nx]);
                 if (!planar) off += cz * (u[idx + sxy] + u[idx - sxy]);
                 u[idx] = (f[idx] - off) * invd;
             }
-            __syncthreads();
+            lds_barrier();
         }
     }
 }
@@ -618,119 +866,112 @@ __device__ __forceinline__ void bottom_smooth(const BottomItem &b, int l, int ns
 template <typename T>
 __global__ __launch_bounds__(kBottomThreads) void k_bottom(const BottomItem *__restrict__ items, int nitems)
 {
+    extern __shared__ double smem[];
     const BottomItem &b = items[blockIdx.x];
-    if (b.state && b.state->done) return;
+    if (b.state && gin<SolveState>(b.state)->done) return;
     const bool planar = b.planar != 0;
     const int tid = threadIdx.x;
-    {
-        const size_t N0 = (size_t)b.n[0][0] * b.n[0][1] * b.n[0][2];
-        const T *ft = (const T *)b.f_top;
-        for (size_t e = tid; e < N0; e += kBottomThreads) {
-            b.f[0][e] = (double)ft[e];
-            b.u[0][e] = 0.0;
+    const int L = b.nlev;
+    double *r = smem + b.off_r;
+    for (int l = 0; l < L; ++l) {
+        const int N = b.n[l][0] * b.n[l][1] * b.n[l][2];
+        double *u = smem + b.off_u[l];
+        double *f = smem + b.off_f[l];
+        const MHS_GLOBAL T *ft = gin<T>(b.f_top);
+        for (int e = tid; e < N; e += kBottomThreads) {
+            u[e] = 0.0;
+            f[e] = (l == 0) ? (double)ft[e] : 0.0;
         }
     }
-    __syncthreads();
-    const int L = b.nlev;
+    lds_barrier();
     for (int l = 0; l < L - 1; ++l) {
         const int nx = b.n[l][0], ny = b.n[l][1], nz = b.n[l][2];
-        const size_t sxy = (size_t)nx * ny;
-        if (l > 0) {
-            const size_t N = sxy * nz;
-            for (size_t e = tid; e < N; e += kBottomThreads) b.u[l][e] = 0.0;
-            __syncthreads();
-        }
-        bottom_smooth(b, l, b.nu1);
+        const int sxy = nx * ny;
+        bottom_smooth(smem, b, l, planar, b.nu1);
         // residual on interior nodes
         {
+            const double *u = smem + b.off_u[l];
+            const double *f = smem + b.off_f[l];
+            const MHS_GLOBAL double *coef = gin<double>(b.coef[l]);
+            const double cz = b.cz[l];
             const int mx = nx - 2, my = ny - 2, mz = planar ? 1 : nz - 2;
             const int nint = mx * my * mz;
-            const double *__restrict__ u = b.u[l];
-            const double *__restrict__ f = b.f[l];
-            const double *__restrict__ coef = b.coef[l];
-            const double cz = b.cz[l];
             for (int e = tid; e < nint; e += kBottomThreads) {
                 const int ii = e % mx, rest = e / mx;
                 const int jj = rest % my, kk = rest / my;
                 const int i = ii + 1, j = jj + 1, k = planar ? 0 : kk + 1;
-                const size_t idx = (size_t)i + (size_t)nx * j + sxy * k;
-                const int kc = planar ? 0 : k;
-                double au = coef[4 * kc] * (u[idx + 1] + u[idx - 1]) + coef[4 * kc + 1] * (u[idx + nx] + u[idx - nx]) +
-                            coef[4 * kc + 2] * u[idx];
+                const int idx = i + nx * j + sxy * k;
+                double au = coef[4 * k] * (u[idx + 1] + u[idx - 1]) + coef[4 * k + 1] * (u[idx + nx] + u[idx - nx]) +
+                            coef[4 * k + 2] * u[idx];
                 if (!planar) au += cz * (u[idx + sxy] + u[idx - sxy]);
-                b.r[idx] = f[idx] - au;
+                r[idx] = f[idx] - au;
             }
         }
-        __syncthreads();
+        lds_barrier();
         // full weighting onto the interior of level l+1
         {
             const int cnx = b.n[l + 1][0], cny = b.n[l + 1][1], cnz = b.n[l + 1][2];
+            double *fc = smem + b.off_f[l + 1];
             const int mx = cnx - 2, my = cny - 2, mz = planar ? 1 : cnz - 2;
             const int nint = mx * my * mz;
-            const double *__restrict__ r = b.r;
-            double *__restrict__ fc = b.f[l + 1];
             for (int e = tid; e < nint; e += kBottomThreads) {
                 const int ii = e % mx, rest = e / mx;
                 const int jj = rest % my, kk = rest / my;
                 const int I = ii + 1, J = jj + 1, K = planar ? 0 : kk + 1;
-                const size_t fidx = (size_t)(2 * I) + (size_t)nx * (2 * J) + sxy * (planar ? 0 : 2 * K);
-                auto row = [&](size_t q) { return 0.25 * r[q - 1] + 0.5 * r[q] + 0.25 * r[q + 1]; };
-                auto pl = [&](size_t q) { return 0.25 * row(q - nx) + 0.5 * row(q) + 0.25 * row(q + nx); };
-                double v = planar ? pl(fidx) : 0.25 * pl(fidx - sxy) + 0.5 * pl(fidx) + 0.25 * pl(fidx + sxy);
-                fc[(size_t)I + (size_t)cnx * J + (size_t)cnx * cny * K] = v;
+                const int fidx = 2 * I + nx * (2 * J) + sxy * (planar ? 0 : 2 * K);
+                auto row = [&](int q) { return 0.25 * r[q - 1] + 0.5 * r[q] + 0.25 * r[q + 1]; };
+                auto pl = [&](int q) { return 0.25 * row(q - nx) + 0.5 * row(q) + 0.25 * row(q + nx); };
+                const double v = planar ? pl(fidx) : 0.25 * pl(fidx - sxy) + 0.5 * pl(fidx) + 0.25 * pl(fidx + sxy);
+                fc[I + cnx * J + cnx * cny * K] = v;
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
     // exact solve on the coarsest grid: u = Minv f over interior nodes
     {
-        const int nx = b.n[L - 1][0], ny = b.n[L - 1][1], nz = b.n[L - 1][2];
+        const int nx = b.n[L - 1][0], ny = b.n[L - 1][1];
         const int mx = nx - 2, my = ny - 2;
-        const size_t sxy = (size_t)nx * ny;
+        const int sxy = nx * ny;
         const int m = b.m;
-        double *__restrict__ u = b.u[L - 1];
-        const double *__restrict__ f = b.f[L - 1];
-        if (L > 1) {
-            const size_t N = sxy * nz;
-            for (size_t e = tid; e < N; e += kBottomThreads) u[e] = 0.0;
-        }
-        __syncthreads();
+        double *u = smem + b.off_u[L - 1];
+        const double *f = smem + b.off_f[L - 1];
         for (int p = tid; p < m; p += kBottomThreads) {
-            double s = 0.0;
+            double acc = 0.0;
             for (int q = 0; q < m; ++q) {
                 const int qi = q % mx, qr = q / mx;
                 const int qj = qr % my, qk = qr / my;
-                const size_t fidx = (size_t)(qi + 1) + (size_t)nx * (qj + 1) + sxy * (planar ? 0 : qk + 1);
-                s += b.minv[(size_t)p * m + q] * f[fidx];
+                const int fidx = (qi + 1) + nx * (qj + 1) + sxy * (planar ? 0 : qk + 1);
+                acc += gin<double>(b.minv)[(size_t)p * m + q] * f[fidx];
             }
             const int pi = p % mx, pr = p / mx;
             const int pj = pr % my, pk = pr / my;
-            u[(size_t)(pi + 1) + (size_t)nx * (pj + 1) + sxy * (planar ? 0 : pk + 1)] = s;
+            u[(pi + 1) + nx * (pj + 1) + sxy * (planar ? 0 : pk + 1)] = acc;
         }
-        __syncthreads();
+        lds_barrier();
     }
     for (int l = L - 2; l >= 0; --l) {
         const int nx = b.n[l][0], ny = b.n[l][1], nz = b.n[l][2];
         const int cnx = b.n[l + 1][0], cny = b.n[l + 1][1];
-        const size_t sxy = (size_t)nx * ny;
+        const int sxy = nx * ny;
         const int mx = nx - 2, my = ny - 2, mz = planar ? 1 : nz - 2;
         const int nint = mx * my * mz;
-        double *__restrict__ u = b.u[l];
-        const double *__restrict__ ec = b.u[l + 1];
+        double *u = smem + b.off_u[l];
+        const double *ec = smem + b.off_u[l + 1];
         for (int e = tid; e < nint; e += kBottomThreads) {
             const int ii = e % mx, rest = e / mx;
             const int jj = rest % my, kk = rest / my;
             const int i = ii + 1, j = jj + 1, k = planar ? 0 : kk + 1;
-            const double v = planar ? interp2(ec, cnx, i, j) : interp3(ec, cnx, cny, i, j, k);
-            u[(size_t)i + (size_t)nx * j + sxy * k] += v;
+            const double v = planar ? interp2<double>(ec, cnx, i, j) : interp3<double>(ec, cnx, cny, i, j, k);
+            u[i + nx * j + sxy * k] += v;
         }
-        __syncthreads();
-        bottom_smooth(b, l, b.nu2);
+        lds_barrier();
+        bottom_smooth(smem, b, l, planar, b.nu2);
     }
     {
-        const size_t N0 = (size_t)b.n[0][0] * b.n[0][1] * b.n[0][2];
-        T *ut = (T *)b.u_top;
-        for (size_t e = tid; e < N0; e += kBottomThreads) ut[e] = (T)b.u[0][e];
+        const int N0 = b.n[0][0] * b.n[0][1] * b.n[0][2];
+        const double *u = smem + b.off_u[0];
+        MHS_GLOBAL T *ut = gout<T>(b.u_top);
+        for (int e = tid; e < N0; e += kBottomThreads) ut[e] = (T)u[e];
     }
 }
 
@@ -769,49 +1010,75 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const FinalizeItem *__res
 
 // ============================================================================
 // Field recovery (Section 2.2): B by central differences of P, p and rho from
-// (9) and (10).  A workgroup owns kTX x kFY nodes of kKZ planes; P planes are
-// staged in LDS with a two-node halo and Bz planes with a one-node halo,
-// three planes of each in flight.  Side and top faces: B = 0.  Base plane:
+// (9) and (10).  A workgroup owns kTX x kFY nodes of `kz` planes; P planes
+// are staged in LDS with a two-node halo (four planes in flight, the next one
+// prefetched into registers) and Bz planes with a one-node halo (three in
+// flight).  At step m the workgroup forms Bz on plane m+1, then writes all
+// five fields of plane m.  Side and top faces: B = 0.  Base plane:
 // one-sided second-order z-derivatives.
 // ============================================================================
 constexpr int kFPX = kTX + 4;
 constexpr int kFPY = kFY + 4;
 constexpr int kFBX = kTX + 2;
 constexpr int kFBY = kFY + 2;
+constexpr int kFCells = kFPX * kFPY;
+constexpr int kFPer = (kFCells + kThreads - 1) / kThreads;
 
 __global__ __launch_bounds__(kThreads) void k_fields(const FieldsItem *__restrict__ items, int nitems)
 {
-    __shared__ double SP[3][kFPY][kFPX];
+    __shared__ double SP[4][kFPY][kFPX];
     __shared__ double SB[3][kFBY][kFBX];
-    const int tile = blockIdx.x;
+    const int tile = xcd_tile();
     const FieldsItem *it = items + find_item(items, nitems, tile);
-    const double *__restrict__ P = it->P;
+    const MHS_GLOBAL double *__restrict__ P = gin<double>(it->P);
     const int nx = it->nx, ny = it->ny, nz = it->nz;
+    const int kz = it->kz;
     int local = tile - it->tile_base;
     const int tx = local % it->ntx;
     local /= it->ntx;
     const int ty = local % it->nty;
     const int tz = local / it->nty;
     const int i0 = tx * kTX, j0 = ty * kFY;
-    const int kb = tz * kKZ;
-    const int ke = min(kb + kKZ, nz);
+    const int kb = tz * kz;
+    const int ke = min(kb + kz, nz);
     const size_t sxy = (size_t)nx * ny;
     const int tid = threadIdx.x;
     const double ix2 = 1.0 / (it->dx * it->dx), iy2 = 1.0 / (it->dy * it->dy);
     const double i2dx = 0.5 / it->dx, i2dy = 0.5 / it->dy, i2dz = 0.5 / it->dz;
     const double alpha = it->alpha, mu0 = it->mu0, g = it->g;
-    const double *tab = it->tab;
+    const MHS_CONST double *tab = gconst<double>(it->tab);
+    MHS_GLOBAL double *__restrict__ oBx = gout<double>(it->Bx);
+    MHS_GLOBAL double *__restrict__ oBy = gout<double>(it->By);
+    MHS_GLOBAL double *__restrict__ oBz = gout<double>(it->Bz);
+    MHS_GLOBAL double *__restrict__ op = gout<double>(it->p);
+    MHS_GLOBAL double *__restrict__ orho = gout<double>(it->rho);
 
-    auto load_plane = [&](int p) {
-        double(*dst)[kFPX] = SP[p % 3];
-        for (int e = tid; e < kFPY * kFPX; e += kThreads) {
+    double pre[kFPer];
+    // unconditional clamped loads; out-of-array cells zeroed when staged
+    auto fetch = [&](int p) {
+#pragma unroll
+        for (int r = 0; r < kFPer; ++r) {
+            const int e = min(tid + r * kThreads, kFCells - 1);
             const int w = e / kFPX, c = e - w * kFPX;
-            const int i = i0 - 2 + c, j = j0 - 2 + w;
-            dst[w][c] = (i >= 0 && i < nx && j >= 0 && j < ny) ? P[(size_t)i + (size_t)nx * j + sxy * p] : 0.0;
+            const int i = min(max(i0 - 2 + c, 0), nx - 1), j = min(max(j0 - 2 + w, 0), ny - 1);
+            pre[r] = P[(size_t)i + (size_t)nx * j + sxy * p];
         }
     };
+    auto stash = [&](int p) {
+        double(*dst)[kFPX] = SP[p & 3];
+#pragma unroll
+        for (int r = 0; r < kFPer; ++r) {
+            const int e = tid + r * kThreads;
+            if (e < kFCells) {
+                const int w = e / kFPX, c = e - w * kFPX;
+                const int i = i0 - 2 + c, j = j0 - 2 + w;
+                dst[w][c] = (i >= 0 && i < nx && j >= 0 && j < ny) ? pre[r] : 0.0;
+            }
+        }
+    };
+    // Bz = -(d2x + d2y) P on plane p, one-node ring; 0 on faces and the top
     auto bz_plane = [&](int p) {
-        double(*src)[kFPX] = SP[p % 3];
+        double(*src)[kFPX] = SP[p & 3];
         double(*dst)[kFBX] = SB[p % 3];
         for (int e = tid; e < kFBY * kFBX; e += kThreads) {
             const int w = e / kFBX, c = e - w * kFBX;
@@ -826,18 +1093,24 @@ __global__ __launch_bounds__(kThreads) void k_fields(const FieldsItem *__restric
         }
     };
 
-    int loaded = (kb == 0) ? -1 : kb - 2;
+    // planes kept: P m-1..m+1 (m+2 prefetched), Bz m-1..m+1.  The base plane
+    // needs P 0..2 and Bz 0..2 instead.
+    const int first = (kb == 0) ? 0 : kb - 1;
+    for (int p = first; p <= min(first + 2, nz - 1); ++p) {
+        fetch(p);
+        stash(p);
+    }
+    lds_barrier();
+    for (int p = first; p <= min(first + 1, nz - 1); ++p) bz_plane(p);
     for (int m = kb; m < ke; ++m) {
-        if (m < nz - 1) {
-            const int hi = min((m == 0) ? 2 : m + 1, nz - 1);
-            while (loaded < hi) {
-                ++loaded;
-                load_plane(loaded);
-                __syncthreads();
-                bz_plane(loaded);
-                __syncthreads();
-            }
-        }
+        // P(m+1) is resident; prefetch the next P plane and form Bz on the
+        // highest plane this step reads (plane 2 for the base plane)
+        const int nxt = (m == 0) ? 3 : m + 2;
+        const int hb = (m == 0) ? 2 : m + 1;
+        const bool pf = (nxt <= nz - 1) && (m + 1 < ke);
+        if (pf) fetch(nxt);
+        if (hb <= nz - 1) bz_plane(hb);
+        lds_barrier();
         const double xi = tab[m], dxi = tab[nz + m], pb = tab[2 * nz + m], rhob = tab[3 * nz + m];
         for (int e = tid; e < kFY * kTX; e += kThreads) {
             const int w = e / kTX, c = e % kTX;
@@ -847,12 +1120,12 @@ __global__ __launch_bounds__(kThreads) void k_fields(const FieldsItem *__restric
             double bx = 0.0, by = 0.0, bz = 0.0, p = pb, rho = rhob;
             if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2 && m <= nz - 2) {
                 const int pw = w + 2, pc = c + 2, bw = w + 1, bc = c + 1;
-                double(*Pc)[kFPX] = SP[m % 3];
+                double(*Pc)[kFPX] = SP[m & 3];
                 double(*Bc)[kFBX] = SB[m % 3];
                 double dzp_xp, dzp_xm, dzp_yp, dzp_ym, dbzz;
                 if (m >= 1) {
-                    double(*Pu)[kFPX] = SP[(m + 1) % 3];
-                    double(*Pd)[kFPX] = SP[(m + 2) % 3];
+                    double(*Pu)[kFPX] = SP[(m + 1) & 3];
+                    double(*Pd)[kFPX] = SP[(m - 1) & 3];
                     dzp_xp = (Pu[pw][pc + 1] - Pd[pw][pc + 1]) * i2dz;
                     dzp_xm = (Pu[pw][pc - 1] - Pd[pw][pc - 1]) * i2dz;
                     dzp_yp = (Pu[pw + 1][pc] - Pd[pw + 1][pc]) * i2dz;
@@ -861,7 +1134,7 @@ __global__ __launch_bounds__(kThreads) void k_fields(const FieldsItem *__restric
                 } else {
                     double(*P1)[kFPX] = SP[1];
                     double(*P2)[kFPX] = SP[2];
-                    auto one = [&](int a, int b) { return (-3.0 * Pc[a][b] + 4.0 * P1[a][b] - P2[a][b]) * i2dz; };
+                    auto one = [&](int a, int bb) { return (-3.0 * Pc[a][bb] + 4.0 * P1[a][bb] - P2[a][bb]) * i2dz; };
                     dzp_xp = one(pw, pc + 1);
                     dzp_xm = one(pw, pc - 1);
                     dzp_yp = one(pw + 1, pc);
@@ -877,13 +1150,15 @@ __global__ __launch_bounds__(kThreads) void k_fields(const FieldsItem *__restric
                 p = pb - xi * bz2 / (2.0 * mu0);
                 rho = rhob + (dxi * bz2 / (2.0 * mu0) + xi * (bx * dbzx + by * dbzy + bz * dbzz) / mu0) / g;
             }
-            it->Bx[idx] = bx;
-            it->By[idx] = by;
-            it->Bz[idx] = bz;
-            it->p[idx] = p;
-            it->rho[idx] = rho;
+            oBx[idx] = bx;
+            oBy[idx] = by;
+            oBz[idx] = bz;
+            op[idx] = p;
+            orho[idx] = rho;
         }
-        __syncthreads();
+        // P(nxt) replaces the slot of plane nxt-4, last read two steps ago
+        if (pf) stash(nxt);
+        lds_barrier();
     }
 }
 
@@ -1045,14 +1320,25 @@ hipError_t launch_ir3(const LevelItem *items, int nitems, int ntiles, bool has_e
     return hipGetLastError();
 }
 
-hipError_t launch_bottom(const BottomItem *items, int nitems, bool dbl, hipStream_t s)
+hipError_t launch_bottom(const BottomItem *items, int nitems, int lds_bytes, bool dbl, hipStream_t s)
 {
     if (nitems <= 0) return hipSuccess;
+    if (lds_bytes <= 0 || lds_bytes > kBottomLdsMax) return hipErrorInvalidValue;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bottom<double>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, kBottomLdsMax);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bottom<float>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, kBottomLdsMax);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
     dim3 grid(nitems), block(kBottomThreads);
     if (dbl)
-        hipLaunchKernelGGL((k_bottom<double>), grid, block, 0, s, items, nitems);
+        hipLaunchKernelGGL((k_bottom<double>), grid, block, lds_bytes, s, items, nitems);
     else
-        hipLaunchKernelGGL((k_bottom<float>), grid, block, 0, s, items, nitems);
+        hipLaunchKernelGGL((k_bottom<float>), grid, block, lds_bytes, s, items, nitems);
     return hipGetLastError();
 }
 

@@ -25,6 +25,8 @@ struct Level {
     double cz = 0.0;
     int st[3] = {0, 0, 0}; // smoother tiles per axis
     int rt[3] = {0, 0, 0}; // restriction tiles per axis (onto level+1)
+    int kz = 1;            // smoother planes per workgroup
+    int kc = 1;            // restriction coarse planes per workgroup
     int sweep_tiles() const { return st[0] * st[1] * st[2]; }
     int restrict_tiles() const { return rt[0] * rt[1] * rt[2]; }
 };
@@ -34,9 +36,7 @@ struct Hierarchy {
     int L = 0; // levels
     int b = 0; // first level handled by the bottom solver
     Level lv[kMaxLevels];
-    double *bu[kMaxLevels] = {};
-    double *bf[kMaxLevels] = {};
-    double *br = nullptr;
+    int lds_bytes = 0;      // bottom solver LDS footprint
     double *minv = nullptr; // device m x m
     int m = 0;              // coarsest unknowns
     double *partials = nullptr;
@@ -51,6 +51,7 @@ struct Launch {
     const void *items = nullptr; // device pointer
     int nitems = 1;
     int ntiles = 0;
+    int lds = 0; // bottom: dynamic LDS bytes
     // copy
     const double *src = nullptr;
     double *dst = nullptr;

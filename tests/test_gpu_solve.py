@@ -180,3 +180,25 @@ def test_error_paths(plans):
     nan_bz[5, 5] = float("nan")
     info = plan.solve_boundary(nan_bz, P, make_opts(), raise_on_error=False)
     assert info.status == _lib.ERR_DIVERGED
+
+
+def test_stage_calls_do_not_disturb_solves(plans):
+    """Stage entry points borrow solver scratch buffers; a solve after them
+    must be unaffected (regression: an FP32 stage call once left nonzero
+    boundary values in the refinement's scratch and broke the next solve)."""
+    dims = (65, 65, 65)
+    w = synth.workload("mhs-129", dims=dims)
+    m = w.model
+    plan = plans(dims)
+    bz = torch.from_numpy(w.bz0).to(DEV)
+    ref_res = solve(plan, bz, m, precision=PREC_MIXED, rtol=1e-10)
+    ref_P = ref_res.P.clone()
+    u32 = torch.randn(dims[::-1], dtype=torch.float32, device=DEV)
+    plan.stage_smooth(m, 3, 0, u32, torch.randn_like(u32), 2, precision=PREC_MIXED)
+    u64 = torch.randn(plan.level_shape(3, 1), dtype=torch.float64, device=DEV)
+    plan.stage_smooth(m, 3, 1, u64, torch.randn_like(u64), 2)
+    plan.stage_residual_norm(m, 3, 1, u64, torch.randn_like(u64))
+    again = solve(plan, bz, m, precision=PREC_MIXED, rtol=1e-10)
+    assert torch.equal(again.P, ref_P)
+    again = solve(plan, bz, m, precision=PREC_FP64, rtol=1e-10)
+    assert (again.P - ref_P).abs().max().item() < 1e-8 * ref_P.abs().max().item()
