@@ -206,34 +206,91 @@ int mhs_stage_residual_norm(mhs_plan *plan, const mhs_model *model, int32_t spac
                             int32_t level, int32_t precision, const void *d_u, const void *d_f,
                             double *norm, void *stream);
 
+/* ---- measurement ------------------------------------------------------- *
+ * When profiling is enabled on a plan, each launch of the selected kernel
+ * classes below is bracketed by HIP events on the call's stream (select
+ * few classes to keep the perturbation small: each event is a queue
+ * packet between kernels).  Solves count only
+ * cycles that executed (the status read-back tells how many), so launches
+ * skipped by the device-side stopping flag are excluded.  Each launch also
+ * adds its compulsory HBM traffic (bytes the kernel must read and write:
+ * each input array once, each output once) to the class. */
+#define MHS_PROF_SMOOTH_L0 0   /* finest-level 3D smoother, FP64 or FP32  */
+#define MHS_PROF_REFINE 1      /* FP64 refinement update + residual       */
+#define MHS_PROF_RESTRICT_L0 2 /* finest-level residual + restriction     */
+#define MHS_PROF_FIELDS 3      /* field recovery                          */
+#define MHS_PROF_BOTTOM 4      /* single-workgroup bottom solver          */
+#define MHS_PROF_COARSE 5      /* every other stencil launch (levels >= 1, 2D) */
+#define MHS_PROF_NCLASS 6
+#define MHS_PROF_ALL 0x3f      /* mask of every class                      */
+
+/* class_mask: bit (1 << MHS_PROF_x) times class x; 0 disables profiling. */
+int mhs_profile_enable(mhs_plan *plan, int32_t class_mask);
+/* Totals since the last reset for one class (synchronizes pending events). */
+int mhs_profile_read(mhs_plan *plan, int32_t klass, double *total_ms, int64_t *launches,
+                     double *bytes, int32_t reset);
+
 /* ---- continuous batching (serving) ------------------------------------ *
- * A batch advances many independent solves together: each tick runs, for
- * every active slot, one V-cycle of its current phase (boundary solve, then
- * interior solve, then fields), and launches each stage of the tick once
- * for all slots (descriptor-driven kernels).  Slots hold a plan, device
- * buffers and options; admission policy (memory budget, queueing) belongs
- * to the caller. */
+ * A batch advances many independent equilibria together.  Each admitted
+ * request goes through the procedure of Section 2.2: the lower-boundary
+ * solve of (11), the interior solve of (8) (FP64 V-cycles or FP32-in-FP64
+ * refinement), then the field recovery.  One tick advances every active
+ * slot by one V-cycle (or one refinement step) of its current phase; the
+ * launches of a tick are merged across slots, so each stage of the tick is
+ * one descriptor-driven launch covering every slot that has it (requests
+ * of different shapes and precisions share launches).  The merged path
+ * runs the same kernels with the same per-request tiling and reduction
+ * order as the single-request entry points, so a request gives bit-for-bit
+ * the result of mhs_solve_boundary + mhs_solve_interior + mhs_fields.
+ *
+ * Memory: the batch holds per-slot status words and its launch-descriptor
+ * tables in a caller-provided device workspace of
+ * mhs_batch_workspace_bytes(max_slots) bytes (256-byte aligned); each slot
+ * uses its own plan's workspace for everything else.  Admission policy
+ * (memory budget, queueing, plan pooling) belongs to the caller.
+ * A batch is used from one host thread; ticks are synchronous. */
 typedef struct mhs_batch mhs_batch;
 
-int mhs_batch_create(int32_t max_slots, mhs_batch **batch);
+/* Device workspace a batch of max_slots (1..1024) slots needs. */
+int mhs_batch_workspace_bytes(int32_t max_slots, size_t *bytes);
+
+/* Create a batch on the current device over d_ws (owned by the caller,
+ * kept until mhs_batch_destroy).  Allocates host structures and pinned
+ * status/descriptor buffers only. */
+int mhs_batch_create(int32_t max_slots, void *d_ws, size_t ws_bytes, mhs_batch **batch);
 int mhs_batch_destroy(mhs_batch *batch);
 
-/* Admit one request into a free slot (MHS_ERR_BUDGET if none).  The plan
- * (exclusive to this slot while it is active), d_bz0, d_P and the five
- * field outputs must stay valid until the slot is released.  Model arrays
- * are copied.  opts->precision selects the interior path. */
+/* Admit one request into a free slot.  The plan must be exclusive to this
+ * slot until the slot is released (a plan already held by an active slot
+ * gives MHS_ERR_INVALID_ARG) and live on the batch's device.  d_bz0
+ * ((ny, nx)), d_P and the five field outputs ((nz, ny, nx)) must stay valid
+ * until the slot is released.  Model arrays are copied; the model's
+ * coefficient tables and the coarsest-grid inverse are built here
+ * (synchronously), so admission can fail with MHS_ERR_NOT_ELLIPTIC or
+ * MHS_ERR_INDEFINITE.  opts->precision selects the interior path (the
+ * boundary solve is always FP64); opts->rtol and max_cycles apply to both
+ * solves; opts->check_every is ignored (every tick reads the status).
+ * MHS_ERR_BUDGET: no free slot, or the request's per-tick descriptors
+ * exceed the slot's share of the descriptor table (very large nu1, nu2 or
+ * inner_cycles).  On success *slot is the slot index (0..max_slots-1). */
 int mhs_batch_admit(mhs_batch *batch, mhs_plan *plan, const mhs_model *model,
                     const double *d_bz0, double *d_P, double *d_Bx, double *d_By, double *d_Bz,
                     double *d_p, double *d_rho, const mhs_opts *opts, int32_t *slot);
 
-/* One tick on `stream`; blocks until the tick's status read-back.
- * *active receives the number of slots still running after the tick. */
+/* One tick on `stream`; returns after the tick's status read-back.
+ * *active (optional) receives the number of slots still running. */
 int mhs_batch_step(mhs_batch *batch, void *stream, int32_t *active);
 
-/* Status of a slot: *done = 1 once its fields are written (info filled). */
-int mhs_batch_poll(mhs_batch *batch, int32_t slot, int32_t *done, mhs_info *info);
+/* Status of a slot.  *done = 1 once the request has finished: its fields
+ * are written (status MHS_OK) or one of its solves stopped with an error
+ * (the slot's info carries the code; later phases are not run).
+ * `boundary` and `interior` (optional) receive the per-solve info: cycles,
+ * refinement steps, residuals, status; `seconds` is the wall time from
+ * admission to the end of that phase. */
+int mhs_batch_poll(mhs_batch *batch, int32_t slot, int32_t *done, mhs_info *boundary,
+                   mhs_info *interior);
 
-/* Free a slot (finished or not) for reuse. */
+/* Free a slot (finished or not) for reuse; its plan may then be reused. */
 int mhs_batch_release(mhs_batch *batch, int32_t slot);
 
 #ifdef __cplusplus

@@ -31,6 +31,9 @@ ERR_NO_CONVERGENCE, ERR_DIVERGED, ERR_BUDGET, ERR_WORKSPACE, ERR_HIP, ERR_UNSUPP
 PREC_FP64 = 1
 PREC_MIXED = 2
 
+PROF_SMOOTH_L0, PROF_REFINE, PROF_RESTRICT_L0, PROF_FIELDS, PROF_BOTTOM, PROF_COARSE = range(6)
+PROF_NAMES = ("smooth_l0", "refine", "restrict_l0", "fields", "bottom", "coarse")
+
 
 class MHSError(RuntimeError):
     def __init__(self, code, message):
@@ -96,6 +99,8 @@ def lib():
         "mhs_stage_correct_smooth": (C.c_int, [vp, P(Model), i32, i32, i32, vp, vp, vp, vp]),
         "mhs_stage_bottom": (C.c_int, [vp, P(Model), i32, i32, vp, vp, i32, i32, P(i32), vp]),
         "mhs_stage_residual_norm": (C.c_int, [vp, P(Model), i32, i32, i32, vp, vp, P(dbl), vp]),
+        "mhs_profile_enable": (C.c_int, [vp, i32]),
+        "mhs_profile_read": (C.c_int, [vp, i32, P(dbl), P(C.c_int64), P(dbl), i32]),
     }
     batch = {
         "mhs_batch_workspace_bytes": (C.c_int, [i32, P(C.c_size_t)]),
@@ -103,7 +108,7 @@ def lib():
         "mhs_batch_destroy": (C.c_int, [vp]),
         "mhs_batch_admit": (C.c_int, [vp, vp, P(Model), vp, vp, vp, vp, vp, vp, vp, P(Opts), P(i32)]),
         "mhs_batch_step": (C.c_int, [vp, vp, P(i32)]),
-        "mhs_batch_poll": (C.c_int, [vp, i32, P(i32), P(Info)]),
+        "mhs_batch_poll": (C.c_int, [vp, i32, P(i32), P(Info), P(Info)]),
         "mhs_batch_release": (C.c_int, [vp, i32]),
     }
     for name, (res, args) in sig.items():

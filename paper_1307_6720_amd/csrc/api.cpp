@@ -20,7 +20,7 @@
 
 using namespace mhs;
 
-namespace {
+namespace mhs {
 
 thread_local std::string g_err;
 
@@ -34,12 +34,6 @@ int fail(int code, const char *fmt, ...)
     g_err = buf;
     return code;
 }
-
-#define HIPCHK(expr)                                                                              \
-    do {                                                                                          \
-        hipError_t e_ = (expr);                                                                   \
-        if (e_ != hipSuccess) return fail(MHS_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
 
 constexpr size_t kAlign = 256;
 constexpr size_t kStagingBytes = 1 << 20;
@@ -413,11 +407,6 @@ int validate_opts(const mhs_opts *o)
 
 // ---- programs -----------------------------------------------------------------
 
-struct Program {
-    std::vector<Launch> launches;
-    bool ok = true;
-};
-
 LevelItem level_item(const Hierarchy &h, int l, int path)
 {
     const Level &lv = h.lv[l];
@@ -463,6 +452,16 @@ void add_sweep(Program &pg, Staging &st, const Hierarchy &h, int l, int path, co
     L.items = d;
     L.nitems = 1;
     L.ntiles = lv.sweep_tiles();
+    L.prof = (l == 0 && !h.planar) ? MHS_PROF_SMOOTH_L0 : MHS_PROF_COARSE;
+    {
+        const double es = path == kF64 ? 8.0 : 4.0;
+        double words = 1.0;                      // write u
+        if (!(L.flags & kZeroIn)) words += 1.0;  // read u
+        if (L.flags & kHasF) words += 1.0;       // read f
+        L.bytes = es * words * (double)lv.N;
+        if ((L.flags & kProlong) && l + 1 < h.L) L.bytes += es * (double)h.lv[l + 1].N;
+    }
+    L.pre = (flags & kNorm) != 0;
     pg.launches.push_back(L);
 }
 
@@ -490,6 +489,11 @@ void add_restrict(Program &pg, Staging &st, const Hierarchy &h, int l, int path,
     L.dbl = path == kF64;
     L.items = d;
     L.ntiles = lv.restrict_tiles();
+    L.prof = (l == 0 && !h.planar) ? MHS_PROF_RESTRICT_L0 : MHS_PROF_COARSE;
+    {
+        const double es = path == kF64 ? 8.0 : 4.0;
+        L.bytes = es * ((f ? 2.0 : 1.0) * (double)lv.N + (double)h.lv[l + 1].N);
+    }
     pg.launches.push_back(L);
 }
 
@@ -536,6 +540,8 @@ void add_bottom(Program &pg, Staging &st, const Hierarchy &h, int path, const vo
     L.dbl = path == kF64;
     L.items = d;
     L.lds = h.lds_bytes;
+    L.prof = MHS_PROF_BOTTOM;
+    L.bytes = (path == kF64 ? 8.0 : 4.0) * 2.0 * (double)h.lv[h.b].N;
     pg.launches.push_back(L);
 }
 
@@ -610,37 +616,153 @@ void *add_cycle(Program &pg, Staging &st, const Hierarchy &h, int path, void *a0
     return cur;
 }
 
-int run_program(const Program &pg, hipStream_t s)
+// The FP64 part of one refinement step: u_out = u_in + e (when e is given),
+// r32 = -A u_out in FP32, and the norm check of u_out.  The inner FP32
+// cycles that produce the next e follow it in the same program.
+void add_ir_step(Program &pg, Staging &st, const Hierarchy &h, const double *uin, double *uout, const void *e,
+                 float *r32, SolveState *state)
 {
+    const Level &l0 = h.lv[0];
+    LevelItem it = level_item(h, 0, kF64);
+    it.u_in = uin;
+    it.u_out = uout;
+    it.ec = e;
+    it.r_out = r32;
+    it.state = state;
+    it.partials = h.partials;
+    it.ntx = l0.st[0];
+    it.nty = l0.st[1];
+    it.ntz = l0.st[2];
+    it.kz = l0.kz;
+    const LevelItem *d = st.put(it);
+    if (!d) {
+        pg.ok = false;
+        return;
+    }
+    Launch L{};
+    L.kind = Launch::kIr3;
+    L.flags = e ? 1 : 0;
+    L.items = d;
+    L.ntiles = l0.sweep_tiles();
+    L.prof = MHS_PROF_REFINE;
+    L.bytes = (double)l0.N * (e ? 8.0 + 4.0 + 8.0 + 4.0 : 8.0 + 4.0);
+    L.pre = true;
+    pg.launches.push_back(L);
+    add_finalize(pg, st, h.partials, h.npart, state);
+}
+
+FieldsItem fields_item(const mhs_plan *p, const mhs_model *model, const double *tab, const double *P, double *Bx,
+                       double *By, double *Bz, double *pr, double *rho)
+{
+    const int nx = p->grid.nx, ny = p->grid.ny, nz = p->grid.nz;
+    FieldsItem fi{};
+    fi.P = P;
+    fi.Bx = Bx;
+    fi.By = By;
+    fi.Bz = Bz;
+    fi.p = pr;
+    fi.rho = rho;
+    fi.tab = tab;
+    fi.alpha = model->alpha;
+    fi.mu0 = model->mu0;
+    fi.g = model->g;
+    fi.dx = p->grid.lx / (nx - 1);
+    fi.dy = p->grid.ly / (ny - 1);
+    fi.dz = p->grid.lz / (nz - 1);
+    fi.nx = nx;
+    fi.ny = ny;
+    fi.nz = nz;
+    fi.ntx = ceil_div(nx, kTX);
+    fi.nty = ceil_div(ny, kFY);
+    fi.kz = chunk(nz, fi.ntx * fi.nty, kKZ);
+    fi.ntz = ceil_div(nz, fi.kz);
+    fi.tile_base = 0;
+    return fi;
+}
+
+hipEvent_t prof_event(Profiler &pr)
+{
+    if (pr.next == pr.pool.size()) {
+        hipEvent_t e = nullptr;
+        // timing-only events: no system-scope fence (cache writeback) at record
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
+        pr.pool.push_back(e);
+    }
+    return pr.pool[pr.next++];
+}
+
+// Fold recorded launches into the class totals.  `last` is the index of the
+// final cycle/step (the one whose check stopped the solve): its launches
+// before the check ran, the rest were skipped by the device-side flag.
+int prof_collect(mhs_plan *p, int last)
+{
+    Profiler &pr = p->prof;
+    for (const ProfRecord &r : pr.pending) {
+        const bool ran = r.cycle < 0 || r.cycle < last || (r.pre && r.cycle == last);
+        if (!ran) continue;
+        HIPCHK(hipEventSynchronize(r.end));
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, r.start, r.end));
+        pr.ms[r.klass] += ms;
+        pr.bytes[r.klass] += r.bytes;
+        pr.launches[r.klass] += 1;
+    }
+    pr.pending.clear();
+    pr.next = 0;
+    return MHS_OK;
+}
+
+hipError_t exec_launch(const Launch &L, hipStream_t s)
+{
+    switch (L.kind) {
+    case Launch::kSweep3:
+        return launch_sweep3((const LevelItem *)L.items, L.nitems, L.ntiles, L.flags, L.dbl, s);
+    case Launch::kSweep2:
+        return launch_sweep2((const LevelItem *)L.items, L.nitems, L.ntiles, L.flags, L.dbl, s);
+    case Launch::kRestrict3:
+        return launch_restrict3((const LevelItem *)L.items, L.nitems, L.ntiles, L.flags != 0, L.dbl, s);
+    case Launch::kRestrict2:
+        return launch_restrict2((const LevelItem *)L.items, L.nitems, L.ntiles, L.dbl, s);
+    case Launch::kIr3:
+        return launch_ir3((const LevelItem *)L.items, L.nitems, L.ntiles, L.flags != 0, s);
+    case Launch::kBottom:
+        return launch_bottom((const BottomItem *)L.items, L.nitems, L.lds, L.dbl, s);
+    case Launch::kFinalize:
+        return launch_finalize((const FinalizeItem *)L.items, L.nitems, s);
+    case Launch::kCopy:
+        return launch_copy(L.src, L.dst, L.n, L.gate, s);
+    case Launch::kFields:
+        return launch_fields((const FieldsItem *)L.items, L.nitems, L.ntiles, s);
+    case Launch::kPrep3:
+        return launch_prep3((const PrepItem *)L.items, L.nitems, L.n, s);
+    case Launch::kPrep2:
+        return launch_prep2((const PrepItem *)L.items, L.nitems, L.n, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+int run_program(mhs_plan *p, const Program &pg, hipStream_t s, int cycle = -1)
+{
+    Profiler &pr = p->prof;
     for (const Launch &L : pg.launches) {
-        hipError_t e = hipSuccess;
-        switch (L.kind) {
-        case Launch::kSweep3:
-            e = launch_sweep3((const LevelItem *)L.items, L.nitems, L.ntiles, L.flags, L.dbl, s);
-            break;
-        case Launch::kSweep2:
-            e = launch_sweep2((const LevelItem *)L.items, L.nitems, L.ntiles, L.flags, L.dbl, s);
-            break;
-        case Launch::kRestrict3:
-            e = launch_restrict3((const LevelItem *)L.items, L.nitems, L.ntiles, L.flags != 0, L.dbl, s);
-            break;
-        case Launch::kRestrict2:
-            e = launch_restrict2((const LevelItem *)L.items, L.nitems, L.ntiles, L.dbl, s);
-            break;
-        case Launch::kIr3:
-            e = launch_ir3((const LevelItem *)L.items, L.nitems, L.ntiles, L.flags != 0, s);
-            break;
-        case Launch::kBottom:
-            e = launch_bottom((const BottomItem *)L.items, L.nitems, L.lds, L.dbl, s);
-            break;
-        case Launch::kFinalize:
-            e = launch_finalize((const FinalizeItem *)L.items, L.nitems, s);
-            break;
-        case Launch::kCopy:
-            e = launch_copy(L.src, L.dst, L.n, L.gate, s);
-            break;
+        ProfRecord rec{};
+        const bool timed = L.prof >= 0 && ((pr.mask >> L.prof) & 1) != 0;
+        if (timed) {
+            rec.klass = L.prof;
+            rec.cycle = cycle;
+            rec.pre = L.pre;
+            rec.bytes = L.bytes;
+            rec.start = prof_event(pr);
+            rec.end = prof_event(pr);
+            if (!rec.start || !rec.end) return fail(MHS_ERR_HIP, "event creation failed");
+            HIPCHK(hipEventRecord(rec.start, s));
         }
+        const hipError_t e = exec_launch(L, s);
         if (e != hipSuccess) return fail(MHS_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+        if (timed) {
+            HIPCHK(hipEventRecord(rec.end, s));
+            pr.pending.push_back(rec);
+        }
     }
     return MHS_OK;
 }
@@ -729,7 +851,7 @@ int drive(mhs_plan *p, const Program &cycle, const SolveState *d_state, const mh
         const int nb = next_batch(ss, o, launched);
         if (nb <= 0) break;
         for (int q = 0; q < nb; ++q) {
-            int st = run_program(cycle, s);
+            int st = run_program(p, cycle, s, launched + q);
             if (st) return st;
         }
         launched += nb;
@@ -739,7 +861,7 @@ int drive(mhs_plan *p, const Program &cycle, const SolveState *d_state, const mh
         if (ss.done != kRunning) break;
     }
     *out = ss;
-    return MHS_OK;
+    return prof_collect(p, ss.checks - 1);
 }
 
 double seconds_since(std::chrono::steady_clock::time_point t0)
@@ -747,7 +869,7 @@ double seconds_since(std::chrono::steady_clock::time_point t0)
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
-} // namespace
+} // namespace mhs
 
 // =================================================================================
 // C ABI
@@ -834,6 +956,7 @@ int mhs_plan_destroy(mhs_plan *p)
         (void)hipEventSynchronize(p->stage.inflight);
         (void)hipEventDestroy(p->stage.inflight);
     }
+    for (hipEvent_t e : p->prof.pool) (void)hipEventDestroy(e);
     if (p->stage.host) (void)hipHostFree(p->stage.host);
     if (p->h_states) (void)hipHostFree(p->h_states);
     delete p;
@@ -987,36 +1110,12 @@ int mhs_solve_interior(mhs_plan *p, const mhs_model *model, double *d_P, const m
             void *bb = (a == l0.u[kF32]) ? l0.t[kF32] : l0.u[kF32];
             ebuf = add_cycle(inner, p->stage, h, kF32, a, bb, r32, c == 0, false, o->nu1, o->nu2, d_state);
         }
-        auto ir_step = [&](Program &pg, const double *uin, double *uout, bool has_e) {
-            LevelItem it = level_item(h, 0, kF64);
-            it.u_in = uin;
-            it.u_out = uout;
-            it.ec = has_e ? ebuf : nullptr;
-            it.r_out = r32;
-            it.state = d_state;
-            it.partials = h.partials;
-            it.ntx = l0.st[0];
-            it.nty = l0.st[1];
-            it.ntz = l0.st[2];
-            it.kz = l0.kz;
-            const LevelItem *d = p->stage.put(it);
-            if (!d) {
-                pg.ok = false;
-                return;
-            }
-            Launch L{};
-            L.kind = Launch::kIr3;
-            L.flags = has_e ? 1 : 0;
-            L.items = d;
-            L.ntiles = l0.sweep_tiles();
-            pg.launches.push_back(L);
-            add_finalize(pg, p->stage, h.partials, h.npart, d_state);
-            pg.launches.insert(pg.launches.end(), inner.launches.begin(), inner.launches.end());
-        };
         Program first, odd, even;
-        ir_step(first, d_P, nullptr, false);
-        ir_step(odd, d_P, T0, true);
-        ir_step(even, T0, d_P, true);
+        add_ir_step(first, p->stage, h, d_P, nullptr, nullptr, r32, d_state);
+        add_ir_step(odd, p->stage, h, d_P, T0, ebuf, r32, d_state);
+        add_ir_step(even, p->stage, h, T0, d_P, ebuf, r32, d_state);
+        for (Program *pg : {&first, &odd, &even})
+            pg->launches.insert(pg->launches.end(), inner.launches.begin(), inner.launches.end());
         if (!first.ok || !odd.ok || !even.ok || !inner.ok || !d_state || !d_prep)
             return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
         if ((st = flush_staging(p, s))) return st;
@@ -1029,7 +1128,7 @@ int mhs_solve_interior(mhs_plan *p, const mhs_model *model, double *d_P, const m
             for (int q = 0; q < nb; ++q) {
                 const int step = launched + q;
                 const Program &pg = step == 0 ? first : ((step & 1) ? odd : even);
-                if ((st = run_program(pg, s))) return st;
+                if ((st = run_program(p, pg, s, step))) return st;
             }
             launched += nb;
             if ((st = read_state(p, d_state, &ss, s))) return st;
@@ -1037,6 +1136,7 @@ int mhs_solve_interior(mhs_plan *p, const mhs_model *model, double *d_P, const m
             if (ss.done != kRunning) break;
         }
         fin = ss;
+        if ((st = prof_collect(p, fin.checks - 1))) return st;
         const int steps = std::max(0, fin.checks - 1);
         inner_total = steps * o->inner_cycles;
         if (steps & 1) {
@@ -1081,32 +1181,46 @@ int mhs_fields(mhs_plan *p, const mhs_model *model, const double *d_P, double *d
     if (tab_off + tab.size() * sizeof(double) > p->stage.cap) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
     std::memcpy(p->stage.host + tab_off, tab.data(), tab.size() * sizeof(double));
     p->stage.used += tab.size() * sizeof(double);
-    FieldsItem fi{};
-    fi.P = d_P;
-    fi.Bx = d_Bx;
-    fi.By = d_By;
-    fi.Bz = d_Bz;
-    fi.p = d_p;
-    fi.rho = d_rho;
-    fi.tab = (const double *)(p->stage.dev + tab_off);
-    fi.alpha = model->alpha;
-    fi.mu0 = model->mu0;
-    fi.g = model->g;
-    fi.dx = p->grid.lx / (nx - 1);
-    fi.dy = p->grid.ly / (ny - 1);
-    fi.dz = p->grid.lz / (nz - 1);
-    fi.nx = nx;
-    fi.ny = ny;
-    fi.nz = nz;
-    fi.ntx = ceil_div(nx, kTX);
-    fi.nty = ceil_div(ny, kFY);
-    fi.kz = chunk(nz, fi.ntx * fi.nty, kKZ);
-    fi.ntz = ceil_div(nz, fi.kz);
-    fi.tile_base = 0;
+    const FieldsItem fi = fields_item(p, model, (const double *)(p->stage.dev + tab_off), d_P, d_Bx, d_By, d_Bz, d_p,
+                                      d_rho);
     const FieldsItem *d = p->stage.put(fi);
     if (!d) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
     if ((st = flush_staging(p, s))) return st;
-    HIPCHK(launch_fields(d, 1, fi.ntx * fi.nty * fi.ntz, s));
+    Program pg;
+    Launch L{};
+    L.kind = Launch::kFields;
+    L.items = d;
+    L.ntiles = fi.ntx * fi.nty * fi.ntz;
+    L.prof = MHS_PROF_FIELDS;
+    L.bytes = 48.0 * (double)nx * ny * nz;
+    pg.launches.push_back(L);
+    return run_program(p, pg, s);
+}
+
+int mhs_profile_enable(mhs_plan *p, int32_t class_mask)
+{
+    if (!p) return fail(MHS_ERR_INVALID_ARG, "plan is NULL");
+    if (class_mask < 0 || class_mask > MHS_PROF_ALL) return fail(MHS_ERR_INVALID_ARG, "bad class mask");
+    p->prof.mask = class_mask;
+    return MHS_OK;
+}
+
+int mhs_profile_read(mhs_plan *p, int32_t klass, double *total_ms, int64_t *launches, double *bytes,
+                     int32_t reset)
+{
+    if (!p || klass < 0 || klass >= MHS_PROF_NCLASS) return fail(MHS_ERR_INVALID_ARG, "bad plan or class");
+    int st = prof_collect(p, -1 + (1 << 30)); // anything still pending was launched by an asynchronous call
+    if (st) return st;
+    if (total_ms) *total_ms = p->prof.ms[klass];
+    if (launches) *launches = p->prof.launches[klass];
+    if (bytes) *bytes = p->prof.bytes[klass];
+    if (reset) {
+        for (int k = 0; k < MHS_PROF_NCLASS; ++k) {
+            p->prof.ms[k] = 0.0;
+            p->prof.bytes[k] = 0.0;
+            p->prof.launches[k] = 0;
+        }
+    }
     return MHS_OK;
 }
 
@@ -1179,7 +1293,7 @@ int mhs_stage_smooth(mhs_plan *p, const mhs_model *model, int32_t space, int32_t
     }
     if (!pg.ok) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
     if ((st = flush_staging(p, s))) return st;
-    if ((st = run_program(pg, s))) return st;
+    if ((st = run_program(p, pg, s))) return st;
     if (cur != d_u) HIPCHK(hipMemcpyAsync(d_u, cur, bytes, hipMemcpyDeviceToDevice, s));
     return release_twin(*h, level, path, s);
 }
@@ -1199,7 +1313,7 @@ int mhs_stage_restrict(mhs_plan *p, const mhs_model *model, int32_t space, int32
     add_restrict(pg, p->stage, *h, level, path, d_u, d_f, d_fc, nullptr);
     if (!pg.ok) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
     if ((st = flush_staging(p, s))) return st;
-    return run_program(pg, s);
+    return run_program(p, pg, s);
 }
 
 int mhs_stage_correct_smooth(mhs_plan *p, const mhs_model *model, int32_t space, int32_t level, int32_t precision,
@@ -1220,7 +1334,7 @@ int mhs_stage_correct_smooth(mhs_plan *p, const mhs_model *model, int32_t space,
     add_sweep(pg, p->stage, *h, level, path, d_u, tw, d_f, d_ec, kProlong, nullptr, nullptr);
     if (!pg.ok) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
     if ((st = flush_staging(p, s))) return st;
-    if ((st = run_program(pg, s))) return st;
+    if ((st = run_program(p, pg, s))) return st;
     HIPCHK(hipMemcpyAsync(d_u, tw, bytes, hipMemcpyDeviceToDevice, s));
     return release_twin(*h, level, path, s);
 }
@@ -1240,7 +1354,7 @@ int mhs_stage_bottom(mhs_plan *p, const mhs_model *model, int32_t space, int32_t
     add_bottom(pg, p->stage, *h, path, d_f, d_u, nu1, nu2, nullptr);
     if (!pg.ok) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
     if ((st = flush_staging(p, s))) return st;
-    return run_program(pg, s);
+    return run_program(p, pg, s);
 }
 
 int mhs_stage_residual_norm(mhs_plan *p, const mhs_model *model, int32_t space, int32_t level, int32_t precision,
@@ -1262,7 +1376,7 @@ int mhs_stage_residual_norm(mhs_plan *p, const mhs_model *model, int32_t space, 
     add_finalize(pg, p->stage, p->d_scratch_norm, h->lv[level].sweep_tiles(), d_state);
     if (!pg.ok || !d_state) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
     if ((st = flush_staging(p, s))) return st;
-    if ((st = run_program(pg, s))) return st;
+    if ((st = run_program(p, pg, s))) return st;
     if ((st = release_twin(*h, level, path, s))) return st;
     SolveState ss{};
     if ((st = read_state(p, d_state, &ss, s))) return st;

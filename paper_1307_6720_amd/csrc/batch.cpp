@@ -1,0 +1,602 @@
+// Continuous batching of independent equilibria.
+//
+// Every request runs the procedure of Section 2.2 (the lower-boundary solve
+// of (11), the interior solve of (8), the field recovery) on its own plan.
+// A tick advances each active request by one V-cycle (or one refinement
+// step) of its current phase.  The per-request programs are built with the
+// same builders as the single-request entry points into a host recorder,
+// tagged with a merge key, and launches with equal key and kernel variant
+// are fused into one multi-item launch whose descriptor table lists the
+// requests' items back to back (tile offsets prefix-summed).  Kernels find
+// their item by binary search over those offsets, so each request keeps its
+// own tiling and reduction order: results are bitwise those of the
+// single-request path.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <vector>
+
+#include "plan.h"
+
+using namespace mhs;
+
+namespace {
+
+constexpr int kMaxBatchSlots = 1024;
+constexpr size_t kWsAlign = 256;
+// Descriptor bytes one request may use per tick (default options need
+// about 6 KB at 257^3; nu1 = nu2 = 16 with several inner cycles do not fit).
+constexpr size_t kSlotStageBytes = 48 * 1024;
+constexpr size_t kItemAlign = 64;
+
+enum Phase : int { kFree = 0, kBoundary, kInterior, kFinish, kDone };
+
+struct Slot {
+    Phase phase = kFree;
+    bool fresh = false; // the current phase starts in the next tick
+    mhs_plan *plan = nullptr;
+    double alpha = 0.0, mu0 = 1.0, g = 1.0;
+    const double *bz0 = nullptr;
+    double *P = nullptr, *Bx = nullptr, *By = nullptr, *Bz = nullptr, *p = nullptr, *rho = nullptr;
+    mhs_opts opts{};
+    int steps = 0; // programs launched in the current phase
+    int ticks = 0; // ticks in the current phase
+    mhs_info info[2]{};
+    std::chrono::steady_clock::time_point t0;
+};
+
+// One launch of one request's program with its merge key.
+struct Rec {
+    int64_t key;
+    int slot;
+    Launch L;
+};
+
+// Keys order the launches of a tick.  A request's program is a prologue
+// followed by one or more V-cycles (segments).  Within a cycle, launches
+// before the bottom solve are numbered from the top and launches after it
+// from the end, so equal stages of requests whose hierarchies differ in
+// depth share a key.  Keys increase along every request's program, so
+// sorting by key keeps each request's own order.
+constexpr int kPartShift = 16;
+constexpr int kMaxPos = (1 << kPartShift) - 1;
+enum Part : int { kPrologue = 0, kDescent = 1, kBottomPart = 2, kAscent = 3, kEpilogue = 4 };
+
+int64_t key_of(int seg, int part, int pos) { return ((int64_t)seg * 8 + part) << kPartShift | pos; }
+
+void tag_cycle(const Program &pg, int seg, int slot, std::vector<Rec> &out)
+{
+    const size_t n = pg.launches.size();
+    size_t ib = n;
+    for (size_t i = 0; i < n; ++i)
+        if (pg.launches[i].kind == Launch::kBottom) {
+            ib = i;
+            break;
+        }
+    int asc = 0;
+    for (size_t i = ib + 1; i < n; ++i)
+        if (pg.launches[i].kind != Launch::kCopy) ++asc;
+    int j = 0, c = 0;
+    for (size_t i = 0; i < n; ++i) {
+        const Launch &L = pg.launches[i];
+        int64_t k;
+        if (i < ib)
+            k = key_of(seg, kDescent, (int)i);
+        else if (i == ib)
+            k = key_of(seg, kBottomPart, 0);
+        else if (L.kind == Launch::kCopy)
+            k = key_of(seg, kEpilogue, c++);
+        else
+            k = key_of(seg, kAscent, kMaxPos - (asc - 1 - j++));
+        out.push_back({k, slot, L});
+    }
+}
+
+void tag_one(const Launch &L, int64_t key, int slot, std::vector<Rec> &out) { out.push_back({key, slot, L}); }
+
+} // namespace
+
+struct mhs_batch {
+    int max_slots = 0;
+    int device = 0;
+    SolveState *d_states = nullptr; // per slot, in the workspace
+    SolveState *h_init = nullptr;   // pinned
+    SolveState *h_read = nullptr;   // pinned
+    Staging stage;                  // merged descriptor tables (pinned host + workspace)
+    std::vector<char> rec_buf;      // host recorder of per-request items (one tick)
+    Staging rec;
+    std::vector<Slot> slots;
+    std::vector<Rec> recs;
+};
+
+namespace {
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t states_bytes(int max_slots) { return align_up((size_t)max_slots * sizeof(SolveState), kWsAlign); }
+size_t stage_bytes(int max_slots) { return (size_t)max_slots * kSlotStageBytes; }
+
+// A recorder is a Staging whose "device" side is its own host buffer: the
+// builders put items there and Launch::items points at them.
+void reset_recorder(mhs_batch *b)
+{
+    b->rec.host = b->rec_buf.data();
+    b->rec.dev = b->rec_buf.data();
+    b->rec.cap = b->rec_buf.size();
+    b->rec.used = 0;
+}
+
+// Append the launches of slot `i` for its current phase to `out`.
+bool build_slot(const Slot &S, int i, SolveState *state, Staging &R, std::vector<Rec> &out)
+{
+    mhs_plan *p = S.plan;
+    const mhs_opts &o = S.opts;
+    if (S.phase == kBoundary) {
+        Hierarchy &h = p->h2;
+        if (S.fresh) {
+            PrepItem pi{};
+            pi.P = S.P;
+            pi.twin = (double *)h.lv[0].t[kF64];
+            pi.bz0 = S.bz0;
+            pi.f2 = (double *)h.lv[0].f[kF64];
+            pi.nx = p->grid.nx;
+            pi.ny = p->grid.ny;
+            pi.nz = 1;
+            pi.warm = o.warm_start;
+            pi.n = (int64_t)p->grid.nx * p->grid.ny;
+            const PrepItem *d = R.put(pi);
+            if (!d) return false;
+            Launch L{};
+            L.kind = Launch::kPrep2;
+            L.items = d;
+            L.n = pi.n;
+            tag_one(L, key_of(0, kPrologue, 0), i, out);
+        }
+        Program pg;
+        void *res = add_cycle(pg, R, h, kF64, S.P, h.lv[0].t[kF64], h.lv[0].f[kF64], false, true, o.nu1, o.nu2,
+                              state);
+        if (res != (void *)S.P) {
+            Launch c{};
+            c.kind = Launch::kCopy;
+            c.src = (const double *)res;
+            c.dst = S.P;
+            c.n = (int64_t)p->grid.nx * p->grid.ny;
+            c.gate = state;
+            pg.launches.push_back(c);
+        }
+        if (!pg.ok) return false;
+        tag_cycle(pg, 0, i, out);
+        return true;
+    }
+    if (S.phase == kInterior) {
+        Hierarchy &h = p->h3;
+        const Level &l0 = h.lv[0];
+        double *T0 = (double *)l0.t[kF64];
+        const int64_t N = (int64_t)l0.N;
+        if (S.fresh) {
+            PrepItem pi{};
+            pi.P = S.P;
+            pi.twin = T0;
+            pi.nx = p->grid.nx;
+            pi.ny = p->grid.ny;
+            pi.nz = p->grid.nz;
+            pi.warm = o.warm_start;
+            pi.n = N;
+            const PrepItem *d = R.put(pi);
+            if (!d) return false;
+            Launch L{};
+            L.kind = Launch::kPrep3;
+            L.items = d;
+            L.n = N;
+            tag_one(L, key_of(0, kPrologue, 0), i, out);
+        }
+        if (o.precision == MHS_PREC_FP64) {
+            Program pg;
+            void *res = add_cycle(pg, R, h, kF64, S.P, T0, nullptr, false, true, o.nu1, o.nu2, state);
+            if (res != (void *)S.P) {
+                Launch c{};
+                c.kind = Launch::kCopy;
+                c.src = (const double *)res;
+                c.dst = S.P;
+                c.n = N;
+                c.gate = state;
+                pg.launches.push_back(c);
+            }
+            if (!pg.ok) return false;
+            tag_cycle(pg, 0, i, out);
+            return true;
+        }
+        // refinement step S.steps: step 0 checks P; odd steps write P + e
+        // into T0, even steps T0 + e into P (the single-request ping-pong)
+        float *r32 = (float *)l0.f[kF32];
+        std::vector<Program> inner((size_t)o.inner_cycles);
+        void *ebuf = nullptr;
+        for (int c = 0; c < o.inner_cycles; ++c) {
+            void *a = c == 0 ? l0.u[kF32] : ebuf;
+            void *bb = (a == l0.u[kF32]) ? l0.t[kF32] : l0.u[kF32];
+            ebuf = add_cycle(inner[(size_t)c], R, h, kF32, a, bb, r32, c == 0, false, o.nu1, o.nu2, state);
+        }
+        const int s = S.steps;
+        const double *uin = (s == 0 || (s & 1)) ? S.P : T0;
+        double *uout = s == 0 ? nullptr : ((s & 1) ? T0 : S.P);
+        Program ir;
+        add_ir_step(ir, R, h, uin, uout, s == 0 ? nullptr : ebuf, r32, state);
+        if (!ir.ok || ir.launches.size() != 2) return false;
+        tag_one(ir.launches[0], key_of(0, kPrologue, 1), i, out);
+        tag_one(ir.launches[1], key_of(0, kPrologue, 2), i, out);
+        for (int c = 0; c < o.inner_cycles; ++c) {
+            if (!inner[(size_t)c].ok) return false;
+            tag_cycle(inner[(size_t)c], c, i, out);
+        }
+        return true;
+    }
+    if (S.phase == kFinish) {
+        const int64_t N = (int64_t)p->h3.lv[0].N;
+        if (o.precision == MHS_PREC_MIXED && (S.info[1].cycles & 1)) {
+            Launch c{};
+            c.kind = Launch::kCopy;
+            c.src = (const double *)p->h3.lv[0].t[kF64];
+            c.dst = S.P;
+            c.n = N;
+            tag_one(c, key_of(0, kPrologue, 0), i, out);
+        }
+        mhs_model m{};
+        m.alpha = S.alpha;
+        m.mu0 = S.mu0;
+        m.g = S.g;
+        const FieldsItem fi = fields_item(p, &m, p->d_fields_tab, S.P, S.Bx, S.By, S.Bz, S.p, S.rho);
+        const FieldsItem *d = R.put(fi);
+        if (!d) return false;
+        Launch L{};
+        L.kind = Launch::kFields;
+        L.items = d;
+        L.ntiles = fi.ntx * fi.nty * fi.ntz;
+        tag_one(L, key_of(0, kDescent, 0), i, out);
+        return true;
+    }
+    return true;
+}
+
+size_t item_size(Launch::Kind k)
+{
+    switch (k) {
+    case Launch::kSweep3:
+    case Launch::kSweep2:
+    case Launch::kRestrict3:
+    case Launch::kRestrict2:
+    case Launch::kIr3:
+        return sizeof(LevelItem);
+    case Launch::kBottom:
+        return sizeof(BottomItem);
+    case Launch::kFinalize:
+        return sizeof(FinalizeItem);
+    case Launch::kFields:
+        return sizeof(FieldsItem);
+    case Launch::kPrep3:
+    case Launch::kPrep2:
+        return sizeof(PrepItem);
+    case Launch::kCopy:
+        return 0;
+    }
+    return 0;
+}
+
+bool same_variant(const Launch &a, const Launch &b)
+{
+    return a.kind == b.kind && a.flags == b.flags && a.dbl == b.dbl;
+}
+
+// Fuse recs[lo, hi) (one key, one variant, distinct slots) into one launch
+// whose descriptor table is written into the batch staging area.
+bool merge(mhs_batch *b, const std::vector<const Rec *> &grp, Launch *out)
+{
+    const Launch &first = grp[0]->L;
+    const size_t sz = item_size(first.kind);
+    Staging &st = b->stage;
+    st.used = align_up(st.used, kItemAlign);
+    if (st.used + sz * grp.size() > st.cap) return false;
+    char *host = st.host + st.used;
+    Launch M = first;
+    M.items = st.dev + st.used;
+    M.nitems = (int)grp.size();
+    M.ntiles = 0;
+    M.lds = 0;
+    M.n = 0;
+    for (size_t q = 0; q < grp.size(); ++q) {
+        const Launch &L = grp[q]->L;
+        char *dst = host + q * sz;
+        std::memcpy(dst, L.items, sz);
+        switch (L.kind) {
+        case Launch::kSweep3:
+        case Launch::kSweep2:
+        case Launch::kRestrict3:
+        case Launch::kRestrict2:
+        case Launch::kIr3:
+            reinterpret_cast<LevelItem *>(dst)->tile_base = M.ntiles;
+            M.ntiles += L.ntiles;
+            break;
+        case Launch::kFields:
+            reinterpret_cast<FieldsItem *>(dst)->tile_base = M.ntiles;
+            M.ntiles += L.ntiles;
+            break;
+        case Launch::kPrep3:
+        case Launch::kPrep2:
+            reinterpret_cast<PrepItem *>(dst)->base = M.n;
+            M.n += L.n;
+            break;
+        case Launch::kBottom:
+            M.lds = std::max(M.lds, L.lds);
+            break;
+        default:
+            break;
+        }
+    }
+    st.used += sz * grp.size();
+    *out = M;
+    return true;
+}
+
+bool active(Phase ph) { return ph == kBoundary || ph == kInterior || ph == kFinish; }
+
+int check_slot(const mhs_batch *b, int32_t slot)
+{
+    if (!b) return fail(MHS_ERR_INVALID_ARG, "batch is NULL");
+    if (slot < 0 || slot >= b->max_slots) return fail(MHS_ERR_INVALID_ARG, "slot %d out of range", slot);
+    return MHS_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+int mhs_batch_workspace_bytes(int32_t max_slots, size_t *bytes)
+{
+    if (!bytes) return fail(MHS_ERR_INVALID_ARG, "bytes is NULL");
+    if (max_slots < 1 || max_slots > kMaxBatchSlots)
+        return fail(MHS_ERR_INVALID_ARG, "max_slots must be in 1..%d", kMaxBatchSlots);
+    *bytes = states_bytes(max_slots) + stage_bytes(max_slots);
+    return MHS_OK;
+}
+
+int mhs_batch_create(int32_t max_slots, void *d_ws, size_t ws_bytes, mhs_batch **out)
+{
+    if (!out) return fail(MHS_ERR_INVALID_ARG, "batch output is NULL");
+    *out = nullptr;
+    size_t need = 0;
+    int st = mhs_batch_workspace_bytes(max_slots, &need);
+    if (st) return st;
+    if (!d_ws || ((uintptr_t)d_ws % kWsAlign) != 0)
+        return fail(MHS_ERR_WORKSPACE, "workspace must be a 256-byte aligned device pointer");
+    if (ws_bytes < need) return fail(MHS_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    mhs_batch *b = new mhs_batch();
+    b->max_slots = max_slots;
+    b->slots.resize((size_t)max_slots);
+    if (hipGetDevice(&b->device) != hipSuccess) {
+        delete b;
+        return fail(MHS_ERR_HIP, "hipGetDevice failed");
+    }
+    b->d_states = (SolveState *)d_ws;
+    b->stage.dev = (char *)d_ws + states_bytes(max_slots);
+    b->stage.cap = stage_bytes(max_slots);
+    b->rec_buf.resize(stage_bytes(max_slots));
+    if (hipHostMalloc((void **)&b->stage.host, b->stage.cap, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&b->h_init, (size_t)max_slots * sizeof(SolveState), hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostMalloc((void **)&b->h_read, (size_t)max_slots * sizeof(SolveState), hipHostMallocDefault) !=
+            hipSuccess) {
+        mhs_batch_destroy(b);
+        return fail(MHS_ERR_HIP, "pinned host allocation failed");
+    }
+    *out = b;
+    return MHS_OK;
+}
+
+int mhs_batch_destroy(mhs_batch *b)
+{
+    if (!b) return MHS_OK;
+    if (b->stage.host) (void)hipHostFree(b->stage.host);
+    if (b->h_init) (void)hipHostFree(b->h_init);
+    if (b->h_read) (void)hipHostFree(b->h_read);
+    delete b;
+    return MHS_OK;
+}
+
+int mhs_batch_admit(mhs_batch *b, mhs_plan *plan, const mhs_model *model, const double *d_bz0, double *d_P,
+                    double *d_Bx, double *d_By, double *d_Bz, double *d_p, double *d_rho, const mhs_opts *o,
+                    int32_t *slot)
+{
+    if (!b || !plan || !d_bz0 || !d_P || !d_Bx || !d_By || !d_Bz || !d_p || !d_rho || !slot)
+        return fail(MHS_ERR_INVALID_ARG, "NULL argument");
+    int st = validate_opts(o);
+    if (st) return st;
+    if ((st = validate_model(plan, model, true))) return st;
+    if (!(plan->precisions & o->precision))
+        return fail(MHS_ERR_UNSUPPORTED, "plan was not created for precision %d", o->precision);
+    if (plan->device != b->device) return fail(MHS_ERR_INVALID_ARG, "plan and batch are on different devices");
+    int free_slot = -1;
+    for (int i = 0; i < b->max_slots; ++i) {
+        const Slot &S = b->slots[(size_t)i];
+        if (S.phase != kFree && S.plan == plan)
+            return fail(MHS_ERR_INVALID_ARG, "plan is already held by slot %d", i);
+        if (S.phase == kFree && free_slot < 0) free_slot = i;
+    }
+    if (free_slot < 0) return fail(MHS_ERR_BUDGET, "no free slot (max_slots %d)", b->max_slots);
+    if ((st = set_device(plan))) return st;
+
+    Slot S{};
+    S.plan = plan;
+    S.alpha = model->alpha;
+    S.mu0 = model->mu0;
+    S.g = model->g;
+    S.bz0 = d_bz0;
+    S.P = d_P;
+    S.Bx = d_Bx;
+    S.By = d_By;
+    S.Bz = d_Bz;
+    S.p = d_p;
+    S.rho = d_rho;
+    S.opts = *o;
+    // every phase's per-tick descriptors must fit the slot's share (with
+    // room for the alignment of each merged table)
+    for (Phase ph : {kBoundary, kInterior, kFinish}) {
+        for (int steps : {0, 1}) {
+            S.phase = ph;
+            S.fresh = true;
+            S.steps = steps;
+            reset_recorder(b);
+            std::vector<Rec> tmp;
+            const bool ok = build_slot(S, free_slot, b->d_states + free_slot, b->rec, tmp);
+            if (!ok || b->rec.used + kItemAlign * tmp.size() > kSlotStageBytes)
+                return fail(MHS_ERR_BUDGET, "the request's per-tick launch descriptors exceed %zu bytes",
+                            kSlotStageBytes);
+        }
+    }
+    // coefficient tables, coarsest inverse and the field tables
+    hipStream_t s0 = nullptr;
+    if ((st = upload_model(plan, model, s0))) return st;
+    const int nz = plan->grid.nz;
+    std::vector<double> tab(4 * (size_t)nz);
+    std::copy(model->xi, model->xi + nz, tab.begin());
+    std::copy(model->dxi, model->dxi + nz, tab.begin() + nz);
+    std::copy(model->pb, model->pb + nz, tab.begin() + 2 * nz);
+    std::copy(model->rhob, model->rhob + nz, tab.begin() + 3 * nz);
+    HIPCHK(hipMemcpy(plan->d_fields_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
+
+    S.phase = kBoundary;
+    S.fresh = true;
+    S.steps = 0;
+    S.ticks = 0;
+    S.t0 = std::chrono::steady_clock::now();
+    b->slots[(size_t)free_slot] = S;
+    *slot = free_slot;
+    return MHS_OK;
+}
+
+int mhs_batch_step(mhs_batch *b, void *stream, int32_t *n_active)
+{
+    if (!b) return fail(MHS_ERR_INVALID_ARG, "batch is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    int cur = -1;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != b->device) HIPCHK(hipSetDevice(b->device));
+
+    // 1. record every active request's program for this tick
+    reset_recorder(b);
+    b->recs.clear();
+    int top = 0; // one past the highest active slot
+    for (int i = 0; i < b->max_slots; ++i) {
+        Slot &S = b->slots[(size_t)i];
+        if (!active(S.phase)) continue;
+        top = i + 1;
+        if (S.fresh && S.phase != kFinish) b->h_init[i] = initial_state(S.opts.rtol, S.opts.max_cycles);
+        if (!build_slot(S, i, b->d_states + i, b->rec, b->recs))
+            return fail(MHS_ERR_WORKSPACE, "descriptor recorder exhausted");
+    }
+    if (n_active) *n_active = 0;
+    if (top == 0) return MHS_OK;
+
+    // 2. merge equal (key, variant) launches across requests
+    std::stable_sort(b->recs.begin(), b->recs.end(), [](const Rec &x, const Rec &y) { return x.key < y.key; });
+    std::vector<Launch> plan_launches;
+    b->stage.used = 0;
+    std::vector<const Rec *> grp;
+    for (size_t lo = 0; lo < b->recs.size();) {
+        size_t hi = lo;
+        while (hi < b->recs.size() && b->recs[hi].key == b->recs[lo].key) ++hi;
+        std::vector<bool> taken(hi - lo, false);
+        for (size_t a = lo; a < hi; ++a) {
+            if (taken[a - lo]) continue;
+            const Launch &La = b->recs[a].L;
+            if (La.kind == Launch::kCopy) {
+                plan_launches.push_back(La);
+                taken[a - lo] = true;
+                continue;
+            }
+            grp.clear();
+            for (size_t c = a; c < hi; ++c)
+                if (!taken[c - lo] && same_variant(b->recs[c].L, La)) {
+                    grp.push_back(&b->recs[c]);
+                    taken[c - lo] = true;
+                }
+            Launch M{};
+            if (!merge(b, grp, &M)) return fail(MHS_ERR_WORKSPACE, "batch descriptor table exhausted");
+            plan_launches.push_back(M);
+        }
+        lo = hi;
+    }
+
+    // 3. descriptors and fresh status words to the device, then the launches
+    if (b->stage.used) HIPCHK(hipMemcpyAsync(b->stage.dev, b->stage.host, b->stage.used, hipMemcpyHostToDevice, s));
+    for (int i = 0; i < top; ++i) {
+        const Slot &S = b->slots[(size_t)i];
+        if (active(S.phase) && S.fresh && S.phase != kFinish)
+            HIPCHK(hipMemcpyAsync(b->d_states + i, b->h_init + i, sizeof(SolveState), hipMemcpyHostToDevice, s));
+    }
+    for (const Launch &L : plan_launches) {
+        const hipError_t e = exec_launch(L, s);
+        if (e != hipSuccess) return fail(MHS_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+    }
+    HIPCHK(hipMemcpyAsync(b->h_read, b->d_states, (size_t)top * sizeof(SolveState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+
+    // 4. phase transitions
+    int running = 0;
+    for (int i = 0; i < top; ++i) {
+        Slot &S = b->slots[(size_t)i];
+        if (!active(S.phase)) continue;
+        S.fresh = false;
+        S.steps += 1;
+        S.ticks += 1;
+        if (S.phase == kFinish) {
+            S.phase = kDone;
+            continue;
+        }
+        const SolveState &ss = b->h_read[i];
+        if (ss.done != kRunning) {
+            const int q = S.phase == kBoundary ? 0 : 1;
+            mhs_info &inf = S.info[q];
+            inf.status = status_of(ss.done);
+            inf.cycles = std::max(0, ss.checks - 1);
+            inf.inner_cycles = (q == 1 && S.opts.precision == MHS_PREC_MIXED) ? inf.cycles * S.opts.inner_cycles : 0;
+            inf.host_syncs = S.ticks;
+            inf.r0 = ss.r0;
+            inf.rel_residual = ss.r0 > 0 ? ss.rnorm / ss.r0 : 0.0;
+            inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - S.t0).count();
+            if (inf.status != MHS_OK) {
+                S.phase = kDone;
+                continue;
+            }
+            S.phase = q == 0 ? kInterior : kFinish;
+            S.fresh = true;
+            S.steps = 0;
+            S.ticks = 0;
+        }
+        ++running;
+    }
+    if (n_active) *n_active = running;
+    return MHS_OK;
+}
+
+int mhs_batch_poll(mhs_batch *b, int32_t slot, int32_t *done, mhs_info *boundary, mhs_info *interior)
+{
+    int st = check_slot(b, slot);
+    if (st) return st;
+    const Slot &S = b->slots[(size_t)slot];
+    if (S.phase == kFree) return fail(MHS_ERR_INVALID_ARG, "slot %d is free", slot);
+    if (done) *done = S.phase == kDone ? 1 : 0;
+    if (boundary) *boundary = S.info[0];
+    if (interior) *interior = S.info[1];
+    return MHS_OK;
+}
+
+int mhs_batch_release(mhs_batch *b, int32_t slot)
+{
+    int st = check_slot(b, slot);
+    if (st) return st;
+    b->slots[(size_t)slot] = Slot{};
+    return MHS_OK;
+}
+
+} // extern "C"

@@ -45,7 +45,7 @@ struct Hierarchy {
 
 // One kernel launch of a program (the device item table is in the workspace).
 struct Launch {
-    enum Kind { kSweep3, kSweep2, kRestrict3, kRestrict2, kIr3, kBottom, kFinalize, kCopy } kind;
+    enum Kind { kSweep3, kSweep2, kRestrict3, kRestrict2, kIr3, kBottom, kFinalize, kCopy, kFields, kPrep3, kPrep2 } kind;
     int flags = 0;
     bool dbl = true;
     const void *items = nullptr; // device pointer
@@ -55,8 +55,11 @@ struct Launch {
     // copy
     const double *src = nullptr;
     double *dst = nullptr;
-    int64_t n = 0;
+    int64_t n = 0; // copy: elements; prep: threads
     const SolveState *gate = nullptr; // copy: skipped once this solve is done
+    int prof = -1;                    // measurement class (MHS_PROF_*), -1 = none
+    double bytes = 0.0;               // compulsory HBM bytes of the launch
+    bool pre = false;                 // runs before the cycle's convergence check
 };
 
 // Host staging of item tables: items are appended in host memory and copied
@@ -78,11 +81,66 @@ struct Staging {
     }
 };
 
+// Event-bracketed launches awaiting collection.
+struct ProfRecord {
+    int klass;
+    int cycle; // index of the cycle/step the launch belongs to (-1: always counted)
+    bool pre;  // launched before that cycle's convergence check
+    double bytes;
+    hipEvent_t start, end;
+};
+
+struct Profiler {
+    int mask = 0; // bit k set: launches of class k are timed
+    std::vector<hipEvent_t> pool;
+    size_t next = 0;
+    std::vector<ProfRecord> pending;
+    double ms[MHS_PROF_NCLASS] = {};
+    double bytes[MHS_PROF_NCLASS] = {};
+    long long launches[MHS_PROF_NCLASS] = {};
+};
+
+struct Program {
+    std::vector<Launch> launches;
+    bool ok = true;
+};
+
 struct ModelCache {
     bool valid = false;
     double alpha = 0.0;
     std::vector<double> xi;
 };
+
+} // namespace mhs
+
+struct mhs_plan;
+
+namespace mhs {
+
+// ---- shared host helpers (api.cpp) ------------------------------------------
+int fail(int code, const char *fmt, ...);
+#define HIPCHK(expr)                                                                                  \
+    do {                                                                                              \
+        hipError_t e_ = (expr);                                                                       \
+        if (e_ != hipSuccess) return ::mhs::fail(MHS_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+int validate_model(const mhs_plan *p, const mhs_model *m, bool need_fields);
+int validate_opts(const mhs_opts *o);
+int upload_model(mhs_plan *p, const mhs_model *model, hipStream_t s);
+int set_device(const mhs_plan *p);
+SolveState initial_state(double rtol, int max_iter);
+int status_of(int32_t done);
+
+// Program builders: append launches whose item tables are put into `st`.
+void add_finalize(Program &pg, Staging &st, const double *partials, int n, SolveState *state);
+void *add_cycle(Program &pg, Staging &st, const Hierarchy &h, int path, void *a0, void *b0, const void *f0,
+                bool first_zero, bool first_norm, int nu1, int nu2, SolveState *state);
+void add_ir_step(Program &pg, Staging &st, const Hierarchy &h, const double *uin, double *uout, const void *e,
+                 float *r32, SolveState *state);
+FieldsItem fields_item(const mhs_plan *p, const mhs_model *model, const double *tab, const double *P, double *Bx,
+                       double *By, double *Bz, double *pr, double *rho);
+hipError_t exec_launch(const Launch &L, hipStream_t s);
 
 } // namespace mhs
 
@@ -101,4 +159,5 @@ struct mhs_plan {
     mhs::ModelCache cache;
     double *d_scratch_norm = nullptr;    // stage residual-norm partials
     int scratch_npart = 0;
+    mhs::Profiler prof;
 };

@@ -175,6 +175,28 @@ class Plan:
                                         _stream(self.device)))
         return out
 
+    # ---- measurement -----------------------------------------------------------
+    def profile(self, enable=True, classes=None):
+        """Time launches of the given classes (names from PROF_NAMES; all by
+        default) with HIP events; enable=False turns profiling off."""
+        mask = 0
+        if enable:
+            names = _lib.PROF_NAMES if classes is None else classes
+            for n in names:
+                mask |= 1 << _lib.PROF_NAMES.index(n)
+        check(_lib.lib().mhs_profile_enable(self.h, mask))
+
+    def profile_read(self, reset=False):
+        """{class: (total_ms, launches, compulsory_bytes)} since the last reset."""
+        out = {}
+        for k, name in enumerate(_lib.PROF_NAMES):
+            ms, n, b = C.c_double(), C.c_int64(), C.c_double()
+            check(_lib.lib().mhs_profile_read(self.h, k, C.byref(ms), C.byref(n), C.byref(b), 0))
+            out[name] = (ms.value, n.value, b.value)
+        if reset:
+            check(_lib.lib().mhs_profile_read(self.h, 0, None, None, None, 1))
+        return out
+
     # ---- stage entry points (kernel-level checks) ----------------------------
     def stage_smooth(self, model, space, level, u, f=None, nsweeps=1, precision=PREC_FP64):
         m = _ModelArgs.of(model)

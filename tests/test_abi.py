@@ -1,0 +1,93 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry
+point include/mhs.h declares, and validates grids and options on the host
+before any device work."""
+
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1307_6720_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mhs.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mhs_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_path():
+    names = declared_functions()
+    for required in ("mhs_solve_boundary", "mhs_solve_interior", "mhs_fields", "mhs_workspace_bytes",
+                     "mhs_plan_create", "mhs_batch_step"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = C.CDLL(_lib.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_version_and_defaults():
+    L = _lib.lib()
+    assert L.mhs_version() >= 10000
+    o = _lib.Opts()
+    L.mhs_default_opts(C.byref(o))
+    assert (o.precision, o.max_cycles, o.nu1, o.nu2, o.inner_cycles) == (_lib.PREC_FP64, 100, 2, 2, 1)
+    assert o.rtol == 1e-10
+
+
+def ws_bytes(nx, ny, nz, prec=3, lengths=(1.0, 1.0, 1.0)):
+    g = _lib.Grid(nx, ny, nz, *lengths)
+    n = C.c_size_t(0)
+    code = _lib.lib().mhs_workspace_bytes(C.byref(g), prec, C.byref(n))
+    return code, n.value
+
+
+@pytest.mark.parametrize("dims", [(33, 33, 33), (257, 257, 257), (513, 513, 257), (129, 129, 65), (65, 17, 9)])
+def test_workspace_sizes(dims):
+    code, n = ws_bytes(*dims)
+    assert code == _lib.MHS_OK
+    N = dims[0] * dims[1] * dims[2]
+    # at least the FP64 twin + FP32 correction, residual and twin on the finest grid
+    assert n >= N * (8 + 3 * 4)
+    # and not much more than two of those
+    assert n < 2.2 * N * (8 + 3 * 4) + (8 << 20)
+    c64, n64 = ws_bytes(*dims, prec=1)
+    assert c64 == _lib.MHS_OK and n64 < n
+
+
+@pytest.mark.parametrize("dims,code", [((32, 33, 33), _lib.ERR_GRID), ((33, 33, 3), _lib.ERR_GRID),
+                                       ((33, 34, 33), _lib.ERR_GRID), ((4097, 5, 5), _lib.ERR_GRID)])
+def test_bad_grids_rejected(dims, code):
+    got, _ = ws_bytes(*dims)
+    assert got == code
+    assert _lib.lib().mhs_last_error()
+
+
+def test_bad_lengths_and_precisions_rejected():
+    assert ws_bytes(33, 33, 33, lengths=(1.0, -1.0, 1.0))[0] == _lib.ERR_INVALID_ARG
+    assert ws_bytes(33, 33, 33, prec=0)[0] == _lib.ERR_INVALID_ARG
+    assert ws_bytes(33, 33, 33, prec=4)[0] == _lib.ERR_INVALID_ARG
+
+
+def test_null_arguments_rejected():
+    L = _lib.lib()
+    assert L.mhs_workspace_bytes(None, 1, None) == _lib.ERR_INVALID_ARG
+    assert L.mhs_solve_boundary(None, None, None, None, None, None) == _lib.ERR_INVALID_ARG
+    assert L.mhs_plan_destroy(None) == _lib.MHS_OK
+
+
+def test_plan_create_rejects_small_or_misaligned_workspace():
+    L = _lib.lib()
+    g = _lib.Grid(33, 33, 33, 1.0, 1.0, 1.0)
+    h = C.c_void_p()
+    # workspace validation happens before any device call
+    assert L.mhs_plan_create(C.byref(g), 3, C.c_void_p(256), 1024, C.byref(h)) == _lib.ERR_WORKSPACE
+    _, n = ws_bytes(33, 33, 33)
+    assert L.mhs_plan_create(C.byref(g), 3, C.c_void_p(4096 + 8), n, C.byref(h)) == _lib.ERR_WORKSPACE

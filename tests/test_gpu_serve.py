@@ -1,0 +1,179 @@
+"""Serving on the GPU: every request gives the same result alone (the
+single-request entry points) and in the mix (merged batch launches), bit
+for bit, whatever else is in the batch; failures stay with their request;
+results also match the exact discrete solution (oracle) to the stated
+tolerance."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import exact, fields
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1307_6720_amd import PREC_FP64, PREC_MIXED, _lib  # noqa: E402
+from paper_1307_6720_amd.serve import Batch, DeviceBackend, Request, Server  # noqa: E402
+from paper_1307_6720_amd.solver import Plan, make_opts, solve  # noqa: E402
+
+DEV = "cuda:0"
+
+# (dims (nx, ny, nz), lengths, alpha, a, precision, rtol)
+CASES = [
+    ((33, 33, 33), (1.0, 1.0, 1.0), 0.0, 0.0, PREC_FP64, 1e-12),
+    ((65, 65, 65), (1.0, 1.0, 1.0), 0.5, 0.5, PREC_MIXED, 1e-10),
+    ((65, 33, 17), (1.0, 0.6, 0.4), 0.3, 0.2, PREC_FP64, 1e-10),
+    ((129, 129, 65), (1.0, 1.0, 0.5), 1.0, 0.5, PREC_MIXED, 1e-10),
+    ((33, 65, 129), (1.0, 1.3, 0.8), 0.7, 0.6, PREC_MIXED, 1e-10),
+    ((65, 65, 65), (1.0, 1.0, 1.0), 0.9, 0.3, PREC_FP64, 1e-10),
+    ((129, 129, 129), (1.0, 1.0, 1.0), 0.5, 0.5, PREC_MIXED, 1e-10),
+]
+
+
+def make_request(i, case, seed=500):
+    dims, lengths, alpha, a, prec, rtol = case
+    nx, ny, nz = dims
+    grid = synth.make_grid(nx, ny, nz, *lengths)
+    rng = np.random.default_rng(seed + i)
+    bz0 = synth.bipolar_magnetogram(nx, ny, grid.lx, grid.ly, 3 + i % 4, rng, sigma=None)
+    model = synth.make_model(grid, alpha, a, 0.2 * lengths[2])
+    return Request(id=i, dims=dims, model=model, bz0=bz0, precision=prec, rtol=rtol, lengths=lengths)
+
+
+def alone(req):
+    nx, ny, nz = req.dims
+    plan = Plan(synth.make_grid(nx, ny, nz, *req.lengths), PREC_FP64 | PREC_MIXED, device=DEV)
+    res = solve(plan, torch.from_numpy(req.bz0).to(DEV), req.model, precision=req.precision, rtol=req.rtol)
+    torch.cuda.synchronize()
+    out = [t.clone() for t in (res.P, res.Bx, res.By, res.Bz, res.p, res.rho)]
+    plan.close()
+    return out, res.info2d, res.info3d
+
+
+@pytest.fixture(scope="module")
+def alone_results():
+    reqs = [make_request(i, c) for i, c in enumerate(CASES)]
+    print("[serve] alone solves", flush=True)
+    return reqs, [alone(r) for r in reqs]
+
+
+def serve(reqs, max_slots, budget=64 << 30, gaps=None):
+    got = {}
+
+    def keep(req, res):
+        got[req.id] = [t.clone() for t in (res.P, *res.F)]
+
+    be = DeviceBackend(max_slots=max_slots, device=DEV)
+    srv = Server(be, budget, on_finish=keep)
+    for k, r in enumerate(reqs):
+        r.arrival = 0.0 if gaps is None else gaps * k
+        r.status = r.finished = r.admitted = None
+    done, stats = srv.run(reqs)
+    torch.cuda.synchronize()
+    be.close()
+    return {r.id: r for r in done}, got, stats
+
+
+@pytest.mark.parametrize("max_slots,gaps", [(8, None), (3, 2e-4), (1, None)])
+def test_same_result_alone_and_in_the_mix(alone_results, max_slots, gaps):
+    reqs, ref = alone_results
+    print(f"[serve] mix max_slots={max_slots} gaps={gaps}", flush=True)
+    done, got, stats = serve(reqs, max_slots, gaps=gaps)
+    assert stats["ok"] == len(reqs)
+    assert stats["peak_active"] <= max_slots
+    for r in reqs:
+        want, i2, i3 = ref[r.id]
+        d = done[r.id]
+        assert d.status == 0
+        assert d.info2d["cycles"] == i2["cycles"] and d.info3d["cycles"] == i3["cycles"], r.id
+        for name, a, b in zip(("P", "Bx", "By", "Bz", "p", "rho"), got[r.id], want):
+            assert torch.equal(a, b), (r.id, name, (a - b).abs().max().item())
+
+
+def test_failures_stay_with_their_request(alone_results):
+    reqs, ref = alone_results
+    keep = [make_request(i, c) for i, c in enumerate(CASES[:3])]
+    nan_req = make_request(10, CASES[1])
+    nan_req.bz0 = nan_req.bz0.copy()
+    nan_req.bz0[7, 9] = np.nan
+    bad = make_request(11, CASES[0])
+    xi = bad.model.xi.copy()
+    xi[4] = 1.0
+    bad.model = synth.Model(bad.model.alpha, xi, bad.model.dxi, bad.model.pb, bad.model.rhob)
+    capped = make_request(12, CASES[2])
+    capped.rtol = 0.0  # never converges: stops at max_cycles
+    print("[serve] failures", flush=True)
+    done, got, stats = serve(keep + [nan_req, bad, capped], max_slots=4)
+    assert done[10].status == _lib.ERR_DIVERGED
+    assert done[11].status == _lib.ERR_NOT_ELLIPTIC
+    assert done[12].status == _lib.ERR_NO_CONVERGENCE and done[12].info2d["cycles"] == 100
+    for r in keep:
+        want, _, _ = ref[r.id]
+        for a, b in zip(got[r.id], want):
+            assert torch.equal(a, b)
+
+
+def test_batch_result_matches_exact_solution(alone_results):
+    reqs, _ = alone_results
+    r = make_request(1, CASES[1])
+    done, got, _ = serve([r], max_slots=2)
+    m = r.model
+    nx, ny, nz = r.dims
+    lx, ly, lz = r.lengths
+    P_ex = exact.solve(r.bz0, nz, m.xi, m.alpha, lx, ly, lz)
+    want = fields.fields(P_ex, m.alpha, m.xi, m.dxi, m.pb, m.rhob, m.mu0, m.g, lx, ly, lz)
+    P, Bx, By, Bz, p, rho = [t.cpu().numpy() for t in got[1]]
+    pb, rb = m.pb[:, None, None], m.rhob[:, None, None]
+
+    def rel(a, b):
+        return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+    assert rel(P, P_ex) < 1e-8
+    for a, b in ((Bx, want[0]), (By, want[1]), (Bz, want[2]), (p - pb, want[3] - pb), (rho - rb, want[4] - rb)):
+        assert rel(a, b) < 1e-8
+
+
+def test_batch_abi_direct():
+    """mhs_batch_* without the server: slots, polling, release and reuse."""
+    reqs = [make_request(i, CASES[i]) for i in (0, 2)]
+    b = Batch(2, DEV)
+    plans, outs, slots = [], [], []
+    for r in reqs:
+        nx, ny, nz = r.dims
+        plan = Plan(synth.make_grid(nx, ny, nz, *r.lengths), PREC_FP64 | PREC_MIXED, device=DEV)
+        P = torch.zeros((nz, ny, nx), dtype=torch.float64, device=DEV)
+        F = tuple(torch.empty_like(P) for _ in range(5))
+        bz = torch.from_numpy(r.bz0).to(DEV)
+        slots.append(b.admit(plan, r.model, bz, P, F, make_opts(r.precision, r.rtol)))
+        plans.append(plan)
+        outs.append((bz, P, F))
+    # a third request does not fit two slots; a plan cannot be admitted twice
+    with pytest.raises(_lib.MHSError) as e:
+        b.admit(plans[0], reqs[0].model, outs[0][0], outs[0][1], outs[0][2], make_opts())
+    assert e.value.code in (_lib.ERR_BUDGET, _lib.ERR_INVALID_ARG)
+    ticks = 0
+    while True:
+        n = b.step()
+        ticks += 1
+        if n == 0:
+            break
+        assert ticks < 500
+    for s in slots:
+        done, i2, i3 = b.poll(s)
+        assert done and i2["status"] == 0 and i3["status"] == 0
+        assert ticks >= i2["cycles"] + i3["cycles"]
+    # release and reuse a slot with the other plan
+    b.release(slots[0])
+    r = reqs[0]
+    P2 = torch.zeros_like(outs[0][1])
+    F2 = tuple(torch.empty_like(P2) for _ in range(5))
+    s2 = b.admit(plans[0], r.model, outs[0][0], P2, F2, make_opts(r.precision, r.rtol))
+    while b.step():
+        pass
+    done, _, _ = b.poll(s2)
+    assert done
+    assert torch.equal(P2, outs[0][1])
+    b.close()
+    for p in plans:
+        p.close()
