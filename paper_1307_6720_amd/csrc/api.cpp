@@ -42,11 +42,12 @@ constexpr size_t kStagingBytes = 1 << 20;
 constexpr int kTargetGroups = 2048;
 
 // LDS bytes of a bottom solver starting at level l: u and f of every level
-// from l down, plus a residual array of level l.
+// from l down with their coefficient tables (4 nz each), plus a residual
+// array of level l.
 size_t bottom_lds(const Hierarchy &h, int l)
 {
     size_t n = 0;
-    for (int q = l; q < h.L; ++q) n += 2 * h.lv[q].N;
+    for (int q = l; q < h.L; ++q) n += 2 * h.lv[q].N + 4 * (size_t)h.lv[q].n[2];
     return 8 * (n + h.lv[l].N);
 }
 
@@ -514,6 +515,8 @@ BottomItem bottom_item(const Hierarchy &h, int path, const void *f_top, void *u_
         off += (int)h.lv[l].N;
         b.off_f[q] = off;
         off += (int)h.lv[l].N;
+        b.off_c[q] = off;
+        off += 4 * h.lv[l].n[2];
     }
     b.off_r = off;
     b.nlev = nl;

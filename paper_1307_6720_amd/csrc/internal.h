@@ -87,6 +87,7 @@ struct BottomItem {
     int32_t n[kMaxLevels][3];
     int32_t off_u[kMaxLevels];    // LDS offsets (doubles)
     int32_t off_f[kMaxLevels];
+    int32_t off_c[kMaxLevels];    // LDS copy of the level's coefficient table (4 * nz)
     int32_t off_r;
     int32_t nlev;
     int32_t m;                    // unknowns of the coarsest grid
@@ -96,7 +97,8 @@ struct BottomItem {
     SolveState *state;
 };
 
-// LDS bytes a bottom hierarchy needs (u and f per level, r for the top level).
+// Largest LDS footprint of a bottom hierarchy (u, f and coefficients per
+// level, r for the top level).
 constexpr int kBottomLdsMax = 160 * 1024;
 
 struct FinalizeItem {

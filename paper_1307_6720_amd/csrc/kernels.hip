@@ -184,9 +184,13 @@ __global__ __launch_bounds__(kThreads) void k_sweep3(const LevelItem *__restrict
     constexpr int D = (HAS_F || PROLONG) ? 3 : kDepth;
     constexpr int kCWPlanes = PROLONG ? 2 : 1;
     constexpr int kFSlots = HAS_F ? 4 : 1;
-    __shared__ T S[4][kWY][kWX];
-    __shared__ T F[kFSlots][kFY3][kFX];
-    __shared__ T CW[kCWPlanes][kCWY][kCWX];
+    constexpr int kCPlane = kCWX * kCWY;
+    __shared__ T S[4 * kWCells];
+    __shared__ T F[kFSlots * kFCells3];
+    __shared__ T CW[kCWPlanes * kCPlane];
+    // prolongation: the coarse correction interpolated in z and y onto every
+    // fine row of the window, at coarse columns (x interpolation at staging)
+    __shared__ T ZW[PROLONG ? kWY * kCWX : 1];
     __shared__ double red[kThreads / 64];
 
     const int tile = xcd_tile();
@@ -214,96 +218,194 @@ __global__ __launch_bounds__(kThreads) void k_sweep3(const LevelItem *__restrict
     const size_t csxy = (size_t)ncx * ncy;
     const int tid = threadIdx.x;
     const int I0 = (i0 - 2) >> 1, J0 = (j0 - 2) >> 1; // coarse window origin
+    constexpr uint32_t es = sizeof(T);
+
+    // ---- per-thread geometry, the same on every plane of the march --------
+    // Window cells this thread stages (slot-local LDS index, byte offset of
+    // the clamped in-plane source, inside-array and interior flags).
+    int st_l[kWPer];
+    uint32_t st_g[kWPer];
+    int st_z[kWPer];
+    uint32_t st_in = 0, st_int = 0, st_odd = 0;
+#pragma unroll
+    for (int r = 0; r < kWPer; ++r) {
+        const int e = tid + r * kThreads;
+        const int ee = min(e, kWCells - 1);
+        const int w = ee / kWX, c = ee - w * kWX;
+        const int i = i0 - 2 + c, j = j0 - 2 + w;
+        st_l[r] = e < kWCells ? w * kWX + sx(c) : -1;
+        st_g[r] = es * (uint32_t)(min(max(i, 0), nx - 1) + nx * min(max(j, 0), ny - 1));
+        st_z[r] = w * kCWX + ((i >> 1) - I0);
+        if (i >= 0 && i < nx && j >= 0 && j < ny) st_in |= 1u << r;
+        if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2) st_int |= 1u << r;
+        if (i & 1) st_odd |= 1u << r;
+    }
+    // right-hand-side window cells
+    int f_l[HAS_F ? kFPer3 : 1];
+    uint32_t f_g[HAS_F ? kFPer3 : 1];
+    if constexpr (HAS_F) {
+#pragma unroll
+        for (int r = 0; r < kFPer3; ++r) {
+            const int e = tid + r * kThreads;
+            const int ee = min(e, kFCells3 - 1);
+            const int w = ee / kFX, c = ee - w * kFX;
+            f_l[r] = e < kFCells3 ? w * kFX + sxf(c) : -1;
+            f_g[r] = es * (uint32_t)(min(i0 - 1 + c, nx - 1) + nx * min(j0 - 1 + w, ny - 1));
+        }
+    }
+    // coarse-window cells (two coarse planes) and the z-y interpolation rows
+    int cw_l[PROLONG ? kCPer : 1];
+    uint32_t cw_g[PROLONG ? kCPer : 1];
+    uint32_t cw_hi = 0;
+    int zw_src[PROLONG ? 2 : 1];
+    uint32_t zw_ok = 0, zw_odd = 0;
+    if constexpr (PROLONG) {
+#pragma unroll
+        for (int r = 0; r < kCPer; ++r) {
+            const int e = tid + r * kThreads;
+            const int ee = min(e, kCCells - 1);
+            const int pl = ee / kCPlane;
+            const int rem = ee - pl * kCPlane;
+            const int w = rem / kCWX, c = rem - w * kCWX;
+            const int I = min(max(I0 + c, 0), ncx - 1), J = min(max(J0 + w, 0), ncy - 1);
+            cw_l[r] = e < kCCells ? ee : -1;
+            cw_g[r] = es * (uint32_t)(I + ncx * J);
+            if (pl) cw_hi |= 1u << r;
+        }
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int e = tid + r * kThreads;
+            const int ee = min(e, kWY * kCWX - 1);
+            const int w = ee / kCWX, lc = ee - w * kCWX;
+            const int j = j0 - 2 + w;
+            zw_src[r] = ((j >> 1) - J0) * kCWX + lc;
+            if (e < kWY * kCWX) zw_ok |= 1u << r;
+            if (j & 1) zw_odd |= 1u << r;
+        }
+    }
+    // red nodes (tile plus a one-node ring) for each plane parity: centre
+    // index and the index of the west neighbour (east = west + 1 in the
+    // colour-split row); -1 where the node is not an interior node
+    int rd_c[2][2], rd_w[2][2], rd_f[2][2];
+#pragma unroll
+    for (int ps = 0; ps < 2; ++ps)
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int e = tid + r * kThreads;
+            const int ee = min(e, (kTY + 2) * kRedPerRow - 1);
+            const int w = 1 + ee / kRedPerRow;
+            const int q = ee - (w - 1) * kRedPerRow;
+            const int c = 1 + ((ps + w) & 1) + 2 * q;
+            const int i = i0 - 2 + c, j = j0 - 2 + w;
+            const bool ok = e < (kTY + 2) * kRedPerRow && i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2;
+            rd_c[ps][r] = ok ? w * kWX + sx(c) : -1;
+            rd_w[ps][r] = w * kWX + sx(c - 1);
+            rd_f[ps][r] = (w - 1) * kFX + sxf(c - 1);
+        }
+    // black nodes of the tile (one per thread) for each plane parity
+    int bk_c[2], bk_w[2], bk_f[2];
+#pragma unroll
+    for (int ps = 0; ps < 2; ++ps) {
+        const int w = 2 + tid / kBlackPerRow;
+        const int q = tid - (w - 2) * kBlackPerRow;
+        const int c = 2 + ((ps + w) & 1) + 2 * q;
+        const int i = i0 - 2 + c, j = j0 - 2 + w;
+        bk_c[ps] = (i <= nx - 2 && j <= ny - 2) ? w * kWX + sx(c) : -1;
+        bk_w[ps] = w * kWX + sx(c - 1);
+        bk_f[ps] = (w - 1) * kFX + sxf(c - 1);
+    }
+    static_assert(kTY * kBlackPerRow == kThreads, "one black node per thread");
+    // tile nodes this thread writes (and sums the residual of)
+    int ow_c[kOwn], ow_w[kOwn], ow_f[kOwn];
+    uint32_t ow_g[kOwn];
+    uint32_t ow_ok = 0;
+#pragma unroll
+    for (int q = 0; q < kOwn; ++q) {
+        const int e = tid + q * kThreads;
+        const int w = 2 + e / kTX, c = 2 + e % kTX;
+        const int i = i0 + c - 2, j = j0 + w - 2;
+        ow_c[q] = w * kWX + sx(c);
+        ow_w[q] = w * kWX + sx(c - 1);
+        ow_f[q] = (w - 1) * kFX + sxf(c - 1);
+        ow_g[q] = es * (uint32_t)(min(i, nx - 1) + nx * min(j, ny - 1));
+        if (i <= nx - 2 && j <= ny - 2) ow_ok |= 1u << q;
+    }
+    const int par0 = (i0 + j0 + 1) & 1; // red parity of plane s is (par0 + s) & 1
+
+    auto at = [](const MHS_GLOBAL T *base, uint32_t byte_off) -> T {
+        return *(const MHS_GLOBAL T *)((const MHS_GLOBAL char *)base + byte_off);
+    };
 
     T pre[D][kWPer];
-    T fpre[D][kFPer3];
-    T cpre[D][kCPer];
+    T fpre[D][HAS_F ? kFPer3 : 1];
+    T cpre[D][PROLONG ? kCPer : 1];
     // Loads are unconditional, from clamped in-bounds addresses, straight
     // into the ring registers; cells outside the array are zeroed when the
-    // plane is staged.  (A conditional load into a zero-initialised register
-    // forces the compiler to drain every outstanding load first.)
-    auto fetch = [&](int p, T(&dst)[kWPer], T(&fdst)[kFPer3], T(&cdst)[kCPer]) {
+    // plane is staged.
+    auto fetch = [&](int p, T(&dst)[kWPer], T(&fdst)[HAS_F ? kFPer3 : 1], T(&cdst)[PROLONG ? kCPer : 1]) {
         if constexpr (!ZERO_IN) {
+            const MHS_GLOBAL T *pl = uin + sxy * (size_t)p;
 #pragma unroll
-            for (int r = 0; r < kWPer; ++r) {
-                const int e = min(tid + r * kThreads, kWCells - 1);
-                const int w = e / kWX, c = e - w * kWX;
-                const int i = min(max(i0 - 2 + c, 0), nx - 1), j = min(max(j0 - 2 + w, 0), ny - 1);
-                dst[r] = uin[(size_t)i + (size_t)nx * j + sxy * p];
-            }
+            for (int r = 0; r < kWPer; ++r) dst[r] = at(pl, st_g[r]);
         }
         if constexpr (HAS_F) {
+            const MHS_GLOBAL T *pl = f + sxy * (size_t)p;
 #pragma unroll
-            for (int r = 0; r < kFPer3; ++r) {
-                const int e = min(tid + r * kThreads, kFCells3 - 1);
-                const int w = e / kFX, c = e - w * kFX;
-                const int i = min(i0 - 1 + c, nx - 1), j = min(j0 - 1 + w, ny - 1);
-                fdst[r] = f[(size_t)i + (size_t)nx * j + sxy * p];
-            }
+            for (int r = 0; r < kFPer3; ++r) fdst[r] = at(pl, f_g[r]);
         }
         if constexpr (PROLONG) {
-            const int K0 = p >> 1, K1 = (p + 1) >> 1;
+            const MHS_GLOBAL T *p0 = ec + csxy * (size_t)(p >> 1);
+            const MHS_GLOBAL T *p1 = ec + csxy * (size_t)((p + 1) >> 1);
 #pragma unroll
-            for (int r = 0; r < kCPer; ++r) {
-                const int e = min(tid + r * kThreads, kCCells - 1);
-                const int pl = e / (kCWX * kCWY);
-                const int rem = e - pl * (kCWX * kCWY);
-                const int w = rem / kCWX, c = rem - w * kCWX;
-                const int I = min(max(I0 + c, 0), ncx - 1), J = min(max(J0 + w, 0), ncy - 1);
-                cdst[r] = ec[(size_t)I + (size_t)ncx * J + csxy * (pl ? K1 : K0)];
-            }
+            for (int r = 0; r < kCPer; ++r) cdst[r] = at(((cw_hi >> r) & 1) ? p1 : p0, cw_g[r]);
         }
     };
-    // coarse correction at fine node (i, j, p) from the LDS coarse window:
-    // coincident nodes copy, midpoints average 2/4/8 values (trilinear)
-    auto corr = [&](int i, int j, int p) {
-        const int lc = (i >> 1) - I0, lw = (j >> 1) - J0;
-        const int oi = i & 1, oj = j & 1, ok = p & 1;
-        const T h = (T)0.5;
-        auto X = [&](int pl, int w) { return oi ? h * (CW[pl][w][lc] + CW[pl][w][lc + 1]) : CW[pl][w][lc]; };
-        auto Y = [&](int pl) { return oj ? h * (X(pl, lw) + X(pl, lw + 1)) : X(pl, lw); };
-        return ok ? h * (Y(0) + Y(1)) : Y(0);
-    };
-    auto stash = [&](int p, const T(&src)[kWPer], const T(&fsrc)[kFPer3], const T(&csrc)[kCPer], bool sync_first) {
+    auto stash = [&](int p, const T(&src)[kWPer], const T(&fsrc)[HAS_F ? kFPer3 : 1],
+                     const T(&csrc)[PROLONG ? kCPer : 1], bool sync_first) {
+        const bool corr = PROLONG && p >= 1 && p <= nz - 2;
         if constexpr (PROLONG) {
             if (sync_first) lds_barrier();
 #pragma unroll
-            for (int r = 0; r < kCPer; ++r) {
-                const int e = tid + r * kThreads;
-                if (e < kCCells) {
-                    const int pl = e / (kCWX * kCWY);
-                    const int rem = e - pl * (kCWX * kCWY);
-                    const int w = rem / kCWX, c = rem - w * kCWX;
-                    CW[pl][w][c] = csrc[r];
+            for (int r = 0; r < kCPer; ++r)
+                if (cw_l[r] >= 0) CW[cw_l[r]] = csrc[r];
+            lds_barrier();
+            const T h = (T)0.5;
+            const bool ok = (p & 1) != 0;
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                if ((zw_ok >> r) & 1) {
+                    const int a = zw_src[r];
+                    const bool oj = (zw_odd >> r) & 1;
+                    const T a0 = CW[a], y0 = oj ? h * (a0 + CW[a + kCWX]) : a0;
+                    T v = y0;
+                    if (ok) {
+                        const T a1 = CW[kCPlane * (kCWPlanes - 1) + a];
+                        const T y1 = oj ? h * (a1 + CW[kCPlane * (kCWPlanes - 1) + a + kCWX]) : a1;
+                        v = h * (y0 + y1);
+                    }
+                    ZW[tid + r * kThreads] = v;
                 }
             }
             lds_barrier();
         }
-        T(*dst)[kWX] = S[p & 3];
+        T *dst = S + (p & 3) * kWCells;
 #pragma unroll
         for (int r = 0; r < kWPer; ++r) {
-            const int e = tid + r * kThreads;
-            if (e < kWCells) {
-                const int w = e / kWX, c = e - w * kWX;
-                const int i = i0 - 2 + c, j = j0 - 2 + w;
-                T v = (T)0;
-                if (!ZERO_IN && i >= 0 && i < nx && j >= 0 && j < ny) v = src[r];
-                if constexpr (PROLONG) {
-                    if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2 && p >= 1 && p <= nz - 2) v += corr(i, j, p);
+            if (st_l[r] < 0) continue;
+            T v = (!ZERO_IN && ((st_in >> r) & 1)) ? src[r] : (T)0;
+            if constexpr (PROLONG) {
+                if (corr && ((st_int >> r) & 1)) {
+                    const T a = ZW[st_z[r]];
+                    v += ((st_odd >> r) & 1) ? (T)0.5 * (a + ZW[st_z[r] + 1]) : a;
                 }
-                dst[w][sx(c)] = v;
             }
+            dst[st_l[r]] = v;
         }
         if constexpr (HAS_F) {
-            T(*fd)[kFX] = F[p & 3];
+            T *fd = F + (p & 3) * kFCells3;
 #pragma unroll
-            for (int r = 0; r < kFPer3; ++r) {
-                const int e = tid + r * kThreads;
-                if (e < kFCells3) {
-                    const int w = e / kFX, c = e - w * kFX;
-                    fd[w][sxf(c)] = fsrc[r];
-                }
-            }
+            for (int r = 0; r < kFPer3; ++r)
+                if (f_l[r] >= 0) fd[f_l[r]] = fsrc[r];
         }
     };
 
@@ -335,11 +437,12 @@ __global__ __launch_bounds__(kThreads) void k_sweep3(const LevelItem *__restrict
             if (s + 1 <= ptop) stash(s + 1, pre[ri], fpre[ri], cpre[ri], false);
             if (s + 1 + D <= ptop) fetch(s + 1 + D, pre[ri], fpre[ri], cpre[ri]);
             lds_barrier();
+            const T *Ps = S + (s & 3) * kWCells;
+            const T *Pu = S + ((s + 1) & 3) * kWCells;
+            const T *Pd = S + ((s - 1) & 3) * kWCells;
             if constexpr (NORM) {
                 // residual of the input iterate at plane s (all values still
                 // old); old plane s-1 comes from registers captured a step ago
-                T(*P)[kWX] = S[s & 3];
-                T(*Pp)[kWX] = S[(s + 1) & 3];
                 const bool do_res = (s >= kb && s < ke);
                 T cx = 0, cy = 0, dd = 0;
                 if (do_res) {
@@ -347,21 +450,17 @@ __global__ __launch_bounds__(kThreads) void k_sweep3(const LevelItem *__restrict
                     cy = coef[4 * s + 1];
                     dd = coef[4 * s + 2];
                 }
+                const T *Fs = F + (s & 3) * kFCells3;
 #pragma unroll
                 for (int q = 0; q < kOwn; ++q) {
-                    const int e = tid + q * kThreads;
-                    const int w = 2 + e / kTX, c = 2 + e % kTX;
-                    const T uc = P[w][sx(c)];
-                    if (do_res) {
-                        const int i = i0 + c - 2, j = j0 + w - 2;
-                        if (i <= nx - 2 && j <= ny - 2) {
-                            T fv = (T)0;
-                            if constexpr (HAS_F) fv = F[s & 3][w - 1][sxf(c - 1)];
-                            const T r = fv - (cx * (P[w][sx(c + 1)] + P[w][sx(c - 1)]) +
-                                              cy * (P[w + 1][sx(c)] + P[w - 1][sx(c)]) + cz * (Pp[w][sx(c)] + below[q]) +
-                                              dd * uc);
-                            acc += (double)r * (double)r;
-                        }
+                    const int o = ow_c[q], ww = ow_w[q];
+                    const T uc = Ps[o];
+                    if (do_res && ((ow_ok >> q) & 1)) {
+                        T fv = (T)0;
+                        if constexpr (HAS_F) fv = Fs[ow_f[q]];
+                        const T r = fv - (cx * (Ps[ww + 1] + Ps[ww]) + cy * (Ps[o + kWX] + Ps[o - kWX]) +
+                                          cz * (Pu[o] + below[q]) + dd * uc);
+                        acc += (double)r * (double)r;
                     }
                     below[q] = uc;
                 }
@@ -370,23 +469,18 @@ __global__ __launch_bounds__(kThreads) void k_sweep3(const LevelItem *__restrict
             // red nodes of plane s on the tile and its one-node ring
             if (s >= 1 && s <= nz - 2) {
                 const T cx = coef[4 * s], cy = coef[4 * s + 1], invd = coef[4 * s + 3];
-                T(*P)[kWX] = S[s & 3];
-                T(*Pm)[kWX] = S[(s - 1) & 3];
-                T(*Pp)[kWX] = S[(s + 1) & 3];
-                T(*Fs)[kFX] = F[s & 3];
-                for (int e = tid; e < (kTY + 2) * kRedPerRow; e += kThreads) {
-                    const int w = 1 + e / kRedPerRow;
-                    const int q = e - (w - 1) * kRedPerRow;
-                    const int c = 1 + ((i0 + j0 + w + s + 1) & 1) + 2 * q;
-                    const int i = i0 - 2 + c, j = j0 - 2 + w;
-                    if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2) {
-                        T fv = (T)0;
-                        if constexpr (HAS_F) fv = Fs[w - 1][sxf(c - 1)];
-                        P[w][sx(c)] = (fv - (cx * (P[w][sx(c + 1)] + P[w][sx(c - 1)]) +
-                                             cy * (P[w + 1][sx(c)] + P[w - 1][sx(c)]) +
-                                             cz * (Pp[w][sx(c)] + Pm[w][sx(c)]))) *
-                                      invd;
-                    }
+                T *P = S + (s & 3) * kWCells;
+                const T *Fs = F + (s & 3) * kFCells3;
+                const int ps = (par0 + s) & 1;
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const int o = ps ? rd_c[1][r] : rd_c[0][r];
+                    if (o < 0) continue;
+                    const int ww = ps ? rd_w[1][r] : rd_w[0][r];
+                    T fv = (T)0;
+                    if constexpr (HAS_F) fv = Fs[ps ? rd_f[1][r] : rd_f[0][r]];
+                    P[o] = (fv - (cx * (P[ww + 1] + P[ww]) + cy * (P[o + kWX] + P[o - kWX]) + cz * (Pu[o] + Pd[o]))) *
+                           invd;
                 }
             }
             lds_barrier();
@@ -394,33 +488,26 @@ __global__ __launch_bounds__(kThreads) void k_sweep3(const LevelItem *__restrict
             const int m = s - 1;
             if (m >= kb && m < ke) {
                 const T cx = coef[4 * m], cy = coef[4 * m + 1], invd = coef[4 * m + 3];
-                T(*P)[kWX] = S[m & 3];
-                T(*Pm)[kWX] = S[(m - 1) & 3];
-                T(*Pp)[kWX] = S[(m + 1) & 3];
-                T(*Fm)[kFX] = F[m & 3];
-                for (int e = tid; e < kTY * kBlackPerRow; e += kThreads) {
-                    const int w = 2 + e / kBlackPerRow;
-                    const int q = e - (w - 2) * kBlackPerRow;
-                    const int c = 2 + ((i0 + j0 + w + m + 1) & 1) + 2 * q;
-                    const int i = i0 - 2 + c, j = j0 - 2 + w;
-                    if (i <= nx - 2 && j <= ny - 2) {
-                        T fv = (T)0;
-                        if constexpr (HAS_F) fv = Fm[w - 1][sxf(c - 1)];
-                        P[w][sx(c)] = (fv - (cx * (P[w][sx(c + 1)] + P[w][sx(c - 1)]) +
-                                             cy * (P[w + 1][sx(c)] + P[w - 1][sx(c)]) +
-                                             cz * (Pp[w][sx(c)] + Pm[w][sx(c)]))) *
-                                      invd;
-                    }
+                T *P = S + (m & 3) * kWCells;
+                const T *Pm = S + ((m - 1) & 3) * kWCells;
+                const T *Fm = F + (m & 3) * kFCells3;
+                const int pb = (par0 + m) & 1;
+                const int o = pb ? bk_c[1] : bk_c[0];
+                if (o >= 0) {
+                    const int ww = pb ? bk_w[1] : bk_w[0];
+                    T fv = (T)0;
+                    if constexpr (HAS_F) fv = Fm[pb ? bk_f[1] : bk_f[0]];
+                    P[o] = (fv - (cx * (P[ww + 1] + P[ww]) + cy * (P[o + kWX] + P[o - kWX]) + cz * (Ps[o] + Pm[o]))) *
+                           invd;
                 }
             }
             lds_barrier();
             if (m >= kb && m < ke) {
-                T(*P)[kWX] = S[m & 3];
-                for (int e = tid; e < kTY * kTX; e += kThreads) {
-                    const int w = 2 + e / kTX, c = 2 + e % kTX;
-                    const int i = i0 + c - 2, j = j0 + w - 2;
-                    if (i <= nx - 2 && j <= ny - 2) uout[(size_t)i + (size_t)nx * j + sxy * m] = P[w][sx(c)];
-                }
+                const T *P = S + (m & 3) * kWCells;
+                MHS_GLOBAL T *ol = uout + sxy * (size_t)m;
+#pragma unroll
+                for (int q = 0; q < kOwn; ++q)
+                    if ((ow_ok >> q) & 1) *(MHS_GLOBAL T *)((MHS_GLOBAL char *)ol + ow_g[q]) = P[ow_c[q]];
             }
         }
     }
@@ -835,31 +922,59 @@ __global__ __launch_bounds__(kThreads) void k_ir3(const LevelItem *__restrict__ 
 // dense solve on the coarsest grid.  Every work array lives in LDS (up to
 // 160 KB on gfx950), so each phase costs LDS latency, not HBM latency.
 // ============================================================================
-__device__ __forceinline__ void bottom_smooth(double *smem, const BottomItem &b, int l, bool planar, int nsweeps)
+// Threads of the bottom solver work row by row: a row is the interior nodes
+// (j, k) fixed, i running; `cnt` nodes of a row go to a power-of-two group
+// of 2^lg lanes and the workgroup covers 1024 / 2^lg rows at a time, so
+// node coordinates come from shifts and one small division per row.
+__device__ __forceinline__ int ceil_log2(int v) { return v <= 1 ? 0 : 32 - __clz(v - 1); }
+
+template <typename Fn>
+__device__ __forceinline__ void bottom_rows(int cnt, int my, int nrows, Fn &&fn)
+{
+    const int lg = ceil_log2(cnt);
+    if ((1 << lg) > kBottomThreads) { // rows longer than the workgroup
+        for (int r = 0; r < nrows; ++r) {
+            const int kk = r / my;
+            for (int q = (int)threadIdx.x; q < cnt; q += kBottomThreads) fn(q, r - kk * my, kk);
+        }
+        return;
+    }
+    const int q = (int)threadIdx.x & ((1 << lg) - 1);
+    if (q >= cnt) return;
+    for (int r = (int)threadIdx.x >> lg; r < nrows; r += kBottomThreads >> lg) {
+        const int kk = r / my;
+        fn(q, r - kk * my, kk);
+    }
+}
+
+// One colour of red-black Gauss-Seidel on level l (colour = (i + j + k) & 1).
+__device__ __forceinline__ void bottom_colour(double *smem, const BottomItem &b, int l, bool planar, int colour)
 {
     const int nx = b.n[l][0], ny = b.n[l][1], nz = b.n[l][2];
     const int mx = nx - 2, my = ny - 2, mz = planar ? 1 : nz - 2;
-    const int nint = mx * my * mz;
     double *u = smem + b.off_u[l];
     const double *f = smem + b.off_f[l];
-    const MHS_GLOBAL double *coef = gin<double>(b.coef[l]);
+    const double *cf = smem + b.off_c[l];
     const double cz = b.cz[l];
     const int sxy = nx * ny;
+    bottom_rows((mx + 1) >> 1, my, my * mz, [&](int q, int jj, int kk) {
+        const int j = jj + 1, k = planar ? 0 : kk + 1;
+        const int i = 1 + ((j + k + 1 + colour) & 1) + 2 * q;
+        if (i > mx) return;
+        const int idx = i + nx * j + sxy * k;
+        double off = cf[4 * k] * (u[idx + 1] + u[idx - 1]) + cf[4 * k + 1] * (u[idx + nx] + u[idx - nx]);
+        if (!planar) off += cz * (u[idx + sxy] + u[idx - sxy]);
+        u[idx] = (f[idx] - off) * cf[4 * k + 3];
+    });
+}
+
+__device__ __forceinline__ void bottom_smooth(double *smem, const BottomItem &b, int l, bool planar, int nsweeps)
+{
     for (int s = 0; s < nsweeps; ++s) {
-        for (int colour = 0; colour < 2; ++colour) {
-            for (int e = threadIdx.x; e < nint; e += kBottomThreads) {
-                const int ii = e % mx, rest = e / mx;
-                const int jj = rest % my, kk = rest / my;
-                const int i = ii + 1, j = jj + 1, k = planar ? 0 : kk + 1;
-                if (((i + j + k) & 1) != colour) continue;
-                const int idx = i + nx * j + sxy * k;
-                const double cx = coef[4 * k], cy = coef[4 * k + 1], invd = coef[4 * k + 3];
-                double off = cx * (u[idx + 1] + u[idx - 1]) + cy * (u[idx + nx] + u[idx - nx]);
-                if (!planar) off += cz * (u[idx + sxy] + u[idx - sxy]);
-                u[idx] = (f[idx] - off) * invd;
-            }
-            lds_barrier();
-        }
+        bottom_colour(smem, b, l, planar, 0);
+        lds_barrier();
+        bottom_colour(smem, b, l, planar, 1);
+        lds_barrier();
     }
 }
 
@@ -873,6 +988,8 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(const BottomItem *__r
     const int tid = threadIdx.x;
     const int L = b.nlev;
     double *r = smem + b.off_r;
+    // every level's u = 0 and f (the top level's from global memory), and
+    // the coefficient tables, into LDS
     for (int l = 0; l < L; ++l) {
         const int N = b.n[l][0] * b.n[l][1] * b.n[l][2];
         double *u = smem + b.off_u[l];
@@ -882,48 +999,45 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(const BottomItem *__r
             u[e] = 0.0;
             f[e] = (l == 0) ? (double)ft[e] : 0.0;
         }
+        const int nc = 4 * b.n[l][2];
+        const MHS_GLOBAL double *cg = gin<double>(b.coef[l]);
+        for (int e = tid; e < nc; e += kBottomThreads) smem[b.off_c[l] + e] = cg[e];
     }
     lds_barrier();
     for (int l = 0; l < L - 1; ++l) {
         const int nx = b.n[l][0], ny = b.n[l][1], nz = b.n[l][2];
         const int sxy = nx * ny;
+        const int mx = nx - 2, my = ny - 2, mz = planar ? 1 : nz - 2;
         bottom_smooth(smem, b, l, planar, b.nu1);
         // residual on interior nodes
         {
             const double *u = smem + b.off_u[l];
             const double *f = smem + b.off_f[l];
-            const MHS_GLOBAL double *coef = gin<double>(b.coef[l]);
+            const double *cf = smem + b.off_c[l];
             const double cz = b.cz[l];
-            const int mx = nx - 2, my = ny - 2, mz = planar ? 1 : nz - 2;
-            const int nint = mx * my * mz;
-            for (int e = tid; e < nint; e += kBottomThreads) {
-                const int ii = e % mx, rest = e / mx;
-                const int jj = rest % my, kk = rest / my;
-                const int i = ii + 1, j = jj + 1, k = planar ? 0 : kk + 1;
+            bottom_rows(mx, my, my * mz, [&](int q, int jj, int kk) {
+                const int i = q + 1, j = jj + 1, k = planar ? 0 : kk + 1;
                 const int idx = i + nx * j + sxy * k;
-                double au = coef[4 * k] * (u[idx + 1] + u[idx - 1]) + coef[4 * k + 1] * (u[idx + nx] + u[idx - nx]) +
-                            coef[4 * k + 2] * u[idx];
+                double au = cf[4 * k] * (u[idx + 1] + u[idx - 1]) + cf[4 * k + 1] * (u[idx + nx] + u[idx - nx]) +
+                            cf[4 * k + 2] * u[idx];
                 if (!planar) au += cz * (u[idx + sxy] + u[idx - sxy]);
                 r[idx] = f[idx] - au;
-            }
+            });
         }
         lds_barrier();
         // full weighting onto the interior of level l+1
         {
             const int cnx = b.n[l + 1][0], cny = b.n[l + 1][1], cnz = b.n[l + 1][2];
             double *fc = smem + b.off_f[l + 1];
-            const int mx = cnx - 2, my = cny - 2, mz = planar ? 1 : cnz - 2;
-            const int nint = mx * my * mz;
-            for (int e = tid; e < nint; e += kBottomThreads) {
-                const int ii = e % mx, rest = e / mx;
-                const int jj = rest % my, kk = rest / my;
-                const int I = ii + 1, J = jj + 1, K = planar ? 0 : kk + 1;
+            const int cmx = cnx - 2, cmy = cny - 2, cmz = planar ? 1 : cnz - 2;
+            bottom_rows(cmx, cmy, cmy * cmz, [&](int q, int jj, int kk) {
+                const int I = q + 1, J = jj + 1, K = planar ? 0 : kk + 1;
                 const int fidx = 2 * I + nx * (2 * J) + sxy * (planar ? 0 : 2 * K);
-                auto row = [&](int q) { return 0.25 * r[q - 1] + 0.5 * r[q] + 0.25 * r[q + 1]; };
-                auto pl = [&](int q) { return 0.25 * row(q - nx) + 0.5 * row(q) + 0.25 * row(q + nx); };
+                auto row = [&](int c) { return 0.25 * r[c - 1] + 0.5 * r[c] + 0.25 * r[c + 1]; };
+                auto pl = [&](int c) { return 0.25 * row(c - nx) + 0.5 * row(c) + 0.25 * row(c + nx); };
                 const double v = planar ? pl(fidx) : 0.25 * pl(fidx - sxy) + 0.5 * pl(fidx) + 0.25 * pl(fidx + sxy);
                 fc[I + cnx * J + cnx * cny * K] = v;
-            }
+            });
         }
         lds_barrier();
     }
@@ -954,16 +1068,13 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(const BottomItem *__r
         const int cnx = b.n[l + 1][0], cny = b.n[l + 1][1];
         const int sxy = nx * ny;
         const int mx = nx - 2, my = ny - 2, mz = planar ? 1 : nz - 2;
-        const int nint = mx * my * mz;
         double *u = smem + b.off_u[l];
         const double *ec = smem + b.off_u[l + 1];
-        for (int e = tid; e < nint; e += kBottomThreads) {
-            const int ii = e % mx, rest = e / mx;
-            const int jj = rest % my, kk = rest / my;
-            const int i = ii + 1, j = jj + 1, k = planar ? 0 : kk + 1;
+        bottom_rows(mx, my, my * mz, [&](int q, int jj, int kk) {
+            const int i = q + 1, j = jj + 1, k = planar ? 0 : kk + 1;
             const double v = planar ? interp2<double>(ec, cnx, i, j) : interp3<double>(ec, cnx, cny, i, j, k);
             u[i + nx * j + sxy * k] += v;
-        }
+        });
         lds_barrier();
         bottom_smooth(smem, b, l, planar, b.nu2);
     }
