@@ -140,10 +140,12 @@ __device__ __forceinline__ T interp2(Ptr ec, int ncx, int i, int j)
 // identical to updating all red nodes and then all black nodes.
 //
 // Loads run kDepth planes ahead of the stencil in a ring of register sets,
-// so kDepth planes of HBM traffic are in flight per workgroup.  With the
-// prolongation-fused variant each register set also carries the two coarse
-// planes the fine plane interpolates from; they are staged in LDS when the
-// fine plane is, and the trilinear correction is added there.
+// so kDepth planes of HBM traffic are in flight per workgroup.  Every index
+// a thread uses (staging cells, red and black nodes, written nodes) is fixed
+// for the whole z-march and computed once.  With the prolongation-fused
+// variant each register set also carries the coarse planes of the next fine
+// plane; they are staged in LDS one step early and interpolated in z and y
+// during the red phase, so staging a plane only adds the x interpolation.
 // ============================================================================
 constexpr int kWX = kTX + 4;
 constexpr int kWY = kTY + 4;
@@ -172,6 +174,18 @@ constexpr int kFHalf = kFX / 2;
 __device__ __forceinline__ int sxf(int c) { return (c & 1) * kFHalf + (c >> 1); }
 static_assert(kFX % 2 == 0, "rhs window width must be even");
 
+// LDS index pairs packed into one register (both < 65536).
+__device__ __forceinline__ uint32_t pk16(int lo, int hi) { return (uint32_t)lo | ((uint32_t)hi << 16); }
+__device__ __forceinline__ int lo16(uint32_t v) { return (int)(v & 0xffffu); }
+__device__ __forceinline__ int hi16(uint32_t v) { return (int)(v >> 16); }
+// a or b by a 0/1 flag, as arithmetic (an indexed or selected register pair
+// would be placed in scratch memory)
+__device__ __forceinline__ uint32_t pick(uint32_t a, uint32_t b, int flag)
+{
+    return a ^ ((a ^ b) & (0u - (uint32_t)flag));
+}
+constexpr int kNone = 0xffff; // "no node" marker in a packed index
+
 template <typename T, int FLAGS>
 __global__ __launch_bounds__(kThreads) void k_sweep3(const LevelItem *__restrict__ items, int nitems)
 {
@@ -185,13 +199,22 @@ __global__ __launch_bounds__(kThreads) void k_sweep3(const LevelItem *__restrict
     constexpr int kCWPlanes = PROLONG ? 2 : 1;
     constexpr int kFSlots = HAS_F ? 4 : 1;
     constexpr int kCPlane = kCWX * kCWY;
-    __shared__ T S[4 * kWCells];
+    // Window rows in LDS: even columns, then odd columns, the odd half
+    // starting 16 banks after the even one, so that the colour phases (every
+    // other column) and the staging of consecutive columns are both free of
+    // bank conflicts.
+    constexpr int HP = sizeof(T) == 8 ? 40 : 48;
+    constexpr int RW = 2 * HP;
+    constexpr int SLOT = kWY * RW;
+    static_assert(HP >= kWX / 2, "half row too short");
+    __shared__ T S[4 * SLOT];
     __shared__ T F[kFSlots * kFCells3];
     __shared__ T CW[kCWPlanes * kCPlane];
     // prolongation: the coarse correction interpolated in z and y onto every
     // fine row of the window, at coarse columns (x interpolation at staging)
     __shared__ T ZW[PROLONG ? kWY * kCWX : 1];
     __shared__ double red[kThreads / 64];
+    auto sxp = [](int c) { return (c & 1) * HP + (c >> 1); };
 
     const int tile = xcd_tile();
     const LevelItem *it = items + find_item(items, nitems, tile);
@@ -203,7 +226,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep3(const LevelItem *__restrict
     const MHS_CONST T *__restrict__ coef = gconst<T>(it->coef);
     const T cz = (T)it->cz;
     const int nx = it->nx, ny = it->ny, nz = it->nz;
-    const int ncx = it->ncx, ncy = it->ncy;
+    const int ncx = it->ncx, ncy = it->ncy, ncz = it->ncz;
     const int kz = it->kz;
     int local = tile - it->tile_base;
     const int tx = local % it->ntx;
@@ -221,11 +244,11 @@ __global__ __launch_bounds__(kThreads) void k_sweep3(const LevelItem *__restrict
     constexpr uint32_t es = sizeof(T);
 
     // ---- per-thread geometry, the same on every plane of the march --------
-    // Window cells this thread stages (slot-local LDS index, byte offset of
-    // the clamped in-plane source, inside-array and interior flags).
-    int st_l[kWPer];
+    // Window cells this thread stages: LDS index (kNone past the window) and
+    // the ZW index of the cell's coarse column; byte offset of the clamped
+    // in-plane source; inside-array, interior and odd-column flags.
+    uint32_t st_i[kWPer];
     uint32_t st_g[kWPer];
-    int st_z[kWPer];
     uint32_t st_in = 0, st_int = 0, st_odd = 0;
 #pragma unroll
     for (int r = 0; r < kWPer; ++r) {
@@ -233,14 +256,13 @@ __global__ __launch_bounds__(kThreads) void k_sweep3(const LevelItem *__restrict
         const int ee = min(e, kWCells - 1);
         const int w = ee / kWX, c = ee - w * kWX;
         const int i = i0 - 2 + c, j = j0 - 2 + w;
-        st_l[r] = e < kWCells ? w * kWX + sx(c) : -1;
+        st_i[r] = pk16(e < kWCells ? w * RW + sxp(c) : kNone, PROLONG ? w * kCWX + ((i >> 1) - I0) : 0);
         st_g[r] = es * (uint32_t)(min(max(i, 0), nx - 1) + nx * min(max(j, 0), ny - 1));
-        st_z[r] = w * kCWX + ((i >> 1) - I0);
         if (i >= 0 && i < nx && j >= 0 && j < ny) st_in |= 1u << r;
         if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2) st_int |= 1u << r;
         if (i & 1) st_odd |= 1u << r;
     }
-    // right-hand-side window cells
+    // right-hand-side window cells (tile plus a one-node ring)
     int f_l[HAS_F ? kFPer3 : 1];
     uint32_t f_g[HAS_F ? kFPer3 : 1];
     if constexpr (HAS_F) {
@@ -253,42 +275,43 @@ __global__ __launch_bounds__(kThreads) void k_sweep3(const LevelItem *__restrict
             f_g[r] = es * (uint32_t)(min(i0 - 1 + c, nx - 1) + nx * min(j0 - 1 + w, ny - 1));
         }
     }
-    // coarse-window cells (two coarse planes) and the z-y interpolation rows
-    int cw_l[PROLONG ? kCPer : 1];
+    // coarse-window cells (two coarse planes; LDS index tid + r * kThreads)
+    // and the z-y interpolation entries this thread computes
     uint32_t cw_g[PROLONG ? kCPer : 1];
     uint32_t cw_hi = 0;
-    int zw_src[PROLONG ? 2 : 1];
-    uint32_t zw_ok = 0, zw_odd = 0;
+    uint32_t zw_src = 0, zw_ok = 0, zw_odd = 0;
     if constexpr (PROLONG) {
 #pragma unroll
         for (int r = 0; r < kCPer; ++r) {
-            const int e = tid + r * kThreads;
-            const int ee = min(e, kCCells - 1);
-            const int pl = ee / kCPlane;
-            const int rem = ee - pl * kCPlane;
+            const int e = min(tid + r * kThreads, kCCells - 1);
+            const int pl = e / kCPlane;
+            const int rem = e - pl * kCPlane;
             const int w = rem / kCWX, c = rem - w * kCWX;
             const int I = min(max(I0 + c, 0), ncx - 1), J = min(max(J0 + w, 0), ncy - 1);
-            cw_l[r] = e < kCCells ? ee : -1;
             cw_g[r] = es * (uint32_t)(I + ncx * J);
             if (pl) cw_hi |= 1u << r;
         }
+        int src[2];
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
             const int e = tid + r * kThreads;
             const int ee = min(e, kWY * kCWX - 1);
             const int w = ee / kCWX, lc = ee - w * kCWX;
             const int j = j0 - 2 + w;
-            zw_src[r] = ((j >> 1) - J0) * kCWX + lc;
+            src[r] = ((j >> 1) - J0) * kCWX + lc;
             if (e < kWY * kCWX) zw_ok |= 1u << r;
             if (j & 1) zw_odd |= 1u << r;
         }
+        zw_src = pk16(src[0], src[1]);
     }
     // red nodes (tile plus a one-node ring) for each plane parity: centre
-    // index and the index of the west neighbour (east = west + 1 in the
-    // colour-split row); -1 where the node is not an interior node
-    int rd_c[2][2], rd_w[2][2], rd_f[2][2];
+    // and west-neighbour indices (east = west + 1 in the colour-split row),
+    // centre kNone where the node is not interior
+    uint32_t rd0[2], rd1[2];
+    uint32_t rdf0 = 0, rdf1 = 0;
 #pragma unroll
-    for (int ps = 0; ps < 2; ++ps)
+    for (int ps = 0; ps < 2; ++ps) {
+        int fi[2];
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
             const int e = tid + r * kThreads;
@@ -298,37 +321,60 @@ __global__ __launch_bounds__(kThreads) void k_sweep3(const LevelItem *__restrict
             const int c = 1 + ((ps + w) & 1) + 2 * q;
             const int i = i0 - 2 + c, j = j0 - 2 + w;
             const bool ok = e < (kTY + 2) * kRedPerRow && i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2;
-            rd_c[ps][r] = ok ? w * kWX + sx(c) : -1;
-            rd_w[ps][r] = w * kWX + sx(c - 1);
-            rd_f[ps][r] = (w - 1) * kFX + sxf(c - 1);
+            const uint32_t v = pk16(ok ? w * RW + sxp(c) : kNone, w * RW + sxp(c - 1));
+            if (ps)
+                rd1[r] = v;
+            else
+                rd0[r] = v;
+            fi[r] = (w - 1) * kFX + sxf(c - 1);
         }
-    // black nodes of the tile (one per thread) for each plane parity
-    int bk_c[2], bk_w[2], bk_f[2];
-#pragma unroll
-    for (int ps = 0; ps < 2; ++ps) {
-        const int w = 2 + tid / kBlackPerRow;
-        const int q = tid - (w - 2) * kBlackPerRow;
-        const int c = 2 + ((ps + w) & 1) + 2 * q;
-        const int i = i0 - 2 + c, j = j0 - 2 + w;
-        bk_c[ps] = (i <= nx - 2 && j <= ny - 2) ? w * kWX + sx(c) : -1;
-        bk_w[ps] = w * kWX + sx(c - 1);
-        bk_f[ps] = (w - 1) * kFX + sxf(c - 1);
+        if constexpr (HAS_F) {
+            if (ps)
+                rdf1 = pk16(fi[0], fi[1]);
+            else
+                rdf0 = pk16(fi[0], fi[1]);
+        }
     }
+    // black nodes of the tile (one per thread) for each plane parity
+    uint32_t bk0 = 0, bk1 = 0;
+    uint32_t bkf = 0;
     static_assert(kTY * kBlackPerRow == kThreads, "one black node per thread");
-    // tile nodes this thread writes (and sums the residual of)
-    int ow_c[kOwn], ow_w[kOwn], ow_f[kOwn];
-    uint32_t ow_g[kOwn];
-    uint32_t ow_ok = 0;
+    {
+        int fi[2];
 #pragma unroll
-    for (int q = 0; q < kOwn; ++q) {
-        const int e = tid + q * kThreads;
-        const int w = 2 + e / kTX, c = 2 + e % kTX;
-        const int i = i0 + c - 2, j = j0 + w - 2;
-        ow_c[q] = w * kWX + sx(c);
-        ow_w[q] = w * kWX + sx(c - 1);
-        ow_f[q] = (w - 1) * kFX + sxf(c - 1);
-        ow_g[q] = es * (uint32_t)(min(i, nx - 1) + nx * min(j, ny - 1));
-        if (i <= nx - 2 && j <= ny - 2) ow_ok |= 1u << q;
+        for (int ps = 0; ps < 2; ++ps) {
+            const int w = 2 + tid / kBlackPerRow;
+            const int q = tid - (w - 2) * kBlackPerRow;
+            const int c = 2 + ((ps + w) & 1) + 2 * q;
+            const int i = i0 - 2 + c, j = j0 - 2 + w;
+            const uint32_t v = pk16((i <= nx - 2 && j <= ny - 2) ? w * RW + sxp(c) : kNone, w * RW + sxp(c - 1));
+            if (ps)
+                bk1 = v;
+            else
+                bk0 = v;
+            fi[ps] = (w - 1) * kFX + sxf(c - 1);
+        }
+        if constexpr (HAS_F) bkf = pk16(fi[0], fi[1]);
+    }
+    // tile nodes this thread writes (and sums the residual of)
+    uint32_t ow[kOwn];
+    uint32_t ow_g[kOwn];
+    uint32_t owf = 0;
+    uint32_t ow_ok = 0;
+    static_assert(kOwn == 2, "two written nodes per thread");
+    {
+        int fi[kOwn];
+#pragma unroll
+        for (int q = 0; q < kOwn; ++q) {
+            const int e = tid + q * kThreads;
+            const int w = 2 + e / kTX, c = 2 + e % kTX;
+            const int i = i0 + c - 2, j = j0 + w - 2;
+            ow[q] = pk16(w * RW + sxp(c), w * RW + sxp(c - 1));
+            fi[q] = (w - 1) * kFX + sxf(c - 1);
+            ow_g[q] = es * (uint32_t)(min(i, nx - 1) + nx * min(j, ny - 1));
+            if (i <= nx - 2 && j <= ny - 2) ow_ok |= 1u << q;
+        }
+        if constexpr (HAS_F && NORM) owf = pk16(fi[0], fi[1]);
     }
     const int par0 = (i0 + j0 + 1) & 1; // red parity of plane s is (par0 + s) & 1
 
@@ -336,9 +382,21 @@ __global__ __launch_bounds__(kThreads) void k_sweep3(const LevelItem *__restrict
         return *(const MHS_GLOBAL T *)((const MHS_GLOBAL char *)base + byte_off);
     };
 
+    // Register ring: set q holds plane p's window (and right-hand side) and,
+    // for the prolongation, the coarse data of plane p + 1, one plane ahead
+    // so that its z-y interpolation can run during the red phase before the
+    // plane is staged.
     T pre[D][kWPer];
     T fpre[D][HAS_F ? kFPer3 : 1];
     T cpre[D][PROLONG ? kCPer : 1];
+    auto fetch_coarse = [&](int p, T(&cdst)[PROLONG ? kCPer : 1]) {
+        if constexpr (PROLONG) {
+            const MHS_GLOBAL T *p0 = ec + csxy * (size_t)min(p >> 1, ncz - 1);
+            const MHS_GLOBAL T *p1 = ec + csxy * (size_t)min((p + 1) >> 1, ncz - 1);
+#pragma unroll
+            for (int r = 0; r < kCPer; ++r) cdst[r] = at(((cw_hi >> r) & 1) ? p1 : p0, cw_g[r]);
+        }
+    };
     // Loads are unconditional, from clamped in-bounds addresses, straight
     // into the ring registers; cells outside the array are zeroed when the
     // plane is staged.
@@ -353,28 +411,24 @@ __global__ __launch_bounds__(kThreads) void k_sweep3(const LevelItem *__restrict
 #pragma unroll
             for (int r = 0; r < kFPer3; ++r) fdst[r] = at(pl, f_g[r]);
         }
-        if constexpr (PROLONG) {
-            const MHS_GLOBAL T *p0 = ec + csxy * (size_t)(p >> 1);
-            const MHS_GLOBAL T *p1 = ec + csxy * (size_t)((p + 1) >> 1);
-#pragma unroll
-            for (int r = 0; r < kCPer; ++r) cdst[r] = at(((cw_hi >> r) & 1) ? p1 : p0, cw_g[r]);
-        }
+        fetch_coarse(p + 1, cdst);
     };
-    auto stash = [&](int p, const T(&src)[kWPer], const T(&fsrc)[HAS_F ? kFPer3 : 1],
-                     const T(&csrc)[PROLONG ? kCPer : 1], bool sync_first) {
-        const bool corr = PROLONG && p >= 1 && p <= nz - 2;
+    auto store_cw = [&](const T(&csrc)[PROLONG ? kCPer : 1]) {
         if constexpr (PROLONG) {
-            if (sync_first) lds_barrier();
 #pragma unroll
             for (int r = 0; r < kCPer; ++r)
-                if (cw_l[r] >= 0) CW[cw_l[r]] = csrc[r];
-            lds_barrier();
+                if (tid + r * kThreads < kCCells) CW[tid + r * kThreads] = csrc[r];
+        }
+    };
+    // z-y interpolation of the staged coarse planes for fine plane p
+    auto zy_rows = [&](int p) {
+        if constexpr (PROLONG) {
             const T h = (T)0.5;
             const bool ok = (p & 1) != 0;
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
                 if ((zw_ok >> r) & 1) {
-                    const int a = zw_src[r];
+                    const int a = r ? hi16(zw_src) : lo16(zw_src);
                     const bool oj = (zw_odd >> r) & 1;
                     const T a0 = CW[a], y0 = oj ? h * (a0 + CW[a + kCWX]) : a0;
                     T v = y0;
@@ -386,20 +440,27 @@ __global__ __launch_bounds__(kThreads) void k_sweep3(const LevelItem *__restrict
                     ZW[tid + r * kThreads] = v;
                 }
             }
-            lds_barrier();
         }
-        T *dst = S + (p & 3) * kWCells;
+    };
+    // stage plane p (window with the coarse correction from ZW, right-hand
+    // side) and the coarse planes of p + 1 carried by the same register set
+    auto stash = [&](int p, const T(&src)[kWPer], const T(&fsrc)[HAS_F ? kFPer3 : 1],
+                     const T(&csrc)[PROLONG ? kCPer : 1]) {
+        const bool corr = PROLONG && p >= 1 && p <= nz - 2;
+        T *dst = S + (p & 3) * SLOT;
 #pragma unroll
         for (int r = 0; r < kWPer; ++r) {
-            if (st_l[r] < 0) continue;
+            const int l = lo16(st_i[r]);
+            if (l == kNone) continue;
             T v = (!ZERO_IN && ((st_in >> r) & 1)) ? src[r] : (T)0;
             if constexpr (PROLONG) {
                 if (corr && ((st_int >> r) & 1)) {
-                    const T a = ZW[st_z[r]];
-                    v += ((st_odd >> r) & 1) ? (T)0.5 * (a + ZW[st_z[r] + 1]) : a;
+                    const int z = hi16(st_i[r]);
+                    const T a = ZW[z];
+                    v += ((st_odd >> r) & 1) ? (T)0.5 * (a + ZW[z + 1]) : a;
                 }
             }
-            dst[st_l[r]] = v;
+            dst[l] = v;
         }
         if constexpr (HAS_F) {
             T *fd = F + (p & 3) * kFCells3;
@@ -407,6 +468,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep3(const LevelItem *__restrict
             for (int r = 0; r < kFPer3; ++r)
                 if (f_l[r] >= 0) fd[f_l[r]] = fsrc[r];
         }
+        store_cw(csrc);
     };
 
     double acc = 0.0;
@@ -419,12 +481,35 @@ __global__ __launch_bounds__(kThreads) void k_sweep3(const LevelItem *__restrict
 #pragma unroll
     for (int q = 0; q < D; ++q) {
         const int p = pbase + q;
-        if (p >= 0 && p <= ptop) fetch(p, pre[q], fpre[q], cpre[q]);
+        fetch(min(max(p, 0), ptop), pre[q], fpre[q], cpre[q]);
     }
-    if (pbase >= 0) stash(pbase, pre[0], fpre[0], cpre[0], false);
-    stash(kb - 1, pre[1], fpre[1], cpre[1], true);
-    if (pbase + D <= ptop) fetch(pbase + D, pre[0], fpre[0], cpre[0]);
-    if (pbase + D + 1 <= ptop) fetch(pbase + D + 1, pre[1], fpre[1], cpre[1]);
+    // warm-up: stage planes kb-2 (if any) and kb-1; the prolongation needs
+    // the z-y rows of each plane ready before it is staged
+    if constexpr (PROLONG) {
+        const int pf = max(pbase, 0);
+        T c0[kCPer];
+        fetch_coarse(pf, c0);
+        store_cw(c0);
+        lds_barrier();
+        zy_rows(pf);
+        lds_barrier();
+    }
+    if (pbase >= 0) {
+        stash(pbase, pre[0], fpre[0], cpre[0]);
+        if constexpr (PROLONG) {
+            lds_barrier();
+            zy_rows(pbase + 1);
+            lds_barrier();
+        }
+    }
+    stash(kb - 1, pre[1], fpre[1], cpre[1]);
+    if constexpr (PROLONG) {
+        lds_barrier();
+        zy_rows(kb);
+        lds_barrier();
+    }
+    fetch(min(pbase + D, ptop), pre[0], fpre[0], cpre[0]);
+    fetch(min(pbase + D + 1, ptop), pre[1], fpre[1], cpre[1]);
 
     for (int s0 = kb - 1; s0 <= ke; s0 += D) {
 #pragma unroll
@@ -432,14 +517,18 @@ __global__ __launch_bounds__(kThreads) void k_sweep3(const LevelItem *__restrict
             const int s = s0 + d;
             if (s > ke) break;
             // stage plane s+1 (slot of plane s-3, free since the last black
-            // phase) and refill its register set with plane s+1+D
+            // phase) and refill its register set with plane s+1+D.  Both are
+            // unconditional (past the top of the chunk they repeat the last
+            // plane, and a stage of plane nz lands in a slot no phase reads)
+            // so that every step issues the same loads and the compiler can
+            // wait for exactly the oldest register set.
             const int ri = (d + 2) % D;
-            if (s + 1 <= ptop) stash(s + 1, pre[ri], fpre[ri], cpre[ri], false);
-            if (s + 1 + D <= ptop) fetch(s + 1 + D, pre[ri], fpre[ri], cpre[ri]);
+            stash(s + 1, pre[ri], fpre[ri], cpre[ri]);
+            fetch(min(s + 1 + D, ptop), pre[ri], fpre[ri], cpre[ri]);
             lds_barrier();
-            const T *Ps = S + (s & 3) * kWCells;
-            const T *Pu = S + ((s + 1) & 3) * kWCells;
-            const T *Pd = S + ((s - 1) & 3) * kWCells;
+            const T *Ps = S + (s & 3) * SLOT;
+            const T *Pu = S + ((s + 1) & 3) * SLOT;
+            const T *Pd = S + ((s - 1) & 3) * SLOT;
             if constexpr (NORM) {
                 // residual of the input iterate at plane s (all values still
                 // old); old plane s-1 comes from registers captured a step ago
@@ -453,12 +542,12 @@ __global__ __launch_bounds__(kThreads) void k_sweep3(const LevelItem *__restrict
                 const T *Fs = F + (s & 3) * kFCells3;
 #pragma unroll
                 for (int q = 0; q < kOwn; ++q) {
-                    const int o = ow_c[q], ww = ow_w[q];
+                    const int o = lo16(ow[q]), ww = hi16(ow[q]);
                     const T uc = Ps[o];
                     if (do_res && ((ow_ok >> q) & 1)) {
                         T fv = (T)0;
-                        if constexpr (HAS_F) fv = Fs[ow_f[q]];
-                        const T r = fv - (cx * (Ps[ww + 1] + Ps[ww]) + cy * (Ps[o + kWX] + Ps[o - kWX]) +
+                        if constexpr (HAS_F) fv = Fs[q ? hi16(owf) : lo16(owf)];
+                        const T r = fv - (cx * (Ps[ww + 1] + Ps[ww]) + cy * (Ps[o + RW] + Ps[o - RW]) +
                                           cz * (Pu[o] + below[q]) + dd * uc);
                         acc += (double)r * (double)r;
                     }
@@ -466,20 +555,26 @@ __global__ __launch_bounds__(kThreads) void k_sweep3(const LevelItem *__restrict
                 }
                 lds_barrier();
             }
+            // z-y rows of plane s+2, whose coarse planes were staged with s+1
+            zy_rows(s + 2);
             // red nodes of plane s on the tile and its one-node ring
             if (s >= 1 && s <= nz - 2) {
                 const T cx = coef[4 * s], cy = coef[4 * s + 1], invd = coef[4 * s + 3];
-                T *P = S + (s & 3) * kWCells;
+                T *P = S + (s & 3) * SLOT;
                 const T *Fs = F + (s & 3) * kFCells3;
                 const int ps = (par0 + s) & 1;
 #pragma unroll
                 for (int r = 0; r < 2; ++r) {
-                    const int o = ps ? rd_c[1][r] : rd_c[0][r];
-                    if (o < 0) continue;
-                    const int ww = ps ? rd_w[1][r] : rd_w[0][r];
+                    const uint32_t pr = pick(rd0[r], rd1[r], ps);
+                    const int o = lo16(pr);
+                    if (o == kNone) continue;
+                    const int ww = hi16(pr);
                     T fv = (T)0;
-                    if constexpr (HAS_F) fv = Fs[ps ? rd_f[1][r] : rd_f[0][r]];
-                    P[o] = (fv - (cx * (P[ww + 1] + P[ww]) + cy * (P[o + kWX] + P[o - kWX]) + cz * (Pu[o] + Pd[o]))) *
+                    if constexpr (HAS_F) {
+                        const uint32_t fr = pick(rdf0, rdf1, ps);
+                        fv = Fs[r ? hi16(fr) : lo16(fr)];
+                    }
+                    P[o] = (fv - (cx * (P[ww + 1] + P[ww]) + cy * (P[o + RW] + P[o - RW]) + cz * (Pu[o] + Pd[o]))) *
                            invd;
                 }
             }
@@ -488,26 +583,27 @@ __global__ __launch_bounds__(kThreads) void k_sweep3(const LevelItem *__restrict
             const int m = s - 1;
             if (m >= kb && m < ke) {
                 const T cx = coef[4 * m], cy = coef[4 * m + 1], invd = coef[4 * m + 3];
-                T *P = S + (m & 3) * kWCells;
-                const T *Pm = S + ((m - 1) & 3) * kWCells;
+                T *P = S + (m & 3) * SLOT;
+                const T *Pm = S + ((m - 1) & 3) * SLOT;
                 const T *Fm = F + (m & 3) * kFCells3;
                 const int pb = (par0 + m) & 1;
-                const int o = pb ? bk_c[1] : bk_c[0];
-                if (o >= 0) {
-                    const int ww = pb ? bk_w[1] : bk_w[0];
+                const uint32_t pr = pick(bk0, bk1, pb);
+                const int o = lo16(pr);
+                if (o != kNone) {
+                    const int ww = hi16(pr);
                     T fv = (T)0;
-                    if constexpr (HAS_F) fv = Fm[pb ? bk_f[1] : bk_f[0]];
-                    P[o] = (fv - (cx * (P[ww + 1] + P[ww]) + cy * (P[o + kWX] + P[o - kWX]) + cz * (Ps[o] + Pm[o]))) *
+                    if constexpr (HAS_F) fv = Fm[pb ? hi16(bkf) : lo16(bkf)];
+                    P[o] = (fv - (cx * (P[ww + 1] + P[ww]) + cy * (P[o + RW] + P[o - RW]) + cz * (Ps[o] + Pm[o]))) *
                            invd;
                 }
             }
             lds_barrier();
             if (m >= kb && m < ke) {
-                const T *P = S + (m & 3) * kWCells;
+                const T *P = S + (m & 3) * SLOT;
                 MHS_GLOBAL T *ol = uout + sxy * (size_t)m;
 #pragma unroll
                 for (int q = 0; q < kOwn; ++q)
-                    if ((ow_ok >> q) & 1) *(MHS_GLOBAL T *)((MHS_GLOBAL char *)ol + ow_g[q]) = P[ow_c[q]];
+                    if ((ow_ok >> q) & 1) *(MHS_GLOBAL T *)((MHS_GLOBAL char *)ol + ow_g[q]) = P[lo16(ow[q])];
             }
         }
     }
@@ -634,9 +730,12 @@ __global__ __launch_bounds__(kThreads) void k_restrict3(const LevelItem *__restr
 {
     constexpr int kCells = kRWY * kRWX;
     constexpr int kPer = (kCells + kThreads - 1) / kThreads;
-    constexpr int D = kDepth;
-    __shared__ T U[4][kRWY][kRWX];
-    __shared__ T R[kRRY][kRRX];
+    constexpr int kRCells = kRRY * kRRX;
+    constexpr int kRPer = (kRCells + kThreads - 1) / kThreads;
+    constexpr int D = HAS_F ? 3 : kDepth;
+    constexpr int USLOT = kRWY * kRWX;
+    __shared__ T U[4 * USLOT];
+    __shared__ T R[kRCells];
 
     const int tile = xcd_tile();
     const LevelItem *it = items + find_item(items, nitems, tile);
@@ -664,80 +763,120 @@ __global__ __launch_bounds__(kThreads) void k_restrict3(const LevelItem *__restr
     const int tI = tid % kCX, tJ = tid / kCX;
     const int I = I0 + tI, J = J0 + tJ;
     const bool valid = (I <= ncx - 2) && (J <= ncy - 2);
+    constexpr uint32_t es = sizeof(T);
 
-    T pre[D][kPer];
-    // unconditional clamped loads; out-of-array cells zeroed when staged
-    auto fetch = [&](int p, T(&dst)[kPer]) {
+    // ---- per-thread geometry, fixed for the whole z-march ------------------
+    // u window cells staged by this thread
+    int st_l[kPer];
+    uint32_t st_g[kPer];
+    uint32_t st_in = 0;
 #pragma unroll
-        for (int r = 0; r < kPer; ++r) {
-            const int e = min(tid + r * kThreads, kCells - 1);
-            const int w = e / kRWX, c = e - w * kRWX;
-            const int i = min(max(ui0 + c, 0), nx - 1), j = min(max(uj0 + w, 0), ny - 1);
-            dst[r] = u[(size_t)i + (size_t)nx * j + sxy * p];
+    for (int r = 0; r < kPer; ++r) {
+        const int e = tid + r * kThreads;
+        const int ee = min(e, kCells - 1);
+        const int w = ee / kRWX, c = ee - w * kRWX;
+        const int i = ui0 + c, j = uj0 + w;
+        st_l[r] = e < kCells ? ee : -1;
+        st_g[r] = es * (uint32_t)(min(max(i, 0), nx - 1) + nx * min(max(j, 0), ny - 1));
+        if (i < nx && j < ny) st_in |= 1u << r;
+    }
+    // residual cells this thread computes: U centre and R index, interior
+    // flag, byte offset of f
+    uint32_t rc[kRPer];
+    uint32_t rc_g[HAS_F ? kRPer : 1];
+    uint32_t rc_int = 0;
+#pragma unroll
+    for (int r = 0; r < kRPer; ++r) {
+        const int e = tid + r * kThreads;
+        const int ee = min(e, kRCells - 1);
+        const int w = ee / kRRX, c = ee - w * kRRX;
+        const int i = fi0 + c, j = fj0 + w;
+        rc[r] = pk16((w + 1) * kRWX + (c + 1), e < kRCells ? ee : kNone);
+        if constexpr (HAS_F) rc_g[r] = es * (uint32_t)(min(i, nx - 1) + nx * min(j, ny - 1));
+        if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2) rc_int |= 1u << r;
+    }
+    const uint32_t out_g = es * (uint32_t)(min(I, ncx - 1) + ncx * min(J, ncy - 1));
+    const size_t csxy = (size_t)ncx * ncy;
+
+    auto at = [](const MHS_GLOBAL T *base, uint32_t byte_off) -> T {
+        return *(const MHS_GLOBAL T *)((const MHS_GLOBAL char *)base + byte_off);
+    };
+    // register set q holds u plane p and f plane p - 1 (the residual plane
+    // computed in the step that stages u plane p)
+    T pre[D][kPer];
+    T fpre[D][HAS_F ? kRPer : 1];
+    auto fetch = [&](int p, T(&dst)[kPer], T(&fdst)[HAS_F ? kRPer : 1]) {
+        const MHS_GLOBAL T *pl = u + sxy * (size_t)p;
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) dst[r] = at(pl, st_g[r]);
+        if constexpr (HAS_F) {
+            const MHS_GLOBAL T *fl = f + sxy * (size_t)max(p - 1, 0);
+#pragma unroll
+            for (int r = 0; r < kRPer; ++r) fdst[r] = at(fl, rc_g[r]);
         }
     };
     auto stash = [&](int p, const T(&src)[kPer]) {
-        T(*dst)[kRWX] = U[p & 3];
+        T *dst = U + (p & 3) * USLOT;
 #pragma unroll
-        for (int r = 0; r < kPer; ++r) {
-            const int e = tid + r * kThreads;
-            if (e < kCells) {
-                const int w = e / kRWX, c = e - w * kRWX;
-                const int i = ui0 + c, j = uj0 + w;
-                dst[w][c] = (i < nx && j < ny) ? src[r] : (T)0;
-            }
-        }
+        for (int r = 0; r < kPer; ++r)
+            if (st_l[r] >= 0) dst[st_l[r]] = ((st_in >> r) & 1) ? src[r] : (T)0;
     };
 
-    // u planes 2Kb-2 .. 2Ke are read; plane p waits in register set (p - pbase) % D
+    // u planes 2Kb-2 .. 2Ke are read; plane p waits in register set
+    // (p - pbase) % D.  Every step issues the same loads (past the top they
+    // repeat the last plane), so the compiler waits for exactly the oldest
+    // register set.
     const int pbase = 2 * Kb - 2, ptop = 2 * Ke;
 #pragma unroll
-    for (int q = 0; q < D; ++q)
-        if (pbase + q <= ptop) fetch(pbase + q, pre[q]);
+    for (int q = 0; q < D; ++q) fetch(min(pbase + q, ptop), pre[q], fpre[q]);
     stash(pbase, pre[0]);
     stash(pbase + 1, pre[1]);
-    if (pbase + D <= ptop) fetch(pbase + D, pre[0]);
-    if (pbase + D + 1 <= ptop) fetch(pbase + D + 1, pre[1]);
+    fetch(min(pbase + D, ptop), pre[0], fpre[0]);
+    fetch(min(pbase + D + 1, ptop), pre[1], fpre[1]);
     T acc = (T)0;
     const T q4 = (T)0.25, h2 = (T)0.5;
+    const int cw = 2 * tJ + 1, cc = 2 * tI + 1;
     for (int m0 = 2 * Kb - 1; m0 <= 2 * Ke - 1; m0 += D) {
 #pragma unroll
         for (int dd = 0; dd < D; ++dd) {
             const int m = m0 + dd;
             if (m > 2 * Ke - 1) break;
-            // stage plane m+1 into the slot of plane m-3 (read two steps ago)
+            // stage u plane m+1 into the slot of plane m-3 (read two steps
+            // ago); its register set also carries f plane m
             const int ri = (dd + 2) % D;
             stash(m + 1, pre[ri]);
-            if (m + 1 + D <= ptop) fetch(m + 1 + D, pre[ri]);
             lds_barrier();
             {
                 const T cx = coef[4 * m], cy = coef[4 * m + 1], d = coef[4 * m + 2];
-                T(*P)[kRWX] = U[m & 3];
-                T(*Pm)[kRWX] = U[(m - 1) & 3];
-                T(*Pp)[kRWX] = U[(m + 1) & 3];
-                for (int e = tid; e < kRRY * kRRX; e += kThreads) {
-                    const int w = e / kRRX, c = e - w * kRRX;
-                    const int i = fi0 + c, j = fj0 + w;
-                    T r = (T)0;
-                    if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2) {
-                        const int uw = w + 1, uc = c + 1;
+                const T *P = U + (m & 3) * USLOT;
+                const T *Pm = U + ((m - 1) & 3) * USLOT;
+                const T *Pp = U + ((m + 1) & 3) * USLOT;
+#pragma unroll
+                for (int r = 0; r < kRPer; ++r) {
+                    const int ri_ = hi16(rc[r]);
+                    if (ri_ == kNone) continue;
+                    const int o = lo16(rc[r]);
+                    T rv = (T)0;
+                    if ((rc_int >> r) & 1) {
                         T fv = (T)0;
-                        if constexpr (HAS_F) fv = f[(size_t)i + (size_t)nx * j + sxy * m];
-                        r = fv - (cx * (P[uw][uc + 1] + P[uw][uc - 1]) + cy * (P[uw + 1][uc] + P[uw - 1][uc]) +
-                                  cz * (Pp[uw][uc] + Pm[uw][uc]) + d * P[uw][uc]);
+                        if constexpr (HAS_F) fv = fpre[ri][r];
+                        rv = fv - (cx * (P[o + 1] + P[o - 1]) + cy * (P[o + kRWX] + P[o - kRWX]) +
+                                   cz * (Pp[o] + Pm[o]) + d * P[o]);
                     }
-                    R[w][c] = r;
+                    R[ri_] = rv;
                 }
             }
+            fetch(min(m + 1 + D, ptop), pre[ri], fpre[ri]);
             lds_barrier();
-            const int cw = 2 * tJ + 1, cc = 2 * tI + 1;
-            auto row = [&](int w) { return q4 * R[w][cc - 1] + h2 * R[w][cc] + q4 * R[w][cc + 1]; };
+            auto row = [&](int w) {
+                return q4 * R[w * kRRX + cc - 1] + h2 * R[w * kRRX + cc] + q4 * R[w * kRRX + cc + 1];
+            };
             const T s2 = q4 * row(cw - 1) + h2 * row(cw) + q4 * row(cw + 1);
             if (m & 1) {
                 const int Kend = (m - 1) >> 1;
                 if (Kend >= Kb) {
                     acc += q4 * s2;
-                    if (valid) fc[(size_t)I + (size_t)ncx * J + (size_t)ncx * ncy * Kend] = acc;
+                    if (valid) *(MHS_GLOBAL T *)((MHS_GLOBAL char *)(fc + csxy * (size_t)Kend) + out_g) = acc;
                 }
                 acc = q4 * s2;
             } else {
@@ -747,8 +886,7 @@ __global__ __launch_bounds__(kThreads) void k_restrict3(const LevelItem *__restr
     }
 }
 
-// 2D residual + nine-point full weighting.  One coarse node per thread,
-// residual computed into LDS for the fine window.
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_restrict2(const LevelItem *__restrict__ items, int nitems)
 {
@@ -813,7 +951,9 @@ template <bool HAS_E>
 __global__ __launch_bounds__(kThreads) void k_ir3(const LevelItem *__restrict__ items, int nitems)
 {
     constexpr int D = kDepth;
-    __shared__ double S[4][kIWY][kIWX];
+    constexpr int SLOT = kIWY * kIWX;
+    constexpr int kOwnI = kTY * kTX / kThreads;
+    __shared__ double S[4 * SLOT];
     __shared__ double red[kThreads / 64];
     const int tile = xcd_tile();
     const LevelItem *it = items + find_item(items, nitems, tile);
@@ -837,51 +977,74 @@ __global__ __launch_bounds__(kThreads) void k_ir3(const LevelItem *__restrict__ 
     const size_t sxy = (size_t)nx * ny;
     const int tid = threadIdx.x;
 
+    // ---- per-thread geometry, fixed for the whole z-march ------------------
+    // window cells staged: LDS index, element offset of the clamped source,
+    // inside-array and interior flags
+    int st_l[kIPer];
+    uint32_t st_g[kIPer];
+    uint32_t st_in = 0, st_int = 0;
+#pragma unroll
+    for (int r = 0; r < kIPer; ++r) {
+        const int e = tid + r * kThreads;
+        const int ee = min(e, kICells - 1);
+        const int w = ee / kIWX, c = ee - w * kIWX;
+        const int i = i0 - 1 + c, j = j0 - 1 + w;
+        st_l[r] = e < kICells ? ee : -1;
+        st_g[r] = (uint32_t)(min(max(i, 0), nx - 1) + nx * min(max(j, 0), ny - 1));
+        if (i < nx && j < ny) st_in |= 1u << r;
+        if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2) st_int |= 1u << r;
+    }
+    // tile nodes this thread updates
+    int ow_l[kOwnI];
+    uint32_t ow_g[kOwnI];
+    uint32_t ow_ok = 0;
+#pragma unroll
+    for (int q = 0; q < kOwnI; ++q) {
+        const int e = tid + q * kThreads;
+        const int w = 1 + e / kTX, c = 1 + e % kTX;
+        const int i = i0 + c - 1, j = j0 + w - 1;
+        ow_l[q] = w * kIWX + c;
+        ow_g[q] = (uint32_t)(min(i, nx - 1) + nx * min(j, ny - 1));
+        if (i <= nx - 2 && j <= ny - 2) ow_ok |= 1u << q;
+    }
+
     double pre[D][kIPer];
-    float epre[D][kIPer];
+    float epre[D][HAS_E ? kIPer : 1];
     // unconditional clamped loads; the correction is added and out-of-array
     // cells are zeroed when the plane is staged
-    auto fetch = [&](int p, double(&dst)[kIPer], float(&edst)[kIPer]) {
+    auto fetch = [&](int p, double(&dst)[kIPer], float(&edst)[HAS_E ? kIPer : 1]) {
+        const MHS_GLOBAL double *pl = uin + sxy * (size_t)p;
+        const MHS_GLOBAL float *el = e32 + sxy * (size_t)p;
 #pragma unroll
         for (int r = 0; r < kIPer; ++r) {
-            const int e = min(tid + r * kThreads, kICells - 1);
-            const int w = e / kIWX, c = e - w * kIWX;
-            const int i = min(max(i0 - 1 + c, 0), nx - 1), j = min(max(j0 - 1 + w, 0), ny - 1);
-            const size_t idx = (size_t)i + (size_t)nx * j + sxy * p;
-            dst[r] = uin[idx];
-            if constexpr (HAS_E) edst[r] = e32[idx];
+            dst[r] = pl[st_g[r]];
+            if constexpr (HAS_E) edst[r] = el[st_g[r]];
         }
     };
-    auto stash = [&](int p, const double(&src)[kIPer], const float(&esrc)[kIPer]) {
-        double(*dst)[kIWX] = S[p & 3];
+    auto stash = [&](int p, const double(&src)[kIPer], const float(&esrc)[HAS_E ? kIPer : 1]) {
+        double *dst = S + (p & 3) * SLOT;
+        const bool corr = HAS_E && p >= 1 && p <= nz - 2;
 #pragma unroll
         for (int r = 0; r < kIPer; ++r) {
-            const int e = tid + r * kThreads;
-            if (e < kICells) {
-                const int w = e / kIWX, c = e - w * kIWX;
-                const int i = i0 - 1 + c, j = j0 - 1 + w;
-                double v = 0.0;
-                if (i < nx && j < ny) {
-                    v = src[r];
-                    if constexpr (HAS_E) {
-                        if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2 && p >= 1 && p <= nz - 2)
-                            v += (double)esrc[r];
-                    }
-                }
-                dst[w][c] = v;
+            if (st_l[r] < 0) continue;
+            double v = ((st_in >> r) & 1) ? src[r] : 0.0;
+            if constexpr (HAS_E) {
+                if (corr && ((st_int >> r) & 1)) v += (double)esrc[r];
             }
+            dst[st_l[r]] = v;
         }
     };
     double acc = 0.0;
-    // planes kb-1 .. ke are read; plane p waits in register set (p - pbase) % D
+    // planes kb-1 .. ke are read; plane p waits in register set (p - pbase) %
+    // D.  Every step issues the same loads (past the top they repeat the
+    // last plane), so the compiler waits for exactly the oldest register set.
     const int pbase = kb - 1, ptop = ke;
 #pragma unroll
-    for (int q = 0; q < D; ++q)
-        if (pbase + q <= ptop) fetch(pbase + q, pre[q], epre[q]);
+    for (int q = 0; q < D; ++q) fetch(min(pbase + q, ptop), pre[q], epre[q]);
     stash(pbase, pre[0], epre[0]);
     stash(pbase + 1, pre[1], epre[1]);
-    if (pbase + D <= ptop) fetch(pbase + D, pre[0], epre[0]);
-    if (pbase + D + 1 <= ptop) fetch(pbase + D + 1, pre[1], epre[1]);
+    fetch(min(pbase + D, ptop), pre[0], epre[0]);
+    fetch(min(pbase + D + 1, ptop), pre[1], epre[1]);
     for (int m0 = kb; m0 < ke; m0 += D) {
 #pragma unroll
         for (int dd = 0; dd < D; ++dd) {
@@ -890,24 +1053,24 @@ __global__ __launch_bounds__(kThreads) void k_ir3(const LevelItem *__restrict__ 
             // plane m+1 goes into the slot of plane m-3 (read two steps ago)
             const int ri = (dd + 2) % D;
             stash(m + 1, pre[ri], epre[ri]);
-            if (m + 1 + D <= ptop) fetch(m + 1 + D, pre[ri], epre[ri]);
+            fetch(min(m + 1 + D, ptop), pre[ri], epre[ri]);
             lds_barrier();
             const double cx = coef[4 * m], cy = coef[4 * m + 1], d = coef[4 * m + 2];
-            double(*P)[kIWX] = S[m & 3];
-            double(*Pm)[kIWX] = S[(m - 1) & 3];
-            double(*Pp)[kIWX] = S[(m + 1) & 3];
-            for (int e = tid; e < kTY * kTX; e += kThreads) {
-                const int w = 1 + e / kTX, c = 1 + e % kTX;
-                const int i = i0 + c - 1, j = j0 + w - 1;
-                if (i <= nx - 2 && j <= ny - 2) {
-                    const size_t idx = (size_t)i + (size_t)nx * j + sxy * m;
-                    const double uc = P[w][c];
-                    const double r = -(cx * (P[w][c + 1] + P[w][c - 1]) + cy * (P[w + 1][c] + P[w - 1][c]) +
-                                       cz * (Pp[w][c] + Pm[w][c]) + d * uc);
-                    if constexpr (HAS_E) uout[idx] = uc;
-                    r32[idx] = (float)r;
-                    acc += r * r;
-                }
+            const double *P = S + (m & 3) * SLOT;
+            const double *Pm = S + ((m - 1) & 3) * SLOT;
+            const double *Pp = S + ((m + 1) & 3) * SLOT;
+            MHS_GLOBAL double *ul = uout + sxy * (size_t)m;
+            MHS_GLOBAL float *rl = r32 + sxy * (size_t)m;
+#pragma unroll
+            for (int q = 0; q < kOwnI; ++q) {
+                if (!((ow_ok >> q) & 1)) continue;
+                const int o = ow_l[q];
+                const double uc = P[o];
+                const double r = -(cx * (P[o + 1] + P[o - 1]) + cy * (P[o + kIWX] + P[o - kIWX]) +
+                                   cz * (Pp[o] + Pm[o]) + d * uc);
+                if constexpr (HAS_E) ul[ow_g[q]] = uc;
+                rl[ow_g[q]] = (float)r;
+                acc += r * r;
             }
         }
     }
