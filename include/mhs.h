@@ -115,6 +115,21 @@ const char *mhs_last_error(void);
  * (MHS_ERR_GRID for a bad axis). */
 int mhs_workspace_bytes(const mhs_grid *grid, int32_t precisions, size_t *bytes);
 
+/* Host-only check of a model against a grid (no device work).  Every
+ * interior plane must have xi < 1 (ellipticity of (8), Section 2.1) and
+ * alpha^2 must lie below the smallest eigenvalue lambda_0 of
+ * -[(1 - xi)(d2x + d2y) + d2z] on the grid, so that the discrete problem is
+ * definite.  Coarse grids under-resolve the lowest mode, whose eigenvalue
+ * lambda_l drops as the grid coarsens: the 3D hierarchy stops above the
+ * first level with lambda_l - alpha^2 < (lambda_0 - alpha^2) / 2 (there the
+ * coarse correction would over-correct that mode more than twofold) and
+ * solves its parent exactly (at most 512 unknowns).  *lambda_min (optional)
+ * receives lambda_0, *levels (optional) the number of 3D levels the solve
+ * will use.  Returns MHS_OK, MHS_ERR_GRID, MHS_ERR_INVALID_ARG,
+ * MHS_ERR_NOT_ELLIPTIC or MHS_ERR_INDEFINITE (alpha^2 >= lambda_0, or too
+ * close to resonance for a coarse grid of at most 512 unknowns). */
+int mhs_check_model(const mhs_grid *grid, const mhs_model *model, double *lambda_min, int32_t *levels);
+
 /* Create a plan on the current HIP device over the caller's workspace
  * (d_workspace: device pointer, 256-byte aligned, >= mhs_workspace_bytes).
  * Clears the workspace (synchronously).  The hierarchy coarsens every axis

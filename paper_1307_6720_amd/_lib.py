@@ -86,6 +86,7 @@ def lib():
         "mhs_version": (i32, []),
         "mhs_last_error": (C.c_char_p, []),
         "mhs_workspace_bytes": (C.c_int, [P(Grid), i32, P(C.c_size_t)]),
+        "mhs_check_model": (C.c_int, [P(Grid), P(Model), P(dbl), P(i32)]),
         "mhs_plan_create": (C.c_int, [P(Grid), i32, vp, C.c_size_t, P(vp)]),
         "mhs_plan_destroy": (C.c_int, [vp]),
         "mhs_plan_levels": (C.c_int, [vp, i32, P(i32)]),

@@ -37,9 +37,17 @@ int fail(int code, const char *fmt, ...)
 
 constexpr size_t kAlign = 256;
 constexpr size_t kStagingBytes = 1 << 20;
-// Workgroups a stencil launch aims for: enough to keep every CU busy with
-// several resident groups while keeping each group's z-march short.
-constexpr int kTargetGroups = 2048;
+// Workgroups a stencil launch aims for: about as many as fit on the chip at
+// once (4-5 per CU on 256 CUs), so that one round of resident groups covers
+// the grid with long z-marches (fewer re-read halo planes, no tail round).
+// The field recovery, whose groups hold more LDS, prefers two rounds.
+#ifndef MHS_TARGET_GROUPS
+#define MHS_TARGET_GROUPS 1024
+#endif
+constexpr int kTargetGroups = MHS_TARGET_GROUPS;
+constexpr int kFieldsTargetGroups = 2048;
+// Largest coarsest grid (unknowns) a model may cut the 3D hierarchy to.
+constexpr int kMaxCutCoarse = 512;
 
 // LDS bytes of a bottom solver starting at level l: u and f of every level
 // from l down with their coefficient tables (4 nz each), plus a residual
@@ -51,9 +59,9 @@ size_t bottom_lds(const Hierarchy &h, int l)
     return 8 * (n + h.lv[l].N);
 }
 
-int chunk(int planes, int xy_tiles, int cap)
+int chunk(int planes, int xy_tiles, int cap, int target = kTargetGroups)
 {
-    const long want = ((long)planes * xy_tiles + kTargetGroups - 1) / kTargetGroups;
+    const long want = ((long)planes * xy_tiles + target - 1) / target;
     return (int)std::max(1L, std::min((long)cap, want));
 }
 
@@ -128,6 +136,14 @@ int build_geometry(Hierarchy &h, const int n0[3], const double len[3], bool plan
         }
     if (h.b < 0) return fail(MHS_ERR_GRID, "coarsest grid too large for the LDS bottom solver");
     h.lds_bytes = (int)bottom_lds(h, h.b);
+    h.Lgeo = h.L;
+    h.bgeo = h.b;
+    h.mcap = h.m;
+    for (int l = 1; l < L; ++l) {
+        const Level &q = h.lv[l];
+        const int mq = (q.n[0] - 2) * (q.n[1] - 2) * (planar ? 1 : q.n[2] - 2);
+        if (mq <= kMaxCutCoarse) h.mcap = std::max(h.mcap, mq);
+    }
     for (int l = 0; l < L; ++l) {
         Level &lv = h.lv[l];
         if (planar) {
@@ -186,7 +202,7 @@ void carve_hierarchy(Hierarchy &h, Carver &cv, int paths)
         lv.coef64 = cv.take<double>(4 * (size_t)lv.n[2]);
         if (paths & 2) lv.coef32 = cv.take<float>(4 * (size_t)lv.n[2]);
     }
-    h.minv = cv.take<double>((size_t)h.m * h.m);
+    h.minv = cv.take<double>((size_t)h.mcap * h.mcap);
     h.npart = l0.sweep_tiles();
     h.partials = cv.take<double>(h.npart);
 }
@@ -300,18 +316,111 @@ int coarse_inverse(const Hierarchy &h, const std::vector<double> &coef, double c
 // Lower bound of the smallest eigenvalue of -[(1 - xi)(d2x + d2y) + d2z] on
 // level l: min_k (1 - xi_k) * lam_h + lam_z, each term the smallest Dirichlet
 // eigenvalue of its one-dimensional operator.
-double definite_bound(const Hierarchy &h, int l, const double *xi, const double len[3])
+// Smallest eigenvalue of -[(1 - xi(z)) (d2x + d2y) + d2z] on the interior
+// unknowns of level l (the operator of (8) without the alpha^2 term).  The
+// operator separates: an in-plane sine mode of eigenvalue lam turns it into
+// the symmetric tridiagonal -d2z + lam diag(1 - xi_k), whose eigenvalues
+// grow with lam (1 - xi > 0), so the minimum sits at the smallest in-plane
+// eigenvalue.  That tridiagonal eigenvalue is found by bisection with
+// Sturm counts (the number of negative pivots of T - x I).
+double level_lambda_min(const Hierarchy &h, int l, const double *xi, const double len[3])
 {
     const Level &lv = h.lv[l];
-    auto lam1 = [](int n, double hh, double length) {
+    auto lam1 = [](double hh, double length) {
         const double s = std::sin(3.14159265358979323846 * hh / (2.0 * length));
         return 4.0 / (hh * hh) * s * s;
     };
-    const double lh = lam1(lv.n[0], lv.h[0], len[0]) + lam1(lv.n[1], lv.h[1], len[1]);
-    const double lz = lam1(lv.n[2], lv.h[2], len[2]);
-    double mn = 1.0;
-    for (int k = 1; k < lv.n[2] - 1; ++k) mn = std::min(mn, 1.0 - xi[(size_t)k << l]);
-    return mn * lh + lz;
+    const double lxy = lam1(lv.h[0], len[0]) + lam1(lv.h[1], len[1]);
+    const int m = lv.n[2] - 2;
+    const double iz2 = 1.0 / (lv.h[2] * lv.h[2]);
+    std::vector<double> a((size_t)m);
+    double hi = 0.0;
+    for (int q = 0; q < m; ++q) {
+        a[(size_t)q] = 2.0 * iz2 + (1.0 - xi[(size_t)(q + 1) << l]) * lxy;
+        hi = q == 0 ? a[0] : std::min(hi, a[(size_t)q]); // Rayleigh quotient of a unit vector
+    }
+    const double b2 = iz2 * iz2;
+    auto below = [&](double x) { // eigenvalues < x
+        int cnt = 0;
+        double d = 1.0;
+        for (int q = 0; q < m; ++q) {
+            d = (a[(size_t)q] - x) - (q ? b2 / d : 0.0);
+            if (d == 0.0) d = -1e-300;
+            if (d < 0.0) ++cnt;
+        }
+        return cnt;
+    };
+    double lo = 0.0;
+    for (int it = 0; it < 200 && hi - lo > 1e-14 * hi; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (below(mid) >= 1)
+            hi = mid;
+        else
+            lo = mid;
+    }
+    return lo;
+}
+
+// Use levels 0..L-1 of a hierarchy: the bottom solver starts at the first
+// level whose bottom part fits the LDS, and the coarsest grid is L-1.
+int set_depth(Hierarchy &h, int L)
+{
+    if (L < 2 || L > h.Lgeo) return fail(MHS_ERR_INDEFINITE, "no usable multigrid hierarchy");
+    Hierarchy t = h; // decide on a copy; commit only a consistent depth
+    t.L = L;
+    const Level &c = t.lv[L - 1];
+    t.m = (c.n[0] - 2) * (c.n[1] - 2) * (t.planar ? 1 : c.n[2] - 2);
+    if (t.m > t.mcap)
+        return fail(MHS_ERR_INDEFINITE,
+                    "alpha^2 is too close to resonance: the coarsest grid that still represents the lowest mode "
+                    "has %d unknowns (max %d)", t.m, t.mcap);
+    t.b = -1;
+    for (int l = 1; l < L; ++l)
+        if (bottom_lds(t, l) <= (size_t)kBottomLdsMax) {
+            t.b = l;
+            break;
+        }
+    if (t.b < 0 || t.b > t.bgeo) return fail(MHS_ERR_INDEFINITE, "coarsest usable grid too large for the bottom solver");
+    h.L = t.L;
+    h.m = t.m;
+    h.b = t.b;
+    h.lds_bytes = (int)bottom_lds(t, t.b);
+    return MHS_OK;
+}
+
+// Depth of the 3D hierarchy for a model (a reading: the paper is silent on
+// the coarse grids).  The operator of (8) must be definite on the grid:
+// alpha^2 below the smallest eigenvalue lambda_0 of
+// -[(1 - xi)(d2x + d2y) + d2z].  Coarse grids under-resolve the lowest mode,
+// so their smallest eigenvalue lambda_l drops as the grid coarsens; a coarse
+// correction built on a level with lambda_l - alpha^2 below half of
+// lambda_0 - alpha^2 over-corrects that mode more than twofold and the
+// cycle stops contracting (near resonance).  The hierarchy therefore stops
+// above the first such level, whose parent is solved exactly.
+constexpr double kResonanceRatio = 0.5;
+
+int model_depth(const Hierarchy &h, const mhs_grid &g, const mhs_model *model, int *depth, double *lambda0)
+{
+    const double len[3] = {g.lx, g.ly, g.lz};
+    const double a2 = model->alpha * model->alpha;
+    int L = h.Lgeo;
+    double gap0 = 0.0;
+    for (int l = 0; l < h.Lgeo; ++l) {
+        const double lmin = level_lambda_min(h, l, model->xi, len);
+        if (l == 0) {
+            if (lambda0) *lambda0 = lmin;
+            if (!(a2 < lmin))
+                return fail(MHS_ERR_INDEFINITE, "alpha^2 = %g is not below the smallest eigenvalue %g of (8) on the grid",
+                            a2, lmin);
+            gap0 = lmin - a2;
+        } else if (!(lmin - a2 >= kResonanceRatio * gap0)) {
+            L = l;
+            break;
+        }
+    }
+    if (L < 2) return fail(MHS_ERR_INDEFINITE, "alpha^2 = %g is too close to resonance for any coarse grid", a2);
+    *depth = L;
+    return MHS_OK;
 }
 
 int upload_model(mhs_plan *p, const mhs_model *model, hipStream_t s)
@@ -321,13 +430,10 @@ int upload_model(mhs_plan *p, const mhs_model *model, hipStream_t s)
     const bool same = p->cache.valid && p->cache.alpha == model->alpha &&
                       std::equal(p->cache.xi.begin(), p->cache.xi.end(), model->xi);
     if (same) return MHS_OK;
-    const double len[3] = {p->grid.lx, p->grid.ly, p->grid.lz};
-    for (int l = 0; l < h.L; ++l) {
-        const double bound = definite_bound(h, l, model->xi, len);
-        if (!(model->alpha * model->alpha < bound))
-            return fail(MHS_ERR_INDEFINITE, "alpha^2 = %g is not below the spectral bound %g of level %d", model->alpha * model->alpha,
-                        bound, l);
-    }
+    int depth = 0;
+    int st0 = model_depth(h, p->grid, model, &depth, nullptr);
+    if (st0) return st0;
+    if ((st0 = set_depth(h, depth))) return st0;
     std::vector<double> tab, minv;
     std::vector<float> t32;
     for (int l = 0; l < h.L; ++l) {
@@ -677,7 +783,7 @@ FieldsItem fields_item(const mhs_plan *p, const mhs_model *model, const double *
     fi.nz = nz;
     fi.ntx = ceil_div(nx, kTX);
     fi.nty = ceil_div(ny, kFY);
-    fi.kz = chunk(nz, fi.ntx * fi.nty, kKZ);
+    fi.kz = chunk(nz, fi.ntx * fi.nty, kKZ, kFieldsTargetGroups);
     fi.ntz = ceil_div(nz, fi.kz);
     fi.tile_base = 0;
     return fi;
@@ -907,6 +1013,20 @@ int mhs_workspace_bytes(const mhs_grid *grid, int32_t precisions, size_t *bytes)
     st = geometry(&tmp, grid);
     if (st) return st;
     *bytes = carve_plan(&tmp, nullptr, precisions);
+    return MHS_OK;
+}
+
+int mhs_check_model(const mhs_grid *grid, const mhs_model *model, double *lambda_min, int32_t *levels)
+{
+    int st = check_grid(grid);
+    if (st) return st;
+    mhs_plan tmp;
+    if ((st = geometry(&tmp, grid))) return st;
+    if ((st = validate_model(&tmp, model, false))) return st;
+    int depth = 0;
+    if ((st = model_depth(tmp.h3, *grid, model, &depth, lambda_min))) return st;
+    if ((st = set_depth(tmp.h3, depth))) return st;
+    if (levels) *levels = depth;
     return MHS_OK;
 }
 

@@ -21,8 +21,14 @@ constexpr int kMaxLevels = 16;
 #ifndef MHS_TILE_Y
 #define MHS_TILE_Y 8
 #endif
+#ifndef MHS_RING_DEPTH_F
+#define MHS_RING_DEPTH_F 2
+#endif
+#ifndef MHS_SWEEP_ATTR
+#define MHS_SWEEP_ATTR
+#endif
 #ifndef MHS_RING_DEPTH
-#define MHS_RING_DEPTH 4
+#define MHS_RING_DEPTH 2
 #endif
 constexpr int kTX = 64;
 constexpr int kTY = MHS_TILE_Y;
@@ -30,6 +36,7 @@ constexpr int kKZ = 32;
 constexpr int kThreads = 256;
 // planes of HBM loads a marching kernel keeps in flight (register ring)
 constexpr int kDepth = MHS_RING_DEPTH;
+constexpr int kDepthF = MHS_RING_DEPTH_F; // with right-hand side or prolongation
 // 3D residual + restriction: kCX x kCY coarse nodes per workgroup, marching
 // kKC coarse planes.
 constexpr int kCX = 32;

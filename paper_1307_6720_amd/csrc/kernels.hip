@@ -187,7 +187,7 @@ __device__ __forceinline__ uint32_t pick(uint32_t a, uint32_t b, int flag)
 constexpr int kNone = 0xffff; // "no node" marker in a packed index
 
 template <typename T, int FLAGS>
-__global__ __launch_bounds__(kThreads) void k_sweep3(const LevelItem *__restrict__ items, int nitems)
+__global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelItem *__restrict__ items, int nitems)
 {
     constexpr bool HAS_F = (FLAGS & kHasF) != 0;
     constexpr bool ZERO_IN = (FLAGS & kZeroIn) != 0;
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep3(const LevelItem *__restrict
     constexpr bool PROLONG = (FLAGS & kProlong) != 0;
     // register-ring depth (planes of loads in flight); shallower when every
     // plane also carries right-hand-side or coarse-correction data
-    constexpr int D = (HAS_F || PROLONG) ? 3 : kDepth;
+    constexpr int D = (HAS_F || PROLONG) ? kDepthF : kDepth;
     constexpr int kCWPlanes = PROLONG ? 2 : 1;
     constexpr int kFSlots = HAS_F ? 4 : 1;
     constexpr int kCPlane = kCWX * kCWY;
@@ -1285,9 +1285,9 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const FinalizeItem *__res
 // ============================================================================
 // Field recovery (Section 2.2): B by central differences of P, p and rho from
 // (9) and (10).  A workgroup owns kTX x kFY nodes of `kz` planes; P planes
-// are staged in LDS with a two-node halo (four planes in flight, the next one
-// prefetched into registers) and Bz planes with a one-node halo (three in
-// flight).  At step m the workgroup forms Bz on plane m+1, then writes all
+// are staged in LDS with a two-node halo (four planes resident, the next ones
+// prefetched into a register ring) and Bz planes with a one-node halo (three
+// resident).  At step m the workgroup forms Bz on plane m+1, then writes all
 // five fields of plane m.  Side and top faces: B = 0.  Base plane:
 // one-sided second-order z-derivatives.
 // ============================================================================
@@ -1297,11 +1297,19 @@ constexpr int kFBX = kTX + 2;
 constexpr int kFBY = kFY + 2;
 constexpr int kFCells = kFPX * kFPY;
 constexpr int kFPer = (kFCells + kThreads - 1) / kThreads;
+constexpr int kDepthFields = 2; // P planes of loads in flight
 
 __global__ __launch_bounds__(kThreads) void k_fields(const FieldsItem *__restrict__ items, int nitems)
 {
-    __shared__ double SP[4][kFPY][kFPX];
-    __shared__ double SB[3][kFBY][kFBX];
+    constexpr int D = kDepthFields;
+    constexpr int PSLOT = kFPY * kFPX;
+    constexpr int BSLOT = kFBY * kFBX;
+    constexpr int kBCells = kFBY * kFBX;
+    constexpr int kBPer = (kBCells + kThreads - 1) / kThreads;
+    constexpr int kOut = kFY * kTX / kThreads;
+    static_assert(kFY * kTX % kThreads == 0, "whole output nodes per thread");
+    __shared__ double SP[4 * PSLOT];
+    __shared__ double SB[3 * BSLOT];
     const int tile = xcd_tile();
     const FieldsItem *it = items + find_item(items, nitems, tile);
     const MHS_GLOBAL double *__restrict__ P = gin<double>(it->P);
@@ -1327,112 +1335,156 @@ __global__ __launch_bounds__(kThreads) void k_fields(const FieldsItem *__restric
     MHS_GLOBAL double *__restrict__ op = gout<double>(it->p);
     MHS_GLOBAL double *__restrict__ orho = gout<double>(it->rho);
 
-    double pre[kFPer];
+    // ---- per-thread geometry, fixed for the whole z-march ------------------
+    // P window cells staged (two-node halo)
+    int st_l[kFPer];
+    uint32_t st_g[kFPer];
+    uint32_t st_in = 0;
+#pragma unroll
+    for (int r = 0; r < kFPer; ++r) {
+        const int e = tid + r * kThreads;
+        const int ee = min(e, kFCells - 1);
+        const int w = ee / kFPX, c = ee - w * kFPX;
+        const int i = i0 - 2 + c, j = j0 - 2 + w;
+        st_l[r] = e < kFCells ? ee : -1;
+        st_g[r] = (uint32_t)(min(max(i, 0), nx - 1) + nx * min(max(j, 0), ny - 1));
+        if (i >= 0 && i < nx && j >= 0 && j < ny) st_in |= 1u << r;
+    }
+    // Bz cells formed (one-node halo): SB index and SP centre; interior flag
+    uint32_t bz_i[kBPer];
+    uint32_t bz_int = 0;
+#pragma unroll
+    for (int r = 0; r < kBPer; ++r) {
+        const int e = tid + r * kThreads;
+        const int ee = min(e, kBCells - 1);
+        const int w = ee / kFBX, c = ee - w * kFBX;
+        const int i = i0 - 1 + c, j = j0 - 1 + w;
+        bz_i[r] = pk16(e < kBCells ? ee : kNone, (w + 1) * kFPX + (c + 1));
+        if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2) bz_int |= 1u << r;
+    }
+    // output nodes: nodes past the array edge are redirected to the nearest
+    // edge node, which they recompute identically, so every lane stores
+    uint32_t o_i[kOut];
+    uint32_t o_g[kOut];
+    uint32_t o_int = 0;
+#pragma unroll
+    for (int q = 0; q < kOut; ++q) {
+        const int e = tid + q * kThreads;
+        const int i = min(i0 + e % kTX, nx - 1), j = min(j0 + e / kTX, ny - 1);
+        const int w = j - j0, c = i - i0;
+        o_i[q] = pk16((w + 2) * kFPX + (c + 2), (w + 1) * kFBX + (c + 1));
+        o_g[q] = (uint32_t)(i + nx * j);
+        if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2) o_int |= 1u << q;
+    }
+
+    double pre[D][kFPer];
     // unconditional clamped loads; out-of-array cells zeroed when staged
-    auto fetch = [&](int p) {
+    auto fetch = [&](int p, double(&dst)[kFPer]) {
+        const MHS_GLOBAL double *pl = P + sxy * (size_t)min(p, nz - 1);
 #pragma unroll
-        for (int r = 0; r < kFPer; ++r) {
-            const int e = min(tid + r * kThreads, kFCells - 1);
-            const int w = e / kFPX, c = e - w * kFPX;
-            const int i = min(max(i0 - 2 + c, 0), nx - 1), j = min(max(j0 - 2 + w, 0), ny - 1);
-            pre[r] = P[(size_t)i + (size_t)nx * j + sxy * p];
-        }
+        for (int r = 0; r < kFPer; ++r) dst[r] = pl[st_g[r]];
     };
-    auto stash = [&](int p) {
-        double(*dst)[kFPX] = SP[p & 3];
+    auto stash = [&](int p, const double(&src)[kFPer]) {
+        double *dst = SP + (p & 3) * PSLOT;
 #pragma unroll
-        for (int r = 0; r < kFPer; ++r) {
-            const int e = tid + r * kThreads;
-            if (e < kFCells) {
-                const int w = e / kFPX, c = e - w * kFPX;
-                const int i = i0 - 2 + c, j = j0 - 2 + w;
-                dst[w][c] = (i >= 0 && i < nx && j >= 0 && j < ny) ? pre[r] : 0.0;
-            }
-        }
+        for (int r = 0; r < kFPer; ++r)
+            if (st_l[r] >= 0) dst[st_l[r]] = ((st_in >> r) & 1) ? src[r] : 0.0;
     };
     // Bz = -(d2x + d2y) P on plane p, one-node ring; 0 on faces and the top
     auto bz_plane = [&](int p) {
-        double(*src)[kFPX] = SP[p & 3];
-        double(*dst)[kFBX] = SB[p % 3];
-        for (int e = tid; e < kFBY * kFBX; e += kThreads) {
-            const int w = e / kFBX, c = e - w * kFBX;
-            const int i = i0 - 1 + c, j = j0 - 1 + w;
+        const double *src = SP + (p & 3) * PSLOT;
+        double *dst = SB + (p % 3) * BSLOT;
+        const bool plane_ok = p <= nz - 2;
+#pragma unroll
+        for (int r = 0; r < kBPer; ++r) {
+            const int l = lo16(bz_i[r]);
+            if (l == kNone) continue;
+            const int s = hi16(bz_i[r]);
             double v = 0.0;
-            if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2 && p <= nz - 2) {
-                const int pw = w + 1, pc = c + 1;
-                v = -((src[pw][pc + 1] - 2.0 * src[pw][pc] + src[pw][pc - 1]) * ix2 +
-                      (src[pw + 1][pc] - 2.0 * src[pw][pc] + src[pw - 1][pc]) * iy2);
-            }
-            dst[w][c] = v;
+            if (plane_ok && ((bz_int >> r) & 1))
+                v = -((src[s + 1] - 2.0 * src[s] + src[s - 1]) * ix2 + (src[s + kFPX] - 2.0 * src[s] + src[s - kFPX]) * iy2);
+            dst[l] = v;
         }
     };
 
-    // planes kept: P m-1..m+1 (m+2 prefetched), Bz m-1..m+1.  The base plane
-    // needs P 0..2 and Bz 0..2 instead.
-    const int first = (kb == 0) ? 0 : kb - 1;
-    for (int p = first; p <= min(first + 2, nz - 1); ++p) {
-        fetch(p);
-        stash(p);
-    }
-    lds_barrier();
-    for (int p = first; p <= min(first + 1, nz - 1); ++p) bz_plane(p);
-    for (int m = kb; m < ke; ++m) {
-        // P(m+1) is resident; prefetch the next P plane and form Bz on the
-        // highest plane this step reads (plane 2 for the base plane)
-        const int nxt = (m == 0) ? 3 : m + 2;
-        const int hb = (m == 0) ? 2 : m + 1;
-        const bool pf = (nxt <= nz - 1) && (m + 1 < ke);
-        if (pf) fetch(nxt);
-        if (hb <= nz - 1) bz_plane(hb);
-        lds_barrier();
-        const double xi = tab[m], dxi = tab[nz + m], pb = tab[2 * nz + m], rhob = tab[3 * nz + m];
-        for (int e = tid; e < kFY * kTX; e += kThreads) {
-            const int w = e / kTX, c = e % kTX;
-            const int i = i0 + c, j = j0 + w;
-            if (i >= nx || j >= ny) continue;
-            const size_t idx = (size_t)i + (size_t)nx * j + sxy * m;
-            double bx = 0.0, by = 0.0, bz = 0.0, p = pb, rho = rhob;
-            if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2 && m <= nz - 2) {
-                const int pw = w + 2, pc = c + 2, bw = w + 1, bc = c + 1;
-                double(*Pc)[kFPX] = SP[m & 3];
-                double(*Bc)[kFBX] = SB[m % 3];
-                double dzp_xp, dzp_xm, dzp_yp, dzp_ym, dbzz;
-                if (m >= 1) {
-                    double(*Pu)[kFPX] = SP[(m + 1) & 3];
-                    double(*Pd)[kFPX] = SP[(m - 1) & 3];
-                    dzp_xp = (Pu[pw][pc + 1] - Pd[pw][pc + 1]) * i2dz;
-                    dzp_xm = (Pu[pw][pc - 1] - Pd[pw][pc - 1]) * i2dz;
-                    dzp_yp = (Pu[pw + 1][pc] - Pd[pw + 1][pc]) * i2dz;
-                    dzp_ym = (Pu[pw - 1][pc] - Pd[pw - 1][pc]) * i2dz;
-                    dbzz = (SB[(m + 1) % 3][bw][bc] - SB[(m + 2) % 3][bw][bc]) * i2dz;
-                } else {
-                    double(*P1)[kFPX] = SP[1];
-                    double(*P2)[kFPX] = SP[2];
-                    auto one = [&](int a, int bb) { return (-3.0 * Pc[a][bb] + 4.0 * P1[a][bb] - P2[a][bb]) * i2dz; };
-                    dzp_xp = one(pw, pc + 1);
-                    dzp_xm = one(pw, pc - 1);
-                    dzp_yp = one(pw + 1, pc);
-                    dzp_ym = one(pw - 1, pc);
-                    dbzz = (-3.0 * SB[0][bw][bc] + 4.0 * SB[1][bw][bc] - SB[2][bw][bc]) * i2dz;
-                }
-                bx = alpha * (Pc[pw + 1][pc] - Pc[pw - 1][pc]) * i2dy + (dzp_xp - dzp_xm) * i2dx;
-                by = -alpha * (Pc[pw][pc + 1] - Pc[pw][pc - 1]) * i2dx + (dzp_yp - dzp_ym) * i2dy;
-                bz = Bc[bw][bc];
-                const double dbzx = (Bc[bw][bc + 1] - Bc[bw][bc - 1]) * i2dx;
-                const double dbzy = (Bc[bw + 1][bc] - Bc[bw - 1][bc]) * i2dy;
-                const double bz2 = bz * bz;
-                p = pb - xi * bz2 / (2.0 * mu0);
-                rho = rhob + (dxi * bz2 / (2.0 * mu0) + xi * (bx * dbzx + by * dbzy + bz * dbzz) / mu0) / g;
-            }
-            oBx[idx] = bx;
-            oBy[idx] = by;
-            oBz[idx] = bz;
-            op[idx] = p;
-            orho[idx] = rho;
+    // P planes q0 .. q0+2 staged and Bz q0 .. q0+1 formed up front (the
+    // base plane also needs Bz on plane 2); then step m forms Bz(m+1),
+    // writes plane m and stages P(m+2) from the register ring, which runs D
+    // planes ahead.
+    const int q0 = (kb == 0) ? 0 : kb - 1;
+    {
+        double tmp[kFPer];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            fetch(q0 + q, tmp);
+            stash(q0 + q, tmp);
         }
-        // P(nxt) replaces the slot of plane nxt-4, last read two steps ago
-        if (pf) stash(nxt);
-        lds_barrier();
+    }
+    // register set d holds plane kb + 2 + d (+ D per round); every step
+    // refills its set unconditionally (past the top it repeats the last
+    // plane), so the compiler can wait for exactly the oldest set
+#pragma unroll
+    for (int q = 0; q < D; ++q) fetch(kb + 2 + q, pre[q]);
+    lds_barrier();
+    bz_plane(q0);
+    bz_plane(q0 + 1);
+    if (kb == 0) bz_plane(2);
+    for (int m0 = kb; m0 < ke; m0 += D) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const int m = m0 + d;
+            if (m >= ke) break;
+            if (m + 1 >= (kb == 0 ? 3 : q0 + 2)) bz_plane(min(m + 1, nz - 1));
+            lds_barrier();
+            const double xi = tab[m], dxi = tab[nz + m], pb = tab[2 * nz + m], rhob = tab[3 * nz + m];
+            const double *Pc = SP + (m & 3) * PSLOT;
+            const double *Bc = SB + (m % 3) * BSLOT;
+            const bool plane_ok = m <= nz - 2;
+#pragma unroll
+            for (int q = 0; q < kOut; ++q) {
+                double bx = 0.0, by = 0.0, bz = 0.0, p = pb, rho = rhob;
+                if (plane_ok && ((o_int >> q) & 1)) {
+                    const int pc = lo16(o_i[q]), bc = hi16(o_i[q]);
+                    double dzp_xp, dzp_xm, dzp_yp, dzp_ym, dbzz;
+                    if (m >= 1) {
+                        const double *Pu = SP + ((m + 1) & 3) * PSLOT;
+                        const double *Pd = SP + ((m - 1) & 3) * PSLOT;
+                        dzp_xp = (Pu[pc + 1] - Pd[pc + 1]) * i2dz;
+                        dzp_xm = (Pu[pc - 1] - Pd[pc - 1]) * i2dz;
+                        dzp_yp = (Pu[pc + kFPX] - Pd[pc + kFPX]) * i2dz;
+                        dzp_ym = (Pu[pc - kFPX] - Pd[pc - kFPX]) * i2dz;
+                        dbzz = (SB[((m + 1) % 3) * BSLOT + bc] - SB[((m + 2) % 3) * BSLOT + bc]) * i2dz;
+                    } else {
+                        const double *P1 = SP + PSLOT;
+                        const double *P2 = SP + 2 * PSLOT;
+                        auto one = [&](int a) { return (-3.0 * Pc[a] + 4.0 * P1[a] - P2[a]) * i2dz; };
+                        dzp_xp = one(pc + 1);
+                        dzp_xm = one(pc - 1);
+                        dzp_yp = one(pc + kFPX);
+                        dzp_ym = one(pc - kFPX);
+                        dbzz = (-3.0 * SB[bc] + 4.0 * SB[BSLOT + bc] - SB[2 * BSLOT + bc]) * i2dz;
+                    }
+                    bx = alpha * (Pc[pc + kFPX] - Pc[pc - kFPX]) * i2dy + (dzp_xp - dzp_xm) * i2dx;
+                    by = -alpha * (Pc[pc + 1] - Pc[pc - 1]) * i2dx + (dzp_yp - dzp_ym) * i2dy;
+                    bz = Bc[bc];
+                    const double dbzx = (Bc[bc + 1] - Bc[bc - 1]) * i2dx;
+                    const double dbzy = (Bc[bc + kFBX] - Bc[bc - kFBX]) * i2dy;
+                    const double bz2 = bz * bz;
+                    p = pb - xi * bz2 / (2.0 * mu0);
+                    rho = rhob + (dxi * bz2 / (2.0 * mu0) + xi * (bx * dbzx + by * dbzy + bz * dbzz) / mu0) / g;
+                }
+                const size_t idx = (size_t)o_g[q] + sxy * (size_t)m;
+                oBx[idx] = bx;
+                oBy[idx] = by;
+                oBz[idx] = bz;
+                op[idx] = p;
+                orho[idx] = rho;
+            }
+            // P(m+2) replaces the slot of plane m-2, last read a step ago
+            if (m + 2 >= q0 + 3) stash(m + 2, pre[d]);
+            fetch(m + 2 + D, pre[d]);
+            lds_barrier();
+        }
     }
 }
 

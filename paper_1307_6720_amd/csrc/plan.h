@@ -33,8 +33,10 @@ struct Level {
 
 struct Hierarchy {
     bool planar = false;
-    int L = 0; // levels
+    int L = 0; // levels in use (the 3D depth may be cut per model)
     int b = 0; // first level handled by the bottom solver
+    int Lgeo = 0, bgeo = 0; // geometric depth and bottom level (buffers are carved for these)
+    int mcap = 0;           // largest coarsest-grid size the inverse buffer holds
     Level lv[kMaxLevels];
     int lds_bytes = 0;      // bottom solver LDS footprint
     double *minv = nullptr; // device m x m

@@ -85,6 +85,19 @@ def workspace_bytes(grid, precisions=PREC_FP64 | PREC_MIXED):
     return n.value
 
 
+def check_model(grid, model):
+    """Host-only validation of a model on a grid (no device needed).
+    Returns (lambda_0, levels): the smallest eigenvalue of
+    -[(1-xi)(d2x+d2y)+d2z] on the grid, and the number of 3D multigrid levels
+    the solve uses.  Raises MHSError (NOT_ELLIPTIC, INDEFINITE, ...)."""
+    g = _grid(grid)
+    m = _ModelArgs.of(model)
+    lam = C.c_double()
+    lv = C.c_int32()
+    check(_lib.lib().mhs_check_model(C.byref(g), C.byref(m.c), C.byref(lam), C.byref(lv)))
+    return lam.value, lv.value
+
+
 def _grid(grid):
     if isinstance(grid, _lib.Grid):
         return grid

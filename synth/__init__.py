@@ -23,6 +23,8 @@ from .workloads import (
     SERVING_SHAPES,
     WORKLOAD_NAMES,
 )
+from . import paper
+from .paper import paper_workload
 
 __all__ = [
     "bipolar_magnetogram",
@@ -41,4 +43,6 @@ __all__ = [
     "nruns",
     "SERVING_SHAPES",
     "WORKLOAD_NAMES",
+    "paper",
+    "paper_workload",
 ]

@@ -1,0 +1,140 @@
+"""The paper's own examples (Section 3): its background atmosphere, the
+force-free three-source case with its null point, and the xi_1 / xi_2
+cross-field runs on [-5.5, 5.5]^2 x [0, 12] at 129^3.
+
+CPU: the background's hydrostatic balance, and the host-side model check
+(definiteness per multigrid level) against the oracle's eigenvalues.
+GPU: every field against the exact discrete solution (oracle), and the
+null point between the negative sources near the base."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import exact, fields
+from paper_1307_6720_amd import _lib
+from paper_1307_6720_amd.solver import check_model
+
+
+def test_background_is_hydrostatic():
+    """dp_b/dz = -p_b g / T_b (Section 3) with p_b(0) = 1, rho_b = p_b/T_b."""
+    z = np.linspace(0.0, 12.0, 240001)
+    p, rho = synth.paper.background(z)
+    T = synth.paper.temperature(z)
+    assert p[0] == 1.0
+    np.testing.assert_allclose(rho, p / T, rtol=1e-15)
+    # centred differences away from the two kinks of T_b
+    dz = z[1] - z[0]
+    dp = (p[2:] - p[:-2]) / (2 * dz)
+    rhs = -p[1:-1] * synth.paper.G / T[1:-1]
+    mask = (np.abs(z[1:-1] - 5.0) > 1e-3) & (np.abs(z[1:-1] - 10.0) > 1e-3)
+    assert np.max(np.abs(dp - rhs)[mask] / np.abs(p[1:-1][mask])) < 1e-7
+    # continuous across the kinks
+    for zc in (5.0, 10.0):
+        lo, hi = synth.paper.background(np.array([zc - 1e-9, zc + 1e-9]))[0]
+        assert abs(lo - hi) < 1e-8 * lo
+    # the corona is 150 times hotter
+    assert synth.paper.temperature(np.array([11.0]))[0] == 150.0
+
+
+def test_xi_profiles_and_derivatives():
+    z = np.linspace(0.0, 12.0, 1201)
+    for which in ("xi1", "xi2"):
+        xi, dxi = synth.paper.xi_profile(z, which)
+        assert xi.max() < 1.0
+        num = np.gradient(xi, z[1] - z[0], edge_order=2)
+        assert np.max(np.abs(num - dxi)) < 1e-3
+
+
+def _levels(grid, xi):
+    n = [grid.nx, grid.ny, grid.nz]
+    out, l = [], 0
+    while True:
+        out.append(exact.min_eigenvalue_bound(*n, xi[:: 2 ** l], grid.lx, grid.ly, grid.lz))
+        if min(n) <= 3:
+            return out
+        n = [(k - 1) // 2 + 1 for k in n]
+        l += 1
+
+
+@pytest.mark.parametrize("name", ["paper-ff", "paper-xi1", "paper-xi2"])
+def test_model_check_matches_oracle_eigenvalues(name):
+    """lambda_0 equals the oracle's exact smallest eigenvalue; the 3D
+    hierarchy stops above the first level whose shifted eigenvalue
+    lambda_l - alpha^2 falls below half of lambda_0 - alpha^2."""
+    w = synth.paper_workload(name)
+    lam, depth = check_model(w.grid, w.model)
+    lv = _levels(w.grid, w.model.xi)
+    assert abs(lam - lv[0]) <= 1e-12 * lv[0]
+    a2 = w.model.alpha ** 2
+    want = next((l for l, x in enumerate(lv) if l and x - a2 < 0.5 * (lv[0] - a2)), len(lv))
+    assert depth == want
+    assert depth >= 2
+
+
+def test_model_check_errors():
+    w = synth.paper_workload("paper-xi1")
+    m = w.model
+    lam, _ = check_model(w.grid, m)
+    too_big = synth.Model(np.sqrt(lam) * 1.0001, m.xi, m.dxi, m.pb, m.rhob, m.mu0, m.g)
+    with pytest.raises(_lib.MHSError) as e:
+        check_model(w.grid, too_big)
+    assert e.value.code == _lib.ERR_INDEFINITE
+    # definite on the grid, but every coarse grid small enough for the exact
+    # solve is indefinite: no usable hierarchy
+    near = synth.Model(np.sqrt(lam) * 0.9999, m.xi, m.dxi, m.pb, m.rhob, m.mu0, m.g)
+    with pytest.raises(_lib.MHSError) as e:
+        check_model(w.grid, near)
+    assert e.value.code == _lib.ERR_INDEFINITE
+    xi = m.xi.copy()
+    xi[7] = 1.0
+    with pytest.raises(_lib.MHSError) as e:
+        check_model(w.grid, synth.Model(m.alpha, xi, m.dxi, m.pb, m.rhob, m.mu0, m.g))
+    assert e.value.code == _lib.ERR_NOT_ELLIPTIC
+
+
+# ---- GPU -------------------------------------------------------------------
+def _exact_fields(w):
+    g, m = w.grid, w.model
+    P = exact.solve(w.bz0, g.nz, m.xi, m.alpha, g.lx, g.ly, g.lz)
+    return P, fields.fields(P, m.alpha, m.xi, m.dxi, m.pb, m.rhob, m.mu0, m.g, g.lx, g.ly, g.lz)
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", ["paper-ff", "paper-xi1", "paper-xi2"])
+@pytest.mark.parametrize("prec,rtol,tol", [(1, 1e-12, 1e-10), (2, 1e-10, 1e-8)])
+def test_paper_case_matches_exact(name, prec, rtol, tol):
+    torch = pytest.importorskip("torch")
+    from paper_1307_6720_amd.solver import Plan, solve
+
+    print(f"[paper] {name} prec={prec}", flush=True)
+    w = synth.paper_workload(name)
+    plan = Plan(w.grid, 3, device="cuda:0")
+    res = solve(plan, torch.from_numpy(w.bz0).to("cuda:0"), w.model, precision=prec, rtol=rtol, max_cycles=200)
+    torch.cuda.synchronize()
+    print(res.info2d, res.info3d, plan.levels(3))
+    P_ex, (Bx, By, Bz, p, rho) = _exact_fields(w)
+    pb, rb = w.model.pb[:, None, None], w.model.rhob[:, None, None]
+    got = [t.cpu().numpy() for t in (res.P, res.Bx, res.By, res.Bz, res.p, res.rho)]
+    errs = {"P": _rel(got[0], P_ex), "Bx": _rel(got[1], Bx), "By": _rel(got[2], By), "Bz": _rel(got[3], Bz),
+            "dp": _rel(got[4] - pb, p - pb) if name != "paper-ff" else float(np.abs(got[4] - pb).max()),
+            "drho": _rel(got[5] - rb, rho - rb) if name != "paper-ff" else float(np.abs(got[5] - rb).max())}
+    print(errs)
+    for k, e in errs.items():
+        assert e < tol, (k, e)
+    if name == "paper-ff":
+        # the null point between the two negative sources near the base
+        g = w.grid
+        x = -5.5 + np.arange(g.nx) * g.lx / (g.nx - 1)
+        y = -5.5 + np.arange(g.ny) * g.ly / (g.ny - 1)
+        B = np.sqrt(got[1][1] ** 2 + got[2][1] ** 2 + got[3][1] ** 2)
+        xs, ys = (x > -1.5) & (x < 1.5), (y > -3.0) & (y < 0.0)
+        sub = B[np.ix_(ys, xs)]
+        j, i = np.unravel_index(np.argmin(sub), sub.shape)
+        assert abs(x[xs][i]) < 0.1 and -2.2 < y[ys][j] < -1.4
+        assert sub.min() < 0.02 * sub.max()
+    plan.close()
