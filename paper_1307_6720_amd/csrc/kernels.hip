@@ -174,6 +174,34 @@ constexpr int kFHalf = kFX / 2;
 __device__ __forceinline__ int sxf(int c) { return (c & 1) * kFHalf + (c >> 1); }
 static_assert(kFX % 2 == 0, "rhs window width must be even");
 
+// Per-plane coefficients of planes base .. base+63, one plane per lane of
+// every wave: the z-march reads plane p's value with a lane broadcast
+// (v_readlane, the index is wave-uniform) instead of a scalar memory load
+// whose wait would also hold up the LDS traffic of the step.
+__device__ __forceinline__ float lane_bcast(float v, int lane)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+__device__ __forceinline__ double lane_bcast(double v, int lane)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename T>
+struct PlaneTab {
+    T v;
+    int base;
+    __device__ __forceinline__ void load(const MHS_CONST T *coef, int b, int comp, int nz)
+    {
+        base = b;
+        const int p = b + (int)(threadIdx.x & 63);
+        v = (p >= 0 && p < nz) ? coef[4 * p + comp] : (T)0;
+    }
+    __device__ __forceinline__ T operator()(int p) const { return lane_bcast(v, p - base); }
+};
+
 // LDS index pairs packed into one register (both < 65536).
 __device__ __forceinline__ uint32_t pk16(int lo, int hi) { return (uint32_t)lo | ((uint32_t)hi << 16); }
 __device__ __forceinline__ int lo16(uint32_t v) { return (int)(v & 0xffffu); }
@@ -207,12 +235,20 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     constexpr int RW = 2 * HP;
     constexpr int SLOT = kWY * RW;
     static_assert(HP >= kWX / 2, "half row too short");
-    __shared__ T S[4 * SLOT];
-    __shared__ T F[kFSlots * kFCells3];
-    __shared__ T CW[kCWPlanes * kCPlane];
+    // five window slots: plane s+1 is staged while black(s-1) of the previous
+    // step may still read planes s-2 .. s, so two barriers per step suffice
+    constexpr int kSlots = 5;
+    __shared__ T S[kSlots * SLOT];
+    auto slot = [](int p) { return (p + kSlots) % kSlots; }; // p >= -1
+    // every staged array has one spare cell past its data: lanes without a
+    // cell store there, so staging is straight-line code (no divergent
+    // branches between the loads and the stores that consume them)
+    constexpr int FSLOT = kFCells3 + 1;
+    __shared__ T F[kFSlots * FSLOT];
+    __shared__ T CW[kCWPlanes * kCPlane + 1];
     // prolongation: the coarse correction interpolated in z and y onto every
     // fine row of the window, at coarse columns (x interpolation at staging)
-    __shared__ T ZW[PROLONG ? kWY * kCWX : 1];
+    __shared__ T ZW[PROLONG ? kWY * kCWX + 1 : 1];
     __shared__ double red[kThreads / 64];
     auto sxp = [](int c) { return (c & 1) * HP + (c >> 1); };
 
@@ -256,7 +292,7 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
         const int ee = min(e, kWCells - 1);
         const int w = ee / kWX, c = ee - w * kWX;
         const int i = i0 - 2 + c, j = j0 - 2 + w;
-        st_i[r] = pk16(e < kWCells ? w * RW + sxp(c) : kNone, PROLONG ? w * kCWX + ((i >> 1) - I0) : 0);
+        st_i[r] = pk16(e < kWCells ? w * RW + sxp(c) : RW - 1, PROLONG ? w * kCWX + ((i >> 1) - I0) : 0);
         st_g[r] = es * (uint32_t)(min(max(i, 0), nx - 1) + nx * min(max(j, 0), ny - 1));
         if (i >= 0 && i < nx && j >= 0 && j < ny) st_in |= 1u << r;
         if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2) st_int |= 1u << r;
@@ -271,7 +307,7 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
             const int e = tid + r * kThreads;
             const int ee = min(e, kFCells3 - 1);
             const int w = ee / kFX, c = ee - w * kFX;
-            f_l[r] = e < kFCells3 ? w * kFX + sxf(c) : -1;
+            f_l[r] = e < kFCells3 ? w * kFX + sxf(c) : kFCells3;
             f_g[r] = es * (uint32_t)(min(i0 - 1 + c, nx - 1) + nx * min(j0 - 1 + w, ny - 1));
         }
     }
@@ -377,6 +413,13 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
         if constexpr (HAS_F && NORM) owf = pk16(fi[0], fi[1]);
     }
     const int par0 = (i0 + j0 + 1) & 1; // red parity of plane s is (par0 + s) & 1
+    // planes kb-1 .. ke (at most kKZ + 2 <= 64) of cx, cy, d, 1/d
+    static_assert(kKZ + 2 <= 64, "one plane per lane");
+    PlaneTab<T> tcx, tcy, tid_, tdd;
+    tcx.load(coef, kb - 1, 0, nz);
+    tcy.load(coef, kb - 1, 1, nz);
+    tid_.load(coef, kb - 1, 3, nz);
+    if constexpr (NORM) tdd.load(coef, kb - 1, 2, nz);
 
     auto at = [](const MHS_GLOBAL T *base, uint32_t byte_off) -> T {
         return *(const MHS_GLOBAL T *)((const MHS_GLOBAL char *)base + byte_off);
@@ -416,8 +459,7 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     auto store_cw = [&](const T(&csrc)[PROLONG ? kCPer : 1]) {
         if constexpr (PROLONG) {
 #pragma unroll
-            for (int r = 0; r < kCPer; ++r)
-                if (tid + r * kThreads < kCCells) CW[tid + r * kThreads] = csrc[r];
+            for (int r = 0; r < kCPer; ++r) CW[min(tid + r * kThreads, kCCells)] = csrc[r];
         }
     };
     // z-y interpolation of the staged coarse planes for fine plane p
@@ -427,7 +469,7 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
             const bool ok = (p & 1) != 0;
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
-                if ((zw_ok >> r) & 1) {
+                {
                     const int a = r ? hi16(zw_src) : lo16(zw_src);
                     const bool oj = (zw_odd >> r) & 1;
                     const T a0 = CW[a], y0 = oj ? h * (a0 + CW[a + kCWX]) : a0;
@@ -437,7 +479,7 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
                         const T y1 = oj ? h * (a1 + CW[kCPlane * (kCWPlanes - 1) + a + kCWX]) : a1;
                         v = h * (y0 + y1);
                     }
-                    ZW[tid + r * kThreads] = v;
+                    ZW[(zw_ok >> r) & 1 ? tid + r * kThreads : kWY * kCWX] = v;
                 }
             }
         }
@@ -447,11 +489,10 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     auto stash = [&](int p, const T(&src)[kWPer], const T(&fsrc)[HAS_F ? kFPer3 : 1],
                      const T(&csrc)[PROLONG ? kCPer : 1]) {
         const bool corr = PROLONG && p >= 1 && p <= nz - 2;
-        T *dst = S + (p & 3) * SLOT;
+        T *dst = S + slot(p) * SLOT;
 #pragma unroll
         for (int r = 0; r < kWPer; ++r) {
-            const int l = lo16(st_i[r]);
-            if (l == kNone) continue;
+            const int l = lo16(st_i[r]); // RW - 1 (an unused padding cell) past the window
             T v = (!ZERO_IN && ((st_in >> r) & 1)) ? src[r] : (T)0;
             if constexpr (PROLONG) {
                 if (corr && ((st_int >> r) & 1)) {
@@ -463,12 +504,20 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
             dst[l] = v;
         }
         if constexpr (HAS_F) {
-            T *fd = F + (p & 3) * kFCells3;
+            T *fd = F + (p & 3) * FSLOT;
 #pragma unroll
-            for (int r = 0; r < kFPer3; ++r)
-                if (f_l[r] >= 0) fd[f_l[r]] = fsrc[r];
+            for (int r = 0; r < kFPer3; ++r) fd[f_l[r]] = fsrc[r];
         }
         store_cw(csrc);
+    };
+
+    // tile nodes of plane m from LDS to u_out
+    auto write_plane = [&](int m) {
+        const T *P = S + slot(m) * SLOT;
+        MHS_GLOBAL T *ol = uout + sxy * (size_t)m;
+#pragma unroll
+        for (int q = 0; q < kOwn; ++q)
+            if ((ow_ok >> q) & 1) *(MHS_GLOBAL T *)((MHS_GLOBAL char *)ol + ow_g[q]) = P[lo16(ow[q])];
     };
 
     double acc = 0.0;
@@ -516,30 +565,30 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
         for (int d = 0; d < D; ++d) {
             const int s = s0 + d;
             if (s > ke) break;
-            // stage plane s+1 (slot of plane s-3, free since the last black
-            // phase) and refill its register set with plane s+1+D.  Both are
-            // unconditional (past the top of the chunk they repeat the last
-            // plane, and a stage of plane nz lands in a slot no phase reads)
-            // so that every step issues the same loads and the compiler can
-            // wait for exactly the oldest register set.
+            // stage plane s+1 (slot of plane s-4; the previous step's black
+            // phase may still read planes s-3 .. s-1) and refill its register
+            // set with plane s+1+D.  Both are unconditional (past the top of
+            // the chunk they repeat the last plane, and a stage of plane nz
+            // lands in a slot no phase reads) so that every step issues the
+            // same loads and the compiler can wait for the oldest set only.
             const int ri = (d + 2) % D;
             stash(s + 1, pre[ri], fpre[ri], cpre[ri]);
             fetch(min(s + 1 + D, ptop), pre[ri], fpre[ri], cpre[ri]);
             lds_barrier();
-            const T *Ps = S + (s & 3) * SLOT;
-            const T *Pu = S + ((s + 1) & 3) * SLOT;
-            const T *Pd = S + ((s - 1) & 3) * SLOT;
+            const T *Ps = S + slot(s) * SLOT;
+            const T *Pu = S + slot(s + 1) * SLOT;
+            const T *Pd = S + slot(s - 1) * SLOT;
             if constexpr (NORM) {
                 // residual of the input iterate at plane s (all values still
                 // old); old plane s-1 comes from registers captured a step ago
                 const bool do_res = (s >= kb && s < ke);
                 T cx = 0, cy = 0, dd = 0;
                 if (do_res) {
-                    cx = coef[4 * s];
-                    cy = coef[4 * s + 1];
-                    dd = coef[4 * s + 2];
+                    cx = tcx(s);
+                    cy = tcy(s);
+                    dd = tdd(s);
                 }
-                const T *Fs = F + (s & 3) * kFCells3;
+                const T *Fs = F + (s & 3) * FSLOT;
 #pragma unroll
                 for (int q = 0; q < kOwn; ++q) {
                     const int o = lo16(ow[q]), ww = hi16(ow[q]);
@@ -557,11 +606,13 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
             }
             // z-y rows of plane s+2, whose coarse planes were staged with s+1
             zy_rows(s + 2);
+            // write plane s-2, final since black(s-2) ended before the barrier
+            if (s - 2 >= kb && s - 2 < ke) write_plane(s - 2);
             // red nodes of plane s on the tile and its one-node ring
             if (s >= 1 && s <= nz - 2) {
-                const T cx = coef[4 * s], cy = coef[4 * s + 1], invd = coef[4 * s + 3];
-                T *P = S + (s & 3) * SLOT;
-                const T *Fs = F + (s & 3) * kFCells3;
+                const T cx = tcx(s), cy = tcy(s), invd = tid_(s);
+                T *P = S + slot(s) * SLOT;
+                const T *Fs = F + (s & 3) * FSLOT;
                 const int ps = (par0 + s) & 1;
 #pragma unroll
                 for (int r = 0; r < 2; ++r) {
@@ -582,10 +633,10 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
             // black nodes of plane m = s - 1 on the tile
             const int m = s - 1;
             if (m >= kb && m < ke) {
-                const T cx = coef[4 * m], cy = coef[4 * m + 1], invd = coef[4 * m + 3];
-                T *P = S + (m & 3) * SLOT;
-                const T *Pm = S + ((m - 1) & 3) * SLOT;
-                const T *Fm = F + (m & 3) * kFCells3;
+                const T cx = tcx(m), cy = tcy(m), invd = tid_(m);
+                T *P = S + slot(m) * SLOT;
+                const T *Pm = S + slot(m - 1) * SLOT;
+                const T *Fm = F + (m & 3) * FSLOT;
                 const int pb = (par0 + m) & 1;
                 const uint32_t pr = pick(bk0, bk1, pb);
                 const int o = lo16(pr);
@@ -597,16 +648,11 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
                            invd;
                 }
             }
-            lds_barrier();
-            if (m >= kb && m < ke) {
-                const T *P = S + (m & 3) * SLOT;
-                MHS_GLOBAL T *ol = uout + sxy * (size_t)m;
-#pragma unroll
-                for (int q = 0; q < kOwn; ++q)
-                    if ((ow_ok >> q) & 1) *(MHS_GLOBAL T *)((MHS_GLOBAL char *)ol + ow_g[q]) = P[lo16(ow[q])];
-            }
         }
     }
+    // the last planes: ke-2 was written in the final step, ke-1 remains
+    lds_barrier();
+    if (ke - 1 >= kb) write_plane(ke - 1);
     if constexpr (NORM) {
         const double tot = block_sum<kThreads>(acc, red);
         if (tid == 0) gout<double>(it->partials)[tile - it->tile_base] = tot;
@@ -827,6 +873,12 @@ __global__ __launch_bounds__(kThreads) void k_restrict3(const LevelItem *__restr
     // repeat the last plane), so the compiler waits for exactly the oldest
     // register set.
     const int pbase = 2 * Kb - 2, ptop = 2 * Ke;
+    // fine planes 2Kb-1 .. 2Ke-1 (at most 2 kKC + 1 <= 64) of cx, cy, d
+    static_assert(2 * kKC + 1 <= 64, "one plane per lane");
+    PlaneTab<T> tcx, tcy, tdd;
+    tcx.load(coef, 2 * Kb - 1, 0, it->nz);
+    tcy.load(coef, 2 * Kb - 1, 1, it->nz);
+    tdd.load(coef, 2 * Kb - 1, 2, it->nz);
 #pragma unroll
     for (int q = 0; q < D; ++q) fetch(min(pbase + q, ptop), pre[q], fpre[q]);
     stash(pbase, pre[0]);
@@ -847,7 +899,7 @@ __global__ __launch_bounds__(kThreads) void k_restrict3(const LevelItem *__restr
             stash(m + 1, pre[ri]);
             lds_barrier();
             {
-                const T cx = coef[4 * m], cy = coef[4 * m + 1], d = coef[4 * m + 2];
+                const T cx = tcx(m), cy = tcy(m), d = tdd(m);
                 const T *P = U + (m & 3) * USLOT;
                 const T *Pm = U + ((m - 1) & 3) * USLOT;
                 const T *Pp = U + ((m + 1) & 3) * USLOT;
@@ -1039,6 +1091,11 @@ __global__ __launch_bounds__(kThreads) void k_ir3(const LevelItem *__restrict__ 
     // D.  Every step issues the same loads (past the top they repeat the
     // last plane), so the compiler waits for exactly the oldest register set.
     const int pbase = kb - 1, ptop = ke;
+    // planes kb .. ke-1 (at most kKZ <= 64) of cx, cy, d
+    PlaneTab<double> tcx, tcy, tdd;
+    tcx.load(coef, kb, 0, nz);
+    tcy.load(coef, kb, 1, nz);
+    tdd.load(coef, kb, 2, nz);
 #pragma unroll
     for (int q = 0; q < D; ++q) fetch(min(pbase + q, ptop), pre[q], epre[q]);
     stash(pbase, pre[0], epre[0]);
@@ -1055,7 +1112,7 @@ __global__ __launch_bounds__(kThreads) void k_ir3(const LevelItem *__restrict__ 
             stash(m + 1, pre[ri], epre[ri]);
             fetch(min(m + 1 + D, ptop), pre[ri], epre[ri]);
             lds_barrier();
-            const double cx = coef[4 * m], cy = coef[4 * m + 1], d = coef[4 * m + 2];
+            const double cx = tcx(m), cy = tcy(m), d = tdd(m);
             const double *P = S + (m & 3) * SLOT;
             const double *Pm = S + ((m - 1) & 3) * SLOT;
             const double *Pp = S + ((m + 1) & 3) * SLOT;
