@@ -20,6 +20,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -60,6 +61,12 @@ def parse():
     ap.add_argument("--batch", type=int, default=6,
                     help="concurrent requests in the batched pass over the workload (0: single stream only)")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--counter-probe", action="store_true",
+                    help="run only the workload of the rocprofv3 FETCH_SIZE/WRITE_SIZE runs")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="print the traffic summary from the two counter runs' counter_collection.csv")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("STATS_CSV", "TRACE_CSV"),
+                    help="print the kernel summary of a --kernel-trace --stats run")
     return ap.parse_args()
 
 
@@ -87,6 +94,155 @@ def recorded_traffic():
         return float(meta["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         return None
+
+
+# ---------------------------------------------------------------------------
+# rocprofv3 helpers: the workload of the counter runs and the summaries kept
+# under profiles/ (the counter-derived traffic is read back by recorded_traffic)
+# ---------------------------------------------------------------------------
+def _short_kernel(name):
+    n = re.sub(r"\(mhs::[^)]*\)", "", name)
+    n = n.replace("void mhs::(anonymous namespace)::", "").replace("mhs::(anonymous namespace)::", "")
+    return re.sub(r"\(.*\)$", "", n)
+
+
+# level-0 FP32 smoother variants of one refinement step and their compulsory
+# bytes per fine node: the zero-guess sweep (read f, write u), two sweeps with
+# f (read u, f; write u) and the prolongation sweep (+ coarse correction, N/8
+# floats)
+SMOOTH_L0_MIX = {"k_sweep3<float, 3>": (1, 8.0), "k_sweep3<float, 1>": (2, 12.0), "k_sweep3<float, 9>": (1, 12.5)}
+COPY_BYTES = 1 << 30
+
+
+def counter_probe():
+    """Workload of the FETCH_SIZE / WRITE_SIZE runs: a device copy of
+    COPY_BYTES (the calibration kernel: it reads and writes exactly that
+    many bytes), then two mixed-path equilibria of the 257^3 workload."""
+    import torch
+
+    import synth
+    from paper_1307_6720_amd import PREC_FP64, PREC_MIXED
+    from paper_1307_6720_amd.solver import Plan, make_opts
+
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    w = synth.workload("mhs-257", run=3)
+    plan = Plan(w.grid, PREC_FP64 | PREC_MIXED, device="cuda:0")
+    bz = torch.from_numpy(w.bz0).to("cuda:0")
+    P = torch.zeros(w.grid.shape, dtype=torch.float64, device="cuda:0")
+    for _ in range(2):
+        plan.solve_boundary(bz, P, make_opts(rtol=1e-10))
+        plan.solve_interior(w.model, P, make_opts(PREC_MIXED, rtol=1e-10))
+    torch.cuda.synchronize()
+    plan.close()
+    print("counter probe done", flush=True)
+
+
+def summarize_counters(fetch_csv, write_csv):
+    """Per-launch HBM traffic of the level-0 FP32 smoother from the two
+    counter runs of counter_probe, each counter scaled by what it reads for
+    the calibration copy.  Prints the summary kept under profiles/."""
+    import collections
+    import csv
+    import statistics
+
+    def load(path, counter):
+        agg = collections.OrderedDict()
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] != counter:
+                    continue
+                k = r["Dispatch_Id"]
+                if k not in agg:
+                    agg[k] = [r["Kernel_Name"], 0.0]
+                agg[k][1] += float(r["Counter_Value"]) * 1024.0  # KiB per dispatch
+        return list(agg.values())
+
+    fetch, write = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
+
+    def calib(rows):
+        # the largest copy kernel is the calibration copy
+        return max(v for n, v in rows if "copyBuffer" in n or "copy" in _short_kernel(n).lower()) / COPY_BYTES
+
+    cf, cw = calib(fetch), calib(write)
+    N = 257 ** 3
+    per = {}
+    for k in SMOOTH_L0_MIX:
+        fv = [v for n, v in fetch if _short_kernel(n) == k]
+        wv = [v for n, v in write if _short_kernel(n) == k]
+        # level-0 launches carry 8x the traffic of level 1; launches issued
+        # after convergence exit at once and carry none
+        f0 = [x for x in fv if x > max(fv) / 3]
+        w0 = [x for x in wv if x > max(wv) / 3]
+        per[k] = (len(f0), statistics.mean(f0) / cf, statistics.mean(w0) / cw)
+    print(f"calibration: a device copy of {COPY_BYTES} B reads FETCH_SIZE = {cf:.4f} x bytes read, "
+          f"WRITE_SIZE = {cw:.4f} x bytes written; counts below are divided by these factors")
+    for k, (n, fb, wb) in per.items():
+        print(f"{k:22s} level-0 launches {n:3d}  read {fb / 1e6:8.1f} MB ({fb / N:5.2f} B/node, "
+              f"compulsory {SMOOTH_L0_MIX[k][1] - 4:.2f})  write {wb / 1e6:8.1f} MB ({wb / N:5.2f} B/node, compulsory 4.00)")
+    tot = sum(c for c, _ in SMOOTH_L0_MIX.values())
+    avg = sum(c * (per[k][1] + per[k][2]) for k, (c, _) in SMOOTH_L0_MIX.items()) / tot
+    alg = sum(c * b for c, b in SMOOTH_L0_MIX.values()) * N / tot
+    print(f"class average per launch (1 zero-guess : 2 with f : 1 prolongation): traffic {avg / 1e6:.1f} MB, "
+          f"compulsory {alg / 1e6:.1f} MB, ratio {avg / alg:.3f}")
+    print(f"kernels_sha256: {kernels_digest()}")
+    print(f"traffic_bytes_per_launch: {avg:.0f}")
+
+
+def summarize_trace(stats_csv, trace_csv, one_groups=1024, top=24):
+    """Kernel-time summary of a rocprofv3 --kernel-trace --stats run of
+    bench.py: the stats table, the launches that ran (> 5 us; launches
+    issued after a solve converged exit at once) by kernel and workgroup
+    count, and the average duration of the level-0 FP32 smoother launches
+    (the kernel bench.py's roofline times with HIP events)."""
+    import collections
+    import csv
+    import statistics
+
+    with open(stats_csv) as fh:
+        rows = list(csv.DictReader(fh))
+    print(f"## kernel stats (top {top}, as written by rocprofv3 --stats)")
+    print(f"{'kernel':58s} {'calls':>6s} {'total_ms':>9s} {'avg_us':>8s} {'pct':>6s}")
+    for r in rows[:top]:
+        print(f"{_short_kernel(r['Name'])[:58]:58s} {int(r['Calls']):6d} {int(r['TotalDurationNs']) / 1e6:9.3f} "
+              f"{float(r['AverageNs']) / 1e3:8.2f} {float(r['Percentage']):6.2f}")
+    with open(trace_csv) as fh:
+        rows = list(csv.DictReader(fh))
+    agg = collections.defaultdict(list)
+    l0 = collections.defaultdict(list)
+    for r in rows:
+        k = _short_kernel(r["Kernel_Name"])
+        g = int(r["Grid_Size_X"]) // max(1, int(r["Workgroup_Size_X"]))
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        agg[(k, g)].append(d)
+        if k in SMOOTH_L0_MIX and d > 25.0:
+            l0[(k, g)].append(d)
+    print()
+    print("## launches that ran (> 5 us), by kernel and workgroup count")
+    print(f"{'kernel':40s} {'groups':>7s} {'ran':>5s} {'avg_us':>8s} {'med_us':>8s} {'skip':>5s} {'ran_ms':>8s}")
+    out = []
+    for (k, g), v in agg.items():
+        ran = sorted(d for d in v if d > 5.0)
+        if ran:
+            out.append((sum(ran), k, g, len(ran), sum(ran) / len(ran), ran[len(ran) // 2], len(v) - len(ran)))
+    for s, k, g, n, avg, med, sk in sorted(out, reverse=True)[:32]:
+        print(f"{k[:40]:40s} {g:7d} {n:5d} {avg:8.2f} {med:8.2f} {sk:5d} {s / 1e3:8.3f}")
+    print()
+    print("## launches (> 25 us) of the mixed path's level-0 smoother; one request's level-0 launch has "
+          f"{one_groups} workgroups, merged launches of several requests have more")
+    tot = cnt = 0
+    for (k, g), v in sorted(l0.items()):
+        print(f"{k:22s} groups {g:5d} launches {len(v):4d} avg_us {statistics.mean(v):8.2f} "
+              f"median_us {statistics.median(v):8.2f}")
+        if g == one_groups:
+            tot += sum(v)
+            cnt += len(v)
+    if cnt:
+        print(f"one-request level-0 launches: {cnt}, average {tot / cnt:.2f} us")
 
 
 def cpu_baseline(run):
@@ -206,11 +362,21 @@ def batched_leg(a, runs, bz, prec, steps, warm=True):
 
 def main():
     a = parse()
+    if a.summarize_counters:
+        summarize_counters(*a.summarize_counters)
+        return
+    if a.summarize_trace:
+        summarize_trace(*a.summarize_trace)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
         print("bench.py: this build measures one GPU only (the path has no multi-GPU sharding); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if a.counter_probe:
+        counter_probe()
+        return
 
     import numpy as np
     import torch
