@@ -65,8 +65,9 @@ def parse():
                     help="run only the workload of the rocprofv3 FETCH_SIZE/WRITE_SIZE runs")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="print the traffic summary from the two counter runs' counter_collection.csv")
-    ap.add_argument("--summarize-trace", nargs=2, metavar=("STATS_CSV", "TRACE_CSV"),
-                    help="print the kernel summary of a --kernel-trace --stats run")
+    ap.add_argument("--summarize-trace", nargs="+", metavar="CSV",
+                    help="print the kernel summary of a --kernel-trace --stats [--marker-trace] run: "
+                         "STATS_CSV TRACE_CSV [MARKER_CSV]")
     return ap.parse_args()
 
 
@@ -80,8 +81,9 @@ def percentile(xs, q):
 
 
 def recorded_traffic():
-    """Per-launch HBM traffic of the level-0 smoother measured with rocprofv3
-    counters, valid only for the kernel source it was measured on."""
+    """HBM traffic of the level-0 smoother measured with rocprofv3 counters
+    (bytes per one-request launch, and traffic / compulsory bytes of merged
+    launches), valid only for the kernel source it was measured on."""
     try:
         meta = {}
         with open(TRAFFIC_FILE) as fh:
@@ -91,7 +93,8 @@ def recorded_traffic():
                     meta[k.strip()] = v.strip()
         if meta.get("kernels_sha256") != kernels_digest():
             return None
-        return float(meta["traffic_bytes_per_launch"])
+        return {"single_bytes_per_launch": float(meta["traffic_bytes_per_launch"]),
+                "merged_ratio": float(meta["merged_traffic_ratio"])}
     except (OSError, KeyError, ValueError):
         return None
 
@@ -114,41 +117,60 @@ SMOOTH_L0_MIX = {"k_sweep3<float, 3>": (1, 8.0), "k_sweep3<float, 1>": (2, 12.0)
 COPY_BYTES = 1 << 30
 
 
-def counter_probe():
+def counter_probe(batch=6, requests=12):
     """Workload of the FETCH_SIZE / WRITE_SIZE runs: a device copy of
     COPY_BYTES (the calibration kernel: it reads and writes exactly that
-    many bytes), then two mixed-path equilibria of the 257^3 workload."""
+    many bytes), two mixed-path equilibria of the 257^3 workload one at a
+    time, then `requests` of its equilibria served with `batch` in flight
+    (the merged launches of the batched pass)."""
     import torch
 
     import synth
     from paper_1307_6720_amd import PREC_FP64, PREC_MIXED
+    from paper_1307_6720_amd.serve import DeviceBackend, Request, Server
     from paper_1307_6720_amd.solver import Plan, make_opts
 
-    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda:0")
+    dev = "cuda:0"
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=dev)
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
     dst.copy_(src)
     torch.cuda.synchronize()
     del src, dst
-    w = synth.workload("mhs-257", run=3)
-    plan = Plan(w.grid, PREC_FP64 | PREC_MIXED, device="cuda:0")
-    bz = torch.from_numpy(w.bz0).to("cuda:0")
-    P = torch.zeros(w.grid.shape, dtype=torch.float64, device="cuda:0")
+    runs = [synth.workload("mhs-257", run=r) for r in range(synth.nruns("mhs-257"))]
+    w = runs[3]
+    plan = Plan(w.grid, PREC_FP64 | PREC_MIXED, device=dev)
+    bz = torch.from_numpy(w.bz0).to(dev)
+    P = torch.zeros(w.grid.shape, dtype=torch.float64, device=dev)
     for _ in range(2):
         plan.solve_boundary(bz, P, make_opts(rtol=1e-10))
         plan.solve_interior(w.model, P, make_opts(PREC_MIXED, rtol=1e-10))
     torch.cuda.synchronize()
     plan.close()
+    bzs = [torch.from_numpy(r.bz0).to(dev) for r in runs]
+    be = DeviceBackend(max_slots=batch, device=dev)
+    srv = Server(be, 64 << 30)
+    reqs = [Request(id=k, dims=(runs[0].grid.nx, runs[0].grid.ny, runs[0].grid.nz), model=runs[k % len(runs)].model,
+                    bz0=bzs[k % len(runs)], precision=PREC_MIXED, rtol=1e-10) for k in range(requests)]
+    done, st = srv.run(reqs)
+    torch.cuda.synchronize()
+    be.close()
+    assert st["ok"] == requests, st
     print("counter probe done", flush=True)
 
 
-def summarize_counters(fetch_csv, write_csv):
-    """Per-launch HBM traffic of the level-0 FP32 smoother from the two
-    counter runs of counter_probe, each counter scaled by what it reads for
-    the calibration copy.  Prints the summary kept under profiles/."""
+def summarize_counters(fetch_csv, write_csv, one_groups=1024):
+    """HBM traffic of the level-0 FP32 smoother from the two counter runs of
+    counter_probe, each counter scaled by what it reads for the calibration
+    copy.  A launch of the smoother covering k requests of the 257^3
+    workload has k * one_groups workgroups; level-0 launches read about
+    8x what level-1 launches of the same k read, and launches issued after
+    a solve converged read nothing.  Prints the summary kept under
+    profiles/: bytes per one-request launch (the 1 : 2 : 1 mix of one
+    refinement step) and the ratio of measured to compulsory bytes over
+    the merged (k > 1) launches."""
     import collections
     import csv
-    import statistics
 
     def load(path, counter):
         agg = collections.OrderedDict()
@@ -156,49 +178,98 @@ def summarize_counters(fetch_csv, write_csv):
             for r in csv.DictReader(fh):
                 if r["Counter_Name"] != counter:
                     continue
-                k = r["Dispatch_Id"]
-                if k not in agg:
-                    agg[k] = [r["Kernel_Name"], 0.0]
-                agg[k][1] += float(r["Counter_Value"]) * 1024.0  # KiB per dispatch
+                d = r["Dispatch_Id"]
+                if d not in agg:
+                    agg[d] = [r["Kernel_Name"], int(r["Grid_Size"]) // max(1, int(r["Workgroup_Size"])), 0.0]
+                agg[d][2] += float(r["Counter_Value"]) * 1024.0  # KiB per dispatch
         return list(agg.values())
 
     fetch, write = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
 
     def calib(rows):
         # the largest copy kernel is the calibration copy
-        return max(v for n, v in rows if "copyBuffer" in n or "copy" in _short_kernel(n).lower()) / COPY_BYTES
+        return max(v for n, g, v in rows if "copy" in n.lower()) / COPY_BYTES
 
     cf, cw = calib(fetch), calib(write)
     N = 257 ** 3
-    per = {}
-    for k in SMOOTH_L0_MIX:
-        fv = [v for n, v in fetch if _short_kernel(n) == k]
-        wv = [v for n, v in write if _short_kernel(n) == k]
-        # level-0 launches carry 8x the traffic of level 1; launches issued
-        # after convergence exit at once and carry none
-        f0 = [x for x in fv if x > max(fv) / 3]
-        w0 = [x for x in wv if x > max(wv) / 3]
-        per[k] = (len(f0), statistics.mean(f0) / cf, statistics.mean(w0) / cw)
+
+    def level0(rows, scale, min_bytes_per_req):
+        out = collections.defaultdict(list)  # (kernel, k) -> bytes
+        for n, g, v in rows:
+            kn = _short_kernel(n)
+            if kn not in SMOOTH_L0_MIX or g % one_groups:
+                continue
+            k = g // one_groups
+            if v / scale > k * min_bytes_per_req:
+                out[(kn, k)].append(v / scale)
+        return out
+
+    # level 0 reads >= 4 B/node (>= 67 MB) and writes 3.94 B/node per request;
+    # level 1 an eighth of that
+    F = level0(fetch, cf, 30e6)
+    W = level0(write, cw, 30e6)
     print(f"calibration: a device copy of {COPY_BYTES} B reads FETCH_SIZE = {cf:.4f} x bytes read, "
           f"WRITE_SIZE = {cw:.4f} x bytes written; counts below are divided by these factors")
-    for k, (n, fb, wb) in per.items():
-        print(f"{k:22s} level-0 launches {n:3d}  read {fb / 1e6:8.1f} MB ({fb / N:5.2f} B/node, "
-              f"compulsory {SMOOTH_L0_MIX[k][1] - 4:.2f})  write {wb / 1e6:8.1f} MB ({wb / N:5.2f} B/node, compulsory 4.00)")
+    print("level-0 launches by variant and requests per launch (k): bytes per request")
+    meas = alg = 0.0
+    for key in sorted(set(F) & set(W)):
+        kn, k = key
+        fb, wb = sum(F[key]) / len(F[key]) / k, sum(W[key]) / len(W[key]) / k
+        c = SMOOTH_L0_MIX[kn][1]
+        print(f"  {kn:22s} k={k}  launches {len(F[key]):3d}  read {fb / N:5.2f} B/node (compulsory {c - 4:.2f})  "
+              f"write {wb / N:5.2f} B/node (compulsory 4.00)")
+        if k > 1:
+            meas += sum(F[key]) + sum(W[key]) * len(F[key]) / len(W[key])
+            alg += k * c * N * len(F[key])
     tot = sum(c for c, _ in SMOOTH_L0_MIX.values())
-    avg = sum(c * (per[k][1] + per[k][2]) for k, (c, _) in SMOOTH_L0_MIX.items()) / tot
-    alg = sum(c * b for c, b in SMOOTH_L0_MIX.values()) * N / tot
-    print(f"class average per launch (1 zero-guess : 2 with f : 1 prolongation): traffic {avg / 1e6:.1f} MB, "
-          f"compulsory {alg / 1e6:.1f} MB, ratio {avg / alg:.3f}")
+    one = {kn: (sum(F[(kn, 1)]) / len(F[(kn, 1)]) + sum(W[(kn, 1)]) / len(W[(kn, 1)])) for kn in SMOOTH_L0_MIX}
+    avg = sum(c * one[kn] for kn, (c, _) in SMOOTH_L0_MIX.items()) / tot
+    alg1 = sum(c * b for c, b in SMOOTH_L0_MIX.values()) * N / tot
+    print(f"one-request launches, class average (1 zero-guess : 2 with f : 1 prolongation): traffic "
+          f"{avg / 1e6:.1f} MB, compulsory {alg1 / 1e6:.1f} MB, ratio {avg / alg1:.3f}")
+    print(f"merged launches (k > 1): traffic / compulsory = {meas / alg:.3f}")
     print(f"kernels_sha256: {kernels_digest()}")
     print(f"traffic_bytes_per_launch: {avg:.0f}")
+    print(f"merged_traffic_ratio: {meas / alg:.4f}")
 
 
-def summarize_trace(stats_csv, trace_csv, one_groups=1024, top=24):
-    """Kernel-time summary of a rocprofv3 --kernel-trace --stats run of
-    bench.py: the stats table, the launches that ran (> 5 us; launches
-    issued after a solve converged exit at once) by kernel and workgroup
-    count, and the average duration of the level-0 FP32 smoother launches
-    (the kernel bench.py's roofline times with HIP events)."""
+def _level0_split(launches):
+    """Pick the level-0 launches among launches of the smoother: (start,
+    end, kernel, groups) tuples.  Within one kernel variant and workgroup
+    count (equal requests per launch), level-0 launches take several times
+    longer than level-1 launches and launches whose items all exited at once
+    take a few microseconds (about 1 us per 1024 workgroups): the level-0
+    launches are those above the largest duration ratio between neighbours
+    among the launches longer than 3 us per 1024 workgroups (at least 5 us)."""
+    import collections
+
+    by = collections.defaultdict(list)
+    for x in launches:
+        by[(x[2], x[3])].append(x)
+    out = []
+    for (_, g), v in by.items():
+        floor = max(5000.0, 3000.0 * g / 1024)
+        v = sorted((x for x in v if (x[1] - x[0]) > floor), key=lambda x: x[1] - x[0])
+        if not v:
+            continue
+        d = [x[1] - x[0] for x in v]
+        gaps = [d[i + 1] / d[i] for i in range(len(d) - 1)]
+        if not gaps or max(gaps) < 1.8:
+            continue  # one cluster: no level-0 / level-1 split to make
+        cut = gaps.index(max(gaps)) + 1
+        out.extend(v[cut:])
+    return sorted(out)
+
+
+def summarize_trace(stats_csv, trace_csv, marker_csv=None, one_groups=1024, top=24):
+    """Kernel-time summary of a rocprofv3 --kernel-trace --stats (and
+    --marker-trace) run of bench.py: the stats table; the launches that ran
+    (> 5 us; launches issued after a solve converged exit at once) by
+    kernel and workgroup count; and the level-0 FP32 smoother launches (a
+    launch covering k requests of the 257^3 workload has k * one_groups
+    workgroups) with their average duration, over the run and inside each
+    ROCTx range of bench.py (the passes whose HIP-event timings give the
+    roofline)."""
     import collections
     import csv
     import statistics
@@ -213,36 +284,50 @@ def summarize_trace(stats_csv, trace_csv, one_groups=1024, top=24):
     with open(trace_csv) as fh:
         rows = list(csv.DictReader(fh))
     agg = collections.defaultdict(list)
-    l0 = collections.defaultdict(list)
+    sm = []  # (start, end, kernel, groups) of the FP32 smoother variants
     for r in rows:
-        k = _short_kernel(r["Kernel_Name"])
+        kn = _short_kernel(r["Kernel_Name"])
         g = int(r["Grid_Size_X"]) // max(1, int(r["Workgroup_Size_X"]))
-        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
-        agg[(k, g)].append(d)
-        if k in SMOOTH_L0_MIX and d > 25.0:
-            l0[(k, g)].append(d)
+        t0, t1 = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+        agg[(kn, g)].append((t1 - t0) / 1e3)
+        if kn in SMOOTH_L0_MIX and g % one_groups == 0:
+            sm.append((t0, t1, kn, g))
     print()
     print("## launches that ran (> 5 us), by kernel and workgroup count")
     print(f"{'kernel':40s} {'groups':>7s} {'ran':>5s} {'avg_us':>8s} {'med_us':>8s} {'skip':>5s} {'ran_ms':>8s}")
     out = []
-    for (k, g), v in agg.items():
+    for (kn, g), v in agg.items():
         ran = sorted(d for d in v if d > 5.0)
         if ran:
-            out.append((sum(ran), k, g, len(ran), sum(ran) / len(ran), ran[len(ran) // 2], len(v) - len(ran)))
-    for s, k, g, n, avg, med, sk in sorted(out, reverse=True)[:32]:
-        print(f"{k[:40]:40s} {g:7d} {n:5d} {avg:8.2f} {med:8.2f} {sk:5d} {s / 1e3:8.3f}")
-    print()
-    print("## launches (> 25 us) of the mixed path's level-0 smoother; one request's level-0 launch has "
-          f"{one_groups} workgroups, merged launches of several requests have more")
-    tot = cnt = 0
-    for (k, g), v in sorted(l0.items()):
-        print(f"{k:22s} groups {g:5d} launches {len(v):4d} avg_us {statistics.mean(v):8.2f} "
-              f"median_us {statistics.median(v):8.2f}")
-        if g == one_groups:
-            tot += sum(v)
-            cnt += len(v)
-    if cnt:
-        print(f"one-request level-0 launches: {cnt}, average {tot / cnt:.2f} us")
+            out.append((sum(ran), kn, g, len(ran), sum(ran) / len(ran), ran[len(ran) // 2], len(v) - len(ran)))
+    for tot, kn, g, n, avg, med, sk in sorted(out, reverse=True)[:32]:
+        print(f"{kn[:40]:40s} {g:7d} {n:5d} {avg:8.2f} {med:8.2f} {sk:5d} {tot / 1e3:8.3f}")
+
+    def table(sel, title):
+        print()
+        print(title)
+        l0 = _level0_split(sel)
+        by = collections.defaultdict(list)
+        for t0, t1, kn, g in l0:
+            by[(kn, g // one_groups)].append((t1 - t0) / 1e3)
+        for (kn, k), v in sorted(by.items()):
+            print(f"  {kn:22s} k={k}  launches {len(v):4d}  avg_us {statistics.mean(v):8.2f}  "
+                  f"median_us {statistics.median(v):8.2f}")
+        ds = [(t1 - t0) / 1e3 for t0, t1, _, _ in l0]
+        if ds:
+            print(f"  all: {len(ds)} launches, average {statistics.mean(ds):.2f} us")
+
+    table(sm, "## level-0 FP32 smoother launches over the whole run, by requests per launch k")
+    if marker_csv:
+        with open(marker_csv) as fh:
+            marks = list(csv.DictReader(fh))
+        for m in marks:
+            name = next((v for v in m.values() if v in ("roofline_pass", "roofline_single_request_pass")), None)
+            if name is None:
+                continue
+            a, b = int(m["Start_Timestamp"]), int(m["End_Timestamp"])
+            table([x for x in sm if a <= x[0] and x[1] <= b],
+                  f"## the same inside the ROCTx range {name} (bench.py times these launches with HIP events)")
 
 
 def cpu_baseline(run):
@@ -333,10 +418,45 @@ def serve_leg(a, torch, dev):
             "speedup_vs_fp64_single": sat["solves_per_s"] / single}
 
 
-def batched_leg(a, runs, bz, prec, steps, warm=True):
+class _Roctx:
+    """ROCTx ranges around the passes of this benchmark (rocprofv3
+    --marker-trace records them; the trace summary uses them to pick the
+    launches of the pass the roofline is computed from).  No-op when the
+    library is absent."""
+
+    def __init__(self):
+        import ctypes
+
+        self.lib = None
+        for name in ("libroctx64.so", "/opt/rocm/lib/libroctx64.so"):
+            try:
+                self.lib = ctypes.CDLL(name)
+                self.lib.roctxRangePushA.argtypes = [ctypes.c_char_p]
+                break
+            except OSError:
+                continue
+
+    def push(self, name):
+        if self.lib is not None:
+            self.lib.roctxRangePushA(name.encode())
+
+    def pop(self):
+        if self.lib is not None:
+            self.lib.roctxRangePop()
+
+
+ROCTX = _Roctx()
+ROOFLINE_RANGE = "roofline_pass"
+
+
+def batched_leg(a, runs, bz, prec, steps, warm=True, profile=False):
     """The same equilibria served by the batching server with `a.batch`
     requests in flight (all queued at once): whole-job throughput and
-    per-request latency."""
+    per-request latency.  With `profile`, two more passes over the same
+    requests time the merged launches with HIP events: every class, then
+    the level-0 smoother alone (inside the ROCTx range ROOFLINE_RANGE)."""
+    import torch
+
     from paper_1307_6720_amd.serve import DeviceBackend, Request, Server
 
     be = DeviceBackend(max_slots=a.batch, device=bz[0].device)
@@ -352,12 +472,27 @@ def batched_leg(a, runs, bz, prec, steps, warm=True):
         srv.run(reqs(a.batch))
     srv.ticks = srv.peak_active = 0
     done, st = srv.run(reqs(steps))
-    be.close()
     assert st["ok"] == steps, st
     cyc = [r.info3d["cycles"] for r in done]
-    return {"solves_per_s": st["solves_per_s"], "ms_per_solve": 1e3 / st["solves_per_s"], "p50_ms": st["p50_ms"],
-            "p99_ms": st["p99_ms"], "requests": steps, "in_flight": a.batch, "ticks": st["ticks"],
-            "cycles": sum(cyc) / len(cyc)}
+    out = {"solves_per_s": st["solves_per_s"], "ms_per_solve": 1e3 / st["solves_per_s"], "p50_ms": st["p50_ms"],
+           "p99_ms": st["p99_ms"], "requests": steps, "in_flight": a.batch, "ticks": st["ticks"],
+           "cycles": sum(cyc) / len(cyc)}
+    if profile:
+        b = be.batch
+        for key, classes in (("prof_all", None), ("prof_smooth_l0", ["smooth_l0"])):
+            b.profile(True, classes)
+            b.profile_read(reset=True)
+            torch.cuda.synchronize()
+            if key == "prof_smooth_l0":
+                ROCTX.push(ROOFLINE_RANGE)
+            srv.run(reqs(steps))
+            torch.cuda.synchronize()
+            if key == "prof_smooth_l0":
+                ROCTX.pop()
+            out[key] = b.profile_read(reset=True)
+            b.profile(False)
+    be.close()
+    return out
 
 
 def main():
@@ -438,7 +573,9 @@ def main():
     # kernel breakdown (every class timed) and the dominant kernel alone
     _, _, _, _, mix_prof = timed(PREC_MIXED, a.steps, classes=list(_lib.PROF_NAMES))
     _, _, _, _, f64_prof = timed(PREC_FP64, a.steps, classes=list(_lib.PROF_NAMES))
+    ROCTX.push("roofline_single_request_pass")
     _, _, _, _, dom_prof = timed(PREC_MIXED, a.steps, classes=["smooth_l0"])
+    ROCTX.pop()
 
     # unfused compulsory-traffic model of the method (bytes per fine node):
     # FP64 V(2,2) 108.57; one refinement step with m FP32 V(2,2) 32 + 74.29 m
@@ -457,19 +594,34 @@ def main():
         return out
 
     kmix = kernels(mix_prof)
-    dom = "smooth_l0"
-    ms, n, b = dom_prof[dom]
-    achieved = b / (ms * 1e-3) / 1e9
     traffic = recorded_traffic()
-    roofline = {"bound": "hbm", "kernel": "level-0 FP32 red-black smoother k_sweep3<float, 3|1|9> (zero guess, with f, with prolongation)",
+
+    def roofline_of(prof, where):
+        ms, n, b = prof["smooth_l0"]
+        achieved = b / (ms * 1e-3) / 1e9
+        return {"bound": "hbm",
+                "kernel": "level-0 FP32 red-black smoother k_sweep3<float, 3|1|9> (zero guess, with f, with prolongation)",
+                "launches_timed": where,
                 "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+                "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
                 "algorithmic_bytes_per_launch": b / n, "avg_launch_us": 1e3 * ms / n, "launches": n}
+
+    roof_single = roofline_of(dom_prof, "one request per launch (single-stream pass)")
+    roof_single["traffic"] = None if traffic is None else traffic["single_bytes_per_launch"]
 
     batched = batched_fp64 = None
     if a.batch > 0:
-        batched = batched_leg(a, runs, bz, PREC_MIXED, a.steps)
+        batched = batched_leg(a, runs, bz, PREC_MIXED, a.steps, profile=True)
         batched_fp64 = batched_leg(a, runs, bz, PREC_FP64, a.steps)
+        roofline = roofline_of(batched.pop("prof_smooth_l0"),
+                               f"merged launches of the batched pass ({a.batch} requests in flight)")
+        # counters taken on merged launches of the same pass: measured bytes
+        # per compulsory byte, times this pass's compulsory bytes per launch
+        roofline["traffic"] = (None if traffic is None else
+                               traffic["merged_ratio"] * roofline["algorithmic_bytes_per_launch"])
+        batched["kernels"] = kernels(batched.pop("prof_all"))
+    else:
+        roofline = roof_single
 
     serving = None
     if a.serve_requests > 0:
@@ -518,6 +670,7 @@ def main():
         "kernels": kmix,
         "kernels_note": "per-class HIP-event timings from a separate pass with every class timed",
         "roofline": roofline,
+        "roofline_single_request": roof_single,
         "serving": serving,
         "context": {"paper_speedup": "x30 GPU vs serial (x32.4 at 128^3, x29.6 at 256^3); hardware unstated"},
     }

@@ -308,6 +308,18 @@ int mhs_batch_poll(mhs_batch *batch, int32_t slot, int32_t *done, mhs_info *boun
 /* Free a slot (finished or not) for reuse; its plan may then be reused. */
 int mhs_batch_release(mhs_batch *batch, int32_t slot);
 
+/* Profiling of a batch's merged launches (the MHS_PROF_* classes above):
+ * each launch of a selected class is bracketed by HIP events on the tick's
+ * stream.  A merged launch counts once if any of its requests' items ran
+ * (items after a request's convergence check exit at once in the tick the
+ * request stops); its compulsory bytes are the sum over the items that
+ * ran.  class_mask 0 disables; bits outside MHS_PROF_ALL are
+ * MHS_ERR_INVALID_ARG.  profile_read returns the totals since the last
+ * reset (ticks are synchronous, so nothing is pending). */
+int mhs_batch_profile_enable(mhs_batch *batch, int32_t class_mask);
+int mhs_batch_profile_read(mhs_batch *batch, int32_t klass, double *total_ms, int64_t *launches,
+                           double *bytes, int32_t reset);
+
 #ifdef __cplusplus
 }
 #endif

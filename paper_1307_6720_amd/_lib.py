@@ -111,6 +111,8 @@ def lib():
         "mhs_batch_step": (C.c_int, [vp, vp, P(i32)]),
         "mhs_batch_poll": (C.c_int, [vp, i32, P(i32), P(Info), P(Info)]),
         "mhs_batch_release": (C.c_int, [vp, i32]),
+        "mhs_batch_profile_enable": (C.c_int, [vp, i32]),
+        "mhs_batch_profile_read": (C.c_int, [vp, i32, P(dbl), P(C.c_int64), P(dbl), i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -96,6 +96,21 @@ void tag_cycle(const Program &pg, int seg, int slot, std::vector<Rec> &out)
 
 void tag_one(const Launch &L, int64_t key, int slot, std::vector<Rec> &out) { out.push_back({key, slot, L}); }
 
+// Profiling of merged launches: one event pair per launch, and per item the
+// slot, whether it runs before its cycle's convergence check, and its
+// compulsory bytes.  After the tick's status read-back an item counts if it
+// ran: it precedes the check, or its request did not stop at this tick.
+struct ProfItem {
+    int slot;
+    bool pre;
+    double bytes;
+};
+struct BatchProf {
+    int klass;
+    size_t first, count; // items
+    hipEvent_t start, end;
+};
+
 } // namespace
 
 struct mhs_batch {
@@ -109,6 +124,9 @@ struct mhs_batch {
     Staging rec;
     std::vector<Slot> slots;
     std::vector<Rec> recs;
+    Profiler prof;                  // class mask, event pool and totals
+    std::vector<ProfItem> prof_items;
+    std::vector<BatchProf> prof_pending;
 };
 
 namespace {
@@ -396,6 +414,7 @@ int mhs_batch_create(int32_t max_slots, void *d_ws, size_t ws_bytes, mhs_batch *
 int mhs_batch_destroy(mhs_batch *b)
 {
     if (!b) return MHS_OK;
+    for (hipEvent_t e : b->prof.pool) (void)hipEventDestroy(e);
     if (b->stage.host) (void)hipHostFree(b->stage.host);
     if (b->h_init) (void)hipHostFree(b->h_init);
     if (b->h_read) (void)hipHostFree(b->h_read);
@@ -500,6 +519,17 @@ int mhs_batch_step(mhs_batch *b, void *stream, int32_t *n_active)
     // 2. merge equal (key, variant) launches across requests
     std::stable_sort(b->recs.begin(), b->recs.end(), [](const Rec &x, const Rec &y) { return x.key < y.key; });
     std::vector<Launch> plan_launches;
+    std::vector<std::pair<size_t, size_t>> launch_items; // per launch: its items in prof_items
+    const bool profiling = b->prof.mask != 0;
+    b->prof_items.clear();
+    b->prof_pending.clear();
+    b->prof.next = 0;
+    auto note_items = [&](const std::vector<const Rec *> &g) {
+        const size_t first = b->prof_items.size();
+        if (profiling)
+            for (const Rec *r : g) b->prof_items.push_back({r->slot, r->L.pre, r->L.bytes});
+        launch_items.emplace_back(first, g.size());
+    };
     b->stage.used = 0;
     std::vector<const Rec *> grp;
     for (size_t lo = 0; lo < b->recs.size();) {
@@ -512,6 +542,7 @@ int mhs_batch_step(mhs_batch *b, void *stream, int32_t *n_active)
             if (La.kind == Launch::kCopy) {
                 plan_launches.push_back(La);
                 taken[a - lo] = true;
+                note_items({&b->recs[a]});
                 continue;
             }
             grp.clear();
@@ -523,6 +554,7 @@ int mhs_batch_step(mhs_batch *b, void *stream, int32_t *n_active)
             Launch M{};
             if (!merge(b, grp, &M)) return fail(MHS_ERR_WORKSPACE, "batch descriptor table exhausted");
             plan_launches.push_back(M);
+            note_items(grp);
         }
         lo = hi;
     }
@@ -534,12 +566,56 @@ int mhs_batch_step(mhs_batch *b, void *stream, int32_t *n_active)
         if (active(S.phase) && S.fresh && S.phase != kFinish)
             HIPCHK(hipMemcpyAsync(b->d_states + i, b->h_init + i, sizeof(SolveState), hipMemcpyHostToDevice, s));
     }
-    for (const Launch &L : plan_launches) {
+    for (size_t q = 0; q < plan_launches.size(); ++q) {
+        const Launch &L = plan_launches[q];
+        const bool timed = profiling && L.prof >= 0 && ((b->prof.mask >> L.prof) & 1) != 0;
+        BatchProf rec{};
+        if (timed) {
+            rec.klass = L.prof;
+            rec.first = launch_items[q].first;
+            rec.count = launch_items[q].second;
+            rec.start = prof_event(b->prof);
+            rec.end = prof_event(b->prof);
+            if (!rec.start || !rec.end) return fail(MHS_ERR_HIP, "event creation failed");
+            HIPCHK(hipEventRecord(rec.start, s));
+        }
         const hipError_t e = exec_launch(L, s);
         if (e != hipSuccess) return fail(MHS_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+        if (timed) {
+            HIPCHK(hipEventRecord(rec.end, s));
+            b->prof_pending.push_back(rec);
+        }
     }
     HIPCHK(hipMemcpyAsync(b->h_read, b->d_states, (size_t)top * sizeof(SolveState), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+
+    // 4a. timed launches: count the items that ran (stopped[i]: slot i's
+    // solve stopped at this tick's check, so its later launches exited)
+    if (!b->prof_pending.empty()) {
+        std::vector<char> stopped((size_t)top, 0);
+        for (int i = 0; i < top; ++i) {
+            const Slot &S = b->slots[(size_t)i];
+            stopped[(size_t)i] = (S.phase == kBoundary || S.phase == kInterior) && b->h_read[i].done != kRunning;
+        }
+        for (const BatchProf &r : b->prof_pending) {
+            double bytes = 0.0;
+            bool ran = false;
+            for (size_t k = r.first; k < r.first + r.count; ++k) {
+                const ProfItem &it = b->prof_items[k];
+                if (it.pre || !stopped[(size_t)it.slot]) {
+                    bytes += it.bytes;
+                    ran = true;
+                }
+            }
+            if (!ran) continue;
+            float ms = 0.0f;
+            HIPCHK(hipEventElapsedTime(&ms, r.start, r.end));
+            b->prof.ms[r.klass] += ms;
+            b->prof.bytes[r.klass] += bytes;
+            b->prof.launches[r.klass] += 1;
+        }
+        b->prof_pending.clear();
+    }
 
     // 4. phase transitions
     int running = 0;
@@ -588,6 +664,31 @@ int mhs_batch_poll(mhs_batch *b, int32_t slot, int32_t *done, mhs_info *boundary
     if (done) *done = S.phase == kDone ? 1 : 0;
     if (boundary) *boundary = S.info[0];
     if (interior) *interior = S.info[1];
+    return MHS_OK;
+}
+
+int mhs_batch_profile_enable(mhs_batch *b, int32_t class_mask)
+{
+    if (!b) return fail(MHS_ERR_INVALID_ARG, "batch is NULL");
+    if (class_mask & ~MHS_PROF_ALL) return fail(MHS_ERR_INVALID_ARG, "unknown profiling class in mask 0x%x", class_mask);
+    b->prof.mask = class_mask;
+    return MHS_OK;
+}
+
+int mhs_batch_profile_read(mhs_batch *b, int32_t klass, double *total_ms, int64_t *launches, double *bytes,
+                           int32_t reset)
+{
+    if (!b) return fail(MHS_ERR_INVALID_ARG, "batch is NULL");
+    if (klass < 0 || klass >= MHS_PROF_NCLASS) return fail(MHS_ERR_INVALID_ARG, "class %d out of range", klass);
+    if (total_ms) *total_ms = b->prof.ms[klass];
+    if (launches) *launches = b->prof.launches[klass];
+    if (bytes) *bytes = b->prof.bytes[klass];
+    if (reset)
+        for (int k = 0; k < MHS_PROF_NCLASS; ++k) {
+            b->prof.ms[k] = 0.0;
+            b->prof.bytes[k] = 0.0;
+            b->prof.launches[k] = 0;
+        }
     return MHS_OK;
 }
 

@@ -27,6 +27,12 @@ constexpr int kMaxLevels = 16;
 #ifndef MHS_SWEEP_ATTR
 #define MHS_SWEEP_ATTR
 #endif
+#ifndef MHS_SWEEP_HP32
+#define MHS_SWEEP_HP32 48
+#endif
+#ifndef MHS_SWEEP_HP64
+#define MHS_SWEEP_HP64 40
+#endif
 #ifndef MHS_RING_DEPTH
 #define MHS_RING_DEPTH 2
 #endif

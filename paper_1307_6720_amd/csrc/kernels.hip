@@ -225,21 +225,28 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     // plane also carries right-hand-side or coarse-correction data
     constexpr int D = (HAS_F || PROLONG) ? kDepthF : kDepth;
     constexpr int kCWPlanes = PROLONG ? 2 : 1;
-    constexpr int kFSlots = HAS_F ? 4 : 1;
+    constexpr int kFSlots = HAS_F ? 5 : 1;
     constexpr int kCPlane = kCWX * kCWY;
     // Window rows in LDS: even columns, then odd columns, the odd half
     // starting 16 banks after the even one, so that the colour phases (every
     // other column) and the staging of consecutive columns are both free of
     // bank conflicts.
-    constexpr int HP = sizeof(T) == 8 ? 40 : 48;
+    constexpr int HP = sizeof(T) == 8 ? MHS_SWEEP_HP64 : MHS_SWEEP_HP32;
     constexpr int RW = 2 * HP;
     constexpr int SLOT = kWY * RW;
-    static_assert(HP >= kWX / 2, "half row too short");
+    // (one spare cell past the odd half: RW - 1 takes the stores of lanes past the window)
+    static_assert(HP >= kWX / 2 + 1, "half row too short");
     // five window slots: plane s+1 is staged while black(s-1) of the previous
     // step may still read planes s-2 .. s, so two barriers per step suffice
     constexpr int kSlots = 5;
     __shared__ T S[kSlots * SLOT];
-    auto slot = [](int p) { return (p + kSlots) % kSlots; }; // p >= -1
+    // Plane p lives in slot (p - kb + 2) % 5 (the right-hand side too, in
+    // its own five slots).  The z-march runs in rounds of kRound steps, a
+    // multiple of five and of the ring depth, so within a round every slot
+    // and register set is a compile-time constant: LDS accesses take their
+    // slot as an immediate offset and no step computes a modulo.
+    constexpr int kRound = 10;
+    static_assert(kRound % kSlots == 0 && kRound % D == 0, "round must cycle slots and ring");
     // every staged array has one spare cell past its data: lanes without a
     // cell store there, so staging is straight-line code (no divergent
     // branches between the loads and the stores that consume them)
@@ -486,10 +493,10 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     };
     // stage plane p (window with the coarse correction from ZW, right-hand
     // side) and the coarse planes of p + 1 carried by the same register set
-    auto stash = [&](int p, const T(&src)[kWPer], const T(&fsrc)[HAS_F ? kFPer3 : 1],
+    auto stash = [&](int p, int sl, const T(&src)[kWPer], const T(&fsrc)[HAS_F ? kFPer3 : 1],
                      const T(&csrc)[PROLONG ? kCPer : 1]) {
         const bool corr = PROLONG && p >= 1 && p <= nz - 2;
-        T *dst = S + slot(p) * SLOT;
+        T *dst = S + sl * SLOT;
 #pragma unroll
         for (int r = 0; r < kWPer; ++r) {
             const int l = lo16(st_i[r]); // RW - 1 (an unused padding cell) past the window
@@ -504,7 +511,7 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
             dst[l] = v;
         }
         if constexpr (HAS_F) {
-            T *fd = F + (p & 3) * FSLOT;
+            T *fd = F + sl * FSLOT;
 #pragma unroll
             for (int r = 0; r < kFPer3; ++r) fd[f_l[r]] = fsrc[r];
         }
@@ -512,8 +519,8 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     };
 
     // tile nodes of plane m from LDS to u_out
-    auto write_plane = [&](int m) {
-        const T *P = S + slot(m) * SLOT;
+    auto write_plane = [&](int m, int sl) {
+        const T *P = S + sl * SLOT;
         MHS_GLOBAL T *ol = uout + sxy * (size_t)m;
 #pragma unroll
         for (int q = 0; q < kOwn; ++q)
@@ -544,14 +551,14 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
         lds_barrier();
     }
     if (pbase >= 0) {
-        stash(pbase, pre[0], fpre[0], cpre[0]);
+        stash(pbase, 0, pre[0], fpre[0], cpre[0]);
         if constexpr (PROLONG) {
             lds_barrier();
             zy_rows(pbase + 1);
             lds_barrier();
         }
     }
-    stash(kb - 1, pre[1], fpre[1], cpre[1]);
+    stash(kb - 1, 1, pre[1], fpre[1], cpre[1]);
     if constexpr (PROLONG) {
         lds_barrier();
         zy_rows(kb);
@@ -560,11 +567,13 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     fetch(min(pbase + D, ptop), pre[0], fpre[0], cpre[0]);
     fetch(min(pbase + D + 1, ptop), pre[1], fpre[1], cpre[1]);
 
-    for (int s0 = kb - 1; s0 <= ke; s0 += D) {
+    for (int s0 = kb - 1; s0 <= ke; s0 += kRound) {
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
+        for (int d = 0; d < kRound; ++d) {
             const int s = s0 + d;
             if (s > ke) break;
+            // slots of planes s-2 .. s+1 (plane s is kb - 1 + d + kRound i)
+            const int sm2 = (d + 4) % kSlots, sm1 = d % kSlots, s00 = (d + 1) % kSlots, sp1 = (d + 2) % kSlots;
             // stage plane s+1 (slot of plane s-4; the previous step's black
             // phase may still read planes s-3 .. s-1) and refill its register
             // set with plane s+1+D.  Both are unconditional (past the top of
@@ -572,12 +581,12 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
             // lands in a slot no phase reads) so that every step issues the
             // same loads and the compiler can wait for the oldest set only.
             const int ri = (d + 2) % D;
-            stash(s + 1, pre[ri], fpre[ri], cpre[ri]);
+            stash(s + 1, sp1, pre[ri], fpre[ri], cpre[ri]);
             fetch(min(s + 1 + D, ptop), pre[ri], fpre[ri], cpre[ri]);
             lds_barrier();
-            const T *Ps = S + slot(s) * SLOT;
-            const T *Pu = S + slot(s + 1) * SLOT;
-            const T *Pd = S + slot(s - 1) * SLOT;
+            const T *Ps = S + s00 * SLOT;
+            const T *Pu = S + sp1 * SLOT;
+            const T *Pd = S + sm1 * SLOT;
             if constexpr (NORM) {
                 // residual of the input iterate at plane s (all values still
                 // old); old plane s-1 comes from registers captured a step ago
@@ -588,7 +597,7 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
                     cy = tcy(s);
                     dd = tdd(s);
                 }
-                const T *Fs = F + (s & 3) * FSLOT;
+                const T *Fs = F + s00 * FSLOT;
 #pragma unroll
                 for (int q = 0; q < kOwn; ++q) {
                     const int o = lo16(ow[q]), ww = hi16(ow[q]);
@@ -607,12 +616,12 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
             // z-y rows of plane s+2, whose coarse planes were staged with s+1
             zy_rows(s + 2);
             // write plane s-2, final since black(s-2) ended before the barrier
-            if (s - 2 >= kb && s - 2 < ke) write_plane(s - 2);
+            if (s - 2 >= kb && s - 2 < ke) write_plane(s - 2, sm2);
             // red nodes of plane s on the tile and its one-node ring
             if (s >= 1 && s <= nz - 2) {
                 const T cx = tcx(s), cy = tcy(s), invd = tid_(s);
-                T *P = S + slot(s) * SLOT;
-                const T *Fs = F + (s & 3) * FSLOT;
+                T *P = S + s00 * SLOT;
+                const T *Fs = F + s00 * FSLOT;
                 const int ps = (par0 + s) & 1;
 #pragma unroll
                 for (int r = 0; r < 2; ++r) {
@@ -634,9 +643,9 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
             const int m = s - 1;
             if (m >= kb && m < ke) {
                 const T cx = tcx(m), cy = tcy(m), invd = tid_(m);
-                T *P = S + slot(m) * SLOT;
-                const T *Pm = S + slot(m - 1) * SLOT;
-                const T *Fm = F + (m & 3) * FSLOT;
+                T *P = S + sm1 * SLOT;
+                const T *Pm = S + sm2 * SLOT;
+                const T *Fm = F + sm1 * FSLOT;
                 const int pb = (par0 + m) & 1;
                 const uint32_t pr = pick(bk0, bk1, pb);
                 const int o = lo16(pr);
@@ -652,7 +661,7 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     }
     // the last planes: ke-2 was written in the final step, ke-1 remains
     lds_barrier();
-    if (ke - 1 >= kb) write_plane(ke - 1);
+    if (ke - 1 >= kb) write_plane(ke - 1, (ke - kb + 1) % kSlots);
     if constexpr (NORM) {
         const double tot = block_sum<kThreads>(acc, red);
         if (tid == 0) gout<double>(it->partials)[tile - it->tile_base] = tot;
@@ -880,25 +889,33 @@ __global__ __launch_bounds__(kThreads) void k_restrict3(const LevelItem *__restr
     tcy.load(coef, 2 * Kb - 1, 1, it->nz);
     tdd.load(coef, 2 * Kb - 1, 2, it->nz);
 #pragma unroll
-    for (int q = 0; q < D; ++q) fetch(min(pbase + q, ptop), pre[q], fpre[q]);
+    for (int q = 0; q < D; ++q) {
+        fetch(min(pbase + q, ptop), pre[q], fpre[q]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
     stash(pbase, pre[0]);
     stash(pbase + 1, pre[1]);
     fetch(min(pbase + D, ptop), pre[0], fpre[0]);
+    __builtin_amdgcn_sched_barrier(0);
     fetch(min(pbase + D + 1, ptop), pre[1], fpre[1]);
+    __builtin_amdgcn_sched_barrier(0);
     T acc = (T)0;
     const T q4 = (T)0.25, h2 = (T)0.5;
     const int cw = 2 * tJ + 1, cc = 2 * tI + 1;
+    // whole rounds of D steps (one back edge, so the compiler's waits hold
+    // only the oldest register set); a step past 2 Ke - 1 only stages and
+    // fetches
     for (int m0 = 2 * Kb - 1; m0 <= 2 * Ke - 1; m0 += D) {
 #pragma unroll
         for (int dd = 0; dd < D; ++dd) {
             const int m = m0 + dd;
-            if (m > 2 * Ke - 1) break;
+            const bool live = m <= 2 * Ke - 1;
             // stage u plane m+1 into the slot of plane m-3 (read two steps
             // ago); its register set also carries f plane m
             const int ri = (dd + 2) % D;
             stash(m + 1, pre[ri]);
             lds_barrier();
-            {
+            if (live) {
                 const T cx = tcx(m), cy = tcy(m), d = tdd(m);
                 const T *P = U + (m & 3) * USLOT;
                 const T *Pm = U + ((m - 1) & 3) * USLOT;
@@ -920,6 +937,7 @@ __global__ __launch_bounds__(kThreads) void k_restrict3(const LevelItem *__restr
             }
             fetch(min(m + 1 + D, ptop), pre[ri], fpre[ri]);
             lds_barrier();
+            if (!live) continue;
             auto row = [&](int w) {
                 return q4 * R[w * kRRX + cc - 1] + h2 * R[w * kRRX + cc] + q4 * R[w * kRRX + cc + 1];
             };
@@ -1097,21 +1115,29 @@ __global__ __launch_bounds__(kThreads) void k_ir3(const LevelItem *__restrict__ 
     tcy.load(coef, kb, 1, nz);
     tdd.load(coef, kb, 2, nz);
 #pragma unroll
-    for (int q = 0; q < D; ++q) fetch(min(pbase + q, ptop), pre[q], epre[q]);
+    for (int q = 0; q < D; ++q) {
+        fetch(min(pbase + q, ptop), pre[q], epre[q]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
     stash(pbase, pre[0], epre[0]);
     stash(pbase + 1, pre[1], epre[1]);
     fetch(min(pbase + D, ptop), pre[0], epre[0]);
+    __builtin_amdgcn_sched_barrier(0);
     fetch(min(pbase + D + 1, ptop), pre[1], epre[1]);
+    __builtin_amdgcn_sched_barrier(0);
+    // whole rounds of D steps (one back edge, so the compiler's waits hold
+    // only the oldest register set); a step past ke - 1 only stages and
+    // fetches
     for (int m0 = kb; m0 < ke; m0 += D) {
 #pragma unroll
         for (int dd = 0; dd < D; ++dd) {
             const int m = m0 + dd;
-            if (m >= ke) break;
             // plane m+1 goes into the slot of plane m-3 (read two steps ago)
             const int ri = (dd + 2) % D;
             stash(m + 1, pre[ri], epre[ri]);
             fetch(min(m + 1 + D, ptop), pre[ri], epre[ri]);
             lds_barrier();
+            if (m >= ke) continue;
             const double cx = tcx(m), cy = tcy(m), d = tdd(m);
             const double *P = S + (m & 3) * SLOT;
             const double *Pm = S + ((m - 1) & 3) * SLOT;
@@ -1481,7 +1507,10 @@ __global__ __launch_bounds__(kThreads) void k_fields(const FieldsItem *__restric
     // refills its set unconditionally (past the top it repeats the last
     // plane), so the compiler can wait for exactly the oldest set
 #pragma unroll
-    for (int q = 0; q < D; ++q) fetch(kb + 2 + q, pre[q]);
+    for (int q = 0; q < D; ++q) {
+        fetch(kb + 2 + q, pre[q]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
     lds_barrier();
     bz_plane(q0);
     bz_plane(q0 + 1);

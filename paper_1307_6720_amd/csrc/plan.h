@@ -143,6 +143,8 @@ void add_ir_step(Program &pg, Staging &st, const Hierarchy &h, const double *uin
 FieldsItem fields_item(const mhs_plan *p, const mhs_model *model, const double *tab, const double *P, double *Bx,
                        double *By, double *Bz, double *pr, double *rho);
 hipError_t exec_launch(const Launch &L, hipStream_t s);
+// Next timing event of the profiler's pool (created on first use); nullptr on failure.
+hipEvent_t prof_event(Profiler &pr);
 
 } // namespace mhs
 

@@ -284,6 +284,26 @@ class Batch:
     def release(self, slot):
         check(_lib.lib().mhs_batch_release(self.h, slot))
 
+    def profile(self, enable=True, classes=None):
+        """Time merged launches of the given classes (names from
+        PROF_NAMES; all by default); enable=False turns profiling off."""
+        mask = 0
+        if enable:
+            for n in (_lib.PROF_NAMES if classes is None else classes):
+                mask |= 1 << _lib.PROF_NAMES.index(n)
+        check(_lib.lib().mhs_batch_profile_enable(self.h, mask))
+
+    def profile_read(self, reset=False):
+        """{class: (total_ms, launches, compulsory_bytes)} since the last reset."""
+        out = {}
+        for k, name in enumerate(_lib.PROF_NAMES):
+            ms, n, b = C.c_double(), C.c_int64(), C.c_double()
+            check(_lib.lib().mhs_batch_profile_read(self.h, k, C.byref(ms), C.byref(n), C.byref(b), 0))
+            out[name] = (ms.value, n.value, b.value)
+        if reset:
+            check(_lib.lib().mhs_batch_profile_read(self.h, 0, None, None, None, 1))
+        return out
+
 
 @dataclass
 class Resident:
