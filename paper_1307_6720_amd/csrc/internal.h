@@ -24,8 +24,11 @@ constexpr int kMaxLevels = 16;
 #ifndef MHS_RING_DEPTH_F
 #define MHS_RING_DEPTH_F 2
 #endif
+// The 3D smoother is unrolled over ten steps; without a bound the register
+// allocator may take more than 128 VGPRs and drop below four workgroups per
+// compute unit, which the level-0 launch (four workgroups per CU) needs.
 #ifndef MHS_SWEEP_ATTR
-#define MHS_SWEEP_ATTR
+#define MHS_SWEEP_ATTR __attribute__((amdgpu_waves_per_eu(4)))
 #endif
 #ifndef MHS_SWEEP_HP32
 #define MHS_SWEEP_HP32 48

@@ -41,6 +41,38 @@ __device__ __forceinline__ const MHS_CONST T *gconst(const void *p)
     return (const MHS_CONST T *)p;
 }
 
+// One plane of an array as a buffer resource (base address and byte length
+// in scalar registers): loads and stores then take a 32-bit per-lane byte
+// offset with no 64-bit address arithmetic per access, and an offset at or
+// past the length reads zero.  Word 3 selects raw 32-bit dword access.
+constexpr int kBufWord3 = 0x00020000;
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const MHS_GLOBAL T *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)bytes, kBufWord3);
+}
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+
 template <typename Item>
 __device__ __forceinline__ int find_item(const Item *items, int n, int tile)
 {
@@ -245,7 +277,7 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     // multiple of five and of the ring depth, so within a round every slot
     // and register set is a compile-time constant: LDS accesses take their
     // slot as an immediate offset and no step computes a modulo.
-    constexpr int kRound = 10;
+    constexpr int kRound = D % kSlots == 0 ? D : kSlots * D; // lcm(5, D) for D < 5
     static_assert(kRound % kSlots == 0 && kRound % D == 0, "round must cycle slots and ring");
     // every staged array has one spare cell past its data: lanes without a
     // cell store there, so staging is straight-line code (no divergent
@@ -450,16 +482,17 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     // Loads are unconditional, from clamped in-bounds addresses, straight
     // into the ring registers; cells outside the array are zeroed when the
     // plane is staged.
+    const uint32_t plane_bytes = es * (uint32_t)sxy;
     auto fetch = [&](int p, T(&dst)[kWPer], T(&fdst)[HAS_F ? kFPer3 : 1], T(&cdst)[PROLONG ? kCPer : 1]) {
         if constexpr (!ZERO_IN) {
-            const MHS_GLOBAL T *pl = uin + sxy * (size_t)p;
+            const auto rs = plane_rsrc(uin + sxy * (size_t)p, plane_bytes);
 #pragma unroll
-            for (int r = 0; r < kWPer; ++r) dst[r] = at(pl, st_g[r]);
+            for (int r = 0; r < kWPer; ++r) dst[r] = bload<T>(rs, st_g[r]);
         }
         if constexpr (HAS_F) {
-            const MHS_GLOBAL T *pl = f + sxy * (size_t)p;
+            const auto rs = plane_rsrc(f + sxy * (size_t)p, plane_bytes);
 #pragma unroll
-            for (int r = 0; r < kFPer3; ++r) fdst[r] = at(pl, f_g[r]);
+            for (int r = 0; r < kFPer3; ++r) fdst[r] = bload<T>(rs, f_g[r]);
         }
         fetch_coarse(p + 1, cdst);
     };
@@ -521,10 +554,10 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     // tile nodes of plane m from LDS to u_out
     auto write_plane = [&](int m, int sl) {
         const T *P = S + sl * SLOT;
-        MHS_GLOBAL T *ol = uout + sxy * (size_t)m;
+        const auto rs = plane_rsrc(uout + sxy * (size_t)m, plane_bytes);
 #pragma unroll
         for (int q = 0; q < kOwn; ++q)
-            if ((ow_ok >> q) & 1) *(MHS_GLOBAL T *)((MHS_GLOBAL char *)ol + ow_g[q]) = P[lo16(ow[q])];
+            if ((ow_ok >> q) & 1) bstore(P[lo16(ow[q])], rs, ow_g[q]);
     };
 
     double acc = 0.0;
@@ -564,99 +597,120 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
         zy_rows(kb);
         lds_barrier();
     }
+    // the two sets in issue order, as the steps issue them (interleaved, the
+    // first wait of every round would have to cover both)
     fetch(min(pbase + D, ptop), pre[0], fpre[0], cpre[0]);
+    __builtin_amdgcn_sched_barrier(0);
     fetch(min(pbase + D + 1, ptop), pre[1], fpre[1], cpre[1]);
+    __builtin_amdgcn_sched_barrier(0);
 
-    for (int s0 = kb - 1; s0 <= ke; s0 += kRound) {
+    // One step: stage plane s+1, red of plane s, black of plane s-1, write
+    // of plane s-2.  ri is the register set of plane s+1; sm2 .. sp1 are the
+    // slots of planes s-2 .. s+1.
+    auto step = [&](const int s, const int ri, const int sm2, const int sm1, const int s00, const int sp1) {
+        // stage plane s+1 (slot of plane s-4; the previous step's black
+        // phase may still read planes s-3 .. s-1) and refill its register
+        // set with plane s+1+D.  Both are unconditional (past the top of
+        // the chunk they repeat the last plane, and a stage of plane nz
+        // lands in a slot no phase reads) so that every step issues the
+        // same loads and the compiler can wait for the oldest set only.
+        stash(s + 1, sp1, pre[ri], fpre[ri], cpre[ri]);
+        fetch(min(s + 1 + D, ptop), pre[ri], fpre[ri], cpre[ri]);
+        // keep each step's loads in its step (moved across steps, the
+        // waits of the next stage would cover the wrong register set)
+        __builtin_amdgcn_sched_barrier(0);
+        lds_barrier();
+        const T *Ps = S + s00 * SLOT;
+        const T *Pu = S + sp1 * SLOT;
+        const T *Pd = S + sm1 * SLOT;
+        if constexpr (NORM) {
+            // residual of the input iterate at plane s (all values still
+            // old); old plane s-1 comes from registers captured a step ago
+            const bool do_res = (s >= kb && s < ke);
+            T cx = 0, cy = 0, dd = 0;
+            if (do_res) {
+                cx = tcx(s);
+                cy = tcy(s);
+                dd = tdd(s);
+            }
+            const T *Fs = F + s00 * FSLOT;
 #pragma unroll
-        for (int d = 0; d < kRound; ++d) {
+            for (int q = 0; q < kOwn; ++q) {
+                const int o = lo16(ow[q]), ww = hi16(ow[q]);
+                const T uc = Ps[o];
+                if (do_res && ((ow_ok >> q) & 1)) {
+                    T fv = (T)0;
+                    if constexpr (HAS_F) fv = Fs[q ? hi16(owf) : lo16(owf)];
+                    const T r = fv - (cx * (Ps[ww + 1] + Ps[ww]) + cy * (Ps[o + RW] + Ps[o - RW]) +
+                                      cz * (Pu[o] + below[q]) + dd * uc);
+                    acc += (double)r * (double)r;
+                }
+                below[q] = uc;
+            }
+            lds_barrier();
+        }
+        // z-y rows of plane s+2, whose coarse planes were staged with s+1
+        zy_rows(s + 2);
+        // write plane s-2, final since black(s-2) ended before the barrier
+        if (s - 2 >= kb && s - 2 < ke) write_plane(s - 2, sm2);
+        // red nodes of plane s on the tile and its one-node ring
+        if (s >= 1 && s <= nz - 2) {
+            const T cx = tcx(s), cy = tcy(s), invd = tid_(s);
+            T *P = S + s00 * SLOT;
+            const T *Fs = F + s00 * FSLOT;
+            const int ps = (par0 + s) & 1;
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const uint32_t pr = pick(rd0[r], rd1[r], ps);
+                const int o = lo16(pr);
+                if (o == kNone) continue;
+                const int ww = hi16(pr);
+                T fv = (T)0;
+                if constexpr (HAS_F) {
+                    const uint32_t fr = pick(rdf0, rdf1, ps);
+                    fv = Fs[r ? hi16(fr) : lo16(fr)];
+                }
+                P[o] = (fv - (cx * (P[ww + 1] + P[ww]) + cy * (P[o + RW] + P[o - RW]) + cz * (Pu[o] + Pd[o]))) *
+                       invd;
+            }
+        }
+        lds_barrier();
+        // black nodes of plane m = s - 1 on the tile
+        const int m = s - 1;
+        if (m >= kb && m < ke) {
+            const T cx = tcx(m), cy = tcy(m), invd = tid_(m);
+            T *P = S + sm1 * SLOT;
+            const T *Pm = S + sm2 * SLOT;
+            const T *Fm = F + sm1 * FSLOT;
+            const int pb = (par0 + m) & 1;
+            const uint32_t pr = pick(bk0, bk1, pb);
+            const int o = lo16(pr);
+            if (o != kNone) {
+                const int ww = hi16(pr);
+                T fv = (T)0;
+                if constexpr (HAS_F) fv = Fm[pb ? hi16(bkf) : lo16(bkf)];
+                P[o] = (fv - (cx * (P[ww + 1] + P[ww]) + cy * (P[o + RW] + P[o - RW]) + cz * (Ps[o] + Pm[o]))) *
+                       invd;
+            }
+        }
+    };
+    // Whole rounds with constant slots and register sets (no exit inside a
+    // round: an early exit would add paths into later steps on which the
+    // newest loads belong to another set, and the compiler's waits would
+    // then drain the ring), then the remaining steps with slots computed.
+    int s0 = kb - 1;
+    for (; s0 + kRound - 1 <= ke; s0 += kRound) {
+#pragma unroll
+        for (int d = 0; d < kRound; ++d)
+            step(s0 + d, (d + 2) % D, (d + 4) % kSlots, d % kSlots, (d + 1) % kSlots, (d + 2) % kSlots);
+    }
+    for (; s0 <= ke; s0 += D) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
             const int s = s0 + d;
             if (s > ke) break;
-            // slots of planes s-2 .. s+1 (plane s is kb - 1 + d + kRound i)
-            const int sm2 = (d + 4) % kSlots, sm1 = d % kSlots, s00 = (d + 1) % kSlots, sp1 = (d + 2) % kSlots;
-            // stage plane s+1 (slot of plane s-4; the previous step's black
-            // phase may still read planes s-3 .. s-1) and refill its register
-            // set with plane s+1+D.  Both are unconditional (past the top of
-            // the chunk they repeat the last plane, and a stage of plane nz
-            // lands in a slot no phase reads) so that every step issues the
-            // same loads and the compiler can wait for the oldest set only.
-            const int ri = (d + 2) % D;
-            stash(s + 1, sp1, pre[ri], fpre[ri], cpre[ri]);
-            fetch(min(s + 1 + D, ptop), pre[ri], fpre[ri], cpre[ri]);
-            lds_barrier();
-            const T *Ps = S + s00 * SLOT;
-            const T *Pu = S + sp1 * SLOT;
-            const T *Pd = S + sm1 * SLOT;
-            if constexpr (NORM) {
-                // residual of the input iterate at plane s (all values still
-                // old); old plane s-1 comes from registers captured a step ago
-                const bool do_res = (s >= kb && s < ke);
-                T cx = 0, cy = 0, dd = 0;
-                if (do_res) {
-                    cx = tcx(s);
-                    cy = tcy(s);
-                    dd = tdd(s);
-                }
-                const T *Fs = F + s00 * FSLOT;
-#pragma unroll
-                for (int q = 0; q < kOwn; ++q) {
-                    const int o = lo16(ow[q]), ww = hi16(ow[q]);
-                    const T uc = Ps[o];
-                    if (do_res && ((ow_ok >> q) & 1)) {
-                        T fv = (T)0;
-                        if constexpr (HAS_F) fv = Fs[q ? hi16(owf) : lo16(owf)];
-                        const T r = fv - (cx * (Ps[ww + 1] + Ps[ww]) + cy * (Ps[o + RW] + Ps[o - RW]) +
-                                          cz * (Pu[o] + below[q]) + dd * uc);
-                        acc += (double)r * (double)r;
-                    }
-                    below[q] = uc;
-                }
-                lds_barrier();
-            }
-            // z-y rows of plane s+2, whose coarse planes were staged with s+1
-            zy_rows(s + 2);
-            // write plane s-2, final since black(s-2) ended before the barrier
-            if (s - 2 >= kb && s - 2 < ke) write_plane(s - 2, sm2);
-            // red nodes of plane s on the tile and its one-node ring
-            if (s >= 1 && s <= nz - 2) {
-                const T cx = tcx(s), cy = tcy(s), invd = tid_(s);
-                T *P = S + s00 * SLOT;
-                const T *Fs = F + s00 * FSLOT;
-                const int ps = (par0 + s) & 1;
-#pragma unroll
-                for (int r = 0; r < 2; ++r) {
-                    const uint32_t pr = pick(rd0[r], rd1[r], ps);
-                    const int o = lo16(pr);
-                    if (o == kNone) continue;
-                    const int ww = hi16(pr);
-                    T fv = (T)0;
-                    if constexpr (HAS_F) {
-                        const uint32_t fr = pick(rdf0, rdf1, ps);
-                        fv = Fs[r ? hi16(fr) : lo16(fr)];
-                    }
-                    P[o] = (fv - (cx * (P[ww + 1] + P[ww]) + cy * (P[o + RW] + P[o - RW]) + cz * (Pu[o] + Pd[o]))) *
-                           invd;
-                }
-            }
-            lds_barrier();
-            // black nodes of plane m = s - 1 on the tile
-            const int m = s - 1;
-            if (m >= kb && m < ke) {
-                const T cx = tcx(m), cy = tcy(m), invd = tid_(m);
-                T *P = S + sm1 * SLOT;
-                const T *Pm = S + sm2 * SLOT;
-                const T *Fm = F + sm1 * FSLOT;
-                const int pb = (par0 + m) & 1;
-                const uint32_t pr = pick(bk0, bk1, pb);
-                const int o = lo16(pr);
-                if (o != kNone) {
-                    const int ww = hi16(pr);
-                    T fv = (T)0;
-                    if constexpr (HAS_F) fv = Fm[pb ? hi16(bkf) : lo16(bkf)];
-                    P[o] = (fv - (cx * (P[ww + 1] + P[ww]) + cy * (P[o + RW] + P[o - RW]) + cz * (Ps[o] + Pm[o]))) *
-                           invd;
-                }
-            }
+            const int t = s - kb + 2; // slot of plane s
+            step(s, (d + 2) % D, (t + 3) % kSlots, (t + 4) % kSlots, t % kSlots, (t + 1) % kSlots);
         }
     }
     // the last planes: ke-2 was written in the final step, ke-1 remains
