@@ -45,7 +45,7 @@ def kernels_digest():
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=18)
+    ap.add_argument("--steps", type=int, default=36)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="mhs-257")
     ap.add_argument("--rtol", type=float, default=1e-10)
@@ -58,7 +58,7 @@ def parse():
                     help="Poisson arrival rate in requests/s (0: 0.5x and 0.9x of the capacity measured "
                          "with every request queued at once)")
     ap.add_argument("--serve-slots", type=int, default=16)
-    ap.add_argument("--batch", type=int, default=6,
+    ap.add_argument("--batch", type=int, default=12,
                     help="concurrent requests in the batched pass over the workload (0: single stream only)")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--counter-probe", action="store_true",

@@ -263,7 +263,12 @@ int mhs_profile_read(mhs_plan *plan, int32_t klass, double *total_ms, int64_t *l
  * mhs_batch_workspace_bytes(max_slots) bytes (256-byte aligned); each slot
  * uses its own plan's workspace for everything else.  Admission policy
  * (memory budget, queueing, plan pooling) belongs to the caller.
- * A batch is used from one host thread; ticks are synchronous. */
+ * A batch is used from one host thread.  Ticks are pipelined two deep:
+ * mhs_batch_step launches tick t and then reads the status of tick t-1
+ * while the device works on tick t, so a request's completion is seen one
+ * call after the tick that completed it, and a request that stopped in
+ * tick t-1 had one more cycle launched in tick t whose kernels exit at
+ * once on its status word (results are unchanged). */
 typedef struct mhs_batch mhs_batch;
 
 /* Device workspace a batch of max_slots (1..1024) slots needs. */
@@ -292,8 +297,10 @@ int mhs_batch_admit(mhs_batch *batch, mhs_plan *plan, const mhs_model *model,
                     const double *d_bz0, double *d_P, double *d_Bx, double *d_By, double *d_Bz,
                     double *d_p, double *d_rho, const mhs_opts *opts, int32_t *slot);
 
-/* One tick on `stream`; returns after the tick's status read-back.
- * *active (optional) receives the number of slots still running. */
+/* Launch one tick on `stream`, then wait for the previous tick and apply
+ * its status (phase changes, completions).  *active (optional) receives the
+ * number of slots still running; call until it is 0.  Use one stream for
+ * every call of a batch (and for the copies into its requests' buffers). */
 int mhs_batch_step(mhs_batch *batch, void *stream, int32_t *active);
 
 /* Status of a slot.  *done = 1 once the request has finished: its fields
@@ -315,7 +322,7 @@ int mhs_batch_release(mhs_batch *batch, int32_t slot);
  * request stops); its compulsory bytes are the sum over the items that
  * ran.  class_mask 0 disables; bits outside MHS_PROF_ALL are
  * MHS_ERR_INVALID_ARG.  profile_read returns the totals since the last
- * reset (ticks are synchronous, so nothing is pending). */
+ * reset over the ticks whose status has been read. */
 int mhs_batch_profile_enable(mhs_batch *batch, int32_t class_mask);
 int mhs_batch_profile_read(mhs_batch *batch, int32_t klass, double *total_ms, int64_t *launches,
                            double *bytes, int32_t reset);

@@ -35,14 +35,16 @@ enum Phase : int { kFree = 0, kBoundary, kInterior, kFinish, kDone };
 
 struct Slot {
     Phase phase = kFree;
-    bool fresh = false; // the current phase starts in the next tick
+    bool fresh = false;       // the current phase starts in the next tick
+    bool finish_sent = false; // the field recovery is launched (kFinish)
+    int64_t epoch = 0;        // identifies the current phase of the current request
     mhs_plan *plan = nullptr;
     double alpha = 0.0, mu0 = 1.0, g = 1.0;
     const double *bz0 = nullptr;
     double *P = nullptr, *Bx = nullptr, *By = nullptr, *Bz = nullptr, *p = nullptr, *rho = nullptr;
     mhs_opts opts{};
     int steps = 0; // programs launched in the current phase
-    int ticks = 0; // ticks in the current phase
+    int ticks = 0; // ticks of the current phase whose status was read
     mhs_info info[2]{};
     std::chrono::steady_clock::time_point t0;
 };
@@ -111,22 +113,46 @@ struct BatchProf {
     hipEvent_t start, end;
 };
 
+// What a tick launched for one slot: the phase and its epoch.  When the
+// tick's status is read, it applies to the slot only if the slot is still
+// in that phase (the epoch matches).
+struct Snap {
+    bool launched = false;
+    Phase phase = kFree;
+    int64_t epoch = 0;
+};
+
+// Buffers of one tick in flight.  Ticks alternate between two of them:
+// tick t is built and launched while tick t-1 still runs, and tick t-1's
+// status is read after that, so the host's work for a tick overlaps the
+// device's work for the previous one.
+struct Tick {
+    Staging stage;                  // merged descriptor tables (pinned host + workspace)
+    SolveState *h_init = nullptr;   // pinned: fresh status words to upload
+    SolveState *h_read = nullptr;   // pinned: status words read back
+    hipEvent_t done = nullptr;      // after the read-back
+    bool live = false;              // launched, status not yet read
+    int top = 0;                    // one past the highest slot launched
+    std::vector<Snap> snap;
+    std::vector<ProfItem> prof_items;
+    std::vector<BatchProf> prof_pending;
+};
+
 } // namespace
 
 struct mhs_batch {
     int max_slots = 0;
     int device = 0;
     SolveState *d_states = nullptr; // per slot, in the workspace
-    SolveState *h_init = nullptr;   // pinned
-    SolveState *h_read = nullptr;   // pinned
-    Staging stage;                  // merged descriptor tables (pinned host + workspace)
+    Tick ticks[2];
+    int64_t tick_no = 0;            // ticks launched
+    int64_t epochs = 0;             // phase epochs handed out
     std::vector<char> rec_buf;      // host recorder of per-request items (one tick)
     Staging rec;
     std::vector<Slot> slots;
     std::vector<Rec> recs;
-    Profiler prof;                  // class mask, event pool and totals
-    std::vector<ProfItem> prof_items;
-    std::vector<BatchProf> prof_pending;
+    Profiler prof;                  // class mask and totals (events: per tick, below)
+    std::vector<hipEvent_t> ev_pool[2];
 };
 
 namespace {
@@ -135,6 +161,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 size_t states_bytes(int max_slots) { return align_up((size_t)max_slots * sizeof(SolveState), kWsAlign); }
 size_t stage_bytes(int max_slots) { return (size_t)max_slots * kSlotStageBytes; }
+constexpr int kTicksInFlight = 2;
 
 // A recorder is a Staging whose "device" side is its own host buffer: the
 // builders put items there and Launch::items points at them.
@@ -308,11 +335,10 @@ bool same_variant(const Launch &a, const Launch &b)
 
 // Fuse recs[lo, hi) (one key, one variant, distinct slots) into one launch
 // whose descriptor table is written into the batch staging area.
-bool merge(mhs_batch *b, const std::vector<const Rec *> &grp, Launch *out)
+bool merge(Staging &st, const std::vector<const Rec *> &grp, Launch *out)
 {
     const Launch &first = grp[0]->L;
     const size_t sz = item_size(first.kind);
-    Staging &st = b->stage;
     st.used = align_up(st.used, kItemAlign);
     if (st.used + sz * grp.size() > st.cap) return false;
     char *host = st.host + st.used;
@@ -374,7 +400,7 @@ int mhs_batch_workspace_bytes(int32_t max_slots, size_t *bytes)
     if (!bytes) return fail(MHS_ERR_INVALID_ARG, "bytes is NULL");
     if (max_slots < 1 || max_slots > kMaxBatchSlots)
         return fail(MHS_ERR_INVALID_ARG, "max_slots must be in 1..%d", kMaxBatchSlots);
-    *bytes = states_bytes(max_slots) + stage_bytes(max_slots);
+    *bytes = states_bytes(max_slots) + kTicksInFlight * stage_bytes(max_slots);
     return MHS_OK;
 }
 
@@ -396,16 +422,21 @@ int mhs_batch_create(int32_t max_slots, void *d_ws, size_t ws_bytes, mhs_batch *
         return fail(MHS_ERR_HIP, "hipGetDevice failed");
     }
     b->d_states = (SolveState *)d_ws;
-    b->stage.dev = (char *)d_ws + states_bytes(max_slots);
-    b->stage.cap = stage_bytes(max_slots);
     b->rec_buf.resize(stage_bytes(max_slots));
-    if (hipHostMalloc((void **)&b->stage.host, b->stage.cap, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&b->h_init, (size_t)max_slots * sizeof(SolveState), hipHostMallocDefault) !=
-            hipSuccess ||
-        hipHostMalloc((void **)&b->h_read, (size_t)max_slots * sizeof(SolveState), hipHostMallocDefault) !=
-            hipSuccess) {
-        mhs_batch_destroy(b);
-        return fail(MHS_ERR_HIP, "pinned host allocation failed");
+    for (int k = 0; k < kTicksInFlight; ++k) {
+        Tick &t = b->ticks[k];
+        t.stage.dev = (char *)d_ws + states_bytes(max_slots) + (size_t)k * stage_bytes(max_slots);
+        t.stage.cap = stage_bytes(max_slots);
+        t.snap.resize((size_t)max_slots);
+        if (hipHostMalloc((void **)&t.stage.host, t.stage.cap, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&t.h_init, (size_t)max_slots * sizeof(SolveState), hipHostMallocDefault) !=
+                hipSuccess ||
+            hipHostMalloc((void **)&t.h_read, (size_t)max_slots * sizeof(SolveState), hipHostMallocDefault) !=
+                hipSuccess ||
+            hipEventCreateWithFlags(&t.done, hipEventDisableTiming) != hipSuccess) {
+            mhs_batch_destroy(b);
+            return fail(MHS_ERR_HIP, "pinned host allocation or event creation failed");
+        }
     }
     *out = b;
     return MHS_OK;
@@ -414,10 +445,16 @@ int mhs_batch_create(int32_t max_slots, void *d_ws, size_t ws_bytes, mhs_batch *
 int mhs_batch_destroy(mhs_batch *b)
 {
     if (!b) return MHS_OK;
-    for (hipEvent_t e : b->prof.pool) (void)hipEventDestroy(e);
-    if (b->stage.host) (void)hipHostFree(b->stage.host);
-    if (b->h_init) (void)hipHostFree(b->h_init);
-    if (b->h_read) (void)hipHostFree(b->h_read);
+    for (Tick &t : b->ticks) {
+        // a tick still in flight copies into the pinned buffers freed below
+        if (t.live && t.done) (void)hipEventSynchronize(t.done);
+        if (t.done) (void)hipEventDestroy(t.done);
+        if (t.stage.host) (void)hipHostFree(t.stage.host);
+        if (t.h_init) (void)hipHostFree(t.h_init);
+        if (t.h_read) (void)hipHostFree(t.h_read);
+    }
+    for (auto &pool : b->ev_pool)
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
     delete b;
     return MHS_OK;
 }
@@ -485,6 +522,8 @@ int mhs_batch_admit(mhs_batch *b, mhs_plan *plan, const mhs_model *model, const 
 
     S.phase = kBoundary;
     S.fresh = true;
+    S.finish_sent = false;
+    S.epoch = ++b->epochs;
     S.steps = 0;
     S.ticks = 0;
     S.t0 = std::chrono::steady_clock::now();
@@ -500,37 +539,48 @@ int mhs_batch_step(mhs_batch *b, void *stream, int32_t *n_active)
     int cur = -1;
     HIPCHK(hipGetDevice(&cur));
     if (cur != b->device) HIPCHK(hipSetDevice(b->device));
+    if (n_active) *n_active = 0;
 
-    // 1. record every active request's program for this tick
+    // Tick t uses buffer t % 2, last used by tick t-2, whose status the
+    // previous call read (after waiting for it).
+    Tick &T = b->ticks[b->tick_no & 1];
+    Tick &prev = b->ticks[(b->tick_no + 1) & 1];
+
+    // 1. record the programs of every slot with work to launch, from the
+    // phases known now (a request that stopped in the tick still in flight
+    // gets one more cycle, whose launches exit at once on its status word)
     reset_recorder(b);
     b->recs.clear();
-    int top = 0; // one past the highest active slot
+    int top = 0;
     for (int i = 0; i < b->max_slots; ++i) {
         Slot &S = b->slots[(size_t)i];
-        if (!active(S.phase)) continue;
+        Snap &sn = T.snap[(size_t)i];
+        sn.launched = false;
+        if (!active(S.phase) || (S.phase == kFinish && S.finish_sent)) continue;
         top = i + 1;
-        if (S.fresh && S.phase != kFinish) b->h_init[i] = initial_state(S.opts.rtol, S.opts.max_cycles);
+        if (S.fresh && S.phase != kFinish) T.h_init[i] = initial_state(S.opts.rtol, S.opts.max_cycles);
         if (!build_slot(S, i, b->d_states + i, b->rec, b->recs))
             return fail(MHS_ERR_WORKSPACE, "descriptor recorder exhausted");
+        sn.launched = true;
+        sn.phase = S.phase;
+        sn.epoch = S.epoch;
     }
-    if (n_active) *n_active = 0;
-    if (top == 0) return MHS_OK;
+    T.top = top;
 
     // 2. merge equal (key, variant) launches across requests
     std::stable_sort(b->recs.begin(), b->recs.end(), [](const Rec &x, const Rec &y) { return x.key < y.key; });
     std::vector<Launch> plan_launches;
     std::vector<std::pair<size_t, size_t>> launch_items; // per launch: its items in prof_items
     const bool profiling = b->prof.mask != 0;
-    b->prof_items.clear();
-    b->prof_pending.clear();
-    b->prof.next = 0;
+    T.prof_items.clear();
+    T.prof_pending.clear();
     auto note_items = [&](const std::vector<const Rec *> &g) {
-        const size_t first = b->prof_items.size();
+        const size_t first = T.prof_items.size();
         if (profiling)
-            for (const Rec *r : g) b->prof_items.push_back({r->slot, r->L.pre, r->L.bytes});
+            for (const Rec *r : g) T.prof_items.push_back({r->slot, r->L.pre, r->L.bytes});
         launch_items.emplace_back(first, g.size());
     };
-    b->stage.used = 0;
+    T.stage.used = 0;
     std::vector<const Rec *> grp;
     for (size_t lo = 0; lo < b->recs.size();) {
         size_t hi = lo;
@@ -552,85 +602,116 @@ int mhs_batch_step(mhs_batch *b, void *stream, int32_t *n_active)
                     taken[c - lo] = true;
                 }
             Launch M{};
-            if (!merge(b, grp, &M)) return fail(MHS_ERR_WORKSPACE, "batch descriptor table exhausted");
+            if (!merge(T.stage, grp, &M)) return fail(MHS_ERR_WORKSPACE, "batch descriptor table exhausted");
             plan_launches.push_back(M);
             note_items(grp);
         }
         lo = hi;
     }
 
-    // 3. descriptors and fresh status words to the device, then the launches
-    if (b->stage.used) HIPCHK(hipMemcpyAsync(b->stage.dev, b->stage.host, b->stage.used, hipMemcpyHostToDevice, s));
-    for (int i = 0; i < top; ++i) {
-        const Slot &S = b->slots[(size_t)i];
-        if (active(S.phase) && S.fresh && S.phase != kFinish)
-            HIPCHK(hipMemcpyAsync(b->d_states + i, b->h_init + i, sizeof(SolveState), hipMemcpyHostToDevice, s));
-    }
-    for (size_t q = 0; q < plan_launches.size(); ++q) {
-        const Launch &L = plan_launches[q];
-        const bool timed = profiling && L.prof >= 0 && ((b->prof.mask >> L.prof) & 1) != 0;
-        BatchProf rec{};
-        if (timed) {
-            rec.klass = L.prof;
-            rec.first = launch_items[q].first;
-            rec.count = launch_items[q].second;
-            rec.start = prof_event(b->prof);
-            rec.end = prof_event(b->prof);
-            if (!rec.start || !rec.end) return fail(MHS_ERR_HIP, "event creation failed");
-            HIPCHK(hipEventRecord(rec.start, s));
-        }
-        const hipError_t e = exec_launch(L, s);
-        if (e != hipSuccess) return fail(MHS_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
-        if (timed) {
-            HIPCHK(hipEventRecord(rec.end, s));
-            b->prof_pending.push_back(rec);
-        }
-    }
-    HIPCHK(hipMemcpyAsync(b->h_read, b->d_states, (size_t)top * sizeof(SolveState), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-
-    // 4a. timed launches: count the items that ran (stopped[i]: slot i's
-    // solve stopped at this tick's check, so its later launches exited)
-    if (!b->prof_pending.empty()) {
-        std::vector<char> stopped((size_t)top, 0);
+    // 3. descriptors and fresh status words to the device, the launches,
+    // then the status read-back
+    if (top > 0) {
+        if (T.stage.used)
+            HIPCHK(hipMemcpyAsync(T.stage.dev, T.stage.host, T.stage.used, hipMemcpyHostToDevice, s));
         for (int i = 0; i < top; ++i) {
             const Slot &S = b->slots[(size_t)i];
-            stopped[(size_t)i] = (S.phase == kBoundary || S.phase == kInterior) && b->h_read[i].done != kRunning;
+            if (T.snap[(size_t)i].launched && S.fresh && S.phase != kFinish)
+                HIPCHK(hipMemcpyAsync(b->d_states + i, T.h_init + i, sizeof(SolveState), hipMemcpyHostToDevice, s));
         }
-        for (const BatchProf &r : b->prof_pending) {
-            double bytes = 0.0;
-            bool ran = false;
-            for (size_t k = r.first; k < r.first + r.count; ++k) {
-                const ProfItem &it = b->prof_items[k];
-                if (it.pre || !stopped[(size_t)it.slot]) {
-                    bytes += it.bytes;
-                    ran = true;
-                }
+        std::vector<hipEvent_t> &pool = b->ev_pool[b->tick_no & 1];
+        size_t ev_next = 0;
+        auto event = [&]() -> hipEvent_t {
+            if (ev_next == pool.size()) {
+                hipEvent_t e = nullptr;
+                if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
+                pool.push_back(e);
             }
-            if (!ran) continue;
-            float ms = 0.0f;
-            HIPCHK(hipEventElapsedTime(&ms, r.start, r.end));
-            b->prof.ms[r.klass] += ms;
-            b->prof.bytes[r.klass] += bytes;
-            b->prof.launches[r.klass] += 1;
+            return pool[ev_next++];
+        };
+        for (size_t q = 0; q < plan_launches.size(); ++q) {
+            const Launch &L = plan_launches[q];
+            const bool timed = profiling && L.prof >= 0 && ((b->prof.mask >> L.prof) & 1) != 0;
+            BatchProf rec{};
+            if (timed) {
+                rec.klass = L.prof;
+                rec.first = launch_items[q].first;
+                rec.count = launch_items[q].second;
+                rec.start = event();
+                rec.end = event();
+                if (!rec.start || !rec.end) return fail(MHS_ERR_HIP, "event creation failed");
+                HIPCHK(hipEventRecord(rec.start, s));
+            }
+            const hipError_t e = exec_launch(L, s);
+            if (e != hipSuccess) return fail(MHS_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+            if (timed) {
+                HIPCHK(hipEventRecord(rec.end, s));
+                T.prof_pending.push_back(rec);
+            }
         }
-        b->prof_pending.clear();
+        HIPCHK(hipMemcpyAsync(T.h_read, b->d_states, (size_t)top * sizeof(SolveState), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipEventRecord(T.done, s));
+        T.live = true;
+        for (int i = 0; i < top; ++i) {
+            Slot &S = b->slots[(size_t)i];
+            if (!T.snap[(size_t)i].launched) continue;
+            S.fresh = false;
+            S.steps += 1;
+            if (S.phase == kFinish) S.finish_sent = true;
+        }
     }
+    b->tick_no += 1;
 
-    // 4. phase transitions
-    int running = 0;
-    for (int i = 0; i < top; ++i) {
-        Slot &S = b->slots[(size_t)i];
-        if (!active(S.phase)) continue;
-        S.fresh = false;
-        S.steps += 1;
-        S.ticks += 1;
-        if (S.phase == kFinish) {
-            S.phase = kDone;
-            continue;
+    // 4. read the previous tick's status (the device is now busy with this
+    // tick) and advance the phases of the requests it covered
+    if (prev.live) {
+        HIPCHK(hipEventSynchronize(prev.done));
+        prev.live = false;
+        // a slot's status applies while the slot is still in the phase the
+        // tick launched (the epoch matches)
+        auto current = [&](int i) {
+            const Snap &sn = prev.snap[(size_t)i];
+            return sn.launched && b->slots[(size_t)i].epoch == sn.epoch;
+        };
+        if (!prev.prof_pending.empty()) {
+            std::vector<char> ran_all((size_t)prev.top, 0), ran_pre((size_t)prev.top, 0);
+            for (int i = 0; i < prev.top; ++i) {
+                if (!current(i)) continue; // its launches exited at once
+                const Snap &sn = prev.snap[(size_t)i];
+                const bool stopped = (sn.phase == kBoundary || sn.phase == kInterior) && prev.h_read[i].done != kRunning;
+                ran_pre[(size_t)i] = 1;
+                ran_all[(size_t)i] = stopped ? 0 : 1;
+            }
+            for (const BatchProf &r : prev.prof_pending) {
+                double bytes = 0.0;
+                bool ran = false;
+                for (size_t k = r.first; k < r.first + r.count; ++k) {
+                    const ProfItem &it = prev.prof_items[k];
+                    if (it.pre ? ran_pre[(size_t)it.slot] : ran_all[(size_t)it.slot]) {
+                        bytes += it.bytes;
+                        ran = true;
+                    }
+                }
+                if (!ran) continue;
+                float ms = 0.0f;
+                HIPCHK(hipEventElapsedTime(&ms, r.start, r.end));
+                b->prof.ms[r.klass] += ms;
+                b->prof.bytes[r.klass] += bytes;
+                b->prof.launches[r.klass] += 1;
+            }
+            prev.prof_pending.clear();
         }
-        const SolveState &ss = b->h_read[i];
-        if (ss.done != kRunning) {
+        for (int i = 0; i < prev.top; ++i) {
+            if (!current(i)) continue;
+            Slot &S = b->slots[(size_t)i];
+            S.ticks += 1;
+            if (S.phase == kFinish) {
+                S.phase = kDone;
+                S.epoch = ++b->epochs;
+                continue;
+            }
+            const SolveState &ss = prev.h_read[i];
+            if (ss.done == kRunning) continue;
             const int q = S.phase == kBoundary ? 0 : 1;
             mhs_info &inf = S.info[q];
             inf.status = status_of(ss.done);
@@ -640,17 +721,21 @@ int mhs_batch_step(mhs_batch *b, void *stream, int32_t *n_active)
             inf.r0 = ss.r0;
             inf.rel_residual = ss.r0 > 0 ? ss.rnorm / ss.r0 : 0.0;
             inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - S.t0).count();
+            S.epoch = ++b->epochs;
             if (inf.status != MHS_OK) {
                 S.phase = kDone;
                 continue;
             }
             S.phase = q == 0 ? kInterior : kFinish;
             S.fresh = true;
+            S.finish_sent = false;
             S.steps = 0;
             S.ticks = 0;
         }
-        ++running;
     }
+    int running = 0;
+    for (const Slot &S : b->slots)
+        if (active(S.phase)) ++running;
     if (n_active) *n_active = running;
     return MHS_OK;
 }

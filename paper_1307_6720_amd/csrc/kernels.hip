@@ -1075,9 +1075,14 @@ template <bool HAS_E>
 __global__ __launch_bounds__(kThreads) void k_ir3(const LevelItem *__restrict__ items, int nitems)
 {
     constexpr int D = kDepth;
-    constexpr int SLOT = kIWY * kIWX;
+    constexpr int SLOT = kIWY * kIWX + 1; // one spare cell: stores of lanes past the window
     constexpr int kOwnI = kTY * kTX / kThreads;
-    __shared__ double S[4 * SLOT];
+    // four slots; the march runs in rounds of four steps (a multiple of the
+    // ring depth), so within a round every slot is a compile-time constant
+    constexpr int kSlotsI = 4;
+    constexpr int kRoundI = 4;
+    static_assert(kRoundI % D == 0, "round must cycle the ring");
+    __shared__ double S[kSlotsI * SLOT];
     __shared__ double red[kThreads / 64];
     const int tile = xcd_tile();
     const LevelItem *it = items + find_item(items, nitems, tile);
@@ -1099,11 +1104,13 @@ __global__ __launch_bounds__(kThreads) void k_ir3(const LevelItem *__restrict__ 
     const int kb = 1 + tz * kz;
     const int ke = min(kb + kz, nz - 1);
     const size_t sxy = (size_t)nx * ny;
+    const uint32_t plane_elems = (uint32_t)sxy;
     const int tid = threadIdx.x;
 
     // ---- per-thread geometry, fixed for the whole z-march ------------------
-    // window cells staged: LDS index, element offset of the clamped source,
-    // inside-array and interior flags
+    // window cells staged: LDS index (the spare cell past the window), byte
+    // offsets of the clamped source in an FP64 and an FP32 plane, inside-
+    // array and interior flags
     int st_l[kIPer];
     uint32_t st_g[kIPer];
     uint32_t st_in = 0, st_int = 0;
@@ -1113,12 +1120,14 @@ __global__ __launch_bounds__(kThreads) void k_ir3(const LevelItem *__restrict__ 
         const int ee = min(e, kICells - 1);
         const int w = ee / kIWX, c = ee - w * kIWX;
         const int i = i0 - 1 + c, j = j0 - 1 + w;
-        st_l[r] = e < kICells ? ee : -1;
+        st_l[r] = e < kICells ? ee : SLOT - 1;
         st_g[r] = (uint32_t)(min(max(i, 0), nx - 1) + nx * min(max(j, 0), ny - 1));
         if (i < nx && j < ny) st_in |= 1u << r;
         if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2) st_int |= 1u << r;
     }
-    // tile nodes this thread updates
+    // tile nodes this thread updates: LDS index and element offset; a node
+    // outside the array gets an offset past the end of the plane, where the
+    // buffer store is dropped
     int ow_l[kOwnI];
     uint32_t ow_g[kOwnI];
     uint32_t ow_ok = 0;
@@ -1127,9 +1136,10 @@ __global__ __launch_bounds__(kThreads) void k_ir3(const LevelItem *__restrict__ 
         const int e = tid + q * kThreads;
         const int w = 1 + e / kTX, c = 1 + e % kTX;
         const int i = i0 + c - 1, j = j0 + w - 1;
+        const bool ok = i <= nx - 2 && j <= ny - 2;
         ow_l[q] = w * kIWX + c;
-        ow_g[q] = (uint32_t)(min(i, nx - 1) + nx * min(j, ny - 1));
-        if (i <= nx - 2 && j <= ny - 2) ow_ok |= 1u << q;
+        ow_g[q] = ok ? (uint32_t)(i + nx * j) : plane_elems;
+        if (ok) ow_ok |= 1u << q;
     }
 
     double pre[D][kIPer];
@@ -1137,20 +1147,19 @@ __global__ __launch_bounds__(kThreads) void k_ir3(const LevelItem *__restrict__ 
     // unconditional clamped loads; the correction is added and out-of-array
     // cells are zeroed when the plane is staged
     auto fetch = [&](int p, double(&dst)[kIPer], float(&edst)[HAS_E ? kIPer : 1]) {
-        const MHS_GLOBAL double *pl = uin + sxy * (size_t)p;
-        const MHS_GLOBAL float *el = e32 + sxy * (size_t)p;
+        const auto ru = plane_rsrc(uin + sxy * (size_t)p, 8u * plane_elems);
+        const auto re = plane_rsrc(e32 + sxy * (size_t)p, 4u * plane_elems);
 #pragma unroll
         for (int r = 0; r < kIPer; ++r) {
-            dst[r] = pl[st_g[r]];
-            if constexpr (HAS_E) edst[r] = el[st_g[r]];
+            dst[r] = bload<double>(ru, 8u * st_g[r]);
+            if constexpr (HAS_E) edst[r] = bload<float>(re, 4u * st_g[r]);
         }
     };
-    auto stash = [&](int p, const double(&src)[kIPer], const float(&esrc)[HAS_E ? kIPer : 1]) {
-        double *dst = S + (p & 3) * SLOT;
+    auto stash = [&](int p, int sl, const double(&src)[kIPer], const float(&esrc)[HAS_E ? kIPer : 1]) {
+        double *dst = S + sl * SLOT;
         const bool corr = HAS_E && p >= 1 && p <= nz - 2;
 #pragma unroll
         for (int r = 0; r < kIPer; ++r) {
-            if (st_l[r] < 0) continue;
             double v = ((st_in >> r) & 1) ? src[r] : 0.0;
             if constexpr (HAS_E) {
                 if (corr && ((st_int >> r) & 1)) v += (double)esrc[r];
@@ -1159,9 +1168,10 @@ __global__ __launch_bounds__(kThreads) void k_ir3(const LevelItem *__restrict__ 
         }
     };
     double acc = 0.0;
-    // planes kb-1 .. ke are read; plane p waits in register set (p - pbase) %
-    // D.  Every step issues the same loads (past the top they repeat the
-    // last plane), so the compiler waits for exactly the oldest register set.
+    // planes kb-1 .. ke are read; plane p lives in register set (p - kb + 1)
+    // % D and in slot (p - kb + 1) % 4.  Every step issues the same loads
+    // (past the top they repeat the last plane), so the compiler waits for
+    // exactly the oldest register set.
     const int pbase = kb - 1, ptop = ke;
     // planes kb .. ke-1 (at most kKZ <= 64) of cx, cy, d
     PlaneTab<double> tcx, tcy, tdd;
@@ -1173,42 +1183,51 @@ __global__ __launch_bounds__(kThreads) void k_ir3(const LevelItem *__restrict__ 
         fetch(min(pbase + q, ptop), pre[q], epre[q]);
         __builtin_amdgcn_sched_barrier(0);
     }
-    stash(pbase, pre[0], epre[0]);
-    stash(pbase + 1, pre[1], epre[1]);
+    stash(pbase, 0, pre[0], epre[0]);
+    stash(pbase + 1, 1, pre[1], epre[1]);
     fetch(min(pbase + D, ptop), pre[0], epre[0]);
     __builtin_amdgcn_sched_barrier(0);
     fetch(min(pbase + D + 1, ptop), pre[1], epre[1]);
     __builtin_amdgcn_sched_barrier(0);
-    // whole rounds of D steps (one back edge, so the compiler's waits hold
-    // only the oldest register set); a step past ke - 1 only stages and
-    // fetches
-    for (int m0 = kb; m0 < ke; m0 += D) {
+
+    // step m: stage plane m+1 (into the slot of plane m-3, read two steps
+    // ago), refill its register set, then the update and residual of plane
+    // m (live = m < ke; a step past the top only stages and fetches)
+    auto step = [&](const int m, const bool live, const int ri, const int sm, const int s0, const int sp) {
+        stash(m + 1, sp, pre[ri], epre[ri]);
+        fetch(min(m + 1 + D, ptop), pre[ri], epre[ri]);
+        __builtin_amdgcn_sched_barrier(0);
+        lds_barrier();
+        if (!live) return;
+        const double cx = tcx(m), cy = tcy(m), d = tdd(m);
+        const double *P = S + s0 * SLOT;
+        const double *Pm = S + sm * SLOT;
+        const double *Pp = S + sp * SLOT;
+        const auto ru = plane_rsrc(uout + sxy * (size_t)m, 8u * plane_elems);
+        const auto rr = plane_rsrc(r32 + sxy * (size_t)m, 4u * plane_elems);
+#pragma unroll
+        for (int q = 0; q < kOwnI; ++q) {
+            const int o = ow_l[q];
+            const double uc = P[o];
+            const double r = -(cx * (P[o + 1] + P[o - 1]) + cy * (P[o + kIWX] + P[o - kIWX]) +
+                               cz * (Pp[o] + Pm[o]) + d * uc);
+            if constexpr (HAS_E) bstore(uc, ru, 8u * ow_g[q]);
+            bstore((float)r, rr, 4u * ow_g[q]);
+            acc += ((ow_ok >> q) & 1) ? r * r : 0.0;
+        }
+    };
+    int m0 = kb;
+    for (; m0 + kRoundI <= ke; m0 += kRoundI) {
+#pragma unroll
+        for (int dd = 0; dd < kRoundI; ++dd)
+            step(m0 + dd, true, (dd + 2) % D, dd % kSlotsI, (dd + 1) % kSlotsI, (dd + 2) % kSlotsI);
+    }
+    for (; m0 < ke; m0 += D) {
 #pragma unroll
         for (int dd = 0; dd < D; ++dd) {
             const int m = m0 + dd;
-            // plane m+1 goes into the slot of plane m-3 (read two steps ago)
-            const int ri = (dd + 2) % D;
-            stash(m + 1, pre[ri], epre[ri]);
-            fetch(min(m + 1 + D, ptop), pre[ri], epre[ri]);
-            lds_barrier();
-            if (m >= ke) continue;
-            const double cx = tcx(m), cy = tcy(m), d = tdd(m);
-            const double *P = S + (m & 3) * SLOT;
-            const double *Pm = S + ((m - 1) & 3) * SLOT;
-            const double *Pp = S + ((m + 1) & 3) * SLOT;
-            MHS_GLOBAL double *ul = uout + sxy * (size_t)m;
-            MHS_GLOBAL float *rl = r32 + sxy * (size_t)m;
-#pragma unroll
-            for (int q = 0; q < kOwnI; ++q) {
-                if (!((ow_ok >> q) & 1)) continue;
-                const int o = ow_l[q];
-                const double uc = P[o];
-                const double r = -(cx * (P[o + 1] + P[o - 1]) + cy * (P[o + kIWX] + P[o - kIWX]) +
-                                   cz * (Pp[o] + Pm[o]) + d * uc);
-                if constexpr (HAS_E) ul[ow_g[q]] = uc;
-                rl[ow_g[q]] = (float)r;
-                acc += r * r;
-            }
+            const int t = m - kb + 1; // slot of plane m
+            step(m, m < ke, (dd + 2) % D, (t + 3) % kSlotsI, t % kSlotsI, (t + 1) % kSlotsI);
         }
     }
     const double tot = block_sum<kThreads>(acc, red);
