@@ -117,7 +117,7 @@ SMOOTH_L0_MIX = {"k_sweep3<float, 3>": (1, 8.0), "k_sweep3<float, 1>": (2, 12.0)
 COPY_BYTES = 1 << 30
 
 
-def counter_probe(batch=6, requests=12):
+def counter_probe(batch=12, requests=24):
     """Workload of the FETCH_SIZE / WRITE_SIZE runs: a device copy of
     COPY_BYTES (the calibration kernel: it reads and writes exactly that
     many bytes), two mixed-path equilibria of the 257^3 workload one at a
@@ -210,19 +210,30 @@ def summarize_counters(fetch_csv, write_csv, one_groups=1024):
     W = level0(write, cw, 30e6)
     print(f"calibration: a device copy of {COPY_BYTES} B reads FETCH_SIZE = {cf:.4f} x bytes read, "
           f"WRITE_SIZE = {cw:.4f} x bytes written; counts below are divided by these factors")
-    print("level-0 launches by variant and requests per launch (k): bytes per request")
+    print("level-0 launches by variant and requests per launch (k): bytes per request, over the launches in "
+          "which every request ran (within 10 % of the median; in the tick where a request stops, its items "
+          "exit at once)")
+
+    def full(xs, k):
+        med = sorted(xs)[len(xs) // 2] / k
+        return [x for x in xs if x / k >= 0.9 * med]
+
     meas = alg = 0.0
     for key in sorted(set(F) & set(W)):
         kn, k = key
-        fb, wb = sum(F[key]) / len(F[key]) / k, sum(W[key]) / len(W[key]) / k
+        fk, wk = full(F[key], k), full(W[key], k)
+        fb, wb = sum(fk) / len(fk) / k, sum(wk) / len(wk) / k
         c = SMOOTH_L0_MIX[kn][1]
-        print(f"  {kn:22s} k={k}  launches {len(F[key]):3d}  read {fb / N:5.2f} B/node (compulsory {c - 4:.2f})  "
-              f"write {wb / N:5.2f} B/node (compulsory 4.00)")
+        print(f"  {kn:22s} k={k:2d}  launches {len(fk):3d} of {len(F[key]):3d}  read {fb / N:5.2f} B/node "
+              f"(compulsory {c - 4:.2f})  write {wb / N:5.2f} B/node (compulsory 4.00)")
         if k > 1:
-            meas += sum(F[key]) + sum(W[key]) * len(F[key]) / len(W[key])
-            alg += k * c * N * len(F[key])
+            meas += (fb + wb) * k * len(fk)
+            alg += k * c * N * len(fk)
     tot = sum(c for c, _ in SMOOTH_L0_MIX.values())
-    one = {kn: (sum(F[(kn, 1)]) / len(F[(kn, 1)]) + sum(W[(kn, 1)]) / len(W[(kn, 1)])) for kn in SMOOTH_L0_MIX}
+    one = {}
+    for kn in SMOOTH_L0_MIX:
+        fk, wk = full(F[(kn, 1)], 1), full(W[(kn, 1)], 1)
+        one[kn] = sum(fk) / len(fk) + sum(wk) / len(wk)
     avg = sum(c * one[kn] for kn, (c, _) in SMOOTH_L0_MIX.items()) / tot
     alg1 = sum(c * b for c, b in SMOOTH_L0_MIX.values()) * N / tot
     print(f"one-request launches, class average (1 zero-guess : 2 with f : 1 prolongation): traffic "
@@ -317,8 +328,9 @@ def summarize_trace(stats_csv, trace_csv, marker_csv=None, one_groups=1024, top=
         if ds:
             print(f"  all: {len(ds)} launches, average {statistics.mean(ds):.2f} us")
 
-    table(sm, "## level-0 FP32 smoother launches over the whole run, by requests per launch k")
-    if marker_csv:
+    if not marker_csv:
+        table(sm, "## level-0 FP32 smoother launches over the whole run, by requests per launch k")
+    else:
         with open(marker_csv) as fh:
             marks = list(csv.DictReader(fh))
         for m in marks:
@@ -428,7 +440,7 @@ class _Roctx:
         import ctypes
 
         self.lib = None
-        for name in ("libroctx64.so", "/opt/rocm/lib/libroctx64.so"):
+        for name in ("librocprofiler-sdk-roctx.so", "/opt/rocm/lib/librocprofiler-sdk-roctx.so", "libroctx64.so"):
             try:
                 self.lib = ctypes.CDLL(name)
                 self.lib.roctxRangePushA.argtypes = [ctypes.c_char_p]
