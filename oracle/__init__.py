@@ -12,6 +12,8 @@ computes, written from Section 2.2 of MacTaggart et al. (arXiv:1307.6720):
 * ``fields`` -- recovery of B, p and rho by central differences
   (Section 2.2, equations (5), (6), (9), (10)).
 * ``dense``  -- brute-force dense solves on tiny grids.
+* ``diagnostics`` -- current density, force-balance and divergence residuals
+  of equations (1)-(3) (Section 2.1) by the same differences.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  It shares no code with the HIP path
