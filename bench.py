@@ -635,6 +635,27 @@ def main():
     else:
         roofline = roof_single
 
+    # diagnostics of (1)-(3) on the last equilibrium's fields (off the
+    # solve's path): j, |force residual|, div B; 80 B per node (read 5, write 5)
+    D = tuple(torch.empty_like(P) for _ in range(5))
+    w = runs[(a.steps - 1) % len(runs)]
+    for _ in range(3):
+        plan.diagnostics(w.model, *F, out=D)
+    plan.profile(True, ["diag"])
+    plan.profile_read(reset=True)
+    for _ in range(10):
+        plan.diagnostics(w.model, *F, out=D)
+    torch.cuda.synchronize()
+    dms, dn, dbytes = plan.profile_read(reset=True)["diag"]
+    plan.profile(False)
+    diag_gbps = dbytes / (dms * 1e-3) / 1e9
+    jx, jy, jz = D[0], D[1], D[2]
+    lor = torch.sqrt((jy * F[2] - jz * F[1]) ** 2 + (jz * F[0] - jx * F[2]) ** 2 + (jx * F[1] - jy * F[0]) ** 2)
+    diagnostics = {"kernel": "k_diag", "avg_us": 1e3 * dms / dn, "launches": dn, "bytes_per_node": 80,
+                   "achieved_gbps": diag_gbps, "frac_of_hbm_peak": diag_gbps / HBM_PEAK_GBPS,
+                   "force_residual_over_lorentz": float(D[3].max() / lor.max())}
+    del D, lor
+
     serving = None
     if a.serve_requests > 0:
         serving = serve_leg(a, torch, dev)
@@ -683,6 +704,7 @@ def main():
         "kernels_note": "per-class HIP-event timings from a separate pass with every class timed",
         "roofline": roofline,
         "roofline_single_request": roof_single,
+        "diagnostics": diagnostics,
         "serving": serving,
         "context": {"paper_speedup": "x30 GPU vs serial (x32.4 at 128^3, x29.6 at 256^3); hardware unstated"},
     }

@@ -221,6 +221,24 @@ int mhs_stage_residual_norm(mhs_plan *plan, const mhs_model *model, int32_t spac
                             int32_t level, int32_t precision, const void *d_u, const void *d_f,
                             double *norm, void *stream);
 
+/* ---- diagnostics --------------------------------------------------------- *
+ * Residuals of the MHS equations of Section 2.1 for fields on the plan's
+ * grid (normally those of mhs_fields): j = (curl B)/mu0 from (2), the
+ * magnitude of the force-balance residual |j x B - grad p - rho g e_z| of
+ * (1), and div B of (3), each by second-order differences as in the field
+ * recovery (central in x, y and above the base; one-sided second order,
+ * (-3 f0 + 4 f1 - f2)/(2 dz), on the base plane k = 0).  On the side faces
+ * and the top face, where the recovery sets B = 0, every output is 0.
+ * A converged equilibrium gives fres and divb of the order of the
+ * truncation error (O(h^2) relative to |j x B|).
+ * All arrays are device (nz, ny, nx) FP64, x fastest, caller-owned; inputs
+ * are read only; the ten arrays must not overlap.  model: only mu0 (> 0)
+ * and g are read.  Asynchronous on `stream`; allocates nothing.
+ * Errors: MHS_ERR_INVALID_ARG (NULL pointer, mu0 <= 0), MHS_ERR_HIP. */
+int mhs_diagnostics(mhs_plan *plan, const mhs_model *model, const double *d_Bx, const double *d_By,
+                    const double *d_Bz, const double *d_p, const double *d_rho, double *d_jx,
+                    double *d_jy, double *d_jz, double *d_fres, double *d_divb, void *stream);
+
 /* ---- measurement ------------------------------------------------------- *
  * When profiling is enabled on a plan, each launch of the selected kernel
  * classes below is bracketed by HIP events on the call's stream (select
@@ -236,8 +254,9 @@ int mhs_stage_residual_norm(mhs_plan *plan, const mhs_model *model, int32_t spac
 #define MHS_PROF_FIELDS 3      /* field recovery                          */
 #define MHS_PROF_BOTTOM 4      /* single-workgroup bottom solver          */
 #define MHS_PROF_COARSE 5      /* every other stencil launch (levels >= 1, 2D) */
-#define MHS_PROF_NCLASS 6
-#define MHS_PROF_ALL 0x3f      /* mask of every class                      */
+#define MHS_PROF_DIAG 6        /* diagnostics (mhs_diagnostics)            */
+#define MHS_PROF_NCLASS 7
+#define MHS_PROF_ALL 0x7f      /* mask of every class                      */
 
 /* class_mask: bit (1 << MHS_PROF_x) times class x; 0 disables profiling. */
 int mhs_profile_enable(mhs_plan *plan, int32_t class_mask);

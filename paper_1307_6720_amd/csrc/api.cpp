@@ -1320,6 +1320,59 @@ int mhs_fields(mhs_plan *p, const mhs_model *model, const double *d_P, double *d
     return run_program(p, pg, s);
 }
 
+int mhs_diagnostics(mhs_plan *p, const mhs_model *model, const double *d_Bx, const double *d_By,
+                    const double *d_Bz, const double *d_p, const double *d_rho, double *d_jx, double *d_jy,
+                    double *d_jz, double *d_fres, double *d_divb, void *stream)
+{
+    if (!p || !model || !d_Bx || !d_By || !d_Bz || !d_p || !d_rho || !d_jx || !d_jy || !d_jz || !d_fres || !d_divb)
+        return fail(MHS_ERR_INVALID_ARG, "NULL argument");
+    if (!(model->mu0 > 0.0) || !std::isfinite(model->mu0) || !std::isfinite(model->g))
+        return fail(MHS_ERR_INVALID_ARG, "mu0 must be positive and g finite");
+    int st = set_device(p);
+    if (st) return st;
+    const int nx = p->grid.nx, ny = p->grid.ny, nz = p->grid.nz;
+    DiagItem it{};
+    it.Bx = d_Bx;
+    it.By = d_By;
+    it.Bz = d_Bz;
+    it.p = d_p;
+    it.rho = d_rho;
+    it.jx = d_jx;
+    it.jy = d_jy;
+    it.jz = d_jz;
+    it.fres = d_fres;
+    it.divb = d_divb;
+    it.mu0 = model->mu0;
+    it.g = model->g;
+    it.dx = p->grid.lx / (nx - 1);
+    it.dy = p->grid.ly / (ny - 1);
+    it.dz = p->grid.lz / (nz - 1);
+    it.nx = nx;
+    it.ny = ny;
+    it.nz = nz;
+    it.kz = chunk(nz, ceil_div(nx, 64) * ceil_div(ny, 4), 64, kFieldsTargetGroups);
+    hipStream_t s = (hipStream_t)stream;
+    Profiler &pr = p->prof;
+    const bool timed = ((pr.mask >> MHS_PROF_DIAG) & 1) != 0;
+    ProfRecord rec{};
+    if (timed) {
+        rec.klass = MHS_PROF_DIAG;
+        rec.cycle = -1;
+        rec.bytes = 80.0 * (double)nx * ny * nz;
+        rec.start = prof_event(pr);
+        rec.end = prof_event(pr);
+        if (!rec.start || !rec.end) return fail(MHS_ERR_HIP, "event creation failed");
+        HIPCHK(hipEventRecord(rec.start, s));
+    }
+    const hipError_t e = launch_diag(it, s);
+    if (e != hipSuccess) return fail(MHS_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+    if (timed) {
+        HIPCHK(hipEventRecord(rec.end, s));
+        pr.pending.push_back(rec);
+    }
+    return MHS_OK;
+}
+
 int mhs_profile_enable(mhs_plan *p, int32_t class_mask)
 {
     if (!p) return fail(MHS_ERR_INVALID_ARG, "plan is NULL");

@@ -136,6 +136,17 @@ struct FieldsItem {
     int32_t kz;
 };
 
+// Diagnostics of an equilibrium (current density, force-balance and
+// divergence residuals): one thread per (x, y) column of a z-chunk.
+struct DiagItem {
+    const double *Bx, *By, *Bz, *p, *rho;
+    double *jx, *jy, *jz, *fres, *divb;
+    double mu0, g;
+    double dx, dy, dz;
+    int32_t nx, ny, nz;
+    int32_t kz; // planes per workgroup
+};
+
 // Whole-array preparation items.
 struct PrepItem {
     double *P;          // 3D potential (or the base plane for 2D)
@@ -169,6 +180,7 @@ hipError_t launch_ir3(const LevelItem *items, int nitems, int ntiles, bool has_e
 hipError_t launch_bottom(const BottomItem *items, int nitems, int lds_bytes, bool dbl, hipStream_t s);
 hipError_t launch_finalize(const FinalizeItem *items, int nitems, hipStream_t s);
 hipError_t launch_fields(const FieldsItem *items, int nitems, int ntiles, hipStream_t s);
+hipError_t launch_diag(const DiagItem &item, hipStream_t s);
 hipError_t launch_prep3(const PrepItem *items, int nitems, int64_t nthreads, hipStream_t s);
 hipError_t launch_prep2(const PrepItem *items, int nitems, int64_t nthreads, hipStream_t s);
 hipError_t launch_copy(const double *src, double *dst, int64_t n, const SolveState *skip,

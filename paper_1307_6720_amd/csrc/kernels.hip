@@ -1648,6 +1648,124 @@ __global__ __launch_bounds__(kThreads) void k_fields(const FieldsItem *__restric
 }
 
 // ============================================================================
+// Diagnostics of equations (1)-(3): j = curl B / mu0, the force-balance
+// residual |j x B - grad p - rho g e_z| and div B, by the differences of the
+// field recovery (central; one-sided second order at the base plane), zero on
+// the side and top faces.  One thread per (x, y) column marches a chunk of
+// planes; the values it needs on plane k+1 (its column of Bx, By, Bz, p and
+// their in-plane neighbours, rho) are loaded while plane k is computed.
+// In-plane neighbours come from the caches (the kernel is a diagnostic, off
+// the solve's path).  Contraction is off so that every value is rounded as
+// the differences are written (the oracle evaluates the same expressions).
+// ============================================================================
+constexpr int kDX = 64, kDY = 4;
+static_assert(kDX * kDY == kThreads, "diagnostics tile is one workgroup");
+
+__global__ __launch_bounds__(kThreads) void k_diag(const DiagItem it)
+{
+#pragma clang fp contract(off)
+    const int i = blockIdx.x * kDX + (int)(threadIdx.x % kDX);
+    const int j = blockIdx.y * kDY + (int)(threadIdx.x / kDX);
+    const int nx = it.nx, ny = it.ny, nz = it.nz;
+    if (i >= nx || j >= ny) return;
+    const int k0 = blockIdx.z * it.kz;
+    const int k1 = min(k0 + it.kz, nz);
+    const size_t sxy = (size_t)nx * ny;
+    const size_t col = (size_t)i + (size_t)nx * j;
+    const bool side = i == 0 || i == nx - 1 || j == 0 || j == ny - 1;
+    const MHS_GLOBAL double *Bx = gin<double>(it.Bx), *By = gin<double>(it.By), *Bz = gin<double>(it.Bz);
+    const MHS_GLOBAL double *pp = gin<double>(it.p), *rho = gin<double>(it.rho);
+    MHS_GLOBAL double *ojx = gout<double>(it.jx), *ojy = gout<double>(it.jy), *ojz = gout<double>(it.jz);
+    MHS_GLOBAL double *ofr = gout<double>(it.fres), *odv = gout<double>(it.divb);
+    const double tdx = 2.0 * it.dx, tdy = 2.0 * it.dy, tdz = 2.0 * it.dz;
+    // in-plane neighbour offsets (clamped: side columns write zeros anyway)
+    const size_t xm = col - (i > 0 ? 1 : 0), xp = col + (i < nx - 1 ? 1 : 0);
+    const size_t ym = col - (j > 0 ? (size_t)nx : 0), yp = col + (j < ny - 1 ? (size_t)nx : 0);
+    struct Col {
+        double bx, by, bz, p;
+    };
+    // in-plane neighbours of the column on one plane, and rho there
+    struct Nb {
+        double bx_xp, bx_xm, bx_yp, bx_ym, by_xp, by_xm, by_yp, by_ym;
+        double bz_xp, bz_xm, bz_yp, bz_ym, p_xp, p_xm, p_yp, p_ym, rho;
+    };
+    // byte offsets within a plane; loads go through per-plane buffer
+    // resources, so the per-lane address state is these five words
+    const uint32_t bc = 8u * (uint32_t)col, bxp = 8u * (uint32_t)xp, bxm = 8u * (uint32_t)xm;
+    const uint32_t byp = 8u * (uint32_t)yp, bym = 8u * (uint32_t)ym;
+    const uint32_t plane_bytes = 8u * (uint32_t)sxy;
+    auto load_col = [&](int k) {
+        const size_t pl = sxy * (size_t)min(max(k, 0), nz - 1);
+        return Col{bload<double>(plane_rsrc(Bx + pl, plane_bytes), bc), bload<double>(plane_rsrc(By + pl, plane_bytes), bc),
+                   bload<double>(plane_rsrc(Bz + pl, plane_bytes), bc), bload<double>(plane_rsrc(pp + pl, plane_bytes), bc)};
+    };
+    auto load_nb = [&](int k) {
+        const size_t pl = sxy * (size_t)min(max(k, 0), nz - 1);
+        const auto rx = plane_rsrc(Bx + pl, plane_bytes), ry = plane_rsrc(By + pl, plane_bytes);
+        const auto rz = plane_rsrc(Bz + pl, plane_bytes), rp = plane_rsrc(pp + pl, plane_bytes);
+        Nb q;
+        q.bx_xp = bload<double>(rx, bxp), q.bx_xm = bload<double>(rx, bxm);
+        q.bx_yp = bload<double>(rx, byp), q.bx_ym = bload<double>(rx, bym);
+        q.by_xp = bload<double>(ry, bxp), q.by_xm = bload<double>(ry, bxm);
+        q.by_yp = bload<double>(ry, byp), q.by_ym = bload<double>(ry, bym);
+        q.bz_xp = bload<double>(rz, bxp), q.bz_xm = bload<double>(rz, bxm);
+        q.bz_yp = bload<double>(rz, byp), q.bz_ym = bload<double>(rz, bym);
+        q.p_xp = bload<double>(rp, bxp), q.p_xm = bload<double>(rp, bxm);
+        q.p_yp = bload<double>(rp, byp), q.p_ym = bload<double>(rp, bym);
+        q.rho = bload<double>(plane_rsrc(rho + pl, plane_bytes), bc);
+        return q;
+    };
+    // columns k-1, k, k+1 and the neighbours of plane k in hand; each step
+    // issues the loads of column k+2 and of plane k+1's neighbours first
+    Col m = load_col(k0 - 1), c = load_col(k0), u = load_col(k0 + 1);
+    Nb nb = load_nb(k0);
+    for (int k = k0; k < k1; ++k) {
+        const Col u2 = load_col(k + 2);
+        const Nb nbn = load_nb(k + 1);
+        const Col w = k == 0 ? u2 : u; // plane 2 for the one-sided base difference
+        double jx = 0.0, jy = 0.0, jz = 0.0, fr = 0.0, dv = 0.0;
+        if (!side && k < nz - 1) {
+            const Nb &q = nb;
+            // z-derivatives: central, or one-sided at the base
+            double dzbx, dzby, dzbz, dzp;
+            if (k > 0) {
+                dzbx = (u.bx - m.bx) / tdz;
+                dzby = (u.by - m.by) / tdz;
+                dzbz = (u.bz - m.bz) / tdz;
+                dzp = (u.p - m.p) / tdz;
+            } else {
+                dzbx = (-3.0 * c.bx + 4.0 * u.bx - w.bx) / tdz;
+                dzby = (-3.0 * c.by + 4.0 * u.by - w.by) / tdz;
+                dzbz = (-3.0 * c.bz + 4.0 * u.bz - w.bz) / tdz;
+                dzp = (-3.0 * c.p + 4.0 * u.p - w.p) / tdz;
+            }
+            const double dxbx = (q.bx_xp - q.bx_xm) / tdx, dybx = (q.bx_yp - q.bx_ym) / tdy;
+            const double dxby = (q.by_xp - q.by_xm) / tdx, dyby = (q.by_yp - q.by_ym) / tdy;
+            const double dxbz = (q.bz_xp - q.bz_xm) / tdx, dybz = (q.bz_yp - q.bz_ym) / tdy;
+            const double dxp = (q.p_xp - q.p_xm) / tdx, dyp = (q.p_yp - q.p_ym) / tdy;
+            jx = (dybz - dzby) / it.mu0;
+            jy = (dzbx - dxbz) / it.mu0;
+            jz = (dxby - dybx) / it.mu0;
+            const double fx = (jy * c.bz - jz * c.by) - dxp;
+            const double fy = (jz * c.bx - jx * c.bz) - dyp;
+            const double fz = (jx * c.by - jy * c.bx) - dzp - q.rho * it.g;
+            fr = sqrt(fx * fx + fy * fy + fz * fz);
+            dv = dxbx + dyby + dzbz;
+        }
+        const size_t pl = sxy * (size_t)k;
+        bstore(jx, plane_rsrc(ojx + pl, plane_bytes), bc);
+        bstore(jy, plane_rsrc(ojy + pl, plane_bytes), bc);
+        bstore(jz, plane_rsrc(ojz + pl, plane_bytes), bc);
+        bstore(fr, plane_rsrc(ofr + pl, plane_bytes), bc);
+        bstore(dv, plane_rsrc(odv + pl, plane_bytes), bc);
+        m = c;
+        c = u;
+        u = u2;
+        nb = nbn;
+    }
+}
+
+// ============================================================================
 // Preparation and copies.
 // ============================================================================
 template <typename Item>
@@ -1838,6 +1956,14 @@ hipError_t launch_fields(const FieldsItem *items, int nitems, int ntiles, hipStr
 {
     if (ntiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fields, dim3(ntiles), dim3(kThreads), 0, s, items, nitems);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag(const DiagItem &item, hipStream_t s)
+{
+    const dim3 grid((unsigned)((item.nx + kDX - 1) / kDX), (unsigned)((item.ny + kDY - 1) / kDY),
+                    (unsigned)((item.nz + item.kz - 1) / item.kz));
+    hipLaunchKernelGGL(k_diag, grid, dim3(kThreads), 0, s, item);
     return hipGetLastError();
 }
 

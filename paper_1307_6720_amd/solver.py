@@ -188,6 +188,22 @@ class Plan:
                                         _stream(self.device)))
         return out
 
+    def diagnostics(self, model, Bx, By, Bz, p, rho, out=None):
+        """Residuals of equations (1)-(3) for the given fields: returns
+        (jx, jy, jz, fres, divb) with j = curl B / mu0, fres the magnitude of
+        the force-balance residual and divb = div B (zero on the side and top
+        faces)."""
+        for t in (Bx, By, Bz, p, rho):
+            if tuple(t.shape) != self.shape or t.dtype != torch.float64 or not t.is_contiguous():
+                raise ValueError(f"fields must be contiguous float64 tensors of shape {self.shape}")
+        if out is None:
+            out = tuple(torch.empty_like(Bx) for _ in range(5))
+        m = _ModelArgs.of(model)
+        with torch.cuda.device(self.device):
+            check(_lib.lib().mhs_diagnostics(self.h, C.byref(m.c), *[_ptr(t) for t in (Bx, By, Bz, p, rho)],
+                                             *[_ptr(t) for t in out], _stream(self.device)))
+        return out
+
     # ---- measurement -----------------------------------------------------------
     def profile(self, enable=True, classes=None):
         """Time launches of the given classes (names from PROF_NAMES; all by
@@ -285,3 +301,8 @@ def solve(plan: Plan, bz0, model, precision=PREC_FP64, rtol=1e-10, rtol2d=None, 
     else:
         F = (None,) * 5
     return SolveResult(P, *F, i2.as_dict(), i3.as_dict())
+
+
+def diagnostics(plan: Plan, model, Bx, By, Bz, p, rho, out=None):
+    """Residuals of equations (1)-(3) on the plan's grid (see Plan.diagnostics)."""
+    return plan.diagnostics(model, Bx, By, Bz, p, rho, out)
