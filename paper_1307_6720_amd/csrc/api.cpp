@@ -423,8 +423,10 @@ int model_depth(const Hierarchy &h, const mhs_grid &g, const mhs_model *model, i
     return MHS_OK;
 }
 
-int upload_model(mhs_plan *p, const mhs_model *model, hipStream_t s)
+int prepare_model(mhs_plan *p, const mhs_model *model, ModelUpload &up)
 {
+    up.parts.clear();
+    up.data.clear();
     const int nz = p->grid.nz;
     Hierarchy &h = p->h3;
     const bool same = p->cache.valid && p->cache.alpha == model->alpha &&
@@ -434,28 +436,47 @@ int upload_model(mhs_plan *p, const mhs_model *model, hipStream_t s)
     int st0 = model_depth(h, p->grid, model, &depth, nullptr);
     if (st0) return st0;
     if ((st0 = set_depth(h, depth))) return st0;
+    auto add = [&](void *dst, const void *src, size_t bytes) {
+        const size_t off = (up.data.size() + 63) & ~size_t(63);
+        up.data.resize(off + bytes);
+        std::memcpy(up.data.data() + off, src, bytes);
+        up.parts.push_back({dst, off, bytes});
+    };
     std::vector<double> tab, minv;
     std::vector<float> t32;
     for (int l = 0; l < h.L; ++l) {
         double cz = 0.0;
         level_coef(h, l, model->alpha, model->xi, tab, cz);
         h.lv[l].cz = cz;
-        HIPCHK(hipMemcpyAsync(h.lv[l].coef64, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        add(h.lv[l].coef64, tab.data(), tab.size() * sizeof(double));
         if (h.lv[l].coef32) {
             t32.assign(tab.begin(), tab.end());
-            HIPCHK(hipMemcpyAsync(h.lv[l].coef32, t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice, s));
+            add(h.lv[l].coef32, t32.data(), t32.size() * sizeof(float));
         }
         if (l == h.L - 1) {
             int st = coarse_inverse(h, tab, cz, minv);
             if (st) return st;
-            HIPCHK(hipMemcpyAsync(h.minv, minv.data(), minv.size() * sizeof(double), hipMemcpyHostToDevice, s));
+            add(h.minv, minv.data(), minv.size() * sizeof(double));
         }
     }
-    // pageable sources: make sure the copies have consumed them before return
-    HIPCHK(hipStreamSynchronize(s));
+    // the plan's tables will hold this model once the copies have run
     p->cache.valid = true;
     p->cache.alpha = model->alpha;
     p->cache.xi.assign(model->xi, model->xi + nz);
+    return MHS_OK;
+}
+
+void invalidate_model(mhs_plan *p) { p->cache.valid = false; }
+
+int upload_model(mhs_plan *p, const mhs_model *model, hipStream_t s)
+{
+    ModelUpload up;
+    int st = prepare_model(p, model, up);
+    if (st) return st;
+    for (const ModelUpload::Part &q : up.parts)
+        HIPCHK(hipMemcpyAsync(q.dst, up.data.data() + q.off, q.bytes, hipMemcpyHostToDevice, s));
+    // pageable sources: make sure the copies have consumed them before return
+    if (!up.parts.empty()) HIPCHK(hipStreamSynchronize(s));
     return MHS_OK;
 }
 

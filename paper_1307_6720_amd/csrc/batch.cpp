@@ -47,6 +47,10 @@ struct Slot {
     int ticks = 0; // ticks of the current phase whose status was read
     mhs_info info[2]{};
     std::chrono::steady_clock::time_point t0;
+    // the model's device tables, copied on the tick that first launches the
+    // request (admission does not touch the device)
+    ModelUpload up;
+    bool upload_pending = false;
 };
 
 // One launch of one request's program with its merge key.
@@ -128,6 +132,8 @@ struct Snap {
 // device's work for the previous one.
 struct Tick {
     Staging stage;                  // merged descriptor tables (pinned host + workspace)
+    char *upload = nullptr;         // pinned: model tables of requests starting in this tick
+    size_t upload_cap = 0;
     SolveState *h_init = nullptr;   // pinned: fresh status words to upload
     SolveState *h_read = nullptr;   // pinned: status words read back
     hipEvent_t done = nullptr;      // after the read-back
@@ -452,6 +458,7 @@ int mhs_batch_destroy(mhs_batch *b)
         if (t.stage.host) (void)hipHostFree(t.stage.host);
         if (t.h_init) (void)hipHostFree(t.h_init);
         if (t.h_read) (void)hipHostFree(t.h_read);
+        if (t.upload) (void)hipHostFree(t.upload);
     }
     for (auto &pool : b->ev_pool)
         for (hipEvent_t e : pool) (void)hipEventDestroy(e);
@@ -494,6 +501,21 @@ int mhs_batch_admit(mhs_batch *b, mhs_plan *plan, const mhs_model *model, const 
     S.p = d_p;
     S.rho = d_rho;
     S.opts = *o;
+    // coefficient tables, coarsest inverse (this also fixes the depth of the
+    // hierarchy for this model) and the field tables, prepared on the host
+    if ((st = prepare_model(plan, model, S.up))) return st;
+    {
+        const int nz = plan->grid.nz;
+        std::vector<double> tab(4 * (size_t)nz);
+        std::copy(model->xi, model->xi + nz, tab.begin());
+        std::copy(model->dxi, model->dxi + nz, tab.begin() + nz);
+        std::copy(model->pb, model->pb + nz, tab.begin() + 2 * nz);
+        std::copy(model->rhob, model->rhob + nz, tab.begin() + 3 * nz);
+        const size_t off = (S.up.data.size() + 63) & ~size_t(63);
+        S.up.data.resize(off + tab.size() * sizeof(double));
+        std::memcpy(S.up.data.data() + off, tab.data(), tab.size() * sizeof(double));
+        S.up.parts.push_back({plan->d_fields_tab, off, tab.size() * sizeof(double)});
+    }
     // every phase's per-tick descriptors must fit the slot's share (with
     // room for the alignment of each merged table)
     for (Phase ph : {kBoundary, kInterior, kFinish}) {
@@ -504,21 +526,14 @@ int mhs_batch_admit(mhs_batch *b, mhs_plan *plan, const mhs_model *model, const 
             reset_recorder(b);
             std::vector<Rec> tmp;
             const bool ok = build_slot(S, free_slot, b->d_states + free_slot, b->rec, tmp);
-            if (!ok || b->rec.used + kItemAlign * tmp.size() > kSlotStageBytes)
+            if (!ok || b->rec.used + kItemAlign * tmp.size() > kSlotStageBytes) {
+                invalidate_model(plan); // the prepared tables never reach the device
                 return fail(MHS_ERR_BUDGET, "the request's per-tick launch descriptors exceed %zu bytes",
                             kSlotStageBytes);
+            }
         }
     }
-    // coefficient tables, coarsest inverse and the field tables
-    hipStream_t s0 = nullptr;
-    if ((st = upload_model(plan, model, s0))) return st;
-    const int nz = plan->grid.nz;
-    std::vector<double> tab(4 * (size_t)nz);
-    std::copy(model->xi, model->xi + nz, tab.begin());
-    std::copy(model->dxi, model->dxi + nz, tab.begin() + nz);
-    std::copy(model->pb, model->pb + nz, tab.begin() + 2 * nz);
-    std::copy(model->rhob, model->rhob + nz, tab.begin() + 3 * nz);
-    HIPCHK(hipMemcpy(plan->d_fields_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
+    S.upload_pending = true;
 
     S.phase = kBoundary;
     S.fresh = true;
@@ -609,9 +624,34 @@ int mhs_batch_step(mhs_batch *b, void *stream, int32_t *n_active)
         lo = hi;
     }
 
-    // 3. descriptors and fresh status words to the device, the launches,
-    // then the status read-back
+    // 3. model tables of starting requests, descriptors and fresh status
+    // words to the device, the launches, then the status read-back
     if (top > 0) {
+        size_t up_bytes = 0;
+        for (int i = 0; i < top; ++i) {
+            const Slot &S = b->slots[(size_t)i];
+            if (T.snap[(size_t)i].launched && S.upload_pending) up_bytes = ((up_bytes + 63) & ~size_t(63)) + S.up.data.size();
+        }
+        if (up_bytes > T.upload_cap) {
+            // this tick buffer's last use (tick t-2) has completed
+            if (T.upload) HIPCHK(hipHostFree(T.upload));
+            T.upload = nullptr;
+            T.upload_cap = 0;
+            HIPCHK(hipHostMalloc((void **)&T.upload, up_bytes, hipHostMallocDefault));
+            T.upload_cap = up_bytes;
+        }
+        size_t up_off = 0;
+        for (int i = 0; i < top; ++i) {
+            Slot &S = b->slots[(size_t)i];
+            if (!T.snap[(size_t)i].launched || !S.upload_pending) continue;
+            up_off = (up_off + 63) & ~size_t(63);
+            std::memcpy(T.upload + up_off, S.up.data.data(), S.up.data.size());
+            for (const ModelUpload::Part &q : S.up.parts)
+                HIPCHK(hipMemcpyAsync(q.dst, T.upload + up_off + q.off, q.bytes, hipMemcpyHostToDevice, s));
+            up_off += S.up.data.size();
+            S.upload_pending = false;
+            S.up = ModelUpload{};
+        }
         if (T.stage.used)
             HIPCHK(hipMemcpyAsync(T.stage.dev, T.stage.host, T.stage.used, hipMemcpyHostToDevice, s));
         for (int i = 0; i < top; ++i) {
@@ -781,6 +821,8 @@ int mhs_batch_release(mhs_batch *b, int32_t slot)
 {
     int st = check_slot(b, slot);
     if (st) return st;
+    Slot &S = b->slots[(size_t)slot];
+    if (S.phase != kFree && S.upload_pending) invalidate_model(S.plan); // its tables never reached the device
     b->slots[(size_t)slot] = Slot{};
     return MHS_OK;
 }

@@ -129,7 +129,21 @@ int fail(int code, const char *fmt, ...);
 
 int validate_model(const mhs_plan *p, const mhs_model *m, bool need_fields);
 int validate_opts(const mhs_opts *o);
+// Host copies of a model's device tables (per-level coefficients, coarsest
+// inverse) with their destinations; prepare_model fills it and sets the
+// plan's depth and model cache, upload_model also copies and waits.
+struct ModelUpload {
+    struct Part {
+        void *dst;
+        size_t off, bytes;
+    };
+    std::vector<Part> parts;
+    std::vector<char> data;
+};
+int prepare_model(mhs_plan *p, const mhs_model *model, ModelUpload &up);
 int upload_model(mhs_plan *p, const mhs_model *model, hipStream_t s);
+// Forget which model the plan's tables hold (its upload did not happen).
+void invalidate_model(mhs_plan *p);
 int set_device(const mhs_plan *p);
 SolveState initial_state(double rtol, int max_iter);
 int status_of(int32_t done);
