@@ -163,13 +163,17 @@ __device__ __forceinline__ T interp2(Ptr ec, int ncx, int i, int j)
 // 3D red-black Gauss-Seidel sweep, ping-pong (u_in -> u_out).
 //
 // A workgroup owns kTX x kTY interior nodes of `kz` consecutive planes.  It
-// stages a (kTY+4) x (kTX+4) window of each plane in LDS (four planes
-// resident) and marches up in z: at step s it updates the red nodes of plane
+// stages a (kTY+4) x (kTX+4) window of each plane of u in LDS (five slots)
+// and marches up in z: at step s it updates the red nodes of plane
 // s on the tile plus a one-node ring, then the black nodes of plane s-1 on
 // the tile, whose red neighbours (planes s-2, s-1, s) are all final by
 // then.  Red nodes of the ring are recomputed from u_in, so neighbouring
 // tiles never read each other's output and one pass is one complete sweep,
 // identical to updating all red nodes and then all black nodes.
+//
+// The right-hand side is needed only at the nodes a thread updates (two
+// red, one black, and its own two for the residual), so it goes from memory
+// straight into registers at those nodes, with no LDS staging.
 //
 // Loads run kDepth planes ahead of the stencil in a ring of register sets,
 // so kDepth planes of HBM traffic are in flight per workgroup.  Every index
@@ -197,14 +201,6 @@ constexpr int kCCells = 2 * kCWX * kCWY;
 constexpr int kCPer = (kCCells + kThreads - 1) / kThreads;
 static_assert(kTY * kTX % kThreads == 0, "tile must be a multiple of the block");
 
-// right-hand-side window: the tile plus a one-node ring, colour-split too
-constexpr int kFX = kTX + 2;
-constexpr int kFY3 = kTY + 2;
-constexpr int kFCells3 = kFX * kFY3;
-constexpr int kFPer3 = (kFCells3 + kThreads - 1) / kThreads;
-constexpr int kFHalf = kFX / 2;
-__device__ __forceinline__ int sxf(int c) { return (c & 1) * kFHalf + (c >> 1); }
-static_assert(kFX % 2 == 0, "rhs window width must be even");
 
 // Per-plane coefficients of planes base .. base+63, one plane per lane of
 // every wave: the z-march reads plane p's value with a lane broadcast
@@ -257,7 +253,9 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     // plane also carries right-hand-side or coarse-correction data
     constexpr int D = (HAS_F || PROLONG) ? kDepthF : kDepth;
     constexpr int kCWPlanes = PROLONG ? 2 : 1;
-    constexpr int kFSlots = HAS_F ? 5 : 1;
+    // right-hand-side values a thread reads per plane: its two red nodes,
+    // its black node and, for the residual, its two own nodes
+    constexpr int kNF = HAS_F ? (NORM ? 5 : 3) : 1;
     constexpr int kCPlane = kCWX * kCWY;
     // Window rows in LDS: even columns, then odd columns, the odd half
     // starting 16 banks after the even one, so that the colour phases (every
@@ -282,8 +280,6 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     // every staged array has one spare cell past its data: lanes without a
     // cell store there, so staging is straight-line code (no divergent
     // branches between the loads and the stores that consume them)
-    constexpr int FSLOT = kFCells3 + 1;
-    __shared__ T F[kFSlots * FSLOT];
     __shared__ T CW[kCWPlanes * kCPlane + 1];
     // prolongation: the coarse correction interpolated in z and y onto every
     // fine row of the window, at coarse columns (x interpolation at staging)
@@ -337,19 +333,6 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
         if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2) st_int |= 1u << r;
         if (i & 1) st_odd |= 1u << r;
     }
-    // right-hand-side window cells (tile plus a one-node ring)
-    int f_l[HAS_F ? kFPer3 : 1];
-    uint32_t f_g[HAS_F ? kFPer3 : 1];
-    if constexpr (HAS_F) {
-#pragma unroll
-        for (int r = 0; r < kFPer3; ++r) {
-            const int e = tid + r * kThreads;
-            const int ee = min(e, kFCells3 - 1);
-            const int w = ee / kFX, c = ee - w * kFX;
-            f_l[r] = e < kFCells3 ? w * kFX + sxf(c) : kFCells3;
-            f_g[r] = es * (uint32_t)(min(i0 - 1 + c, nx - 1) + nx * min(j0 - 1 + w, ny - 1));
-        }
-    }
     // coarse-window cells (two coarse planes; LDS index tid + r * kThreads)
     // and the z-y interpolation entries this thread computes
     uint32_t cw_g[PROLONG ? kCPer : 1];
@@ -383,10 +366,9 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     // and west-neighbour indices (east = west + 1 in the colour-split row),
     // centre kNone where the node is not interior
     uint32_t rd0[2], rd1[2];
-    uint32_t rdf0 = 0, rdf1 = 0;
+    uint32_t rf[2][2]; // [plane parity][r]: byte offset of the node's f (clamped)
 #pragma unroll
     for (int ps = 0; ps < 2; ++ps) {
-        int fi[2];
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
             const int e = tid + r * kThreads;
@@ -401,21 +383,14 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
                 rd1[r] = v;
             else
                 rd0[r] = v;
-            fi[r] = (w - 1) * kFX + sxf(c - 1);
-        }
-        if constexpr (HAS_F) {
-            if (ps)
-                rdf1 = pk16(fi[0], fi[1]);
-            else
-                rdf0 = pk16(fi[0], fi[1]);
+            rf[ps][r] = es * (uint32_t)(min(max(i, 0), nx - 1) + nx * min(max(j, 0), ny - 1));
         }
     }
     // black nodes of the tile (one per thread) for each plane parity
     uint32_t bk0 = 0, bk1 = 0;
-    uint32_t bkf = 0;
+    uint32_t bf[2]; // [plane parity]: byte offset of the black node's f (clamped)
     static_assert(kTY * kBlackPerRow == kThreads, "one black node per thread");
     {
-        int fi[2];
 #pragma unroll
         for (int ps = 0; ps < 2; ++ps) {
             const int w = 2 + tid / kBlackPerRow;
@@ -427,31 +402,38 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
                 bk1 = v;
             else
                 bk0 = v;
-            fi[ps] = (w - 1) * kFX + sxf(c - 1);
+            bf[ps] = es * (uint32_t)(min(i, nx - 1) + nx * min(j, ny - 1));
         }
-        if constexpr (HAS_F) bkf = pk16(fi[0], fi[1]);
     }
     // tile nodes this thread writes (and sums the residual of)
     uint32_t ow[kOwn];
     uint32_t ow_g[kOwn];
-    uint32_t owf = 0;
     uint32_t ow_ok = 0;
     static_assert(kOwn == 2, "two written nodes per thread");
     {
-        int fi[kOwn];
 #pragma unroll
         for (int q = 0; q < kOwn; ++q) {
             const int e = tid + q * kThreads;
             const int w = 2 + e / kTX, c = 2 + e % kTX;
             const int i = i0 + c - 2, j = j0 + w - 2;
             ow[q] = pk16(w * RW + sxp(c), w * RW + sxp(c - 1));
-            fi[q] = (w - 1) * kFX + sxf(c - 1);
             ow_g[q] = es * (uint32_t)(min(i, nx - 1) + nx * min(j, ny - 1));
             if (i <= nx - 2 && j <= ny - 2) ow_ok |= 1u << q;
         }
-        if constexpr (HAS_F && NORM) owf = pk16(fi[0], fi[1]);
     }
     const int par0 = (i0 + j0 + 1) & 1; // red parity of plane s is (par0 + s) & 1
+    // f offsets by plane class: class 0 = planes kb-1, kb+1, ...; class 1 =
+    // planes kb, kb+2, ... (every step of the march knows its planes' class
+    // at compile time)
+    const int ps0 = (par0 + kb - 1) & 1;
+    uint32_t fro[2][2], fbo[2]; // [class][r], [class]
+#pragma unroll
+    for (int cl = 0; cl < 2; ++cl) {
+        const int ps = ps0 ^ cl;
+        fro[cl][0] = pick(rf[0][0], rf[1][0], ps);
+        fro[cl][1] = pick(rf[0][1], rf[1][1], ps);
+        fbo[cl] = pick(bf[0], bf[1], ps);
+    }
     // planes kb-1 .. ke (at most kKZ + 2 <= 64) of cx, cy, d, 1/d
     static_assert(kKZ + 2 <= 64, "one plane per lane");
     PlaneTab<T> tcx, tcy, tid_, tdd;
@@ -469,8 +451,14 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     // so that its z-y interpolation can run during the red phase before the
     // plane is staged.
     T pre[D][kWPer];
-    T fpre[D][HAS_F ? kFPer3 : 1];
+    T fpre[D][kNF];
     T cpre[D][PROLONG ? kCPer : 1];
+    // f of the planes in use: fcur = plane s (red, black, own), fbm = the
+    // black node of plane s-1, fnx = plane s+1 (moved out of the ring when
+    // the plane is staged)
+    T fcur[kNF], fnx[kNF], fbm = (T)0;
+#pragma unroll
+    for (int k = 0; k < kNF; ++k) fcur[k] = fnx[k] = (T)0;
     auto fetch_coarse = [&](int p, T(&cdst)[PROLONG ? kCPer : 1]) {
         if constexpr (PROLONG) {
             const MHS_GLOBAL T *p0 = ec + csxy * (size_t)min(p >> 1, ncz - 1);
@@ -483,7 +471,8 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     // into the ring registers; cells outside the array are zeroed when the
     // plane is staged.
     const uint32_t plane_bytes = es * (uint32_t)sxy;
-    auto fetch = [&](int p, T(&dst)[kWPer], T(&fdst)[HAS_F ? kFPer3 : 1], T(&cdst)[PROLONG ? kCPer : 1]) {
+    // cl: the class of plane p (its colour layout)
+    auto fetch = [&](int p, int cl, T(&dst)[kWPer], T(&fdst)[kNF], T(&cdst)[PROLONG ? kCPer : 1]) {
         if constexpr (!ZERO_IN) {
             const auto rs = plane_rsrc(uin + sxy * (size_t)p, plane_bytes);
 #pragma unroll
@@ -491,8 +480,13 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
         }
         if constexpr (HAS_F) {
             const auto rs = plane_rsrc(f + sxy * (size_t)p, plane_bytes);
-#pragma unroll
-            for (int r = 0; r < kFPer3; ++r) fdst[r] = bload<T>(rs, f_g[r]);
+            fdst[0] = bload<T>(rs, cl ? fro[1][0] : fro[0][0]);
+            fdst[1] = bload<T>(rs, cl ? fro[1][1] : fro[0][1]);
+            fdst[2] = bload<T>(rs, cl ? fbo[1] : fbo[0]);
+            if constexpr (NORM) {
+                fdst[3] = bload<T>(rs, ow_g[0]);
+                fdst[4] = bload<T>(rs, ow_g[1]);
+            }
         }
         fetch_coarse(p + 1, cdst);
     };
@@ -526,7 +520,7 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     };
     // stage plane p (window with the coarse correction from ZW, right-hand
     // side) and the coarse planes of p + 1 carried by the same register set
-    auto stash = [&](int p, int sl, const T(&src)[kWPer], const T(&fsrc)[HAS_F ? kFPer3 : 1],
+    auto stash = [&](int p, int sl, const T(&src)[kWPer], const T(&fsrc)[kNF],
                      const T(&csrc)[PROLONG ? kCPer : 1]) {
         const bool corr = PROLONG && p >= 1 && p <= nz - 2;
         T *dst = S + sl * SLOT;
@@ -544,9 +538,8 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
             dst[l] = v;
         }
         if constexpr (HAS_F) {
-            T *fd = F + sl * FSLOT;
 #pragma unroll
-            for (int r = 0; r < kFPer3; ++r) fd[f_l[r]] = fsrc[r];
+            for (int k = 0; k < kNF; ++k) fnx[k] = fsrc[k];
         }
         store_cw(csrc);
     };
@@ -565,12 +558,13 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
 #pragma unroll
     for (int q = 0; q < kOwn; ++q) below[q] = (T)0;
 
-    // plane p waits in register set (p - pbase) % D until it is staged
+    // plane p waits in register set (p - pbase) % D until it is staged;
+    // its class (for the f offsets) is (p - kb + 1) & 1
     const int pbase = kb - 2;
 #pragma unroll
     for (int q = 0; q < D; ++q) {
         const int p = pbase + q;
-        fetch(min(max(p, 0), ptop), pre[q], fpre[q], cpre[q]);
+        fetch(min(max(p, 0), ptop), (q + 1) & 1, pre[q], fpre[q], cpre[q]);
     }
     // warm-up: stage planes kb-2 (if any) and kb-1; the prolongation needs
     // the z-y rows of each plane ready before it is staged
@@ -597,17 +591,21 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
         zy_rows(kb);
         lds_barrier();
     }
+#pragma unroll
+    for (int k = 0; k < kNF; ++k) fcur[k] = fnx[k]; // f of plane kb-1
     // the two sets in issue order, as the steps issue them (interleaved, the
     // first wait of every round would have to cover both)
-    fetch(min(pbase + D, ptop), pre[0], fpre[0], cpre[0]);
+    fetch(min(pbase + D, ptop), (D + 1) & 1, pre[0], fpre[0], cpre[0]);
     __builtin_amdgcn_sched_barrier(0);
-    fetch(min(pbase + D + 1, ptop), pre[1], fpre[1], cpre[1]);
+    fetch(min(pbase + D + 1, ptop), D & 1, pre[1], fpre[1], cpre[1]);
     __builtin_amdgcn_sched_barrier(0);
 
     // One step: stage plane s+1, red of plane s, black of plane s-1, write
     // of plane s-2.  ri is the register set of plane s+1; sm2 .. sp1 are the
-    // slots of planes s-2 .. s+1.
-    auto step = [&](const int s, const int ri, const int sm2, const int sm1, const int s00, const int sp1) {
+    // slots of planes s-2 .. s+1; d is the step's position in its round
+    // (its parity gives the class of the plane it fetches).
+    auto step = [&](const int s, const int d, const int ri, const int sm2, const int sm1, const int s00,
+                    const int sp1) {
         // stage plane s+1 (slot of plane s-4; the previous step's black
         // phase may still read planes s-3 .. s-1) and refill its register
         // set with plane s+1+D.  Both are unconditional (past the top of
@@ -615,7 +613,7 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
         // lands in a slot no phase reads) so that every step issues the
         // same loads and the compiler can wait for the oldest set only.
         stash(s + 1, sp1, pre[ri], fpre[ri], cpre[ri]);
-        fetch(min(s + 1 + D, ptop), pre[ri], fpre[ri], cpre[ri]);
+        fetch(min(s + 1 + D, ptop), (d + D + 1) & 1, pre[ri], fpre[ri], cpre[ri]);
         // keep each step's loads in its step (moved across steps, the
         // waits of the next stage would cover the wrong register set)
         __builtin_amdgcn_sched_barrier(0);
@@ -633,14 +631,13 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
                 cy = tcy(s);
                 dd = tdd(s);
             }
-            const T *Fs = F + s00 * FSLOT;
 #pragma unroll
             for (int q = 0; q < kOwn; ++q) {
                 const int o = lo16(ow[q]), ww = hi16(ow[q]);
                 const T uc = Ps[o];
                 if (do_res && ((ow_ok >> q) & 1)) {
                     T fv = (T)0;
-                    if constexpr (HAS_F) fv = Fs[q ? hi16(owf) : lo16(owf)];
+                    if constexpr (HAS_F) fv = fcur[3 + q];
                     const T r = fv - (cx * (Ps[ww + 1] + Ps[ww]) + cy * (Ps[o + RW] + Ps[o - RW]) +
                                       cz * (Pu[o] + below[q]) + dd * uc);
                     acc += (double)r * (double)r;
@@ -657,7 +654,6 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
         if (s >= 1 && s <= nz - 2) {
             const T cx = tcx(s), cy = tcy(s), invd = tid_(s);
             T *P = S + s00 * SLOT;
-            const T *Fs = F + s00 * FSLOT;
             const int ps = (par0 + s) & 1;
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
@@ -666,10 +662,7 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
                 if (o == kNone) continue;
                 const int ww = hi16(pr);
                 T fv = (T)0;
-                if constexpr (HAS_F) {
-                    const uint32_t fr = pick(rdf0, rdf1, ps);
-                    fv = Fs[r ? hi16(fr) : lo16(fr)];
-                }
+                if constexpr (HAS_F) fv = fcur[r];
                 P[o] = (fv - (cx * (P[ww + 1] + P[ww]) + cy * (P[o + RW] + P[o - RW]) + cz * (Pu[o] + Pd[o]))) *
                        invd;
             }
@@ -681,17 +674,22 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
             const T cx = tcx(m), cy = tcy(m), invd = tid_(m);
             T *P = S + sm1 * SLOT;
             const T *Pm = S + sm2 * SLOT;
-            const T *Fm = F + sm1 * FSLOT;
             const int pb = (par0 + m) & 1;
             const uint32_t pr = pick(bk0, bk1, pb);
             const int o = lo16(pr);
             if (o != kNone) {
                 const int ww = hi16(pr);
                 T fv = (T)0;
-                if constexpr (HAS_F) fv = Fm[pb ? hi16(bkf) : lo16(bkf)];
+                if constexpr (HAS_F) fv = fbm;
                 P[o] = (fv - (cx * (P[ww + 1] + P[ww]) + cy * (P[o + RW] + P[o - RW]) + cz * (Ps[o] + Pm[o]))) *
                        invd;
             }
+        }
+        // f of the next step: black of plane s, all of plane s+1
+        if constexpr (HAS_F) {
+            fbm = fcur[2];
+#pragma unroll
+            for (int k = 0; k < kNF; ++k) fcur[k] = fnx[k];
         }
     };
     // Whole rounds with constant slots and register sets (no exit inside a
@@ -702,7 +700,7 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     for (; s0 + kRound - 1 <= ke; s0 += kRound) {
 #pragma unroll
         for (int d = 0; d < kRound; ++d)
-            step(s0 + d, (d + 2) % D, (d + 4) % kSlots, d % kSlots, (d + 1) % kSlots, (d + 2) % kSlots);
+            step(s0 + d, d, (d + 2) % D, (d + 4) % kSlots, d % kSlots, (d + 1) % kSlots, (d + 2) % kSlots);
     }
     for (; s0 <= ke; s0 += D) {
 #pragma unroll
@@ -710,7 +708,7 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
             const int s = s0 + d;
             if (s > ke) break;
             const int t = s - kb + 2; // slot of plane s
-            step(s, (d + 2) % D, (t + 3) % kSlots, (t + 4) % kSlots, t % kSlots, (t + 1) % kSlots);
+            step(s, d, (d + 2) % D, (t + 3) % kSlots, (t + 4) % kSlots, t % kSlots, (t + 1) % kSlots);
         }
     }
     // the last planes: ke-2 was written in the final step, ke-1 remains
