@@ -177,3 +177,63 @@ def test_batch_abi_direct():
     b.close()
     for p in plans:
         p.close()
+
+
+def test_batch_profile_counts_merged_launches(alone_results):
+    """mhs_batch_profile_*: merged launches are timed per class, their
+    compulsory bytes add up over the requests whose items ran, and timing
+    does not change any result."""
+    from paper_1307_6720_amd import _lib as L
+
+    reqs, ref = alone_results
+    pick = [make_request(i, CASES[i]) for i in (1, 3)]  # two mixed-precision requests
+    b = Batch(2, DEV)
+    b.profile(True, ["smooth_l0", "refine"])
+    plans, outs = [], []
+    for r in pick:
+        nx, ny, nz = r.dims
+        plan = Plan(synth.make_grid(nx, ny, nz, *r.lengths), PREC_FP64 | PREC_MIXED, device=DEV)
+        P = torch.zeros((nz, ny, nx), dtype=torch.float64, device=DEV)
+        F = tuple(torch.empty_like(P) for _ in range(5))
+        b.admit(plan, r.model, torch.from_numpy(r.bz0).to(DEV), P, F, make_opts(r.precision, r.rtol))
+        plans.append(plan)
+        outs.append((P, F))
+    while b.step():
+        pass
+    prof = b.profile_read(reset=True)
+    b.close()
+    ms, n, by = prof["smooth_l0"]
+    assert n > 0 and ms > 0
+    # every level-0 FP32 sweep of a request moves 8, 12 or 12.5 B per node:
+    # the class total is a combination of those, bounded by the extremes
+    nodes = sum(np.prod(r.dims) for r in pick)
+    assert by > 0 and by <= n * 12.5 * 4 * nodes
+    assert prof["refine"][1] > 0
+    for r, (P, F), plan in zip(pick, outs, plans):
+        want = ref[r.id][0]
+        for a, w in zip((P, *F), want):
+            assert torch.equal(a, w)
+        plan.close()
+
+
+def test_release_before_first_tick_keeps_plan_consistent(alone_results):
+    """Admission only prepares the model tables; a slot released before its
+    first tick never uploads them, and the plan must not believe it holds
+    that model: a later single-request solve with the same model is right."""
+    reqs, ref = alone_results
+    r = make_request(2, CASES[2])
+    nx, ny, nz = r.dims
+    plan = Plan(synth.make_grid(nx, ny, nz, *r.lengths), PREC_FP64 | PREC_MIXED, device=DEV)
+    b = Batch(1, DEV)
+    P = torch.zeros((nz, ny, nx), dtype=torch.float64, device=DEV)
+    F = tuple(torch.empty_like(P) for _ in range(5))
+    bz = torch.from_numpy(r.bz0).to(DEV)
+    s = b.admit(plan, r.model, bz, P, F, make_opts(r.precision, r.rtol))
+    b.release(s)  # no tick ran: the tables were never copied
+    b.close()
+    res = solve(plan, bz, r.model, precision=r.precision, rtol=r.rtol)
+    torch.cuda.synchronize()
+    want = ref[r.id][0]
+    for a, w in zip((res.P, res.Bx, res.By, res.Bz, res.p, res.rho), want):
+        assert torch.equal(a, w)
+    plan.close()
