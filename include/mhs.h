@@ -48,7 +48,7 @@ extern "C" {
 /* ---- status codes ------------------------------------------------------ */
 #define MHS_OK 0
 #define MHS_ERR_INVALID_ARG 1    /* null pointer, bad option value          */
-#define MHS_ERR_GRID 2           /* an axis is not 2^L+1 nodes, or too small */
+#define MHS_ERR_GRID 2           /* an axis is not 2^L+1 nodes (L >= 2), or over 2e9 nodes */
 #define MHS_ERR_NOT_ELLIPTIC 3   /* xi(z_k) >= 1 at an interior plane (8)   */
 #define MHS_ERR_INDEFINITE 4     /* alpha^2 too close to the spectrum of (8) */
 #define MHS_ERR_NO_CONVERGENCE 5 /* max_cycles reached; P holds last iterate */

@@ -95,6 +95,8 @@ int check_grid(const mhs_grid *g)
         !std::isfinite(g->lz))
         return fail(MHS_ERR_INVALID_ARG, "box lengths must be positive and finite");
     const double npts = (double)g->nx * g->ny * g->nz;
+    // at most 2e9 nodes (32-bit node indices); with nz >= 5 an FP64 x-y
+    // plane then stays under 4 GB (the kernels' 32-bit byte offsets)
     if (npts > 2.0e9) return fail(MHS_ERR_GRID, "grid too large (%g nodes)", npts);
     return MHS_OK;
 }

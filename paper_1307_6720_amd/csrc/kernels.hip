@@ -1790,9 +1790,11 @@ __global__ __launch_bounds__(256) void k_prep3(const PrepItem *__restrict__ item
     const int64_t e = g - it.base;
     if (e >= it.n) return;
     const int nx = it.nx, ny = it.ny, nz = it.nz;
-    const int i = (int)(e % nx);
-    const int64_t r = e / nx;
-    const int j = (int)(r % ny), k = (int)(r / ny);
+    // 32-bit index arithmetic (a plan's grids have fewer than 2^31 nodes)
+    const uint32_t e32 = (uint32_t)e, r = e32 / (uint32_t)nx;
+    const int i = (int)(e32 - r * (uint32_t)nx);
+    const uint32_t kk = r / (uint32_t)ny;
+    const int j = (int)(r - kk * (uint32_t)ny), k = (int)kk;
     const bool side = (i == 0 || i == nx - 1 || j == 0 || j == ny - 1);
     if (k == 0) {
         if (side) it.P[e] = 0.0;

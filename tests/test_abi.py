@@ -63,7 +63,9 @@ def test_workspace_sizes(dims):
 
 
 @pytest.mark.parametrize("dims,code", [((32, 33, 33), _lib.ERR_GRID), ((33, 33, 3), _lib.ERR_GRID),
-                                       ((33, 34, 33), _lib.ERR_GRID), ((4097, 5, 5), _lib.ERR_GRID)])
+                                       ((33, 34, 33), _lib.ERR_GRID), ((4097, 5, 5), _lib.ERR_GRID),
+                                       # over 2e9 nodes (32-bit node indices)
+                                       ((32769, 16385, 5), _lib.ERR_GRID)])
 def test_bad_grids_rejected(dims, code):
     got, _ = ws_bytes(*dims)
     assert got == code
