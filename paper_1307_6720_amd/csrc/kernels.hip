@@ -264,8 +264,11 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     constexpr int HP = sizeof(T) == 8 ? MHS_SWEEP_HP64 : MHS_SWEEP_HP32;
     constexpr int RW = 2 * HP;
     constexpr int SLOT = kWY * RW;
-    // (one spare cell past the odd half: RW - 1 takes the stores of lanes past the window)
-    static_assert(HP >= kWX / 2 + 1, "half row too short");
+    // (spare cells past the halves: RW - 1 takes the stores of lanes past the
+    // window; kTrash, in row 1, the updates of lanes without a node, and
+    // every neighbour it reads is a padding cell too)
+    static_assert(HP >= kWX / 2 + 2, "half row too short");
+    constexpr int kTrash = RW + HP - 1;
     // five window slots: plane s+1 is staged while black(s-1) of the previous
     // step may still read planes s-2 .. s, so two barriers per step suffice
     constexpr int kSlots = 5;
@@ -363,8 +366,8 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
         zw_src = pk16(src[0], src[1]);
     }
     // red nodes (tile plus a one-node ring) for each plane parity: centre
-    // and west-neighbour indices (east = west + 1 in the colour-split row),
-    // centre kNone where the node is not interior
+    // and west-neighbour indices (east = west + 1 in the colour-split row);
+    // a lane whose node is not interior updates the padding cell kTrash
     uint32_t rd0[2], rd1[2];
     uint32_t rf[2][2]; // [plane parity][r]: byte offset of the node's f (clamped)
 #pragma unroll
@@ -378,7 +381,7 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
             const int c = 1 + ((ps + w) & 1) + 2 * q;
             const int i = i0 - 2 + c, j = j0 - 2 + w;
             const bool ok = e < (kTY + 2) * kRedPerRow && i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2;
-            const uint32_t v = pk16(ok ? w * RW + sxp(c) : kNone, w * RW + sxp(c - 1));
+            const uint32_t v = ok ? pk16(w * RW + sxp(c), w * RW + sxp(c - 1)) : pk16(kTrash, kTrash - 1);
             if (ps)
                 rd1[r] = v;
             else
@@ -397,7 +400,8 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
             const int q = tid - (w - 2) * kBlackPerRow;
             const int c = 2 + ((ps + w) & 1) + 2 * q;
             const int i = i0 - 2 + c, j = j0 - 2 + w;
-            const uint32_t v = pk16((i <= nx - 2 && j <= ny - 2) ? w * RW + sxp(c) : kNone, w * RW + sxp(c - 1));
+            const uint32_t v = (i <= nx - 2 && j <= ny - 2) ? pk16(w * RW + sxp(c), w * RW + sxp(c - 1))
+                                                            : pk16(kTrash, kTrash - 1);
             if (ps)
                 bk1 = v;
             else
@@ -417,11 +421,18 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
             const int w = 2 + e / kTX, c = 2 + e % kTX;
             const int i = i0 + c - 2, j = j0 + w - 2;
             ow[q] = pk16(w * RW + sxp(c), w * RW + sxp(c - 1));
-            ow_g[q] = es * (uint32_t)(min(i, nx - 1) + nx * min(j, ny - 1));
-            if (i <= nx - 2 && j <= ny - 2) ow_ok |= 1u << q;
+            // a node outside the interior gets an offset past the plane: its
+            // buffer store is dropped (and a load there reads zero)
+            const bool ok = i <= nx - 2 && j <= ny - 2;
+            ow_g[q] = ok ? es * (uint32_t)(i + nx * j) : es * (uint32_t)sxy;
+            if (ok) ow_ok |= 1u << q;
         }
     }
     const int par0 = (i0 + j0 + 1) & 1; // red parity of plane s is (par0 + s) & 1
+    // waves holding a second red node (red nodes tid + kThreads exist for
+    // tid < (kTY + 2) kRedPerRow - kThreads); uniform per wave
+    const bool two_red =
+        __builtin_amdgcn_readfirstlane(tid) < (kTY + 2) * kRedPerRow - kThreads;
     // f offsets by plane class: class 0 = planes kb-1, kb+1, ...; class 1 =
     // planes kb, kb+2, ... (every step of the march knows its planes' class
     // at compile time)
@@ -549,8 +560,7 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
         const T *P = S + sl * SLOT;
         const auto rs = plane_rsrc(uout + sxy * (size_t)m, plane_bytes);
 #pragma unroll
-        for (int q = 0; q < kOwn; ++q)
-            if ((ow_ok >> q) & 1) bstore(P[lo16(ow[q])], rs, ow_g[q]);
+        for (int q = 0; q < kOwn; ++q) bstore(P[lo16(ow[q])], rs, ow_g[q]);
     };
 
     double acc = 0.0;
@@ -655,17 +665,32 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
             const T cx = tcx(s), cy = tcy(s), invd = tid_(s);
             T *P = S + s00 * SLOT;
             const int ps = (par0 + s) & 1;
+            // the second red node exists only for the first waves (the
+            // ring has more red nodes than the workgroup has threads): a
+            // wave-uniform choice, with both nodes' reads issued together
+            auto red = [&](int nr) {
+                int o[2], ww[2];
+                T v[2];
 #pragma unroll
-            for (int r = 0; r < 2; ++r) {
-                const uint32_t pr = pick(rd0[r], rd1[r], ps);
-                const int o = lo16(pr);
-                if (o == kNone) continue;
-                const int ww = hi16(pr);
-                T fv = (T)0;
-                if constexpr (HAS_F) fv = fcur[r];
-                P[o] = (fv - (cx * (P[ww + 1] + P[ww]) + cy * (P[o + RW] + P[o - RW]) + cz * (Pu[o] + Pd[o]))) *
-                       invd;
-            }
+                for (int r = 0; r < 2; ++r) {
+                    if (r >= nr) break;
+                    const uint32_t pr = pick(rd0[r], rd1[r], ps);
+                    o[r] = lo16(pr);
+                    ww[r] = hi16(pr);
+                    T fv = (T)0;
+                    if constexpr (HAS_F) fv = fcur[r];
+                    v[r] = (fv - (cx * (P[ww[r] + 1] + P[ww[r]]) + cy * (P[o[r] + RW] + P[o[r] - RW]) +
+                                  cz * (Pu[o[r]] + Pd[o[r]]))) *
+                           invd;
+                }
+#pragma unroll
+                for (int r = 0; r < 2; ++r)
+                    if (r < nr) P[o[r]] = v[r];
+            };
+            if (two_red)
+                red(2);
+            else
+                red(1);
         }
         lds_barrier();
         // black nodes of plane m = s - 1 on the tile
@@ -677,13 +702,10 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
             const int pb = (par0 + m) & 1;
             const uint32_t pr = pick(bk0, bk1, pb);
             const int o = lo16(pr);
-            if (o != kNone) {
-                const int ww = hi16(pr);
-                T fv = (T)0;
-                if constexpr (HAS_F) fv = fbm;
-                P[o] = (fv - (cx * (P[ww + 1] + P[ww]) + cy * (P[o + RW] + P[o - RW]) + cz * (Ps[o] + Pm[o]))) *
-                       invd;
-            }
+            const int ww = hi16(pr);
+            T fv = (T)0;
+            if constexpr (HAS_F) fv = fbm;
+            P[o] = (fv - (cx * (P[ww + 1] + P[ww]) + cy * (P[o + RW] + P[o - RW]) + cz * (Ps[o] + Pm[o]))) * invd;
         }
         // f of the next step: black of plane s, all of plane s+1
         if constexpr (HAS_F) {
@@ -1840,8 +1862,10 @@ hipError_t sweep3_dispatch(const LevelItem *items, int nitems, int ntiles, int f
     case F:                                                                              \
         hipLaunchKernelGGL((k_sweep3<T, F>), grid, block, 0, s, items, nitems);         \
         break;
-        MHS_CASE(0) MHS_CASE(1) MHS_CASE(2) MHS_CASE(3) MHS_CASE(4) MHS_CASE(5) MHS_CASE(6) MHS_CASE(7)
-        MHS_CASE(8) MHS_CASE(9) MHS_CASE(12) MHS_CASE(13)
+        // the variants the cycle builders and stage entry points launch:
+        // plain, with f, first sweep from zero, with the norm of the input,
+        // with the prolongation (other combinations never occur)
+        MHS_CASE(0) MHS_CASE(1) MHS_CASE(3) MHS_CASE(4) MHS_CASE(5) MHS_CASE(8) MHS_CASE(9)
 #undef MHS_CASE
     default:
         return hipErrorInvalidValue;
@@ -1858,8 +1882,10 @@ hipError_t sweep2_dispatch(const LevelItem *items, int nitems, int ntiles, int f
     case F:                                                                              \
         hipLaunchKernelGGL((k_sweep2<T, F>), grid, block, 0, s, items, nitems);         \
         break;
-        MHS_CASE(0) MHS_CASE(1) MHS_CASE(2) MHS_CASE(3) MHS_CASE(4) MHS_CASE(5) MHS_CASE(6) MHS_CASE(7)
-        MHS_CASE(8) MHS_CASE(9) MHS_CASE(12) MHS_CASE(13)
+        // the variants the cycle builders and stage entry points launch:
+        // plain, with f, first sweep from zero, with the norm of the input,
+        // with the prolongation (other combinations never occur)
+        MHS_CASE(0) MHS_CASE(1) MHS_CASE(3) MHS_CASE(4) MHS_CASE(5) MHS_CASE(8) MHS_CASE(9)
 #undef MHS_CASE
     default:
         return hipErrorInvalidValue;
