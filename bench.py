@@ -635,6 +635,29 @@ def main():
     else:
         roofline = roof_single
 
+    def copy_reference(nbytes):
+        """A plain device copy (torch copy_ of float32) moving the same bytes
+        as one launch of the dominant kernel: half read, half written."""
+        n = max(1, int(nbytes // 8))
+        x = torch.ones(n, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(10):
+            y.copy_(x)
+        t1.record()
+        torch.cuda.synchronize()
+        gbps = 8.0 * n / (t0.elapsed_time(t1) / 10 * 1e-3) / 1e9
+        del x, y
+        return gbps
+
+    for r in (roofline, roof_single):
+        if "copy_reference_gbps" not in r:
+            r["copy_reference_gbps"] = copy_reference(r["algorithmic_bytes_per_launch"])
+            r["frac_of_copy_reference"] = r["achieved"] / r["copy_reference_gbps"]
+
     # diagnostics of (1)-(3) on the last equilibrium's fields (off the
     # solve's path): j, |force residual|, div B; 80 B per node (read 5, write 5)
     D = tuple(torch.empty_like(P) for _ in range(5))
