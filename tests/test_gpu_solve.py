@@ -128,6 +128,61 @@ def test_full_size_257_parity(plans, run, prec):
         assert e < 1e-8, (n, e)
 
 
+def test_full_size_513_properties():
+    """The large single equilibrium (513 x 513 x 257, dz = 2 dx, a = 1 so
+    that xi(0) = 1, 40 bipoles plus noise), mixed path to rtol 1e-10, where
+    the exact solve would be too slow: the oracle's own residual of (8)
+    over the whole grid and of (11) on the base meets the tolerance, and B,
+    p, rho on three sampled blocks (one on the base) equal the oracle's
+    field recovery of the GPU's P there."""
+    print("[solve] 513x513x257 mixed", flush=True)
+    w = synth.workload("mhs-513x513x257")
+    m = w.model
+    g = w.grid
+    plan = Plan(g, PREC_FP64 | PREC_MIXED, device=DEV)
+    res = solve(plan, torch.from_numpy(w.bz0).to(DEV), m, precision=PREC_MIXED, rtol=1e-10)
+    torch.cuda.synchronize()
+    assert res.info2d["status"] == 0 and res.info3d["status"] == 0, (res.info2d, res.info3d)
+    P = res.P.cpu().numpy()
+    lengths = (g.lx, g.ly, g.lz)
+    # (8): relative residual against that of the zero start (base plane only)
+    P0 = np.zeros_like(P)
+    P0[0] = P[0]
+    r = ref.norm3_interior(ref.residual3(P, None, m.xi, m.alpha, lengths))
+    r0 = ref.norm3_interior(ref.residual3(P0, None, m.xi, m.alpha, lengths))
+    assert r / r0 <= 1.01e-10, r / r0
+    assert abs(r0 / res.info3d["r0"] - 1) < 1e-9
+    assert abs((r / r0) / res.info3d["rel_residual"] - 1) < 1e-3
+    del P0
+    # (11) on the base: (Pxx + Pyy) = -bz0
+    f2 = -w.bz0.copy()
+    f2[0] = f2[-1] = 0
+    f2[:, 0] = f2[:, -1] = 0
+    r2 = ref.residual2(P[0], f2, (g.lx, g.ly))
+    r20 = ref.residual2(np.zeros_like(P[0]), f2, (g.lx, g.ly))
+    assert np.linalg.norm(r2) / np.linalg.norm(r20) <= 1.01e-10
+    # fields on blocks (local stencils: halo 2 in x, y and 1 in z)
+    hx, hy, hz = g.lx / (g.nx - 1), g.ly / (g.ny - 1), g.lz / (g.nz - 1)
+    got = [t for t in (res.Bx, res.By, res.Bz, res.p, res.rho)]
+    for (k0, j0, i0) in ((0, 200, 310), (100, 37, 60), (230, 400, 450)):
+        nb = 24
+        sl = (slice(k0, k0 + nb), slice(j0, j0 + nb), slice(i0, i0 + nb))
+        want = fields.fields(P[sl], m.alpha, m.xi[sl[0]], m.dxi[sl[0]], m.pb[sl[0]], m.rhob[sl[0]], m.mu0, m.g,
+                             (nb - 1) * hx, (nb - 1) * hy, (nb - 1) * hz)
+        # compare where the block's stencils are the full grid's: away from
+        # the block's side faces, below its top, and at its base only on
+        # the grid's base
+        inner = (slice(0 if k0 == 0 else 1, nb - 2), slice(2, nb - 2), slice(2, nb - 2))
+        for name, gt, wt in zip(("Bx", "By", "Bz", "p", "rho"), got, want):
+            gb = gt[sl].cpu().numpy()[inner]
+            wb = wt[inner]
+            if name in ("p", "rho"):
+                base = (m.pb if name == "p" else m.rhob)[sl[0]][inner[0]][:, None, None]
+                gb, wb = gb - base, wb - base
+            assert rel(gb, wb) < 1e-12, (name, (k0, j0, i0), rel(gb, wb))
+    plan.close()
+
+
 def test_repeat_is_bitwise_deterministic(plans):
     w = synth.workload("mhs-129", dims=(65, 65, 65))
     plan = plans((65, 65, 65))
