@@ -24,9 +24,15 @@
  *   - trilinear (bilinear) prolongation of the coarse correction;
  *   - coarse operators by rediscretisation with doubled spacing and xi
  *     sampled at the coarse nodes;
- *   - coarsening of all axes together while every axis has more than 3
- *     nodes, and an exact dense solve (Gaussian elimination with partial
- *     pivoting) on the coarsest grid.
+ *   - coarsening of x and y at every level, and of z as well unless the z
+ *     spacing is at least sqrt(2) times the larger in-plane spacing (then
+ *     only x and y are halved: semicoarsening, with the residual weighted
+ *     and the correction interpolated within each plane), while every axis
+ *     that is halved has more than 3 nodes, and an exact dense solve
+ *     (Gaussian elimination with partial pivoting) on the coarsest grid.
+ *     The paper does not say how the coarse grids are built; this rule
+ *     keeps coarse levels of grids with dz > dx closer to equal spacing,
+ *     which point relaxation needs to smooth in every direction.
  * Stopping rule: ||r_k||_2 / ||r_0||_2 <= rtol over interior nodes, with
  * r_0 the residual of the initial iterate (P = 0 in the interior, step 1 of
  * the procedure in Section 2.2).
@@ -61,15 +67,30 @@ static int valid_axis(int n)
     return (m & (m - 1)) == 0;
 }
 
-/* Number of levels: coarsen every axis together while all axes exceed 3. */
-int ref_nlevels3(int nx, int ny, int nz)
+/* Whether the step from a grid of n nodes on a box of lengths len keeps
+ * the z axis: dz^2 >= 2 max(dx, dy)^2. */
+static int keeps_z(const int *n, const double *len)
 {
-    if (!valid_axis(nx) || !valid_axis(ny) || !valid_axis(nz)) return REF_BAD_GRID;
+    double hx = len[0] / (double)(n[0] - 1), hy = len[1] / (double)(n[1] - 1);
+    double hz = len[2] / (double)(n[2] - 1);
+    double hxy = hx > hy ? hx : hy;
+    return hz * hz >= 2.0 * hxy * hxy;
+}
+
+/* Number of levels of the 3D hierarchy; keepz (may be NULL, room for 32
+ * entries) receives, per step l -> l+1, 1 if z is kept and 0 if halved. */
+int ref_levels3(const int *n0, const double *len, int *keepz)
+{
+    if (!valid_axis(n0[0]) || !valid_axis(n0[1]) || !valid_axis(n0[2])) return REF_BAD_GRID;
+    int n[3] = {n0[0], n0[1], n0[2]};
     int L = 1;
-    while (nx > 3 && ny > 3 && nz > 3) {
-        nx = (nx - 1) / 2 + 1;
-        ny = (ny - 1) / 2 + 1;
-        nz = (nz - 1) / 2 + 1;
+    for (;;) {
+        int kz = keeps_z(n, len);
+        if (!(n[0] > 3 && n[1] > 3 && (kz || n[2] > 3))) break;
+        if (keepz && L - 1 < 32) keepz[L - 1] = kz;
+        n[0] = (n[0] - 1) / 2 + 1;
+        n[1] = (n[1] - 1) / 2 + 1;
+        if (!kz) n[2] = (n[2] - 1) / 2 + 1;
         L++;
     }
     return L;
@@ -183,6 +204,29 @@ void ref_restrict3(const int *nf, const double *rf, double *fc)
             }
 }
 
+/* Full weighting within each plane (z kept): fc(I,J,k) = sum w(a)w(b)
+ * rf(2I+a, 2J+b, k), at coarse interior nodes; coarse boundary = 0. */
+void ref_restrict3_xy(const int *nf, const double *rf, double *fc)
+{
+    static const double w[3] = {0.25, 0.5, 0.25};
+    int nxf = nf[0], nyf = nf[1], nz = nf[2];
+    int ncx = (nf[0] - 1) / 2 + 1, ncy = (nf[1] - 1) / 2 + 1;
+    for (int k = 0; k < nz; k++)
+        for (int J = 0; J < ncy; J++)
+            for (int I = 0; I < ncx; I++) {
+                double s = 0.0;
+                if (I > 0 && I < ncx - 1 && J > 0 && J < ncy - 1 && k > 0 && k < nz - 1) {
+                    for (int b = -1; b <= 1; b++)
+                        for (int a = -1; a <= 1; a++) {
+                            size_t idx = (size_t)(2 * I + a) +
+                                         (size_t)nxf * ((size_t)(2 * J + b) + (size_t)nyf * (size_t)k);
+                            s += w[a + 1] * w[b + 1] * rf[idx];
+                        }
+                }
+                fc[(size_t)I + (size_t)ncx * ((size_t)J + (size_t)ncy * (size_t)k)] = s;
+            }
+}
+
 /* Linear interpolation weight of coarse node C for fine index i along one
  * axis: 1 if i == 2C, 1/2 if |i - 2C| == 1, else 0. */
 static double lin_w(int i, int C)
@@ -207,6 +251,24 @@ void ref_prolong3(const int *nc, const double *ec, double *uf)
                         for (int I = i / 2; I <= (i + 1) / 2; I++)
                             s += lin_w(i, I) * lin_w(j, J) * lin_w(k, K) *
                                  ec[(size_t)I + (size_t)ncx * ((size_t)J + (size_t)ncy * (size_t)K)];
+                AT3(uf, i, j, k) += s;
+            }
+}
+
+/* uf += I(ec) on fine interior nodes, I = bilinear interpolation within
+ * each plane (z kept). */
+void ref_prolong3_xy(const int *nc, const double *ec, double *uf)
+{
+    int ncx = nc[0], ncy = nc[1], nz = nc[2];
+    int nx = 2 * (ncx - 1) + 1, ny = 2 * (ncy - 1) + 1;
+    for (int k = 1; k < nz - 1; k++)
+        for (int j = 1; j < ny - 1; j++)
+            for (int i = 1; i < nx - 1; i++) {
+                double s = 0.0;
+                for (int J = j / 2; J <= (j + 1) / 2; J++)
+                    for (int I = i / 2; I <= (i + 1) / 2; I++)
+                        s += lin_w(i, I) * lin_w(j, J) *
+                             ec[(size_t)I + (size_t)ncx * ((size_t)J + (size_t)ncy * (size_t)k)];
                 AT3(uf, i, j, k) += s;
             }
 }
@@ -303,6 +365,7 @@ typedef struct {
     double *xi; /* xi sampled at this level's z nodes */
     double *u, *f, *r;
     size_t N;
+    int keepz;  /* the step to the next level keeps z */
 } lev3;
 
 static void free_levels3(lev3 *lv, int L)
@@ -318,7 +381,10 @@ static int build_levels3(lev3 *lv, int L, const int *n, const double *len, const
                          double *u0, const double *f0)
 {
     memset(lv, 0, sizeof(lev3) * (size_t)L);
+    int keepz[32] = {0};
+    if (ref_levels3(n, len, keepz) != L) return REF_BAD_GRID;
     int nn[3] = {n[0], n[1], n[2]};
+    size_t stride = 1; /* fine z nodes per z step of this level */
     for (int l = 0; l < L; l++) {
         for (int a = 0; a < 3; a++) {
             lv[l].n[a] = nn[a];
@@ -328,8 +394,8 @@ static int build_levels3(lev3 *lv, int L, const int *n, const double *len, const
         lv[l].xi = (double *)malloc(sizeof(double) * (size_t)nn[2]);
         lv[l].r = (double *)calloc(lv[l].N, sizeof(double));
         if (!lv[l].xi || !lv[l].r) return REF_NOMEM;
-        int stride = 1 << l;
         for (int k = 0; k < nn[2]; k++) lv[l].xi[k] = xi[(size_t)k * stride];
+        lv[l].keepz = (l < L - 1) ? keepz[l] : 0;
         if (l == 0) {
             lv[l].u = u0;
             lv[l].f = (double *)f0;
@@ -338,7 +404,12 @@ static int build_levels3(lev3 *lv, int L, const int *n, const double *len, const
             lv[l].f = (double *)calloc(lv[l].N, sizeof(double));
             if (!lv[l].u || !lv[l].f) return REF_NOMEM;
         }
-        for (int a = 0; a < 3; a++) nn[a] = (nn[a] - 1) / 2 + 1;
+        nn[0] = (nn[0] - 1) / 2 + 1;
+        nn[1] = (nn[1] - 1) / 2 + 1;
+        if (!lv[l].keepz) {
+            nn[2] = (nn[2] - 1) / 2 + 1;
+            stride *= 2;
+        }
     }
     return REF_OK;
 }
@@ -350,11 +421,17 @@ static int vcycle3(lev3 *lv, int l, int L, double alpha, int nu1, int nu2)
     ref_rbgs3(c->n, c->h, c->xi, alpha, c->u, c->f, nu1);
     ref_residual3(c->n, c->h, c->xi, alpha, c->u, c->f, c->r);
     lev3 *d = &lv[l + 1];
-    ref_restrict3(c->n, c->r, d->f);
+    if (c->keepz)
+        ref_restrict3_xy(c->n, c->r, d->f);
+    else
+        ref_restrict3(c->n, c->r, d->f);
     memset(d->u, 0, sizeof(double) * d->N);
     int st = vcycle3(lv, l + 1, L, alpha, nu1, nu2);
     if (st != REF_OK) return st;
-    ref_prolong3(d->n, d->u, c->u);
+    if (c->keepz)
+        ref_prolong3_xy(d->n, d->u, c->u);
+    else
+        ref_prolong3(d->n, d->u, c->u);
     ref_rbgs3(c->n, c->h, c->xi, alpha, c->u, c->f, nu2);
     return REF_OK;
 }
@@ -368,7 +445,7 @@ int ref_mg3(const int *n, const double *len, const double *xi, double alpha, dou
             double rtol, int max_cycles, int nu1, int nu2, int *cycles_out,
             double *relres_out, double *hist)
 {
-    int L = ref_nlevels3(n[0], n[1], n[2]);
+    int L = ref_levels3(n, len, NULL);
     if (L < 1) return REF_BAD_GRID;
     lev3 *lv = (lev3 *)calloc((size_t)L, sizeof(lev3));
     if (!lv) return REF_NOMEM;
@@ -404,7 +481,7 @@ int ref_mg3(const int *n, const double *len, const double *xi, double alpha, dou
 int ref_vcycle3_once(const int *n, const double *len, const double *xi, double alpha,
                      double *u, const double *f, int nu1, int nu2)
 {
-    int L = ref_nlevels3(n[0], n[1], n[2]);
+    int L = ref_levels3(n, len, NULL);
     if (L < 1) return REF_BAD_GRID;
     lev3 *lv = (lev3 *)calloc((size_t)L, sizeof(lev3));
     if (!lv) return REF_NOMEM;

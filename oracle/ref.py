@@ -31,13 +31,15 @@ def _load():
     lib = C.CDLL(LIB)
     vp = C.c_void_p
     sig = {
-        "ref_nlevels3": (C.c_int, [C.c_int, C.c_int, C.c_int]),
+        "ref_levels3": (C.c_int, [_ip, _dp, _ip]),
         "ref_nlevels2": (C.c_int, [C.c_int, C.c_int]),
         "ref_residual3": (None, [_ip, _dp, _dp, C.c_double, _dp, vp, _dp]),
         "ref_norm3_interior": (C.c_double, [_ip, _dp]),
         "ref_rbgs3": (None, [_ip, _dp, _dp, C.c_double, _dp, vp, C.c_int]),
         "ref_restrict3": (None, [_ip, _dp, _dp]),
         "ref_prolong3": (None, [_ip, _dp, _dp]),
+        "ref_restrict3_xy": (None, [_ip, _dp, _dp]),
+        "ref_prolong3_xy": (None, [_ip, _dp, _dp]),
         "ref_direct3": (C.c_int, [_ip, _dp, _dp, C.c_double, _dp, vp]),
         "ref_mg3": (C.c_int, [_ip, _dp, _dp, C.c_double, _dp, C.c_double, C.c_int, C.c_int,
                               C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double), vp]),
@@ -84,8 +86,15 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-def nlevels3(nx, ny, nz):
-    return _load().ref_nlevels3(nx, ny, nz)
+def levels3(nx, ny, nz, lengths=(1.0, 1.0, 1.0)):
+    """(number of 3D levels, [1 if the step l -> l+1 keeps z else 0])."""
+    keep = np.zeros(32, dtype=np.int32)
+    L = _load().ref_levels3(np.array([nx, ny, nz], dtype=np.int32), _f64(lengths), keep)
+    return L, [int(v) for v in keep[: max(L - 1, 0)]]
+
+
+def nlevels3(nx, ny, nz, lengths=(1.0, 1.0, 1.0)):
+    return levels3(nx, ny, nz, lengths)[0]
 
 
 def nlevels2(nx, ny):
@@ -128,6 +137,23 @@ def prolong3(ec, uf):
     ec = _f64(ec)
     uf = _f64(uf).copy()
     _load().ref_prolong3(_n3(ec.shape), ec, uf)
+    return uf
+
+
+def restrict3_xy(rf):
+    """Full weighting within each plane (z kept)."""
+    rf = _f64(rf)
+    nz, ny, nx = rf.shape
+    fc = np.zeros((nz, (ny - 1) // 2 + 1, (nx - 1) // 2 + 1))
+    _load().ref_restrict3_xy(_n3(rf.shape), rf, fc)
+    return fc
+
+
+def prolong3_xy(ec, uf):
+    """Return uf + I(ec) on interior fine nodes (bilinear within planes)."""
+    ec = _f64(ec)
+    uf = _f64(uf).copy()
+    _load().ref_prolong3_xy(_n3(ec.shape), ec, uf)
     return uf
 
 

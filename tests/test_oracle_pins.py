@@ -32,12 +32,22 @@ def lam_mn(nx, ny, m, n, lx=1.0, ly=1.0):
 
 # ---------------------------------------------------------------- grid rules
 def test_level_count_rule():
-    # coarsen every axis together while all exceed 3 nodes
-    assert ref.nlevels3(3, 3, 3) == 1
-    assert ref.nlevels3(33, 33, 33) == 5
+    # x and y halve at every step; z halves too unless dz^2 >= 2 max(dx, dy)^2;
+    # stop when an axis to be halved has 3 nodes
+    assert ref.levels3(3, 3, 3) == (1, [])
+    assert ref.levels3(33, 33, 33) == (5, [0, 0, 0, 0])
     assert ref.nlevels3(257, 257, 257) == 8
-    assert ref.nlevels3(513, 513, 257) == 8  # coarsest 5 x 5 x 3
-    assert ref.nlevels3(129, 129, 65) == 6  # coarsest 5 x 5 x 3
+    # dz = 2 dx: 513^2 x 257 -> 257^3 -> ... -> 3^3
+    assert ref.levels3(513, 513, 257) == (9, [1, 0, 0, 0, 0, 0, 0, 0])
+    assert ref.levels3(129, 129, 65) == (7, [1, 0, 0, 0, 0, 0])
+    # equal spacing by the box lengths: no semicoarsening
+    assert ref.levels3(129, 129, 65, (1.0, 1.0, 0.5)) == (6, [0] * 5)
+    # dz = 4 dx: two steps keep z, then 5^3 -> 3^3
+    assert ref.levels3(17, 17, 5) == (4, [1, 1, 0])
+    # the larger in-plane spacing decides: dx = 1/64, dy = 1/32, dz = 1/16
+    assert ref.levels3(65, 33, 17) == (5, [1, 0, 0, 0])
+    # dz = 1.25 dx (< sqrt 2): all axes halve
+    assert ref.levels3(33, 33, 33, (1.0, 1.0, 1.25))[1] == [0, 0, 0, 0]
     assert ref.nlevels2(513, 513) == 9
     assert ref.nlevels3(30, 33, 33) < 0  # not 2^L + 1
 
@@ -263,6 +273,41 @@ def test_prolongation_reproduces_trilinear():
     assert np.all(uf[0] == 0) and np.all(uf[:, -1] == 0)
 
 
+def test_plane_restriction_is_2d_full_weighting_per_plane():
+    """With z kept, the restriction is the pinned 2D full weighting applied to
+    each interior plane (zero on the bottom and top planes), so it also maps
+    a field bilinear in x and y to its coarse-node values."""
+    rng = np.random.default_rng(4)
+    rf = rng.normal(size=(7, 17, 9))
+    fc = ref.restrict3_xy(rf)
+    assert fc.shape == (7, 9, 5)
+    for k in range(1, 6):
+        assert rel(fc[k], ref.restrict2(rf[k])) < 1e-15
+    assert np.all(fc[0] == 0) and np.all(fc[-1] == 0)
+    f = trilinear_field((7, 17, 9), 5)
+    fc = ref.restrict3_xy(f)
+    assert rel(fc[1:-1, 1:-1, 1:-1], f[1:-1, ::2, ::2][:, 1:-1, 1:-1]) < 1e-14
+    # point response: weights 1/4 * 1/2 (offsets +-1 in x, 0 in y), one plane
+    rf = np.zeros((5, 9, 9))
+    rf[2, 4, 3] = 1.0
+    fc = ref.restrict3_xy(rf)
+    assert fc[2, 2, 1] == 0.125 and fc[2, 2, 2] == 0.125 and fc.sum() == 0.25
+
+
+def test_plane_prolongation_is_bilinear_per_plane():
+    ec = trilinear_field((7, 5, 9), 6)
+    ec[0] = ec[-1] = 0
+    ec[:, 0] = ec[:, -1] = 0
+    ec[:, :, 0] = ec[:, :, -1] = 0
+    uf = ref.prolong3_xy(ec, np.zeros((7, 9, 17)))
+    yc, xc = (np.linspace(0, 1, s) for s in ec.shape[1:])
+    yf, xf = (np.linspace(0, 1, s) for s in uf.shape[1:])
+    t = np.apply_along_axis(lambda v: np.interp(xf, xc, v), 2, ec)
+    t = np.apply_along_axis(lambda v: np.interp(yf, yc, v), 1, t)
+    assert rel(uf[1:-1, 1:-1, 1:-1], t[1:-1, 1:-1, 1:-1]) < 1e-14
+    assert np.all(uf[0] == 0) and np.all(uf[-1] == 0) and np.all(uf[:, :, 0] == 0)
+
+
 def test_residual_matches_dense_matrix():
     shape = (5, 9, 7 + 2)
     rng = np.random.default_rng(9)
@@ -309,22 +354,29 @@ def _vcycle_from_stages(u, f, xi, alpha, lengths, nu1=2, nu2=2):
     """V-cycle assembled from the separately pinned stages: red-black
     smoothing, residual, full weighting, a zero initial coarse guess, xi
     sampled at coarse nodes (xi_{l+1}[k] = xi_l[2k]), doubled spacing, an
-    exact dense solve on the coarsest grid and trilinear prolongation."""
-    if min(u.shape) <= 3:
+    exact dense solve on the coarsest grid and trilinear prolongation; on a
+    step that keeps z (dz^2 >= 2 max(dx, dy)^2) the transfers act within
+    planes and xi is not resampled."""
+    nz, ny, nx = u.shape
+    hx, hy, hz = lengths[0] / (nx - 1), lengths[1] / (ny - 1), lengths[2] / (nz - 1)
+    keep = hz * hz >= 2.0 * max(hx, hy) ** 2
+    if nx <= 3 or ny <= 3 or (nz <= 3 and not keep):
         return dense.solve3(u, f, xi, alpha, *lengths)
     u = ref.rbgs3(u, f, xi, alpha, nu1, lengths)
-    fc = ref.restrict3(ref.residual3(u, f, xi, alpha, lengths))
-    ec = _vcycle_from_stages(np.zeros_like(fc), fc, xi[::2], alpha, lengths, nu1, nu2)
-    u = ref.prolong3(ec, u)
+    r = ref.residual3(u, f, xi, alpha, lengths)
+    fc = ref.restrict3_xy(r) if keep else ref.restrict3(r)
+    ec = _vcycle_from_stages(np.zeros_like(fc), fc, xi if keep else xi[::2], alpha, lengths, nu1, nu2)
+    u = ref.prolong3_xy(ec, u) if keep else ref.prolong3(ec, u)
     return ref.rbgs3(u, f, xi, alpha, nu2, lengths)
 
 
-@pytest.mark.parametrize("shape", [(5, 9, 9), (17, 17, 9), (9, 17, 33)])
-def test_vcycle_equals_composition_of_stages(shape):
+@pytest.mark.parametrize("shape,lengths", [((5, 9, 9), (1.0, 1.5, 0.75)), ((17, 17, 9), (1.0, 1.5, 0.75)),
+                                           ((9, 17, 33), (1.0, 1.5, 0.75)), ((9, 17, 33), (1.0, 1.0, 1.0)),
+                                           ((5, 17, 17), (1.0, 1.0, 1.0))])
+def test_vcycle_equals_composition_of_stages(shape, lengths):
     rng = np.random.default_rng(len(shape) + shape[0])
     nz = shape[0]
     xi = 0.9 * np.exp(-np.linspace(0, 1, nz) / 0.15)
-    lengths = (1.0, 1.5, 0.75)
     u0 = rng.normal(size=shape)
     f = rng.normal(size=shape)
     want = _vcycle_from_stages(u0, f, xi, 0.7, lengths)
@@ -370,6 +422,25 @@ def test_vcycle_contraction_poisson():
     P, st, cyc, rr, hist = ref.mg3(ubc, np.zeros(n), 0.0, rtol=1e-12, history=True)
     rates = hist[3:] / hist[2:-1]
     assert rates.max() < 0.2
+
+
+def test_vcycle_contraction_with_dz_twice_dx():
+    """dz = 2 dx with xi -> 1 at the base (the strongly anisotropic large
+    case): halving x and y alone first keeps the cycle contracting as on an
+    equally spaced grid (below 0.15 per cycle); coarsening all three axes
+    together would leave every level anisotropic (about 0.26 per cycle
+    here)."""
+    nz, n = 33, 65
+    z = np.linspace(0.0, 1.0, nz)
+    xi = np.exp(-z / 0.1)
+    rng = np.random.default_rng(4)
+    ubc = np.zeros((nz, n, n))
+    ubc[0, 1:-1, 1:-1] = rng.normal(size=(n - 2, n - 2))
+    P, st, cyc, rr, hist = ref.mg3(ubc, xi, 0.8, rtol=1e-12, history=True)
+    assert st == ref.OK
+    rates = hist[3:] / hist[2:-1]
+    assert rates.max() < 0.15, rates
+    assert rel(P, exact.solve_interior(ubc[0], nz, xi, 0.8, 1.0, 1.0, 1.0)) < 1e-9
 
 
 # ---------------------------------------------------------------- fields
