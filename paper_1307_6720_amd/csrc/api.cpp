@@ -101,14 +101,18 @@ int check_grid(const mhs_grid *g)
     return MHS_OK;
 }
 
-// Geometry of a hierarchy (no buffers): coarsen every axis together while all
-// axes exceed 3 nodes.
+// Geometry of a hierarchy (no buffers).  Every step halves x and y; a 3D
+// step halves z as well unless dz^2 >= 2 max(dx, dy)^2, when it keeps z (x-y
+// semicoarsening: the paper does not say how coarse grids are built, and
+// halving only the finer axes brings a grid with dz > dx toward equal
+// spacing, where point red-black smoothing reduces the oscillatory error in
+// every direction).  Coarsening stops when an axis to be halved has 3 nodes.
 int build_geometry(Hierarchy &h, const int n0[3], const double len[3], bool planar)
 {
     h = Hierarchy();
     h.planar = planar;
     int n[3] = {n0[0], n0[1], planar ? 1 : n0[2]};
-    int L = 0;
+    int L = 0, zs = 0;
     for (;;) {
         if (L >= kMaxLevels) return fail(MHS_ERR_GRID, "too many levels");
         Level &lv = h.lv[L];
@@ -117,12 +121,19 @@ int build_geometry(Hierarchy &h, const int n0[3], const double len[3], bool plan
         lv.h[1] = len[1] / (n[1] - 1);
         lv.h[2] = planar ? 1.0 : len[2] / (n[2] - 1);
         lv.N = (size_t)n[0] * n[1] * n[2];
+        lv.zs = zs;
         ++L;
-        const bool more = planar ? (n[0] > 3 && n[1] > 3) : (n[0] > 3 && n[1] > 3 && n[2] > 3);
+        const double hxy = std::max(lv.h[0], lv.h[1]);
+        const bool keepz = !planar && lv.h[2] * lv.h[2] >= 2.0 * hxy * hxy;
+        const bool more = n[0] > 3 && n[1] > 3 && (planar || keepz || n[2] > 3);
         if (!more) break;
+        lv.keepz = keepz;
         n[0] = (n[0] - 1) / 2 + 1;
         n[1] = (n[1] - 1) / 2 + 1;
-        if (!planar) n[2] = (n[2] - 1) / 2 + 1;
+        if (!planar && !keepz) {
+            n[2] = (n[2] - 1) / 2 + 1;
+            ++zs;
+        }
     }
     h.L = L;
     if (L < 2) return fail(MHS_ERR_GRID, "grid too small for multigrid");
@@ -238,7 +249,8 @@ int geometry(mhs_plan *p, const mhs_grid *g)
 // ---- coefficient tables and the coarsest-grid inverse --------------------------
 
 // cx_k = (1 - xi_k)/dx^2, cy_k = (1 - xi_k)/dy^2, d_k = alpha^2 - 2cx - 2cy - 2cz
-// (equation (8) at level l, xi sampled at the level's nodes: xi_l[k] = xi[k 2^l]).
+// (equation (8) at level l, xi sampled at the level's nodes: xi_l[k] = xi[k 2^zs],
+// zs the number of steps above l that halved z).
 void level_coef(const Hierarchy &h, int l, double alpha, const double *xi, std::vector<double> &out,
                 double &cz)
 {
@@ -248,7 +260,7 @@ void level_coef(const Hierarchy &h, int l, double alpha, const double *xi, std::
     const double ix2 = 1.0 / (lv.h[0] * lv.h[0]), iy2 = 1.0 / (lv.h[1] * lv.h[1]);
     cz = h.planar ? 0.0 : 1.0 / (lv.h[2] * lv.h[2]);
     for (int k = 0; k < nz; ++k) {
-        const double x = h.planar ? 0.0 : xi[(size_t)k << l];
+        const double x = h.planar ? 0.0 : xi[(size_t)k << lv.zs];
         const double cx = (1.0 - x) * ix2, cy = (1.0 - x) * iy2;
         const double a2 = h.planar ? 0.0 : alpha * alpha;
         const double d = a2 - 2.0 * cx - 2.0 * cy - 2.0 * cz;
@@ -338,7 +350,7 @@ double level_lambda_min(const Hierarchy &h, int l, const double *xi, const doubl
     std::vector<double> a((size_t)m);
     double hi = 0.0;
     for (int q = 0; q < m; ++q) {
-        a[(size_t)q] = 2.0 * iz2 + (1.0 - xi[(size_t)(q + 1) << l]) * lxy;
+        a[(size_t)q] = 2.0 * iz2 + (1.0 - xi[(size_t)(q + 1) << lv.zs]) * lxy;
         hi = q == 0 ? a[0] : std::min(hi, a[(size_t)q]); // Rayleigh quotient of a unit vector
     }
     const double b2 = iz2 * iz2;
@@ -615,7 +627,7 @@ void add_restrict(Program &pg, Staging &st, const Hierarchy &h, int l, int path,
     }
     Launch L{};
     L.kind = h.planar ? Launch::kRestrict2 : Launch::kRestrict3;
-    L.flags = f ? 1 : 0;
+    L.flags = (f ? kRestrictHasF : 0) | (lv.keepz ? kRestrictKeepZ : 0);
     L.dbl = path == kF64;
     L.items = d;
     L.ntiles = lv.restrict_tiles();
@@ -852,7 +864,8 @@ hipError_t exec_launch(const Launch &L, hipStream_t s)
     case Launch::kSweep2:
         return launch_sweep2((const LevelItem *)L.items, L.nitems, L.ntiles, L.flags, L.dbl, s);
     case Launch::kRestrict3:
-        return launch_restrict3((const LevelItem *)L.items, L.nitems, L.ntiles, L.flags != 0, L.dbl, s);
+        return launch_restrict3((const LevelItem *)L.items, L.nitems, L.ntiles, (L.flags & kRestrictHasF) != 0,
+                                (L.flags & kRestrictKeepZ) != 0, L.dbl, s);
     case Launch::kRestrict2:
         return launch_restrict2((const LevelItem *)L.items, L.nitems, L.ntiles, L.dbl, s);
     case Launch::kIr3:

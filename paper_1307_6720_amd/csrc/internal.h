@@ -168,11 +168,17 @@ enum SweepFlags : int {
     kProlong = 8,   // add the interpolated coarse correction to u_in first
 };
 
+// Launch flags of the 3D restriction.
+enum RestrictFlags : int {
+    kRestrictHasF = 1,  // read the right-hand side
+    kRestrictKeepZ = 2, // the step to the coarse level halves x and y only
+};
+
 hipError_t launch_sweep3(const LevelItem *items, int nitems, int ntiles, int flags, bool dbl,
                          hipStream_t s);
 hipError_t launch_sweep2(const LevelItem *items, int nitems, int ntiles, int flags, bool dbl,
                          hipStream_t s);
-hipError_t launch_restrict3(const LevelItem *items, int nitems, int ntiles, bool has_f, bool dbl,
+hipError_t launch_restrict3(const LevelItem *items, int nitems, int ntiles, bool has_f, bool keepz, bool dbl,
                             hipStream_t s);
 hipError_t launch_restrict2(const LevelItem *items, int nitems, int ntiles, bool dbl,
                             hipStream_t s);

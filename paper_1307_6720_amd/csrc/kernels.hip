@@ -470,10 +470,13 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     T fcur[kNF], fnx[kNF], fbm = (T)0;
 #pragma unroll
     for (int k = 0; k < kNF; ++k) fcur[k] = fnx[k] = (T)0;
+    // fine plane p lies between coarse planes p >> zs and (p + zs) >> zs
+    // (zs = 0: the step kept z, and plane p has a coarse plane of its own)
+    const int zs = ncz < nz ? 1 : 0;
     auto fetch_coarse = [&](int p, T(&cdst)[PROLONG ? kCPer : 1]) {
         if constexpr (PROLONG) {
-            const MHS_GLOBAL T *p0 = ec + csxy * (size_t)min(p >> 1, ncz - 1);
-            const MHS_GLOBAL T *p1 = ec + csxy * (size_t)min((p + 1) >> 1, ncz - 1);
+            const MHS_GLOBAL T *p0 = ec + csxy * (size_t)min(p >> zs, ncz - 1);
+            const MHS_GLOBAL T *p1 = ec + csxy * (size_t)min((p + zs) >> zs, ncz - 1);
 #pragma unroll
             for (int r = 0; r < kCPer; ++r) cdst[r] = at(((cw_hi >> r) & 1) ? p1 : p0, cw_g[r]);
         }
@@ -511,7 +514,7 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     auto zy_rows = [&](int p) {
         if constexpr (PROLONG) {
             const T h = (T)0.5;
-            const bool ok = (p & 1) != 0;
+            const bool ok = (p & zs) != 0;
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
                 {
@@ -843,7 +846,9 @@ __global__ __launch_bounds__(kThreads) void k_sweep2(const LevelItem *__restrict
 // ============================================================================
 // 3D residual r = f - A u (on the fly) + full weighting onto coarse nodes:
 //   f_c(I,J,K) = sum_{a,b,c in -1..1} w_a w_b w_c r(2I+a, 2J+b, 2K+c),
-//   w_0 = 1/2, w_{+-1} = 1/4.
+//   w_0 = 1/2, w_{+-1} = 1/4,
+// or, on a step that keeps z (x-y semicoarsening), the same weights within
+// each plane: f_c(I,J,k) = sum_{a,b} w_a w_b r(2I+a, 2J+b, k).
 // A workgroup owns kCX x kCY coarse nodes and marches kKC coarse planes; each
 // fine plane's residual is computed once into LDS from an LDS-staged window
 // of u (three planes in flight) and folded into the coarse sums.
@@ -854,7 +859,7 @@ constexpr int kRRX = 2 * kCX + 1;
 constexpr int kRRY = 2 * kCY + 1;
 static_assert(kCX * kCY == kThreads, "one coarse node per thread");
 
-template <typename T, bool HAS_F>
+template <typename T, bool HAS_F, bool KEEPZ>
 __global__ __launch_bounds__(kThreads) void k_restrict3(const LevelItem *__restrict__ items, int nitems)
 {
     constexpr int kCells = kRWY * kRWX;
@@ -951,17 +956,19 @@ __global__ __launch_bounds__(kThreads) void k_restrict3(const LevelItem *__restr
             if (st_l[r] >= 0) dst[st_l[r]] = ((st_in >> r) & 1) ? src[r] : (T)0;
     };
 
-    // u planes 2Kb-2 .. 2Ke are read; plane p waits in register set
-    // (p - pbase) % D.  Every step issues the same loads (past the top they
-    // repeat the last plane), so the compiler waits for exactly the oldest
-    // register set.
-    const int pbase = 2 * Kb - 2, ptop = 2 * Ke;
-    // fine planes 2Kb-1 .. 2Ke-1 (at most 2 kKC + 1 <= 64) of cx, cy, d
+    // residual planes mfirst .. mlast (2Kb-1 .. 2Ke-1, or Kb .. Ke-1 when z
+    // is kept) from u planes mfirst-1 .. mlast+1; plane p waits in register
+    // set (p - pbase) % D.  Every step issues the same loads (past the top
+    // they repeat the last plane), so the compiler waits for exactly the
+    // oldest register set.
+    const int mfirst = KEEPZ ? Kb : 2 * Kb - 1, mlast = KEEPZ ? Ke - 1 : 2 * Ke - 1;
+    const int pbase = mfirst - 1, ptop = mlast + 1;
+    // the residual planes' cx, cy, d (at most 2 kKC + 1 <= 64)
     static_assert(2 * kKC + 1 <= 64, "one plane per lane");
     PlaneTab<T> tcx, tcy, tdd;
-    tcx.load(coef, 2 * Kb - 1, 0, it->nz);
-    tcy.load(coef, 2 * Kb - 1, 1, it->nz);
-    tdd.load(coef, 2 * Kb - 1, 2, it->nz);
+    tcx.load(coef, mfirst, 0, it->nz);
+    tcy.load(coef, mfirst, 1, it->nz);
+    tdd.load(coef, mfirst, 2, it->nz);
 #pragma unroll
     for (int q = 0; q < D; ++q) {
         fetch(min(pbase + q, ptop), pre[q], fpre[q]);
@@ -977,13 +984,13 @@ __global__ __launch_bounds__(kThreads) void k_restrict3(const LevelItem *__restr
     const T q4 = (T)0.25, h2 = (T)0.5;
     const int cw = 2 * tJ + 1, cc = 2 * tI + 1;
     // whole rounds of D steps (one back edge, so the compiler's waits hold
-    // only the oldest register set); a step past 2 Ke - 1 only stages and
+    // only the oldest register set); a step past mlast only stages and
     // fetches
-    for (int m0 = 2 * Kb - 1; m0 <= 2 * Ke - 1; m0 += D) {
+    for (int m0 = mfirst; m0 <= mlast; m0 += D) {
 #pragma unroll
         for (int dd = 0; dd < D; ++dd) {
             const int m = m0 + dd;
-            const bool live = m <= 2 * Ke - 1;
+            const bool live = m <= mlast;
             // stage u plane m+1 into the slot of plane m-3 (read two steps
             // ago); its register set also carries f plane m
             const int ri = (dd + 2) % D;
@@ -1016,7 +1023,9 @@ __global__ __launch_bounds__(kThreads) void k_restrict3(const LevelItem *__restr
                 return q4 * R[w * kRRX + cc - 1] + h2 * R[w * kRRX + cc] + q4 * R[w * kRRX + cc + 1];
             };
             const T s2 = q4 * row(cw - 1) + h2 * row(cw) + q4 * row(cw + 1);
-            if (m & 1) {
+            if constexpr (KEEPZ) {
+                if (valid) *(MHS_GLOBAL T *)((MHS_GLOBAL char *)(fc + csxy * (size_t)m) + out_g) = s2;
+            } else if (m & 1) {
                 const int Kend = (m - 1) >> 1;
                 if (Kend >= Kb) {
                     acc += q4 * s2;
@@ -1364,17 +1373,19 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(const BottomItem *__r
             });
         }
         lds_barrier();
-        // full weighting onto the interior of level l+1
+        // full weighting onto the interior of level l+1 (within planes when
+        // the step keeps z)
         {
             const int cnx = b.n[l + 1][0], cny = b.n[l + 1][1], cnz = b.n[l + 1][2];
+            const bool zc = !planar && cnz < nz;
             double *fc = smem + b.off_f[l + 1];
             const int cmx = cnx - 2, cmy = cny - 2, cmz = planar ? 1 : cnz - 2;
             bottom_rows(cmx, cmy, cmy * cmz, [&](int q, int jj, int kk) {
                 const int I = q + 1, J = jj + 1, K = planar ? 0 : kk + 1;
-                const int fidx = 2 * I + nx * (2 * J) + sxy * (planar ? 0 : 2 * K);
+                const int fidx = 2 * I + nx * (2 * J) + sxy * (zc ? 2 * K : K);
                 auto row = [&](int c) { return 0.25 * r[c - 1] + 0.5 * r[c] + 0.25 * r[c + 1]; };
                 auto pl = [&](int c) { return 0.25 * row(c - nx) + 0.5 * row(c) + 0.25 * row(c + nx); };
-                const double v = planar ? pl(fidx) : 0.25 * pl(fidx - sxy) + 0.5 * pl(fidx) + 0.25 * pl(fidx + sxy);
+                const double v = !zc ? pl(fidx) : 0.25 * pl(fidx - sxy) + 0.5 * pl(fidx) + 0.25 * pl(fidx + sxy);
                 fc[I + cnx * J + cnx * cny * K] = v;
             });
         }
@@ -1405,13 +1416,15 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(const BottomItem *__r
     for (int l = L - 2; l >= 0; --l) {
         const int nx = b.n[l][0], ny = b.n[l][1], nz = b.n[l][2];
         const int cnx = b.n[l + 1][0], cny = b.n[l + 1][1];
+        const bool zc = !planar && b.n[l + 1][2] < nz;
         const int sxy = nx * ny;
         const int mx = nx - 2, my = ny - 2, mz = planar ? 1 : nz - 2;
         double *u = smem + b.off_u[l];
         const double *ec = smem + b.off_u[l + 1];
         bottom_rows(mx, my, my * mz, [&](int q, int jj, int kk) {
             const int i = q + 1, j = jj + 1, k = planar ? 0 : kk + 1;
-            const double v = planar ? interp2<double>(ec, cnx, i, j) : interp3<double>(ec, cnx, cny, i, j, k);
+            const double v = zc ? interp3<double>(ec, cnx, cny, i, j, k)
+                                : interp2<double>(ec + (size_t)cnx * cny * k, cnx, i, j);
             u[i + nx * j + sxy * k] += v;
         });
         lds_barrier();
@@ -1909,20 +1922,30 @@ hipError_t launch_sweep2(const LevelItem *items, int nitems, int ntiles, int fla
                : sweep2_dispatch<float>(items, nitems, ntiles, flags, s);
 }
 
-hipError_t launch_restrict3(const LevelItem *items, int nitems, int ntiles, bool has_f, bool dbl, hipStream_t s)
+template <typename T, bool HAS_F>
+static void restrict3_variant(const LevelItem *items, int nitems, dim3 grid, bool keepz, hipStream_t s)
+{
+    if (keepz)
+        hipLaunchKernelGGL((k_restrict3<T, HAS_F, true>), grid, dim3(kThreads), 0, s, items, nitems);
+    else
+        hipLaunchKernelGGL((k_restrict3<T, HAS_F, false>), grid, dim3(kThreads), 0, s, items, nitems);
+}
+
+hipError_t launch_restrict3(const LevelItem *items, int nitems, int ntiles, bool has_f, bool keepz, bool dbl,
+                            hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
-    dim3 grid(ntiles), block(kThreads);
+    dim3 grid(ntiles);
     if (dbl) {
         if (has_f)
-            hipLaunchKernelGGL((k_restrict3<double, true>), grid, block, 0, s, items, nitems);
+            restrict3_variant<double, true>(items, nitems, grid, keepz, s);
         else
-            hipLaunchKernelGGL((k_restrict3<double, false>), grid, block, 0, s, items, nitems);
+            restrict3_variant<double, false>(items, nitems, grid, keepz, s);
     } else {
         if (has_f)
-            hipLaunchKernelGGL((k_restrict3<float, true>), grid, block, 0, s, items, nitems);
+            restrict3_variant<float, true>(items, nitems, grid, keepz, s);
         else
-            hipLaunchKernelGGL((k_restrict3<float, false>), grid, block, 0, s, items, nitems);
+            restrict3_variant<float, false>(items, nitems, grid, keepz, s);
     }
     return hipGetLastError();
 }

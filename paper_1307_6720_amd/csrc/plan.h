@@ -27,6 +27,8 @@ struct Level {
     int rt[3] = {0, 0, 0}; // restriction tiles per axis (onto level+1)
     int kz = 1;            // smoother planes per workgroup
     int kc = 1;            // restriction coarse planes per workgroup
+    int zs = 0;            // xi of plane k is xi[k << zs] of the finest grid
+    bool keepz = false;    // the step to level+1 halves x and y only
     int sweep_tiles() const { return st[0] * st[1] * st[2]; }
     int restrict_tiles() const { return rt[0] * rt[1] * rt[2]; }
 };

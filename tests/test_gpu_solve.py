@@ -59,15 +59,21 @@ def plans():
 
 
 @pytest.mark.parametrize("dims,cycles", [((33, 33, 33), 1), ((33, 33, 33), 3), ((65, 33, 17), 2),
-                                         ((129, 65, 65), 2)])
+                                         ((129, 65, 65), 2), ((129, 129, 65), 2), ((33, 33, 5), 3)])
 def test_fixed_cycle_algorithm_parity(plans, dims, cycles):
     """Same V(2,2) method as the oracle's C twin: equal iterates after a fixed
-    number of cycles (2D and 3D)."""
+    number of cycles (2D and 3D).  (65, 33, 17) and (129, 129, 65) halve x
+    and y alone on their first step; (33, 33, 5) does so on three steps, two
+    of them inside the bottom solver."""
     nx, ny, nz = dims
     print(f"[solve] fixed cycles {dims} x{cycles}", flush=True)
     w = synth.workload("mhs-129", dims=dims)
     m = w.model
     plan = plans(dims)
+    L, keep = ref.levels3(nx, ny, nz)
+    assert plan.levels(3) == L
+    assert [plan.level_shape(3, l + 1)[0] == plan.level_shape(3, l)[0] for l in range(L - 1)] == \
+        [bool(k) for k in keep]
     # 2D: oracle P0 after `cycles` cycles
     P0_ref, st, c2, _ = ref.mg2(w.bz0, rtol=0.0, max_cycles=cycles)
     assert c2 == cycles
@@ -143,6 +149,11 @@ def test_full_size_513_properties():
     res = solve(plan, torch.from_numpy(w.bz0).to(DEV), m, precision=PREC_MIXED, rtol=1e-10)
     torch.cuda.synchronize()
     assert res.info2d["status"] == 0 and res.info3d["status"] == 0, (res.info2d, res.info3d)
+    # dz = 2 dx: the first step halves x and y only, and the cycle contracts
+    # as on an equally spaced grid (9 refinement steps; 18 with all axes
+    # halved together)
+    assert plan.level_shape(3, 1) == (257, 257, 257)
+    assert res.info3d["cycles"] <= 10, res.info3d
     P = res.P.cpu().numpy()
     lengths = (g.lx, g.ly, g.lz)
     # (8): relative residual against that of the zero start (base plane only)

@@ -19,7 +19,9 @@ from paper_1307_6720_amd import PREC_FP64, PREC_MIXED  # noqa: E402
 from paper_1307_6720_amd.solver import Plan  # noqa: E402
 
 DEV = "cuda:0"
-SHAPES = [(33, 33, 33), (17, 33, 129), (33, 65, 65)]  # (nz, ny, nx)
+# (nz, ny, nx) on a 1.0 x 1.3 x 0.8 box; (9, 65, 129) has dz^2 >= 2 max(dx, dy)^2
+# on levels 0 and 1, whose steps halve x and y only
+SHAPES = [(33, 33, 33), (17, 33, 129), (33, 65, 65), (9, 65, 129)]
 
 
 def rel(a, b):
@@ -51,13 +53,39 @@ def setup(request):
     plan.close()
 
 
+def level_xi(plan, model, level):
+    """xi at the z nodes of a level (every (nz0 - 1) / (nz_l - 1)-th node)."""
+    nz0 = plan.level_shape(3, 0)[0]
+    return model.xi[:: (nz0 - 1) // (plan.level_shape(3, level)[0] - 1)]
+
+
+def keeps_z(plan, level):
+    return plan.level_shape(3, level + 1)[0] == plan.level_shape(3, level)[0]
+
+
+def restrict(plan, level, r):
+    return ref.restrict3_xy(r) if keeps_z(plan, level) else ref.restrict3(r)
+
+
+def prolong(plan, level, ec, u):
+    return ref.prolong3_xy(ec, u) if keeps_z(plan, level) else ref.prolong3(ec, u)
+
+
 def level_args(plan, model, grid, level):
     if level >= bottom_level(plan, model):
         pytest.skip("level handled by the bottom solver")
     shape = plan.level_shape(3, level)
-    xi = model.xi[:: 2 ** level]
+    xi = level_xi(plan, model, level)
     lengths = (grid.lx, grid.ly, grid.lz)
     return shape, xi, lengths
+
+
+def test_level_shapes_match_oracle_rule(setup):
+    grid, plan, model = setup
+    L, keep = ref.levels3(grid.nx, grid.ny, grid.nz, (grid.lx, grid.ly, grid.lz))
+    assert plan.levels(3) <= L
+    for l in range(plan.levels(3) - 1):
+        assert keeps_z(plan, l) == bool(keep[l]), l
 
 
 def tg(a, dtype=torch.float64):
@@ -99,7 +127,7 @@ def test_restrict3(setup, level):
     rng = np.random.default_rng(level + 3)
     u = rng.normal(size=shape)
     f = rng.normal(size=shape) if level > 0 else None
-    want = ref.restrict3(ref.residual3(u, f, xi, model.alpha, lengths))
+    want = restrict(plan, level, ref.residual3(u, f, xi, model.alpha, lengths))
     fc = torch.zeros(cshape, dtype=torch.float64, device=DEV)
     plan.stage_restrict(model, 3, level, tg(u), None if f is None else tg(f), fc)
     assert rel(fc.cpu().numpy(), want) < 1e-13
@@ -112,7 +140,7 @@ def test_restrict3_fp32(setup):
     rng = np.random.default_rng(5)
     u = rng.normal(size=shape).astype(np.float32).astype(np.float64)
     f = rng.normal(size=shape).astype(np.float32).astype(np.float64)
-    want = ref.restrict3(ref.residual3(u, f, xi, model.alpha, lengths))
+    want = restrict(plan, 0, ref.residual3(u, f, xi, model.alpha, lengths))
     fc = torch.zeros(cshape, dtype=torch.float32, device=DEV)
     plan.stage_restrict(model, 3, 0, tg(u, torch.float32), tg(f, torch.float32), fc, precision=PREC_MIXED)
     assert rel(fc.double().cpu().numpy(), want) < 1e-5
@@ -130,7 +158,7 @@ def test_correct_smooth3(setup, level):
     ec[0] = ec[-1] = 0
     ec[:, 0] = ec[:, -1] = 0
     ec[:, :, 0] = ec[:, :, -1] = 0
-    want = ref.rbgs3(ref.prolong3(ec, u0), f, xi, model.alpha, 1, lengths)
+    want = ref.rbgs3(prolong(plan, level, ec, u0), f, xi, model.alpha, 1, lengths)
     u = tg(u0)
     plan.stage_correct_smooth(model, 3, level, u, tg(f), tg(ec))
     assert rel(u.cpu().numpy(), want) < 1e-13
@@ -146,7 +174,7 @@ def test_bottom3(setup):
     f = rng.normal(size=shape)
     u = torch.zeros(shape, dtype=torch.float64, device=DEV)
     assert plan.stage_bottom(model, 3, u, tg(f)) == b
-    xi = model.xi[:: 2 ** b]
+    xi = level_xi(plan, model, b)
     lengths = (grid.lx, grid.ly, grid.lz)
     want = ref.vcycle3_once(np.zeros(shape), f, xi, model.alpha, 2, 2, lengths)
     assert rel(u.cpu().numpy(), want) < 1e-12
