@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--batch", type=int, default=12,
                     help="concurrent requests in the batched pass over the workload (0: single stream only)")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--large-workload", default="mhs-513x513x257",
+                    help="the large single equilibrium reported beside the headline ('' skips it)")
     ap.add_argument("--counter-probe", action="store_true",
                     help="run only the workload of the rocprofv3 FETCH_SIZE/WRITE_SIZE runs")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -461,6 +463,43 @@ ROCTX = _Roctx()
 ROOFLINE_RANGE = "roofline_pass"
 
 
+def large_leg(a, torch, dev, reps=5):
+    """The large anisotropic equilibrium (513 x 513 x 257, dz = 2 dx, xi(0) =
+    1): per path, the solve time, the refinement steps or V-cycles and the
+    traffic model's rate of the 3D part, plus the level shapes (the first
+    step halves x and y only)."""
+    import synth
+    from paper_1307_6720_amd import PREC_FP64, PREC_MIXED
+    from paper_1307_6720_amd.solver import Plan, solve
+
+    w = synth.workload(a.large_workload)
+    g = w.grid
+    N = g.npoints
+    plan = Plan(g, PREC_FP64 | PREC_MIXED, device=dev)
+    bz = torch.from_numpy(w.bz0).to(dev)
+    arrays = tuple(torch.empty(g.shape, dtype=torch.float64, device=dev) for _ in range(6))
+    out = {"workload": a.large_workload, "grid": f"{g.nx}x{g.ny}x{g.nz}", "rtol": a.rtol}
+    for prec, name, per_cycle in ((PREC_MIXED, "mixed", (32.0 + 74.29 * a.inner_cycles) * N),
+                                  (PREC_FP64, "fp64", 108.57 * N)):
+        for _ in range(2):
+            solve(plan, bz, w.model, precision=prec, rtol=a.rtol, inner_cycles=a.inner_cycles, out=arrays)
+        torch.cuda.synchronize()
+        ts, res = [], None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            res = solve(plan, bz, w.model, precision=prec, rtol=a.rtol, inner_cycles=a.inner_cycles, out=arrays)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        i3 = res.info3d
+        out[name] = {"ms_per_solve": 1e3 * sum(ts) / reps, "cycles_3d": i3["cycles"],
+                     "cycles_2d": res.info2d["cycles"], "rel_residual": i3["rel_residual"],
+                     "model_gbps_3d": i3["cycles"] * per_cycle / i3["seconds"] / 1e9}
+    out["levels"] = [list(plan.level_shape(3, l)) for l in range(plan.levels(3))]
+    plan.close()
+    del arrays
+    return out
+
+
 def batched_leg(a, runs, bz, prec, steps, warm=True, profile=False):
     """The same equilibria served by the batching server with `a.batch`
     requests in flight (all queued at once): whole-job throughput and
@@ -682,6 +721,7 @@ def main():
     serving = None
     if a.serve_requests > 0:
         serving = serve_leg(a, torch, dev)
+    large = large_leg(a, torch, dev) if a.large_workload else None
 
     single_mixed = a.steps / mix_total
     if batched is not None:
@@ -729,6 +769,7 @@ def main():
         "roofline_single_request": roof_single,
         "diagnostics": diagnostics,
         "serving": serving,
+        "large_case": large,
         "context": {"paper_speedup": "x30 GPU vs serial (x32.4 at 128^3, x29.6 at 256^3); hardware unstated"},
     }
     if not a.no_cpu:
