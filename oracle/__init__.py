@@ -14,6 +14,8 @@ computes, written from Section 2.2 of MacTaggart et al. (arXiv:1307.6720):
 * ``dense``  -- brute-force dense solves on tiny grids.
 * ``diagnostics`` -- current density, force-balance and divergence residuals
   of equations (1)-(3) (Section 2.1) by the same differences.
+* ``fieldlines`` -- magnetic field lines (the curves Section 3 draws):
+  fourth-order Runge-Kutta in arc length on trilinearly interpolated B.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  It shares no code with the HIP path
