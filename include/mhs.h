@@ -243,6 +243,33 @@ int mhs_diagnostics(mhs_plan *plan, const mhs_model *model, const double *d_Bx, 
                     const double *d_Bz, const double *d_p, const double *d_rho, double *d_jx,
                     double *d_jy, double *d_jz, double *d_fres, double *d_divb, void *stream);
 
+/* ---- field lines --------------------------------------------------------- *
+ * Magnetic field lines, the curves through which Section 3 presents each
+ * equilibrium (the paper does not say how it traces them).  Line l starts at
+ * seed l and follows dx/ds = B/|B| in arc length s with the classical
+ * fourth-order Runge-Kutta method and a fixed step ds (ds < 0 traces against
+ * B).  B between nodes is the trilinear interpolation of the node values of
+ * the cell holding the point (nested linear interpolations along x, then y,
+ * then z); a Runge-Kutta stage outside the box takes the value at its
+ * coordinates clamped to the box.  A line ends when a step would leave the
+ * box [0, lx] x [0, ly] x [0, lz] (status 1; that point is dropped), when a
+ * stage finds |B| <= bmin (status 2: a null), or after max_steps steps
+ * (status 0); a seed outside the box gives a line of one point, status 1.
+ * d_Bx, d_By, d_Bz: device (nz, ny, nx) FP64 on the plan's grid (normally
+ * from mhs_fields).  d_seeds: device nlines x 3 (x, y, z).  d_points: device
+ * (max_steps + 1) x nlines x 3, point n of line l at 3 (n nlines + l)
+ * (point 0 = the seed; points past d_count[l] are not written).  d_count,
+ * d_status: device int32, nlines each.  All caller-owned; asynchronous on
+ * `stream`; allocates nothing.  Errors: MHS_ERR_INVALID_ARG (NULL pointer
+ * with nlines > 0, nlines < 0, max_steps < 0, ds zero or not finite, bmin
+ * negative or not finite), MHS_ERR_HIP. */
+#define MHS_LINE_MAX_STEPS 0
+#define MHS_LINE_EXIT 1
+#define MHS_LINE_NULL 2
+int mhs_trace_field_lines(mhs_plan *plan, const double *d_Bx, const double *d_By, const double *d_Bz,
+                          const double *d_seeds, int32_t nlines, double ds, int32_t max_steps, double bmin,
+                          double *d_points, int32_t *d_count, int32_t *d_status, void *stream);
+
 /* ---- measurement ------------------------------------------------------- *
  * When profiling is enabled on a plan, each launch of the selected kernel
  * classes below is bracketed by HIP events on the call's stream (select
@@ -259,8 +286,9 @@ int mhs_diagnostics(mhs_plan *plan, const mhs_model *model, const double *d_Bx, 
 #define MHS_PROF_BOTTOM 4      /* single-workgroup bottom solver          */
 #define MHS_PROF_COARSE 5      /* every other stencil launch (levels >= 1, 2D) */
 #define MHS_PROF_DIAG 6        /* diagnostics (mhs_diagnostics)            */
-#define MHS_PROF_NCLASS 7
-#define MHS_PROF_ALL 0x7f      /* mask of every class                      */
+#define MHS_PROF_TRACE 7       /* field lines (mhs_trace_field_lines)      */
+#define MHS_PROF_NCLASS 8
+#define MHS_PROF_ALL 0xff      /* mask of every class                      */
 
 /* class_mask: bit (1 << MHS_PROF_x) times class x; 0 disables profiling. */
 int mhs_profile_enable(mhs_plan *plan, int32_t class_mask);

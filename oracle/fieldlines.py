@@ -66,7 +66,8 @@ def _tangent(B, pos, lengths, bmin):
     ok = b > bmin
     with np.errstate(divide="ignore", invalid="ignore"):
         t = np.stack([bx / b, by / b, bz / b], axis=1)
-    return t, ok
+    # a failed stage ends the line; zero keeps the later stages finite
+    return np.where(ok[:, None], t, 0.0), ok
 
 
 def _inside(pos, lengths):
@@ -100,8 +101,7 @@ def trace(Bx, By, Bz, seeds, ds, max_steps, bmin=0.0, lengths=(1.0, 1.0, 1.0)):
         k3, ok3 = _tangent(B, p + hh * k2, lengths, bmin)
         k4, ok4 = _tangent(B, p + ds * k3, lengths, bmin)
         null = ~(ok1 & ok2 & ok3 & ok4)
-        with np.errstate(invalid="ignore"):
-            q = p + h6 * (((k1 + 2.0 * k2) + 2.0 * k3) + k4)
+        q = p + h6 * (((k1 + 2.0 * k2) + 2.0 * k3) + k4)
         out = ~null & ~_inside(q, lengths)
         step = ~null & ~out
         status[idx[null]] = NULL

@@ -32,7 +32,8 @@ PREC_FP64 = 1
 PREC_MIXED = 2
 
 PROF_SMOOTH_L0, PROF_REFINE, PROF_RESTRICT_L0, PROF_FIELDS, PROF_BOTTOM, PROF_COARSE = range(6)
-PROF_NAMES = ("smooth_l0", "refine", "restrict_l0", "fields", "bottom", "coarse", "diag")
+PROF_NAMES = ("smooth_l0", "refine", "restrict_l0", "fields", "bottom", "coarse", "diag", "trace")
+LINE_MAX_STEPS, LINE_EXIT, LINE_NULL = 0, 1, 2
 
 
 class MHSError(RuntimeError):
@@ -101,6 +102,7 @@ def lib():
         "mhs_stage_bottom": (C.c_int, [vp, P(Model), i32, i32, vp, vp, i32, i32, P(i32), vp]),
         "mhs_stage_residual_norm": (C.c_int, [vp, P(Model), i32, i32, i32, vp, vp, P(dbl), vp]),
         "mhs_diagnostics": (C.c_int, [vp, P(Model)] + [vp] * 10 + [vp]),
+        "mhs_trace_field_lines": (C.c_int, [vp, vp, vp, vp, vp, i32, dbl, i32, dbl, vp, vp, vp, vp]),
         "mhs_profile_enable": (C.c_int, [vp, i32]),
         "mhs_profile_read": (C.c_int, [vp, i32, P(dbl), P(C.c_int64), P(dbl), i32]),
     }

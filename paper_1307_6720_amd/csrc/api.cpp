@@ -1409,6 +1409,62 @@ int mhs_diagnostics(mhs_plan *p, const mhs_model *model, const double *d_Bx, con
     return MHS_OK;
 }
 
+int mhs_trace_field_lines(mhs_plan *p, const double *d_Bx, const double *d_By, const double *d_Bz,
+                          const double *d_seeds, int32_t nlines, double ds, int32_t max_steps, double bmin,
+                          double *d_points, int32_t *d_count, int32_t *d_status, void *stream)
+{
+    if (!p) return fail(MHS_ERR_INVALID_ARG, "plan is NULL");
+    if (nlines < 0 || max_steps < 0) return fail(MHS_ERR_INVALID_ARG, "nlines and max_steps must be >= 0");
+    if (!(ds != 0.0) || !std::isfinite(ds)) return fail(MHS_ERR_INVALID_ARG, "ds must be finite and nonzero");
+    if (!(bmin >= 0.0) || !std::isfinite(bmin)) return fail(MHS_ERR_INVALID_ARG, "bmin must be finite and >= 0");
+    if (nlines == 0) return MHS_OK;
+    if (!d_Bx || !d_By || !d_Bz || !d_seeds || !d_points || !d_count || !d_status)
+        return fail(MHS_ERR_INVALID_ARG, "NULL argument");
+    int st = set_device(p);
+    if (st) return st;
+    TraceItem it{};
+    it.Bx = d_Bx;
+    it.By = d_By;
+    it.Bz = d_Bz;
+    it.seeds = d_seeds;
+    it.points = d_points;
+    it.count = d_count;
+    it.status = d_status;
+    it.lx = p->grid.lx;
+    it.ly = p->grid.ly;
+    it.lz = p->grid.lz;
+    it.dx = p->grid.lx / (p->grid.nx - 1);
+    it.dy = p->grid.ly / (p->grid.ny - 1);
+    it.dz = p->grid.lz / (p->grid.nz - 1);
+    it.ds = ds;
+    it.bmin = bmin;
+    it.nx = p->grid.nx;
+    it.ny = p->grid.ny;
+    it.nz = p->grid.nz;
+    it.nlines = nlines;
+    it.max_steps = max_steps;
+    hipStream_t s = (hipStream_t)stream;
+    Profiler &pr = p->prof;
+    const bool timed = ((pr.mask >> MHS_PROF_TRACE) & 1) != 0;
+    ProfRecord rec{};
+    if (timed) {
+        rec.klass = MHS_PROF_TRACE;
+        rec.cycle = -1;
+        rec.bytes = 0.0; // gathers through the caches: no compulsory-traffic model
+        rec.start = prof_event(pr);
+        rec.end = prof_event(pr);
+        if (!rec.start || !rec.end) return fail(MHS_ERR_HIP, "event creation failed");
+        HIPCHK(hipEventRecord(rec.start, s));
+    }
+    const hipError_t e = launch_trace(it, s);
+    if (e != hipSuccess) return fail(MHS_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+    if (timed) {
+        HIPCHK(hipEventRecord(rec.end, s));
+        pr.pending.push_back(rec);
+    }
+    return MHS_OK;
+}
+
 int mhs_profile_enable(mhs_plan *p, int32_t class_mask)
 {
     if (!p) return fail(MHS_ERR_INVALID_ARG, "plan is NULL");

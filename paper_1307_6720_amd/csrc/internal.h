@@ -147,6 +147,21 @@ struct DiagItem {
     int32_t kz; // planes per workgroup
 };
 
+// Field-line tracing: one thread per line (seeds and points x, y, z
+// interleaved; points of step n at 3 (n nlines + l)).
+struct TraceItem {
+    const double *Bx, *By, *Bz;
+    const double *seeds; // nlines x 3
+    double *points;      // (max_steps + 1) x nlines x 3
+    int32_t *count;      // points per line (>= 1)
+    int32_t *status;     // 0 step cap, 1 left the box, 2 |B| <= bmin
+    double lx, ly, lz;
+    double dx, dy, dz;
+    double ds, bmin;
+    int32_t nx, ny, nz;
+    int32_t nlines, max_steps;
+};
+
 // Whole-array preparation items.
 struct PrepItem {
     double *P;          // 3D potential (or the base plane for 2D)
@@ -187,6 +202,7 @@ hipError_t launch_bottom(const BottomItem *items, int nitems, int lds_bytes, boo
 hipError_t launch_finalize(const FinalizeItem *items, int nitems, hipStream_t s);
 hipError_t launch_fields(const FieldsItem *items, int nitems, int ntiles, hipStream_t s);
 hipError_t launch_diag(const DiagItem &item, hipStream_t s);
+hipError_t launch_trace(const TraceItem &item, hipStream_t s);
 hipError_t launch_prep3(const PrepItem *items, int nitems, int64_t nthreads, hipStream_t s);
 hipError_t launch_prep2(const PrepItem *items, int nitems, int64_t nthreads, hipStream_t s);
 hipError_t launch_copy(const double *src, double *dst, int64_t n, const SolveState *skip,

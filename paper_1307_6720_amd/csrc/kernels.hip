@@ -1799,6 +1799,104 @@ __global__ __launch_bounds__(kThreads) void k_diag(const DiagItem it)
 }
 
 // ============================================================================
+// Field lines (the curves of Section 3's figures): dx/ds = B/|B| in arc
+// length, classical fourth-order Runge-Kutta with a fixed step ds, B between
+// nodes by trilinear interpolation (nested linear interpolations a + t (b -
+// a) along x, then y, then z, coordinates clamped to the box).  A line ends
+// when a step would leave the box (kTraceExit; that point is not written),
+// when a stage finds |B| <= bmin (kTraceNull), or after max_steps steps.
+// One thread per line; point n of line l is at points[3 (n nlines + l)], so
+// the lanes of a wave write consecutive records.  Contraction is off: every
+// operation is rounded as written, as in the oracle's definition.
+// ============================================================================
+constexpr int kTraceThreads = 256;
+enum TraceStatus : int32_t { kTraceMaxSteps = 0, kTraceExit = 1, kTraceNull = 2 };
+
+__global__ __launch_bounds__(kTraceThreads) void k_trace(const TraceItem it)
+{
+#pragma clang fp contract(off)
+    const int l = blockIdx.x * kTraceThreads + (int)threadIdx.x;
+    if (l >= it.nlines) return;
+    const MHS_GLOBAL double *Bx = gin<double>(it.Bx), *By = gin<double>(it.By), *Bz = gin<double>(it.Bz);
+    const MHS_GLOBAL double *seed = gin<double>(it.seeds) + 3 * (size_t)l;
+    MHS_GLOBAL double *pts = gout<double>(it.points);
+    const size_t rec = 3 * (size_t)it.nlines; // doubles per step
+    const int nx = it.nx, ny = it.ny;
+    const size_t sxy = (size_t)nx * ny;
+    auto locate = [](double x, double len, double h, int n, int &i, double &t) {
+        const double p = fmin(fmax(x, 0.0), len);
+        const double f = p / h;
+        i = min((int)floor(f), n - 2);
+        t = f - (double)i;
+    };
+    auto lerp = [](double a, double b, double t) { return a + t * (b - a); };
+    // unit tangent at (x, y, z); false when |B| <= bmin
+    auto tangent = [&](double x, double y, double z, double &tx, double &ty, double &tz) {
+        int i, j, k;
+        double fx, fy, fz;
+        locate(x, it.lx, it.dx, nx, i, fx);
+        locate(y, it.ly, it.dy, ny, j, fy);
+        locate(z, it.lz, it.dz, it.nz, k, fz);
+        const size_t c = (size_t)i + (size_t)nx * j + sxy * k;
+        auto trilin = [&](const MHS_GLOBAL double *F) {
+            const double c00 = lerp(F[c], F[c + 1], fx);
+            const double c10 = lerp(F[c + nx], F[c + nx + 1], fx);
+            const double c01 = lerp(F[c + sxy], F[c + sxy + 1], fx);
+            const double c11 = lerp(F[c + sxy + nx], F[c + sxy + nx + 1], fx);
+            return lerp(lerp(c00, c10, fy), lerp(c01, c11, fy), fz);
+        };
+        const double bx = trilin(Bx), by = trilin(By), bz = trilin(Bz);
+        const double b = sqrt((bx * bx + by * by) + bz * bz);
+        if (!(b > it.bmin)) return false;
+        tx = bx / b;
+        ty = by / b;
+        tz = bz / b;
+        return true;
+    };
+    auto inside = [&](double x, double y, double z) {
+        return x >= 0.0 && x <= it.lx && y >= 0.0 && y <= it.ly && z >= 0.0 && z <= it.lz;
+    };
+    double x = seed[0], y = seed[1], z = seed[2];
+    MHS_GLOBAL double *o = pts + 3 * (size_t)l;
+    o[0] = x;
+    o[1] = y;
+    o[2] = z;
+    const double ds = it.ds, hh = 0.5 * ds, h6 = ds / 6.0;
+    int n = 0;
+    int32_t st = kTraceMaxSteps;
+    if (!inside(x, y, z)) {
+        st = kTraceExit;
+    } else {
+        for (; n < it.max_steps; ++n) {
+            double k1x, k1y, k1z, k2x, k2y, k2z, k3x, k3y, k3z, k4x, k4y, k4z;
+            if (!tangent(x, y, z, k1x, k1y, k1z) ||
+                !tangent(x + hh * k1x, y + hh * k1y, z + hh * k1z, k2x, k2y, k2z) ||
+                !tangent(x + hh * k2x, y + hh * k2y, z + hh * k2z, k3x, k3y, k3z) ||
+                !tangent(x + ds * k3x, y + ds * k3y, z + ds * k3z, k4x, k4y, k4z)) {
+                st = kTraceNull;
+                break;
+            }
+            const double qx = x + h6 * (((k1x + 2.0 * k2x) + 2.0 * k3x) + k4x);
+            const double qy = y + h6 * (((k1y + 2.0 * k2y) + 2.0 * k3y) + k4y);
+            const double qz = z + h6 * (((k1z + 2.0 * k2z) + 2.0 * k3z) + k4z);
+            if (!inside(qx, qy, qz)) {
+                st = kTraceExit;
+                break;
+            }
+            x = qx;
+            y = qy;
+            z = qz;
+            o += rec;
+            o[0] = x;
+            o[1] = y;
+            o[2] = z;
+        }
+    }
+    gout<int32_t>(it.count)[l] = n + 1;
+    gout<int32_t>(it.status)[l] = st;
+}
+
+// ============================================================================
 // Preparation and copies.
 // ============================================================================
 template <typename Item>
@@ -2013,6 +2111,14 @@ hipError_t launch_diag(const DiagItem &item, hipStream_t s)
     const dim3 grid((unsigned)((item.nx + kDX - 1) / kDX), (unsigned)((item.ny + kDY - 1) / kDY),
                     (unsigned)((item.nz + item.kz - 1) / item.kz));
     hipLaunchKernelGGL(k_diag, grid, dim3(kThreads), 0, s, item);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace(const TraceItem &item, hipStream_t s)
+{
+    if (item.nlines <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((item.nlines + kTraceThreads - 1) / kTraceThreads);
+    hipLaunchKernelGGL(k_trace, dim3(blocks), dim3(kTraceThreads), 0, s, item);
     return hipGetLastError();
 }
 

@@ -204,6 +204,32 @@ class Plan:
                                              *[_ptr(t) for t in out], _stream(self.device)))
         return out
 
+    def trace_field_lines(self, Bx, By, Bz, seeds, ds, max_steps, bmin=0.0, out=None):
+        """Field lines through `seeds` (torch float64 (nlines, 3) on the
+        plan's device): returns (points, count, status) with points of shape
+        (max_steps + 1, nlines, 3) (line l is points[:count[l], l]; later
+        entries are not written), count and status int32 (nlines,); status
+        0 = step cap, 1 = left the box, 2 = |B| <= bmin.  ds < 0 traces
+        against B."""
+        for t in (Bx, By, Bz):
+            if tuple(t.shape) != self.shape or t.dtype != torch.float64 or not t.is_contiguous():
+                raise ValueError(f"fields must be contiguous float64 tensors of shape {self.shape}")
+        if seeds.dtype != torch.float64 or seeds.dim() != 2 or seeds.shape[1] != 3 or not seeds.is_contiguous():
+            raise ValueError("seeds must be a contiguous float64 tensor of shape (nlines, 3)")
+        n = seeds.shape[0]
+        if out is None:
+            out = (torch.empty((max_steps + 1, n, 3), dtype=torch.float64, device=seeds.device),
+                   torch.empty(n, dtype=torch.int32, device=seeds.device),
+                   torch.empty(n, dtype=torch.int32, device=seeds.device))
+        pts, cnt, st = out
+        if tuple(pts.shape) != (max_steps + 1, n, 3) or tuple(cnt.shape) != (n,) or tuple(st.shape) != (n,):
+            raise ValueError("output shapes must be (max_steps + 1, nlines, 3), (nlines,), (nlines,)")
+        with torch.cuda.device(self.device):
+            check(_lib.lib().mhs_trace_field_lines(self.h, _ptr(Bx), _ptr(By), _ptr(Bz), _ptr(seeds), n,
+                                                   float(ds), int(max_steps), float(bmin), _ptr(pts), _ptr(cnt),
+                                                   _ptr(st), _stream(self.device)))
+        return pts, cnt, st
+
     # ---- measurement -----------------------------------------------------------
     def profile(self, enable=True, classes=None):
         """Time launches of the given classes (names from PROF_NAMES; all by
@@ -306,3 +332,8 @@ def solve(plan: Plan, bz0, model, precision=PREC_FP64, rtol=1e-10, rtol2d=None, 
 def diagnostics(plan: Plan, model, Bx, By, Bz, p, rho, out=None):
     """Residuals of equations (1)-(3) on the plan's grid (see Plan.diagnostics)."""
     return plan.diagnostics(model, Bx, By, Bz, p, rho, out)
+
+
+def trace_field_lines(plan: Plan, Bx, By, Bz, seeds, ds, max_steps, bmin=0.0, out=None):
+    """Field lines on the plan's grid (see Plan.trace_field_lines)."""
+    return plan.trace_field_lines(Bx, By, Bz, seeds, ds, max_steps, bmin, out)

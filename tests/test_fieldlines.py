@@ -122,8 +122,138 @@ def test_linear_null_spine_and_fan():
     assert np.abs(d[:, 0] * 0.1 - d[:, 1] * 0.2).max() < 1e-13
 
 
+def test_exact_null_at_a_node_ends_the_line():
+    """|B| = 0 exactly (a null on a node, bmin = 0): the line that reaches
+    it ends there with status NULL, and no stage produces NaN."""
+    n = 9
+    shape, lengths = (n, n, n), (1.0, 1.0, 1.0)
+    z, y, x = grid_coords(shape, lengths)
+    B = (np.zeros(shape), np.zeros(shape), -(z - 0.5))
+    pts, count, status = ofl.trace(*B, np.array([[0.5, 0.5, 0.75], [0.5, 0.5, 0.5]]), 0.125, 10, 0.0, lengths)
+    assert list(status) == [ofl.NULL, ofl.NULL]
+    assert count[1] == 1 and np.all(np.isfinite(pts))
+    assert abs(pts[count[0] - 1, 0, 2] - 0.5) < 0.126
+
+
 def test_seed_outside_and_zero_steps():
     B, lengths = helix_case(5)
     pts, count, status = ofl.trace(*B, np.array([[1.2, 0.5, 0.5], [0.5, 0.5, 0.5]]), 0.1, 0, 0.0, lengths)
     assert list(count) == [1, 1] and list(status) == [ofl.EXIT, ofl.MAXSTEPS]
     assert np.array_equal(pts[0], [[1.2, 0.5, 0.5], [0.5, 0.5, 0.5]])
+
+
+# --------------------------------------------------------------------- GPU
+torch = pytest.importorskip("torch")
+
+
+def smooth_field(shape, lengths, seed):
+    """A smooth random field (a few sine modes per component) with nulls
+    near some points."""
+    z, y, x = grid_coords(shape, lengths)
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(3):
+        F = np.zeros(shape)
+        for _ in range(4):
+            a, kx, ky, kz, ph = rng.normal(), *rng.integers(1, 4, 3), rng.uniform(0, 6.3)
+            F += a * np.sin(kx * np.pi * x / lengths[0] + ph) * np.cos(ky * np.pi * y / lengths[1]) \
+                * np.cos(kz * np.pi * z / lengths[2] + 0.5 * ph)
+        out.append(F)
+    return out
+
+
+def gpu_trace(grid, B, seeds, ds, max_steps, bmin):
+    from paper_1307_6720_amd.solver import Plan, trace_field_lines
+
+    plan = Plan(grid, device="cuda:0")
+    dev = [torch.from_numpy(np.ascontiguousarray(F)).to("cuda:0") for F in B]
+    s = torch.from_numpy(np.ascontiguousarray(seeds, dtype=np.float64)).to("cuda:0")
+    pts, cnt, st = trace_field_lines(plan, *dev, s, ds, max_steps, bmin)
+    torch.cuda.synchronize()
+    plan.close()
+    return pts.cpu().numpy(), cnt.cpu().numpy(), st.cpu().numpy()
+
+
+def compare_lines(got, want):
+    pts, cnt, st = got
+    wpts, wcnt, wst = want
+    assert np.array_equal(cnt, wcnt) and np.array_equal(st, wst)
+    worst = 0.0
+    for l in range(len(cnt)):
+        worst = max(worst, np.abs(pts[: cnt[l], l] - wpts[: cnt[l], l]).max())
+    return worst
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("shape,lengths,ds,bmin", [((33, 65, 129), (1.0, 1.3, 0.8), 0.011, 0.05),
+                                                   ((17, 17, 17), (1.0, 1.0, 1.0), -0.03, 0.0),
+                                                   ((65, 33, 17), (0.5, 2.0, 1.0), 0.02, 0.2)])
+def test_gpu_field_lines_match_oracle(shape, lengths, ds, bmin):
+    """Random smooth fields, 3000 seeds (a few outside the box): every line's
+    point count and end status equal the oracle's exactly, and its points
+    agree to rounding (the kernel evaluates the oracle's expressions in the
+    same order)."""
+    nz, ny, nx = shape
+    B = smooth_field(shape, lengths, sum(shape))
+    rng = np.random.default_rng(7)
+    seeds = rng.uniform(-0.02, 1.02, size=(3000, 3)) * np.array(lengths)
+    print(f"[lines] shape={shape} ds={ds} bmin={bmin}", flush=True)
+    got = gpu_trace(synth.make_grid(nx, ny, nz, *lengths), B, seeds, ds, 150, bmin)
+    want = ofl.trace(*B, seeds, ds, 150, bmin, lengths)
+    assert (want[2] == ofl.EXIT).any() and (want[1] > 10).any()
+    assert compare_lines(got, want) <= 1e-13
+
+
+@pytest.mark.gpu
+def test_gpu_field_lines_of_a_solved_equilibrium():
+    """Lines of the 129^3 workload's recovered B from seeds on the base:
+    equal to the oracle's lines on the same B; ds > 0 and ds < 0 from the
+    same seeds are the lines of B and of -B."""
+    from paper_1307_6720_amd import PREC_MIXED
+    from paper_1307_6720_amd.solver import Plan, solve, trace_field_lines
+
+    w = synth.workload("mhs-129")
+    g = w.grid
+    plan = Plan(g, device="cuda:0")
+    print("[lines] solved 129^3", flush=True)
+    res = solve(plan, torch.from_numpy(w.bz0).to("cuda:0"), w.model, precision=PREC_MIXED, rtol=1e-10)
+    B = (res.Bx, res.By, res.Bz)
+    rng = np.random.default_rng(11)
+    seeds = np.concatenate([rng.uniform(0.05, 0.95, size=(400, 2)), np.full((400, 1), 0.0)], axis=1)
+    sd = torch.from_numpy(seeds).to("cuda:0")
+    fwd = [t.cpu().numpy() for t in trace_field_lines(plan, *B, sd, 0.004, 400, 1e-6)]
+    neg = tuple(-t for t in B)
+    back = [t.cpu().numpy() for t in trace_field_lines(plan, *neg, sd, 0.004, 400, 1e-6)]
+    rev = [t.cpu().numpy() for t in trace_field_lines(plan, *B, sd, -0.004, 400, 1e-6)]
+    Bh = [t.cpu().numpy() for t in B]
+    plan.close()
+    assert compare_lines(fwd, ofl.trace(*Bh, seeds, 0.004, 400, 1e-6, (g.lx, g.ly, g.lz))) <= 1e-13
+    # -B with ds is B with -ds, operation for operation
+    assert compare_lines(back, rev) == 0.0
+    # lines from the base either return to it, leave through a side or the top,
+    # or run to the cap; some of each kind the magnetogram's bipoles make
+    assert (fwd[2] == ofl.EXIT).sum() > 0
+
+
+@pytest.mark.gpu
+def test_gpu_field_lines_edge_cases():
+    from paper_1307_6720_amd import MHSError
+    from paper_1307_6720_amd.solver import Plan, trace_field_lines
+
+    shape, lengths = (9, 9, 9), (1.0, 1.0, 1.0)
+    B = [torch.from_numpy(F).to("cuda:0") for F in helix_case(9)[0]]
+    plan = Plan(synth.make_grid(9, 9, 9), device="cuda:0")
+    print("[lines] edge cases", flush=True)
+    empty = torch.zeros((0, 3), dtype=torch.float64, device="cuda:0")
+    pts, cnt, st = trace_field_lines(plan, *B, empty, 0.1, 5)
+    assert pts.shape == (6, 0, 3) and cnt.numel() == 0
+    seeds = torch.tensor([[0.5, 0.5, 0.5], [-1.0, 0.5, 0.5]], dtype=torch.float64, device="cuda:0")
+    pts, cnt, st = trace_field_lines(plan, *B, seeds, 0.1, 0)
+    assert cnt.tolist() == [1, 1] and st.tolist() == [ofl.MAXSTEPS, ofl.EXIT]
+    for bad in (dict(ds=0.0), dict(ds=float("nan")), dict(bmin=-1.0)):
+        kw = dict(ds=0.1, bmin=0.0)
+        kw.update(bad)
+        with pytest.raises(MHSError):
+            trace_field_lines(plan, *B, seeds, kw["ds"], 3, kw["bmin"])
+    torch.cuda.synchronize()
+    plan.close()
