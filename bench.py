@@ -718,6 +718,31 @@ def main():
                    "force_residual_over_lorentz": float(D[3].max() / lor.max())}
     del D, lor
 
+    # field lines of the same equilibrium from 16384 seeds on the base
+    # (RK4, ds = half a node spacing, at most 1024 steps): one thread per line
+    gx = torch.linspace(0.02, 0.98, 128, dtype=torch.float64, device=dev)
+    seeds = torch.stack([gx.repeat(128) * grid.lx, gx.repeat_interleave(128) * grid.ly,
+                         torch.zeros(128 * 128, dtype=torch.float64, device=dev)], dim=1).contiguous()
+    ds = 0.5 * grid.lx / (grid.nx - 1)
+    L_out = (torch.empty((1025, seeds.shape[0], 3), dtype=torch.float64, device=dev),
+             torch.empty(seeds.shape[0], dtype=torch.int32, device=dev),
+             torch.empty(seeds.shape[0], dtype=torch.int32, device=dev))
+    plan.trace_field_lines(*F[:3], seeds, ds, 1024, 1e-8, out=L_out)
+    plan.profile(True, ["trace"])
+    plan.profile_read(reset=True)
+    for _ in range(3):
+        plan.trace_field_lines(*F[:3], seeds, ds, 1024, 1e-8, out=L_out)
+    torch.cuda.synchronize()
+    tms, tn, _ = plan.profile_read(reset=True)["trace"]
+    plan.profile(False)
+    cnt, st = L_out[1].cpu(), L_out[2].cpu()
+    steps = int((cnt - 1).sum())
+    field_lines = {"kernel": "k_trace", "lines": int(seeds.shape[0]), "ds": ds, "max_steps": 1024,
+                   "steps_taken": steps, "avg_ms": tms / tn, "steps_per_s": steps / (tms / tn * 1e-3),
+                   "ended": {"left_box": int((st == 1).sum()), "null": int((st == 2).sum()),
+                             "step_cap": int((st == 0).sum())}}
+    del L_out
+
     serving = None
     if a.serve_requests > 0:
         serving = serve_leg(a, torch, dev)
@@ -768,6 +793,7 @@ def main():
         "roofline": roofline,
         "roofline_single_request": roof_single,
         "diagnostics": diagnostics,
+        "field_lines": field_lines,
         "serving": serving,
         "large_case": large,
         "context": {"paper_speedup": "x30 GPU vs serial (x32.4 at 128^3, x29.6 at 256^3); hardware unstated"},
