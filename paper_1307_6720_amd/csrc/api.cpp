@@ -45,6 +45,16 @@ constexpr size_t kStagingBytes = 1 << 20;
 #define MHS_TARGET_GROUPS 1024
 #endif
 constexpr int kTargetGroups = MHS_TARGET_GROUPS;
+#ifndef MHS_COARSE_TARGET_GROUPS
+#define MHS_COARSE_TARGET_GROUPS 1024
+#endif
+constexpr int kCoarseTargetGroups = MHS_COARSE_TARGET_GROUPS;
+// The same per request for levels >= 1 in merged launches of the batch
+// (many requests per launch fill the chip with fewer groups each).
+#ifndef MHS_BATCH_COARSE_TARGET_GROUPS
+#define MHS_BATCH_COARSE_TARGET_GROUPS 128
+#endif
+constexpr int kBatchCoarseTargetGroups = MHS_BATCH_COARSE_TARGET_GROUPS;
 constexpr int kFieldsTargetGroups = 2048;
 // Largest coarsest grid (unknowns) a model may cut the 3D hierarchy to.
 constexpr int kMaxCutCoarse = 512;
@@ -164,11 +174,15 @@ int build_geometry(Hierarchy &h, const int n0[3], const double len[3], bool plan
             lv.st[1] = ceil_div(lv.n[1] - 2, kTY2);
             lv.st[2] = 1;
             lv.kz = 1;
+            lv.stz_b = 1;
+            lv.kz_b = 1;
         } else {
             lv.st[0] = ceil_div(lv.n[0] - 2, kTX);
             lv.st[1] = ceil_div(lv.n[1] - 2, kTY);
-            lv.kz = chunk(lv.n[2] - 2, lv.st[0] * lv.st[1], kKZ);
+            lv.kz = chunk(lv.n[2] - 2, lv.st[0] * lv.st[1], kKZ, l == 0 ? kTargetGroups : kCoarseTargetGroups);
             lv.st[2] = ceil_div(lv.n[2] - 2, lv.kz);
+            lv.kz_b = l == 0 ? lv.kz : chunk(lv.n[2] - 2, lv.st[0] * lv.st[1], kKZ, kBatchCoarseTargetGroups);
+            lv.stz_b = ceil_div(lv.n[2] - 2, lv.kz_b);
         }
         if (l + 1 < L) {
             const Level &c2 = h.lv[l + 1];
@@ -177,9 +191,13 @@ int build_geometry(Hierarchy &h, const int n0[3], const double len[3], bool plan
             if (planar) {
                 lv.rt[2] = 1;
                 lv.kc = 1;
+                lv.rtz_b = 1;
+                lv.kc_b = 1;
             } else {
-                lv.kc = chunk(c2.n[2] - 2, lv.rt[0] * lv.rt[1], kKC);
+                lv.kc = chunk(c2.n[2] - 2, lv.rt[0] * lv.rt[1], kKC, l == 0 ? kTargetGroups : kCoarseTargetGroups);
                 lv.rt[2] = ceil_div(c2.n[2] - 2, lv.kc);
+                lv.kc_b = l == 0 ? lv.kc : chunk(c2.n[2] - 2, lv.rt[0] * lv.rt[1], kKC, kBatchCoarseTargetGroups);
+                lv.rtz_b = ceil_div(c2.n[2] - 2, lv.kc_b);
             }
         }
     }
@@ -577,10 +595,13 @@ void add_sweep(Program &pg, Staging &st, const Hierarchy &h, int l, int path, co
     it.ec = ec;
     it.state = state;
     it.partials = partials;
+    // levels >= 1 have no reductions: their z-chunking does not change a
+    // result, so merged launches may use the batched chunking
+    const bool bt = h.batched && l > 0;
     it.ntx = lv.st[0];
     it.nty = lv.st[1];
-    it.ntz = lv.st[2];
-    it.kz = lv.kz;
+    it.ntz = bt ? lv.stz_b : lv.st[2];
+    it.kz = bt ? lv.kz_b : lv.kz;
     it.tile_base = 0;
     const LevelItem *d = st.put(it);
     if (!d) {
@@ -593,7 +614,7 @@ void add_sweep(Program &pg, Staging &st, const Hierarchy &h, int l, int path, co
     L.dbl = path == kF64;
     L.items = d;
     L.nitems = 1;
-    L.ntiles = lv.sweep_tiles();
+    L.ntiles = it.ntx * it.nty * it.ntz;
     L.prof = (l == 0 && !h.planar) ? MHS_PROF_SMOOTH_L0 : MHS_PROF_COARSE;
     {
         const double es = path == kF64 ? 8.0 : 4.0;
@@ -616,10 +637,11 @@ void add_restrict(Program &pg, Staging &st, const Hierarchy &h, int l, int path,
     it.f = f;
     it.u_out = fc;
     it.state = state;
+    const bool bt = h.batched && l > 0;
     it.ntx = lv.rt[0];
     it.nty = lv.rt[1];
-    it.ntz = lv.rt[2];
-    it.kz = lv.kc;
+    it.ntz = bt ? lv.rtz_b : lv.rt[2];
+    it.kz = bt ? lv.kc_b : lv.kc;
     const LevelItem *d = st.put(it);
     if (!d) {
         pg.ok = false;
@@ -630,7 +652,7 @@ void add_restrict(Program &pg, Staging &st, const Hierarchy &h, int l, int path,
     L.flags = (f ? kRestrictHasF : 0) | (lv.keepz ? kRestrictKeepZ : 0);
     L.dbl = path == kF64;
     L.items = d;
-    L.ntiles = lv.restrict_tiles();
+    L.ntiles = it.ntx * it.nty * it.ntz;
     L.prof = (l == 0 && !h.planar) ? MHS_PROF_RESTRICT_L0 : MHS_PROF_COARSE;
     {
         const double es = path == kF64 ? 8.0 : 4.0;

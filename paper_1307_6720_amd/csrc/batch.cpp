@@ -180,9 +180,18 @@ void reset_recorder(mhs_batch *b)
 }
 
 // Append the launches of slot `i` for its current phase to `out`.
+// Records a plan's launches with the batched z-chunking of its 3D levels
+// >= 1 for as long as it lives.
+struct BatchedTiling {
+    Hierarchy &h;
+    explicit BatchedTiling(Hierarchy &hh) : h(hh) { h.batched = true; }
+    ~BatchedTiling() { h.batched = false; }
+};
+
 bool build_slot(const Slot &S, int i, SolveState *state, Staging &R, std::vector<Rec> &out)
 {
     mhs_plan *p = S.plan;
+    BatchedTiling tiling(p->h3);
     const mhs_opts &o = S.opts;
     if (S.phase == kBoundary) {
         Hierarchy &h = p->h2;

@@ -27,6 +27,10 @@ struct Level {
     int rt[3] = {0, 0, 0}; // restriction tiles per axis (onto level+1)
     int kz = 1;            // smoother planes per workgroup
     int kc = 1;            // restriction coarse planes per workgroup
+    // z-chunking of levels >= 1 in batched (merged) launches: fewer, longer
+    // z-marches, since the merged launch has many requests' tiles
+    int kz_b = 1, stz_b = 1;
+    int kc_b = 1, rtz_b = 1;
     int zs = 0;            // xi of plane k is xi[k << zs] of the finest grid
     bool keepz = false;    // the step to level+1 halves x and y only
     int sweep_tiles() const { return st[0] * st[1] * st[2]; }
@@ -41,6 +45,7 @@ struct Hierarchy {
     int mcap = 0;           // largest coarsest-grid size the inverse buffer holds
     Level lv[kMaxLevels];
     int lds_bytes = 0;      // bottom solver LDS footprint
+    bool batched = false;   // builders record launches for merging (z-chunking kz_b, kc_b)
     double *minv = nullptr; // device m x m
     int m = 0;              // coarsest unknowns
     double *partials = nullptr;
