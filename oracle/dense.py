@@ -74,11 +74,22 @@ def operator2(shape, lx=1.0, ly=1.0):
     return A
 
 
-def solve2(bz0, lx=1.0, ly=1.0):
-    """Solve the five-point form of (11), P0 = 0 on the edges."""
+def solve2(bz0, lx=1.0, ly=1.0, edges=None):
+    """Solve the five-point form of (11) with P0 = 0 on the edges, or with
+    the edge values of the array `edges` (same shape) as Dirichlet data."""
     bz0 = np.asarray(bz0, dtype=np.float64)
+    ny, nx = bz0.shape
+    dx, dy = lx / (nx - 1), ly / (ny - 1)
     A = operator2(bz0.shape, lx, ly)
-    x = np.linalg.solve(A, -bz0[1:-1, 1:-1].reshape(-1))
     P0 = np.zeros_like(bz0)
-    P0[1:-1, 1:-1] = x.reshape(bz0.shape[0] - 2, bz0.shape[1] - 2)
+    rhs = -bz0[1:-1, 1:-1].copy()
+    if edges is not None:
+        e = np.asarray(edges, dtype=np.float64)
+        P0[0], P0[-1], P0[:, 0], P0[:, -1] = e[0], e[-1], e[:, 0], e[:, -1]
+        rhs[:, 0] -= P0[1:-1, 0] / dx**2
+        rhs[:, -1] -= P0[1:-1, -1] / dx**2
+        rhs[0, :] -= P0[0, 1:-1] / dy**2
+        rhs[-1, :] -= P0[-1, 1:-1] / dy**2
+    x = np.linalg.solve(A, rhs.reshape(-1))
+    P0[1:-1, 1:-1] = x.reshape(ny - 2, nx - 2)
     return P0

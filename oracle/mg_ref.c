@@ -631,10 +631,14 @@ static int vcycle2(lev2 *lv, int l, int L, int nu1, int nu2)
 }
 
 /* Multigrid solve of equation (11) on the lower boundary: P0 (nx*ny, x
- * fastest) receives the solution; its edges are set to zero and its
- * interior is the initial guess.  Bz0 on edge nodes is not read. */
-int ref_mg2(const int *n, const double *len, const double *bz0, double *P0, double rtol,
-            int max_cycles, int nu1, int nu2, int *cycles_out, double *relres_out, double *hist)
+ * fastest) receives the solution; its interior is the initial guess.  Its
+ * edges are set to zero (the B = 0 side walls of Section 2.2), or, with
+ * keep_edges, kept as the Dirichlet data (the summary of Section 5 leaves
+ * P on the side boundaries to the problem).  Bz0 on edge nodes is not
+ * read. */
+int ref_mg2_edges(const int *n, const double *len, const double *bz0, double *P0, double rtol,
+                  int max_cycles, int nu1, int nu2, int *cycles_out, double *relres_out, double *hist,
+                  int keep_edges)
 {
     int L = ref_nlevels2(n[0], n[1]);
     if (L < 1) return REF_BAD_GRID;
@@ -664,7 +668,7 @@ int ref_mg2(const int *n, const double *len, const double *bz0, double *P0, doub
             for (int i = 0; i < nx; i++) {
                 int edge = (i == 0 || i == nx - 1 || j == 0 || j == ny - 1);
                 AT2(lv[0].f, i, j) = edge ? 0.0 : -AT2(bz0, i, j);
-                if (edge) AT2(P0, i, j) = 0.0;
+                if (edge && !keep_edges) AT2(P0, i, j) = 0.0;
             }
         ref_residual2(lv[0].n, lv[0].h, P0, lv[0].f, lv[0].r);
         r0 = ref_norm2_interior(lv[0].n, lv[0].r);
@@ -691,6 +695,12 @@ int ref_mg2(const int *n, const double *len, const double *bz0, double *P0, doub
     }
     free(lv);
     return st;
+}
+
+int ref_mg2(const int *n, const double *len, const double *bz0, double *P0, double rtol,
+            int max_cycles, int nu1, int nu2, int *cycles_out, double *relres_out, double *hist)
+{
+    return ref_mg2_edges(n, len, bz0, P0, rtol, max_cycles, nu1, nu2, cycles_out, relres_out, hist, 0);
 }
 
 /* One step of the paper's lower-boundary relaxation kernel (Section 4):

@@ -52,6 +52,8 @@ def _load():
         "ref_direct2": (C.c_int, [_ip, _dp, _dp, vp]),
         "ref_mg2": (C.c_int, [_ip, _dp, _dp, _dp, C.c_double, C.c_int, C.c_int, C.c_int,
                               C.POINTER(C.c_int), C.POINTER(C.c_double), vp]),
+        "ref_mg2_edges": (C.c_int, [_ip, _dp, _dp, _dp, C.c_double, C.c_int, C.c_int, C.c_int,
+                                    C.POINTER(C.c_int), C.POINTER(C.c_double), vp, C.c_int]),
         "ref_jacobi2": (None, [_ip, _dp, _dp, _dp, _dp]),
         "ref_solve": (C.c_int, [_ip, _dp, _dp, _dp, C.c_double, _dp, C.c_double, C.c_double,
                                 C.c_int, C.c_int, C.c_int, _dp]),
@@ -232,15 +234,16 @@ def direct2(u, f, lengths=(1.0, 1.0)):
 
 
 def mg2(bz0, rtol=1e-10, max_cycles=50, nu1=2, nu2=2, lengths=(1.0, 1.0), P0=None,
-        history=False):
-    """Multigrid solve of (11).  Returns (P0, status, cycles, relres[, hist])."""
+        history=False, keep_edges=False):
+    """Multigrid solve of (11).  Returns (P0, status, cycles, relres[, hist]).
+    With keep_edges, P0's edge values are the Dirichlet data (else zero)."""
     bz0 = _f64(bz0)
     P0 = np.zeros_like(bz0) if P0 is None else _f64(P0).copy()
     cyc = C.c_int(0)
     rel = C.c_double(0.0)
     hist = np.zeros(max_cycles + 1)
-    st = _load().ref_mg2(_n2(bz0.shape), _f64(lengths), bz0, P0, rtol, max_cycles, nu1, nu2,
-                         C.byref(cyc), C.byref(rel), _ptr(hist))
+    st = _load().ref_mg2_edges(_n2(bz0.shape), _f64(lengths), bz0, P0, rtol, max_cycles, nu1, nu2,
+                               C.byref(cyc), C.byref(rel), _ptr(hist), int(keep_edges))
     out = (P0, st, cyc.value, rel.value)
     return out + (hist[: cyc.value + 1],) if history else out
 

@@ -79,6 +79,56 @@ def test_boundary_dense_bruteforce(nx, ny):
     assert rel(P0, want) < 1e-11
 
 
+def test_boundary_given_edges():
+    """P given on the edges of the base (the summary's 'P defined on the side
+    boundaries'): bilinear data with Bz0 = 0 is reproduced exactly (every
+    second difference of a bilinear function vanishes), and random edges
+    with a random magnetogram match the dense solve."""
+    ny, nx = 17, 33
+    y, x = np.meshgrid(np.linspace(0, 0.7, ny), np.linspace(0, 1.0, nx), indexing="ij")
+    u = 0.3 + 1.2 * x - 0.7 * y + 2.1 * x * y
+    bc = u.copy()
+    bc[1:-1, 1:-1] = 0.0
+    got, st, _, _ = ref.mg2(np.zeros_like(u), rtol=1e-14, lengths=(1.0, 0.7), P0=bc, keep_edges=True)
+    assert st == ref.OK and rel(got, u) < 1e-12
+    assert rel(dense.solve2(np.zeros_like(u), 1.0, 0.7, edges=u), u) < 1e-13
+    rng = np.random.default_rng(6)
+    bz = rng.normal(size=(9, 17))
+    e = rng.normal(size=(9, 17))
+    want = dense.solve2(bz, 1.0, 1.0, edges=e)
+    e[1:-1, 1:-1] = 0.0
+    got, st, _, _ = ref.mg2(bz, rtol=1e-14, P0=e, keep_edges=True)
+    assert st == ref.OK and rel(got, want) < 1e-11
+    # the default still zeroes the edges
+    got0, _, _, _ = ref.mg2(bz, rtol=1e-14, P0=e)
+    assert rel(got0, dense.solve2(bz)) < 1e-11
+
+
+def test_interior_given_faces():
+    """P given on every face ('define the other boundary conditions'): with
+    alpha = 0 a trilinear P satisfies (8) exactly for any xi (its second
+    differences vanish), so the solve returns it; random faces match the
+    dense solve."""
+    shape, lengths = (17, 9, 33), (1.0, 0.8, 1.3)
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.linspace(0, lengths[2], nz), np.linspace(0, lengths[1], ny),
+                          np.linspace(0, lengths[0], nx), indexing="ij")
+    u = 1.0 + x - 2 * y + 0.5 * z + x * y - y * z + 3 * x * z + x * y * z
+    xi = 0.9 * np.exp(-np.linspace(0, 1, nz) / 0.2)
+    bc = u.copy()
+    bc[1:-1, 1:-1, 1:-1] = 0.0
+    got, st, _, _ = ref.mg3(bc, xi, 0.0, rtol=1e-14, lengths=lengths)
+    assert st == ref.OK and rel(got, u) < 1e-11
+    rng = np.random.default_rng(12)
+    shape = (9, 9, 17)
+    bc = rng.normal(size=shape)
+    bc[1:-1, 1:-1, 1:-1] = 0.0
+    xi = rng.uniform(0, 0.8, 9)
+    want = dense.solve3(bc, None, xi, 0.6)
+    got, st, _, _ = ref.mg3(bc, xi, 0.6, rtol=1e-14)
+    assert st == ref.OK and rel(got, want) < 1e-11
+
+
 def test_boundary_paper_jacobi_fixed_point():
     """Iterating the paper's printed lower-boundary Jacobi update (Section 4)
     reaches the oracle's solution of (11): this pins the sign convention of
