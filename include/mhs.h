@@ -85,8 +85,20 @@ typedef struct mhs_opts {
     int32_t inner_cycles; /* FP32 V-cycles per refinement step (mixed)      */
     int32_t warm_start;   /* 1: use P's interior as the initial guess       */
     int32_t check_every;  /* cycles launched between host status reads; 0 = adaptive */
-    int32_t reserved;
+    int32_t faces;        /* MHS_FACES_ZERO or MHS_FACES_GIVEN (below)      */
 } mhs_opts;
+
+/* Dirichlet data on the faces other than the base.  Section 2.2 takes
+ * B = 0 there, i.e. P = 0 on the side and top faces and on the edges of the
+ * base (MHS_FACES_ZERO, the default); its procedure (summarised in Section
+ * 5) leaves the other boundary conditions to the problem.  With
+ * MHS_FACES_GIVEN the values already in P on those faces (the edges of
+ * plane 0 for mhs_solve_boundary; the side and top faces for
+ * mhs_solve_interior) are the Dirichlet data and are not modified.
+ * mhs_fields still applies the B = 0 reading on the side and top faces, so
+ * with given faces only its interior nodes are the fields of P. */
+#define MHS_FACES_ZERO 0
+#define MHS_FACES_GIVEN 1
 
 typedef struct mhs_info {
     int32_t status;       /* MHS_OK or an MHS_ERR_* code                    */
@@ -158,7 +170,8 @@ int mhs_plan_bottom_level(const mhs_plan *plan, int32_t space, int32_t *level);
 /* Step 2 of the procedure of Section 2.2: multigrid solve of equation (11).
  * d_bz0: device, nx*ny doubles (edge values are not read).  d_P: device,
  * nx*ny*nz doubles; plane k = 0 (its first nx*ny doubles) receives P0 with
- * zero edges; the other planes are not touched.  Initial guess 0 unless
+ * zero edges (or keeps the given edges, opts->faces); the other planes are
+ * not touched.  Initial guess 0 unless
  * opts->warm_start.  Always FP64.  On MHS_ERR_NO_CONVERGENCE plane 0 holds
  * the last iterate and *info is filled. */
 int mhs_solve_boundary(mhs_plan *plan, const double *d_bz0, double *d_P, const mhs_opts *opts,
@@ -166,7 +179,8 @@ int mhs_solve_boundary(mhs_plan *plan, const double *d_bz0, double *d_P, const m
 
 /* Step 3 of the procedure: multigrid solve of equation (8) in place.  Plane
  * k = 0 of d_P is the Dirichlet data from mhs_solve_boundary; the side and
- * top faces are set to 0; the interior starts from 0 (step 1) unless
+ * top faces are set to 0 (or kept as given, opts->faces); the interior
+ * starts from 0 (step 1) unless
  * opts->warm_start.  opts->precision selects plain FP64 V-cycles or FP32
  * V-cycles inside FP64 iterative refinement (fine residual, update and the
  * coarsest solve in FP64).  Validates xi < 1 on interior planes

@@ -34,6 +34,7 @@ PREC_MIXED = 2
 PROF_SMOOTH_L0, PROF_REFINE, PROF_RESTRICT_L0, PROF_FIELDS, PROF_BOTTOM, PROF_COARSE = range(6)
 PROF_NAMES = ("smooth_l0", "refine", "restrict_l0", "fields", "bottom", "coarse", "diag", "trace")
 LINE_MAX_STEPS, LINE_EXIT, LINE_NULL = 0, 1, 2
+FACES_ZERO, FACES_GIVEN = 0, 1
 
 
 class MHSError(RuntimeError):
@@ -56,7 +57,7 @@ class Model(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("max_cycles", C.c_int32), ("rtol", C.c_double),
                 ("nu1", C.c_int32), ("nu2", C.c_int32), ("inner_cycles", C.c_int32),
-                ("warm_start", C.c_int32), ("check_every", C.c_int32), ("reserved", C.c_int32)]
+                ("warm_start", C.c_int32), ("check_every", C.c_int32), ("faces", C.c_int32)]
 
 
 class Info(C.Structure):

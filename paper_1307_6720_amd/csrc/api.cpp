@@ -562,6 +562,8 @@ int validate_opts(const mhs_opts *o)
     if (!(o->rtol >= 0.0) || !std::isfinite(o->rtol)) return fail(MHS_ERR_INVALID_ARG, "rtol must be >= 0");
     if (o->inner_cycles < 1 || o->inner_cycles > 16) return fail(MHS_ERR_INVALID_ARG, "inner_cycles must be in 1..16");
     if (o->check_every < 0) return fail(MHS_ERR_INVALID_ARG, "check_every must be >= 0");
+    if (o->faces != MHS_FACES_ZERO && o->faces != MHS_FACES_GIVEN)
+        return fail(MHS_ERR_INVALID_ARG, "faces must be MHS_FACES_ZERO or MHS_FACES_GIVEN");
     return MHS_OK;
 }
 
@@ -1055,6 +1057,7 @@ void mhs_default_opts(mhs_opts *o)
     o->inner_cycles = 1;
     o->warm_start = 0;
     o->check_every = 0;
+    o->faces = MHS_FACES_ZERO;
 }
 
 int32_t mhs_version(void) { return 10000; }
@@ -1193,6 +1196,7 @@ int mhs_solve_boundary(mhs_plan *p, const double *d_bz0, double *d_P, const mhs_
     pi.ny = p->grid.ny;
     pi.nz = 1;
     pi.warm = o->warm_start;
+    pi.faces = o->faces;
     pi.n = (int64_t)p->grid.nx * p->grid.ny;
     pi.base = 0;
     const PrepItem *d_prep = p->stage.put(pi);
@@ -1256,6 +1260,7 @@ int mhs_solve_interior(mhs_plan *p, const mhs_model *model, double *d_P, const m
     pi.ny = p->grid.ny;
     pi.nz = p->grid.nz;
     pi.warm = o->warm_start;
+    pi.faces = o->faces;
     pi.n = N;
     const PrepItem *d_prep = p->stage.put(pi);
     SolveState fin{};

@@ -205,6 +205,7 @@ bool build_slot(const Slot &S, int i, SolveState *state, Staging &R, std::vector
             pi.ny = p->grid.ny;
             pi.nz = 1;
             pi.warm = o.warm_start;
+            pi.faces = o.faces;
             pi.n = (int64_t)p->grid.nx * p->grid.ny;
             const PrepItem *d = R.put(pi);
             if (!d) return false;
@@ -243,6 +244,7 @@ bool build_slot(const Slot &S, int i, SolveState *state, Staging &R, std::vector
             pi.ny = p->grid.ny;
             pi.nz = p->grid.nz;
             pi.warm = o.warm_start;
+            pi.faces = o.faces;
             pi.n = N;
             const PrepItem *d = R.put(pi);
             if (!d) return false;

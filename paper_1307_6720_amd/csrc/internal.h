@@ -170,6 +170,8 @@ struct PrepItem {
     double *f2;         // 2D: right-hand side -bz0
     int32_t nx, ny, nz;
     int32_t warm;
+    int32_t faces;      // 1: keep P's faces (2D: edges) as Dirichlet data
+    int32_t pad;
     int64_t n;          // points covered
     int64_t base;       // first global thread of this item
 };

@@ -1930,11 +1930,11 @@ __global__ __launch_bounds__(256) void k_prep3(const PrepItem *__restrict__ item
     const int j = (int)(r - kk * (uint32_t)ny), k = (int)kk;
     const bool side = (i == 0 || i == nx - 1 || j == 0 || j == ny - 1);
     if (k == 0) {
-        if (side) it.P[e] = 0.0;
-        if (it.twin) it.twin[e] = side ? 0.0 : it.P[e];
+        if (side && !it.faces) it.P[e] = 0.0;
+        if (it.twin) it.twin[e] = (side && !it.faces) ? 0.0 : it.P[e];
     } else if (side || k == nz - 1) {
-        it.P[e] = 0.0;
-        if (it.twin) it.twin[e] = 0.0;
+        if (!it.faces) it.P[e] = 0.0;
+        if (it.twin) it.twin[e] = it.faces ? it.P[e] : 0.0;
     } else if (!it.warm) {
         it.P[e] = 0.0;
     }
@@ -1952,8 +1952,8 @@ __global__ __launch_bounds__(256) void k_prep2(const PrepItem *__restrict__ item
     const int i = (int)(e % nx), j = (int)(e / nx);
     const bool edge = (i == 0 || i == nx - 1 || j == 0 || j == ny - 1);
     it.f2[e] = edge ? 0.0 : -it.bz0[e];
-    if (edge || !it.warm) it.P[e] = 0.0;
-    if (edge && it.twin) it.twin[e] = 0.0;
+    if (edge ? !it.faces : !it.warm) it.P[e] = 0.0;
+    if (edge && it.twin) it.twin[e] = it.faces ? it.P[e] : 0.0;
 }
 
 // dst = src; skipped once `skip` (if given) reports a finished solve.

@@ -25,7 +25,7 @@ def _ptr(t):
 
 
 def make_opts(precision=PREC_FP64, rtol=1e-10, max_cycles=100, nu1=2, nu2=2, inner_cycles=1,
-              warm_start=False, check_every=0):
+              warm_start=False, check_every=0, faces_given=False):
     o = _lib.Opts()
     _lib.lib().mhs_default_opts(C.byref(o))
     o.precision = precision
@@ -36,6 +36,7 @@ def make_opts(precision=PREC_FP64, rtol=1e-10, max_cycles=100, nu1=2, nu2=2, inn
     o.inner_cycles = inner_cycles
     o.warm_start = 1 if warm_start else 0
     o.check_every = check_every
+    o.faces = _lib.FACES_GIVEN if faces_given else _lib.FACES_ZERO
     return o
 
 

@@ -237,3 +237,47 @@ def test_release_before_first_tick_keeps_plan_consistent(alone_results):
     for a, w in zip((res.P, res.Bx, res.By, res.Bz, res.p, res.rho), want):
         assert torch.equal(a, w)
     plan.close()
+
+
+def test_batch_with_given_faces_equals_single_solve():
+    """A request whose faces are given (opts.faces = MHS_FACES_GIVEN) in a
+    batch beside a default request: the batch keeps its faces and gives
+    bitwise the result of the single-request calls."""
+    reqs = [make_request(i, CASES[i]) for i in (0, 1)]
+    b = Batch(2, DEV)
+    plans, outs, slots, singles = [], [], [], []
+    rng = np.random.default_rng(5)
+    print("[serve] given faces in a batch", flush=True)
+    for q, r in enumerate(reqs):
+        nx, ny, nz = r.dims
+        plan = Plan(synth.make_grid(nx, ny, nz, *r.lengths), PREC_FP64 | PREC_MIXED, device=DEV)
+        faces = np.zeros((nz, ny, nx))
+        if q == 0:
+            faces = rng.normal(size=(nz, ny, nx))
+            faces[1:-1, 1:-1, 1:-1] = 0.0
+        o = make_opts(r.precision, r.rtol, faces_given=(q == 0))
+        bz = torch.from_numpy(r.bz0).to(DEV)
+        # single-request calls first
+        Ps = torch.from_numpy(faces.copy()).to(DEV)
+        plan.solve_boundary(bz, Ps, o)
+        plan.solve_interior(r.model, Ps, o)
+        Fs = tuple(torch.empty_like(Ps) for _ in range(5))
+        plan.fields(r.model, Ps, Fs)
+        singles.append((Ps, Fs))
+        P = torch.from_numpy(faces.copy()).to(DEV)
+        F = tuple(torch.empty_like(P) for _ in range(5))
+        slots.append(b.admit(plan, r.model, bz, P, F, o))
+        plans.append(plan)
+        outs.append((P, F))
+    while b.step():
+        pass
+    for s, (P, F), (Ps, Fs) in zip(slots, outs, singles):
+        done, i2, i3 = b.poll(s)
+        assert done and i2["status"] == 0 and i3["status"] == 0
+        assert torch.equal(P, Ps)
+        assert all(torch.equal(a, c) for a, c in zip(F, Fs))
+    P0 = outs[0][0].cpu().numpy()
+    assert np.abs(P0[-1]).max() > 0 and np.abs(P0[:, 0]).max() > 0  # faces kept
+    b.close()
+    for p in plans:
+        p.close()

@@ -268,3 +268,53 @@ def test_stage_calls_do_not_disturb_solves(plans):
     assert torch.equal(again.P, ref_P)
     again = solve(plan, bz, m, precision=PREC_FP64, rtol=1e-10)
     assert (again.P - ref_P).abs().max().item() < 1e-8 * ref_P.abs().max().item()
+
+
+@pytest.mark.parametrize("dims", [(33, 33, 33), (65, 33, 17)])
+def test_given_faces_fixed_cycles_and_exact_trilinear(plans, dims):
+    """Dirichlet data given on every face (opts.faces = MHS_FACES_GIVEN):
+    the same iterates as the oracle's twin after a fixed number of cycles
+    (2D with given edges, then 3D with given side and top faces), and a
+    trilinear P with alpha = 0 is reproduced by both paths (its second
+    differences vanish, so it solves (8) for any xi)."""
+    nx, ny, nz = dims
+    print(f"[solve] given faces {dims}", flush=True)
+    w = synth.workload("mhs-129", dims=dims)
+    m = w.model
+    plan = plans(dims)
+    rng = np.random.default_rng(sum(dims))
+    faces = rng.normal(size=(nz, ny, nx))
+    faces[1:-1, 1:-1, 1:-1] = 0.0
+    # 2D: edges of plane 0 given
+    e2 = faces[0].copy()
+    e2[1:-1, 1:-1] = 0.0
+    P0_ref, _, c2, _ = ref.mg2(w.bz0, rtol=0.0, max_cycles=2, P0=e2, keep_edges=True)
+    P = torch.from_numpy(faces.copy()).to(DEV)
+    P[0, 1:-1, 1:-1] = 7.0  # interior of plane 0 is not an input
+    bz = torch.from_numpy(w.bz0).to(DEV)
+    info = plan.solve_boundary(bz, P, make_opts(rtol=0.0, max_cycles=2, faces_given=True), raise_on_error=False)
+    assert info.cycles == 2
+    assert rel(P[0].cpu().numpy(), P0_ref) < 1e-12
+    # 3D: side and top faces given, base from the 2D solve
+    ubc = faces.copy()
+    ubc[0] = P0_ref
+    P3_ref, _, _, rr = ref.mg3(ubc, m.xi, m.alpha, rtol=0.0, max_cycles=2)
+    P.copy_(torch.from_numpy(ubc))
+    info = plan.solve_interior(m, P, make_opts(rtol=0.0, max_cycles=2, faces_given=True), raise_on_error=False)
+    assert info.cycles == 2 and abs(info.rel_residual - rr) <= 1e-9 * rr
+    assert rel(P.cpu().numpy(), P3_ref) < 1e-12
+    # a trilinear P (alpha = 0) from its faces, both precisions
+    z, y, x = np.meshgrid(np.linspace(0, 1, nz), np.linspace(0, 1, ny), np.linspace(0, 1, nx), indexing="ij")
+    u = 1.0 + x - 2 * y + 0.5 * z + x * y - y * z + 3 * x * z + x * y * z
+    m0 = synth.Model(0.0, m.xi, m.dxi, m.pb, m.rhob)
+    for prec, tol in ((PREC_FP64, 1e-10), (PREC_MIXED, 1e-8)):
+        bc = u.copy()
+        bc[1:-1, 1:-1, 1:-1] = 0.0
+        P.copy_(torch.from_numpy(bc))
+        plan.solve_interior(m0, P, make_opts(prec, rtol=1e-12 if prec == PREC_FP64 else 1e-10, faces_given=True))
+        assert rel(P.cpu().numpy(), u) < tol, prec
+    # the default still zeroes the faces
+    P.copy_(torch.from_numpy(ubc))
+    plan.solve_interior(m, P, make_opts(rtol=0.0, max_cycles=1), raise_on_error=False)
+    Ph = P.cpu().numpy()
+    assert np.all(Ph[-1] == 0) and np.all(Ph[:, 0] == 0) and np.all(Ph[:, :, -1] == 0)

@@ -80,8 +80,9 @@ def test_boundary_dense_bruteforce(nx, ny):
 
 
 def test_boundary_given_edges():
-    """P given on the edges of the base (the summary's 'P defined on the side
-    boundaries'): bilinear data with Bz0 = 0 is reproduced exactly (every
+    """P given on the edges of the base (the summary of Section 5 leaves P on
+    the side boundaries to the problem): bilinear data with Bz0 = 0 is
+    reproduced exactly (every
     second difference of a bilinear function vanishes), and random edges
     with a random magnetogram match the dense solve."""
     ny, nx = 17, 33
@@ -105,7 +106,8 @@ def test_boundary_given_edges():
 
 
 def test_interior_given_faces():
-    """P given on every face ('define the other boundary conditions'): with
+    """P given on every face (the summary leaves the other boundary
+    conditions to the problem): with
     alpha = 0 a trilinear P satisfies (8) exactly for any xi (its second
     differences vanish), so the solve returns it; random faces match the
     dense solve."""
