@@ -779,10 +779,12 @@ def main():
         "ir_step_model_gbps": mix_vc_gbps,
         "single_stream": {"mixed": {"solves_per_s": single_mixed, "ms_per_solve": 1e3 * mix_total / a.steps,
                                     "p50_ms": 1e3 * percentile(mix_lat, 0.5),
-                                    "p99_ms": 1e3 * percentile(mix_lat, 0.99)},
+                                    "p99_ms": 1e3 * percentile(mix_lat, 0.99),
+                                    "solves_per_s_at_p50": 1.0 / percentile(mix_lat, 0.5)},
                           "fp64": {"solves_per_s": a.steps / f64_total, "ms_per_solve": 1e3 * f64_total / a.steps,
                                    "p50_ms": 1e3 * percentile(f64_lat, 0.5),
-                                   "p99_ms": 1e3 * percentile(f64_lat, 0.99)}},
+                                   "p99_ms": 1e3 * percentile(f64_lat, 0.99),
+                                   "solves_per_s_at_p50": 1.0 / percentile(f64_lat, 0.5)}},
         "batched": {"mixed": batched, "fp64": batched_fp64},
         "fp64": {"value": a.steps / f64_total, "unit": "solves/s", "ms_per_step": 1e3 * f64_total / a.steps,
                  "p50_ms": 1e3 * percentile(f64_lat, 0.5), "p99_ms": 1e3 * percentile(f64_lat, 0.99),
