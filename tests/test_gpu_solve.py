@@ -318,3 +318,65 @@ def test_given_faces_fixed_cycles_and_exact_trilinear(plans, dims):
     plan.solve_interior(m, P, make_opts(rtol=0.0, max_cycles=1), raise_on_error=False)
     Ph = P.cpu().numpy()
     assert np.all(Ph[-1] == 0) and np.all(Ph[:, 0] == 0) and np.all(Ph[:, :, -1] == 0)
+
+
+def test_zero_magnetogram_gives_the_background():
+    """Bz0 = 0: r0 = 0, so both solves stop at once with P = 0; then B = 0,
+    p = p_b and rho = rho_b on every node."""
+    print("[solve] zero magnetogram", flush=True)
+    w = synth.workload("mhs-129", dims=(33, 33, 33))
+    m = w.model
+    plan = Plan(w.grid, PREC_FP64 | PREC_MIXED, device=DEV)
+    for prec in (PREC_FP64, PREC_MIXED):
+        res = solve(plan, torch.zeros((33, 33), dtype=torch.float64, device=DEV), m, precision=prec)
+        assert res.info2d["status"] == 0 and res.info3d["status"] == 0
+        assert res.info2d["cycles"] == 0 and res.info3d["cycles"] == 0
+        assert torch.count_nonzero(res.P) == 0
+        for B in (res.Bx, res.By, res.Bz):
+            assert torch.count_nonzero(B) == 0
+        assert np.array_equal(res.p.cpu().numpy(), np.broadcast_to(m.pb[:, None, None], (33, 33, 33)))
+        assert np.array_equal(res.rho.cpu().numpy(), np.broadcast_to(m.rhob[:, None, None], (33, 33, 33)))
+    plan.close()
+
+
+@pytest.mark.parametrize("dims,lengths", [((5, 5, 5), (1.0, 1.0, 1.0)), ((5, 5, 257), (1.0, 1.0, 64.0)),
+                                          ((257, 5, 9), (1.0, 1.0 / 64, 1.0 / 32)), ((9, 129, 5), (0.3, 2.0, 0.05))])
+def test_extreme_shapes_match_exact(dims, lengths):
+    """The smallest grid (two levels) and long thin boxes (an axis of 5
+    nodes beside one of 257, spacings within a factor 3 of each other; the
+    hierarchy stops when an axis to be halved has 3 nodes and the coarsest
+    grid holds up to a few hundred unknowns): both paths against the exact
+    discrete solution."""
+    nx, ny, nz = dims
+    print(f"[solve] extreme shape {dims} {lengths}", flush=True)
+    grid = synth.make_grid(nx, ny, nz, *lengths)
+    rng = np.random.default_rng(nx + ny + nz)
+    bz0 = np.zeros((ny, nx))
+    bz0[1:-1, 1:-1] = rng.normal(size=(ny - 2, nx - 2))
+    m = synth.make_model(grid, 0.3, 0.5, 0.3 * lengths[2])
+    plan = Plan(grid, PREC_FP64 | PREC_MIXED, device=DEV)
+    want = exact.solve(bz0, nz, m.xi, m.alpha, *lengths)
+    for prec, rtol, tol in ((PREC_FP64, 1e-12, 1e-10), (PREC_MIXED, 1e-10, 1e-8)):
+        res = solve(plan, torch.from_numpy(bz0).to(DEV), m, precision=prec, rtol=rtol, max_cycles=200)
+        assert res.info2d["status"] == 0 and res.info3d["status"] == 0, (res.info2d, res.info3d)
+        assert rel(res.P.cpu().numpy(), want) < tol, (prec, rel(res.P.cpu().numpy(), want))
+    plan.close()
+
+
+def test_strong_anisotropy_reports_no_convergence():
+    """dz = dx / 64 (5 x 5 x 257 on the unit cube): every step halves all
+    axes (no z-only coarsening is built), point smoothing cannot reduce the
+    error along z, and the solve stops at its cycle cap with
+    MHS_ERR_NO_CONVERGENCE, P holding the last iterate and info filled."""
+    print("[solve] dz << dx", flush=True)
+    grid = synth.make_grid(5, 5, 257)
+    m = synth.make_model(grid, 0.3, 0.5, 0.3)
+    bz0 = np.zeros((5, 5))
+    bz0[1:-1, 1:-1] = np.random.default_rng(3).normal(size=(3, 3))
+    plan = Plan(grid, PREC_FP64, device=DEV)
+    P = torch.zeros((257, 5, 5), dtype=torch.float64, device=DEV)
+    plan.solve_boundary(torch.from_numpy(bz0).to(DEV), P, make_opts(rtol=1e-12))
+    info = plan.solve_interior(m, P, make_opts(rtol=1e-12, max_cycles=30), raise_on_error=False)
+    assert info.status == _lib.ERR_NO_CONVERGENCE and info.cycles == 30
+    assert 1e-12 < info.rel_residual < 1.0 and torch.isfinite(P).all()
+    plan.close()
