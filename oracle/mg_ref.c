@@ -24,15 +24,17 @@
  *   - trilinear (bilinear) prolongation of the coarse correction;
  *   - coarse operators by rediscretisation with doubled spacing and xi
  *     sampled at the coarse nodes;
- *   - coarsening of x and y at every level, and of z as well unless the z
- *     spacing is at least sqrt(2) times the larger in-plane spacing (then
- *     only x and y are halved: semicoarsening, with the residual weighted
- *     and the correction interpolated within each plane), while every axis
- *     that is halved has more than 3 nodes, and an exact dense solve
- *     (Gaussian elimination with partial pivoting) on the coarsest grid.
- *     The paper does not say how the coarse grids are built; this rule
- *     keeps coarse levels of grids with dz > dx closer to equal spacing,
- *     which point relaxation needs to smooth in every direction.
+ *   - coarsening of every axis, except that a step keeps z when the z
+ *     spacing is at least sqrt(2) times the larger in-plane spacing (x-y
+ *     semicoarsening: residual weighted and correction interpolated within
+ *     each plane) and keeps x and y when the z spacing is at most 1/sqrt(2)
+ *     times the smaller in-plane spacing (z semicoarsening: weighting and
+ *     interpolation along z only), while every axis that is halved has more
+ *     than 3 nodes, and an exact dense solve (Gaussian elimination with
+ *     partial pivoting) on the coarsest grid.  The paper does not say how
+ *     the coarse grids are built; this rule brings the coarse levels of
+ *     grids with dz != dx toward equal spacing, which point relaxation
+ *     needs to smooth in every direction.
  * Stopping rule: ||r_k||_2 / ||r_0||_2 <= rtol over interior nodes, with
  * r_0 the residual of the initial iterate (P = 0 in the interior, step 1 of
  * the procedure in Section 2.2).
@@ -67,30 +69,41 @@ static int valid_axis(int n)
     return (m & (m - 1)) == 0;
 }
 
-/* Whether the step from a grid of n nodes on a box of lengths len keeps
- * the z axis: dz^2 >= 2 max(dx, dy)^2. */
-static int keeps_z(const int *n, const double *len)
+/* Kind of the step from a grid of n nodes on a box of lengths len:
+ * STEP_XY (z kept) when dz^2 >= 2 max(dx, dy)^2, STEP_Z (x and y kept) when
+ * 2 dz^2 <= min(dx, dy)^2, else STEP_ALL. */
+#define STEP_ALL 0
+#define STEP_XY 1
+#define STEP_Z 2
+static int step_kind(const int *n, const double *len)
 {
     double hx = len[0] / (double)(n[0] - 1), hy = len[1] / (double)(n[1] - 1);
     double hz = len[2] / (double)(n[2] - 1);
-    double hxy = hx > hy ? hx : hy;
-    return hz * hz >= 2.0 * hxy * hxy;
+    double hmax = hx > hy ? hx : hy, hmin = hx < hy ? hx : hy;
+    if (hz * hz >= 2.0 * hmax * hmax) return STEP_XY;
+    if (2.0 * hz * hz <= hmin * hmin) return STEP_Z;
+    return STEP_ALL;
 }
 
-/* Number of levels of the 3D hierarchy; keepz (may be NULL, room for 32
- * entries) receives, per step l -> l+1, 1 if z is kept and 0 if halved. */
-int ref_levels3(const int *n0, const double *len, int *keepz)
+/* Number of levels of the 3D hierarchy; kinds (may be NULL, room for 32
+ * entries) receives the kind of each step l -> l+1 (STEP_ALL: every axis
+ * halved, STEP_XY: x and y halved, STEP_Z: z halved).  Coarsening stops
+ * when an axis that the next step would halve has 3 nodes. */
+int ref_levels3(const int *n0, const double *len, int *kinds)
 {
     if (!valid_axis(n0[0]) || !valid_axis(n0[1]) || !valid_axis(n0[2])) return REF_BAD_GRID;
     int n[3] = {n0[0], n0[1], n0[2]};
     int L = 1;
     for (;;) {
-        int kz = keeps_z(n, len);
-        if (!(n[0] > 3 && n[1] > 3 && (kz || n[2] > 3))) break;
-        if (keepz && L - 1 < 32) keepz[L - 1] = kz;
-        n[0] = (n[0] - 1) / 2 + 1;
-        n[1] = (n[1] - 1) / 2 + 1;
-        if (!kz) n[2] = (n[2] - 1) / 2 + 1;
+        int kind = step_kind(n, len);
+        int hxy = kind != STEP_Z, hz = kind != STEP_XY;
+        if ((hxy && (n[0] <= 3 || n[1] <= 3)) || (hz && n[2] <= 3)) break;
+        if (kinds && L - 1 < 32) kinds[L - 1] = kind;
+        if (hxy) {
+            n[0] = (n[0] - 1) / 2 + 1;
+            n[1] = (n[1] - 1) / 2 + 1;
+        }
+        if (hz) n[2] = (n[2] - 1) / 2 + 1;
         L++;
     }
     return L;
@@ -255,6 +268,38 @@ void ref_prolong3(const int *nc, const double *ec, double *uf)
             }
 }
 
+/* Full weighting along z (x and y kept): fc(i,j,K) = sum w(c) rf(i, j, 2K+c)
+ * at coarse interior nodes; coarse boundary = 0. */
+void ref_restrict3_z(const int *nf, const double *rf, double *fc)
+{
+    static const double w[3] = {0.25, 0.5, 0.25};
+    int nx = nf[0], ny = nf[1];
+    int ncz = (nf[2] - 1) / 2 + 1;
+    for (int K = 0; K < ncz; K++)
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++) {
+                double s = 0.0;
+                if (i > 0 && i < nx - 1 && j > 0 && j < ny - 1 && K > 0 && K < ncz - 1)
+                    for (int c = -1; c <= 1; c++) s += w[c + 1] * AT3(rf, i, j, 2 * K + c);
+                AT3(fc, i, j, K) = s;
+            }
+}
+
+/* uf += I(ec) on fine interior nodes, I = linear interpolation along z
+ * (x and y kept). */
+void ref_prolong3_z(const int *nc, const double *ec, double *uf)
+{
+    int nx = nc[0], ny = nc[1], ncz = nc[2];
+    int nz = 2 * (ncz - 1) + 1;
+    for (int k = 1; k < nz - 1; k++)
+        for (int j = 1; j < ny - 1; j++)
+            for (int i = 1; i < nx - 1; i++) {
+                double s = 0.0;
+                for (int K = k / 2; K <= (k + 1) / 2; K++) s += lin_w(k, K) * AT3(ec, i, j, K);
+                AT3(uf, i, j, k) += s;
+            }
+}
+
 /* uf += I(ec) on fine interior nodes, I = bilinear interpolation within
  * each plane (z kept). */
 void ref_prolong3_xy(const int *nc, const double *ec, double *uf)
@@ -365,7 +410,7 @@ typedef struct {
     double *xi; /* xi sampled at this level's z nodes */
     double *u, *f, *r;
     size_t N;
-    int keepz;  /* the step to the next level keeps z */
+    int kind;   /* kind of the step to the next level (STEP_*) */
 } lev3;
 
 static void free_levels3(lev3 *lv, int L)
@@ -381,8 +426,8 @@ static int build_levels3(lev3 *lv, int L, const int *n, const double *len, const
                          double *u0, const double *f0)
 {
     memset(lv, 0, sizeof(lev3) * (size_t)L);
-    int keepz[32] = {0};
-    if (ref_levels3(n, len, keepz) != L) return REF_BAD_GRID;
+    int kinds[32] = {0};
+    if (ref_levels3(n, len, kinds) != L) return REF_BAD_GRID;
     int nn[3] = {n[0], n[1], n[2]};
     size_t stride = 1; /* fine z nodes per z step of this level */
     for (int l = 0; l < L; l++) {
@@ -395,7 +440,7 @@ static int build_levels3(lev3 *lv, int L, const int *n, const double *len, const
         lv[l].r = (double *)calloc(lv[l].N, sizeof(double));
         if (!lv[l].xi || !lv[l].r) return REF_NOMEM;
         for (int k = 0; k < nn[2]; k++) lv[l].xi[k] = xi[(size_t)k * stride];
-        lv[l].keepz = (l < L - 1) ? keepz[l] : 0;
+        lv[l].kind = (l < L - 1) ? kinds[l] : STEP_ALL;
         if (l == 0) {
             lv[l].u = u0;
             lv[l].f = (double *)f0;
@@ -404,9 +449,11 @@ static int build_levels3(lev3 *lv, int L, const int *n, const double *len, const
             lv[l].f = (double *)calloc(lv[l].N, sizeof(double));
             if (!lv[l].u || !lv[l].f) return REF_NOMEM;
         }
-        nn[0] = (nn[0] - 1) / 2 + 1;
-        nn[1] = (nn[1] - 1) / 2 + 1;
-        if (!lv[l].keepz) {
+        if (lv[l].kind != STEP_Z) {
+            nn[0] = (nn[0] - 1) / 2 + 1;
+            nn[1] = (nn[1] - 1) / 2 + 1;
+        }
+        if (lv[l].kind != STEP_XY) {
             nn[2] = (nn[2] - 1) / 2 + 1;
             stride *= 2;
         }
@@ -421,15 +468,19 @@ static int vcycle3(lev3 *lv, int l, int L, double alpha, int nu1, int nu2)
     ref_rbgs3(c->n, c->h, c->xi, alpha, c->u, c->f, nu1);
     ref_residual3(c->n, c->h, c->xi, alpha, c->u, c->f, c->r);
     lev3 *d = &lv[l + 1];
-    if (c->keepz)
+    if (c->kind == STEP_XY)
         ref_restrict3_xy(c->n, c->r, d->f);
+    else if (c->kind == STEP_Z)
+        ref_restrict3_z(c->n, c->r, d->f);
     else
         ref_restrict3(c->n, c->r, d->f);
     memset(d->u, 0, sizeof(double) * d->N);
     int st = vcycle3(lv, l + 1, L, alpha, nu1, nu2);
     if (st != REF_OK) return st;
-    if (c->keepz)
+    if (c->kind == STEP_XY)
         ref_prolong3_xy(d->n, d->u, c->u);
+    else if (c->kind == STEP_Z)
+        ref_prolong3_z(d->n, d->u, c->u);
     else
         ref_prolong3(d->n, d->u, c->u);
     ref_rbgs3(c->n, c->h, c->xi, alpha, c->u, c->f, nu2);

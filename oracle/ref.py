@@ -40,6 +40,8 @@ def _load():
         "ref_prolong3": (None, [_ip, _dp, _dp]),
         "ref_restrict3_xy": (None, [_ip, _dp, _dp]),
         "ref_prolong3_xy": (None, [_ip, _dp, _dp]),
+        "ref_restrict3_z": (None, [_ip, _dp, _dp]),
+        "ref_prolong3_z": (None, [_ip, _dp, _dp]),
         "ref_direct3": (C.c_int, [_ip, _dp, _dp, C.c_double, _dp, vp]),
         "ref_mg3": (C.c_int, [_ip, _dp, _dp, C.c_double, _dp, C.c_double, C.c_int, C.c_int,
                               C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double), vp]),
@@ -88,8 +90,12 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
+STEP_ALL, STEP_XY, STEP_Z = 0, 1, 2
+
+
 def levels3(nx, ny, nz, lengths=(1.0, 1.0, 1.0)):
-    """(number of 3D levels, [1 if the step l -> l+1 keeps z else 0])."""
+    """(number of 3D levels, [kind of each step l -> l+1]): STEP_ALL halves
+    every axis, STEP_XY keeps z, STEP_Z keeps x and y."""
     keep = np.zeros(32, dtype=np.int32)
     L = _load().ref_levels3(np.array([nx, ny, nz], dtype=np.int32), _f64(lengths), keep)
     return L, [int(v) for v in keep[: max(L - 1, 0)]]
@@ -156,6 +162,23 @@ def prolong3_xy(ec, uf):
     ec = _f64(ec)
     uf = _f64(uf).copy()
     _load().ref_prolong3_xy(_n3(ec.shape), ec, uf)
+    return uf
+
+
+def restrict3_z(rf):
+    """Full weighting along z only (x and y kept)."""
+    rf = _f64(rf)
+    nz, ny, nx = rf.shape
+    fc = np.zeros(((nz - 1) // 2 + 1, ny, nx))
+    _load().ref_restrict3_z(_n3(rf.shape), rf, fc)
+    return fc
+
+
+def prolong3_z(ec, uf):
+    """Return uf + I(ec) on interior fine nodes (linear along z)."""
+    ec = _f64(ec)
+    uf = _f64(uf).copy()
+    _load().ref_prolong3_z(_n3(ec.shape), ec, uf)
     return uf
 
 

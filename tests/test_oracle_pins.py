@@ -48,6 +48,14 @@ def test_level_count_rule():
     assert ref.levels3(65, 33, 17) == (5, [1, 0, 0, 0])
     # dz = 1.25 dx (< sqrt 2): all axes halve
     assert ref.levels3(33, 33, 33, (1.0, 1.0, 1.25))[1] == [0, 0, 0, 0]
+    # x and y kept while 2 dz^2 <= min(dx, dy)^2: dz = dx / 64 halves z six
+    # times (257 -> 5 nodes, dz = dx), then all axes once
+    assert ref.levels3(5, 5, 257) == (8, [2, 2, 2, 2, 2, 2, 0])
+    assert ref.levels3(9, 9, 129) == (7, [2, 2, 2, 2, 0, 0])
+    # the smaller in-plane spacing decides: dx = 1/4, dy = 1/16, dz = 1/64
+    assert ref.levels3(5, 17, 65)[1][:2] == [2, 2]
+    assert ref.levels3(5, 17, 17)[1][0] == 0  # dz = dy: 2 dz^2 > dy^2
+    assert ref.levels3(5, 17, 17, (1.0, 1.0, 0.6))[1][0] == 2  # dz = 0.6 dy (< 1/sqrt 2)
     assert ref.nlevels2(513, 513) == 9
     assert ref.nlevels3(30, 33, 33) < 0  # not 2^L + 1
 
@@ -360,6 +368,31 @@ def test_plane_prolongation_is_bilinear_per_plane():
     assert np.all(uf[0] == 0) and np.all(uf[-1] == 0) and np.all(uf[:, :, 0] == 0)
 
 
+def test_z_restriction_and_prolongation_act_along_z():
+    """With x and y kept, the restriction is the 1D full weighting along z
+    of each column (zero on the coarse boundary) and the prolongation is
+    linear interpolation along z (numpy.interp), exact on data linear in
+    z."""
+    rng = np.random.default_rng(8)
+    rf = rng.normal(size=(17, 6, 7))
+    fc = ref.restrict3_z(rf)
+    assert fc.shape == (9, 6, 7)
+    want = np.zeros_like(fc)
+    want[1:-1, 1:-1, 1:-1] = (0.25 * rf[1:-3:2] + 0.5 * rf[2:-2:2] + 0.25 * rf[3:-1:2])[:, 1:-1, 1:-1]
+    assert rel(fc, want) < 1e-15
+    f = trilinear_field((17, 6, 7), 9)
+    assert rel(ref.restrict3_z(f)[1:-1, 1:-1, 1:-1], f[::2][1:-1, 1:-1, 1:-1]) < 1e-14
+    ec = trilinear_field((9, 5, 6), 10)
+    ec[0] = ec[-1] = 0
+    ec[:, 0] = ec[:, -1] = 0
+    ec[:, :, 0] = ec[:, :, -1] = 0
+    uf = ref.prolong3_z(ec, np.zeros((17, 5, 6)))
+    zc, zf = np.linspace(0, 1, 9), np.linspace(0, 1, 17)
+    t = np.apply_along_axis(lambda v: np.interp(zf, zc, v), 0, ec)
+    assert rel(uf[1:-1, 1:-1, 1:-1], t[1:-1, 1:-1, 1:-1]) < 1e-14
+    assert np.all(uf[:, 0] == 0) and np.all(uf[0] == 0) and np.all(uf[-1] == 0)
+
+
 def test_residual_matches_dense_matrix():
     shape = (5, 9, 7 + 2)
     rng = np.random.default_rng(9)
@@ -411,20 +444,22 @@ def _vcycle_from_stages(u, f, xi, alpha, lengths, nu1=2, nu2=2):
     planes and xi is not resampled."""
     nz, ny, nx = u.shape
     hx, hy, hz = lengths[0] / (nx - 1), lengths[1] / (ny - 1), lengths[2] / (nz - 1)
-    keep = hz * hz >= 2.0 * max(hx, hy) ** 2
-    if nx <= 3 or ny <= 3 or (nz <= 3 and not keep):
+    kind = "xy" if hz * hz >= 2.0 * max(hx, hy) ** 2 else "z" if 2.0 * hz * hz <= min(hx, hy) ** 2 else "all"
+    if (kind != "z" and (nx <= 3 or ny <= 3)) or (kind != "xy" and nz <= 3):
         return dense.solve3(u, f, xi, alpha, *lengths)
     u = ref.rbgs3(u, f, xi, alpha, nu1, lengths)
     r = ref.residual3(u, f, xi, alpha, lengths)
-    fc = ref.restrict3_xy(r) if keep else ref.restrict3(r)
-    ec = _vcycle_from_stages(np.zeros_like(fc), fc, xi if keep else xi[::2], alpha, lengths, nu1, nu2)
-    u = ref.prolong3_xy(ec, u) if keep else ref.prolong3(ec, u)
-    return ref.rbgs3(u, f, xi, alpha, nu2, lengths)
+    restrict = {"xy": ref.restrict3_xy, "z": ref.restrict3_z, "all": ref.restrict3}[kind]
+    prolong = {"xy": ref.prolong3_xy, "z": ref.prolong3_z, "all": ref.prolong3}[kind]
+    fc = restrict(r)
+    ec = _vcycle_from_stages(np.zeros_like(fc), fc, xi if kind == "xy" else xi[::2], alpha, lengths, nu1, nu2)
+    return ref.rbgs3(prolong(ec, u), f, xi, alpha, nu2, lengths)
 
 
 @pytest.mark.parametrize("shape,lengths", [((5, 9, 9), (1.0, 1.5, 0.75)), ((17, 17, 9), (1.0, 1.5, 0.75)),
                                            ((9, 17, 33), (1.0, 1.5, 0.75)), ((9, 17, 33), (1.0, 1.0, 1.0)),
-                                           ((5, 17, 17), (1.0, 1.0, 1.0))])
+                                           ((5, 17, 17), (1.0, 1.0, 1.0)), ((33, 5, 9), (1.0, 1.0, 1.0)),
+                                           ((65, 9, 5), (1.0, 1.0, 1.0))])
 def test_vcycle_equals_composition_of_stages(shape, lengths):
     rng = np.random.default_rng(len(shape) + shape[0])
     nz = shape[0]
@@ -474,6 +509,22 @@ def test_vcycle_contraction_poisson():
     P, st, cyc, rr, hist = ref.mg3(ubc, np.zeros(n), 0.0, rtol=1e-12, history=True)
     rates = hist[3:] / hist[2:-1]
     assert rates.max() < 0.2
+
+
+def test_vcycle_contraction_with_dz_much_below_dx():
+    """dz = dx / 32 (9 x 9 x 257): halving z alone until the spacing is
+    equal keeps the cycle contracting (below 0.15 per cycle); halving every
+    axis leaves point smoothing unable to reduce the error along z and the
+    cycle barely contracts."""
+    nz, n = 257, 9
+    xi = 0.5 * np.exp(-np.linspace(0.0, 1.0, nz) / 0.3)
+    rng = np.random.default_rng(5)
+    ubc = np.zeros((nz, n, n))
+    ubc[0, 1:-1, 1:-1] = rng.normal(size=(n - 2, n - 2))
+    P, st, cyc, rr, hist = ref.mg3(ubc, xi, 0.3, rtol=1e-12, history=True)
+    assert st == ref.OK
+    assert (hist[3:] / hist[2:-1]).max() < 0.15
+    assert rel(P, exact.solve_interior(ubc[0], nz, xi, 0.3, 1.0, 1.0, 1.0)) < 1e-9
 
 
 def test_vcycle_contraction_with_dz_twice_dx():
