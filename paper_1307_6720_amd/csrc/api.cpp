@@ -111,12 +111,13 @@ int check_grid(const mhs_grid *g)
     return MHS_OK;
 }
 
-// Geometry of a hierarchy (no buffers).  Every step halves x and y; a 3D
-// step halves z as well unless dz^2 >= 2 max(dx, dy)^2, when it keeps z (x-y
-// semicoarsening: the paper does not say how coarse grids are built, and
-// halving only the finer axes brings a grid with dz > dx toward equal
+// Geometry of a hierarchy (no buffers).  A 2D step halves both axes.  A 3D
+// step halves every axis, except that it keeps z when dz^2 >= 2 max(dx, dy)^2
+// (x-y semicoarsening) and keeps x and y when 2 dz^2 <= min(dx, dy)^2 (z
+// semicoarsening): the paper does not say how coarse grids are built, and
+// halving only the finer axes brings a grid with dz != dx toward equal
 // spacing, where point red-black smoothing reduces the oscillatory error in
-// every direction).  Coarsening stops when an axis to be halved has 3 nodes.
+// every direction.  Coarsening stops when an axis to be halved has 3 nodes.
 int build_geometry(Hierarchy &h, const int n0[3], const double len[3], bool planar)
 {
     h = Hierarchy();
@@ -133,13 +134,18 @@ int build_geometry(Hierarchy &h, const int n0[3], const double len[3], bool plan
         lv.N = (size_t)n[0] * n[1] * n[2];
         lv.zs = zs;
         ++L;
-        const double hxy = std::max(lv.h[0], lv.h[1]);
-        const bool keepz = !planar && lv.h[2] * lv.h[2] >= 2.0 * hxy * hxy;
-        const bool more = n[0] > 3 && n[1] > 3 && (planar || keepz || n[2] > 3);
+        const double hmax = std::max(lv.h[0], lv.h[1]), hmin = std::min(lv.h[0], lv.h[1]);
+        const double hz2 = lv.h[2] * lv.h[2];
+        const bool keepz = !planar && hz2 >= 2.0 * hmax * hmax;
+        const bool keepxy = !planar && !keepz && 2.0 * hz2 <= hmin * hmin;
+        const bool more = (keepxy || (n[0] > 3 && n[1] > 3)) && (planar || keepz || n[2] > 3);
         if (!more) break;
         lv.keepz = keepz;
-        n[0] = (n[0] - 1) / 2 + 1;
-        n[1] = (n[1] - 1) / 2 + 1;
+        lv.keepxy = keepxy;
+        if (!keepxy) {
+            n[0] = (n[0] - 1) / 2 + 1;
+            n[1] = (n[1] - 1) / 2 + 1;
+        }
         if (!planar && !keepz) {
             n[2] = (n[2] - 1) / 2 + 1;
             ++zs;
@@ -640,17 +646,24 @@ void add_restrict(Program &pg, Staging &st, const Hierarchy &h, int l, int path,
     it.u_out = fc;
     it.state = state;
     const bool bt = h.batched && l > 0;
-    it.ntx = lv.rt[0];
-    it.nty = lv.rt[1];
-    it.ntz = bt ? lv.rtz_b : lv.rt[2];
-    it.kz = bt ? lv.kc_b : lv.kc;
+    const bool zonly = !h.planar && lv.keepxy;
+    if (zonly) { // one thread per coarse interior node
+        const Level &c = h.lv[l + 1];
+        it.ntx = ceil_div((c.n[0] - 2) * (c.n[1] - 2) * (c.n[2] - 2), kThreads);
+        it.nty = it.ntz = it.kz = 1;
+    } else {
+        it.ntx = lv.rt[0];
+        it.nty = lv.rt[1];
+        it.ntz = bt ? lv.rtz_b : lv.rt[2];
+        it.kz = bt ? lv.kc_b : lv.kc;
+    }
     const LevelItem *d = st.put(it);
     if (!d) {
         pg.ok = false;
         return;
     }
     Launch L{};
-    L.kind = h.planar ? Launch::kRestrict2 : Launch::kRestrict3;
+    L.kind = h.planar ? Launch::kRestrict2 : zonly ? Launch::kRestrict3Z : Launch::kRestrict3;
     L.flags = (f ? kRestrictHasF : 0) | (lv.keepz ? kRestrictKeepZ : 0);
     L.dbl = path == kF64;
     L.items = d;
@@ -730,6 +743,50 @@ void add_finalize(Program &pg, Staging &st, const double *partials, int n, Solve
     pg.launches.push_back(L);
 }
 
+// u += I_z(ec) on level l, whose step to level l+1 halves z only (the
+// smoother's fused prolongation assumes halved x and y).
+void add_prolong_z(Program &pg, Staging &st, const Hierarchy &h, int l, int path, void *u, const void *ec,
+                   SolveState *state)
+{
+    LevelItem it = level_item(h, l, path);
+    const Level &lv = h.lv[l];
+    it.u_in = u;
+    it.u_out = u;
+    it.ec = ec;
+    it.state = state;
+    it.ntx = ceil_div((lv.n[0] - 2) * (lv.n[1] - 2) * (lv.n[2] - 2), kThreads);
+    it.nty = it.ntz = it.kz = 1;
+    const LevelItem *d = st.put(it);
+    if (!d) {
+        pg.ok = false;
+        return;
+    }
+    Launch L{};
+    L.kind = Launch::kProlong3Z;
+    L.dbl = path == kF64;
+    L.items = d;
+    L.ntiles = it.ntx;
+    L.prof = MHS_PROF_COARSE;
+    {
+        const double es = path == kF64 ? 8.0 : 4.0;
+        L.bytes = es * (2.0 * (double)lv.N + (double)h.lv[l + 1].N);
+    }
+    pg.launches.push_back(L);
+}
+
+// First post-smoothing sweep of level l with the coarse correction ec: fused
+// into the sweep, or (after a step that halves z only) added first.
+void add_correct_sweep(Program &pg, Staging &st, const Hierarchy &h, int l, int path, void *cur, void *oth,
+                       const void *f, const void *ec, SolveState *state)
+{
+    if (h.lv[l].keepxy) {
+        add_prolong_z(pg, st, h, l, path, cur, ec, state);
+        add_sweep(pg, st, h, l, path, cur, oth, f, nullptr, 0, state, nullptr);
+    } else {
+        add_sweep(pg, st, h, l, path, cur, oth, f, ec, kProlong, state, nullptr);
+    }
+}
+
 // One V(nu1, nu2) cycle.  Level 0 ping-pongs between a0 (input) and b0; the
 // returned pointer is the buffer holding the level-0 result.  With
 // `first_norm`, the first sweep also sums the residual of the input iterate
@@ -767,7 +824,7 @@ void *add_cycle(Program &pg, Staging &st, const Hierarchy &h, int path, void *a0
         const Level &lv = h.lv[l];
         void *c = lcur[l];
         void *o = (c == lv.u[path]) ? lv.t[path] : lv.u[path];
-        add_sweep(pg, st, h, l, path, c, o, lv.f[path], ec, kProlong, state, nullptr);
+        add_correct_sweep(pg, st, h, l, path, c, o, lv.f[path], ec, state);
         std::swap(c, o);
         for (int s = 1; s < nu2; ++s) {
             add_sweep(pg, st, h, l, path, c, o, lv.f[path], nullptr, 0, state, nullptr);
@@ -775,7 +832,7 @@ void *add_cycle(Program &pg, Staging &st, const Hierarchy &h, int path, void *a0
         }
         ec = c;
     }
-    add_sweep(pg, st, h, 0, path, cur, oth, f0, ec, kProlong, state, nullptr);
+    add_correct_sweep(pg, st, h, 0, path, cur, oth, f0, ec, state);
     std::swap(cur, oth);
     for (int s = 1; s < nu2; ++s) {
         add_sweep(pg, st, h, 0, path, cur, oth, f0, nullptr, 0, state, nullptr);
@@ -892,6 +949,11 @@ hipError_t exec_launch(const Launch &L, hipStream_t s)
                                 (L.flags & kRestrictKeepZ) != 0, L.dbl, s);
     case Launch::kRestrict2:
         return launch_restrict2((const LevelItem *)L.items, L.nitems, L.ntiles, L.dbl, s);
+    case Launch::kRestrict3Z:
+        return launch_restrict3_z((const LevelItem *)L.items, L.nitems, L.ntiles, (L.flags & kRestrictHasF) != 0,
+                                  L.dbl, s);
+    case Launch::kProlong3Z:
+        return launch_prolong3_z((const LevelItem *)L.items, L.nitems, L.ntiles, L.dbl, s);
     case Launch::kIr3:
         return launch_ir3((const LevelItem *)L.items, L.nitems, L.ntiles, L.flags != 0, s);
     case Launch::kBottom:
@@ -1626,7 +1688,7 @@ int mhs_stage_correct_smooth(mhs_plan *p, const mhs_model *model, int32_t space,
     HIPCHK(hipMemcpyAsync(tw, d_u, bytes, hipMemcpyDeviceToDevice, s));
     if ((st = begin_staging(p))) return st;
     Program pg;
-    add_sweep(pg, p->stage, *h, level, path, d_u, tw, d_f, d_ec, kProlong, nullptr, nullptr);
+    add_correct_sweep(pg, p->stage, *h, level, path, d_u, tw, d_f, d_ec, nullptr);
     if (!pg.ok) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
     if ((st = flush_staging(p, s))) return st;
     if ((st = run_program(p, pg, s))) return st;

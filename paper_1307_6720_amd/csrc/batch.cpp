@@ -329,6 +329,8 @@ size_t item_size(Launch::Kind k)
     case Launch::kRestrict3:
     case Launch::kRestrict2:
     case Launch::kIr3:
+    case Launch::kRestrict3Z:
+    case Launch::kProlong3Z:
         return sizeof(LevelItem);
     case Launch::kBottom:
         return sizeof(BottomItem);
@@ -375,6 +377,8 @@ bool merge(Staging &st, const std::vector<const Rec *> &grp, Launch *out)
         case Launch::kRestrict3:
         case Launch::kRestrict2:
         case Launch::kIr3:
+        case Launch::kRestrict3Z:
+        case Launch::kProlong3Z:
             reinterpret_cast<LevelItem *>(dst)->tile_base = M.ntiles;
             M.ntiles += L.ntiles;
             break;

@@ -199,6 +199,9 @@ hipError_t launch_restrict3(const LevelItem *items, int nitems, int ntiles, bool
                             hipStream_t s);
 hipError_t launch_restrict2(const LevelItem *items, int nitems, int ntiles, bool dbl,
                             hipStream_t s);
+// steps that keep x and y: one thread per node (ntiles = ceil(nodes / kThreads))
+hipError_t launch_restrict3_z(const LevelItem *items, int nitems, int ntiles, bool has_f, bool dbl, hipStream_t s);
+hipError_t launch_prolong3_z(const LevelItem *items, int nitems, int ntiles, bool dbl, hipStream_t s);
 hipError_t launch_ir3(const LevelItem *items, int nitems, int ntiles, bool has_e, hipStream_t s);
 hipError_t launch_bottom(const BottomItem *items, int nitems, int lds_bytes, bool dbl, hipStream_t s);
 hipError_t launch_finalize(const FinalizeItem *items, int nitems, hipStream_t s);

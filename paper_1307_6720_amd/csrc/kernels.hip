@@ -1040,6 +1040,67 @@ __global__ __launch_bounds__(kThreads) void k_restrict3(const LevelItem *__restr
 }
 
 
+// ============================================================================
+// Steps that keep x and y (z semicoarsening, for grids with dz well below dx
+// and dy): residual + full weighting along z, and the correction's linear
+// interpolation along z.  One thread per coarse (restriction) or fine
+// (prolongation) interior node, reads through the caches; such levels are
+// rare and small, so these kernels favour plainness over the tiled march.
+// ============================================================================
+template <typename T, bool HAS_F>
+__global__ __launch_bounds__(kThreads) void k_restrict3_z(const LevelItem *__restrict__ items, int nitems)
+{
+    const int tile = xcd_tile();
+    const LevelItem *it = items + find_item(items, nitems, tile);
+    if (it->state && gin<SolveState>(it->state)->done) return;
+    const int nx = it->nx, ny = it->ny, ncz = it->ncz;
+    const int mx = nx - 2, my = ny - 2;
+    const int64_t e = (int64_t)(tile - it->tile_base) * kThreads + threadIdx.x;
+    if (e >= (int64_t)mx * my * (ncz - 2)) return;
+    const int i = 1 + (int)(e % mx);
+    const int64_t q = e / mx;
+    const int j = 1 + (int)(q % my), K = 1 + (int)(q / my);
+    const MHS_GLOBAL T *__restrict__ u = gin<T>(it->u_in);
+    const MHS_GLOBAL T *__restrict__ f = gin<T>(it->f);
+    MHS_GLOBAL T *__restrict__ fc = gout<T>(it->u_out);
+    const MHS_CONST T *__restrict__ coef = gconst<T>(it->coef);
+    const T cz = (T)it->cz;
+    const size_t sxy = (size_t)nx * ny, col = (size_t)i + (size_t)nx * j;
+    T acc = (T)0;
+#pragma unroll
+    for (int c = -1; c <= 1; ++c) {
+        const int k = 2 * K + c; // 1 <= k <= nz - 2
+        const size_t o = col + sxy * k;
+        const T cx = coef[4 * k], cy = coef[4 * k + 1], d = coef[4 * k + 2];
+        const T fv = HAS_F ? f[o] : (T)0;
+        const T rv = fv - (cx * (u[o + 1] + u[o - 1]) + cy * (u[o + nx] + u[o - nx]) + cz * (u[o + sxy] + u[o - sxy]) +
+                           d * u[o]);
+        acc += (c == 0 ? (T)0.5 : (T)0.25) * rv;
+    }
+    fc[col + sxy * K] = acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_prolong3_z(const LevelItem *__restrict__ items, int nitems)
+{
+    const int tile = xcd_tile();
+    const LevelItem *it = items + find_item(items, nitems, tile);
+    if (it->state && gin<SolveState>(it->state)->done) return;
+    const int nx = it->nx, ny = it->ny, nz = it->nz;
+    const int mx = nx - 2, my = ny - 2;
+    const int64_t e = (int64_t)(tile - it->tile_base) * kThreads + threadIdx.x;
+    if (e >= (int64_t)mx * my * (nz - 2)) return;
+    const int i = 1 + (int)(e % mx);
+    const int64_t q = e / mx;
+    const int j = 1 + (int)(q % my), k = 1 + (int)(q / my);
+    const MHS_GLOBAL T *__restrict__ ec = gin<T>(it->ec);
+    MHS_GLOBAL T *__restrict__ u = gout<T>(it->u_out);
+    const size_t sxy = (size_t)nx * ny, col = (size_t)i + (size_t)nx * j;
+    const size_t c0 = col + sxy * (size_t)(k >> 1); // coarse plane k/2 (x, y kept)
+    const T v = (k & 1) ? (T)0.5 * ec[c0] + (T)0.5 * ec[c0 + sxy] : ec[c0];
+    u[col + sxy * k] += v;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_restrict2(const LevelItem *__restrict__ items, int nitems)
 {
@@ -1377,14 +1438,15 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(const BottomItem *__r
         // the step keeps z)
         {
             const int cnx = b.n[l + 1][0], cny = b.n[l + 1][1], cnz = b.n[l + 1][2];
-            const bool zc = !planar && cnz < nz;
+            const bool zc = !planar && cnz < nz; // the step halves z
+            const bool xyc = cnx < nx;           // the step halves x and y
             double *fc = smem + b.off_f[l + 1];
             const int cmx = cnx - 2, cmy = cny - 2, cmz = planar ? 1 : cnz - 2;
             bottom_rows(cmx, cmy, cmy * cmz, [&](int q, int jj, int kk) {
                 const int I = q + 1, J = jj + 1, K = planar ? 0 : kk + 1;
-                const int fidx = 2 * I + nx * (2 * J) + sxy * (zc ? 2 * K : K);
+                const int fidx = (xyc ? 2 * I : I) + nx * (xyc ? 2 * J : J) + sxy * (zc ? 2 * K : K);
                 auto row = [&](int c) { return 0.25 * r[c - 1] + 0.5 * r[c] + 0.25 * r[c + 1]; };
-                auto pl = [&](int c) { return 0.25 * row(c - nx) + 0.5 * row(c) + 0.25 * row(c + nx); };
+                auto pl = [&](int c) { return xyc ? 0.25 * row(c - nx) + 0.5 * row(c) + 0.25 * row(c + nx) : r[c]; };
                 const double v = !zc ? pl(fidx) : 0.25 * pl(fidx - sxy) + 0.5 * pl(fidx) + 0.25 * pl(fidx + sxy);
                 fc[I + cnx * J + cnx * cny * K] = v;
             });
@@ -1417,14 +1479,21 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(const BottomItem *__r
         const int nx = b.n[l][0], ny = b.n[l][1], nz = b.n[l][2];
         const int cnx = b.n[l + 1][0], cny = b.n[l + 1][1];
         const bool zc = !planar && b.n[l + 1][2] < nz;
+        const bool xyc = cnx < nx;
         const int sxy = nx * ny;
         const int mx = nx - 2, my = ny - 2, mz = planar ? 1 : nz - 2;
         double *u = smem + b.off_u[l];
         const double *ec = smem + b.off_u[l + 1];
         bottom_rows(mx, my, my * mz, [&](int q, int jj, int kk) {
             const int i = q + 1, j = jj + 1, k = planar ? 0 : kk + 1;
-            const double v = zc ? interp3<double>(ec, cnx, cny, i, j, k)
-                                : interp2<double>(ec + (size_t)cnx * cny * k, cnx, i, j);
+            double v;
+            if (xyc) {
+                v = zc ? interp3<double>(ec, cnx, cny, i, j, k)
+                       : interp2<double>(ec + (size_t)cnx * cny * k, cnx, i, j);
+            } else { // x and y kept: linear along z
+                const double *e0 = ec + i + nx * j + sxy * (k >> 1);
+                v = (k & 1) ? 0.5 * e0[0] + 0.5 * e0[sxy] : e0[0];
+            }
             u[i + nx * j + sxy * k] += v;
         });
         lds_barrier();
@@ -2045,6 +2114,35 @@ hipError_t launch_restrict3(const LevelItem *items, int nitems, int ntiles, bool
         else
             restrict3_variant<float, false>(items, nitems, grid, keepz, s);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_restrict3_z(const LevelItem *items, int nitems, int ntiles, bool has_f, bool dbl, hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    dim3 grid(ntiles), block(kThreads);
+    if (dbl) {
+        if (has_f)
+            hipLaunchKernelGGL((k_restrict3_z<double, true>), grid, block, 0, s, items, nitems);
+        else
+            hipLaunchKernelGGL((k_restrict3_z<double, false>), grid, block, 0, s, items, nitems);
+    } else {
+        if (has_f)
+            hipLaunchKernelGGL((k_restrict3_z<float, true>), grid, block, 0, s, items, nitems);
+        else
+            hipLaunchKernelGGL((k_restrict3_z<float, false>), grid, block, 0, s, items, nitems);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong3_z(const LevelItem *items, int nitems, int ntiles, bool dbl, hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    dim3 grid(ntiles), block(kThreads);
+    if (dbl)
+        hipLaunchKernelGGL((k_prolong3_z<double>), grid, block, 0, s, items, nitems);
+    else
+        hipLaunchKernelGGL((k_prolong3_z<float>), grid, block, 0, s, items, nitems);
     return hipGetLastError();
 }
 

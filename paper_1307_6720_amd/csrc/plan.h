@@ -33,6 +33,7 @@ struct Level {
     int kc_b = 1, rtz_b = 1;
     int zs = 0;            // xi of plane k is xi[k << zs] of the finest grid
     bool keepz = false;    // the step to level+1 halves x and y only
+    bool keepxy = false;   // the step to level+1 halves z only
     int sweep_tiles() const { return st[0] * st[1] * st[2]; }
     int restrict_tiles() const { return rt[0] * rt[1] * rt[2]; }
 };
@@ -54,7 +55,10 @@ struct Hierarchy {
 
 // One kernel launch of a program (the device item table is in the workspace).
 struct Launch {
-    enum Kind { kSweep3, kSweep2, kRestrict3, kRestrict2, kIr3, kBottom, kFinalize, kCopy, kFields, kPrep3, kPrep2 } kind;
+    enum Kind {
+        kSweep3, kSweep2, kRestrict3, kRestrict2, kIr3, kBottom, kFinalize, kCopy, kFields, kPrep3, kPrep2,
+        kRestrict3Z, kProlong3Z
+    } kind;
     int flags = 0;
     bool dbl = true;
     const void *items = nullptr; // device pointer

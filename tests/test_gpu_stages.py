@@ -20,8 +20,9 @@ from paper_1307_6720_amd.solver import Plan  # noqa: E402
 
 DEV = "cuda:0"
 # (nz, ny, nx) on a 1.0 x 1.3 x 0.8 box; (9, 65, 129) has dz^2 >= 2 max(dx, dy)^2
-# on levels 0 and 1, whose steps halve x and y only
-SHAPES = [(33, 33, 33), (17, 33, 129), (33, 65, 65), (9, 65, 129)]
+# on levels 0 and 1, whose steps halve x and y only; (129, 9, 17) has
+# 2 dz^2 <= min(dx, dy)^2 on levels 0 to 2, whose steps halve z only
+SHAPES = [(33, 33, 33), (17, 33, 129), (33, 65, 65), (9, 65, 129), (129, 9, 17)]
 
 
 def rel(a, b):
@@ -63,12 +64,22 @@ def keeps_z(plan, level):
     return plan.level_shape(3, level + 1)[0] == plan.level_shape(3, level)[0]
 
 
+def keeps_xy(plan, level):
+    return plan.level_shape(3, level + 1)[2] == plan.level_shape(3, level)[2]
+
+
+def step_kind(plan, level):
+    return ref.STEP_XY if keeps_z(plan, level) else ref.STEP_Z if keeps_xy(plan, level) else ref.STEP_ALL
+
+
 def restrict(plan, level, r):
-    return ref.restrict3_xy(r) if keeps_z(plan, level) else ref.restrict3(r)
+    return {ref.STEP_XY: ref.restrict3_xy, ref.STEP_Z: ref.restrict3_z,
+            ref.STEP_ALL: ref.restrict3}[step_kind(plan, level)](r)
 
 
 def prolong(plan, level, ec, u):
-    return ref.prolong3_xy(ec, u) if keeps_z(plan, level) else ref.prolong3(ec, u)
+    return {ref.STEP_XY: ref.prolong3_xy, ref.STEP_Z: ref.prolong3_z,
+            ref.STEP_ALL: ref.prolong3}[step_kind(plan, level)](ec, u)
 
 
 def level_args(plan, model, grid, level):
@@ -85,7 +96,7 @@ def test_level_shapes_match_oracle_rule(setup):
     L, keep = ref.levels3(grid.nx, grid.ny, grid.nz, (grid.lx, grid.ly, grid.lz))
     assert plan.levels(3) <= L
     for l in range(plan.levels(3) - 1):
-        assert keeps_z(plan, l) == bool(keep[l]), l
+        assert step_kind(plan, l) == keep[l], l
 
 
 def tg(a, dtype=torch.float64):
