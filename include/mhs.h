@@ -145,12 +145,13 @@ int mhs_check_model(const mhs_grid *grid, const mhs_model *model, double *lambda
 /* Create a plan on the current HIP device over the caller's workspace
  * (d_workspace: device pointer, 256-byte aligned, >= mhs_workspace_bytes).
  * Clears the workspace (synchronously).  Each step of the 3D hierarchy
- * halves x and y, and z too unless dz^2 >= 2 max(dx, dy)^2 at that level
- * (then the step keeps z: restriction and prolongation act within planes);
- * the 2D hierarchy halves both axes.  Coarsening stops when an axis to be
- * halved has 3 nodes; the coarsest grid is solved exactly.  (The paper,
- * Section 2.2, leaves the coarse grids open; with dz > dx, keeping z makes
- * the coarse levels equally spaced, which point smoothing needs.) */
+ * halves every axis, except that it keeps z when dz^2 >= 2 max(dx, dy)^2
+ * (restriction and prolongation within planes) and keeps x and y when
+ * 2 dz^2 <= min(dx, dy)^2 (restriction and prolongation along z); the 2D
+ * hierarchy halves both axes.  Coarsening stops when an axis to be halved
+ * has 3 nodes; the coarsest grid is solved exactly.  (The paper, Section
+ * 2.2, leaves the coarse grids open; halving only the finer axes makes the
+ * coarse levels equally spaced, which point smoothing needs.) */
 int mhs_plan_create(const mhs_grid *grid, int32_t precisions, void *d_workspace,
                     size_t workspace_bytes, mhs_plan **plan);
 
