@@ -28,6 +28,9 @@ CASES = [
     ((33, 65, 129), (1.0, 1.3, 0.8), 0.7, 0.6, PREC_MIXED, 1e-10),
     ((65, 65, 65), (1.0, 1.0, 1.0), 0.9, 0.3, PREC_FP64, 1e-10),
     ((129, 129, 129), (1.0, 1.0, 1.0), 0.5, 0.5, PREC_MIXED, 1e-10),
+    # steps that halve z alone (dz = dx / 8), and x and y alone (dz = 2 dx)
+    ((17, 17, 129), (1.0, 1.0, 1.0), 0.4, 0.5, PREC_MIXED, 1e-10),
+    ((65, 65, 33), (1.0, 1.0, 1.0), 0.2, 0.4, PREC_FP64, 1e-10),
 ]
 
 
