@@ -17,6 +17,7 @@ JSON line.  Inputs are resident in HBM before timing starts.
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -614,6 +615,11 @@ def main():
             plan.profile(False)
         return total, lat, cyc, t3, prof
 
+    # Python's full garbage collections traverse every live object (torch and
+    # numpy bring ~170k); one in a timed pass stalls the host ~40-60 ms between
+    # two library calls.  Long-lived objects move to the permanent generation.
+    gc.collect()
+    gc.freeze()
     for prec in (PREC_MIXED, PREC_FP64):
         for k in range(a.warmup):
             step(k, prec)

@@ -71,6 +71,10 @@ class Server:
     buffers, in use or idle).
     on_finish(req, resident): optional; called before a finished request's
     resources return to the pool (e.g. to copy its outputs).
+
+    The tick loop runs in Python: a full garbage collection during it (tens
+    of ms with torch loaded) delays every request in flight.  Latency-bound
+    callers can call ``gc.collect(); gc.freeze()`` once after setting up.
     """
 
     def __init__(self, backend, hbm_budget, on_finish=None):
