@@ -138,3 +138,38 @@ def test_paper_case_matches_exact(name, prec, rtol, tol):
         assert abs(x[xs][i]) < 0.1 and -2.2 < y[ys][j] < -1.4
         assert sub.min() < 0.02 * sub.max()
     plan.close()
+
+
+def test_paper_parameters_match_the_printed_values():
+    """The paper's Section 3 inputs as printed (tests/golden/paper_section3.json,
+    each value keyed by its subsection) against what synth builds: domain
+    and resolution, the three sources, alpha, the coronal temperature and
+    both cross-field profiles evaluated from the printed coefficients."""
+    import json
+    import os
+
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_section3.json")))
+    from synth import paper
+
+    dom = g["domain_sec3"]
+    w = synth.paper_workload("paper-ff")
+    assert (w.grid.nx - 1, w.grid.ny - 1, w.grid.nz - 1) == (dom["intervals_per_axis"],) * 3
+    assert (w.grid.lx, w.grid.ly, w.grid.lz) == (dom["x"][1] - dom["x"][0], dom["y"][1] - dom["y"][0],
+                                                  dom["z"][1] - dom["z"][0])
+    assert paper.ORIGIN == (dom["x"][0], dom["y"][0])
+    ff = g["force_free_sec3_1"]
+    assert w.model.alpha == ff["alpha"] and np.all(w.model.xi == ff["xi"])
+    assert paper.WIDTH == ff["source_width_l"]
+    assert [list(s) for s in paper.SOURCES] == ff["sources_x0_y0_b0"]
+    assert paper.T_COR == g["background_sec3"]["t_cor"]
+    z = np.linspace(0.0, 12.0, 97)
+    t = paper.temperature(z)
+    tc = g["background_sec3"]["t_cor"]
+    assert np.allclose(t, np.where(z <= 5, 1.0, np.where(z <= 10, tc ** ((z - 5) / 5), tc)), rtol=1e-14)
+    x1, x2 = g["xi_profiles_sec3_2"]["xi1"], g["xi_profiles_sec3_2"]["xi2"]
+    xi1, _ = paper.xi_profile(z, "xi1")
+    xi2, _ = paper.xi_profile(z, "xi2")
+    assert np.allclose(xi1, x1["amplitude"] * np.exp(-x1["decay_rate"] * z), rtol=1e-14, atol=0)
+    want2 = (x2["amplitude"] + x2["sine_amplitude"] * np.sin(x2["sine_wavenumber_over_pi"] * np.pi * z)) \
+        * np.exp(-x2["decay_rate"] * z)
+    assert np.allclose(xi2, want2, rtol=1e-14, atol=1e-16)
