@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--large-workload", default="mhs-513x513x257",
                     help="the large single equilibrium reported beside the headline ('' skips it)")
+    ap.add_argument("--large-only", action="store_true",
+                    help="run only the large-equilibrium leg (the workload of its rocprofv3 summary)")
     ap.add_argument("--counter-probe", action="store_true",
                     help="run only the workload of the rocprofv3 FETCH_SIZE/WRITE_SIZE runs")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -492,9 +494,17 @@ def large_leg(a, torch, dev, reps=5):
             torch.cuda.synchronize()
             ts.append(time.perf_counter() - t0)
         i3 = res.info3d
+        # per-class HIP-event timings and compulsory-byte rates of one more pass
+        plan.profile(True)
+        plan.profile_read(reset=True)
+        solve(plan, bz, w.model, precision=prec, rtol=a.rtol, inner_cycles=a.inner_cycles, out=arrays)
+        torch.cuda.synchronize()
+        kern = {k: {"launches": n, "avg_us": 1e3 * ms / n, "gbps": b / (ms * 1e-3) / 1e9}
+                for k, (ms, n, b) in plan.profile_read(reset=True).items() if n and ms > 0}
+        plan.profile(False)
         out[name] = {"ms_per_solve": 1e3 * sum(ts) / reps, "cycles_3d": i3["cycles"],
                      "cycles_2d": res.info2d["cycles"], "rel_residual": i3["rel_residual"],
-                     "model_gbps_3d": i3["cycles"] * per_cycle / i3["seconds"] / 1e9}
+                     "model_gbps_3d": i3["cycles"] * per_cycle / i3["seconds"] / 1e9, "kernels": kern}
     out["levels"] = [list(plan.level_shape(3, l)) for l in range(plan.levels(3))]
     plan.close()
     del arrays
@@ -563,6 +573,11 @@ def main():
 
     if a.counter_probe:
         counter_probe()
+        return
+    if a.large_only:
+        import torch
+
+        print(json.dumps({"large_case": large_leg(a, torch, torch.device("cuda:0"))}), flush=True)
         return
 
     import numpy as np
