@@ -299,7 +299,7 @@ int mhs_trace_field_lines(mhs_plan *plan, const double *d_Bx, const double *d_By
 #define MHS_PROF_RESTRICT_L0 2 /* finest-level residual + restriction     */
 #define MHS_PROF_FIELDS 3      /* field recovery                          */
 #define MHS_PROF_BOTTOM 4      /* single-workgroup bottom solver          */
-#define MHS_PROF_COARSE 5      /* every other stencil launch (levels >= 1, 2D) */
+#define MHS_PROF_COARSE 5      /* every other stencil launch (levels >= 1, 2D, z-only prolongation) */
 #define MHS_PROF_DIAG 6        /* diagnostics (mhs_diagnostics)            */
 #define MHS_PROF_TRACE 7       /* field lines (mhs_trace_field_lines)      */
 #define MHS_PROF_NCLASS 8
