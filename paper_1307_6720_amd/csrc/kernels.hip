@@ -252,6 +252,9 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     // register-ring depth (planes of loads in flight); shallower when every
     // plane also carries right-hand-side or coarse-correction data
     constexpr int D = (HAS_F || PROLONG) ? kDepthF : kDepth;
+    // the register classes of f (by plane parity) and the round of lcm(5, D)
+    // steps are written for a ring of two planes
+    static_assert(D == 2, "the smoother's march assumes a register ring of depth 2");
     constexpr int kCWPlanes = PROLONG ? 2 : 1;
     // right-hand-side values a thread reads per plane: its two red nodes,
     // its black node and, for the residual, its two own nodes
