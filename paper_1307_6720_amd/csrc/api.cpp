@@ -178,16 +178,21 @@ int build_geometry(Hierarchy &h, const int n0[3], const double len[3], bool plan
         if (planar) {
             lv.st[0] = ceil_div(lv.n[0] - 2, kTX);
             lv.st[1] = ceil_div(lv.n[1] - 2, kTY2);
+            lv.ity = lv.st[1];
             lv.st[2] = 1;
             lv.kz = 1;
             lv.stz_b = 1;
             lv.kz_b = 1;
         } else {
             lv.st[0] = ceil_div(lv.n[0] - 2, kTX);
-            lv.st[1] = ceil_div(lv.n[1] - 2, kTY);
-            lv.kz = chunk(lv.n[2] - 2, lv.st[0] * lv.st[1], kKZ, l == 0 ? kTargetGroups : kCoarseTargetGroups);
+            lv.st[1] = ceil_div(lv.n[1] - 2, kSTY);
+            lv.ity = ceil_div(lv.n[1] - 2, kTY);
+            // z-chunks sized in kTX x kTY tiles of kThreads threads: the
+            // smoother's taller tiles give fewer, larger workgroups over the
+            // same number of threads
+            lv.kz = chunk(lv.n[2] - 2, lv.st[0] * lv.ity, kKZ, l == 0 ? kTargetGroups : kCoarseTargetGroups);
             lv.st[2] = ceil_div(lv.n[2] - 2, lv.kz);
-            lv.kz_b = l == 0 ? lv.kz : chunk(lv.n[2] - 2, lv.st[0] * lv.st[1], kKZ, kBatchCoarseTargetGroups);
+            lv.kz_b = l == 0 ? lv.kz : chunk(lv.n[2] - 2, lv.st[0] * lv.ity, kKZ, kBatchCoarseTargetGroups);
             lv.stz_b = ceil_div(lv.n[2] - 2, lv.kz_b);
         }
         if (l + 1 < L) {
@@ -240,7 +245,7 @@ void carve_hierarchy(Hierarchy &h, Carver &cv, int paths)
         if (paths & 2) lv.coef32 = cv.take<float>(4 * (size_t)lv.n[2]);
     }
     h.minv = cv.take<double>((size_t)h.mcap * h.mcap);
-    h.npart = l0.sweep_tiles();
+    h.npart = std::max(l0.sweep_tiles(), l0.ir_tiles());
     h.partials = cv.take<double>(h.npart);
 }
 
@@ -802,7 +807,7 @@ void *add_cycle(Program &pg, Staging &st, const Hierarchy &h, int path, void *a0
         if (s == 0 && first_norm) flags |= kNorm;
         add_sweep(pg, st, h, 0, path, cur, oth, f0, nullptr, flags, state, h.partials);
         std::swap(cur, oth);
-        if (s == 0 && first_norm) add_finalize(pg, st, h.partials, h.npart, state);
+        if (s == 0 && first_norm) add_finalize(pg, st, h.partials, h.lv[0].sweep_tiles(), state);
     }
     add_restrict(pg, st, h, 0, path, cur, f0, h.lv[1].f[path], state);
     void *lcur[kMaxLevels] = {};
@@ -856,7 +861,7 @@ void add_ir_step(Program &pg, Staging &st, const Hierarchy &h, const double *uin
     it.state = state;
     it.partials = h.partials;
     it.ntx = l0.st[0];
-    it.nty = l0.st[1];
+    it.nty = l0.ity;
     it.ntz = l0.st[2];
     it.kz = l0.kz;
     const LevelItem *d = st.put(it);
@@ -868,12 +873,12 @@ void add_ir_step(Program &pg, Staging &st, const Hierarchy &h, const double *uin
     L.kind = Launch::kIr3;
     L.flags = e ? 1 : 0;
     L.items = d;
-    L.ntiles = l0.sweep_tiles();
+    L.ntiles = l0.ir_tiles();
     L.prof = MHS_PROF_REFINE;
     L.bytes = (double)l0.N * (e ? 8.0 + 4.0 + 8.0 + 4.0 : 8.0 + 4.0);
     L.pre = true;
     pg.launches.push_back(L);
-    add_finalize(pg, st, h.partials, h.npart, state);
+    add_finalize(pg, st, h.partials, l0.ir_tiles(), state);
 }
 
 FieldsItem fields_item(const mhs_plan *p, const mhs_model *model, const double *tab, const double *P, double *Bx,

@@ -16,8 +16,8 @@ namespace mhs {
 constexpr int kMaxLevels = 16;
 
 // ---- tile geometry ---------------------------------------------------------
-// 3D smoother / refinement residual: x-y tile of kTX x kTY interior nodes,
-// marching kKZ planes in z; 256 threads.
+// 3D refinement residual: x-y tile of kTX x kTY interior nodes, marching
+// kKZ planes in z; 256 threads (the smoother's tile height is kSTY below).
 #ifndef MHS_TILE_Y
 #define MHS_TILE_Y 8
 #endif
@@ -43,6 +43,15 @@ constexpr int kTX = 64;
 constexpr int kTY = MHS_TILE_Y;
 constexpr int kKZ = 32;
 constexpr int kThreads = 256;
+// The 3D smoother's own tile height: one black node of the tile per thread,
+// so a workgroup of kSTY * kTX / 2 threads.  Taller tiles stage fewer halo
+// cells per updated node and recompute fewer red nodes of the ring.
+#ifndef MHS_SWEEP_TILE_Y
+#define MHS_SWEEP_TILE_Y 16
+#endif
+constexpr int kSTY = MHS_SWEEP_TILE_Y;
+constexpr int kSThreads = kSTY * kTX / 2;
+static_assert(kSThreads % 64 == 0 && kSThreads <= 1024, "smoother workgroup size");
 // planes of HBM loads a marching kernel keeps in flight (register ring)
 constexpr int kDepth = MHS_RING_DEPTH;
 constexpr int kDepthF = MHS_RING_DEPTH_F; // with right-hand side or prolongation

@@ -162,8 +162,8 @@ __device__ __forceinline__ T interp2(Ptr ec, int ncx, int i, int j)
 // ============================================================================
 // 3D red-black Gauss-Seidel sweep, ping-pong (u_in -> u_out).
 //
-// A workgroup owns kTX x kTY interior nodes of `kz` consecutive planes.  It
-// stages a (kTY+4) x (kTX+4) window of each plane of u in LDS (five slots)
+// A workgroup owns kTX x kSTY interior nodes of `kz` consecutive planes.  It
+// stages a (kSTY+4) x (kTX+4) window of each plane of u in LDS (five slots)
 // and marches up in z: at step s it updates the red nodes of plane
 // s on the tile plus a one-node ring, then the black nodes of plane s-1 on
 // the tile, whose red neighbours (planes s-2, s-1, s) are all final by
@@ -184,22 +184,24 @@ __device__ __forceinline__ T interp2(Ptr ec, int ncx, int i, int j)
 // during the red phase, so staging a plane only adds the x interpolation.
 // ============================================================================
 constexpr int kWX = kTX + 4;
-constexpr int kWY = kTY + 4;
+constexpr int kWY = kSTY + 4;
 constexpr int kWCells = kWX * kWY;
 // LDS rows store even columns first, then odd columns, so the colour phases
 // (which touch every other column) read consecutive doubles: no bank conflicts
 constexpr int kHalf = kWX / 2;
 __device__ __forceinline__ int sx(int c) { return (c & 1) * kHalf + (c >> 1); }
 static_assert(kWX % 2 == 0, "window width must be even");
-constexpr int kWPer = (kWCells + kThreads - 1) / kThreads;
+constexpr int kWPer = (kWCells + kSThreads - 1) / kSThreads;
 constexpr int kRedPerRow = kTX / 2 + 1;
 constexpr int kBlackPerRow = kTX / 2;
-constexpr int kOwn = kTY * kTX / kThreads;
+constexpr int kOwn = kSTY * kTX / kSThreads;
 constexpr int kCWX = kTX / 2 + 4;
-constexpr int kCWY = kTY / 2 + 4;
+constexpr int kCWY = kSTY / 2 + 4;
 constexpr int kCCells = 2 * kCWX * kCWY;
-constexpr int kCPer = (kCCells + kThreads - 1) / kThreads;
-static_assert(kTY * kTX % kThreads == 0, "tile must be a multiple of the block");
+constexpr int kCPer = (kCCells + kSThreads - 1) / kSThreads;
+static_assert(kSTY * kTX % kSThreads == 0, "tile must be a multiple of the block");
+static_assert((kSTY + 2) * kRedPerRow <= 2 * kSThreads, "at most two red nodes of the ring per thread");
+static_assert(kWY * kCWX <= 2 * kSThreads, "at most two z-y interpolation entries per thread");
 
 
 // Per-plane coefficients of planes base .. base+63, one plane per lane of
@@ -243,7 +245,7 @@ __device__ __forceinline__ uint32_t pick(uint32_t a, uint32_t b, int flag)
 constexpr int kNone = 0xffff; // "no node" marker in a packed index
 
 template <typename T, int FLAGS>
-__global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelItem *__restrict__ items, int nitems)
+__global__ __launch_bounds__(kSThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelItem *__restrict__ items, int nitems)
 {
     constexpr bool HAS_F = (FLAGS & kHasF) != 0;
     constexpr bool ZERO_IN = (FLAGS & kZeroIn) != 0;
@@ -290,7 +292,7 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     // prolongation: the coarse correction interpolated in z and y onto every
     // fine row of the window, at coarse columns (x interpolation at staging)
     __shared__ T ZW[PROLONG ? kWY * kCWX + 1 : 1];
-    __shared__ double red[kThreads / 64];
+    __shared__ double red[kSThreads / 64];
     auto sxp = [](int c) { return (c & 1) * HP + (c >> 1); };
 
     const int tile = xcd_tile();
@@ -310,7 +312,7 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     local /= it->ntx;
     const int ty = local % it->nty;
     const int tz = local / it->nty;
-    const int i0 = 1 + tx * kTX, j0 = 1 + ty * kTY;
+    const int i0 = 1 + tx * kTX, j0 = 1 + ty * kSTY;
     const int kb = 1 + tz * kz;
     const int ke = min(kb + kz, nz - 1);
     const int ptop = min(ke + 1, nz - 1); // highest plane read
@@ -329,7 +331,7 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     uint32_t st_in = 0, st_int = 0, st_odd = 0;
 #pragma unroll
     for (int r = 0; r < kWPer; ++r) {
-        const int e = tid + r * kThreads;
+        const int e = tid + r * kSThreads;
         const int ee = min(e, kWCells - 1);
         const int w = ee / kWX, c = ee - w * kWX;
         const int i = i0 - 2 + c, j = j0 - 2 + w;
@@ -339,7 +341,7 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
         if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2) st_int |= 1u << r;
         if (i & 1) st_odd |= 1u << r;
     }
-    // coarse-window cells (two coarse planes; LDS index tid + r * kThreads)
+    // coarse-window cells (two coarse planes; LDS index tid + r * kSThreads)
     // and the z-y interpolation entries this thread computes
     uint32_t cw_g[PROLONG ? kCPer : 1];
     uint32_t cw_hi = 0;
@@ -347,7 +349,7 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     if constexpr (PROLONG) {
 #pragma unroll
         for (int r = 0; r < kCPer; ++r) {
-            const int e = min(tid + r * kThreads, kCCells - 1);
+            const int e = min(tid + r * kSThreads, kCCells - 1);
             const int pl = e / kCPlane;
             const int rem = e - pl * kCPlane;
             const int w = rem / kCWX, c = rem - w * kCWX;
@@ -358,7 +360,7 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
         int src[2];
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
-            const int e = tid + r * kThreads;
+            const int e = tid + r * kSThreads;
             const int ee = min(e, kWY * kCWX - 1);
             const int w = ee / kCWX, lc = ee - w * kCWX;
             const int j = j0 - 2 + w;
@@ -377,13 +379,13 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     for (int ps = 0; ps < 2; ++ps) {
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
-            const int e = tid + r * kThreads;
-            const int ee = min(e, (kTY + 2) * kRedPerRow - 1);
+            const int e = tid + r * kSThreads;
+            const int ee = min(e, (kSTY + 2) * kRedPerRow - 1);
             const int w = 1 + ee / kRedPerRow;
             const int q = ee - (w - 1) * kRedPerRow;
             const int c = 1 + ((ps + w) & 1) + 2 * q;
             const int i = i0 - 2 + c, j = j0 - 2 + w;
-            const bool ok = e < (kTY + 2) * kRedPerRow && i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2;
+            const bool ok = e < (kSTY + 2) * kRedPerRow && i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2;
             const uint32_t v = ok ? pk16(w * RW + sxp(c), w * RW + sxp(c - 1)) : pk16(kTrash, kTrash - 1);
             if (ps)
                 rd1[r] = v;
@@ -395,7 +397,7 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     // black nodes of the tile (one per thread) for each plane parity
     uint32_t bk0 = 0, bk1 = 0;
     uint32_t bf[2]; // [plane parity]: byte offset of the black node's f (clamped)
-    static_assert(kTY * kBlackPerRow == kThreads, "one black node per thread");
+    static_assert(kSTY * kBlackPerRow == kSThreads, "one black node per thread");
     {
 #pragma unroll
         for (int ps = 0; ps < 2; ++ps) {
@@ -420,7 +422,7 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     {
 #pragma unroll
         for (int q = 0; q < kOwn; ++q) {
-            const int e = tid + q * kThreads;
+            const int e = tid + q * kSThreads;
             const int w = 2 + e / kTX, c = 2 + e % kTX;
             const int i = i0 + c - 2, j = j0 + w - 2;
             ow[q] = pk16(w * RW + sxp(c), w * RW + sxp(c - 1));
@@ -432,10 +434,10 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
         }
     }
     const int par0 = (i0 + j0 + 1) & 1; // red parity of plane s is (par0 + s) & 1
-    // waves holding a second red node (red nodes tid + kThreads exist for
-    // tid < (kTY + 2) kRedPerRow - kThreads); uniform per wave
+    // waves holding a second red node (red nodes tid + kSThreads exist for
+    // tid < (kSTY + 2) kRedPerRow - kSThreads); uniform per wave
     const bool two_red =
-        __builtin_amdgcn_readfirstlane(tid) < (kTY + 2) * kRedPerRow - kThreads;
+        __builtin_amdgcn_readfirstlane(tid) < (kSTY + 2) * kRedPerRow - kSThreads;
     // f offsets by plane class: class 0 = planes kb-1, kb+1, ...; class 1 =
     // planes kb, kb+2, ... (every step of the march knows its planes' class
     // at compile time)
@@ -510,7 +512,7 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     auto store_cw = [&](const T(&csrc)[PROLONG ? kCPer : 1]) {
         if constexpr (PROLONG) {
 #pragma unroll
-            for (int r = 0; r < kCPer; ++r) CW[min(tid + r * kThreads, kCCells)] = csrc[r];
+            for (int r = 0; r < kCPer; ++r) CW[min(tid + r * kSThreads, kCCells)] = csrc[r];
         }
     };
     // z-y interpolation of the staged coarse planes for fine plane p
@@ -530,7 +532,7 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
                         const T y1 = oj ? h * (a1 + CW[kCPlane * (kCWPlanes - 1) + a + kCWX]) : a1;
                         v = h * (y0 + y1);
                     }
-                    ZW[(zw_ok >> r) & 1 ? tid + r * kThreads : kWY * kCWX] = v;
+                    ZW[(zw_ok >> r) & 1 ? tid + r * kSThreads : kWY * kCWX] = v;
                 }
             }
         }
@@ -743,7 +745,7 @@ __global__ __launch_bounds__(kThreads) MHS_SWEEP_ATTR void k_sweep3(const LevelI
     lds_barrier();
     if (ke - 1 >= kb) write_plane(ke - 1, (ke - kb + 1) % kSlots);
     if constexpr (NORM) {
-        const double tot = block_sum<kThreads>(acc, red);
+        const double tot = block_sum<kSThreads>(acc, red);
         if (tid == 0) gout<double>(it->partials)[tile - it->tile_base] = tot;
     }
 }
@@ -2039,7 +2041,7 @@ __global__ __launch_bounds__(256) void k_copy(const double *__restrict__ src, do
 template <typename T>
 hipError_t sweep3_dispatch(const LevelItem *items, int nitems, int ntiles, int flags, hipStream_t s)
 {
-    dim3 grid(ntiles), block(kThreads);
+    dim3 grid(ntiles), block(kSThreads);
     switch (flags & 15) {
 #define MHS_CASE(F)                                                                      \
     case F:                                                                              \

@@ -34,7 +34,9 @@ struct Level {
     int zs = 0;            // xi of plane k is xi[k << zs] of the finest grid
     bool keepz = false;    // the step to level+1 halves x and y only
     bool keepxy = false;   // the step to level+1 halves z only
+    int ity = 0;           // refinement-step tiles in y (kTY rows; the smoother's are kSTY)
     int sweep_tiles() const { return st[0] * st[1] * st[2]; }
+    int ir_tiles() const { return st[0] * ity * st[2]; }
     int restrict_tiles() const { return rt[0] * rt[1] * rt[2]; }
 };
 
