@@ -120,6 +120,9 @@ def _short_kernel(name):
 # floats)
 SMOOTH_L0_MIX = {"k_sweep3<float, 3>": (1, 8.0), "k_sweep3<float, 1>": (2, 12.0), "k_sweep3<float, 9>": (1, 12.5)}
 COPY_BYTES = 1 << 30
+# workgroups of a one-request level-0 smoother launch at 257^3: 4 x 16 tiles
+# of 64 x 16 nodes per plane, 8 chunks of 32 planes
+SMOOTH_L0_GROUPS_257 = 512
 
 
 def counter_probe(batch=12, requests=24):
@@ -164,7 +167,7 @@ def counter_probe(batch=12, requests=24):
     print("counter probe done", flush=True)
 
 
-def summarize_counters(fetch_csv, write_csv, one_groups=1024):
+def summarize_counters(fetch_csv, write_csv, one_groups=SMOOTH_L0_GROUPS_257):
     """HBM traffic of the level-0 FP32 smoother from the two counter runs of
     counter_probe, each counter scaled by what it reads for the calibration
     copy.  A launch of the smoother covering k requests of the 257^3
@@ -249,14 +252,18 @@ def summarize_counters(fetch_csv, write_csv, one_groups=1024):
     print(f"merged_traffic_ratio: {meas / alg:.4f}")
 
 
-def _level0_split(launches):
+def _level0_split(launches, one_groups):
     """Pick the level-0 launches among launches of the smoother: (start,
     end, kernel, groups) tuples.  Within one kernel variant and workgroup
     count (equal requests per launch), level-0 launches take several times
     longer than level-1 launches and launches whose items all exited at once
     take a few microseconds (about 1 us per 1024 workgroups): the level-0
     launches are those above the largest duration ratio between neighbours
-    among the launches longer than 3 us per 1024 workgroups (at least 5 us)."""
+    among the launches longer than 3 us per 1024 workgroups (at least 5 us).
+    Where the durations form one cluster (merged launches, whose level-1
+    launches have other workgroup counts), the cluster is level 0 if its
+    median takes at least 15 us per request (a level-0 FP32 sweep of one
+    257^3 request takes 25-55 us, a level-1 sweep under 10 us)."""
     import collections
 
     by = collections.defaultdict(list)
@@ -271,13 +278,16 @@ def _level0_split(launches):
         d = [x[1] - x[0] for x in v]
         gaps = [d[i + 1] / d[i] for i in range(len(d) - 1)]
         if not gaps or max(gaps) < 1.8:
-            continue  # one cluster: no level-0 / level-1 split to make
+            # one cluster: no level-0 / level-1 split to make
+            if d[len(d) // 2] >= 15000.0 * max(1, g // one_groups):
+                out.extend(v)
+            continue
         cut = gaps.index(max(gaps)) + 1
         out.extend(v[cut:])
     return sorted(out)
 
 
-def summarize_trace(stats_csv, trace_csv, marker_csv=None, one_groups=1024, top=24):
+def summarize_trace(stats_csv, trace_csv, marker_csv=None, one_groups=SMOOTH_L0_GROUPS_257, top=24):
     """Kernel-time summary of a rocprofv3 --kernel-trace --stats (and
     --marker-trace) run of bench.py: the stats table; the launches that ran
     (> 5 us; launches issued after a solve converged exit at once) by
@@ -322,7 +332,7 @@ def summarize_trace(stats_csv, trace_csv, marker_csv=None, one_groups=1024, top=
     def table(sel, title):
         print()
         print(title)
-        l0 = _level0_split(sel)
+        l0 = _level0_split(sel, one_groups)
         by = collections.defaultdict(list)
         for t0, t1, kn, g in l0:
             by[(kn, g // one_groups)].append((t1 - t0) / 1e3)
