@@ -1,7 +1,8 @@
 """Kernel-level parity: each HIP stage against the oracle's same operation.
 
-Shapes span several tiles with ragged edges in every axis (tiles are 64 x 8
-x 32 nodes for the smoother, 32 x 8 x 16 coarse nodes for the restriction).
+Shapes span several tiles with ragged edges in every axis (tiles are 64 x 16
+x 32 nodes for the smoother, 64 x 8 x 32 for the refinement step, 32 x 8 x 16
+coarse nodes for the restriction).
 Tolerances: FP64 stages agree to rounding (1e-13 relative); FP32 stages are
 compared with the FP64 oracle at 1e-5 relative.
 """
