@@ -62,8 +62,16 @@ constexpr int kCY = 8;
 constexpr int kKC = 16;
 // 2D smoother: kTX x kTY2 interior nodes per workgroup.
 constexpr int kTY2 = 16;
-// field recovery: kTX x kFY nodes per workgroup, marching kKZ planes.
-constexpr int kFY = 8;
+// field recovery: kTX x kFY nodes per workgroup of kFThreads threads (four
+// nodes per thread), marching kKZ planes.
+#ifndef MHS_FIELDS_TILE_Y
+#define MHS_FIELDS_TILE_Y 16
+#endif
+#ifndef MHS_FIELDS_THREADS
+#define MHS_FIELDS_THREADS 256
+#endif
+constexpr int kFY = MHS_FIELDS_TILE_Y;
+constexpr int kFThreads = MHS_FIELDS_THREADS;
 // bottom solver: one workgroup per item.
 constexpr int kBottomThreads = 1024;
 // largest coarsest-grid system solved by the dense inverse

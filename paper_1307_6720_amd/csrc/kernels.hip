@@ -1559,18 +1559,18 @@ constexpr int kFPY = kFY + 4;
 constexpr int kFBX = kTX + 2;
 constexpr int kFBY = kFY + 2;
 constexpr int kFCells = kFPX * kFPY;
-constexpr int kFPer = (kFCells + kThreads - 1) / kThreads;
+constexpr int kFPer = (kFCells + kFThreads - 1) / kFThreads;
 constexpr int kDepthFields = 2; // P planes of loads in flight
 
-__global__ __launch_bounds__(kThreads) void k_fields(const FieldsItem *__restrict__ items, int nitems)
+__global__ __launch_bounds__(kFThreads) void k_fields(const FieldsItem *__restrict__ items, int nitems)
 {
     constexpr int D = kDepthFields;
     constexpr int PSLOT = kFPY * kFPX;
     constexpr int BSLOT = kFBY * kFBX;
     constexpr int kBCells = kFBY * kFBX;
-    constexpr int kBPer = (kBCells + kThreads - 1) / kThreads;
-    constexpr int kOut = kFY * kTX / kThreads;
-    static_assert(kFY * kTX % kThreads == 0, "whole output nodes per thread");
+    constexpr int kBPer = (kBCells + kFThreads - 1) / kFThreads;
+    constexpr int kOut = kFY * kTX / kFThreads;
+    static_assert(kFY * kTX % kFThreads == 0, "whole output nodes per thread");
     __shared__ double SP[4 * PSLOT];
     __shared__ double SB[3 * BSLOT];
     const int tile = xcd_tile();
@@ -1605,7 +1605,7 @@ __global__ __launch_bounds__(kThreads) void k_fields(const FieldsItem *__restric
     uint32_t st_in = 0;
 #pragma unroll
     for (int r = 0; r < kFPer; ++r) {
-        const int e = tid + r * kThreads;
+        const int e = tid + r * kFThreads;
         const int ee = min(e, kFCells - 1);
         const int w = ee / kFPX, c = ee - w * kFPX;
         const int i = i0 - 2 + c, j = j0 - 2 + w;
@@ -1618,7 +1618,7 @@ __global__ __launch_bounds__(kThreads) void k_fields(const FieldsItem *__restric
     uint32_t bz_int = 0;
 #pragma unroll
     for (int r = 0; r < kBPer; ++r) {
-        const int e = tid + r * kThreads;
+        const int e = tid + r * kFThreads;
         const int ee = min(e, kBCells - 1);
         const int w = ee / kFBX, c = ee - w * kFBX;
         const int i = i0 - 1 + c, j = j0 - 1 + w;
@@ -1632,7 +1632,7 @@ __global__ __launch_bounds__(kThreads) void k_fields(const FieldsItem *__restric
     uint32_t o_int = 0;
 #pragma unroll
     for (int q = 0; q < kOut; ++q) {
-        const int e = tid + q * kThreads;
+        const int e = tid + q * kFThreads;
         const int i = min(i0 + e % kTX, nx - 1), j = min(j0 + e / kTX, ny - 1);
         const int w = j - j0, c = i - i0;
         o_i[q] = pk16((w + 2) * kFPX + (c + 2), (w + 1) * kFBX + (c + 1));
@@ -2205,7 +2205,7 @@ hipError_t launch_finalize(const FinalizeItem *items, int nitems, hipStream_t s)
 hipError_t launch_fields(const FieldsItem *items, int nitems, int ntiles, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fields, dim3(ntiles), dim3(kThreads), 0, s, items, nitems);
+    hipLaunchKernelGGL(k_fields, dim3(ntiles), dim3(kFThreads), 0, s, items, nitems);
     return hipGetLastError();
 }
 
