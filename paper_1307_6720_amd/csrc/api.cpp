@@ -902,8 +902,8 @@ FieldsItem fields_item(const mhs_plan *p, const mhs_model *model, const double *
     fi.nx = nx;
     fi.ny = ny;
     fi.nz = nz;
-    fi.ntx = ceil_div(nx, kTX);
-    fi.nty = ceil_div(ny, kFY);
+    fi.ntx = ceil_div(nx - 2, kTX); // interior tiles; edge tiles write the side faces
+    fi.nty = ceil_div(ny - 2, kFY);
     fi.kz = chunk(nz, fi.ntx * fi.nty, kKZ, kFieldsTargetGroups);
     fi.ntz = ceil_div(nz, fi.kz);
     fi.tile_base = 0;

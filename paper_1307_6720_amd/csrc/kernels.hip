@@ -1547,7 +1547,9 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const FinalizeItem *__res
 
 // ============================================================================
 // Field recovery (Section 2.2): B by central differences of P, p and rho from
-// (9) and (10).  A workgroup owns kTX x kFY nodes of `kz` planes; P planes
+// (9) and (10).  A workgroup owns kTX x kFY interior nodes of `kz` planes
+// (workgroups at the array edge also write the side-face nodes next to their
+// tile, whose values need no differences); P planes
 // are staged in LDS with a two-node halo (four planes resident, the next ones
 // prefetched into a register ring) and Bz planes with a one-node halo (three
 // resident).  At step m the workgroup forms Bz on plane m+1, then writes all
@@ -1583,7 +1585,7 @@ __global__ __launch_bounds__(kFThreads) void k_fields(const FieldsItem *__restri
     local /= it->ntx;
     const int ty = local % it->nty;
     const int tz = local / it->nty;
-    const int i0 = tx * kTX, j0 = ty * kFY;
+    const int i0 = 1 + tx * kTX, j0 = 1 + ty * kFY;
     const int kb = tz * kz;
     const int ke = min(kb + kz, nz);
     const size_t sxy = (size_t)nx * ny;
@@ -1625,19 +1627,51 @@ __global__ __launch_bounds__(kFThreads) void k_fields(const FieldsItem *__restri
         bz_i[r] = pk16(e < kBCells ? ee : kNone, (w + 1) * kFPX + (c + 1));
         if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2) bz_int |= 1u << r;
     }
-    // output nodes: nodes past the array edge are redirected to the nearest
-    // edge node, which they recompute identically, so every lane stores
+    // output nodes: nodes past the interior are redirected to the nearest
+    // interior node, which they recompute identically, so every lane stores
     uint32_t o_i[kOut];
     uint32_t o_g[kOut];
     uint32_t o_int = 0;
 #pragma unroll
     for (int q = 0; q < kOut; ++q) {
         const int e = tid + q * kFThreads;
-        const int i = min(i0 + e % kTX, nx - 1), j = min(j0 + e / kTX, ny - 1);
+        const int i = min(i0 + e % kTX, nx - 2), j = min(j0 + e / kTX, ny - 2);
         const int w = j - j0, c = i - i0;
         o_i[q] = pk16((w + 2) * kFPX + (c + 2), (w + 1) * kFBX + (c + 1));
         o_g[q] = (uint32_t)(i + nx * j);
         if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2) o_int |= 1u << q;
+    }
+    // side-face nodes next to the tile (at most one per thread): the x faces
+    // over the tile's rows extended to the y faces, then the y faces over the
+    // tile's columns.  B = 0 there, so p = p_b and rho = rho_b.
+    static_assert(2 * (kFY + 2) + 2 * kTX <= kFThreads, "one face node per thread");
+    uint32_t f_g = 0;
+    bool f_ok = false;
+    {
+        const bool xlo = tx == 0, xhi = tx == it->ntx - 1, ylo = ty == 0, yhi = ty == it->nty - 1;
+        const int jb = ylo ? 0 : j0, je = yhi ? ny - 1 : j0 + kFY - 1; // rows of the x faces
+        const int ie = min(i0 + kTX - 1, nx - 2);                      // last interior column
+        const int nxf = je - jb + 1, nyf = ie - i0 + 1;
+        int e = tid, fi = -1, fj = -1;
+        if (xlo) {
+            if (e < nxf) fi = 0, fj = jb + e;
+            e -= nxf;
+        }
+        if (xhi && fi < 0) {
+            if (e >= 0 && e < nxf) fi = nx - 1, fj = jb + e;
+            e -= nxf;
+        }
+        if (ylo && fi < 0) {
+            if (e >= 0 && e < nyf) fi = i0 + e, fj = 0;
+            e -= nyf;
+        }
+        if (yhi && fi < 0) {
+            if (e >= 0 && e < nyf) fi = i0 + e, fj = ny - 1;
+        }
+        if (fi >= 0) {
+            f_ok = true;
+            f_g = (uint32_t)(fi + nx * fj);
+        }
     }
 
     double pre[D][kFPer];
@@ -1745,6 +1779,14 @@ __global__ __launch_bounds__(kFThreads) void k_fields(const FieldsItem *__restri
                 oBz[idx] = bz;
                 op[idx] = p;
                 orho[idx] = rho;
+            }
+            if (f_ok) {
+                const size_t idx = (size_t)f_g + sxy * (size_t)m;
+                oBx[idx] = 0.0;
+                oBy[idx] = 0.0;
+                oBz[idx] = 0.0;
+                op[idx] = pb;
+                orho[idx] = rhob;
             }
             // P(m+2) replaces the slot of plane m-2, last read a step ago
             if (m + 2 >= q0 + 3) stash(m + 2, pre[d]);
