@@ -1347,7 +1347,7 @@ int mhs_solve_interior(mhs_plan *p, const mhs_model *model, double *d_P, const m
         }
         if (!cyc.ok || !d_state || !d_prep) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
         if ((st = flush_staging(p, s))) return st;
-        HIPCHK(launch_prep3(d_prep, 1, N, s));
+        HIPCHK(launch_prep3(d_prep, 1, prep3_threads(N), s));
         if ((st = drive(p, cyc, d_state, o, &fin, &syncs, s))) return st;
     } else {
         // FP64 iterative refinement around FP32 V-cycles.  Step 0 only
@@ -1372,7 +1372,7 @@ int mhs_solve_interior(mhs_plan *p, const mhs_model *model, double *d_P, const m
         if (!first.ok || !odd.ok || !even.ok || !inner.ok || !d_state || !d_prep)
             return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
         if ((st = flush_staging(p, s))) return st;
-        HIPCHK(launch_prep3(d_prep, 1, N, s));
+        HIPCHK(launch_prep3(d_prep, 1, prep3_threads(N), s));
         int launched = 0;
         SolveState ss{};
         for (;;) {

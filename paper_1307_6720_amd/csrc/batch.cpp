@@ -251,7 +251,7 @@ bool build_slot(const Slot &S, int i, SolveState *state, Staging &R, std::vector
             Launch L{};
             L.kind = Launch::kPrep3;
             L.items = d;
-            L.n = N;
+            L.n = prep3_threads(N); // threads (base of the merged launch counts threads)
             tag_one(L, key_of(0, kPrologue, 0), i, out);
         }
         if (o.precision == MHS_PREC_FP64) {

@@ -225,6 +225,9 @@ hipError_t launch_finalize(const FinalizeItem *items, int nitems, hipStream_t s)
 hipError_t launch_fields(const FieldsItem *items, int nitems, int ntiles, hipStream_t s);
 hipError_t launch_diag(const DiagItem &item, hipStream_t s);
 hipError_t launch_trace(const TraceItem &item, hipStream_t s);
+// 3D preparation: nodes per thread, and the threads an item of n nodes takes
+constexpr int kPrepNodes = 4;
+inline int64_t prep3_threads(int64_t n) { return (n + kPrepNodes - 1) / kPrepNodes; }
 hipError_t launch_prep3(const PrepItem *items, int nitems, int64_t nthreads, hipStream_t s);
 hipError_t launch_prep2(const PrepItem *items, int nitems, int64_t nthreads, hipStream_t s);
 hipError_t launch_copy(const double *src, double *dst, int64_t n, const SolveState *skip,

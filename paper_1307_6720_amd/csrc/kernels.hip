@@ -2036,23 +2036,37 @@ __global__ __launch_bounds__(256) void k_prep3(const PrepItem *__restrict__ item
 {
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const PrepItem &it = items[find_prep(items, nitems, g)];
-    const int64_t e = g - it.base;
-    if (e >= it.n) return;
+    const int64_t e0 = (g - it.base) * kPrepNodes;
+    if (e0 >= it.n) return;
     const int nx = it.nx, ny = it.ny, nz = it.nz;
-    // 32-bit index arithmetic (a plan's grids have fewer than 2^31 nodes)
-    const uint32_t e32 = (uint32_t)e, r = e32 / (uint32_t)nx;
-    const int i = (int)(e32 - r * (uint32_t)nx);
+    // kPrepNodes consecutive nodes per thread: the divisions for the first,
+    // then stepping along x (32-bit index arithmetic: a plan's grids have
+    // fewer than 2^31 nodes)
+    const uint32_t e32 = (uint32_t)e0, r = e32 / (uint32_t)nx;
+    int i = (int)(e32 - r * (uint32_t)nx);
     const uint32_t kk = r / (uint32_t)ny;
-    const int j = (int)(r - kk * (uint32_t)ny), k = (int)kk;
-    const bool side = (i == 0 || i == nx - 1 || j == 0 || j == ny - 1);
-    if (k == 0) {
-        if (side && !it.faces) it.P[e] = 0.0;
-        if (it.twin) it.twin[e] = (side && !it.faces) ? 0.0 : it.P[e];
-    } else if (side || k == nz - 1) {
-        if (!it.faces) it.P[e] = 0.0;
-        if (it.twin) it.twin[e] = it.faces ? it.P[e] : 0.0;
-    } else if (!it.warm) {
-        it.P[e] = 0.0;
+    int j = (int)(r - kk * (uint32_t)ny), k = (int)kk;
+#pragma unroll
+    for (int q = 0; q < kPrepNodes; ++q) {
+        const int64_t e = e0 + q;
+        if (e >= it.n) break;
+        const bool side = (i == 0 || i == nx - 1 || j == 0 || j == ny - 1);
+        if (k == 0) {
+            if (side && !it.faces) it.P[e] = 0.0;
+            if (it.twin) it.twin[e] = (side && !it.faces) ? 0.0 : it.P[e];
+        } else if (side || k == nz - 1) {
+            if (!it.faces) it.P[e] = 0.0;
+            if (it.twin) it.twin[e] = it.faces ? it.P[e] : 0.0;
+        } else if (!it.warm) {
+            it.P[e] = 0.0;
+        }
+        if (++i == nx) {
+            i = 0;
+            if (++j == ny) {
+                j = 0;
+                ++k;
+            }
+        }
     }
 }
 
