@@ -411,8 +411,9 @@ def serve_leg(a, torch, dev):
         p.close()
     del outs
 
-    be = DeviceBackend(max_slots=a.serve_slots, device=dev)
-    srv = Server(be, int(a.serve_budget_gb * (1 << 30)))
+    budget = int(a.serve_budget_gb * (1 << 30))
+    be = DeviceBackend(max_slots=a.serve_slots, device=dev, hbm_budget=budget)
+    srv = Server(be, budget)
 
     def stream(arrivals):
         reqs = [Request(id=i, dims=(w.grid.nx, w.grid.ny, w.grid.nz), model=w.model, bz0=bz,

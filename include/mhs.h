@@ -127,6 +127,13 @@ const char *mhs_last_error(void);
  * (MHS_ERR_GRID for a bad axis). */
 int mhs_workspace_bytes(const mhs_grid *grid, int32_t precisions, size_t *bytes);
 
+/* Device memory one request of `grid` holds while it is served: the plan's
+ * workspace (mhs_workspace_bytes for `precisions`) plus its arrays, bz0
+ * (nx*ny doubles), P and the five field outputs (6*nx*ny*nz doubles).  The
+ * batch counts this against its budget at admission (mhs_batch_create).
+ * Errors: MHS_ERR_INVALID_ARG, MHS_ERR_GRID. */
+int mhs_request_bytes(const mhs_grid *grid, int32_t precisions, size_t *bytes);
+
 /* Host-only check of a model against a grid (no device work).  Every
  * interior plane must have xi < 1 (ellipticity of (8), Section 2.1) and
  * alpha^2 must lie below the smallest eigenvalue lambda_0 of
@@ -209,10 +216,14 @@ int mhs_fields(mhs_plan *plan, const mhs_model *model, const double *d_P, double
  * the same kernels as the solves. */
 
 /* u <- nsweeps red-black Gauss-Seidel sweeps on A u = f (f may be NULL:
- * zero).  Red = (i+j+k) even, updated first. */
+ * zero).  Red = (i+j+k) even, updated first.  zero_guess = 1: the first
+ * sweep starts from u = 0 (the start of a coarse-grid correction, whose
+ * Dirichlet data are zero): the interior values of u are not read, and its
+ * boundary values, which later sweeps read, must be 0.  zero_guess must be
+ * 0 or 1, and 1 needs f. */
 int mhs_stage_smooth(mhs_plan *plan, const mhs_model *model, int32_t space, int32_t level,
                      int32_t precision, void *d_u, const void *d_f, int32_t nsweeps,
-                     void *stream);
+                     int32_t zero_guess, void *stream);
 
 /* f_c <- full weighting of r = f - A u (r = 0 on boundary nodes) onto the
  * interior nodes of level+1; boundary nodes of f_c are not written. */
@@ -327,8 +338,13 @@ int mhs_profile_read(mhs_plan *plan, int32_t klass, double *total_ms, int64_t *l
  * Memory: the batch holds per-slot status words and its launch-descriptor
  * tables in a caller-provided device workspace of
  * mhs_batch_workspace_bytes(max_slots) bytes (256-byte aligned); each slot
- * uses its own plan's workspace for everything else.  Admission policy
- * (memory budget, queueing, plan pooling) belongs to the caller.
+ * uses its own plan's workspace for everything else.  Admission by HBM
+ * footprint: a batch created with an hbm_budget admits a request only while
+ * the footprints (mhs_request_bytes) of the requests it holds, this one
+ * included, stay within that budget; a request holds its footprint from
+ * admission until mhs_batch_release.  The batch allocates none of that
+ * memory (the caller does, before admission); queueing requests that do
+ * not fit and pooling plans between requests belong to the caller.
  * A batch is used from one host thread.  Ticks are pipelined two deep:
  * mhs_batch_step launches tick t and then reads the status of tick t-1
  * while the device works on tick t, so a request's completion is seen one
@@ -341,10 +357,14 @@ typedef struct mhs_batch mhs_batch;
 int mhs_batch_workspace_bytes(int32_t max_slots, size_t *bytes);
 
 /* Create a batch on the current device over d_ws (owned by the caller,
- * kept until mhs_batch_destroy).  Allocates host structures and pinned
- * status/descriptor buffers only. */
-int mhs_batch_create(int32_t max_slots, void *d_ws, size_t ws_bytes, mhs_batch **batch);
+ * kept until mhs_batch_destroy).  hbm_budget: bytes of device memory the
+ * admitted requests may hold together (0 = no limit; see Memory above).
+ * Allocates host structures and pinned status/descriptor buffers only. */
+int mhs_batch_create(int32_t max_slots, size_t hbm_budget, void *d_ws, size_t ws_bytes, mhs_batch **batch);
 int mhs_batch_destroy(mhs_batch *batch);
+
+/* Footprint (mhs_request_bytes) of the requests the batch holds now. */
+int mhs_batch_bytes_in_use(const mhs_batch *batch, size_t *bytes);
 
 /* Admit one request into a free slot.  The plan must be exclusive to this
  * slot until the slot is released (a plan already held by an active slot
@@ -356,8 +376,9 @@ int mhs_batch_destroy(mhs_batch *batch);
  * MHS_ERR_INDEFINITE.  opts->precision selects the interior path (the
  * boundary solve is always FP64); opts->rtol and max_cycles apply to both
  * solves; opts->check_every is ignored (every tick reads the status).
- * MHS_ERR_BUDGET: no free slot, or the request's per-tick descriptors
- * exceed the slot's share of the descriptor table (very large nu1, nu2 or
+ * MHS_ERR_BUDGET: no free slot, the request's footprint would take the
+ * batch over its hbm_budget, or the request's per-tick descriptors exceed
+ * the slot's share of the descriptor table (very large nu1, nu2 or
  * inner_cycles).  On success *slot is the slot index (0..max_slots-1). */
 int mhs_batch_admit(mhs_batch *batch, mhs_plan *plan, const mhs_model *model,
                     const double *d_bz0, double *d_P, double *d_Bx, double *d_By, double *d_Bz,

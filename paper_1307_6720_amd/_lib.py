@@ -88,6 +88,7 @@ def lib():
         "mhs_version": (i32, []),
         "mhs_last_error": (C.c_char_p, []),
         "mhs_workspace_bytes": (C.c_int, [P(Grid), i32, P(C.c_size_t)]),
+        "mhs_request_bytes": (C.c_int, [P(Grid), i32, P(C.c_size_t)]),
         "mhs_check_model": (C.c_int, [P(Grid), P(Model), P(dbl), P(i32)]),
         "mhs_plan_create": (C.c_int, [P(Grid), i32, vp, C.c_size_t, P(vp)]),
         "mhs_plan_destroy": (C.c_int, [vp]),
@@ -97,7 +98,7 @@ def lib():
         "mhs_solve_boundary": (C.c_int, [vp, vp, vp, P(Opts), P(Info), vp]),
         "mhs_solve_interior": (C.c_int, [vp, P(Model), vp, P(Opts), P(Info), vp]),
         "mhs_fields": (C.c_int, [vp, P(Model), vp, vp, vp, vp, vp, vp, vp]),
-        "mhs_stage_smooth": (C.c_int, [vp, P(Model), i32, i32, i32, vp, vp, i32, vp]),
+        "mhs_stage_smooth": (C.c_int, [vp, P(Model), i32, i32, i32, vp, vp, i32, i32, vp]),
         "mhs_stage_restrict": (C.c_int, [vp, P(Model), i32, i32, i32, vp, vp, vp, vp]),
         "mhs_stage_correct_smooth": (C.c_int, [vp, P(Model), i32, i32, i32, vp, vp, vp, vp]),
         "mhs_stage_bottom": (C.c_int, [vp, P(Model), i32, i32, vp, vp, i32, i32, P(i32), vp]),
@@ -109,7 +110,8 @@ def lib():
     }
     batch = {
         "mhs_batch_workspace_bytes": (C.c_int, [i32, P(C.c_size_t)]),
-        "mhs_batch_create": (C.c_int, [i32, vp, C.c_size_t, P(vp)]),
+        "mhs_batch_create": (C.c_int, [i32, C.c_size_t, vp, C.c_size_t, P(vp)]),
+        "mhs_batch_bytes_in_use": (C.c_int, [vp, P(C.c_size_t)]),
         "mhs_batch_destroy": (C.c_int, [vp]),
         "mhs_batch_admit": (C.c_int, [vp, vp, P(Model), vp, vp, vp, vp, vp, vp, vp, P(Opts), P(i32)]),
         "mhs_batch_step": (C.c_int, [vp, vp, P(i32)]),

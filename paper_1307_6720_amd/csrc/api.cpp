@@ -356,9 +356,6 @@ int coarse_inverse(const Hierarchy &h, const std::vector<double> &coef, double c
     return MHS_OK;
 }
 
-// Lower bound of the smallest eigenvalue of -[(1 - xi)(d2x + d2y) + d2z] on
-// level l: min_k (1 - xi_k) * lam_h + lam_z, each term the smallest Dirichlet
-// eigenvalue of its one-dimensional operator.
 // Smallest eigenvalue of -[(1 - xi(z)) (d2x + d2y) + d2z] on the interior
 // unknowns of level l (the operator of (8) without the alpha^2 term).  The
 // operator separates: an in-plane sine mode of eigenvalue lam turns it into
@@ -1144,6 +1141,17 @@ int mhs_workspace_bytes(const mhs_grid *grid, int32_t precisions, size_t *bytes)
     return MHS_OK;
 }
 
+int mhs_request_bytes(const mhs_grid *grid, int32_t precisions, size_t *bytes)
+{
+    if (!bytes) return fail(MHS_ERR_INVALID_ARG, "bytes is NULL");
+    size_t ws = 0;
+    const int st = mhs_workspace_bytes(grid, precisions, &ws);
+    if (st) return st;
+    const size_t n = (size_t)grid->nx * grid->ny * grid->nz;
+    *bytes = ws + 6 * sizeof(double) * n + sizeof(double) * (size_t)grid->nx * grid->ny;
+    return MHS_OK;
+}
+
 int mhs_check_model(const mhs_grid *grid, const mhs_model *model, double *lambda_min, int32_t *levels)
 {
     int st = check_grid(grid);
@@ -1632,14 +1640,16 @@ int release_twin(Hierarchy &h, int level, int path, hipStream_t s)
 extern "C" {
 
 int mhs_stage_smooth(mhs_plan *p, const mhs_model *model, int32_t space, int32_t level, int32_t precision,
-                     void *d_u, const void *d_f, int32_t nsweeps, void *stream)
+                     void *d_u, const void *d_f, int32_t nsweeps, int32_t zero_guess, void *stream)
 {
     hipStream_t s = (hipStream_t)stream;
     Hierarchy *h = nullptr;
     int path = 0;
     int st = stage_common(p, model, space, level, precision, &h, &path, s);
     if (st) return st;
-    if (!d_u || nsweeps < 1) return fail(MHS_ERR_INVALID_ARG, "bad u or nsweeps");
+    if (!d_u || nsweeps < 1 || (zero_guess != 0 && zero_guess != 1))
+        return fail(MHS_ERR_INVALID_ARG, "bad u, nsweeps or zero_guess");
+    if (zero_guess && !d_f) return fail(MHS_ERR_INVALID_ARG, "a sweep from a zero guess needs f");
     void *tw = stage_twin(*h, level, path);
     if (!tw || level >= h->b) return fail(MHS_ERR_UNSUPPORTED, "level %d is handled by the bottom solver", level);
     if (path == kF32 && level == 0) tw = h->lv[0].t[kF32];
@@ -1650,7 +1660,9 @@ int mhs_stage_smooth(mhs_plan *p, const mhs_model *model, int32_t space, int32_t
     Program pg;
     void *cur = d_u, *oth = tw;
     for (int q = 0; q < nsweeps; ++q) {
-        add_sweep(pg, p->stage, *h, level, path, cur, oth, d_f, nullptr, 0, nullptr, nullptr);
+        const bool zero = q == 0 && zero_guess;
+        add_sweep(pg, p->stage, *h, level, path, zero ? nullptr : cur, oth, d_f, nullptr, zero ? kZeroIn : 0, nullptr,
+                  nullptr);
         std::swap(cur, oth);
     }
     if (!pg.ok) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");

@@ -51,6 +51,7 @@ struct Slot {
     // request (admission does not touch the device)
     ModelUpload up;
     bool upload_pending = false;
+    size_t bytes = 0; // device footprint counted against the batch's budget
 };
 
 // One launch of one request's program with its merge key.
@@ -149,6 +150,8 @@ struct Tick {
 struct mhs_batch {
     int max_slots = 0;
     int device = 0;
+    size_t budget = 0;  // HBM budget of the admitted requests (0 = none)
+    size_t in_use = 0;  // footprint of the slots not yet released
     SolveState *d_states = nullptr; // per slot, in the workspace
     Tick ticks[2];
     int64_t tick_no = 0;            // ticks launched
@@ -425,7 +428,7 @@ int mhs_batch_workspace_bytes(int32_t max_slots, size_t *bytes)
     return MHS_OK;
 }
 
-int mhs_batch_create(int32_t max_slots, void *d_ws, size_t ws_bytes, mhs_batch **out)
+int mhs_batch_create(int32_t max_slots, size_t hbm_budget, void *d_ws, size_t ws_bytes, mhs_batch **out)
 {
     if (!out) return fail(MHS_ERR_INVALID_ARG, "batch output is NULL");
     *out = nullptr;
@@ -437,6 +440,7 @@ int mhs_batch_create(int32_t max_slots, void *d_ws, size_t ws_bytes, mhs_batch *
     if (ws_bytes < need) return fail(MHS_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
     mhs_batch *b = new mhs_batch();
     b->max_slots = max_slots;
+    b->budget = hbm_budget;
     b->slots.resize((size_t)max_slots);
     if (hipGetDevice(&b->device) != hipSuccess) {
         delete b;
@@ -501,6 +505,11 @@ int mhs_batch_admit(mhs_batch *b, mhs_plan *plan, const mhs_model *model, const 
         if (S.phase == kFree && free_slot < 0) free_slot = i;
     }
     if (free_slot < 0) return fail(MHS_ERR_BUDGET, "no free slot (max_slots %d)", b->max_slots);
+    size_t need = 0;
+    if ((st = mhs_request_bytes(&plan->grid, plan->precisions, &need))) return st;
+    if (b->budget && b->in_use + need > b->budget)
+        return fail(MHS_ERR_BUDGET, "admission would hold %zu bytes of device memory, over the budget of %zu",
+                    b->in_use + need, b->budget);
     if ((st = set_device(plan))) return st;
 
     Slot S{};
@@ -557,6 +566,8 @@ int mhs_batch_admit(mhs_batch *b, mhs_plan *plan, const mhs_model *model, const 
     S.steps = 0;
     S.ticks = 0;
     S.t0 = std::chrono::steady_clock::now();
+    S.bytes = need;
+    b->in_use += need;
     b->slots[(size_t)free_slot] = S;
     *slot = free_slot;
     return MHS_OK;
@@ -838,7 +849,15 @@ int mhs_batch_release(mhs_batch *b, int32_t slot)
     if (st) return st;
     Slot &S = b->slots[(size_t)slot];
     if (S.phase != kFree && S.upload_pending) invalidate_model(S.plan); // its tables never reached the device
+    b->in_use -= S.bytes;
     b->slots[(size_t)slot] = Slot{};
+    return MHS_OK;
+}
+
+int mhs_batch_bytes_in_use(const mhs_batch *b, size_t *bytes)
+{
+    if (!b || !bytes) return fail(MHS_ERR_INVALID_ARG, "NULL argument");
+    *bytes = b->in_use;
     return MHS_OK;
 }
 

@@ -236,7 +236,10 @@ class Server:
 class Batch:
     """Binding of mhs_batch (workspace from torch)."""
 
-    def __init__(self, max_slots, device="cuda:0"):
+    def __init__(self, max_slots, device="cuda:0", hbm_budget=0):
+        """hbm_budget: bytes the admitted requests may hold together
+        (mhs_request_bytes each; 0 = no limit): admission past it raises
+        MHSError with code MHS_ERR_BUDGET."""
         import torch
 
         self.torch = torch
@@ -248,8 +251,14 @@ class Batch:
         with torch.cuda.device(self.device):
             self.ws = torch.empty(n.value, dtype=torch.uint8, device=self.device)
             h = C.c_void_p()
-            check(L.mhs_batch_create(max_slots, C.c_void_p(self.ws.data_ptr()), n.value, C.byref(h)))
+            check(L.mhs_batch_create(max_slots, int(hbm_budget), C.c_void_p(self.ws.data_ptr()), n.value,
+                                     C.byref(h)))
         self.h = h
+
+    def bytes_in_use(self):
+        n = C.c_size_t()
+        check(_lib.lib().mhs_batch_bytes_in_use(self.h, C.byref(n)))
+        return n.value
 
     def close(self):
         if getattr(self, "h", None):
@@ -322,22 +331,25 @@ class Resident:
 
 
 class DeviceBackend:
-    def __init__(self, max_slots=32, device="cuda:0", precisions=PREC_FP64 | PREC_MIXED):
+    """Plans and buffers from torch, requests through a Batch.  hbm_budget
+    is also handed to the batch (mhs_batch_create), which then refuses an
+    admission past it; the Server's pool budget, which counts idle
+    residents too, keeps admissions within it first."""
+
+    def __init__(self, max_slots=32, device="cuda:0", precisions=PREC_FP64 | PREC_MIXED, hbm_budget=0):
         import torch
 
         self.torch = torch
         self.device = torch.device(device)
         self.precisions = precisions
         self.max_slots = max_slots
-        self.batch = Batch(max_slots, device)
+        self.batch = Batch(max_slots, device, hbm_budget)
 
     def footprint(self, key):
-        from .solver import GridSpec, workspace_bytes
+        from .solver import GridSpec, request_bytes
 
         (nx, ny, nz), (lx, ly, lz) = key
-        n = nx * ny * nz
-        ws = workspace_bytes(GridSpec(nx, ny, nz, lx, ly, lz), self.precisions)
-        return ws + 6 * 8 * n + 8 * nx * ny
+        return request_bytes(GridSpec(nx, ny, nz, lx, ly, lz), self.precisions)
 
     def acquire(self, key):
         from .solver import GridSpec, Plan

@@ -24,6 +24,33 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def _same_device(a, b):
+    a, b = torch.device(a), torch.device(b)
+    if a.type != b.type:
+        return False
+    if a.type != "cuda":
+        return True
+    ia = torch.cuda.current_device() if a.index is None else a.index
+    ib = torch.cuda.current_device() if b.index is None else b.index
+    return ia == ib
+
+
+def check_array(t, shape, dtype, device, name):
+    """Raise ValueError unless `t` is a contiguous tensor of `dtype` and
+    `shape` on `device`.  The C ABI takes bare pointers and cannot check
+    sizes, so every array is checked here before its pointer is passed."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if not _same_device(t.device, device):
+        raise ValueError(f"{name} must be on {device}, got {t.device}")
+
+
 def make_opts(precision=PREC_FP64, rtol=1e-10, max_cycles=100, nu1=2, nu2=2, inner_cycles=1,
               warm_start=False, check_every=0, faces_given=False):
     o = _lib.Opts()
@@ -83,6 +110,15 @@ def workspace_bytes(grid, precisions=PREC_FP64 | PREC_MIXED):
     g = _grid(grid)
     n = C.c_size_t(0)
     check(_lib.lib().mhs_workspace_bytes(C.byref(g), precisions, C.byref(n)))
+    return n.value
+
+
+def request_bytes(grid, precisions=PREC_FP64 | PREC_MIXED):
+    """Device bytes one served request holds: workspace, bz0, P and the
+    five field outputs (mhs_request_bytes)."""
+    g = _grid(grid)
+    n = C.c_size_t(0)
+    check(_lib.lib().mhs_request_bytes(C.byref(g), precisions, C.byref(n)))
     return n.value
 
 
@@ -155,9 +191,18 @@ class Plan:
         check(_lib.lib().mhs_plan_level_dims(self.h, space, level, C.byref(a), C.byref(b), C.byref(c)))
         return (c.value, b.value, a.value) if space == 3 else (b.value, a.value)
 
+    def _check(self, t, shape, name, dtype=torch.float64):
+        check_array(t, shape, dtype, self.device, name)
+
+    def _check_fields(self, ts, names):
+        for t, n in zip(ts, names):
+            self._check(t, self.shape, n)
+
     # ---- the three steps of the procedure ------------------------------------
     def solve_boundary(self, bz0, P, opts=None, raise_on_error=True):
         """Multigrid solve of equation (11); writes plane 0 of P."""
+        self._check(bz0, self.shape[1:], "bz0")
+        self._check(P, self.shape, "P")
         opts = opts or make_opts()
         info = _lib.Info()
         with torch.cuda.device(self.device):
@@ -169,6 +214,7 @@ class Plan:
 
     def solve_interior(self, model, P, opts=None, raise_on_error=True):
         """Multigrid solve of equation (8) in place (FP64 or mixed)."""
+        self._check(P, self.shape, "P")
         opts = opts or make_opts()
         m = _ModelArgs.of(model)
         info = _lib.Info()
@@ -181,8 +227,13 @@ class Plan:
 
     def fields(self, model, P, out=None):
         """B, p, rho by central differences; returns (Bx, By, Bz, p, rho)."""
+        self._check(P, self.shape, "P")
         if out is None:
             out = tuple(torch.empty_like(P) for _ in range(5))
+        out = tuple(out)
+        if len(out) != 5:
+            raise ValueError("out must hold five tensors (Bx, By, Bz, p, rho)")
+        self._check_fields(out, ("Bx", "By", "Bz", "p", "rho"))
         m = _ModelArgs.of(model)
         with torch.cuda.device(self.device):
             check(_lib.lib().mhs_fields(self.h, C.byref(m.c), _ptr(P), *[_ptr(t) for t in out],
@@ -194,11 +245,13 @@ class Plan:
         (jx, jy, jz, fres, divb) with j = curl B / mu0, fres the magnitude of
         the force-balance residual and divb = div B (zero on the side and top
         faces)."""
-        for t in (Bx, By, Bz, p, rho):
-            if tuple(t.shape) != self.shape or t.dtype != torch.float64 or not t.is_contiguous():
-                raise ValueError(f"fields must be contiguous float64 tensors of shape {self.shape}")
+        self._check_fields((Bx, By, Bz, p, rho), ("Bx", "By", "Bz", "p", "rho"))
         if out is None:
             out = tuple(torch.empty_like(Bx) for _ in range(5))
+        out = tuple(out)
+        if len(out) != 5:
+            raise ValueError("out must hold five tensors (jx, jy, jz, fres, divb)")
+        self._check_fields(out, ("jx", "jy", "jz", "fres", "divb"))
         m = _ModelArgs.of(model)
         with torch.cuda.device(self.device):
             check(_lib.lib().mhs_diagnostics(self.h, C.byref(m.c), *[_ptr(t) for t in (Bx, By, Bz, p, rho)],
@@ -212,19 +265,19 @@ class Plan:
         entries are not written), count and status int32 (nlines,); status
         0 = step cap, 1 = left the box, 2 = |B| <= bmin.  ds < 0 traces
         against B."""
-        for t in (Bx, By, Bz):
-            if tuple(t.shape) != self.shape or t.dtype != torch.float64 or not t.is_contiguous():
-                raise ValueError(f"fields must be contiguous float64 tensors of shape {self.shape}")
-        if seeds.dtype != torch.float64 or seeds.dim() != 2 or seeds.shape[1] != 3 or not seeds.is_contiguous():
-            raise ValueError("seeds must be a contiguous float64 tensor of shape (nlines, 3)")
+        self._check_fields((Bx, By, Bz), ("Bx", "By", "Bz"))
+        if not isinstance(seeds, torch.Tensor) or seeds.dim() != 2:
+            raise ValueError("seeds must be a tensor of shape (nlines, 3)")
         n = seeds.shape[0]
+        self._check(seeds, (n, 3), "seeds")
         if out is None:
             out = (torch.empty((max_steps + 1, n, 3), dtype=torch.float64, device=seeds.device),
                    torch.empty(n, dtype=torch.int32, device=seeds.device),
                    torch.empty(n, dtype=torch.int32, device=seeds.device))
         pts, cnt, st = out
-        if tuple(pts.shape) != (max_steps + 1, n, 3) or tuple(cnt.shape) != (n,) or tuple(st.shape) != (n,):
-            raise ValueError("output shapes must be (max_steps + 1, nlines, 3), (nlines,), (nlines,)")
+        self._check(pts, (max_steps + 1, n, 3), "points")
+        self._check(cnt, (n,), "count", torch.int32)
+        self._check(st, (n,), "status", torch.int32)
         with torch.cuda.device(self.device):
             check(_lib.lib().mhs_trace_field_lines(self.h, _ptr(Bx), _ptr(By), _ptr(Bz), _ptr(seeds), n,
                                                    float(ds), int(max_steps), float(bmin), _ptr(pts), _ptr(cnt),
@@ -254,14 +307,30 @@ class Plan:
         return out
 
     # ---- stage entry points (kernel-level checks) ----------------------------
-    def stage_smooth(self, model, space, level, u, f=None, nsweeps=1, precision=PREC_FP64):
+    def _check_stage(self, space, level, precision, arrays):
+        """arrays: (tensor or None, level offset, name); level offset 1 = the
+        next coarser level's shape."""
+        if space not in (2, 3) or precision not in (PREC_FP64, PREC_MIXED):
+            raise ValueError("space must be 2 or 3 and precision MHS_PREC_FP64 or MHS_PREC_MIXED")
+        dtype = torch.float64 if precision == PREC_FP64 else torch.float32
+        for t, off, name in arrays:
+            if t is not None:
+                self._check(t, self.level_shape(space, level + off), name, dtype)
+
+    def stage_smooth(self, model, space, level, u, f=None, nsweeps=1, precision=PREC_FP64, zero_guess=False):
+        """nsweeps red-black sweeps on level `level`; zero_guess: the first
+        sweep starts from u = 0, as the first sweep of a coarse-grid
+        correction does (u's interior is not read; its boundary must be 0)."""
+        self._check_stage(space, level, precision, ((u, 0, "u"), (f, 0, "f")))
         m = _ModelArgs.of(model)
         with torch.cuda.device(self.device):
             check(_lib.lib().mhs_stage_smooth(self.h, C.byref(m.c) if m else None, space, level, precision,
-                                              _ptr(u), _ptr(f), nsweeps, _stream(self.device)))
+                                              _ptr(u), _ptr(f), nsweeps, 1 if zero_guess else 0,
+                                              _stream(self.device)))
         return u
 
     def stage_restrict(self, model, space, level, u, f, fc, precision=PREC_FP64):
+        self._check_stage(space, level, precision, ((u, 0, "u"), (f, 0, "f"), (fc, 1, "fc")))
         m = _ModelArgs.of(model)
         with torch.cuda.device(self.device):
             check(_lib.lib().mhs_stage_restrict(self.h, C.byref(m.c) if m else None, space, level, precision,
@@ -269,6 +338,7 @@ class Plan:
         return fc
 
     def stage_correct_smooth(self, model, space, level, u, f, ec, precision=PREC_FP64):
+        self._check_stage(space, level, precision, ((u, 0, "u"), (f, 0, "f"), (ec, 1, "ec")))
         m = _ModelArgs.of(model)
         with torch.cuda.device(self.device):
             check(_lib.lib().mhs_stage_correct_smooth(self.h, C.byref(m.c) if m else None, space, level,
@@ -277,6 +347,16 @@ class Plan:
         return u
 
     def stage_bottom(self, model, space, u, f, nu1=2, nu2=2, precision=PREC_FP64):
+        # the bottom level depends on the model (uploaded by the call), so
+        # the shape is checked against every level the plan has
+        if space not in (2, 3) or precision not in (PREC_FP64, PREC_MIXED):
+            raise ValueError("space must be 2 or 3 and precision MHS_PREC_FP64 or MHS_PREC_MIXED")
+        shapes = [self.level_shape(space, l) for l in range(1, self.levels(space))]
+        if not isinstance(u, torch.Tensor) or tuple(u.shape) not in shapes:
+            raise ValueError(f"u must have the shape of a coarse level, one of {shapes}")
+        dtype = torch.float64 if precision == PREC_FP64 else torch.float32
+        self._check(u, tuple(u.shape), "u", dtype)
+        self._check(f, tuple(u.shape), "f", dtype)
         m = _ModelArgs.of(model)
         lvl = C.c_int32()
         with torch.cuda.device(self.device):
@@ -285,6 +365,7 @@ class Plan:
         return lvl.value
 
     def stage_residual_norm(self, model, space, level, u, f=None, precision=PREC_FP64):
+        self._check_stage(space, level, precision, ((u, 0, "u"), (f, 0, "f")))
         m = _ModelArgs.of(model)
         out = C.c_double()
         with torch.cuda.device(self.device):

@@ -95,3 +95,52 @@ def test_plan_create_rejects_small_or_misaligned_workspace():
     assert L.mhs_plan_create(C.byref(g), 3, C.c_void_p(256), 1024, C.byref(h)) == _lib.ERR_WORKSPACE
     _, n = ws_bytes(33, 33, 33)
     assert L.mhs_plan_create(C.byref(g), 3, C.c_void_p(4096 + 8), n, C.byref(h)) == _lib.ERR_WORKSPACE
+
+
+def test_request_bytes_counts_workspace_and_arrays():
+    for dims in ((33, 33, 33), (257, 257, 257), (129, 129, 65)):
+        g = _lib.Grid(*dims, 1.0, 1.0, 1.0)
+        n = C.c_size_t(0)
+        assert _lib.lib().mhs_request_bytes(C.byref(g), 3, C.byref(n)) == _lib.MHS_OK
+        _, ws = ws_bytes(*dims)
+        nx, ny, nz = dims
+        assert n.value == ws + 8 * (6 * nx * ny * nz + nx * ny)
+    bad = _lib.Grid(32, 33, 33, 1.0, 1.0, 1.0)
+    assert _lib.lib().mhs_request_bytes(C.byref(bad), 3, C.byref(C.c_size_t())) == _lib.ERR_GRID
+    assert _lib.lib().mhs_batch_bytes_in_use(None, None) == _lib.ERR_INVALID_ARG
+
+
+torch = pytest.importorskip("torch")
+
+
+def test_binding_rejects_wrong_arrays_before_the_c_call():
+    """The C ABI takes bare pointers; the torch binding checks dtype, shape,
+    contiguity and device of every array first (no GPU needed: the check
+    raises before any library call)."""
+    from paper_1307_6720_amd import solver
+
+    good = torch.zeros((3, 4, 5), dtype=torch.float64)
+    solver.check_array(good, (3, 4, 5), torch.float64, "cpu", "P")
+    for t, why in ((good.float(), "float64"), (good[:, :, :4], "shape"), (good.transpose(0, 2).contiguous(), "shape"),
+                   (torch.zeros((5, 4, 3), dtype=torch.float64).transpose(0, 2), "contiguous"),
+                   (good.numpy(), "tensor")):
+        with pytest.raises(ValueError, match=why):
+            solver.check_array(t, (3, 4, 5), torch.float64, "cpu", "P")
+    with pytest.raises(ValueError, match="must be on"):
+        solver.check_array(good, (3, 4, 5), torch.float64, "cuda:0", "P")
+    # a Plan's entry points run the checks before the C call
+    plan = solver.Plan.__new__(solver.Plan)
+    plan.cgrid = _lib.Grid(5, 4, 3, 1.0, 1.0, 1.0)
+    plan.device = torch.device("cpu")
+    plan.h = None
+    bz = torch.zeros((4, 5), dtype=torch.float64)
+    with pytest.raises(ValueError, match="bz0"):
+        plan.solve_boundary(bz.float(), good)
+    with pytest.raises(ValueError, match="P"):
+        plan.solve_boundary(bz, good[:2])
+    with pytest.raises(ValueError, match="P"):
+        plan.solve_interior(None, good.float())
+    with pytest.raises(ValueError, match="Bx"):
+        plan.fields(None, good, out=(good[:1],) + tuple(torch.zeros_like(good) for _ in range(4)))
+    with pytest.raises(ValueError, match="five"):
+        plan.fields(None, good, out=(good,) * 4)

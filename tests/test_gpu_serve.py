@@ -284,3 +284,143 @@ def test_batch_with_given_faces_equals_single_solve():
     b.close()
     for p in plans:
         p.close()
+
+
+def test_merged_257_batch_equals_single_solves():
+    """The headline configuration: 257^3 requests (three runs of the
+    benchmark's workload, both precisions) merged into one batch give bit
+    for bit the single-request results.  Merged launches chunk the z-march
+    of levels >= 1 differently from a single request; those levels carry no
+    reductions, so nothing may change."""
+    runs = [(1, PREC_MIXED), (2, PREC_FP64), (4, PREC_MIXED)]
+    works = [synth.workload("mhs-257", run=r) for r, _ in runs]
+    plans = [Plan(w.grid, PREC_FP64 | PREC_MIXED, device=DEV) for w in works]
+    singles = []
+    for (r, prec), w, plan in zip(runs, works, plans):
+        print(f"[serve] 257^3 run {r} alone", flush=True)
+        res = solve(plan, torch.from_numpy(w.bz0).to(DEV), w.model, precision=prec, rtol=1e-10)
+        torch.cuda.synchronize()
+        singles.append(([t.clone() for t in (res.P, res.Bx, res.By, res.Bz, res.p, res.rho)],
+                        res.info2d["cycles"], res.info3d["cycles"]))
+        del res
+    print("[serve] 257^3 runs merged", flush=True)
+    b = Batch(len(runs), DEV)
+    outs, slots = [], []
+    for (r, prec), w, plan in zip(runs, works, plans):
+        P = torch.zeros(w.grid.shape, dtype=torch.float64, device=DEV)
+        F = tuple(torch.empty_like(P) for _ in range(5))
+        bz = torch.from_numpy(w.bz0).to(DEV)
+        slots.append(b.admit(plan, w.model, bz, P, F, make_opts(prec, 1e-10)))
+        outs.append((bz, P, F))
+    while b.step():
+        pass
+    torch.cuda.synchronize()
+    for s, (bz, P, F), (want, c2, c3) in zip(slots, outs, singles):
+        done, i2, i3 = b.poll(s)
+        assert done and i2["status"] == 0 and i3["status"] == 0
+        assert (i2["cycles"], i3["cycles"]) == (c2, c3)
+        for name, a, w_ in zip(("P", "Bx", "By", "Bz", "p", "rho"), (P, *F), want):
+            assert torch.equal(a, w_), (name, (a - w_).abs().max().item())
+    b.close()
+    for p in plans:
+        p.close()
+
+
+def test_batch_refuses_admission_over_its_budget():
+    """mhs_batch_create's HBM budget: a request whose footprint
+    (mhs_request_bytes) would take the batch over it is refused with
+    MHS_ERR_BUDGET; after a release it fits again."""
+    from paper_1307_6720_amd.solver import request_bytes
+
+    reqs = [make_request(i, CASES[1]) for i in range(2)]  # 65^3, mixed
+    nx, ny, nz = reqs[0].dims
+    grid = synth.make_grid(nx, ny, nz)
+    one = request_bytes(grid)
+    b = Batch(4, DEV, hbm_budget=one + one // 2)
+    plans, outs = [], []
+    for r in reqs:
+        plan = Plan(grid, PREC_FP64 | PREC_MIXED, device=DEV)
+        P = torch.zeros((nz, ny, nx), dtype=torch.float64, device=DEV)
+        F = tuple(torch.empty_like(P) for _ in range(5))
+        plans.append(plan)
+        outs.append((torch.from_numpy(r.bz0).to(DEV), P, F))
+    s0 = b.admit(plans[0], reqs[0].model, *outs[0], make_opts(PREC_MIXED, 1e-10))
+    assert b.bytes_in_use() == one
+    with pytest.raises(_lib.MHSError) as e:
+        b.admit(plans[1], reqs[1].model, *outs[1], make_opts(PREC_MIXED, 1e-10))
+    assert e.value.code == _lib.ERR_BUDGET
+    while b.step():
+        pass
+    assert b.poll(s0)[0]
+    b.release(s0)
+    assert b.bytes_in_use() == 0
+    s1 = b.admit(plans[1], reqs[1].model, *outs[1], make_opts(PREC_MIXED, 1e-10))
+    while b.step():
+        pass
+    assert b.poll(s1)[0]
+    b.close()
+    for p in plans:
+        p.close()
+
+
+def test_budget_bound_serving_queues_evicts_and_matches_alone():
+    """A serving run on the device whose HBM budget binds: 65^3 and 257^3
+    requests under a budget that holds one 257^3 request, or several small
+    ones, but not both.  The 257^3 request waits until the small ones have
+    finished and their idle residents are evicted; the small request behind
+    it waits for the 257^3 one and evicts it in turn.  The in-flight
+    footprint never exceeds the budget, and every result is bit for bit its
+    single-request result."""
+    from paper_1307_6720_amd.solver import request_bytes
+
+    small = (65, 65, 65)
+    big = (257, 257, 257)
+    one = (1.0, 1.0, 1.0)
+    cases = [(small, one, 0.3, 0.2, PREC_MIXED, 1e-10),
+             (small, one, 0.8, 0.6, PREC_FP64, 1e-10),
+             (small, one, 0.5, 0.5, PREC_MIXED, 1e-10),
+             (big, one, 0.5, 0.5, PREC_MIXED, 1e-10),
+             (small, one, 0.1, 0.9, PREC_FP64, 1e-10)]
+    reqs = [make_request(i, c, seed=900) for i, c in enumerate(cases)]
+    fp_big = request_bytes(synth.make_grid(*big))
+    fp_small = request_bytes(synth.make_grid(*small))
+    budget = fp_big + fp_small // 2
+    print(f"[serve] budget {budget / 2**30:.3f} GiB (257^3 request {fp_big / 2**30:.3f} GiB)", flush=True)
+    want = {r.id: alone(r) for r in reqs}
+    got = {}
+    in_use = []
+    freed = []
+
+    def keep(req, res):
+        got[req.id] = [t.clone() for t in (res.P, *res.F)]
+
+    be = DeviceBackend(max_slots=4, device=DEV, hbm_budget=budget)
+    srv = Server(be, budget, on_finish=keep)
+    orig_step, orig_free = be.step, be.free
+
+    def step():
+        in_use.append(be.batch.bytes_in_use())
+        return orig_step()
+
+    def free(res):
+        freed.append(res.key[0])
+        return orig_free(res)
+
+    be.step, be.free = step, free
+    for r in reqs:
+        r.arrival = 0.0
+    done, stats = srv.run(reqs)
+    torch.cuda.synchronize()
+    be.close()
+    assert stats["ok"] == len(reqs)
+    assert stats["peak_resident_bytes"] <= budget and max(in_use) <= budget
+    d = {x.id: x for x in done}
+    small_done = max(d[i].finished for i in (0, 1, 2))
+    assert d[3].admitted >= small_done  # the 257^3 request waited for memory
+    assert d[4].admitted >= d[3].finished  # and the last small one for it
+    assert freed.count(small) >= 1 and freed.count(big) >= 1  # idle residents were evicted
+    for r in reqs:
+        w, i2, i3 = want[r.id]
+        assert d[r.id].status == 0 and d[r.id].info3d["cycles"] == i3["cycles"]
+        for name, a, b_ in zip(("P", "Bx", "By", "Bz", "p", "rho"), got[r.id], w):
+            assert torch.equal(a, b_), (r.id, name)

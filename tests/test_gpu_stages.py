@@ -119,15 +119,32 @@ def test_smooth3_fp64(setup, level, with_f, nsweeps):
     assert rel(u.cpu().numpy(), want) < 1e-13
 
 
-def test_smooth3_fp32(setup):
+def f32(a):
+    """Round to FP32 and back: the inputs both sides see."""
+    return np.asarray(a).astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("level", [0, 1])
+@pytest.mark.parametrize("zero_guess", [False, True])
+@pytest.mark.parametrize("nsweeps", [1, 2])
+def test_smooth3_fp32(setup, level, zero_guess, nsweeps):
+    """The inner solver's FP32 sweeps: with a right-hand side, and from a
+    zero guess (the first pre-smoothing sweep of every FP32 cycle at level
+    0 and of every coarse level), against the FP64 oracle."""
     grid, plan, model = setup
-    shape, xi, lengths = level_args(plan, model, grid, 0)
-    rng = np.random.default_rng(7)
-    u0 = rng.normal(size=shape).astype(np.float32).astype(np.float64)
-    f = rng.normal(size=shape).astype(np.float32).astype(np.float64)
-    want = ref.rbgs3(u0, f, xi, model.alpha, 2, lengths)
+    shape, xi, lengths = level_args(plan, model, grid, level)
+    rng = np.random.default_rng(7 + 10 * level + nsweeps)
+    u0 = f32(rng.normal(size=shape))
+    f = f32(rng.normal(size=shape))
+    if zero_guess:
+        # a correction: zero Dirichlet data; the interior values are not read
+        u0[0] = u0[-1] = 0
+        u0[:, 0] = u0[:, -1] = 0
+        u0[:, :, 0] = u0[:, :, -1] = 0
+    want = ref.rbgs3(np.zeros(shape) if zero_guess else u0, f, xi, model.alpha, nsweeps, lengths)
     u = tg(u0, torch.float32)
-    plan.stage_smooth(model, 3, 0, u, tg(f, torch.float32), 2, precision=PREC_MIXED)
+    plan.stage_smooth(model, 3, level, u, tg(f, torch.float32), nsweeps, precision=PREC_MIXED,
+                      zero_guess=zero_guess)
     assert rel(u.double().cpu().numpy(), want) < 1e-5
 
 
@@ -145,17 +162,38 @@ def test_restrict3(setup, level):
     assert rel(fc.cpu().numpy(), want) < 1e-13
 
 
-def test_restrict3_fp32(setup):
+@pytest.mark.parametrize("level", [0, 1])
+def test_restrict3_fp32(setup, level):
     grid, plan, model = setup
-    shape, xi, lengths = level_args(plan, model, grid, 0)
-    cshape = plan.level_shape(3, 1)
-    rng = np.random.default_rng(5)
-    u = rng.normal(size=shape).astype(np.float32).astype(np.float64)
-    f = rng.normal(size=shape).astype(np.float32).astype(np.float64)
-    want = restrict(plan, 0, ref.residual3(u, f, xi, model.alpha, lengths))
+    shape, xi, lengths = level_args(plan, model, grid, level)
+    cshape = plan.level_shape(3, level + 1)
+    rng = np.random.default_rng(5 + level)
+    u = f32(rng.normal(size=shape))
+    f = f32(rng.normal(size=shape))
+    want = restrict(plan, level, ref.residual3(u, f, xi, model.alpha, lengths))
     fc = torch.zeros(cshape, dtype=torch.float32, device=DEV)
-    plan.stage_restrict(model, 3, 0, tg(u, torch.float32), tg(f, torch.float32), fc, precision=PREC_MIXED)
+    plan.stage_restrict(model, 3, level, tg(u, torch.float32), tg(f, torch.float32), fc, precision=PREC_MIXED)
     assert rel(fc.double().cpu().numpy(), want) < 1e-5
+
+
+@pytest.mark.parametrize("level", [0, 1])
+def test_correct_smooth3_fp32(setup, level):
+    """The FP32 prolongation fused into the first post-smoothing sweep (or
+    the z-only prolongation before it), levels 0 and 1."""
+    grid, plan, model = setup
+    shape, xi, lengths = level_args(plan, model, grid, level)
+    cshape = plan.level_shape(3, level + 1)
+    rng = np.random.default_rng(level + 31)
+    u0 = f32(rng.normal(size=shape))
+    f = f32(rng.normal(size=shape))
+    ec = f32(rng.normal(size=cshape))
+    ec[0] = ec[-1] = 0
+    ec[:, 0] = ec[:, -1] = 0
+    ec[:, :, 0] = ec[:, :, -1] = 0
+    want = ref.rbgs3(prolong(plan, level, ec, u0), f, xi, model.alpha, 1, lengths)
+    u = tg(u0, torch.float32)
+    plan.stage_correct_smooth(model, 3, level, u, tg(f, torch.float32), tg(ec, torch.float32), precision=PREC_MIXED)
+    assert rel(u.double().cpu().numpy(), want) < 1e-5
 
 
 @pytest.mark.parametrize("level", [0, 1])

@@ -255,6 +255,29 @@ def test_interior_dense_bruteforce(shape, lengths):
     assert rel(ref.direct3(ubc, None, xi, alpha, lengths), want) < 1e-11
 
 
+@pytest.mark.parametrize("shape,lengths", [((5, 5, 5), (1.0, 1.0, 1.0)), ((9, 9, 9), (1.0, 2.0, 0.5)),
+                                           ((17, 9, 5), (1.0, 1.0, 1.0)), ((9, 17, 5), (0.7, 1.3, 2.0))])
+def test_min_eigenvalue_bound_equals_dense_spectrum(shape, lengths):
+    """Definiteness of (8) (Section 2.1: xi < 1 makes the operator elliptic;
+    alpha^2 must stay below the spectrum).  The per-mode tridiagonal
+    eigenvalue equals the smallest eigenvalue of the dense matrix
+    -[(1 - xi)(d2x + d2y) + d2z] built node by node (alpha = 0), for random
+    xi < 1 including values close to 1; and alpha^2 just below it leaves
+    the dense operator negative definite, just above it does not."""
+    nz, ny, nx = shape
+    lx, ly, lz = lengths
+    rng = np.random.default_rng(7 * nz + ny)
+    xi = rng.uniform(-0.5, 0.98, size=nz)
+    A, _ = dense.operator3(shape, xi, 0.0, lx, ly, lz)
+    assert np.allclose(A, A.T, rtol=0, atol=0)
+    lam_dense = np.linalg.eigvalsh(-A)
+    lam0 = exact.min_eigenvalue_bound(nx, ny, nz, xi, lx, ly, lz)
+    assert abs(lam0 - lam_dense[0]) <= 1e-12 * lam_dense[-1]
+    for s, definite in ((1 - 1e-6, True), (1 + 1e-6, False)):
+        Aa, _ = dense.operator3(shape, xi, np.sqrt(s * lam0), lx, ly, lz)
+        assert (np.linalg.eigvalsh(Aa)[-1] < 0) == definite
+
+
 def test_interior_with_source_dense():
     """Nonzero right-hand side and boundary data together (the form the
     coarse levels and the refinement inner solve see)."""
