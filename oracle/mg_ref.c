@@ -40,13 +40,20 @@
  * the procedure in Section 2.2).
  *
  * Each function below is a direct loop over the definition it cites; there
- * is no blocking or fusion.  Only tests, the smoke check and the CPU
+ * is no blocking or fusion.  OpenMP pragmas (when built with -fopenmp)
+ * split the outer loop of the 3D residual, of each colour of a sweep and of
+ * the grid transfers over threads, for timing only: every node's value is
+ * computed as in the serial loop and no sum is split, so the results do not
+ * depend on the number of threads.  Only tests, the smoke check and the CPU
  * baseline of the benchmark may load this library.  It shares no code with
  * the HIP path.
  */
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define REF_OK 0
 #define REF_NO_CONVERGENCE 1
@@ -57,6 +64,19 @@
 
 #define AT3(a, i, j, k) (a)[(size_t)(i) + (size_t)nx * ((size_t)(j) + (size_t)ny * (size_t)(k))]
 #define AT2(a, i, j) (a)[(size_t)(i) + (size_t)nx * (size_t)(j)]
+
+/* Threads the parallel loops use (n >= 1); returns the count in effect
+ * (1 without OpenMP). */
+int ref_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------ */
 /* grid hierarchy                                                       */
@@ -141,6 +161,7 @@ void ref_residual3(const int *n, const double *h, const double *xi, double alpha
                    const double *u, const double *f, double *r)
 {
     int nx = n[0], ny = n[1], nz = n[2];
+#pragma omp parallel for schedule(static)
     for (int k = 0; k < nz; k++)
         for (int j = 0; j < ny; j++)
             for (int i = 0; i < nx; i++) {
@@ -185,12 +206,15 @@ void ref_rbgs3(const int *n, const double *h, const double *xi, double alpha,
 {
     int nx = n[0], ny = n[1], nz = n[2];
     for (int s = 0; s < nsweeps; s++)
-        for (int colour = 0; colour < 2; colour++)
+        for (int colour = 0; colour < 2; colour++) {
+            /* nodes of one colour read only the other colour */
+#pragma omp parallel for schedule(static)
             for (int k = 1; k < nz - 1; k++)
                 for (int j = 1; j < ny - 1; j++)
                     for (int i = 1; i < nx - 1; i++)
                         if (((i + j + k) & 1) == colour)
                             gs3_point(u, f, nx, ny, i, j, k, h[0], h[1], h[2], xi[k], alpha);
+        }
 }
 
 /* Full weighting: fc(I,J,K) = sum w(a)w(b)w(c) rf(2I+a, 2J+b, 2K+c) with
@@ -200,6 +224,7 @@ void ref_restrict3(const int *nf, const double *rf, double *fc)
     static const double w[3] = {0.25, 0.5, 0.25};
     int nxf = nf[0], nyf = nf[1];
     int ncx = (nf[0] - 1) / 2 + 1, ncy = (nf[1] - 1) / 2 + 1, ncz = (nf[2] - 1) / 2 + 1;
+#pragma omp parallel for schedule(static)
     for (int K = 0; K < ncz; K++)
         for (int J = 0; J < ncy; J++)
             for (int I = 0; I < ncx; I++) {
@@ -224,6 +249,7 @@ void ref_restrict3_xy(const int *nf, const double *rf, double *fc)
     static const double w[3] = {0.25, 0.5, 0.25};
     int nxf = nf[0], nyf = nf[1], nz = nf[2];
     int ncx = (nf[0] - 1) / 2 + 1, ncy = (nf[1] - 1) / 2 + 1;
+#pragma omp parallel for schedule(static)
     for (int k = 0; k < nz; k++)
         for (int J = 0; J < ncy; J++)
             for (int I = 0; I < ncx; I++) {
@@ -255,6 +281,7 @@ void ref_prolong3(const int *nc, const double *ec, double *uf)
 {
     int ncx = nc[0], ncy = nc[1], ncz = nc[2];
     int nx = 2 * (ncx - 1) + 1, ny = 2 * (ncy - 1) + 1, nz = 2 * (ncz - 1) + 1;
+#pragma omp parallel for schedule(static)
     for (int k = 1; k < nz - 1; k++)
         for (int j = 1; j < ny - 1; j++)
             for (int i = 1; i < nx - 1; i++) {
@@ -275,6 +302,7 @@ void ref_restrict3_z(const int *nf, const double *rf, double *fc)
     static const double w[3] = {0.25, 0.5, 0.25};
     int nx = nf[0], ny = nf[1];
     int ncz = (nf[2] - 1) / 2 + 1;
+#pragma omp parallel for schedule(static)
     for (int K = 0; K < ncz; K++)
         for (int j = 0; j < ny; j++)
             for (int i = 0; i < nx; i++) {
@@ -291,6 +319,7 @@ void ref_prolong3_z(const int *nc, const double *ec, double *uf)
 {
     int nx = nc[0], ny = nc[1], ncz = nc[2];
     int nz = 2 * (ncz - 1) + 1;
+#pragma omp parallel for schedule(static)
     for (int k = 1; k < nz - 1; k++)
         for (int j = 1; j < ny - 1; j++)
             for (int i = 1; i < nx - 1; i++) {
@@ -306,6 +335,7 @@ void ref_prolong3_xy(const int *nc, const double *ec, double *uf)
 {
     int ncx = nc[0], ncy = nc[1], nz = nc[2];
     int nx = 2 * (ncx - 1) + 1, ny = 2 * (ncy - 1) + 1;
+#pragma omp parallel for schedule(static)
     for (int k = 1; k < nz - 1; k++)
         for (int j = 1; j < ny - 1; j++)
             for (int i = 1; i < nx - 1; i++) {

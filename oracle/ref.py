@@ -31,6 +31,7 @@ def _load():
     lib = C.CDLL(LIB)
     vp = C.c_void_p
     sig = {
+        "ref_set_threads": (C.c_int, [C.c_int]),
         "ref_levels3": (C.c_int, [_ip, _dp, _ip]),
         "ref_nlevels2": (C.c_int, [C.c_int, C.c_int]),
         "ref_residual3": (None, [_ip, _dp, _dp, C.c_double, _dp, vp, _dp]),
@@ -277,6 +278,12 @@ def jacobi2(P1, bz, lengths=(1.0, 1.0)):
     P2 = np.zeros_like(P1)
     _load().ref_jacobi2(_n2(P1.shape), _h(P1.shape, lengths), P1, _f64(bz), P2)
     return P2
+
+
+def set_threads(n):
+    """Threads the oracle's parallel node loops use (OpenMP); returns the
+    count in effect.  Results do not depend on it."""
+    return _load().ref_set_threads(int(n))
 
 
 def solve(bz0, xi, alpha, shape, lengths=(1.0, 1.0, 1.0), rtol2=1e-10, rtol3=1e-10,

@@ -191,20 +191,25 @@ def test_mixed_steps_track_fp64_cycles_129(plans):
 
 def test_full_size_513_against_exact():
     """The large single equilibrium (513 x 513 x 257, dz = 2 dx, a = 1 so
-    that xi(0) = 1, 40 bipoles plus noise), mixed path to rtol 1e-10: every
+    that xi(0) = 1, 40 bipoles plus noise), mixed path to rtol 1e-12: every
     node of P, B, p - p_b and rho - rho_b within 1e-8 of the exact discrete
     solution and its field recovery; the first step of the hierarchy halves
-    x and y only, and the cycle converges as on an equally spaced grid."""
+    x and y only, and the cycle converges as on an equally spaced grid.
+    The rtol is calibrated for this grid: the noise on every node of the
+    magnetogram puts energy into the shortest modes, whose error the
+    derivatives of B, p and rho amplify; at rtol 1e-10 P is within 7e-10
+    but rho - rho_b only within 2.4e-7, at 1e-11 within 3.5e-8, at 1e-12
+    within 6e-9 (measured on both paths)."""
     print("[solve] 513x513x257 mixed", flush=True)
     w = synth.workload("mhs-513x513x257")
     m = w.model
     g = w.grid
     plan = Plan(g, PREC_FP64 | PREC_MIXED, device=DEV)
-    res = solve(plan, torch.from_numpy(w.bz0).to(DEV), m, precision=PREC_MIXED, rtol=1e-10)
+    res = solve(plan, torch.from_numpy(w.bz0).to(DEV), m, precision=PREC_MIXED, rtol=1e-12)
     torch.cuda.synchronize()
     assert res.info2d["status"] == 0 and res.info3d["status"] == 0, (res.info2d, res.info3d)
     assert plan.level_shape(3, 1) == (257, 257, 257)
-    assert res.info3d["cycles"] <= 10, res.info3d
+    assert res.info3d["cycles"] <= 12, res.info3d
     print("[solve] 513x513x257 exact solve and fields on the host", flush=True)
     want_P = exact.solve(w.bz0, g.nz, m.xi, m.alpha, g.lx, g.ly, g.lz)
     want = fields.fields(want_P, m.alpha, m.xi, m.dxi, m.pb, m.rhob, m.mu0, m.g, g.lx, g.ly, g.lz)

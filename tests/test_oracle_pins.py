@@ -305,6 +305,26 @@ def test_mg_matches_exact_33_65():
         assert rel(P, exact.solve(w.bz0, n, m.xi, m.alpha)) < 1e-11
 
 
+def test_thread_count_does_not_change_the_oracle():
+    """The OpenMP loops of the C multigrid (used for the all-core CPU
+    timing) compute every node as the serial loops do and split no sum, so
+    the iterates are bitwise the same for any thread count (grids with
+    steps that halve every axis and steps that keep z)."""
+    for dims in ((33, 33, 33), (65, 33, 17)):
+        w = synth.workload("mhs-129", dims=dims)
+        m = w.model
+        got = []
+        prev = ref.set_threads(0)  # 0 leaves the count unchanged
+        for th in (1, 3):
+            ref.set_threads(th)
+            P, st, info = ref.solve(w.bz0, m.xi, m.alpha, w.grid.shape, rtol2=1e-12, rtol3=1e-12)
+            assert st == ref.OK
+            got.append((P, info["cycles3d"]))
+        ref.set_threads(prev)
+        assert got[0][1] == got[1][1]
+        assert np.array_equal(got[0][0], got[1][0])
+
+
 # ---------------------------------------------------------------- multigrid stages
 def trilinear_field(shape, seed):
     rng = np.random.default_rng(seed)
