@@ -414,6 +414,27 @@ int mhs_batch_profile_enable(mhs_batch *batch, int32_t class_mask);
 int mhs_batch_profile_read(mhs_batch *batch, int32_t klass, double *total_ms, int64_t *launches,
                            double *bytes, int32_t reset);
 
+/* ---- interior solve without allocation -------------------------------- *
+ * For callers that cannot allocate device memory or create a plan (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): mhs_solve_interior for `grid` without a plan or workspace.
+ * Same arguments, semantics, kernels and results as mhs_solve_interior on a
+ * plan of the same grid (bitwise), with opts->precision selecting the path.
+ * The hierarchy lives in a fixed device array of 48 MiB inside the library
+ * (one copy per device, held until the process ends), so the grid's
+ * workspace for that one precision must fit: grids up to 129 x 129 x 129
+ * with either precision; larger ones return MHS_ERR_WORKSPACE before any
+ * device work.  Devices 0..15 (else MHS_ERR_UNSUPPORTED).  The call
+ * allocates no device or pinned host memory (host bookkeeping uses the C++
+ * heap), clears the part of the array it uses with a fill kernel, and
+ * returns once its stream has drained.  Every call on a device shares that
+ * device's array and finds the previous call's contents in it: calls on one
+ * device from several threads of a process are serialised by the library;
+ * work of another library instance or a caller's kernel that touched the
+ * array concurrently would race with it. */
+int mhs_solve_interior_noalloc(const mhs_grid *grid, const mhs_model *model, double *d_P,
+                               const mhs_opts *opts, mhs_info *info, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -97,6 +97,7 @@ def lib():
         "mhs_plan_bottom_level": (C.c_int, [vp, i32, P(i32)]),
         "mhs_solve_boundary": (C.c_int, [vp, vp, vp, P(Opts), P(Info), vp]),
         "mhs_solve_interior": (C.c_int, [vp, P(Model), vp, P(Opts), P(Info), vp]),
+        "mhs_solve_interior_noalloc": (C.c_int, [P(Grid), P(Model), vp, P(Opts), P(Info), vp]),
         "mhs_fields": (C.c_int, [vp, P(Model), vp, vp, vp, vp, vp, vp, vp]),
         "mhs_stage_smooth": (C.c_int, [vp, P(Model), i32, i32, i32, vp, vp, i32, i32, vp]),
         "mhs_stage_restrict": (C.c_int, [vp, P(Model), i32, i32, i32, vp, vp, vp, vp]),

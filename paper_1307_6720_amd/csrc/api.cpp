@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1011,7 +1012,9 @@ int flush_staging(mhs_plan *p, hipStream_t s)
 {
     if (p->stage.used == 0) return MHS_OK;
     HIPCHK(hipMemcpyAsync(p->stage.dev, p->stage.host, p->stage.used, hipMemcpyHostToDevice, s));
-    HIPCHK(hipEventRecord(p->stage.inflight, s));
+    // (a plan without the event waits for its stream before its host
+    // staging is reused)
+    if (p->stage.inflight) HIPCHK(hipEventRecord(p->stage.inflight, s));
     return MHS_OK;
 }
 
@@ -1101,6 +1104,9 @@ double seconds_since(std::chrono::steady_clock::time_point t0)
 {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
+
+int solve_interior_on(mhs_plan *p, const mhs_model *model, double *d_P, const mhs_opts *o, mhs_info *info,
+                      hipStream_t s, std::chrono::steady_clock::time_point t0);
 
 } // namespace mhs
 
@@ -1320,7 +1326,18 @@ int mhs_solve_interior(mhs_plan *p, const mhs_model *model, double *d_P, const m
     if (!(p->precisions & o->precision))
         return fail(MHS_ERR_UNSUPPORTED, "plan was not created for precision %d", o->precision);
     if ((st = set_device(p))) return st;
-    hipStream_t s = (hipStream_t)stream;
+    return solve_interior_on(p, model, d_P, o, info, (hipStream_t)stream, t0);
+}
+
+} // extern "C"
+
+namespace mhs {
+
+// The interior solve on a validated plan whose device is current.
+int solve_interior_on(mhs_plan *p, const mhs_model *model, double *d_P, const mhs_opts *o, mhs_info *info,
+                      hipStream_t s, std::chrono::steady_clock::time_point t0)
+{
+    int st = MHS_OK;
     Hierarchy &h = p->h3;
     if ((st = upload_model(p, model, s))) return st;
     if ((st = begin_staging(p))) return st;
@@ -1420,6 +1437,10 @@ int mhs_solve_interior(mhs_plan *p, const mhs_model *model, double *d_P, const m
                     fin.r0 > 0 ? fin.rnorm / fin.r0 : 0.0);
     return MHS_OK;
 }
+
+} // namespace mhs
+
+extern "C" {
 
 int mhs_fields(mhs_plan *p, const mhs_model *model, const double *d_P, double *d_Bx, double *d_By, double *d_Bz,
                double *d_p, double *d_rho, void *stream)
@@ -1756,6 +1777,85 @@ int mhs_stage_residual_norm(mhs_plan *p, const mhs_model *model, int32_t space, 
     if ((st = read_state(p, d_state, &ss, s))) return st;
     *norm = ss.rnorm;
     return MHS_OK;
+}
+
+} // extern "C"
+
+// =================================================================================
+// Interior solve over a scratch array the library owns (no allocation per call)
+// =================================================================================
+namespace {
+
+// The largest workspace this path carves: a 129^3 grid with either
+// precision (mixed: 47.2 MiB) fits, 257^3 does not.
+constexpr size_t kScratchBytes = size_t(48) << 20;
+constexpr int kScratchDevices = 16;
+
+// One copy per device, held from the library's load until the process ends.
+// Host code never uses this name as an address: each device's address comes
+// from hipGetSymbolAddress below.
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+struct ScratchSlot {
+    std::mutex mu;        // one call at a time per device in this process
+    char *dev = nullptr;  // this device's address of `scratch`
+    mhs_plan plan;        // host bookkeeping of the hierarchy carved in it
+    SolveState states[4]; // status read-back (pageable)
+};
+ScratchSlot g_scratch[kScratchDevices];
+// descriptor staging, pageable: the call waits for its stream before it
+// returns, so the next call may overwrite it
+char g_scratch_stage[kScratchDevices][kStagingBytes];
+
+} // namespace
+
+extern "C" {
+
+int mhs_solve_interior_noalloc(const mhs_grid *grid, const mhs_model *model, double *d_P, const mhs_opts *o,
+                               mhs_info *info, void *stream)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!grid || !d_P) return fail(MHS_ERR_INVALID_ARG, "NULL argument");
+    int st = validate_opts(o);
+    if (st) return st;
+    size_t need = 0;
+    if ((st = mhs_workspace_bytes(grid, o->precision, &need))) return st;
+    if (need - kAlign > kScratchBytes)
+        return fail(MHS_ERR_WORKSPACE, "grid %dx%dx%d needs %zu bytes of scratch, the library holds %zu", grid->nx,
+                    grid->ny, grid->nz, need - kAlign, kScratchBytes);
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kScratchDevices)
+        return fail(MHS_ERR_UNSUPPORTED, "device %d: the scratch path serves devices 0..%d", dev,
+                    kScratchDevices - 1);
+    ScratchSlot &slot = g_scratch[dev];
+    std::lock_guard<std::mutex> lock(slot.mu);
+    if (!slot.dev) {
+        void *ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr || ((uintptr_t)ptr % kAlign) != 0) return fail(MHS_ERR_HIP, "scratch symbol address is unusable");
+        slot.dev = (char *)ptr;
+    }
+    mhs_plan &p = slot.plan;
+    p = mhs_plan();
+    p.precisions = o->precision;
+    p.device = dev;
+    if ((st = geometry(&p, grid))) return st;
+    if ((st = validate_model(&p, model, false))) return st;
+    p.ws = slot.dev;
+    p.ws_bytes = kScratchBytes;
+    const size_t used = carve_plan(&p, p.ws, o->precision) - kAlign;
+    p.stage.host = g_scratch_stage[dev];
+    p.h_states = slot.states;
+    hipStream_t s = (hipStream_t)stream;
+    // the previous call's contents: coarse boundary nodes must read as zero
+    HIPCHK(launch_zero(p.ws, (used + 15) & ~size_t(15), s));
+    st = solve_interior_on(&p, model, d_P, o, info, s, t0);
+    // nothing of this call may still run when the next one clears the array
+    const hipError_t e = hipStreamSynchronize(s);
+    if (st == MHS_OK && e != hipSuccess)
+        return fail(MHS_ERR_HIP, "hipStreamSynchronize failed: %s", hipGetErrorString(e));
+    return st;
 }
 
 } // extern "C"

@@ -232,6 +232,8 @@ hipError_t launch_prep3(const PrepItem *items, int nitems, int64_t nthreads, hip
 hipError_t launch_prep2(const PrepItem *items, int nitems, int64_t nthreads, hipStream_t s);
 hipError_t launch_copy(const double *src, double *dst, int64_t n, const SolveState *skip,
                        hipStream_t s);
+// dst[0 .. bytes) = 0; dst 16-byte aligned, bytes a multiple of 16
+hipError_t launch_zero(void *dst, size_t bytes, hipStream_t s);
 
 // tile counts
 inline int ceil_div(int a, int b) { return (a + b - 1) / b; }

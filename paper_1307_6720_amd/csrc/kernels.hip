@@ -2094,6 +2094,14 @@ __global__ __launch_bounds__(256) void k_copy(const double *__restrict__ src, do
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) dst[e] = src[e];
 }
 
+// dst[0 .. n) = 0 in 16-byte words (a fill kernel rather than a memset, so
+// the clear can sit in a captured stream).
+__global__ __launch_bounds__(256) void k_zero(uint4 *__restrict__ dst, int64_t n)
+{
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
+        dst[e] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 template <typename T>
 hipError_t sweep3_dispatch(const LevelItem *items, int nitems, int ntiles, int flags, hipStream_t s)
 {
@@ -2294,6 +2302,17 @@ hipError_t launch_prep2(const PrepItem *items, int nitems, int64_t nthreads, hip
     if (nthreads <= 0) return hipSuccess;
     const int64_t blocks = (nthreads + 255) / 256;
     hipLaunchKernelGGL(k_prep2, dim3((unsigned)blocks), dim3(256), 0, s, items, nitems);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void *dst, size_t bytes, hipStream_t s)
+{
+    if (bytes == 0) return hipSuccess;
+    if (((uintptr_t)dst | bytes) & 15) return hipErrorInvalidValue;
+    const int64_t n = (int64_t)(bytes / 16);
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, (uint4 *)dst, n);
     return hipGetLastError();
 }
 

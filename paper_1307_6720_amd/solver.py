@@ -135,6 +135,26 @@ def check_model(grid, model):
     return lam.value, lv.value
 
 
+def solve_interior_noalloc(grid, model, P, opts=None, raise_on_error=True):
+    """Equation (8) in place on P's device without a plan or workspace
+    (mhs_solve_interior_noalloc): the library's fixed scratch array holds
+    the hierarchy, so grids up to 129^3 only; same results as
+    Plan.solve_interior.  Plane 0 of P must already hold the base solution."""
+    g = _grid(grid)
+    if not isinstance(P, torch.Tensor) or P.device.type != "cuda":
+        raise ValueError("P must be a CUDA tensor")
+    check_array(P, (g.nz, g.ny, g.nx), torch.float64, P.device, "P")
+    opts = opts or make_opts()
+    m = _ModelArgs.of(model)
+    info = _lib.Info()
+    with torch.cuda.device(P.device):
+        code = _lib.lib().mhs_solve_interior_noalloc(C.byref(g), C.byref(m.c), _ptr(P), C.byref(opts),
+                                                     C.byref(info), _stream(P.device))
+    if raise_on_error:
+        check(code)
+    return info
+
+
 def _grid(grid):
     if isinstance(grid, _lib.Grid):
         return grid

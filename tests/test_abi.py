@@ -97,6 +97,32 @@ def test_plan_create_rejects_small_or_misaligned_workspace():
     assert L.mhs_plan_create(C.byref(g), 3, C.c_void_p(4096 + 8), n, C.byref(h)) == _lib.ERR_WORKSPACE
 
 
+def test_noalloc_solve_refuses_grids_past_its_array():
+    """The interior solve without allocation holds its hierarchy in a fixed
+    48 MiB device array: a grid whose workspace does not fit (257^3) is
+    refused on the host before any device call, and so are bad arguments."""
+    L = _lib.lib()
+    o = _lib.Opts()
+    L.mhs_default_opts(C.byref(o))
+    xi = (C.c_double * 257)()
+    m = _lib.Model(0.0, xi, None, None, None, 1.0, 1.0)
+    fake = C.c_void_p(1 << 20)  # never dereferenced: the size check comes first
+    for prec in (_lib.PREC_FP64, _lib.PREC_MIXED):
+        o.precision = prec
+        g = _lib.Grid(257, 257, 257, 1.0, 1.0, 1.0)
+        assert L.mhs_solve_interior_noalloc(C.byref(g), C.byref(m), fake, C.byref(o), None,
+                                            None) == _lib.ERR_WORKSPACE
+        assert b"scratch" in L.mhs_last_error()
+    g = _lib.Grid(129, 129, 129, 1.0, 1.0, 1.0)
+    assert L.mhs_solve_interior_noalloc(C.byref(g), C.byref(m), None, C.byref(o), None, None) == _lib.ERR_INVALID_ARG
+    bad = _lib.Grid(32, 33, 33, 1.0, 1.0, 1.0)
+    assert L.mhs_solve_interior_noalloc(C.byref(bad), C.byref(m), fake, C.byref(o), None, None) == _lib.ERR_GRID
+    # the largest grid it serves fits with either precision
+    for prec in (_lib.PREC_FP64, _lib.PREC_MIXED):
+        code, n = ws_bytes(129, 129, 129, prec=prec)
+        assert code == _lib.MHS_OK and n - 256 <= 48 << 20
+
+
 def test_request_bytes_counts_workspace_and_arrays():
     for dims in ((33, 33, 33), (257, 257, 257), (129, 129, 65)):
         g = _lib.Grid(*dims, 1.0, 1.0, 1.0)
