@@ -65,6 +65,8 @@ def _load():
         f = getattr(lib, name)
         f.restype = res
         f.argtypes = args
+    # one thread unless asked (set_threads): test workers run side by side
+    lib.ref_set_threads(1)
     _lib = lib
     return lib
 
