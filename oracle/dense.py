@@ -93,3 +93,48 @@ def solve2(bz0, lx=1.0, ly=1.0, edges=None):
     x = np.linalg.solve(A, rhs.reshape(-1))
     P0[1:-1, 1:-1] = x.reshape(ny - 2, nx - 2)
     return P0
+
+
+def general_operator(a, b, u_bc, lengths=(1.0, 1.0, 1.0)):
+    """Dense matrix of a lap_h + b (Section 2.2's general form, central
+    differences, not divided by a) over the interior unknowns of u_bc's grid
+    (3D (nz, ny, nx) or a face (ny, nx) with the lengths of its two axes),
+    and the right-hand-side shift -(couplings to u_bc's boundary values)."""
+    u_bc = np.asarray(u_bc, dtype=np.float64)
+    nd = u_bc.ndim
+    shape = u_bc.shape
+    h = [l / (n - 1) for n, l in zip(shape[::-1], lengths)]  # (hx, hy[, hz])
+    inner = [n - 2 for n in shape]
+    idx = np.arange(int(np.prod(inner))).reshape(inner)
+    m = idx.size
+    A = np.zeros((m, m))
+    shift = np.zeros(m)
+    for node in np.ndindex(*inner):
+        p = tuple(q + 1 for q in node)  # array index (k, j, i) or (j, i)
+        r = idx[node]
+        av = a[p]
+        A[r, r] = b[p] - 2.0 * av * sum(1.0 / hh**2 for hh in h)
+        for axis in range(nd):
+            hh = h[nd - 1 - axis]  # array axis 0 is z (3D) or y (2D)
+            for step in (-1, 1):
+                q = list(p)
+                q[axis] += step
+                q = tuple(q)
+                if 0 < q[axis] < shape[axis] - 1:
+                    A[r, idx[tuple(v - 1 for v in q)]] += av / hh**2
+                else:
+                    shift[r] -= av / hh**2 * u_bc[q]
+    return A, shift
+
+
+def general(a, b, c, u_bc, lengths=(1.0, 1.0, 1.0)):
+    """Exact discrete solution of a lap_h u + b u = c with u_bc's boundary
+    values as Dirichlet data (shapes as general_operator)."""
+    u_bc = np.asarray(u_bc, dtype=np.float64)
+    nd = u_bc.ndim
+    inner = tuple(slice(1, -1) for _ in range(nd))
+    A, shift = general_operator(a, b, u_bc, lengths)
+    x = np.linalg.solve(A, np.asarray(c, dtype=np.float64)[inner].reshape(-1) + shift)
+    u = u_bc.copy()
+    u[inner] = x.reshape(u[inner].shape)
+    return u

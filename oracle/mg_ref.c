@@ -39,6 +39,10 @@
  * r_0 the residual of the initial iterate (P = 0 in the interior, step 1 of
  * the procedure in Section 2.2).
  *
+ * The last section solves the general scalar problem Section 2.2 reduces
+ * the model to, a(x) lap u + b(x) u = c(x) with u given on the boundary, in
+ * the box or on one of its faces, by the same multigrid (ref_gen_*).
+ *
  * Each function below is a direct loop over the definition it cites; there
  * is no blocking or fusion.  OpenMP pragmas (when built with -fopenmp)
  * split the outer loop of the 3D residual, of each colour of a sweep and of
@@ -823,5 +827,354 @@ int ref_solve(const int *n, const double *len, const double *bz0, const double *
         info[2] = r2;
         info[3] = r3;
     }
+    return st;
+}
+
+/* ------------------------------------------------------------------ */
+/* The general scalar elliptic problem of Section 2.2                   */
+/*     a(x) lap u + b(x) u = c(x) in D,   u given on the boundary of D, */
+/* with lap the 3D Laplacian (interior) or the 2D one (a face of the    */
+/* box: `planar`, one plane of nx*ny nodes, spacings h[0], h[1]).       */
+/* ------------------------------------------------------------------ */
+/* Reading (the paper states the form, not a discretisation): each
+ * interior row is divided by a (a != 0 on interior nodes), giving
+ *     lap_h u + beta u = gamma,  beta = b/a,  gamma = c/a,
+ * which has the same discrete solution; the multigrid below works on this
+ * form (its residual and stopping rule included) with 7-point (5-point)
+ * central differences, red-black Gauss-Seidel, the full weighting and
+ * interpolation of the problems above, the same coarsening rule, beta
+ * sampled at the coarse nodes (as xi is), and an exact solve on the
+ * coarsest grid.  The problem must be definite with room to spare: beta
+ * at most half the smallest eigenvalue of -lap_h on the coarsest grid
+ * (REF_INDEFINITE otherwise), so that every level's operator is definite
+ * and no coarse correction over-corrects the lowest mode. */
+#define REF_INDEFINITE (-4)
+
+typedef struct {
+    int n[3];     /* nodes per axis (n[2] = 1 when planar) */
+    double h[3];  /* spacings (h[2] unused when planar) */
+    int planar;
+} gdom;
+
+static int gen_interior(const gdom *d, int i, int j, int k)
+{
+    if (i < 1 || i > d->n[0] - 2 || j < 1 || j > d->n[1] - 2) return 0;
+    return d->planar ? k == 0 : (k >= 1 && k <= d->n[2] - 2);
+}
+
+/* (lap_h u + beta u) at an interior node */
+static double gen_op_at(const gdom *d, const double *u, const double *beta, int i, int j, int k)
+{
+    int nx = d->n[0], ny = d->n[1];
+    double c = AT3(u, i, j, k);
+    double v = (AT3(u, i + 1, j, k) - 2.0 * c + AT3(u, i - 1, j, k)) / (d->h[0] * d->h[0]) +
+               (AT3(u, i, j + 1, k) - 2.0 * c + AT3(u, i, j - 1, k)) / (d->h[1] * d->h[1]);
+    if (!d->planar) v += (AT3(u, i, j, k + 1) - 2.0 * c + AT3(u, i, j, k - 1)) / (d->h[2] * d->h[2]);
+    return v + AT3(beta, i, j, k) * c;
+}
+
+static void gen_dom(gdom *d, const int *n, const double *h, int planar)
+{
+    d->planar = planar;
+    d->n[0] = n[0];
+    d->n[1] = n[1];
+    d->n[2] = planar ? 1 : n[2];
+    d->h[0] = h[0];
+    d->h[1] = h[1];
+    d->h[2] = planar ? 1.0 : h[2];
+}
+
+/* beta = b/a, gamma = c/a on interior nodes, 0 elsewhere; REF_SINGULAR if
+ * a vanishes (or any value is not finite) at an interior node. */
+int ref_gen_normalise(const int *n, int planar, const double *a, const double *b, const double *c,
+                      double *beta, double *gamma)
+{
+    gdom d;
+    double h[3] = {1.0, 1.0, 1.0};
+    gen_dom(&d, n, h, planar);
+    int nx = d.n[0], ny = d.n[1], nz = d.n[2];
+    int st = REF_OK;
+    for (int k = 0; k < nz; k++)
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++) {
+                double bv = 0.0, gv = 0.0;
+                if (gen_interior(&d, i, j, k)) {
+                    double av = AT3(a, i, j, k);
+                    if (av == 0.0 || !isfinite(av) || !isfinite(AT3(b, i, j, k)) || !isfinite(AT3(c, i, j, k)))
+                        st = REF_SINGULAR;
+                    bv = AT3(b, i, j, k) / av;
+                    gv = AT3(c, i, j, k) / av;
+                }
+                AT3(beta, i, j, k) = bv;
+                AT3(gamma, i, j, k) = gv;
+            }
+    return st;
+}
+
+/* r = gamma - (lap_h u + beta u) on interior nodes, 0 elsewhere */
+void ref_gen_residual(const int *n, const double *h, int planar, const double *beta, const double *u,
+                      const double *gamma, double *r)
+{
+    gdom d;
+    gen_dom(&d, n, h, planar);
+    int nx = d.n[0], ny = d.n[1], nz = d.n[2];
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < nz; k++)
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++)
+                AT3(r, i, j, k) = gen_interior(&d, i, j, k)
+                                      ? AT3(gamma, i, j, k) - gen_op_at(&d, u, beta, i, j, k)
+                                      : 0.0;
+}
+
+/* nsweeps red-black Gauss-Seidel sweeps in place: every interior node with
+ * (i+j+k) even (red) solves its row for itself, then every odd one. */
+void ref_gen_rbgs(const int *n, const double *h, int planar, const double *beta, double *u,
+                  const double *gamma, int nsweeps)
+{
+    gdom d;
+    gen_dom(&d, n, h, planar);
+    int nx = d.n[0], ny = d.n[1], nz = d.n[2];
+    double sum = 2.0 / (d.h[0] * d.h[0]) + 2.0 / (d.h[1] * d.h[1]) + (planar ? 0.0 : 2.0 / (d.h[2] * d.h[2]));
+    for (int s = 0; s < nsweeps; s++)
+        for (int colour = 0; colour < 2; colour++) {
+#pragma omp parallel for schedule(static)
+            for (int k = 0; k < nz; k++)
+                for (int j = 0; j < ny; j++)
+                    for (int i = 0; i < nx; i++) {
+                        if (((i + j + k) & 1) != colour || !gen_interior(&d, i, j, k)) continue;
+                        /* the node's row: off + (beta - sum) u = gamma, off the
+                         * neighbour terms */
+                        double off = (AT3(u, i + 1, j, k) + AT3(u, i - 1, j, k)) / (d.h[0] * d.h[0]) +
+                                     (AT3(u, i, j + 1, k) + AT3(u, i, j - 1, k)) / (d.h[1] * d.h[1]);
+                        if (!planar) off += (AT3(u, i, j, k + 1) + AT3(u, i, j, k - 1)) / (d.h[2] * d.h[2]);
+                        AT3(u, i, j, k) = (AT3(gamma, i, j, k) - off) / (AT3(beta, i, j, k) - sum);
+                    }
+        }
+}
+
+/* beta on the next coarser grid: its value at the coincident fine node.
+ * kind: STEP_ALL, STEP_XY or STEP_Z (3D); planar grids halve x and y. */
+void ref_gen_inject(const int *nf, int planar, int kind, const double *bf, double *bc)
+{
+    int nx = nf[0], ny = nf[1], nz = planar ? 1 : nf[2];
+    int sx = (planar || kind != STEP_Z) ? 2 : 1, sz = (!planar && kind != STEP_XY) ? 2 : 1;
+    int ncx = (nx - 1) / sx + 1, ncy = (ny - 1) / sx + 1, ncz = planar ? 1 : (nz - 1) / sz + 1;
+    for (int K = 0; K < ncz; K++)
+        for (int J = 0; J < ncy; J++)
+            for (int I = 0; I < ncx; I++)
+                bc[(size_t)I + (size_t)ncx * ((size_t)J + (size_t)ncy * (size_t)K)] = AT3(bf, sx * I, sx * J, sz * K);
+}
+
+/* Exact solve of lap_h u + beta u = gamma on the interior nodes of one
+ * grid (Gaussian elimination); boundary values of u move to the right. */
+int ref_gen_direct(const int *n, const double *h, int planar, const double *beta, double *u,
+                   const double *gamma)
+{
+    gdom d;
+    gen_dom(&d, n, h, planar);
+    int nx = d.n[0], ny = d.n[1], nz = d.n[2];
+    int mx = nx - 2, my = ny - 2, mz = planar ? 1 : nz - 2, k0 = planar ? 0 : 1;
+    int m = mx * my * mz;
+    double *M = (double *)calloc((size_t)m * m, sizeof(double));
+    double *rhs = (double *)calloc((size_t)m, sizeof(double));
+    double *x = (double *)calloc((size_t)m, sizeof(double));
+    if (!M || !rhs || !x) {
+        free(M); free(rhs); free(x);
+        return REF_NOMEM;
+    }
+    double cx = 1.0 / (d.h[0] * d.h[0]), cy = 1.0 / (d.h[1] * d.h[1]), cz = planar ? 0.0 : 1.0 / (d.h[2] * d.h[2]);
+    for (int k = k0; k < k0 + mz; k++)
+        for (int j = 1; j < ny - 1; j++)
+            for (int i = 1; i < nx - 1; i++) {
+                int row = (i - 1) + mx * ((j - 1) + my * (k - k0));
+                M[(size_t)row * m + row] = AT3(beta, i, j, k) - 2.0 * (cx + cy + cz);
+                double rv = AT3(gamma, i, j, k);
+                int nb[6][3] = {{i + 1, j, k}, {i - 1, j, k}, {i, j + 1, k}, {i, j - 1, k}, {i, j, k + 1}, {i, j, k - 1}};
+                double cf[6] = {cx, cx, cy, cy, cz, cz};
+                for (int q = 0; q < (planar ? 4 : 6); q++) {
+                    int a = nb[q][0], bb = nb[q][1], c = nb[q][2];
+                    if (gen_interior(&d, a, bb, c))
+                        M[(size_t)row * m + ((a - 1) + mx * ((bb - 1) + my * (c - k0)))] += cf[q];
+                    else
+                        rv -= cf[q] * AT3(u, a, bb, c);
+                }
+                rhs[row] = rv;
+            }
+    int st = gauss_solve(M, rhs, x, m);
+    if (st == REF_OK)
+        for (int k = k0; k < k0 + mz; k++)
+            for (int j = 1; j < ny - 1; j++)
+                for (int i = 1; i < nx - 1; i++) AT3(u, i, j, k) = x[(i - 1) + mx * ((j - 1) + my * (k - k0))];
+    free(M); free(rhs); free(x);
+    return st;
+}
+
+typedef struct {
+    int n[3];
+    double h[3];
+    double *beta, *u, *f, *r;
+    size_t N;
+    int kind; /* step to the next level (3D); planar steps halve x and y */
+} glev;
+
+static void free_glev(glev *lv, int L)
+{
+    for (int l = 0; l < L; l++) {
+        free(lv[l].beta);
+        if (l > 0) { free(lv[l].u); free(lv[l].f); }
+        free(lv[l].r);
+    }
+}
+
+/* Levels of the general problem: the coarsening rule of the problems above
+ * (every axis halved, or x and y only, or z only, for 3D; x and y for a
+ * plane) with beta sampled at the coarse nodes. */
+static int build_glev(glev *lv, int L, const int *n, const double *len, int planar, const double *beta0, double *u0,
+                      const double *f0)
+{
+    memset(lv, 0, sizeof(glev) * (size_t)L);
+    int kinds[32] = {0};
+    if (!planar && ref_levels3(n, len, kinds) != L) return REF_BAD_GRID;
+    int nn[3] = {n[0], n[1], planar ? 1 : n[2]};
+    for (int l = 0; l < L; l++) {
+        for (int a = 0; a < 3; a++) {
+            lv[l].n[a] = nn[a];
+            lv[l].h[a] = (planar && a == 2) ? 1.0 : len[a] / (double)(nn[a] - 1);
+        }
+        lv[l].N = (size_t)nn[0] * nn[1] * nn[2];
+        lv[l].kind = planar ? STEP_XY : ((l < L - 1) ? kinds[l] : STEP_ALL);
+        lv[l].beta = (double *)calloc(lv[l].N, sizeof(double));
+        lv[l].r = (double *)calloc(lv[l].N, sizeof(double));
+        if (!lv[l].beta || !lv[l].r) return REF_NOMEM;
+        if (l == 0) {
+            memcpy(lv[0].beta, beta0, sizeof(double) * lv[0].N);
+            lv[l].u = u0;
+            lv[l].f = (double *)f0;
+        } else {
+            ref_gen_inject(lv[l - 1].n, planar, lv[l - 1].kind, lv[l - 1].beta, lv[l].beta);
+            lv[l].u = (double *)calloc(lv[l].N, sizeof(double));
+            lv[l].f = (double *)calloc(lv[l].N, sizeof(double));
+            if (!lv[l].u || !lv[l].f) return REF_NOMEM;
+        }
+        if (planar || lv[l].kind != STEP_Z) {
+            nn[0] = (nn[0] - 1) / 2 + 1;
+            nn[1] = (nn[1] - 1) / 2 + 1;
+        }
+        if (!planar && lv[l].kind != STEP_XY) nn[2] = (nn[2] - 1) / 2 + 1;
+    }
+    return REF_OK;
+}
+
+static int gen_vcycle(glev *lv, int l, int L, int planar, int nu1, int nu2)
+{
+    glev *c = &lv[l];
+    if (l == L - 1) return ref_gen_direct(c->n, c->h, planar, c->beta, c->u, c->f);
+    ref_gen_rbgs(c->n, c->h, planar, c->beta, c->u, c->f, nu1);
+    ref_gen_residual(c->n, c->h, planar, c->beta, c->u, c->f, c->r);
+    glev *d = &lv[l + 1];
+    if (planar)
+        ref_restrict2(c->n, c->r, d->f);
+    else if (c->kind == STEP_XY)
+        ref_restrict3_xy(c->n, c->r, d->f);
+    else if (c->kind == STEP_Z)
+        ref_restrict3_z(c->n, c->r, d->f);
+    else
+        ref_restrict3(c->n, c->r, d->f);
+    memset(d->u, 0, sizeof(double) * d->N);
+    int st = gen_vcycle(lv, l + 1, L, planar, nu1, nu2);
+    if (st != REF_OK) return st;
+    if (planar)
+        ref_prolong2(d->n, d->u, c->u);
+    else if (c->kind == STEP_XY)
+        ref_prolong3_xy(d->n, d->u, c->u);
+    else if (c->kind == STEP_Z)
+        ref_prolong3_z(d->n, d->u, c->u);
+    else
+        ref_prolong3(d->n, d->u, c->u);
+    ref_gen_rbgs(c->n, c->h, planar, c->beta, c->u, c->f, nu2);
+    return REF_OK;
+}
+
+/* Smallest eigenvalue of -lap_h (zero boundary) on an n-node grid: the
+ * sum over axes of (4/h^2) sin^2(pi/(2(n-1))). */
+static double gen_lap_lambda_min(const int *n, const double *h, int planar)
+{
+    const double pi = 3.14159265358979323846;
+    double s = 0.0;
+    for (int a = 0; a < (planar ? 2 : 3); a++) {
+        double t = sin(pi / (2.0 * (double)(n[a] - 1)));
+        s += 4.0 / (h[a] * h[a]) * t * t;
+    }
+    return s;
+}
+
+static double ref_norm3_interior_any(const int *n, int planar, const double *r)
+{
+    return planar ? ref_norm2_interior(n, r) : ref_norm3_interior(n, r);
+}
+
+/* Levels of the general problem's hierarchy (3D: the rule above; planar:
+ * both axes halved until one has 3 nodes). */
+int ref_gen_levels(const int *n, const double *len, int planar)
+{
+    return planar ? ref_nlevels2(n[0], n[1]) : ref_levels3(n, len, NULL);
+}
+
+/* Multigrid solve of a lap u + b u = c for u (x fastest; nz = 1 when planar)
+ * in place: u's boundary values are the Dirichlet data, its interior values
+ * the initial guess.  len = box lengths (len[2] unused when planar).  Runs
+ * V(nu1, nu2) cycles until ||r||/||r0|| <= rtol (r of the divided form) or
+ * max_cycles; with rtol < 0 runs exactly max_cycles cycles.  hist (may be
+ * NULL) receives ||r_c|| for c = 0..cycles. */
+int ref_gen_mg(const int *n, const double *len, int planar, const double *a, const double *b, const double *c,
+               double *u, double rtol, int max_cycles, int nu1, int nu2, int *cycles_out, double *relres_out,
+               double *hist)
+{
+    int L = ref_gen_levels(n, len, planar);
+    if (L < 1) return REF_BAD_GRID;
+    size_t N = (size_t)n[0] * n[1] * (planar ? 1 : n[2]);
+    double *beta = (double *)calloc(N, sizeof(double));
+    double *gamma = (double *)calloc(N, sizeof(double));
+    glev *lv = (glev *)calloc((size_t)L, sizeof(glev));
+    if (!beta || !gamma || !lv) {
+        free(beta); free(gamma); free(lv);
+        return REF_NOMEM;
+    }
+    int st = ref_gen_normalise(n, planar, a, b, c, beta, gamma);
+    if (st == REF_OK) st = build_glev(lv, L, n, len, planar, beta, u, gamma);
+    if (st == REF_OK) {
+        double bmax = -INFINITY;
+        for (size_t e = 0; e < N; e++)
+            if (beta[e] > bmax) bmax = beta[e];
+        if (!(bmax < 0.5 * gen_lap_lambda_min(lv[L - 1].n, lv[L - 1].h, planar))) st = REF_INDEFINITE;
+    }
+    int cycles = 0;
+    double r0 = 0.0, res = 0.0;
+    if (st == REF_OK) {
+        glev *f = &lv[0];
+        ref_gen_residual(f->n, f->h, planar, f->beta, f->u, f->f, f->r);
+        r0 = ref_norm3_interior_any(f->n, planar, f->r);
+        res = r0;
+        if (hist) hist[0] = r0;
+        st = (r0 == 0.0 && rtol >= 0.0) ? REF_OK : REF_NO_CONVERGENCE;
+        while (st == REF_NO_CONVERGENCE && cycles < max_cycles) {
+            int s2 = gen_vcycle(lv, 0, L, planar, nu1, nu2);
+            if (s2 != REF_OK) { st = s2; break; }
+            cycles++;
+            ref_gen_residual(f->n, f->h, planar, f->beta, f->u, f->f, f->r);
+            res = ref_norm3_interior_any(f->n, planar, f->r);
+            if (hist) hist[cycles] = res;
+            if (!isfinite(res) || res > 10.0 * r0) { st = REF_DIVERGED; break; }
+            if (rtol >= 0.0 && res <= rtol * r0) st = REF_OK;
+        }
+        if (rtol < 0.0 && st == REF_NO_CONVERGENCE) st = REF_OK;
+    }
+    if (cycles_out) *cycles_out = cycles;
+    if (relres_out) *relres_out = (r0 > 0.0) ? res / r0 : 0.0;
+    free_glev(lv, L);
+    free(lv);
+    free(beta);
+    free(gamma);
     return st;
 }

@@ -16,6 +16,7 @@ import numpy as np
 from .build import LIB, build
 
 OK, NO_CONVERGENCE, DIVERGED = 0, 1, 2
+BAD_GRID, SINGULAR, NOMEM, INDEFINITE = -1, -2, -3, -4
 
 _lib = None
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
@@ -32,6 +33,14 @@ def _load():
     vp = C.c_void_p
     sig = {
         "ref_set_threads": (C.c_int, [C.c_int]),
+        "ref_gen_mg": (C.c_int, [_ip, _dp, C.c_int, _dp, _dp, _dp, _dp, C.c_double, C.c_int, C.c_int, C.c_int,
+                                 C.POINTER(C.c_int), C.POINTER(C.c_double), vp]),
+        "ref_gen_levels": (C.c_int, [_ip, _dp, C.c_int]),
+        "ref_gen_residual": (None, [_ip, _dp, C.c_int, _dp, _dp, _dp, _dp]),
+        "ref_gen_normalise": (C.c_int, [_ip, C.c_int, _dp, _dp, _dp, _dp, _dp]),
+        "ref_gen_rbgs": (None, [_ip, _dp, C.c_int, _dp, _dp, _dp, C.c_int]),
+        "ref_gen_direct": (C.c_int, [_ip, _dp, C.c_int, _dp, _dp, _dp]),
+        "ref_gen_inject": (None, [_ip, C.c_int, C.c_int, _dp, _dp]),
         "ref_levels3": (C.c_int, [_ip, _dp, _ip]),
         "ref_nlevels2": (C.c_int, [C.c_int, C.c_int]),
         "ref_residual3": (None, [_ip, _dp, _dp, C.c_double, _dp, vp, _dp]),
@@ -298,3 +307,92 @@ def solve(bz0, xi, alpha, shape, lengths=(1.0, 1.0, 1.0), rtol2=1e-10, rtol3=1e-
                            _f64(xi), alpha, P, rtol2, rtol3, max_cycles, nu1, nu2, info)
     return P, st, dict(cycles2d=int(info[0]), cycles3d=int(info[1]),
                        relres2d=float(info[2]), relres3d=float(info[3]))
+
+
+# ---------------------------------------------------------------- the general operator
+def gen_mg(u, a, b, c, rtol=1e-10, max_cycles=50, nu1=2, nu2=2, lengths=(1.0, 1.0, 1.0), planar=False):
+    """Multigrid solve of a lap u + b u = c (Section 2.2's general form) in
+    place of a copy of u: 3D arrays (nz, ny, nx), or planar (ny, nx) arrays
+    for a face (lengths of its two axes).  u's boundary values are the
+    Dirichlet data.  rtol < 0 runs exactly max_cycles cycles.  Returns
+    (u, status, cycles, relres, hist)."""
+    u = _f64(u).copy()
+    a, b, c = _f64(a), _f64(b), _f64(c)
+    n = _n2(u.shape) if planar else _n3(u.shape)
+    if planar:
+        n = np.array([n[0], n[1], 1], dtype=np.int32)
+    ln = np.asarray(lengths, dtype=np.float64)
+    if ln.size < 3:
+        ln = np.concatenate([ln, [1.0] * (3 - ln.size)])
+    cyc = C.c_int(0)
+    rel = C.c_double(0.0)
+    hist = np.zeros(max_cycles + 1)
+    st = _load().ref_gen_mg(n, ln, 1 if planar else 0, a, b, c, u, float(rtol), int(max_cycles), int(nu1), int(nu2),
+                            C.byref(cyc), C.byref(rel), hist.ctypes.data_as(C.c_void_p))
+    return u, st, cyc.value, rel.value, hist[: cyc.value + 1]
+
+
+def gen_levels(shape, lengths=(1.0, 1.0, 1.0), planar=False):
+    n = _n2(shape) if planar else _n3(shape)
+    if planar:
+        n = np.array([n[0], n[1], 1], dtype=np.int32)
+    ln = np.asarray(list(lengths) + [1.0] * (3 - len(lengths)), dtype=np.float64)
+    return _load().ref_gen_levels(n, ln, 1 if planar else 0)
+
+
+def gen_residual(u, a, b, c, lengths=(1.0, 1.0, 1.0), planar=False):
+    """Residual c/a - (lap_h u + (b/a) u) of the divided form on interior
+    nodes (0 elsewhere)."""
+    u, a, b, c = _f64(u), _f64(a), _f64(b), _f64(c)
+    n = _n2(u.shape) if planar else _n3(u.shape)
+    if planar:
+        n = np.array([n[0], n[1], 1], dtype=np.int32)
+    beta, gamma, r = np.zeros_like(u), np.zeros_like(u), np.zeros_like(u)
+    st = _load().ref_gen_normalise(n, 1 if planar else 0, a, b, c, beta, gamma)
+    if planar:
+        h = np.array([lengths[0] / (u.shape[1] - 1), lengths[1] / (u.shape[0] - 1), 1.0])
+    else:
+        h = _h(u.shape, lengths)
+    _load().ref_gen_residual(n, h, 1 if planar else 0, beta, u, gamma, r)
+    return r, st
+
+
+def _gen_nh(shape, lengths, planar):
+    if planar:
+        ny, nx = shape
+        return (np.array([nx, ny, 1], dtype=np.int32),
+                np.array([lengths[0] / (nx - 1), lengths[1] / (ny - 1), 1.0]))
+    return _n3(shape), _h(shape, lengths)
+
+
+def gen_rbgs(u, beta, gamma, nsweeps=1, lengths=(1.0, 1.0, 1.0), planar=False):
+    """Red-black Gauss-Seidel sweeps of lap_h u + beta u = gamma on a copy."""
+    u = _f64(u).copy()
+    n, h = _gen_nh(u.shape, lengths, planar)
+    _load().ref_gen_rbgs(n, h, 1 if planar else 0, _f64(beta), u, _f64(gamma), int(nsweeps))
+    return u
+
+
+def gen_direct(u, beta, gamma, lengths=(1.0, 1.0, 1.0), planar=False):
+    """Exact solve of lap_h u + beta u = gamma (u's boundary as data)."""
+    u = _f64(u).copy()
+    n, h = _gen_nh(u.shape, lengths, planar)
+    st = _load().ref_gen_direct(n, h, 1 if planar else 0, _f64(beta), u, _f64(gamma))
+    return u, st
+
+
+def gen_inject(beta, kind=0, planar=False):
+    """beta on the next coarser grid (kind: STEP_ALL, STEP_XY, STEP_Z)."""
+    beta = _f64(beta)
+    if planar:
+        ny, nx = beta.shape
+        n = np.array([nx, ny, 1], dtype=np.int32)
+        out = np.zeros(((ny - 1) // 2 + 1, (nx - 1) // 2 + 1))
+    else:
+        nz, ny, nx = beta.shape
+        n = _n3(beta.shape)
+        sx = 1 if kind == STEP_Z else 2
+        sz = 1 if kind == STEP_XY else 2
+        out = np.zeros(((nz - 1) // sz + 1, (ny - 1) // sx + 1, (nx - 1) // sx + 1))
+    _load().ref_gen_inject(n, 1 if planar else 0, int(kind), beta, out)
+    return out
