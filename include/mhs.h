@@ -61,6 +61,8 @@ extern "C" {
 /* ---- precisions (bit mask for plans, single value for a solve) -------- */
 #define MHS_PREC_FP64 1  /* FP64 V(nu1,nu2) cycles                          */
 #define MHS_PREC_MIXED 2 /* FP32 V-cycles inside FP64 iterative refinement  */
+#define MHS_PLAN_GENERAL 4 /* plan mask only: the plan also serves
+                              mhs_solve_general and mhs_solve_face        */
 
 typedef struct mhs_grid {
     int32_t nx, ny, nz; /* nodes per axis, each 2^L + 1, L >= 2            */
@@ -123,7 +125,9 @@ int32_t mhs_version(void);
 const char *mhs_last_error(void);
 
 /* Bytes of device workspace a plan for `grid` needs.  `precisions` is a
- * bit mask of MHS_PREC_* paths the plan must support.  Validates the grid
+ * bit mask of MHS_PREC_* paths the plan must support (at least one), plus
+ * MHS_PLAN_GENERAL for the general-operator entry points (about 3.4 more
+ * doubles per node of the grid, and the same for its faces).  Validates the grid
  * (MHS_ERR_GRID for a bad axis). */
 int mhs_workspace_bytes(const mhs_grid *grid, int32_t precisions, size_t *bytes);
 
@@ -205,6 +209,54 @@ int mhs_solve_interior(mhs_plan *plan, const mhs_model *model, double *d_P, cons
  * nx*ny*nz doubles on the device.  Asynchronous. */
 int mhs_fields(mhs_plan *plan, const mhs_model *model, const double *d_P, double *d_Bx,
                double *d_By, double *d_Bz, double *d_p, double *d_rho, void *stream);
+
+/* ---- the general elliptic problem (Section 2.2) -------------------------- *
+ * Section 2.2 reduces the model to scalar problems of the form
+ *     a(x) lap u + b(x) u = c(x) in D,  u given on the boundary of D,
+ * with lap the 3D Laplacian in the interior or the 2D one on a boundary
+ * face, and notes that elliptic problems other than (11) may be posed on
+ * the other faces.  These entry points solve that form with per-node a, b,
+ * c (second-order central differences, the plan's grid) by FP64 V(nu1,nu2)
+ * multigrid: each interior row is divided by a (lap u + (b/a) u = c/a, the
+ * same discrete solution; the residual and stopping rule are those of this
+ * form), red-black Gauss-Seidel, the full weighting, interpolation and
+ * coarsening of the solve of (8), b/a sampled at the coarse nodes, and an
+ * exact solve of the coarsest grid (at most 96 unknowns, else
+ * MHS_ERR_UNSUPPORTED).  The plan must have been created with
+ * MHS_PLAN_GENERAL in its mask (else MHS_ERR_UNSUPPORTED);
+ * opts->precision must be MHS_PREC_FP64; opts->faces is ignored (the
+ * boundary values in u are always the data).  Errors before any cycle:
+ * MHS_ERR_INVALID_ARG if a vanishes or a, b, c are not finite at an
+ * interior node; MHS_ERR_INDEFINITE unless max(b/a) stays below half the
+ * smallest eigenvalue of -lap on the coarsest grid (then every level is
+ * definite and no coarse correction over-corrects the lowest mode).  The
+ * call reads back once after that check and then like the other solves. */
+
+/* 3D: d_a, d_b, d_c, d_u: device, nx*ny*nz doubles (x fastest).  u's
+ * boundary nodes are the Dirichlet data (not modified); its interior
+ * starts from 0 unless opts->warm_start and receives the solution. */
+int mhs_solve_general(mhs_plan *plan, const double *d_a, const double *d_b, const double *d_c, double *d_u,
+                      const mhs_opts *opts, mhs_info *info, void *stream);
+
+/* A face of the box: the 2D problem on face `face` of d_P (nx*ny*nz
+ * doubles), with the face's own edges (values in d_P) as Dirichlet data;
+ * the interior nodes of that face of d_P receive the solution, nothing else
+ * of d_P is written.  Face coordinates (first index fastest) and the shape
+ * of d_a, d_b, d_c (device, contiguous):
+ *   MHS_FACE_BASE (z = 0), MHS_FACE_TOP (z = lz): (x, y), ny*nx values;
+ *   MHS_FACE_XLO (x = 0), MHS_FACE_XHI (x = lx): (y, z), nz*ny values;
+ *   MHS_FACE_YLO (y = 0), MHS_FACE_YHI (y = ly): (x, z), nz*nx values.
+ * Filling the side and top faces this way and then calling
+ * mhs_solve_interior with opts->faces = MHS_FACES_GIVEN poses (8) with
+ * boundary data from elliptic problems on every face. */
+#define MHS_FACE_BASE 0
+#define MHS_FACE_TOP 1
+#define MHS_FACE_XLO 2
+#define MHS_FACE_XHI 3
+#define MHS_FACE_YLO 4
+#define MHS_FACE_YHI 5
+int mhs_solve_face(mhs_plan *plan, int32_t face, const double *d_a, const double *d_b, const double *d_c,
+                   double *d_P, const mhs_opts *opts, mhs_info *info, void *stream);
 
 /* ---- stage entry points (kernel-level checks; asynchronous) ----------- *
  * `space` is 3 (equation (8) at 3D level `level`) or 2 (equation (11) at
@@ -313,8 +365,9 @@ int mhs_trace_field_lines(mhs_plan *plan, const double *d_Bx, const double *d_By
 #define MHS_PROF_COARSE 5      /* every other stencil launch (levels >= 1, 2D, z-only prolongation) */
 #define MHS_PROF_DIAG 6        /* diagnostics (mhs_diagnostics)            */
 #define MHS_PROF_TRACE 7       /* field lines (mhs_trace_field_lines)      */
-#define MHS_PROF_NCLASS 8
-#define MHS_PROF_ALL 0xff      /* mask of every class                      */
+#define MHS_PROF_GENERAL 8     /* general operator (mhs_solve_general, _face) */
+#define MHS_PROF_NCLASS 9
+#define MHS_PROF_ALL 0x1ff     /* mask of every class                      */
 
 /* class_mask: bit (1 << MHS_PROF_x) times class x; 0 disables profiling. */
 int mhs_profile_enable(mhs_plan *plan, int32_t class_mask);

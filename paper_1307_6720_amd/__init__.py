@@ -6,9 +6,9 @@ marshals torch tensors into it.  Importing the package does not load the
 library; the first call does, and fails loudly if it has not been built.
 """
 
-from ._lib import PREC_FP64, PREC_MIXED, MHSError  # noqa: F401
+from ._lib import PLAN_GENERAL, PREC_FP64, PREC_MIXED, MHSError  # noqa: F401
 
-__all__ = ["PREC_FP64", "PREC_MIXED", "MHSError", "Plan", "solve", "make_opts", "workspace_bytes"]
+__all__ = ["PREC_FP64", "PREC_MIXED", "PLAN_GENERAL", "MHSError", "Plan", "solve", "make_opts", "workspace_bytes"]
 
 
 def __getattr__(name):

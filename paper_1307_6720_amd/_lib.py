@@ -30,9 +30,11 @@ ERR_NO_CONVERGENCE, ERR_DIVERGED, ERR_BUDGET, ERR_WORKSPACE, ERR_HIP, ERR_UNSUPP
 
 PREC_FP64 = 1
 PREC_MIXED = 2
+PLAN_GENERAL = 4  # plan mask bit: the general-operator entry points
+FACE_BASE, FACE_TOP, FACE_XLO, FACE_XHI, FACE_YLO, FACE_YHI = range(6)
 
 PROF_SMOOTH_L0, PROF_REFINE, PROF_RESTRICT_L0, PROF_FIELDS, PROF_BOTTOM, PROF_COARSE = range(6)
-PROF_NAMES = ("smooth_l0", "refine", "restrict_l0", "fields", "bottom", "coarse", "diag", "trace")
+PROF_NAMES = ("smooth_l0", "refine", "restrict_l0", "fields", "bottom", "coarse", "diag", "trace", "general")
 LINE_MAX_STEPS, LINE_EXIT, LINE_NULL = 0, 1, 2
 FACES_ZERO, FACES_GIVEN = 0, 1
 
@@ -99,6 +101,8 @@ def lib():
         "mhs_solve_interior": (C.c_int, [vp, P(Model), vp, P(Opts), P(Info), vp]),
         "mhs_solve_interior_noalloc": (C.c_int, [P(Grid), P(Model), vp, P(Opts), P(Info), vp]),
         "mhs_fields": (C.c_int, [vp, P(Model), vp, vp, vp, vp, vp, vp, vp]),
+        "mhs_solve_general": (C.c_int, [vp, vp, vp, vp, vp, P(Opts), P(Info), vp]),
+        "mhs_solve_face": (C.c_int, [vp, i32, vp, vp, vp, vp, P(Opts), P(Info), vp]),
         "mhs_stage_smooth": (C.c_int, [vp, P(Model), i32, i32, i32, vp, vp, i32, i32, vp]),
         "mhs_stage_restrict": (C.c_int, [vp, P(Model), i32, i32, i32, vp, vp, vp, vp]),
         "mhs_stage_correct_smooth": (C.c_int, [vp, P(Model), i32, i32, i32, vp, vp, vp, vp]),

@@ -36,7 +36,6 @@ int fail(int code, const char *fmt, ...)
     return code;
 }
 
-constexpr size_t kAlign = 256;
 constexpr size_t kStagingBytes = 1 << 20;
 // Workgroups a stencil launch aims for: about as many as fit on the chip at
 // once (4-5 per CU on 256 CUs), so that one round of resident groups covers
@@ -75,19 +74,6 @@ int chunk(int planes, int xy_tiles, int cap, int target = kTargetGroups)
     const long want = ((long)planes * xy_tiles + target - 1) / target;
     return (int)std::max(1L, std::min((long)cap, want));
 }
-
-struct Carver {
-    char *base;
-    size_t off = 0;
-    template <typename T>
-    T *take(size_t count)
-    {
-        off = (off + kAlign - 1) & ~(kAlign - 1);
-        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
-        off += count * sizeof(T);
-        return p;
-    }
-};
 
 bool valid_axis(int n)
 {
@@ -263,6 +249,7 @@ size_t carve_plan(mhs_plan *p, char *base, int precisions)
     p->d_scratch_norm = cv.take<double>(p->scratch_npart);
     p->stage.dev = cv.take<char>(kStagingBytes);
     p->stage.cap = kStagingBytes;
+    if (precisions & MHS_PLAN_GENERAL) gen_create(p, cv);
     return cv.off + kAlign;
 }
 
@@ -971,11 +958,19 @@ hipError_t exec_launch(const Launch &L, hipStream_t s)
         return launch_prep3((const PrepItem *)L.items, L.nitems, L.n, s);
     case Launch::kPrep2:
         return launch_prep2((const PrepItem *)L.items, L.nitems, L.n, s);
+    case Launch::kGenSweep:
+    case Launch::kGenResid:
+    case Launch::kGenRestrict:
+    case Launch::kGenProlong:
+    case Launch::kGenCoarsest:
+        return gen_exec(L, s);
+    case Launch::kZero:
+        return launch_zero(L.dst, (size_t)L.n, s);
     }
     return hipErrorInvalidValue;
 }
 
-int run_program(mhs_plan *p, const Program &pg, hipStream_t s, int cycle = -1)
+int run_program(mhs_plan *p, const Program &pg, hipStream_t s, int cycle)
 {
     Profiler &pr = p->prof;
     for (const Launch &L : pg.launches) {
@@ -1139,7 +1134,8 @@ int mhs_workspace_bytes(const mhs_grid *grid, int32_t precisions, size_t *bytes)
     if (!bytes) return fail(MHS_ERR_INVALID_ARG, "bytes is NULL");
     int st = check_grid(grid);
     if (st) return st;
-    if (precisions <= 0 || precisions > 3) return fail(MHS_ERR_INVALID_ARG, "precisions must be a mask of 1|2");
+    if (precisions <= 0 || precisions > 7 || (precisions & 3) == 0)
+        return fail(MHS_ERR_INVALID_ARG, "precisions must be a mask of 1|2 (at least one), optionally with 4");
     mhs_plan tmp;
     st = geometry(&tmp, grid);
     if (st) return st;

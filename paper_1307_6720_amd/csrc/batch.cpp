@@ -346,8 +346,9 @@ size_t item_size(Launch::Kind k)
         return sizeof(PrepItem);
     case Launch::kCopy:
         return 0;
+    default: // the general operator's launches are never batched
+        return 0;
     }
-    return 0;
 }
 
 bool same_variant(const Launch &a, const Launch &b)

@@ -2,7 +2,9 @@
 // workspace, coefficient tables, launch programs and the C-ABI glue.
 #pragma once
 
+#include <chrono>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -12,6 +14,23 @@
 namespace mhs {
 
 enum Path : int { kF64 = 0, kF32 = 1 };
+
+constexpr size_t kAlign = 256;
+
+// Carves 256-byte aligned regions out of a workspace (base == nullptr:
+// only counts the bytes).
+struct Carver {
+    char *base;
+    size_t off = 0;
+    template <typename T>
+    T *take(size_t count)
+    {
+        off = (off + kAlign - 1) & ~(kAlign - 1);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
 
 struct Level {
     int n[3] = {0, 0, 0}; // nx, ny, nz (nz = 1 for the 2D problem)
@@ -59,7 +78,9 @@ struct Hierarchy {
 struct Launch {
     enum Kind {
         kSweep3, kSweep2, kRestrict3, kRestrict2, kIr3, kBottom, kFinalize, kCopy, kFields, kPrep3, kPrep2,
-        kRestrict3Z, kProlong3Z
+        kRestrict3Z, kProlong3Z,
+        // the general operator (general.hip): items are GenItem
+        kGenSweep, kGenResid, kGenRestrict, kGenProlong, kGenCoarsest, kZero
     } kind;
     int flags = 0;
     bool dbl = true;
@@ -170,6 +191,26 @@ void add_ir_step(Program &pg, Staging &st, const Hierarchy &h, const double *uin
 FieldsItem fields_item(const mhs_plan *p, const mhs_model *model, const double *tab, const double *P, double *Bx,
                        double *By, double *Bz, double *pr, double *rho);
 hipError_t exec_launch(const Launch &L, hipStream_t s);
+int run_program(mhs_plan *p, const Program &pg, hipStream_t s, int cycle = -1);
+int begin_staging(mhs_plan *p);
+int flush_staging(mhs_plan *p, hipStream_t s);
+int read_state(mhs_plan *p, const SolveState *d_state, SolveState *out, hipStream_t s);
+int drive(mhs_plan *p, const Program &cycle, const SolveState *d_state, const mhs_opts *o, SolveState *out,
+          int *syncs, hipStream_t s);
+double seconds_since(std::chrono::steady_clock::time_point t0);
+
+// Shapes and step kinds of a multigrid hierarchy (api.cpp).
+int build_geometry(Hierarchy &h, const int n0[3], const double len[3], bool planar);
+
+// ---- the general operator (general.hip) -----------------------------------
+struct GenPlan;
+// Geometry of the general problems' hierarchies (3D and the three face
+// orientations) and their buffers; base == nullptr only counts bytes.
+void gen_create(mhs_plan *p, Carver &cv);
+struct GenPlanDeleter {
+    void operator()(GenPlan *g) const;
+};
+hipError_t gen_exec(const Launch &L, hipStream_t s);
 // Next timing event of the profiler's pool (created on first use); nullptr on failure.
 hipEvent_t prof_event(Profiler &pr);
 
@@ -191,4 +232,5 @@ struct mhs_plan {
     double *d_scratch_norm = nullptr;    // stage residual-norm partials
     int scratch_npart = 0;
     mhs::Profiler prof;
+    std::unique_ptr<mhs::GenPlan, mhs::GenPlanDeleter> gen; // the general operator (MHS_PLAN_GENERAL)
 };

@@ -245,6 +245,50 @@ class Plan:
             check(code)
         return info
 
+    # ---- the general elliptic problem of Section 2.2 ---------------------------
+    def solve_general(self, a, b, c, u, opts=None, raise_on_error=True):
+        """a lap u + b u = c on the plan's 3D grid (per-node FP64 a, b, c of
+        the grid's shape); u's boundary values are the Dirichlet data, its
+        interior receives the solution.  The plan needs PLAN_GENERAL."""
+        for t, n in ((a, "a"), (b, "b"), (c, "c"), (u, "u")):
+            self._check(t, self.shape, n)
+        opts = opts or make_opts()
+        info = _lib.Info()
+        with torch.cuda.device(self.device):
+            code = _lib.lib().mhs_solve_general(self.h, _ptr(a), _ptr(b), _ptr(c), _ptr(u), C.byref(opts),
+                                                C.byref(info), _stream(self.device))
+        if raise_on_error:
+            check(code)
+        return info
+
+    def face_shape(self, face):
+        """Shape (n2, n1) of the coefficient arrays of a face problem."""
+        nz, ny, nx = self.shape
+        if face in (_lib.FACE_BASE, _lib.FACE_TOP):
+            return (ny, nx)
+        if face in (_lib.FACE_XLO, _lib.FACE_XHI):
+            return (nz, ny)
+        if face in (_lib.FACE_YLO, _lib.FACE_YHI):
+            return (nz, nx)
+        raise ValueError("face must be one of FACE_BASE .. FACE_YHI")
+
+    def solve_face(self, face, a, b, c, P, opts=None, raise_on_error=True):
+        """a lap u + b u = c on one face of the box (2D Laplacian in the
+        face's coordinates), the face's edges in P as Dirichlet data; the
+        interior nodes of that face of P receive the solution."""
+        fs = self.face_shape(face)
+        for t, n in ((a, "a"), (b, "b"), (c, "c")):
+            self._check(t, fs, n)
+        self._check(P, self.shape, "P")
+        opts = opts or make_opts()
+        info = _lib.Info()
+        with torch.cuda.device(self.device):
+            code = _lib.lib().mhs_solve_face(self.h, int(face), _ptr(a), _ptr(b), _ptr(c), _ptr(P), C.byref(opts),
+                                             C.byref(info), _stream(self.device))
+        if raise_on_error:
+            check(code)
+        return info
+
     def fields(self, model, P, out=None):
         """B, p, rho by central differences; returns (Bx, By, Bz, p, rho)."""
         self._check(P, self.shape, "P")
