@@ -66,6 +66,8 @@ def parse():
                     help="the large single equilibrium reported beside the headline ('' skips it)")
     ap.add_argument("--large-rtol", type=float, default=1e-12,
                     help="stopping rtol of the large equilibrium (calibrated for 1e-8 error in every field)")
+    ap.add_argument("--no-general", dest="general", action="store_false",
+                    help="skip the general-operator leg (a lap u + b u = c at 257^3)")
     ap.add_argument("--large-only", action="store_true",
                     help="run only the large-equilibrium leg (the workload of its rocprofv3 summary)")
     ap.add_argument("--counter-probe", action="store_true",
@@ -595,6 +597,45 @@ def large_leg(a, torch, dev, reps=5):
     return out
 
 
+def general_leg(torch, dev, n=257, reps=3, rtol=1e-10):
+    """The general problem a lap u + b u = c (per-node coefficients, the
+    synth.general_problem recipe) on an n^3 unit box: time per solve to
+    rtol, V-cycles, and the HIP-event rate of its kernels (algorithmic bytes:
+    a sweep reads u, b/a, c/a and writes u, 32 B per node)."""
+    import synth
+    from paper_1307_6720_amd import PLAN_GENERAL, PREC_FP64
+    from paper_1307_6720_amd.solver import Plan, make_opts
+
+    g = synth.make_grid(n, n, n)
+    a, b, c, u = synth.general_problem(g.shape, (g.lx, g.ly, g.lz), 41)
+    a, b, c, u0 = (torch.from_numpy(x).to(dev) for x in (a, b, c, u))
+    plan = Plan(g, PREC_FP64 | PLAN_GENERAL, device=dev)
+    u = u0.clone()
+    opts = make_opts(PREC_FP64, rtol)
+    plan.solve_general(a, b, c, u, opts)
+    ts, info = [], None
+    for _ in range(reps):
+        u.copy_(u0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = plan.solve_general(a, b, c, u, opts)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    u.copy_(u0)
+    plan.profile(True, ["general"])
+    plan.profile_read(reset=True)
+    plan.solve_general(a, b, c, u, opts)
+    torch.cuda.synchronize()
+    ms, nl, by = plan.profile_read(reset=True)["general"]
+    plan.profile(False)
+    plan.close()
+    return {"grid": f"{n}^3", "rtol": rtol, "ms_per_solve": 1e3 * sum(ts) / reps, "cycles": info.cycles,
+            "rel_residual": info.rel_residual, "kernel_ms": ms, "launches": nl,
+            "kernel_gbps": by / (ms * 1e-3) / 1e9 if ms > 0 else None,
+            "note": "FP64 V(2,2); one-thread-per-node kernels; GB/s from algorithmic bytes (sweep 32 B/node, "
+                    "residual 32, restriction 8 + 8/8, prolongation 16 + 8/8) over summed HIP-event durations"}
+
+
 def batched_leg(a, runs, bz, prec, steps, warm=True, profile=False):
     """The same equilibria served by the batching server with `a.batch`
     requests in flight (all queued at once): whole-job throughput and
@@ -852,6 +893,7 @@ def main():
     if a.serve_requests > 0:
         serving = serve_leg(a, torch, dev)
     large = large_leg(a, torch, dev) if a.large_workload else None
+    general = general_leg(torch, dev) if a.general else None
 
     single_mixed = a.steps / mix_total
     if batched is not None:
@@ -903,6 +945,7 @@ def main():
         "field_lines": field_lines,
         "serving": serving,
         "large_case": large,
+        "general": general,
         "context": {"paper_speedup": "x30 GPU vs serial (x32.4 at 128^3, x29.6 at 256^3); hardware unstated"},
     }
     if not a.no_cpu:

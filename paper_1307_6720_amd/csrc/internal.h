@@ -33,6 +33,12 @@ constexpr int kMaxLevels = 16;
 #ifndef MHS_SWEEP_HP32
 #define MHS_SWEEP_HP32 48
 #endif
+#ifndef MHS_SWEEP_RW32
+#define MHS_SWEEP_RW32 98
+#endif
+#ifndef MHS_SWEEP_ROWMAP32
+#define MHS_SWEEP_ROWMAP32 1
+#endif
 #ifndef MHS_SWEEP_HP64
 #define MHS_SWEEP_HP64 40
 #endif

@@ -262,17 +262,30 @@ __global__ __launch_bounds__(kSThreads) MHS_SWEEP_ATTR void k_sweep3(const Level
     // its black node and, for the residual, its two own nodes
     constexpr int kNF = HAS_F ? (NORM ? 5 : 3) : 1;
     constexpr int kCPlane = kCWX * kCWY;
-    // Window rows in LDS: even columns, then odd columns, the odd half
-    // starting 16 banks after the even one, so that the colour phases (every
-    // other column) and the staging of consecutive columns are both free of
-    // bank conflicts.
+    // Window rows in LDS: even columns, then odd columns (half rows of HP
+    // values), the odd half starting 16 banks after the even one.  The LDS
+    // serves a wave's 32-bit accesses in half-waves of 32 lanes (measured: a
+    // plain row layout, whose colour phases read every other word, raised
+    // the bank-conflict cycles per LDS instruction of the FP32 sweep from
+    // 1.37 to 1.80), so a half-wave reading or writing 32 nodes of one
+    // colour in one row, or 32 consecutive cells of one row, is free of
+    // conflicts.  With the row-aligned lane maps below the FP32 sweep has
+    // 0.29 conflict cycles per LDS instruction (0.05 with stores masked off
+    // for lanes without a cell, which cost more than they save); its time
+    // is the same either way, so the LDS does not bound it.
     constexpr int HP = sizeof(T) == 8 ? MHS_SWEEP_HP64 : MHS_SWEEP_HP32;
-    constexpr int RW = 2 * HP;
+    // FP32: the row pitch is 2 (mod 32) words, so that a half-wave spanning
+    // several rows at the same columns (the last window columns, the last
+    // red pair of the ring) spreads over the banks; the lane maps below keep
+    // every other half-wave inside one row
+    constexpr bool ROWMAP = sizeof(T) == 4 && MHS_SWEEP_ROWMAP32;
+    constexpr int RW = sizeof(T) == 8 ? 2 * HP : MHS_SWEEP_RW32;
     constexpr int SLOT = kWY * RW;
-    // (spare cells past the halves: RW - 1 takes the stores of lanes past the
-    // window; kTrash, in row 1, the updates of lanes without a node, and
-    // every neighbour it reads is a padding cell too)
-    static_assert(HP >= kWX / 2 + 2, "half row too short");
+    // (spare cells: kSpare takes the stores of lanes past the window; kTrash,
+    // in row 1, the updates of lanes without a node, and every neighbour it
+    // reads is a padding cell too)
+    static_assert(HP >= kWX / 2 + 2 && RW >= HP + kWX / 2 + 1, "half row too short");
+    constexpr int kSpare = RW - 1;
     constexpr int kTrash = RW + HP - 1;
     // five window slots: plane s+1 is staged while black(s-1) of the previous
     // step may still read planes s-2 .. s, so two barriers per step suffice
@@ -294,6 +307,36 @@ __global__ __launch_bounds__(kSThreads) MHS_SWEEP_ATTR void k_sweep3(const Level
     __shared__ T ZW[PROLONG ? kWY * kCWX + 1 : 1];
     __shared__ double red[kSThreads / 64];
     auto sxp = [](int c) { return (c & 1) * HP + (c >> 1); };
+    // Lane maps (FP32, row-aligned): window cell e -> (row, column): 64
+    // consecutive columns per row, then the last kWX - 64 columns of every
+    // row; red node e of the ring -> (row, pair q): 32 pairs per row, then
+    // the last pair (q = kRedPerRow - 1) of every row.  (FP64: row-major.)
+    auto cell_rc = [](int e, int &w, int &c) {
+        if (!ROWMAP) {
+            w = e / kWX;
+            c = e - w * kWX;
+        } else if (e < 64 * kWY) {
+            w = e >> 6;
+            c = e & 63;
+        } else {
+            const int x = e - 64 * kWY;
+            w = x / (kWX - 64);
+            c = 64 + x - w * (kWX - 64);
+        }
+    };
+    auto red_wq = [](int e, int &w, int &q) {
+        if (!ROWMAP) {
+            w = 1 + e / kRedPerRow;
+            q = e - (w - 1) * kRedPerRow;
+        } else if (e < 32 * (kSTY + 2)) {
+            w = 1 + (e >> 5);
+            q = e & 31;
+        } else {
+            w = 1 + e - 32 * (kSTY + 2);
+            q = kRedPerRow - 1;
+        }
+    };
+    static_assert(!ROWMAP || (kRedPerRow == 33 && kWX - 64 == 4), "the row-aligned maps assume a 64-wide tile");
 
     const int tile = xcd_tile();
     const LevelItem *it = items + find_item(items, nitems, tile);
@@ -333,9 +376,10 @@ __global__ __launch_bounds__(kSThreads) MHS_SWEEP_ATTR void k_sweep3(const Level
     for (int r = 0; r < kWPer; ++r) {
         const int e = tid + r * kSThreads;
         const int ee = min(e, kWCells - 1);
-        const int w = ee / kWX, c = ee - w * kWX;
+        int w, c;
+        cell_rc(ee, w, c);
         const int i = i0 - 2 + c, j = j0 - 2 + w;
-        st_i[r] = pk16(e < kWCells ? w * RW + sxp(c) : RW - 1, PROLONG ? w * kCWX + ((i >> 1) - I0) : 0);
+        st_i[r] = pk16(e < kWCells ? w * RW + sxp(c) : kSpare, PROLONG ? w * kCWX + ((i >> 1) - I0) : 0);
         st_g[r] = es * (uint32_t)(min(max(i, 0), nx - 1) + nx * min(max(j, 0), ny - 1));
         if (i >= 0 && i < nx && j >= 0 && j < ny) st_in |= 1u << r;
         if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2) st_int |= 1u << r;
@@ -381,8 +425,8 @@ __global__ __launch_bounds__(kSThreads) MHS_SWEEP_ATTR void k_sweep3(const Level
         for (int r = 0; r < 2; ++r) {
             const int e = tid + r * kSThreads;
             const int ee = min(e, (kSTY + 2) * kRedPerRow - 1);
-            const int w = 1 + ee / kRedPerRow;
-            const int q = ee - (w - 1) * kRedPerRow;
+            int w, q;
+            red_wq(ee, w, q);
             const int c = 1 + ((ps + w) & 1) + 2 * q;
             const int i = i0 - 2 + c, j = j0 - 2 + w;
             const bool ok = e < (kSTY + 2) * kRedPerRow && i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2;
@@ -545,7 +589,7 @@ __global__ __launch_bounds__(kSThreads) MHS_SWEEP_ATTR void k_sweep3(const Level
         T *dst = S + sl * SLOT;
 #pragma unroll
         for (int r = 0; r < kWPer; ++r) {
-            const int l = lo16(st_i[r]); // RW - 1 (an unused padding cell) past the window
+            const int l = lo16(st_i[r]); // kSpare (a padding cell) past the window
             T v = (!ZERO_IN && ((st_in >> r) & 1)) ? src[r] : (T)0;
             if constexpr (PROLONG) {
                 if (corr && ((st_int >> r) & 1)) {

@@ -2,7 +2,8 @@
 
 This package only draws and evaluates *inputs*: boundary magnetograms Bz0,
 the cross-field profile xi(z) and its derivative, the background atmosphere
-p_b(z), rho_b(z), and the request stream of the serving workload.  It holds
+p_b(z), rho_b(z), the request stream of the serving workload, and the
+coefficients and data of the general problem a lap u + b u = c.  It holds
 none of the solver's arithmetic (no discrete operator, no multigrid, no field
 recovery), so either side may import it without sharing method code.
 """
@@ -25,6 +26,7 @@ from .workloads import (
 )
 from . import paper
 from .paper import paper_workload
+from .general import general_problem
 
 __all__ = [
     "bipolar_magnetogram",
@@ -45,4 +47,5 @@ __all__ = [
     "WORKLOAD_NAMES",
     "paper",
     "paper_workload",
+    "general_problem",
 ]

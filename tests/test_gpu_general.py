@@ -29,18 +29,7 @@ def rel(a, b):
 
 
 def coefficients(shape, lengths, seed):
-    """Smooth a > 0 and b <= 0 varying along every axis, random c and
-    boundary values (the interior of u is the zero initial guess)."""
-    rng = np.random.default_rng(seed)
-    axes = [np.linspace(0.0, L, n) for n, L in zip(shape[::-1], lengths)]
-    grids = np.meshgrid(*axes[::-1], indexing="ij")  # z, y, x (or y, x)
-    s = sum((q + 1) * g for q, g in enumerate(grids[::-1]))
-    a = 1.0 + 0.5 * np.sin(s)
-    b = -(1.0 + grids[-1] ** 2) - 5.0 * grids[0] ** 2
-    c = rng.normal(size=shape)
-    u = rng.normal(size=shape)
-    u[tuple(slice(1, -1) for _ in shape)] = 0.0
-    return a, b, c, u
+    return synth.general_problem(shape, lengths, seed)
 
 
 def dev(a):
