@@ -88,6 +88,7 @@ typedef struct mhs_opts {
     int32_t warm_start;   /* 1: use P's interior as the initial guess       */
     int32_t check_every;  /* cycles launched between host status reads; 0 = adaptive */
     int32_t faces;        /* MHS_FACES_ZERO or MHS_FACES_GIVEN (below)      */
+    int32_t graph;        /* 1: each cycle replayed as a captured HIP graph (below) */
 } mhs_opts;
 
 /* Dirichlet data on the faces other than the base.  Section 2.2 takes
@@ -115,7 +116,17 @@ typedef struct mhs_info {
 typedef struct mhs_plan mhs_plan;
 
 /* Fill *opts with defaults: FP64, V(2,2), rtol 1e-10, max_cycles 100,
- * inner_cycles 1, check_every 0 (adaptive). */
+ * inner_cycles 1, check_every 0 (adaptive), graph 0.
+ *
+ * opts->graph: the launches of one V-cycle (FP64) or refinement step
+ * (mixed) of a solve are the same in every cycle of the call and, for a
+ * plan, in every call with the same launch shapes; with graph = 1 they are
+ * captured once as a HIP graph (kept by the plan, at most eight, on a
+ * capture stream of its own) and replayed per cycle, with graph = 0
+ * launched one by one.  Results are bitwise the same either way.  Off by
+ * default: on MI355X the replays were 1-7 % slower than launching the
+ * kernels (33^3 to 257^3, both paths).  Ignored (launched one by one) while
+ * the plan profiles (mhs_profile_enable) and by mhs_solve_interior_noalloc. */
 void mhs_default_opts(mhs_opts *opts);
 
 /* Library version as 10000*major + 100*minor + patch. */
@@ -283,11 +294,12 @@ int mhs_stage_restrict(mhs_plan *plan, const mhs_model *model, int32_t space, in
                        int32_t precision, const void *d_u, const void *d_f, void *d_fc,
                        void *stream);
 
-/* u <- one red-black sweep applied to u + I(e_c), where I is trilinear
- * (bilinear in 2D) interpolation from level+1, added on interior nodes only. */
+/* u <- nsweeps (>= 1) red-black sweeps applied to u + I(e_c), where I is
+ * trilinear (bilinear in 2D) interpolation from level+1, added on interior
+ * nodes only (the first sweep fused with it, as in the cycle). */
 int mhs_stage_correct_smooth(mhs_plan *plan, const mhs_model *model, int32_t space,
                              int32_t level, int32_t precision, void *d_u, const void *d_f,
-                             const void *d_ec, void *stream);
+                             const void *d_ec, int32_t nsweeps, void *stream);
 
 /* u <- one V(nu1,nu2) cycle, starting from u = 0, on A u = f over the
  * plan's bottom levels (from level mhs_plan_bottom_level() to the coarsest,

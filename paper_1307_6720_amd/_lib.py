@@ -59,7 +59,8 @@ class Model(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("max_cycles", C.c_int32), ("rtol", C.c_double),
                 ("nu1", C.c_int32), ("nu2", C.c_int32), ("inner_cycles", C.c_int32),
-                ("warm_start", C.c_int32), ("check_every", C.c_int32), ("faces", C.c_int32)]
+                ("warm_start", C.c_int32), ("check_every", C.c_int32), ("faces", C.c_int32),
+                ("graph", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -105,7 +106,7 @@ def lib():
         "mhs_solve_face": (C.c_int, [vp, i32, vp, vp, vp, vp, P(Opts), P(Info), vp]),
         "mhs_stage_smooth": (C.c_int, [vp, P(Model), i32, i32, i32, vp, vp, i32, i32, vp]),
         "mhs_stage_restrict": (C.c_int, [vp, P(Model), i32, i32, i32, vp, vp, vp, vp]),
-        "mhs_stage_correct_smooth": (C.c_int, [vp, P(Model), i32, i32, i32, vp, vp, vp, vp]),
+        "mhs_stage_correct_smooth": (C.c_int, [vp, P(Model), i32, i32, i32, vp, vp, vp, i32, vp]),
         "mhs_stage_bottom": (C.c_int, [vp, P(Model), i32, i32, vp, vp, i32, i32, P(i32), vp]),
         "mhs_stage_residual_norm": (C.c_int, [vp, P(Model), i32, i32, i32, vp, vp, P(dbl), vp]),
         "mhs_diagnostics": (C.c_int, [vp, P(Model)] + [vp] * 10 + [vp]),

@@ -560,6 +560,7 @@ int validate_opts(const mhs_opts *o)
     if (o->check_every < 0) return fail(MHS_ERR_INVALID_ARG, "check_every must be >= 0");
     if (o->faces != MHS_FACES_ZERO && o->faces != MHS_FACES_GIVEN)
         return fail(MHS_ERR_INVALID_ARG, "faces must be MHS_FACES_ZERO or MHS_FACES_GIVEN");
+    if (o->graph != 0 && o->graph != 1) return fail(MHS_ERR_INVALID_ARG, "graph must be 0 or 1");
     return MHS_OK;
 }
 
@@ -996,6 +997,72 @@ int run_program(mhs_plan *p, const Program &pg, hipStream_t s, int cycle)
     return MHS_OK;
 }
 
+bool same_launch(const Launch &a, const Launch &b)
+{
+    return a.kind == b.kind && a.flags == b.flags && a.dbl == b.dbl && a.items == b.items && a.nitems == b.nitems &&
+           a.ntiles == b.ntiles && a.lds == b.lds && a.src == b.src && a.dst == b.dst && a.n == b.n &&
+           a.gate == b.gate;
+}
+
+// The executable graph of a cycle program: from the plan's cache, else
+// captured on the plan's capture stream (nothing runs while capturing).
+constexpr size_t kGraphCache = 8;
+int cycle_graph(mhs_plan *p, const Program &pg, hipGraphExec_t *out)
+{
+    *out = nullptr;
+    for (CachedGraph &g : p->graphs) {
+        if (g.launches.size() != pg.launches.size()) continue;
+        bool eq = true;
+        for (size_t q = 0; q < pg.launches.size() && eq; ++q) eq = same_launch(g.launches[q], pg.launches[q]);
+        if (eq) {
+            g.last_use = ++p->graph_clock;
+            *out = g.exec;
+            return MHS_OK;
+        }
+    }
+    if (!p->cap) HIPCHK(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t le = hipSuccess;
+    for (const Launch &L : pg.launches) {
+        le = exec_launch(L, p->cap);
+        if (le != hipSuccess) break;
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(p->cap, &graph);
+    if (le != hipSuccess || ee != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(MHS_ERR_HIP, "cycle capture failed: %s", hipGetErrorString(le != hipSuccess ? le : ee));
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return fail(MHS_ERR_HIP, "cycle graph instantiation failed: %s", hipGetErrorString(ie));
+    if (p->graphs.size() >= kGraphCache) {
+        size_t old = 0;
+        for (size_t q = 1; q < p->graphs.size(); ++q)
+            if (p->graphs[q].last_use < p->graphs[old].last_use) old = q;
+        (void)hipGraphExecDestroy(p->graphs[old].exec);
+        p->graphs.erase(p->graphs.begin() + (long)old);
+    }
+    CachedGraph g;
+    g.launches = pg.launches;
+    g.exec = exec;
+    g.last_use = ++p->graph_clock;
+    p->graphs.push_back(std::move(g));
+    *out = exec;
+    return MHS_OK;
+}
+
+int run_cycle(mhs_plan *p, const Program &pg, hipStream_t s, int cycle, bool graph)
+{
+    if (!graph || !p->graphs_ok || p->prof.mask != 0) return run_program(p, pg, s, cycle);
+    hipGraphExec_t exec = nullptr;
+    int st = cycle_graph(p, pg, &exec);
+    if (st) return st;
+    HIPCHK(hipGraphLaunch(exec, s));
+    return MHS_OK;
+}
+
 int begin_staging(mhs_plan *p)
 {
     if (p->stage.inflight) HIPCHK(hipEventSynchronize(p->stage.inflight));
@@ -1082,7 +1149,7 @@ int drive(mhs_plan *p, const Program &cycle, const SolveState *d_state, const mh
         const int nb = next_batch(ss, o, launched);
         if (nb <= 0) break;
         for (int q = 0; q < nb; ++q) {
-            int st = run_program(p, cycle, s, launched + q);
+            int st = run_cycle(p, cycle, s, launched + q, o->graph != 0);
             if (st) return st;
         }
         launched += nb;
@@ -1123,6 +1190,7 @@ void mhs_default_opts(mhs_opts *o)
     o->warm_start = 0;
     o->check_every = 0;
     o->faces = MHS_FACES_ZERO;
+    o->graph = 0;
 }
 
 int32_t mhs_version(void) { return 10000; }
@@ -1220,6 +1288,8 @@ int mhs_plan_destroy(mhs_plan *p)
     for (hipEvent_t e : p->prof.pool) (void)hipEventDestroy(e);
     if (p->stage.host) (void)hipHostFree(p->stage.host);
     if (p->h_states) (void)hipHostFree(p->h_states);
+    for (mhs::CachedGraph &g : p->graphs) (void)hipGraphExecDestroy(g.exec);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
     delete p;
     return MHS_OK;
 }
@@ -1402,7 +1472,7 @@ int solve_interior_on(mhs_plan *p, const mhs_model *model, double *d_P, const mh
             for (int q = 0; q < nb; ++q) {
                 const int step = launched + q;
                 const Program &pg = step == 0 ? first : ((step & 1) ? odd : even);
-                if ((st = run_program(p, pg, s, step))) return st;
+                if ((st = run_cycle(p, pg, s, step, o->graph != 0))) return st;
             }
             launched += nb;
             if ((st = read_state(p, d_state, &ss, s))) return st;
@@ -1708,25 +1778,32 @@ int mhs_stage_restrict(mhs_plan *p, const mhs_model *model, int32_t space, int32
 }
 
 int mhs_stage_correct_smooth(mhs_plan *p, const mhs_model *model, int32_t space, int32_t level, int32_t precision,
-                             void *d_u, const void *d_f, const void *d_ec, void *stream)
+                             void *d_u, const void *d_f, const void *d_ec, int32_t nsweeps, void *stream)
 {
     hipStream_t s = (hipStream_t)stream;
     Hierarchy *h = nullptr;
     int path = 0;
     int st = stage_common(p, model, space, level, precision, &h, &path, s);
     if (st) return st;
-    if (!d_u || !d_ec || level + 1 >= h->L) return fail(MHS_ERR_INVALID_ARG, "bad arrays or level");
+    if (!d_u || !d_ec || level + 1 >= h->L || nsweeps < 1) return fail(MHS_ERR_INVALID_ARG, "bad arrays, level or nsweeps");
     void *tw = stage_twin(*h, level, path);
     if (!tw || level >= h->b) return fail(MHS_ERR_UNSUPPORTED, "level %d is handled by the bottom solver", level);
+    if (path == kF32 && level == 0) tw = h->lv[0].t[kF32];
     const size_t bytes = h->lv[level].N * (path == kF64 ? 8 : 4);
     HIPCHK(hipMemcpyAsync(tw, d_u, bytes, hipMemcpyDeviceToDevice, s));
     if ((st = begin_staging(p))) return st;
     Program pg;
-    add_correct_sweep(pg, p->stage, *h, level, path, d_u, tw, d_f, d_ec, nullptr);
+    void *cur = d_u, *oth = tw;
+    add_correct_sweep(pg, p->stage, *h, level, path, cur, oth, d_f, d_ec, nullptr);
+    std::swap(cur, oth);
+    for (int q = 1; q < nsweeps; ++q) {
+        add_sweep(pg, p->stage, *h, level, path, cur, oth, d_f, nullptr, 0, nullptr, nullptr);
+        std::swap(cur, oth);
+    }
     if (!pg.ok) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
     if ((st = flush_staging(p, s))) return st;
     if ((st = run_program(p, pg, s))) return st;
-    HIPCHK(hipMemcpyAsync(d_u, tw, bytes, hipMemcpyDeviceToDevice, s));
+    if (cur != d_u) HIPCHK(hipMemcpyAsync(d_u, cur, bytes, hipMemcpyDeviceToDevice, s));
     return release_twin(*h, level, path, s);
 }
 
@@ -1836,6 +1913,7 @@ int mhs_solve_interior_noalloc(const mhs_grid *grid, const mhs_model *model, dou
     p = mhs_plan();
     p.precisions = o->precision;
     p.device = dev;
+    p.graphs_ok = false; // a capture stream and graph objects would be allocations
     if ((st = geometry(&p, grid))) return st;
     if ((st = validate_model(&p, model, false))) return st;
     p.ws = slot.dev;

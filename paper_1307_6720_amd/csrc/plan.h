@@ -141,6 +141,15 @@ struct Program {
     bool ok = true;
 };
 
+// A cycle program captured as a HIP graph.  Kernels read their work items
+// from the staging area, so an executable graph stays valid for every call
+// whose launches (kernel, variant, item address, grid) are the same.
+struct CachedGraph {
+    std::vector<Launch> launches;
+    hipGraphExec_t exec = nullptr;
+    unsigned long long last_use = 0;
+};
+
 struct ModelCache {
     bool valid = false;
     double alpha = 0.0;
@@ -192,6 +201,9 @@ FieldsItem fields_item(const mhs_plan *p, const mhs_model *model, const double *
                        double *By, double *Bz, double *pr, double *rho);
 hipError_t exec_launch(const Launch &L, hipStream_t s);
 int run_program(mhs_plan *p, const Program &pg, hipStream_t s, int cycle = -1);
+// One cycle's launches: replayed as a captured graph when `graph` is set and
+// no class is being profiled, else launched one by one.
+int run_cycle(mhs_plan *p, const Program &pg, hipStream_t s, int cycle, bool graph);
 int begin_staging(mhs_plan *p);
 int flush_staging(mhs_plan *p, hipStream_t s);
 int read_state(mhs_plan *p, const SolveState *d_state, SolveState *out, hipStream_t s);
@@ -233,4 +245,9 @@ struct mhs_plan {
     int scratch_npart = 0;
     mhs::Profiler prof;
     std::unique_ptr<mhs::GenPlan, mhs::GenPlanDeleter> gen; // the general operator (MHS_PLAN_GENERAL)
+    // cycle programs captured as graphs (capture stream created on first use)
+    bool graphs_ok = true;
+    hipStream_t cap = nullptr;
+    std::vector<mhs::CachedGraph> graphs;
+    unsigned long long graph_clock = 0;
 };

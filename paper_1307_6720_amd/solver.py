@@ -52,7 +52,7 @@ def check_array(t, shape, dtype, device, name):
 
 
 def make_opts(precision=PREC_FP64, rtol=1e-10, max_cycles=100, nu1=2, nu2=2, inner_cycles=1,
-              warm_start=False, check_every=0, faces_given=False):
+              warm_start=False, check_every=0, faces_given=False, graph=False):
     o = _lib.Opts()
     _lib.lib().mhs_default_opts(C.byref(o))
     o.precision = precision
@@ -64,6 +64,7 @@ def make_opts(precision=PREC_FP64, rtol=1e-10, max_cycles=100, nu1=2, nu2=2, inn
     o.warm_start = 1 if warm_start else 0
     o.check_every = check_every
     o.faces = _lib.FACES_GIVEN if faces_given else _lib.FACES_ZERO
+    o.graph = 1 if graph else 0
     return o
 
 
@@ -401,12 +402,14 @@ class Plan:
                                                 _ptr(u), _ptr(f), _ptr(fc), _stream(self.device)))
         return fc
 
-    def stage_correct_smooth(self, model, space, level, u, f, ec, precision=PREC_FP64):
+    def stage_correct_smooth(self, model, space, level, u, f, ec, precision=PREC_FP64, nsweeps=1):
+        """u + I(ec) followed by nsweeps sweeps (the first fused with the
+        interpolation)."""
         self._check_stage(space, level, precision, ((u, 0, "u"), (f, 0, "f"), (ec, 1, "ec")))
         m = _ModelArgs.of(model)
         with torch.cuda.device(self.device):
             check(_lib.lib().mhs_stage_correct_smooth(self.h, C.byref(m.c) if m else None, space, level,
-                                                      precision, _ptr(u), _ptr(f), _ptr(ec),
+                                                      precision, _ptr(u), _ptr(f), _ptr(ec), int(nsweeps),
                                                       _stream(self.device)))
         return u
 

@@ -227,6 +227,37 @@ def test_full_size_513_against_exact():
     plan.close()
 
 
+@pytest.mark.parametrize("prec", [PREC_FP64, PREC_MIXED])
+def test_graph_replays_equal_eager_launches(plans, prec):
+    """A cycle replayed as a captured HIP graph computes what launching its
+    kernels one by one does: over several calls in a row (the plan's cached
+    graphs replayed, a new P each call, eager solves and other device work
+    in between) every result is bitwise the eager one, with the same cycle
+    counts."""
+    dims = (65, 65, 65)
+    w = synth.workload("mhs-129", dims=dims)
+    m = w.model
+    plan = plans(dims)
+    bz = torch.from_numpy(w.bz0).to(DEV)
+
+    def run(graph):
+        P = torch.zeros(w.grid.shape, dtype=torch.float64, device=DEV)
+        i2 = plan.solve_boundary(bz, P, make_opts(PREC_FP64, 1e-10, graph=graph))
+        i3 = plan.solve_interior(m, P, make_opts(prec, 1e-10, graph=graph))
+        torch.cuda.synchronize()
+        return P, i2, i3
+
+    want, w2, w3 = run(False)
+    for k in range(3):
+        got, i2, i3 = run(True)
+        assert torch.equal(got, want), k
+        assert (i2.cycles, i3.cycles, i3.inner_cycles) == (w2.cycles, w3.cycles, w3.inner_cycles)
+        x = torch.arange(4096, dtype=torch.float64, device=DEV)
+        assert float((x * 2).sum()) == 4095.0 * 4096.0
+        again, _, _ = run(False)
+        assert torch.equal(again, want)
+
+
 def test_repeat_is_bitwise_deterministic(plans):
     w = synth.workload("mhs-129", dims=(65, 65, 65))
     plan = plans((65, 65, 65))

@@ -126,7 +126,7 @@ def f32(a):
 
 @pytest.mark.parametrize("level", [0, 1])
 @pytest.mark.parametrize("zero_guess", [False, True])
-@pytest.mark.parametrize("nsweeps", [1, 2])
+@pytest.mark.parametrize("nsweeps", [1, 2, 3])
 def test_smooth3_fp32(setup, level, zero_guess, nsweeps):
     """The inner solver's FP32 sweeps: with a right-hand side, and from a
     zero guess (the first pre-smoothing sweep of every FP32 cycle at level
@@ -177,9 +177,11 @@ def test_restrict3_fp32(setup, level):
 
 
 @pytest.mark.parametrize("level", [0, 1])
-def test_correct_smooth3_fp32(setup, level):
+@pytest.mark.parametrize("nsweeps", [1, 2])
+def test_correct_smooth3_fp32(setup, level, nsweeps):
     """The FP32 prolongation fused into the first post-smoothing sweep (or
-    the z-only prolongation before it), levels 0 and 1."""
+    the z-only prolongation before it) and the sweep after it, levels 0 and
+    1."""
     grid, plan, model = setup
     shape, xi, lengths = level_args(plan, model, grid, level)
     cshape = plan.level_shape(3, level + 1)
@@ -190,9 +192,10 @@ def test_correct_smooth3_fp32(setup, level):
     ec[0] = ec[-1] = 0
     ec[:, 0] = ec[:, -1] = 0
     ec[:, :, 0] = ec[:, :, -1] = 0
-    want = ref.rbgs3(prolong(plan, level, ec, u0), f, xi, model.alpha, 1, lengths)
+    want = ref.rbgs3(prolong(plan, level, ec, u0), f, xi, model.alpha, nsweeps, lengths)
     u = tg(u0, torch.float32)
-    plan.stage_correct_smooth(model, 3, level, u, tg(f, torch.float32), tg(ec, torch.float32), precision=PREC_MIXED)
+    plan.stage_correct_smooth(model, 3, level, u, tg(f, torch.float32), tg(ec, torch.float32), precision=PREC_MIXED,
+                              nsweeps=nsweeps)
     assert rel(u.double().cpu().numpy(), want) < 1e-5
 
 
