@@ -50,7 +50,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="mhs-257")
     ap.add_argument("--rtol", type=float, default=1e-10)
-    ap.add_argument("--inner-cycles", type=int, default=1)
+    ap.add_argument("--inner-cycles", type=int, default=3,
+                    help="FP32 V-cycles per refinement step of the mixed path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-run", type=int, default=3)
     ap.add_argument("--serve-requests", type=int, default=512,
@@ -489,7 +490,7 @@ def serve_leg(a, torch, dev):
 
     def stream(arrivals):
         reqs = [Request(id=i, dims=(w.grid.nx, w.grid.ny, w.grid.nz), model=w.model, bz0=bz,
-                        precision=PREC_MIXED, rtol=a.rtol, arrival=t)
+                        precision=PREC_MIXED, rtol=a.rtol, inner_cycles=a.inner_cycles, arrival=t)
                 for i, (t, w, bz) in enumerate(zip(arrivals, works, bzs))]
         srv.ticks = srv.peak_active = srv.peak_queue = 0
         return srv.run(reqs)[1]
@@ -653,7 +654,7 @@ def batched_leg(a, runs, bz, prec, steps, warm=True, profile=False):
         return [Request(id=k, dims=(runs[k % len(runs)].grid.nx, runs[k % len(runs)].grid.ny,
                                     runs[k % len(runs)].grid.nz),
                         model=runs[k % len(runs)].model, bz0=bz[k % len(runs)], precision=prec, rtol=a.rtol,
-                        arrival=0.0) for k in range(n)]
+                        inner_cycles=a.inner_cycles, arrival=0.0) for k in range(n)]
 
     if warm:
         srv.run(reqs(a.batch))
@@ -899,11 +900,11 @@ def main():
     if batched is not None:
         value, ms_step = batched["solves_per_s"], batched["ms_per_solve"]
         p50, p99 = batched["p50_ms"], batched["p99_ms"]
-        path = f"mixed (FP32 V(2,2) in FP64 refinement), {a.batch} requests in flight (continuous batching)"
+        path = f"mixed ({m} FP32 V(2,2) per FP64 refinement step), {a.batch} requests in flight (continuous batching)"
     else:
         value, ms_step = single_mixed, 1e3 * mix_total / a.steps
         p50, p99 = 1e3 * percentile(mix_lat, 0.5), 1e3 * percentile(mix_lat, 0.99)
-        path = "mixed (FP32 V(2,2) in FP64 refinement), one request at a time"
+        path = f"mixed ({m} FP32 V(2,2) per FP64 refinement step), one request at a time"
     line = {
         "metric": METRIC,
         "value": value,

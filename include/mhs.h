@@ -116,7 +116,7 @@ typedef struct mhs_info {
 typedef struct mhs_plan mhs_plan;
 
 /* Fill *opts with defaults: FP64, V(2,2), rtol 1e-10, max_cycles 100,
- * inner_cycles 1, check_every 0 (adaptive), graph 0.
+ * inner_cycles 3, check_every 0 (adaptive), graph 0.
  *
  * opts->graph: the launches of one V-cycle (FP64) or refinement step
  * (mixed) of a solve are the same in every cycle of the call and, for a

@@ -1186,7 +1186,7 @@ void mhs_default_opts(mhs_opts *o)
     o->rtol = 1e-10;
     o->nu1 = 2;
     o->nu2 = 2;
-    o->inner_cycles = 1;
+    o->inner_cycles = 3;
     o->warm_start = 0;
     o->check_every = 0;
     o->faces = MHS_FACES_ZERO;

@@ -38,6 +38,7 @@ class Request:
     bz0: object
     precision: int = PREC_MIXED
     rtol: float = 1e-10
+    inner_cycles: int | None = None  # FP32 V-cycles per refinement step (mixed); None: the library's default
     lengths: tuple = (1.0, 1.0, 1.0)
     arrival: float = 0.0  # seconds after the start of the run
     # filled by the server
@@ -374,7 +375,7 @@ class DeviceBackend:
         if isinstance(b, np.ndarray):
             b = torch.from_numpy(np.ascontiguousarray(b, dtype=np.float64))
         res.bz0.copy_(b, non_blocking=False)
-        opts = make_opts(req.precision, req.rtol)
+        opts = make_opts(req.precision, req.rtol, inner_cycles=req.inner_cycles)
         return self.batch.admit(res.plan, req.model, res.bz0, res.P, res.F, opts)
 
     def step(self):

@@ -51,7 +51,7 @@ def check_array(t, shape, dtype, device, name):
         raise ValueError(f"{name} must be on {device}, got {t.device}")
 
 
-def make_opts(precision=PREC_FP64, rtol=1e-10, max_cycles=100, nu1=2, nu2=2, inner_cycles=1,
+def make_opts(precision=PREC_FP64, rtol=1e-10, max_cycles=100, nu1=2, nu2=2, inner_cycles=None,
               warm_start=False, check_every=0, faces_given=False, graph=False):
     o = _lib.Opts()
     _lib.lib().mhs_default_opts(C.byref(o))
@@ -60,7 +60,8 @@ def make_opts(precision=PREC_FP64, rtol=1e-10, max_cycles=100, nu1=2, nu2=2, inn
     o.max_cycles = max_cycles
     o.nu1 = nu1
     o.nu2 = nu2
-    o.inner_cycles = inner_cycles
+    if inner_cycles is not None:  # None keeps the library's default
+        o.inner_cycles = inner_cycles
     o.warm_start = 1 if warm_start else 0
     o.check_every = check_every
     o.faces = _lib.FACES_GIVEN if faces_given else _lib.FACES_ZERO
@@ -455,7 +456,7 @@ class SolveResult:
 
 
 def solve(plan: Plan, bz0, model, precision=PREC_FP64, rtol=1e-10, rtol2d=None, max_cycles=100,
-          inner_cycles=1, fields=True, out=None):
+          inner_cycles=None, fields=True, out=None):
     """The whole path: (11) on the base, (8) in the interior, then B, p, rho.
 
     bz0: torch float64 (ny, nx) on the plan's device; model: synth.Model-like.

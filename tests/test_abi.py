@@ -38,7 +38,7 @@ def test_version_and_defaults():
     assert L.mhs_version() >= 10000
     o = _lib.Opts()
     L.mhs_default_opts(C.byref(o))
-    assert (o.precision, o.max_cycles, o.nu1, o.nu2, o.inner_cycles) == (_lib.PREC_FP64, 100, 2, 2, 1)
+    assert (o.precision, o.max_cycles, o.nu1, o.nu2, o.inner_cycles) == (_lib.PREC_FP64, 100, 2, 2, 3)
     assert o.rtol == 1e-10
 
 

@@ -141,9 +141,10 @@ def test_full_size_257_parity(plans, exact257, run):
     """The headline size, every run the benchmark times (alpha in {0, 0.5,
     1} x a in {0, 0.5}), in its launch configuration and stopping rule
     (rtol 1e-10): every node of P, B, p - p_b, rho - rho_b of both paths
-    within 1e-8 of the exact discrete solution, and the mixed path's
-    refinement steps within one of the FP64 path's V-cycles (a weaker FP32
-    inner cycle would need more steps)."""
+    within 1e-8 of the exact discrete solution, and the mixed path's FP32
+    V-cycles (refinement steps times the cycles per step) within one step of
+    the FP64 path's V-cycles (a weaker FP32 inner cycle would need more
+    steps)."""
     w, want_P = exact257(run)
     m = w.model
     plan = plans((257, 257, 257))
@@ -156,9 +157,10 @@ def test_full_size_257_parity(plans, exact257, run):
         print(errs, res.info2d, res.info3d)
         for n, e in errs.items():
             assert e < 1e-8, (prec, n, e)
-        counts[prec] = res.info3d["cycles"]
+        counts[prec] = res.info3d["inner_cycles" if prec == PREC_MIXED else "cycles"]
+        per_step = res.info3d["inner_cycles"] // max(1, res.info3d["cycles"])
         del res
-    assert abs(counts[PREC_MIXED] - counts[PREC_FP64]) <= 1, counts
+    assert abs(counts[PREC_MIXED] - counts[PREC_FP64]) <= max(1, per_step), counts
 
 
 @pytest.mark.parametrize("run", [0, 5])
@@ -177,16 +179,22 @@ def test_full_size_257_fp64_to_1e10(plans, exact257, run):
         assert e < 1e-10, (n, e)
 
 
-def test_mixed_steps_track_fp64_cycles_129(plans):
-    """At 129^3 (mhs-129) the mixed path needs no more refinement steps than
-    the FP64 path needs V-cycles, give or take one, at the same rtol."""
+@pytest.mark.parametrize("m", [1, 2, 3])
+def test_mixed_steps_track_fp64_cycles_129(plans, m):
+    """At 129^3 (mhs-129) the mixed path with m FP32 V-cycles per refinement
+    step needs as many FP32 V-cycles as the FP64 path needs V-cycles, give
+    or take one step, at the same rtol: each step's inner cycles contract
+    like FP64 cycles, so a weakened FP32 cycle fails this."""
     w = synth.workload("mhs-129")
     plan = plans((129, 129, 129))
     counts = {}
     for prec in (PREC_FP64, PREC_MIXED):
-        res = solve(plan, torch.from_numpy(w.bz0).to(DEV), w.model, precision=prec, rtol=1e-10, fields=False)
-        counts[prec] = res.info3d["cycles"]
-    assert abs(counts[PREC_MIXED] - counts[PREC_FP64]) <= 1, counts
+        res = solve(plan, torch.from_numpy(w.bz0).to(DEV), w.model, precision=prec, rtol=1e-10, fields=False,
+                    inner_cycles=m)
+        counts[prec] = res.info3d["inner_cycles" if prec == PREC_MIXED else "cycles"]
+        if prec == PREC_MIXED:
+            assert res.info3d["inner_cycles"] == m * res.info3d["cycles"], res.info3d
+    assert abs(counts[PREC_MIXED] - counts[PREC_FP64]) <= m, counts
 
 
 def test_full_size_513_against_exact():
