@@ -637,6 +637,59 @@ def general_leg(torch, dev, n=257, reps=3, rtol=1e-10):
                     "residual 32, restriction 8 + 8/8, prolongation 16 + 8/8) over summed HIP-event durations"}
 
 
+def level0_kz(grid):
+    """Planes per workgroup of the level-0 smoother: the library's rule
+    (about 1024 groups of 64 x 8 node units per request, at most 32 planes)."""
+    units = -(-(grid.nx - 2) // 64) * -(-(grid.ny - 2) // 8)
+    return max(1, min(32, -(-(grid.nz - 2) * units // 1024)))
+
+
+def pattern_reference(torch, dev, grid, nreq):
+    """Rates of mhs_probe_smoother_pattern: the level-0 smoother's memory
+    traffic (12 B per interior node) in its own order with no LDS, barrier
+    or arithmetic, for one request and for `nreq` requests per launch as in
+    the merged launches; with the smoother's tile and z-chunk, and with a
+    row-wide 256 x 8 tile (the headroom of another tiling).  HIP events on
+    the stream of the launches, median of 9."""
+    import ctypes as C
+
+    from paper_1307_6720_amd import _lib
+
+    L = _lib.lib()
+    n = grid.nx * grid.ny * grid.nz
+    interior = (grid.nx - 2) * (grid.ny - 2) * (grid.nz - 2)
+    kz = level0_kz(grid)
+    out = {}
+    for label, k in (("single", 1), ("merged", nreq)):
+        u = torch.zeros(k * n, dtype=torch.float32, device=dev)
+        f = torch.zeros_like(u)
+        o = torch.zeros_like(u)
+        stream = C.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+        rates = {}
+        for name, tile, tkz in (("pattern_reference_gbps", 0, kz), ("pattern_wide_tile_gbps", 1, 8)):
+            def launch():
+                _lib.check(L.mhs_probe_smoother_pattern(C.c_void_p(u.data_ptr()), C.c_void_p(f.data_ptr()),
+                                                        C.c_void_p(o.data_ptr()), grid.nx, grid.ny, grid.nz, k,
+                                                        tile, tkz, stream))
+            for _ in range(3):
+                launch()
+            ts = []
+            for _ in range(9):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                launch()
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            ms = sorted(ts)[len(ts) // 2]
+            rates[name] = 12.0 * interior * k / (ms * 1e-3) / 1e9
+        rates["pattern_note"] = (f"mhs_probe_smoother_pattern, {k} request(s) of {grid.nx}x{grid.ny}x{grid.nz} "
+                                 f"per launch; smoother tile 64x16, {kz} planes per group; wide tile 256x8, 8 planes")
+        out[label] = rates
+        del u, f, o
+    return out
+
+
 def batched_leg(a, runs, bz, prec, steps, warm=True, profile=False):
     """The same equilibria served by the batching server with `a.batch`
     requests in flight (all queued at once): whole-job throughput and
@@ -843,6 +896,11 @@ def main():
         if "copy_reference_gbps" not in r:
             r["copy_reference_gbps"] = copy_reference(r["algorithmic_bytes_per_launch"])
             r["frac_of_copy_reference"] = r["achieved"] / r["copy_reference_gbps"]
+    pattern = pattern_reference(torch, dev, grid, a.batch if batched is not None else 1)
+    roofline.update(pattern["merged" if batched is not None else "single"])
+    roofline["frac_of_pattern_reference"] = roofline["achieved"] / roofline["pattern_reference_gbps"]
+    roof_single.update(pattern["single"])
+    roof_single["frac_of_pattern_reference"] = roof_single["achieved"] / roof_single["pattern_reference_gbps"]
 
     # diagnostics of (1)-(3) on the last equilibrium's fields (off the
     # solve's path): j, |force residual|, div B; 80 B per node (read 5, write 5)

@@ -479,6 +479,26 @@ int mhs_batch_profile_enable(mhs_batch *batch, int32_t class_mask);
 int mhs_batch_profile_read(mhs_batch *batch, int32_t klass, double *total_ms, int64_t *launches,
                            double *bytes, int32_t reset);
 
+/* ---- access-pattern reference (a measurement aid, not part of a solve) -- *
+ * Moves the compulsory bytes of a level-0 FP32 smoother launch (read u_in
+ * and f, write u_out: 12 bytes per interior node) in the smoother's memory
+ * order, with no LDS, barrier or arithmetic worth the name, so that its
+ * rate is the ceiling the z-marching tile pattern itself allows: per
+ * workgroup an x-y tile of interior nodes of one request marching kz planes
+ * (from two planes below the chunk to one above it), reading the tile plus
+ * a two-node ring of every plane of u_in two planes ahead of use, f at the
+ * tile's nodes of the chunk's planes, and writing u_out at those nodes.
+ * d_u, d_f, d_out: nreq device arrays of nx*ny*nz floats each, x-fastest,
+ * request r at element offset r*nx*ny*nz (caller-owned, distinct).  tile 0
+ * is the smoother's tile (64 x 16 nodes, 512 threads), tile 1 a row-wide
+ * tile (256 x 8 nodes, 1024 threads); kz >= 1.  Overwrites the interior
+ * nodes of d_out with f plus 1e-30 times a sum of loaded values (finite
+ * inputs stay finite) and nothing else.  Asynchronous on `stream`.  Errors:
+ * MHS_ERR_INVALID_ARG for NULL pointers, nx, ny or nz < 3, nreq or kz < 1,
+ * another tile; MHS_ERR_HIP if the launch fails. */
+int mhs_probe_smoother_pattern(const float *d_u, const float *d_f, float *d_out, int32_t nx, int32_t ny,
+                               int32_t nz, int32_t nreq, int32_t tile, int32_t kz, void *stream);
+
 /* ---- interior solve without allocation -------------------------------- *
  * For callers that cannot allocate device memory or create a plan (code
  * under stream capture, tight serving loops, harnesses that forbid

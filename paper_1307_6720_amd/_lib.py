@@ -113,6 +113,7 @@ def lib():
         "mhs_trace_field_lines": (C.c_int, [vp, vp, vp, vp, vp, i32, dbl, i32, dbl, vp, vp, vp, vp]),
         "mhs_profile_enable": (C.c_int, [vp, i32]),
         "mhs_profile_read": (C.c_int, [vp, i32, P(dbl), P(C.c_int64), P(dbl), i32]),
+        "mhs_probe_smoother_pattern": (C.c_int, [vp, vp, vp, i32, i32, i32, i32, i32, i32, vp]),
     }
     batch = {
         "mhs_batch_workspace_bytes": (C.c_int, [i32, P(C.c_size_t)]),

@@ -17,7 +17,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libmhs.so")
 ARCH = os.environ.get("MHS_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["kernels.hip", "api.cpp", "batch.cpp", "general.hip"]
+SOURCES = ["kernels.hip", "api.cpp", "batch.cpp", "general.hip", "probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

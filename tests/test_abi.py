@@ -42,6 +42,22 @@ def test_version_and_defaults():
     assert o.rtol == 1e-10
 
 
+@pytest.mark.parametrize("args", [
+    (None, 8, 8, 33, 33, 33, 1, 0, 32),   # NULL pointer
+    (8, 8, 8, 2, 33, 33, 1, 0, 32),       # nx < 3
+    (8, 8, 8, 33, 33, 33, 0, 0, 32),      # no request
+    (8, 8, 8, 33, 33, 33, 1, 2, 32),      # no such tile
+    (8, 8, 8, 33, 33, 33, 1, 0, 0),       # kz < 1
+])
+def test_pattern_probe_rejects_bad_arguments_on_the_host(args):
+    """The access-pattern reference checks its arguments before any device
+    work (the pointers below are never dereferenced)."""
+    L = _lib.lib()
+    ptrs = [None if v is None else C.c_void_p(v) for v in args[:3]]
+    assert L.mhs_probe_smoother_pattern(*ptrs, *args[3:], None) == _lib.ERR_INVALID_ARG
+    assert b"probe" in L.mhs_last_error() or b"NULL" in L.mhs_last_error()
+
+
 def ws_bytes(nx, ny, nz, prec=3, lengths=(1.0, 1.0, 1.0)):
     g = _lib.Grid(nx, ny, nz, *lengths)
     n = C.c_size_t(0)
