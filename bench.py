@@ -103,7 +103,7 @@ def recorded_traffic():
                     meta[k.strip()] = v.strip()
         if meta.get("kernels_sha256") != kernels_digest():
             return None
-        return {"single_bytes_per_launch": float(meta["traffic_bytes_per_launch"]),
+        return {"single_ratio": float(meta["single_traffic_ratio"]),
                 "merged_ratio": float(meta["merged_traffic_ratio"])}
     except (OSError, KeyError, ValueError):
         return None
@@ -119,11 +119,12 @@ def _short_kernel(name):
     return re.sub(r"\(.*\)$", "", n)
 
 
-# level-0 FP32 smoother variants of one refinement step and their compulsory
-# bytes per fine node: the zero-guess sweep (read f, write u), two sweeps with
-# f (read u, f; write u) and the prolongation sweep (+ coarse correction, N/8
-# floats)
-SMOOTH_L0_MIX = {"k_sweep3<float, 3>": (1, 8.0), "k_sweep3<float, 1>": (2, 12.0), "k_sweep3<float, 9>": (1, 12.5)}
+# level-0 FP32 smoother variants and their compulsory bytes per fine node:
+# the zero-guess sweep (read f, write u; the first sweep of a refinement
+# step), sweeps with f (read u, f; write u) and the prolongation sweep
+# (+ coarse correction, N/8 floats); per FP32 V(2,2) cycle one prolongation
+# sweep and two or three with f
+SMOOTH_L0_MIX = {"k_sweep3<float, 3>": 8.0, "k_sweep3<float, 1>": 12.0, "k_sweep3<float, 9>": 12.5}
 COPY_BYTES = 1 << 30
 # workgroups of a one-request level-0 smoother launch at 257^3: 4 x 16 tiles
 # of 64 x 16 nodes per plane, 8 chunks of 32 planes
@@ -179,9 +180,10 @@ def summarize_counters(fetch_csv, write_csv, one_groups=SMOOTH_L0_GROUPS_257):
     workload has k * one_groups workgroups; level-0 launches read about
     8x what level-1 launches of the same k read, and launches issued after
     a solve converged read nothing.  Prints the summary kept under
-    profiles/: bytes per one-request launch (the 1 : 2 : 1 mix of one
-    refinement step) and the ratio of measured to compulsory bytes over
-    the merged (k > 1) launches."""
+    profiles/: the ratio of measured to compulsory bytes over the
+    one-request (k = 1) and over the merged (k > 1) launches, weighted by
+    their launch counts (bench.py scales its own compulsory bytes per launch
+    by them)."""
     import collections
     import csv
 
@@ -231,29 +233,24 @@ def summarize_counters(fetch_csv, write_csv, one_groups=SMOOTH_L0_GROUPS_257):
         med = sorted(xs)[len(xs) // 2] / k
         return [x for x in xs if x / k >= 0.9 * med]
 
-    meas = alg = 0.0
+    meas = alg = meas1 = alg1 = 0.0
     for key in sorted(set(F) & set(W)):
         kn, k = key
         fk, wk = full(F[key], k), full(W[key], k)
         fb, wb = sum(fk) / len(fk) / k, sum(wk) / len(wk) / k
-        c = SMOOTH_L0_MIX[kn][1]
+        c = SMOOTH_L0_MIX[kn]
         print(f"  {kn:22s} k={k:2d}  launches {len(fk):3d} of {len(F[key]):3d}  read {fb / N:5.2f} B/node "
               f"(compulsory {c - 4:.2f})  write {wb / N:5.2f} B/node (compulsory 4.00)")
         if k > 1:
             meas += (fb + wb) * k * len(fk)
             alg += k * c * N * len(fk)
-    tot = sum(c for c, _ in SMOOTH_L0_MIX.values())
-    one = {}
-    for kn in SMOOTH_L0_MIX:
-        fk, wk = full(F[(kn, 1)], 1), full(W[(kn, 1)], 1)
-        one[kn] = sum(fk) / len(fk) + sum(wk) / len(wk)
-    avg = sum(c * one[kn] for kn, (c, _) in SMOOTH_L0_MIX.items()) / tot
-    alg1 = sum(c * b for c, b in SMOOTH_L0_MIX.values()) * N / tot
-    print(f"one-request launches, class average (1 zero-guess : 2 with f : 1 prolongation): traffic "
-          f"{avg / 1e6:.1f} MB, compulsory {alg1 / 1e6:.1f} MB, ratio {avg / alg1:.3f}")
+        else:
+            meas1 += (fb + wb) * len(fk)
+            alg1 += c * N * len(fk)
+    print(f"one-request launches (k = 1): traffic / compulsory = {meas1 / alg1:.3f}")
     print(f"merged launches (k > 1): traffic / compulsory = {meas / alg:.3f}")
     print(f"kernels_sha256: {kernels_digest()}")
-    print(f"traffic_bytes_per_launch: {avg:.0f}")
+    print(f"single_traffic_ratio: {meas1 / alg1:.4f}")
     print(f"merged_traffic_ratio: {meas / alg:.4f}")
 
 
@@ -858,7 +855,8 @@ def main():
                 "algorithmic_bytes_per_launch": b / n, "avg_launch_us": 1e3 * ms / n, "launches": n}
 
     roof_single = roofline_of(dom_prof, "one request per launch (single-stream pass)")
-    roof_single["traffic"] = None if traffic is None else traffic["single_bytes_per_launch"]
+    roof_single["traffic"] = (None if traffic is None else
+                              traffic["single_ratio"] * roof_single["algorithmic_bytes_per_launch"])
 
     batched = batched_fp64 = None
     if a.batch > 0:
