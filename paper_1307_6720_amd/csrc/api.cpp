@@ -1097,12 +1097,31 @@ int read_state(mhs_plan *p, const SolveState *d_state, SolveState *out, hipStrea
 }
 
 // How many more cycles (including the one that only checks) to launch.
-int next_batch(const SolveState &ss, const mhs_opts *o, int launched)
+int hint_of(const mhs_plan *p, int kind, const mhs_opts *o)
+{
+    const CycleHint &h = p->last_cycles[kind];
+    return h.matches(o) ? h.cycles : 0;
+}
+
+void record_cycles(mhs_plan *p, int kind, const mhs_opts *o, const SolveState &ss)
+{
+    CycleHint &h = p->last_cycles[kind];
+    if (ss.done != kConverged) return;
+    h.cycles = std::max(0, ss.checks - 1);
+    h.rtol = o->rtol;
+    h.nu1 = o->nu1;
+    h.nu2 = o->nu2;
+    h.inner = o->inner_cycles;
+}
+
+int next_batch(const SolveState &ss, const mhs_opts *o, int launched, int hint)
 {
     const int remaining = o->max_cycles + 1 - launched;
     if (remaining <= 0) return 0;
     if (o->check_every > 0) return std::min(o->check_every, remaining);
-    int want = 4;
+    // first batch: as many cycles as the plan's last solve of this kind
+    // needed, plus the one that checks; else four
+    int want = (launched == 0 && hint > 0) ? hint + 1 : 4;
     if (ss.checks >= 2 && ss.r0 > 0.0 && ss.rnorm > 0.0) {
         const double rel = ss.rnorm / ss.r0;
         const double rate = std::pow(rel, 1.0 / (ss.checks - 1));
@@ -1141,12 +1160,12 @@ int set_device(const mhs_plan *p)
 // Drive cycles of `cycle` (each starts with the norm check of the current
 // iterate) until the device-side state is no longer running.
 int drive(mhs_plan *p, const Program &cycle, const SolveState *d_state, const mhs_opts *o, SolveState *out,
-          int *syncs, hipStream_t s)
+          int *syncs, hipStream_t s, int kind)
 {
     int launched = 0;
     SolveState ss{};
     for (;;) {
-        const int nb = next_batch(ss, o, launched);
+        const int nb = next_batch(ss, o, launched, hint_of(p, kind, o));
         if (nb <= 0) break;
         for (int q = 0; q < nb; ++q) {
             int st = run_cycle(p, cycle, s, launched + q, o->graph != 0);
@@ -1159,6 +1178,7 @@ int drive(mhs_plan *p, const Program &cycle, const SolveState *d_state, const mh
         if (ss.done != kRunning) break;
     }
     *out = ss;
+    record_cycles(p, kind, o, ss);
     return prof_collect(p, ss.checks - 1);
 }
 
@@ -1364,7 +1384,7 @@ int mhs_solve_boundary(mhs_plan *p, const double *d_bz0, double *d_P, const mhs_
     HIPCHK(launch_prep2(d_prep, 1, pi.n, s));
     SolveState fin{};
     int syncs = 0;
-    if ((st = drive(p, cyc, d_state, o, &fin, &syncs, s))) return st;
+    if ((st = drive(p, cyc, d_state, o, &fin, &syncs, s, kSolve2D))) return st;
     const int status = status_of(fin.done);
     if (info) {
         info->status = status;
@@ -1439,7 +1459,7 @@ int solve_interior_on(mhs_plan *p, const mhs_model *model, double *d_P, const mh
         if (!cyc.ok || !d_state || !d_prep) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
         if ((st = flush_staging(p, s))) return st;
         HIPCHK(launch_prep3(d_prep, 1, prep3_threads(N), s));
-        if ((st = drive(p, cyc, d_state, o, &fin, &syncs, s))) return st;
+        if ((st = drive(p, cyc, d_state, o, &fin, &syncs, s, kSolve3D64))) return st;
     } else {
         // FP64 iterative refinement around FP32 V-cycles.  Step 0 only
         // computes r = -A P; step s >= 1 applies the previous correction
@@ -1467,7 +1487,7 @@ int solve_interior_on(mhs_plan *p, const mhs_model *model, double *d_P, const mh
         int launched = 0;
         SolveState ss{};
         for (;;) {
-            const int nb = next_batch(ss, o, launched);
+            const int nb = next_batch(ss, o, launched, hint_of(p, kSolve3DMixed, o));
             if (nb <= 0) break;
             for (int q = 0; q < nb; ++q) {
                 const int step = launched + q;
@@ -1480,6 +1500,7 @@ int solve_interior_on(mhs_plan *p, const mhs_model *model, double *d_P, const mh
             if (ss.done != kRunning) break;
         }
         fin = ss;
+        record_cycles(p, kSolve3DMixed, o, ss);
         if ((st = prof_collect(p, fin.checks - 1))) return st;
         const int steps = std::max(0, fin.checks - 1);
         inner_total = steps * o->inner_cycles;

@@ -578,7 +578,7 @@ int gen_solve(mhs_plan *p, GenHier &g, double *u0, const double *a, const double
                     "coarsest grid (%g)", hred[0], 0.5 * lam);
     SolveState fin{};
     int syncs = 1;
-    if ((st = drive(p, cyc, d_state, o, &fin, &syncs, s))) return st;
+    if ((st = drive(p, cyc, d_state, o, &fin, &syncs, s, kSolveGeneral))) return st;
     const int status = status_of(fin.done);
     if (info) {
         info->status = status;

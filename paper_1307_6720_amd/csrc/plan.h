@@ -207,8 +207,26 @@ int run_cycle(mhs_plan *p, const Program &pg, hipStream_t s, int cycle, bool gra
 int begin_staging(mhs_plan *p);
 int flush_staging(mhs_plan *p, hipStream_t s);
 int read_state(mhs_plan *p, const SolveState *d_state, SolveState *out, hipStream_t s);
+// Solve kinds whose last cycle count sizes the first speculative batch.
+enum SolveKind : int { kSolve2D = 0, kSolve3D64 = 1, kSolve3DMixed = 2, kSolveGeneral = 3, kSolveKinds = 4 };
+// The cycles (or refinement steps) a converged solve took, with the options
+// that fix how many it needs for a given problem.
+struct CycleHint {
+    int cycles = 0;
+    double rtol = 0.0;
+    int nu1 = 0, nu2 = 0, inner = 0;
+    bool matches(const mhs_opts *o) const
+    {
+        return cycles > 0 && rtol == o->rtol && nu1 == o->nu1 && nu2 == o->nu2 && inner == o->inner_cycles;
+    }
+};
+int next_batch(const SolveState &ss, const mhs_opts *o, int launched, int hint);
+// The first batch of a solve of `kind` on plan p, and the record of a
+// finished one.
+int hint_of(const mhs_plan *p, int kind, const mhs_opts *o);
+void record_cycles(mhs_plan *p, int kind, const mhs_opts *o, const SolveState &ss);
 int drive(mhs_plan *p, const Program &cycle, const SolveState *d_state, const mhs_opts *o, SolveState *out,
-          int *syncs, hipStream_t s);
+          int *syncs, hipStream_t s, int kind);
 double seconds_since(std::chrono::steady_clock::time_point t0);
 
 // Shapes and step kinds of a multigrid hierarchy (api.cpp).
@@ -250,4 +268,8 @@ struct mhs_plan {
     hipStream_t cap = nullptr;
     std::vector<mhs::CachedGraph> graphs;
     unsigned long long graph_clock = 0;
+    // cycles (or refinement steps) the last converged solve of each kind
+    // took: the next solve with the same options launches that many plus
+    // the checking one in its first batch
+    mhs::CycleHint last_cycles[mhs::kSolveKinds];
 };
