@@ -351,6 +351,11 @@ size_t item_size(Launch::Kind k)
     }
 }
 
+// Compulsory bytes of a finest-level launch from which a request's
+// finest-level launches are kept out of launches merged with requests of
+// another shape (at 257^3 a sweep moves 136-212 MB, at 129^3 17-27 MB).
+constexpr double kRunBytes = 64e6;
+
 bool same_variant(const Launch &a, const Launch &b)
 {
     return a.kind == b.kind && a.flags == b.flags && a.dbl == b.dbl;
@@ -624,10 +629,55 @@ int mhs_batch_step(mhs_batch *b, void *stream, int32_t *n_active)
     };
     T.stage.used = 0;
     std::vector<const Rec *> grp;
+    // Finest-level launches of large requests are not merged with those of
+    // requests of another shape: the tiles of a merged launch are split
+    // among the XCDs in contiguous ranges, and tiles of different shapes
+    // march different numbers of planes, so such a launch would leave some
+    // XCDs idle while others finish the large request's tiles.  Instead a
+    // request's consecutive finest-level launches (the refinement step and
+    // the pre-smoothing of its first cycle; the post-smoothing of a cycle
+    // and the pre-smoothing of the next) run back to back as a run of its
+    // own, launched just before its request's first launch that is not part
+    // of it.  Launches of requests of one shape are merged as they are.
+    auto deferrable = [](const Launch &L) {
+        return (L.prof == MHS_PROF_SMOOTH_L0 || L.prof == MHS_PROF_RESTRICT_L0 || L.prof == MHS_PROF_REFINE) &&
+               L.bytes >= kRunBytes;
+    };
+    auto same_shape = [](const Launch &a, const Launch &c) {
+        const LevelItem *x = reinterpret_cast<const LevelItem *>(a.items);
+        const LevelItem *y = reinterpret_cast<const LevelItem *>(c.items);
+        return x->nx == y->nx && x->ny == y->ny && x->nz == y->nz;
+    };
+    std::vector<std::vector<const Rec *>> run((size_t)b->max_slots);
+    auto flush = [&](int slot) {
+        for (const Rec *r : run[(size_t)slot]) {
+            grp.assign(1, r);
+            Launch M{};
+            if (!merge(T.stage, grp, &M)) return false;
+            plan_launches.push_back(M);
+            note_items(grp);
+        }
+        run[(size_t)slot].clear();
+        return true;
+    };
     for (size_t lo = 0; lo < b->recs.size();) {
         size_t hi = lo;
         while (hi < b->recs.size() && b->recs[hi].key == b->recs[lo].key) ++hi;
         std::vector<bool> taken(hi - lo, false);
+        for (size_t a = lo; a < hi; ++a) {
+            const Rec &r = b->recs[a];
+            bool defer = r.L.kind == Launch::kFinalize && !run[(size_t)r.slot].empty();
+            if (deferrable(r.L))
+                for (size_t c = lo; c < hi && !defer; ++c)
+                    defer = same_variant(b->recs[c].L, r.L) && !same_shape(b->recs[c].L, r.L);
+            if (defer) {
+                run[(size_t)r.slot].push_back(&r);
+                taken[a - lo] = true;
+            }
+        }
+        for (size_t a = lo; a < hi; ++a)
+            if (!taken[a - lo] && !run[(size_t)b->recs[a].slot].empty() && !flush(b->recs[a].slot))
+                return fail(MHS_ERR_WORKSPACE, "batch descriptor table exhausted");
         for (size_t a = lo; a < hi; ++a) {
             if (taken[a - lo]) continue;
             const Launch &La = b->recs[a].L;
@@ -650,6 +700,8 @@ int mhs_batch_step(mhs_batch *b, void *stream, int32_t *n_active)
         }
         lo = hi;
     }
+    for (int i = 0; i < b->max_slots; ++i)
+        if (!run[(size_t)i].empty() && !flush(i)) return fail(MHS_ERR_WORKSPACE, "batch descriptor table exhausted");
 
     // 3. model tables of starting requests, descriptors and fresh status
     // words to the device, the launches, then the status read-back
