@@ -354,7 +354,10 @@ size_t item_size(Launch::Kind k)
 // Compulsory bytes of a finest-level launch from which a request's
 // finest-level launches are kept out of launches merged with requests of
 // another shape (at 257^3 a sweep moves 136-212 MB, at 129^3 17-27 MB).
-constexpr double kRunBytes = 64e6;
+#ifndef MHS_RUN_BYTES
+#define MHS_RUN_BYTES 64e6
+#endif
+constexpr double kRunBytes = MHS_RUN_BYTES;
 
 bool same_variant(const Launch &a, const Launch &b)
 {
@@ -406,6 +409,24 @@ bool merge(Staging &st, const std::vector<const Rec *> &grp, Launch *out)
         default:
             break;
         }
+    }
+    switch (first.kind) {
+    case Launch::kSweep3:
+    case Launch::kSweep2:
+    case Launch::kRestrict3:
+    case Launch::kRestrict2:
+    case Launch::kIr3:
+    case Launch::kRestrict3Z:
+    case Launch::kProlong3Z: {
+        LevelItem *i0 = reinterpret_cast<LevelItem *>(host);
+        for (size_t q = 1; q < grp.size(); ++q) {
+            const LevelItem *iq = reinterpret_cast<const LevelItem *>(host + q * sz);
+            if (iq->nx != i0->nx || iq->ny != i0->ny || iq->nz != i0->nz) i0->spread = 1;
+        }
+        break;
+    }
+    default:
+        break;
     }
     st.used += sz * grp.size();
     *out = M;

@@ -112,7 +112,8 @@ struct LevelItem {
     int32_t ntx, nty, ntz; // tiles per axis
     int32_t tile_base;     // first global tile of this item in its launch
     int32_t kz;            // planes per workgroup (smoother: fine planes, restriction: coarse planes)
-    int32_t pad;
+    int32_t spread;        // read on a launch's first item: 1 = its tiles go to the XCDs in turn
+                           // (items of several shapes), 0 = in contiguous ranges per XCD
 };
 
 // One request of the bottom solver: a full V-cycle from level `top` of the

@@ -110,6 +110,14 @@ __device__ __forceinline__ int xcd_tile()
     const int per = nb / kXcds, rem = nb % kXcds;
     return x * per + min(x, rem) + q;
 }
+// A launch whose items have different shapes (requests of several sizes
+// merged by the batch) takes its tiles in dispatch order instead: its items'
+// tiles march different numbers of planes, and contiguous ranges would give
+// some XCDs only the long marches.
+__device__ __forceinline__ int launch_tile(const LevelItem *items, int nitems)
+{
+    return (nitems > 1 && items[0].spread) ? (int)blockIdx.x : xcd_tile();
+}
 
 __device__ __forceinline__ double wave_sum(double v)
 {
@@ -338,7 +346,7 @@ __global__ __launch_bounds__(kSThreads) MHS_SWEEP_ATTR void k_sweep3(const Level
     };
     static_assert(!ROWMAP || (kRedPerRow == 33 && kWX - 64 == 4), "the row-aligned maps assume a 64-wide tile");
 
-    const int tile = xcd_tile();
+    const int tile = launch_tile(items, nitems);
     const LevelItem *it = items + find_item(items, nitems, tile);
     if (it->state && gin<SolveState>(it->state)->done) return;
     const MHS_GLOBAL T *__restrict__ uin = gin<T>(it->u_in);
@@ -812,7 +820,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep2(const LevelItem *__restrict
     __shared__ T S[kW2Y][kW2X];
     __shared__ double red[kThreads / 64];
 
-    const int tile = xcd_tile();
+    const int tile = launch_tile(items, nitems);
     const LevelItem *it = items + find_item(items, nitems, tile);
     if (it->state && gin<SolveState>(it->state)->done) return;
     const MHS_GLOBAL T *__restrict__ uin = gin<T>(it->u_in);
@@ -920,7 +928,7 @@ __global__ __launch_bounds__(kThreads) void k_restrict3(const LevelItem *__restr
     __shared__ T U[4 * USLOT];
     __shared__ T R[kRCells];
 
-    const int tile = xcd_tile();
+    const int tile = launch_tile(items, nitems);
     const LevelItem *it = items + find_item(items, nitems, tile);
     if (it->state && gin<SolveState>(it->state)->done) return;
     const MHS_GLOBAL T *__restrict__ u = gin<T>(it->u_in);
@@ -1099,7 +1107,7 @@ __global__ __launch_bounds__(kThreads) void k_restrict3(const LevelItem *__restr
 template <typename T, bool HAS_F>
 __global__ __launch_bounds__(kThreads) void k_restrict3_z(const LevelItem *__restrict__ items, int nitems)
 {
-    const int tile = xcd_tile();
+    const int tile = launch_tile(items, nitems);
     const LevelItem *it = items + find_item(items, nitems, tile);
     if (it->state && gin<SolveState>(it->state)->done) return;
     const int nx = it->nx, ny = it->ny, ncz = it->ncz;
@@ -1132,7 +1140,7 @@ __global__ __launch_bounds__(kThreads) void k_restrict3_z(const LevelItem *__res
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_prolong3_z(const LevelItem *__restrict__ items, int nitems)
 {
-    const int tile = xcd_tile();
+    const int tile = launch_tile(items, nitems);
     const LevelItem *it = items + find_item(items, nitems, tile);
     if (it->state && gin<SolveState>(it->state)->done) return;
     const int nx = it->nx, ny = it->ny, nz = it->nz;
@@ -1155,7 +1163,7 @@ __global__ __launch_bounds__(kThreads) void k_restrict2(const LevelItem *__restr
 {
     __shared__ T U[kRWY][kRWX];
     __shared__ T R[kRRY][kRRX];
-    const int tile = xcd_tile();
+    const int tile = launch_tile(items, nitems);
     const LevelItem *it = items + find_item(items, nitems, tile);
     if (it->state && gin<SolveState>(it->state)->done) return;
     const MHS_GLOBAL T *__restrict__ u = gin<T>(it->u_in);
@@ -1223,7 +1231,7 @@ __global__ __launch_bounds__(kThreads) void k_ir3(const LevelItem *__restrict__ 
     static_assert(kRoundI % D == 0, "round must cycle the ring");
     __shared__ double S[kSlotsI * SLOT];
     __shared__ double red[kThreads / 64];
-    const int tile = xcd_tile();
+    const int tile = launch_tile(items, nitems);
     const LevelItem *it = items + find_item(items, nitems, tile);
     if (it->state && gin<SolveState>(it->state)->done) return;
     const MHS_GLOBAL double *__restrict__ uin = gin<double>(it->u_in);
