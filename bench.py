@@ -59,7 +59,8 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=0.0,
                     help="Poisson arrival rate in requests/s (0: 0.5x and 0.9x of the capacity measured "
                          "with every request queued at once)")
-    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-slots", type=int, default=32,
+                    help="slots of the serving batch (requests in flight)")
     ap.add_argument("--batch", type=int, default=12,
                     help="concurrent requests in the batched pass over the workload (0: single stream only)")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
