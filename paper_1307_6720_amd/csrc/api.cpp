@@ -768,13 +768,13 @@ void add_prolong_z(Program &pg, Staging &st, const Hierarchy &h, int l, int path
 // First post-smoothing sweep of level l with the coarse correction ec: fused
 // into the sweep, or (after a step that halves z only) added first.
 void add_correct_sweep(Program &pg, Staging &st, const Hierarchy &h, int l, int path, void *cur, void *oth,
-                       const void *f, const void *ec, SolveState *state)
+                       const void *f, const void *ec, SolveState *state, int flags)
 {
     if (h.lv[l].keepxy) {
         add_prolong_z(pg, st, h, l, path, cur, ec, state);
-        add_sweep(pg, st, h, l, path, cur, oth, f, nullptr, 0, state, nullptr);
+        add_sweep(pg, st, h, l, path, cur, oth, f, nullptr, flags, state, nullptr);
     } else {
-        add_sweep(pg, st, h, l, path, cur, oth, f, ec, kProlong, state, nullptr);
+        add_sweep(pg, st, h, l, path, cur, oth, f, ec, kProlong | flags, state, nullptr);
     }
 }
 
@@ -787,13 +787,26 @@ void *add_cycle(Program &pg, Staging &st, const Hierarchy &h, int path, void *a0
 {
     const int b = h.b;
     void *cur = a0, *oth = b0;
-    for (int s = 0; s < nu1; ++s) {
-        int flags = 0;
-        if (s == 0 && first_zero) flags |= kZeroIn;
-        if (s == 0 && first_norm) flags |= kNorm;
+    // sweeps s0 .. n-1 of level l after the first, ping-pong between c and
+    // o; on the 2D hierarchy two per launch (the launch-bound small planes)
+    auto more = [&](int l, void *&c, void *&o, const void *f, int s0, int n) {
+        for (int s = s0; s < n;) {
+            const bool pair = h.planar && s + 1 < n;
+            add_sweep(pg, st, h, l, path, c, o, f, nullptr, pair ? kTwoSweeps : 0, state, nullptr);
+            std::swap(c, o);
+            s += pair ? 2 : 1;
+        }
+    };
+    // the first sweep (flags) and, on the 2D hierarchy, the second with it
+    auto pair_first = [&](int n) { return h.planar && n >= 2 ? kTwoSweeps : 0; };
+    {
+        int flags = pair_first(nu1);
+        if (first_zero) flags |= kZeroIn;
+        if (first_norm) flags |= kNorm;
         add_sweep(pg, st, h, 0, path, cur, oth, f0, nullptr, flags, state, h.partials);
         std::swap(cur, oth);
-        if (s == 0 && first_norm) add_finalize(pg, st, h.partials, h.lv[0].sweep_tiles(), state);
+        if (first_norm) add_finalize(pg, st, h.partials, h.lv[0].sweep_tiles(), state);
+        more(0, cur, oth, f0, (flags & kTwoSweeps) ? 2 : 1, nu1);
     }
     add_restrict(pg, st, h, 0, path, cur, f0, h.lv[1].f[path], state);
     void *lcur[kMaxLevels] = {};
@@ -801,11 +814,9 @@ void *add_cycle(Program &pg, Staging &st, const Hierarchy &h, int path, void *a0
         const Level &lv = h.lv[l];
         void *c = lv.u[path], *o = lv.t[path];
         // first sweep from a zero guess writes lv.u
-        add_sweep(pg, st, h, l, path, nullptr, c, lv.f[path], nullptr, kZeroIn, state, nullptr);
-        for (int s = 1; s < nu1; ++s) {
-            add_sweep(pg, st, h, l, path, c, o, lv.f[path], nullptr, 0, state, nullptr);
-            std::swap(c, o);
-        }
+        const int fl = kZeroIn | pair_first(nu1);
+        add_sweep(pg, st, h, l, path, nullptr, c, lv.f[path], nullptr, fl, state, nullptr);
+        more(l, c, o, lv.f[path], (fl & kTwoSweeps) ? 2 : 1, nu1);
         lcur[l] = c;
         add_restrict(pg, st, h, l, path, c, lv.f[path], h.lv[l + 1].f[path], state);
     }
@@ -815,19 +826,17 @@ void *add_cycle(Program &pg, Staging &st, const Hierarchy &h, int path, void *a0
         const Level &lv = h.lv[l];
         void *c = lcur[l];
         void *o = (c == lv.u[path]) ? lv.t[path] : lv.u[path];
-        add_correct_sweep(pg, st, h, l, path, c, o, lv.f[path], ec, state);
+        const int fl = pair_first(nu2);
+        add_correct_sweep(pg, st, h, l, path, c, o, lv.f[path], ec, state, fl);
         std::swap(c, o);
-        for (int s = 1; s < nu2; ++s) {
-            add_sweep(pg, st, h, l, path, c, o, lv.f[path], nullptr, 0, state, nullptr);
-            std::swap(c, o);
-        }
+        more(l, c, o, lv.f[path], fl ? 2 : 1, nu2);
         ec = c;
     }
-    add_correct_sweep(pg, st, h, 0, path, cur, oth, f0, ec, state);
-    std::swap(cur, oth);
-    for (int s = 1; s < nu2; ++s) {
-        add_sweep(pg, st, h, 0, path, cur, oth, f0, nullptr, 0, state, nullptr);
+    {
+        const int fl = pair_first(nu2);
+        add_correct_sweep(pg, st, h, 0, path, cur, oth, f0, ec, state, fl);
         std::swap(cur, oth);
+        more(0, cur, oth, f0, fl ? 2 : 1, nu2);
     }
     return cur;
 }
@@ -1767,11 +1776,14 @@ int mhs_stage_smooth(mhs_plan *p, const mhs_model *model, int32_t space, int32_t
     if ((st = begin_staging(p))) return st;
     Program pg;
     void *cur = d_u, *oth = tw;
-    for (int q = 0; q < nsweeps; ++q) {
+    // as in the cycles: on the 2D hierarchy two sweeps per launch
+    for (int q = 0; q < nsweeps;) {
         const bool zero = q == 0 && zero_guess;
-        add_sweep(pg, p->stage, *h, level, path, zero ? nullptr : cur, oth, d_f, nullptr, zero ? kZeroIn : 0, nullptr,
-                  nullptr);
+        const bool pair = h->planar && q + 1 < nsweeps;
+        add_sweep(pg, p->stage, *h, level, path, zero ? nullptr : cur, oth, d_f, nullptr,
+                  (zero ? kZeroIn : 0) | (pair ? kTwoSweeps : 0), nullptr, nullptr);
         std::swap(cur, oth);
+        q += pair ? 2 : 1;
     }
     if (!pg.ok) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
     if ((st = flush_staging(p, s))) return st;
@@ -1815,11 +1827,15 @@ int mhs_stage_correct_smooth(mhs_plan *p, const mhs_model *model, int32_t space,
     if ((st = begin_staging(p))) return st;
     Program pg;
     void *cur = d_u, *oth = tw;
-    add_correct_sweep(pg, p->stage, *h, level, path, cur, oth, d_f, d_ec, nullptr);
+    // as in the cycles: on the 2D hierarchy two sweeps per launch
+    const bool pair0 = h->planar && nsweeps >= 2;
+    add_correct_sweep(pg, p->stage, *h, level, path, cur, oth, d_f, d_ec, nullptr, pair0 ? kTwoSweeps : 0);
     std::swap(cur, oth);
-    for (int q = 1; q < nsweeps; ++q) {
-        add_sweep(pg, p->stage, *h, level, path, cur, oth, d_f, nullptr, 0, nullptr, nullptr);
+    for (int q = pair0 ? 2 : 1; q < nsweeps;) {
+        const bool pair = h->planar && q + 1 < nsweeps;
+        add_sweep(pg, p->stage, *h, level, path, cur, oth, d_f, nullptr, pair ? kTwoSweeps : 0, nullptr, nullptr);
         std::swap(cur, oth);
+        q += pair ? 2 : 1;
     }
     if (!pg.ok) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
     if ((st = flush_staging(p, s))) return st;

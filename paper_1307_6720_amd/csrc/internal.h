@@ -207,6 +207,7 @@ enum SweepFlags : int {
     kZeroIn = 2,    // input iterate is zero (first sweep from a zero guess)
     kNorm = 4,      // also write per-tile ||f - A u_in||^2 partials
     kProlong = 8,   // add the interpolated coarse correction to u_in first
+    kTwoSweeps = 16, // two complete sweeps in one launch (2D only)
 };
 
 // Launch flags of the 3D restriction.

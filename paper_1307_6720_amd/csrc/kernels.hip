@@ -803,10 +803,16 @@ __global__ __launch_bounds__(kSThreads) MHS_SWEEP_ATTR void k_sweep3(const Level
 }
 
 // ============================================================================
-// 2D red-black sweep for equation (11): one plane, ping-pong.
+// 2D red-black sweeps for equation (11): one plane, ping-pong; one or two
+// complete sweeps per launch (kTwoSweeps).  A workgroup stages its
+// kTX x kTY2 tile plus a halo of two nodes per sweep, and sweep s updates
+// the red nodes of the tile and a ring of 2 (NS - s) - 1 nodes, then the
+// black nodes of the tile and a ring of 2 (NS - s) - 2: every value the
+// tile's last black update reads is then final, as in the sweeps done one
+// launch at a time, and a ring node computed by two workgroups gets the
+// same value in both.  Two sweeps per launch cost one launch instead of two
+// on these small, launch-bound planes.
 // ============================================================================
-constexpr int kW2X = kTX + 4;
-constexpr int kW2Y = kTY2 + 4;
 constexpr int kOwn2 = kTY2 * kTX / kThreads;
 static_assert(kTY2 * kTX % kThreads == 0, "tile must be a multiple of the block");
 
@@ -817,7 +823,10 @@ __global__ __launch_bounds__(kThreads) void k_sweep2(const LevelItem *__restrict
     constexpr bool ZERO_IN = (FLAGS & kZeroIn) != 0;
     constexpr bool NORM = (FLAGS & kNorm) != 0;
     constexpr bool PROLONG = (FLAGS & kProlong) != 0;
-    __shared__ T S[kW2Y][kW2X];
+    constexpr int NS = (FLAGS & kTwoSweeps) ? 2 : 1;
+    constexpr int H = 2 * NS; // halo
+    constexpr int WX = kTX + 2 * H, WY = kTY2 + 2 * H;
+    __shared__ T S[WY][WX];
     __shared__ double red[kThreads / 64];
 
     const int tile = launch_tile(items, nitems);
@@ -836,9 +845,10 @@ __global__ __launch_bounds__(kThreads) void k_sweep2(const LevelItem *__restrict
     const int tid = threadIdx.x;
     const T cx = coef[0], cy = coef[1], d = coef[2], invd = coef[3];
 
-    for (int e = tid; e < kW2Y * kW2X; e += kThreads) {
-        const int w = e / kW2X, c = e - w * kW2X;
-        const int i = i0 - 2 + c, j = j0 - 2 + w;
+    // window cell (w, c) is node (i0 - H + c, j0 - H + w)
+    for (int e = tid; e < WY * WX; e += kThreads) {
+        const int w = e / WX, c = e - w * WX;
+        const int i = i0 - H + c, j = j0 - H + w;
         T v = (T)0;
         if (i >= 0 && i < nx && j >= 0 && j < ny) {
             if constexpr (!ZERO_IN) v = uin[(size_t)i + (size_t)nx * j];
@@ -854,8 +864,8 @@ __global__ __launch_bounds__(kThreads) void k_sweep2(const LevelItem *__restrict
 #pragma unroll
         for (int q = 0; q < kOwn2; ++q) {
             const int e = tid + q * kThreads;
-            const int w = 2 + e / kTX, c = 2 + e % kTX;
-            const int i = i0 + c - 2, j = j0 + w - 2;
+            const int w = H + e / kTX, c = H + e % kTX;
+            const int i = i0 + c - H, j = j0 + w - H;
             if (i <= nx - 2 && j <= ny - 2) {
                 T fv = (T)0;
                 if constexpr (HAS_F) fv = f[(size_t)i + (size_t)nx * j];
@@ -865,33 +875,35 @@ __global__ __launch_bounds__(kThreads) void k_sweep2(const LevelItem *__restrict
         }
         lds_barrier();
     }
-    for (int e = tid; e < (kTY2 + 2) * kRedPerRow; e += kThreads) {
-        const int w = 1 + e / kRedPerRow;
-        const int q = e - (w - 1) * kRedPerRow;
-        const int c = 1 + ((i0 + j0 + w + 1) & 1) + 2 * q;
-        const int i = i0 - 2 + c, j = j0 - 2 + w;
-        if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2) {
-            T fv = (T)0;
-            if constexpr (HAS_F) fv = f[(size_t)i + (size_t)nx * j];
-            S[w][c] = (fv - (cx * (S[w][c + 1] + S[w][c - 1]) + cy * (S[w + 1][c] + S[w - 1][c]))) * invd;
+    // nodes of colour p ((i + j) & 1, red = 0) on the tile and a ring of r
+    // nodes: (kTY2 + 2r) rows of kTX/2 + r nodes each
+    auto colour = [&](int p, int r) {
+        const int per_row = kTX / 2 + r;
+        for (int e = tid; e < (kTY2 + 2 * r) * per_row; e += kThreads) {
+            const int rr = e / per_row;
+            const int q = e - rr * per_row;
+            const int w = H - r + rr;
+            const int j = j0 - H + w;
+            const int c0 = H - r;
+            const int c = c0 + ((p - j - (i0 - H) - c0) & 1) + 2 * q;
+            const int i = i0 - H + c;
+            if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2) {
+                T fv = (T)0;
+                if constexpr (HAS_F) fv = f[(size_t)i + (size_t)nx * j];
+                S[w][c] = (fv - (cx * (S[w][c + 1] + S[w][c - 1]) + cy * (S[w + 1][c] + S[w - 1][c]))) * invd;
+            }
         }
+    };
+#pragma unroll
+    for (int sw = 0; sw < NS; ++sw) {
+        colour(0, 2 * (NS - sw) - 1);
+        lds_barrier();
+        colour(1, 2 * (NS - sw) - 2);
+        lds_barrier();
     }
-    lds_barrier();
-    for (int e = tid; e < kTY2 * kBlackPerRow; e += kThreads) {
-        const int w = 2 + e / kBlackPerRow;
-        const int q = e - (w - 2) * kBlackPerRow;
-        const int c = 2 + ((i0 + j0 + w + 1) & 1) + 2 * q;
-        const int i = i0 - 2 + c, j = j0 - 2 + w;
-        if (i <= nx - 2 && j <= ny - 2) {
-            T fv = (T)0;
-            if constexpr (HAS_F) fv = f[(size_t)i + (size_t)nx * j];
-            S[w][c] = (fv - (cx * (S[w][c + 1] + S[w][c - 1]) + cy * (S[w + 1][c] + S[w - 1][c]))) * invd;
-        }
-    }
-    lds_barrier();
     for (int e = tid; e < kTY2 * kTX; e += kThreads) {
-        const int w = 2 + e / kTX, c = 2 + e % kTX;
-        const int i = i0 + c - 2, j = j0 + w - 2;
+        const int w = H + e / kTX, c = H + e % kTX;
+        const int i = i0 + c - H, j = j0 + w - H;
         if (i <= nx - 2 && j <= ny - 2) uout[(size_t)i + (size_t)nx * j] = S[w][c];
     }
     if constexpr (NORM) {
@@ -2178,15 +2190,17 @@ template <typename T>
 hipError_t sweep2_dispatch(const LevelItem *items, int nitems, int ntiles, int flags, hipStream_t s)
 {
     dim3 grid(ntiles), block(kThreads);
-    switch (flags & 15) {
+    switch (flags & 31) {
 #define MHS_CASE(F)                                                                      \
     case F:                                                                              \
         hipLaunchKernelGGL((k_sweep2<T, F>), grid, block, 0, s, items, nitems);         \
         break;
         // the variants the cycle builders and stage entry points launch:
         // plain, with f, first sweep from zero, with the norm of the input,
-        // with the prolongation (other combinations never occur)
+        // with the prolongation (other combinations never occur), each as
+        // one sweep or two
         MHS_CASE(0) MHS_CASE(1) MHS_CASE(3) MHS_CASE(4) MHS_CASE(5) MHS_CASE(8) MHS_CASE(9)
+        MHS_CASE(16) MHS_CASE(17) MHS_CASE(19) MHS_CASE(20) MHS_CASE(21) MHS_CASE(24) MHS_CASE(25)
 #undef MHS_CASE
     default:
         return hipErrorInvalidValue;

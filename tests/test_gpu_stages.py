@@ -252,20 +252,31 @@ def test_residual_norm3(setup, level):
 
 
 # ---------------------------------------------------------------- 2D stages
-@pytest.mark.parametrize("nsweeps", [1, 2])
-def test_smooth2(setup, nsweeps):
+@pytest.mark.parametrize("level", [0, 1])
+@pytest.mark.parametrize("zero_guess", [False, True])
+@pytest.mark.parametrize("nsweeps", [1, 2, 3, 4])
+def test_smooth2(setup, level, zero_guess, nsweeps):
+    """2D sweeps, two per launch where the count allows (as in the cycles):
+    n sweeps equal the oracle's n sequential red-black sweeps."""
     grid, plan, model = setup
-    shape = plan.level_shape(2, 0)
-    rng = np.random.default_rng(nsweeps)
+    if level >= plan.bottom_level(2):
+        pytest.skip("level handled by the bottom solver")
+    shape = plan.level_shape(2, level)
+    rng = np.random.default_rng(10 * nsweeps + level + 100 * zero_guess)
     u0 = rng.normal(size=shape)
     f = rng.normal(size=shape)
-    want = ref.rbgs2(u0, f, nsweeps, (grid.lx, grid.ly))
+    if zero_guess:
+        # a correction: zero Dirichlet data; the interior values are not read
+        u0[0] = u0[-1] = 0
+        u0[:, 0] = u0[:, -1] = 0
+    want = ref.rbgs2(np.zeros(shape) if zero_guess else u0, f, nsweeps, (grid.lx, grid.ly))
     u = tg(u0)
-    plan.stage_smooth(None, 2, 0, u, tg(f), nsweeps)
+    plan.stage_smooth(None, 2, level, u, tg(f), nsweeps, zero_guess=zero_guess)
     assert rel(u.cpu().numpy(), want) < 1e-13
 
 
-def test_restrict2_correct2(setup):
+@pytest.mark.parametrize("nsweeps", [1, 2, 3])
+def test_restrict2_correct2(setup, nsweeps):
     grid, plan, model = setup
     shape = plan.level_shape(2, 0)
     cshape = plan.level_shape(2, 1)
@@ -279,7 +290,7 @@ def test_restrict2_correct2(setup):
     ec = rng.normal(size=cshape)
     ec[0] = ec[-1] = 0
     ec[:, 0] = ec[:, -1] = 0
-    want = ref.rbgs2(ref.prolong2(ec, u), f, 1, (grid.lx, grid.ly))
+    want = ref.rbgs2(ref.prolong2(ec, u), f, nsweeps, (grid.lx, grid.ly))
     ut = tg(u)
-    plan.stage_correct_smooth(None, 2, 0, ut, tg(f), tg(ec))
+    plan.stage_correct_smooth(None, 2, 0, ut, tg(f), tg(ec), nsweeps=nsweeps)
     assert rel(ut.cpu().numpy(), want) < 1e-13
