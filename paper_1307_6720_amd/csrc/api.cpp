@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -982,8 +983,14 @@ hipError_t exec_launch(const Launch &L, hipStream_t s)
 
 int run_program(mhs_plan *p, const Program &pg, hipStream_t s, int cycle)
 {
+    return run_range(p, pg, 0, pg.launches.size(), s, cycle);
+}
+
+int run_range(mhs_plan *p, const Program &pg, size_t begin, size_t end, hipStream_t s, int cycle)
+{
     Profiler &pr = p->prof;
-    for (const Launch &L : pg.launches) {
+    for (size_t q = begin; q < end; ++q) {
+        const Launch &L = pg.launches[q];
         ProfRecord rec{};
         const bool timed = L.prof >= 0 && ((pr.mask >> L.prof) & 1) != 0;
         if (timed) {
@@ -1168,27 +1175,65 @@ int set_device(const mhs_plan *p)
 
 // Drive cycles of `cycle` (each starts with the norm check of the current
 // iterate) until the device-side state is no longer running.
-int drive(mhs_plan *p, const Program &cycle, const SolveState *d_state, const mhs_opts *o, SolveState *out,
-          int *syncs, hipStream_t s, int kind)
+// Launches of a program up to and including its convergence check (its first
+// finalize; the whole program if it has none).
+size_t check_len(const Program &pg)
 {
-    int launched = 0;
+    for (size_t i = 0; i < pg.launches.size(); ++i)
+        if (pg.launches[i].kind == Launch::kFinalize) return i + 1;
+    return pg.launches.size();
+}
+
+int drive_programs(mhs_plan *p, const std::function<const Program &(int)> &prog, const SolveState *d_state,
+                   const mhs_opts *o, int hint, SolveState *out, int *syncs, hipStream_t s)
+{
+    // Each program (cycle or refinement step) starts with the convergence
+    // check of the iterate before it.  A batch of nb programs runs the rest
+    // of the program whose check ended the previous batch, nb - 1 programs
+    // whole and the check of the next one, so the status read after it
+    // covers the newest iterate and no launch is issued past a check the
+    // host is about to read (graph replays take whole programs).
+    const bool graph = o->graph != 0;
+    int checked = 0;      // programs whose check has been launched
+    size_t resume = 0;    // first launch not yet run of program checked-1 (0: all ran)
     SolveState ss{};
+    int st = MHS_OK;
     for (;;) {
-        const int nb = next_batch(ss, o, launched, hint_of(p, kind, o));
+        const int nb = next_batch(ss, o, checked, hint);
         if (nb <= 0) break;
-        for (int q = 0; q < nb; ++q) {
-            int st = run_cycle(p, cycle, s, launched + q, o->graph != 0);
-            if (st) return st;
+        if (resume) {
+            const Program &pg = prog(checked - 1);
+            if ((st = run_range(p, pg, resume, pg.launches.size(), s, checked - 1))) return st;
+            resume = 0;
         }
-        launched += nb;
-        int st = read_state(p, d_state, &ss, s);
-        if (st) return st;
+        for (int q = 0; q < nb; ++q) {
+            const int k = checked + q;
+            const Program &pg = prog(k);
+            const size_t c = check_len(pg);
+            if (graph || q + 1 < nb || c == pg.launches.size()) {
+                if ((st = run_cycle(p, pg, s, k, graph))) return st;
+            } else {
+                if ((st = run_range(p, pg, 0, c, s, k))) return st;
+                resume = c;
+            }
+        }
+        checked += nb;
+        if ((st = read_state(p, d_state, &ss, s))) return st;
         ++*syncs;
         if (ss.done != kRunning) break;
     }
     *out = ss;
-    record_cycles(p, kind, o, ss);
-    return prof_collect(p, ss.checks - 1);
+    return MHS_OK;
+}
+
+int drive(mhs_plan *p, const Program &cycle, const SolveState *d_state, const mhs_opts *o, SolveState *out,
+          int *syncs, hipStream_t s, int kind)
+{
+    int st = drive_programs(
+        p, [&](int) -> const Program & { return cycle; }, d_state, o, hint_of(p, kind, o), out, syncs, s);
+    if (st) return st;
+    record_cycles(p, kind, o, *out);
+    return prof_collect(p, out->checks - 1);
 }
 
 double seconds_since(std::chrono::steady_clock::time_point t0)
@@ -1493,21 +1538,12 @@ int solve_interior_on(mhs_plan *p, const mhs_model *model, double *d_P, const mh
             return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
         if ((st = flush_staging(p, s))) return st;
         HIPCHK(launch_prep3(d_prep, 1, prep3_threads(N), s));
-        int launched = 0;
         SolveState ss{};
-        for (;;) {
-            const int nb = next_batch(ss, o, launched, hint_of(p, kSolve3DMixed, o));
-            if (nb <= 0) break;
-            for (int q = 0; q < nb; ++q) {
-                const int step = launched + q;
-                const Program &pg = step == 0 ? first : ((step & 1) ? odd : even);
-                if ((st = run_cycle(p, pg, s, step, o->graph != 0))) return st;
-            }
-            launched += nb;
-            if ((st = read_state(p, d_state, &ss, s))) return st;
-            ++syncs;
-            if (ss.done != kRunning) break;
-        }
+        if ((st = drive_programs(
+                 p,
+                 [&](int step) -> const Program & { return step == 0 ? first : ((step & 1) ? odd : even); },
+                 d_state, o, hint_of(p, kSolve3DMixed, o), &ss, &syncs, s)))
+            return st;
         fin = ss;
         record_cycles(p, kSolve3DMixed, o, ss);
         if ((st = prof_collect(p, fin.checks - 1))) return st;

@@ -201,6 +201,8 @@ FieldsItem fields_item(const mhs_plan *p, const mhs_model *model, const double *
                        double *By, double *Bz, double *pr, double *rho);
 hipError_t exec_launch(const Launch &L, hipStream_t s);
 int run_program(mhs_plan *p, const Program &pg, hipStream_t s, int cycle = -1);
+// Launches [begin, end) of a program.
+int run_range(mhs_plan *p, const Program &pg, size_t begin, size_t end, hipStream_t s, int cycle);
 // One cycle's launches: replayed as a captured graph when `graph` is set and
 // no class is being profiled, else launched one by one.
 int run_cycle(mhs_plan *p, const Program &pg, hipStream_t s, int cycle, bool graph);
