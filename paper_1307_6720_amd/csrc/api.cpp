@@ -1549,10 +1549,9 @@ int solve_interior_on(mhs_plan *p, const mhs_model *model, double *d_P, const mh
         if ((st = prof_collect(p, fin.checks - 1))) return st;
         const int steps = std::max(0, fin.checks - 1);
         inner_total = steps * o->inner_cycles;
-        if (steps & 1) {
-            HIPCHK(launch_copy(T0, d_P, N, nullptr, s));
-            HIPCHK(hipStreamSynchronize(s));
-        }
+        // an odd step count leaves the iterate in the twin; the copy is
+        // stream-ordered like the rest of the solve's work
+        if (steps & 1) HIPCHK(launch_copy(T0, d_P, N, nullptr, s));
     }
     const int status = status_of(fin.done);
     if (info) {
