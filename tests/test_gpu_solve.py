@@ -294,6 +294,32 @@ def test_check_every_does_not_change_result(plans):
         assert torch.equal(P, out[0][0])
 
 
+@pytest.mark.parametrize("prec", [PREC_FP64, PREC_MIXED])
+def test_repeat_solve_reads_status_once_with_same_result(plans, prec):
+    """A plan remembers how many cycles its last converged solve of a kind
+    took with the same options: a repeat launches that many plus the
+    checking one before its first status read, so it reads the status once,
+    and its result is bitwise that of a solve on a fresh plan (batches end
+    on a convergence check; launches past convergence exit at once)."""
+    w = synth.workload("mhs-129", dims=(65, 65, 65))
+    m = w.model
+    bz = torch.from_numpy(w.bz0).to(DEV)
+    fresh = Plan(w.grid, PREC_FP64 | PREC_MIXED, device=DEV)
+    P0 = torch.zeros((65, 65, 65), dtype=torch.float64, device=DEV)
+    i2a = fresh.solve_boundary(bz, P0, make_opts(rtol=1e-10))
+    i3a = fresh.solve_interior(m, P0, make_opts(prec, rtol=1e-10))
+    fresh.close()
+    plan = plans((65, 65, 65))
+    for rep in range(2):
+        P = torch.zeros((65, 65, 65), dtype=torch.float64, device=DEV)
+        i2 = plan.solve_boundary(bz, P, make_opts(rtol=1e-10))
+        i3 = plan.solve_interior(m, P, make_opts(prec, rtol=1e-10))
+        torch.cuda.synchronize()
+        assert (i2.cycles, i3.cycles) == (i2a.cycles, i3a.cycles)
+        assert torch.equal(P, P0)
+    assert i2.host_syncs == 1 and i3.host_syncs == 1, (i2.host_syncs, i3.host_syncs)
+
+
 def test_error_paths(plans):
     w = synth.workload("mhs-129", dims=(33, 33, 33))
     m = w.model
