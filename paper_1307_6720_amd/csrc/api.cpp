@@ -227,6 +227,8 @@ void carve_hierarchy(Hierarchy &h, Carver &cv, int paths)
             if (l < b) lv.t[p] = cv.take<char>(lv.N * es);
         }
     }
+    // the model's tables, then the coarsest inverse, in one contiguous range
+    // from level 0's FP64 table: a model is uploaded with a single copy
     for (int l = 0; l < L; ++l) {
         Level &lv = h.lv[l];
         lv.coef64 = cv.take<double>(4 * (size_t)lv.n[2]);
@@ -350,8 +352,8 @@ int coarse_inverse(const Hierarchy &h, const std::vector<double> &coef, double c
 // operator separates: an in-plane sine mode of eigenvalue lam turns it into
 // the symmetric tridiagonal -d2z + lam diag(1 - xi_k), whose eigenvalues
 // grow with lam (1 - xi > 0), so the minimum sits at the smallest in-plane
-// eigenvalue.  That tridiagonal eigenvalue is found by bisection with
-// Sturm counts (the number of negative pivots of T - x I).
+// eigenvalue.  That tridiagonal eigenvalue is bracketed with Sturm counts
+// (the number of negative pivots of T - x I), three points per pass.
 double level_lambda_min(const Hierarchy &h, int l, const double *xi, const double len[3])
 {
     const Level &lv = h.lv[l];
@@ -369,23 +371,40 @@ double level_lambda_min(const Hierarchy &h, int l, const double *xi, const doubl
         hi = q == 0 ? a[0] : std::min(hi, a[(size_t)q]); // Rayleigh quotient of a unit vector
     }
     const double b2 = iz2 * iz2;
-    auto below = [&](double x) { // eigenvalues < x
-        int cnt = 0;
-        double d = 1.0;
+    // whether some eigenvalue lies below each of three points: three
+    // independent pivot recurrences in one pass, so their divisions overlap
+    auto below3 = [&](const double x[3], bool out[3]) {
+        double d[3] = {1.0, 1.0, 1.0};
+        int cnt[3] = {0, 0, 0};
         for (int q = 0; q < m; ++q) {
-            d = (a[(size_t)q] - x) - (q ? b2 / d : 0.0);
-            if (d == 0.0) d = -1e-300;
-            if (d < 0.0) ++cnt;
+            for (int c = 0; c < 3; ++c) {
+                double v = (a[(size_t)q] - x[c]) - (q ? b2 / d[c] : 0.0);
+                if (v == 0.0) v = -1e-300;
+                cnt[c] += v < 0.0;
+                d[c] = v;
+            }
         }
-        return cnt;
+        for (int c = 0; c < 3; ++c) out[c] = cnt[c] >= 1;
     };
+    // quartersection of [lo, hi]: the smallest eigenvalue stays in it, lo
+    // below it, until the bracket is 1e-14 of hi wide
     double lo = 0.0;
-    for (int it = 0; it < 200 && hi - lo > 1e-14 * hi; ++it) {
-        const double mid = 0.5 * (lo + hi);
-        if (below(mid) >= 1)
-            hi = mid;
-        else
-            lo = mid;
+    for (int it = 0; it < 100 && hi - lo > 1e-14 * hi; ++it) {
+        const double w = hi - lo;
+        const double x[3] = {lo + 0.25 * w, lo + 0.5 * w, lo + 0.75 * w};
+        bool b[3];
+        below3(x, b);
+        if (b[0]) {
+            hi = x[0];
+        } else if (b[1]) {
+            lo = x[0];
+            hi = x[1];
+        } else if (b[2]) {
+            lo = x[1];
+            hi = x[2];
+        } else {
+            lo = x[2];
+        }
     }
     return lo;
 }
@@ -465,11 +484,19 @@ int prepare_model(mhs_plan *p, const mhs_model *model, ModelUpload &up)
     int st0 = model_depth(h, p->grid, model, &depth, nullptr);
     if (st0) return st0;
     if ((st0 = set_depth(h, depth))) return st0;
+    // the tables lie in one device range from level 0's FP64 table (the
+    // plan's layout); the host image mirrors it, padding zeroed, so that a
+    // single copy uploads the model
+    char *const base = (char *)h.lv[0].coef64;
+    bool contiguous = true;
     auto add = [&](void *dst, const void *src, size_t bytes) {
-        const size_t off = (up.data.size() + 63) & ~size_t(63);
-        up.data.resize(off + bytes);
+        if ((char *)dst < base) {
+            contiguous = false;
+            return;
+        }
+        const size_t off = (size_t)((char *)dst - base);
+        if (up.data.size() < off + bytes) up.data.resize(off + bytes);
         std::memcpy(up.data.data() + off, src, bytes);
-        up.parts.push_back({dst, off, bytes});
     };
     std::vector<double> tab, minv;
     std::vector<float> t32;
@@ -488,6 +515,8 @@ int prepare_model(mhs_plan *p, const mhs_model *model, ModelUpload &up)
             add(h.minv, minv.data(), minv.size() * sizeof(double));
         }
     }
+    if (!contiguous) return fail(MHS_ERR_WORKSPACE, "model tables are not laid out from level 0's table");
+    up.parts.push_back({base, 0, up.data.size()});
     // the plan's tables will hold this model once the copies have run
     p->cache.valid = true;
     p->cache.alpha = model->alpha;
@@ -1485,6 +1514,11 @@ int solve_interior_on(mhs_plan *p, const mhs_model *model, double *d_P, const mh
     SolveState *d_state = (SolveState *)p->stage.put(initial_state(o->rtol, o->max_cycles));
     double *T0 = (double *)h.lv[0].t[kF64];
     const int64_t N = (int64_t)h.lv[0].N;
+    // mixed path: when the plan's last solve of this kind took an odd number
+    // of refinement steps, a cold start begins from the twin, so that the
+    // same count ends in P with no copy
+    const int hint = mixed ? hint_of(p, kSolve3DMixed, o) : 0;
+    const bool swap = mixed && !o->warm_start && (hint & 1);
     PrepItem pi{};
     pi.P = d_P;
     pi.twin = T0;
@@ -1493,6 +1527,7 @@ int solve_interior_on(mhs_plan *p, const mhs_model *model, double *d_P, const mh
     pi.nz = p->grid.nz;
     pi.warm = o->warm_start;
     pi.faces = o->faces;
+    pi.swap = swap ? 1 : 0;
     pi.n = N;
     const PrepItem *d_prep = p->stage.put(pi);
     SolveState fin{};
@@ -1516,8 +1551,10 @@ int solve_interior_on(mhs_plan *p, const mhs_model *model, double *d_P, const mh
         if ((st = drive(p, cyc, d_state, o, &fin, &syncs, s, kSolve3D64))) return st;
     } else {
         // FP64 iterative refinement around FP32 V-cycles.  Step 0 only
-        // computes r = -A P; step s >= 1 applies the previous correction
-        // (P -> T0 for odd s, T0 -> P for even s) and recomputes r.
+        // computes r = -A U; step s >= 1 applies the previous correction
+        // (U -> V for odd s, V -> U for even s) and recomputes r.  U is P
+        // and V its twin, or the other way round (`swap`).
+        double *U = swap ? T0 : d_P, *V = swap ? d_P : T0;
         const Level &l0 = h.lv[0];
         float *r32 = (float *)l0.f[kF32];
         // inner cycles: locate the final correction buffer
@@ -1529,9 +1566,9 @@ int solve_interior_on(mhs_plan *p, const mhs_model *model, double *d_P, const mh
             ebuf = add_cycle(inner, p->stage, h, kF32, a, bb, r32, c == 0, false, o->nu1, o->nu2, d_state);
         }
         Program first, odd, even;
-        add_ir_step(first, p->stage, h, d_P, nullptr, nullptr, r32, d_state);
-        add_ir_step(odd, p->stage, h, d_P, T0, ebuf, r32, d_state);
-        add_ir_step(even, p->stage, h, T0, d_P, ebuf, r32, d_state);
+        add_ir_step(first, p->stage, h, U, nullptr, nullptr, r32, d_state);
+        add_ir_step(odd, p->stage, h, U, V, ebuf, r32, d_state);
+        add_ir_step(even, p->stage, h, V, U, ebuf, r32, d_state);
         for (Program *pg : {&first, &odd, &even})
             pg->launches.insert(pg->launches.end(), inner.launches.begin(), inner.launches.end());
         if (!first.ok || !odd.ok || !even.ok || !inner.ok || !d_state || !d_prep)
@@ -1542,16 +1579,17 @@ int solve_interior_on(mhs_plan *p, const mhs_model *model, double *d_P, const mh
         if ((st = drive_programs(
                  p,
                  [&](int step) -> const Program & { return step == 0 ? first : ((step & 1) ? odd : even); },
-                 d_state, o, hint_of(p, kSolve3DMixed, o), &ss, &syncs, s)))
+                 d_state, o, hint, &ss, &syncs, s)))
             return st;
         fin = ss;
         record_cycles(p, kSolve3DMixed, o, ss);
         if ((st = prof_collect(p, fin.checks - 1))) return st;
         const int steps = std::max(0, fin.checks - 1);
         inner_total = steps * o->inner_cycles;
-        // an odd step count leaves the iterate in the twin; the copy is
-        // stream-ordered like the rest of the solve's work
-        if (steps & 1) HIPCHK(launch_copy(T0, d_P, N, nullptr, s));
+        // the iterate ends in V after an odd step count, else in U; when
+        // that is the twin, the copy is stream-ordered like the rest of the
+        // solve's work
+        if (((steps & 1) ? V : U) == T0) HIPCHK(launch_copy(T0, d_P, N, nullptr, s));
     }
     const int status = status_of(fin.done);
     if (info) {

@@ -195,7 +195,7 @@ struct PrepItem {
     int32_t nx, ny, nz;
     int32_t warm;
     int32_t faces;      // 1: keep P's faces (2D: edges) as Dirichlet data
-    int32_t pad;
+    int32_t swap;       // 3D: the zero interior goes to the twin, P's interior is left as it is
     int64_t n;          // points covered
     int64_t base;       // first global thread of this item
 };

@@ -2095,7 +2095,8 @@ __device__ __forceinline__ int find_prep(const Item *items, int n, int64_t g)
 
 // Interior start of (8): P = 0 on side and top faces and on the base edges,
 // P = 0 in the interior (step 1 of the procedure) unless warm-started, and
-// the twin's faces equal P's faces.
+// the twin's faces equal P's faces.  With `swap` (cold starts only) the
+// solve starts from the twin: its interior is zeroed and P's is not touched.
 __global__ __launch_bounds__(256) void k_prep3(const PrepItem *__restrict__ items, int nitems)
 {
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -2121,6 +2122,8 @@ __global__ __launch_bounds__(256) void k_prep3(const PrepItem *__restrict__ item
         } else if (side || k == nz - 1) {
             if (!it.faces) it.P[e] = 0.0;
             if (it.twin) it.twin[e] = it.faces ? it.P[e] : 0.0;
+        } else if (it.swap) {
+            it.twin[e] = 0.0;
         } else if (!it.warm) {
             it.P[e] = 0.0;
         }

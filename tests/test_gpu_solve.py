@@ -320,6 +320,55 @@ def test_repeat_solve_reads_status_once_with_same_result(plans, prec):
     assert i2.host_syncs == 1 and i3.host_syncs == 1, (i2.host_syncs, i3.host_syncs)
 
 
+def test_mixed_start_from_twin_matches_fresh_plan():
+    """After a mixed solve of an odd number of refinement steps, the plan's
+    next cold mixed solve starts from P's twin so that the same count ends in
+    P without a copy.  Its result is bitwise that of a fresh plan: with the
+    predicted count, with an even count (a cap of two steps: the iterate is
+    copied back from the twin), and with none (zero magnetogram)."""
+    w = synth.workload("mhs-129", dims=(65, 65, 65))
+    m = w.model
+    bz = torch.from_numpy(w.bz0).to(DEV)
+    zero = torch.zeros_like(bz)
+
+    def run(plan, b, rtol, **kw):
+        P = torch.zeros((65, 65, 65), dtype=torch.float64, device=DEV)
+        plan.solve_boundary(b, P, make_opts(rtol=1e-10))
+        info = plan.solve_interior(m, P, make_opts(PREC_MIXED, rtol=rtol, **kw), raise_on_error=False)
+        torch.cuda.synchronize()
+        return P, info
+
+    def fresh(b, rtol, **kw):
+        plan = Plan(w.grid, PREC_FP64 | PREC_MIXED, device=DEV)
+        try:
+            return run(plan, b, rtol, **kw)
+        finally:
+            plan.close()
+
+    # a tolerance whose solve takes an odd number of steps
+    for rtol in (1e-10, 1e-9, 1e-11, 1e-8, 1e-12):
+        want, wi = fresh(bz, rtol)
+        assert wi.status == 0, wi.status
+        if wi.cycles % 2 == 1 and wi.cycles > 2:
+            break
+    else:
+        pytest.fail("no tolerance gave an odd step count")
+    cap, ci = fresh(bz, rtol, max_cycles=2)
+    assert ci.status == _lib.ERR_NO_CONVERGENCE and ci.cycles == 2
+    none, ni = fresh(zero, rtol)
+    assert ni.status == 0 and ni.cycles == 0
+    plan = Plan(w.grid, PREC_FP64 | PREC_MIXED, device=DEV)
+    try:
+        run(plan, bz, rtol)  # records the odd count
+        for b, kw, P_want, i_want in ((bz, {}, want, wi), (bz, {"max_cycles": 2}, cap, ci), (zero, {}, none, ni),
+                                      (bz, {}, want, wi)):
+            P, info = run(plan, b, rtol, **kw)
+            assert (info.status, info.cycles) == (i_want.status, i_want.cycles)
+            assert torch.equal(P, P_want)
+    finally:
+        plan.close()
+
+
 def test_error_paths(plans):
     w = synth.workload("mhs-129", dims=(33, 33, 33))
     m = w.model
