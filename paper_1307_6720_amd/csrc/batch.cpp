@@ -44,6 +44,9 @@ struct Slot {
     double *P = nullptr, *Bx = nullptr, *By = nullptr, *Bz = nullptr, *p = nullptr, *rho = nullptr;
     mhs_opts opts{};
     int steps = 0; // programs launched in the current phase
+    // mixed interior phase: the iterate starts in P's twin (the plan's last
+    // converged count was odd, so the same count ends in P without a copy)
+    bool swap = false;
     int ticks = 0; // ticks of the current phase whose status was read
     mhs_info info[2]{};
     std::chrono::steady_clock::time_point t0;
@@ -248,6 +251,7 @@ bool build_slot(const Slot &S, int i, SolveState *state, Staging &R, std::vector
             pi.nz = p->grid.nz;
             pi.warm = o.warm_start;
             pi.faces = o.faces;
+            pi.swap = S.swap ? 1 : 0;
             pi.n = N;
             const PrepItem *d = R.put(pi);
             if (!d) return false;
@@ -273,8 +277,9 @@ bool build_slot(const Slot &S, int i, SolveState *state, Staging &R, std::vector
             tag_cycle(pg, 0, i, out);
             return true;
         }
-        // refinement step S.steps: step 0 checks P; odd steps write P + e
-        // into T0, even steps T0 + e into P (the single-request ping-pong)
+        // refinement step S.steps: step 0 checks U; odd steps write U + e
+        // into V, even steps V + e into U (the single-request ping-pong; U
+        // is P and V its twin, or the other way round with S.swap)
         float *r32 = (float *)l0.f[kF32];
         std::vector<Program> inner((size_t)o.inner_cycles);
         void *ebuf = nullptr;
@@ -284,8 +289,9 @@ bool build_slot(const Slot &S, int i, SolveState *state, Staging &R, std::vector
             ebuf = add_cycle(inner[(size_t)c], R, h, kF32, a, bb, r32, c == 0, false, o.nu1, o.nu2, state);
         }
         const int s = S.steps;
-        const double *uin = (s == 0 || (s & 1)) ? S.P : T0;
-        double *uout = s == 0 ? nullptr : ((s & 1) ? T0 : S.P);
+        double *U = S.swap ? T0 : S.P, *V = S.swap ? S.P : T0;
+        const double *uin = (s == 0 || (s & 1)) ? U : V;
+        double *uout = s == 0 ? nullptr : ((s & 1) ? V : U);
         Program ir;
         add_ir_step(ir, R, h, uin, uout, s == 0 ? nullptr : ebuf, r32, state);
         if (!ir.ok || ir.launches.size() != 2) return false;
@@ -299,7 +305,8 @@ bool build_slot(const Slot &S, int i, SolveState *state, Staging &R, std::vector
     }
     if (S.phase == kFinish) {
         const int64_t N = (int64_t)p->h3.lv[0].N;
-        if (o.precision == MHS_PREC_MIXED && (S.info[1].cycles & 1)) {
+        // the iterate ends in V after an odd step count, else in U
+        if (o.precision == MHS_PREC_MIXED && ((S.info[1].cycles & 1) != (S.swap ? 1 : 0))) {
             Launch c{};
             c.kind = Launch::kCopy;
             c.src = (const double *)p->h3.lv[0].t[kF64];
@@ -862,10 +869,14 @@ int mhs_batch_step(mhs_batch *b, void *stream, int32_t *n_active)
             inf.rel_residual = ss.r0 > 0 ? ss.rnorm / ss.r0 : 0.0;
             inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - S.t0).count();
             S.epoch = ++b->epochs;
+            if (q == 1 && S.opts.precision == MHS_PREC_MIXED) record_cycles(S.plan, kSolve3DMixed, &S.opts, ss);
             if (inf.status != MHS_OK) {
                 S.phase = kDone;
                 continue;
             }
+            if (q == 0)
+                S.swap = S.opts.precision == MHS_PREC_MIXED && !S.opts.warm_start &&
+                         (hint_of(S.plan, kSolve3DMixed, &S.opts) & 1);
             S.phase = q == 0 ? kInterior : kFinish;
             S.fresh = true;
             S.finish_sent = false;
