@@ -221,6 +221,23 @@ int mhs_solve_interior(mhs_plan *plan, const mhs_model *model, double *d_P, cons
 int mhs_fields(mhs_plan *plan, const mhs_model *model, const double *d_P, double *d_Bx,
                double *d_By, double *d_Bz, double *d_p, double *d_rho, void *stream);
 
+/* Steps 2 and 3 of the procedure and the field recovery in one call: the
+ * same work and results (bitwise) as mhs_solve_boundary(opts2d), then
+ * mhs_solve_interior(opts3d), then mhs_fields, on one stream, with fewer
+ * host round trips: the model's 3D tables are computed on the host while
+ * the base cycles run, and the field recovery is enqueued behind every
+ * batch of interior cycles, running only once the solve has converged with
+ * its iterate in d_P (else it runs after the final copy).  d_Bx ... d_rho:
+ * all five (nx*ny*nz doubles on the device) or all NULL (no recovery).
+ * Errors as the three calls; the first failing step ends the call (a base
+ * solve that does not converge leaves the interior and the outputs
+ * untouched).  Returns when the interior solve's status is known; the
+ * recovery may still run on the stream. */
+int mhs_solve_equilibrium(mhs_plan *plan, const mhs_model *model, const double *d_bz0, double *d_P,
+                          double *d_Bx, double *d_By, double *d_Bz, double *d_p, double *d_rho,
+                          const mhs_opts *opts2d, const mhs_opts *opts3d, mhs_info *info2d,
+                          mhs_info *info3d, void *stream);
+
 /* ---- the general elliptic problem (Section 2.2) -------------------------- *
  * Section 2.2 reduces the model to scalar problems of the form
  *     a(x) lap u + b(x) u = c(x) in D,  u given on the boundary of D,

@@ -102,6 +102,8 @@ def lib():
         "mhs_solve_interior": (C.c_int, [vp, P(Model), vp, P(Opts), P(Info), vp]),
         "mhs_solve_interior_noalloc": (C.c_int, [P(Grid), P(Model), vp, P(Opts), P(Info), vp]),
         "mhs_fields": (C.c_int, [vp, P(Model), vp, vp, vp, vp, vp, vp, vp]),
+        "mhs_solve_equilibrium": (C.c_int, [vp, P(Model), vp, vp, vp, vp, vp, vp, vp, P(Opts), P(Opts), P(Info),
+                                            P(Info), vp]),
         "mhs_solve_general": (C.c_int, [vp, vp, vp, vp, vp, P(Opts), P(Info), vp]),
         "mhs_solve_face": (C.c_int, [vp, i32, vp, vp, vp, vp, P(Opts), P(Info), vp]),
         "mhs_stage_smooth": (C.c_int, [vp, P(Model), i32, i32, i32, vp, vp, i32, i32, vp]),

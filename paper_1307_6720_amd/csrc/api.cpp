@@ -932,7 +932,40 @@ FieldsItem fields_item(const mhs_plan *p, const mhs_model *model, const double *
     fi.kz = chunk(nz, fi.ntx * fi.nty, kKZ, kFieldsTargetGroups);
     fi.ntz = ceil_div(nz, fi.kz);
     fi.tile_base = 0;
+    fi.gate = nullptr;
+    fi.gate_odd = -1;
     return fi;
+}
+
+int stage_fields(mhs_plan *p, const mhs_model *model, const double *d_P, double *Bx, double *By, double *Bz,
+                 double *pr, double *rho, const FieldsItem **d_item, FieldsItem *item)
+{
+    // the table goes through the staging buffer with the launch items
+    const int nz = p->grid.nz;
+    const size_t bytes = 4 * (size_t)nz * sizeof(double);
+    p->stage.used = (p->stage.used + 63) & ~size_t(63);
+    const size_t tab_off = p->stage.used;
+    if (tab_off + bytes > p->stage.cap) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
+    double *tab = (double *)(p->stage.host + tab_off);
+    std::copy(model->xi, model->xi + nz, tab);
+    std::copy(model->dxi, model->dxi + nz, tab + nz);
+    std::copy(model->pb, model->pb + nz, tab + 2 * nz);
+    std::copy(model->rhob, model->rhob + nz, tab + 3 * nz);
+    p->stage.used += bytes;
+    *item = fields_item(p, model, (const double *)(p->stage.dev + tab_off), d_P, Bx, By, Bz, pr, rho);
+    *d_item = p->stage.put(*item);
+    return *d_item ? MHS_OK : fail(MHS_ERR_WORKSPACE, "staging area exhausted");
+}
+
+Launch fields_launch(const mhs_plan *p, const FieldsItem *d, const FieldsItem &fi)
+{
+    Launch L{};
+    L.kind = Launch::kFields;
+    L.items = d;
+    L.ntiles = fi.ntx * fi.nty * fi.ntz;
+    L.prof = MHS_PROF_FIELDS;
+    L.bytes = 48.0 * (double)p->grid.nx * p->grid.ny * p->grid.nz;
+    return L;
 }
 
 hipEvent_t prof_event(Profiler &pr)
@@ -1213,8 +1246,14 @@ size_t check_len(const Program &pg)
     return pg.launches.size();
 }
 
+// `tail` (optional) enqueues more work after every batch, before its status
+// read; `overlap` (optional) runs once on the host after the first two
+// programs are enqueued (the device works on them meanwhile; enqueuing a
+// whole batch of small launches first would leave the host behind the
+// device).
 int drive_programs(mhs_plan *p, const std::function<const Program &(int)> &prog, const SolveState *d_state,
-                   const mhs_opts *o, int hint, SolveState *out, int *syncs, hipStream_t s)
+                   const mhs_opts *o, int hint, SolveState *out, int *syncs, hipStream_t s,
+                   const std::function<int()> *overlap = nullptr, const std::function<int()> *tail = nullptr)
 {
     // Each program (cycle or refinement step) starts with the convergence
     // check of the iterate before it.  A batch of nb programs runs the rest
@@ -1245,8 +1284,13 @@ int drive_programs(mhs_plan *p, const std::function<const Program &(int)> &prog,
                 if ((st = run_range(p, pg, 0, c, s, k))) return st;
                 resume = c;
             }
+            if (overlap && (q == 1 || q + 1 == nb)) {
+                if ((st = (*overlap)())) return st;
+                overlap = nullptr;
+            }
         }
         checked += nb;
+        if (tail && (st = (*tail)())) return st;
         if ((st = read_state(p, d_state, &ss, s))) return st;
         ++*syncs;
         if (ss.done != kRunning) break;
@@ -1256,10 +1300,10 @@ int drive_programs(mhs_plan *p, const std::function<const Program &(int)> &prog,
 }
 
 int drive(mhs_plan *p, const Program &cycle, const SolveState *d_state, const mhs_opts *o, SolveState *out,
-          int *syncs, hipStream_t s, int kind)
+          int *syncs, hipStream_t s, int kind, const std::function<int()> *overlap)
 {
     int st = drive_programs(
-        p, [&](int) -> const Program & { return cycle; }, d_state, o, hint_of(p, kind, o), out, syncs, s);
+        p, [&](int) -> const Program & { return cycle; }, d_state, o, hint_of(p, kind, o), out, syncs, s, overlap);
     if (st) return st;
     record_cycles(p, kind, o, *out);
     return prof_collect(p, out->checks - 1);
@@ -1270,8 +1314,17 @@ double seconds_since(std::chrono::steady_clock::time_point t0)
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
+// Field recovery requested with an interior solve: launched behind every
+// batch of the solve, gated on its convergence, so that a solve whose last
+// batch converges as predicted has its fields before its status is read.
+struct FieldsReq {
+    const mhs_model *model;
+    double *Bx, *By, *Bz, *p, *rho;
+};
 int solve_interior_on(mhs_plan *p, const mhs_model *model, double *d_P, const mhs_opts *o, mhs_info *info,
-                      hipStream_t s, std::chrono::steady_clock::time_point t0);
+                      hipStream_t s, std::chrono::steady_clock::time_point t0, const FieldsReq *fr = nullptr);
+int solve_boundary_on(mhs_plan *p, const double *d_bz0, double *d_P, const mhs_opts *o, mhs_info *info, hipStream_t s,
+                      std::chrono::steady_clock::time_point t0, const std::function<int()> *overlap = nullptr);
 
 } // namespace mhs
 
@@ -1433,7 +1486,18 @@ int mhs_solve_boundary(mhs_plan *p, const double *d_bz0, double *d_P, const mhs_
     int st = validate_opts(o);
     if (st) return st;
     if ((st = set_device(p))) return st;
-    hipStream_t s = (hipStream_t)stream;
+    return solve_boundary_on(p, d_bz0, d_P, o, info, (hipStream_t)stream, t0);
+}
+
+} // extern "C"
+
+namespace mhs {
+
+// The base solve on a plan whose device is current, with validated options.
+int solve_boundary_on(mhs_plan *p, const double *d_bz0, double *d_P, const mhs_opts *o, mhs_info *info, hipStream_t s,
+                      std::chrono::steady_clock::time_point t0, const std::function<int()> *overlap)
+{
+    int st = MHS_OK;
     Hierarchy &h = p->h2;
     if ((st = begin_staging(p))) return st;
     SolveState *d_state = (SolveState *)p->stage.put(initial_state(o->rtol, o->max_cycles));
@@ -1467,7 +1531,7 @@ int mhs_solve_boundary(mhs_plan *p, const double *d_bz0, double *d_P, const mhs_
     HIPCHK(launch_prep2(d_prep, 1, pi.n, s));
     SolveState fin{};
     int syncs = 0;
-    if ((st = drive(p, cyc, d_state, o, &fin, &syncs, s, kSolve2D))) return st;
+    if ((st = drive(p, cyc, d_state, o, &fin, &syncs, s, kSolve2D, overlap))) return st;
     const int status = status_of(fin.done);
     if (info) {
         info->status = status;
@@ -1484,6 +1548,10 @@ int mhs_solve_boundary(mhs_plan *p, const double *d_bz0, double *d_P, const mhs_
     return MHS_OK;
 }
 
+} // namespace mhs
+
+extern "C" {
+
 int mhs_solve_interior(mhs_plan *p, const mhs_model *model, double *d_P, const mhs_opts *o, mhs_info *info,
                        void *stream)
 {
@@ -1498,13 +1566,53 @@ int mhs_solve_interior(mhs_plan *p, const mhs_model *model, double *d_P, const m
     return solve_interior_on(p, model, d_P, o, info, (hipStream_t)stream, t0);
 }
 
+int mhs_solve_equilibrium(mhs_plan *p, const mhs_model *model, const double *d_bz0, double *d_P, double *d_Bx,
+                          double *d_By, double *d_Bz, double *d_p, double *d_rho, const mhs_opts *o2,
+                          const mhs_opts *o3, mhs_info *info2, mhs_info *info3, void *stream)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!p || !d_bz0 || !d_P) return fail(MHS_ERR_INVALID_ARG, "NULL argument");
+    const int nf = (d_Bx != nullptr) + (d_By != nullptr) + (d_Bz != nullptr) + (d_p != nullptr) + (d_rho != nullptr);
+    if (nf != 0 && nf != 5) return fail(MHS_ERR_INVALID_ARG, "field outputs: all five or none");
+    int st = validate_opts(o2);
+    if (st) return st;
+    if ((st = validate_opts(o3))) return st;
+    if ((st = validate_model(p, model, nf == 5))) return st;
+    if (!(p->precisions & o3->precision))
+        return fail(MHS_ERR_UNSUPPORTED, "plan was not created for precision %d", o3->precision);
+    if ((st = set_device(p))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    // the model's 3D tables are prepared on the host while the first batch
+    // of base cycles runs
+    ModelUpload up;
+    int prep_st = MHS_OK;
+    bool prepared = false;
+    const std::function<int()> prep = [&]() -> int {
+        prep_st = prepare_model(p, model, up);
+        prepared = prep_st == MHS_OK;
+        return MHS_OK;
+    };
+    st = solve_boundary_on(p, d_bz0, d_P, o2, info2, s, t0, &prep);
+    if (!st && !prepared && prep_st == MHS_OK) prep_st = prepare_model(p, model, up); // the hook did not run
+    if (st || prep_st) {
+        if (prepared && !up.parts.empty()) invalidate_model(p); // the tables never reach the device
+        return st ? st : prep_st;
+    }
+    for (const ModelUpload::Part &q : up.parts)
+        HIPCHK(hipMemcpyAsync(q.dst, up.data.data() + q.off, q.bytes, hipMemcpyHostToDevice, s));
+    // pageable source: the copy has consumed it before `up` goes away
+    if (!up.parts.empty()) HIPCHK(hipStreamSynchronize(s));
+    const FieldsReq fr{model, d_Bx, d_By, d_Bz, d_p, d_rho};
+    return solve_interior_on(p, model, d_P, o3, info3, s, std::chrono::steady_clock::now(), nf ? &fr : nullptr);
+}
+
 } // extern "C"
 
 namespace mhs {
 
 // The interior solve on a validated plan whose device is current.
 int solve_interior_on(mhs_plan *p, const mhs_model *model, double *d_P, const mhs_opts *o, mhs_info *info,
-                      hipStream_t s, std::chrono::steady_clock::time_point t0)
+                      hipStream_t s, std::chrono::steady_clock::time_point t0, const FieldsReq *fr)
 {
     int st = MHS_OK;
     Hierarchy &h = p->h3;
@@ -1533,6 +1641,28 @@ int solve_interior_on(mhs_plan *p, const mhs_model *model, double *d_P, const mh
     SolveState fin{};
     int syncs = 0;
     int inner_total = 0;
+    // field recovery (fr): an item gated on convergence with P holding the
+    // iterate, launched behind every batch, and an ungated one for a solve
+    // whose iterate ends in the twin (run after the copy)
+    const FieldsItem *d_fgated = nullptr, *d_fplain = nullptr;
+    FieldsItem fitem{};
+    bool fields_done = false;
+    auto stage_fields_pair = [&](const SolveState *gate, int gate_odd) -> int {
+        int e = stage_fields(p, fr->model, d_P, fr->Bx, fr->By, fr->Bz, fr->p, fr->rho, &d_fplain, &fitem);
+        if (e) return e;
+        FieldsItem g = fitem;
+        g.gate = gate;
+        g.gate_odd = gate_odd;
+        d_fgated = p->stage.put(g);
+        return d_fgated ? MHS_OK : fail(MHS_ERR_WORKSPACE, "staging area exhausted");
+    };
+    const std::function<int()> gated_fields = [&]() -> int {
+        Program pg;
+        Launch L = fields_launch(p, d_fgated, fitem);
+        L.prof = -1; // mostly a launch that exits at once: not timed
+        pg.launches.push_back(L);
+        return run_program(p, pg, s);
+    };
     if (!mixed) {
         Program cyc;
         void *res = add_cycle(cyc, p->stage, h, kF64, d_P, T0, nullptr, false, true, o->nu1, o->nu2, d_state);
@@ -1546,9 +1676,17 @@ int solve_interior_on(mhs_plan *p, const mhs_model *model, double *d_P, const mh
             cyc.launches.push_back(c);
         }
         if (!cyc.ok || !d_state || !d_prep) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
+        if (fr && (st = stage_fields_pair(d_state, -1))) return st;
         if ((st = flush_staging(p, s))) return st;
         HIPCHK(launch_prep3(d_prep, 1, prep3_threads(N), s));
-        if ((st = drive(p, cyc, d_state, o, &fin, &syncs, s, kSolve3D64))) return st;
+        if ((st = drive_programs(
+                 p, [&](int) -> const Program & { return cyc; }, d_state, o, hint_of(p, kSolve3D64, o), &fin, &syncs,
+                 s, nullptr, fr ? &gated_fields : nullptr)))
+            return st;
+        record_cycles(p, kSolve3D64, o, fin);
+        if ((st = prof_collect(p, fin.checks - 1))) return st;
+        // P holds the iterate of every checked cycle: the gated recovery ran
+        fields_done = true;
     } else {
         // FP64 iterative refinement around FP32 V-cycles.  Step 0 only
         // computes r = -A U; step s >= 1 applies the previous correction
@@ -1573,13 +1711,15 @@ int solve_interior_on(mhs_plan *p, const mhs_model *model, double *d_P, const mh
             pg->launches.insert(pg->launches.end(), inner.launches.begin(), inner.launches.end());
         if (!first.ok || !odd.ok || !even.ok || !inner.ok || !d_state || !d_prep)
             return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
+        // P holds the iterate after an odd count with swap, an even one without
+        if (fr && (st = stage_fields_pair(d_state, swap ? 1 : 0))) return st;
         if ((st = flush_staging(p, s))) return st;
         HIPCHK(launch_prep3(d_prep, 1, prep3_threads(N), s));
         SolveState ss{};
         if ((st = drive_programs(
                  p,
                  [&](int step) -> const Program & { return step == 0 ? first : ((step & 1) ? odd : even); },
-                 d_state, o, hint, &ss, &syncs, s)))
+                 d_state, o, hint, &ss, &syncs, s, nullptr, fr ? &gated_fields : nullptr)))
             return st;
         fin = ss;
         record_cycles(p, kSolve3DMixed, o, ss);
@@ -1589,9 +1729,17 @@ int solve_interior_on(mhs_plan *p, const mhs_model *model, double *d_P, const mh
         // the iterate ends in V after an odd step count, else in U; when
         // that is the twin, the copy is stream-ordered like the rest of the
         // solve's work
-        if (((steps & 1) ? V : U) == T0) HIPCHK(launch_copy(T0, d_P, N, nullptr, s));
+        if (((steps & 1) ? V : U) == T0)
+            HIPCHK(launch_copy(T0, d_P, N, nullptr, s));
+        else
+            fields_done = true;
     }
     const int status = status_of(fin.done);
+    if (fr && status == MHS_OK && !fields_done) {
+        Program pg;
+        pg.launches.push_back(fields_launch(p, d_fplain, fitem));
+        if ((st = run_program(p, pg, s))) return st;
+    }
     if (info) {
         info->status = status;
         info->cycles = std::max(0, fin.checks - 1);
@@ -1619,32 +1767,13 @@ int mhs_fields(mhs_plan *p, const mhs_model *model, const double *d_P, double *d
     if (st) return st;
     if ((st = set_device(p))) return st;
     hipStream_t s = (hipStream_t)stream;
-    const int nx = p->grid.nx, ny = p->grid.ny, nz = p->grid.nz;
     if ((st = begin_staging(p))) return st;
-    // the table goes through the staging buffer too (one transfer)
-    std::vector<double> tab(4 * (size_t)nz);
-    std::copy(model->xi, model->xi + nz, tab.begin());
-    std::copy(model->dxi, model->dxi + nz, tab.begin() + nz);
-    std::copy(model->pb, model->pb + nz, tab.begin() + 2 * nz);
-    std::copy(model->rhob, model->rhob + nz, tab.begin() + 3 * nz);
-    p->stage.used = (p->stage.used + 63) & ~size_t(63);
-    const size_t tab_off = p->stage.used;
-    if (tab_off + tab.size() * sizeof(double) > p->stage.cap) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
-    std::memcpy(p->stage.host + tab_off, tab.data(), tab.size() * sizeof(double));
-    p->stage.used += tab.size() * sizeof(double);
-    const FieldsItem fi = fields_item(p, model, (const double *)(p->stage.dev + tab_off), d_P, d_Bx, d_By, d_Bz, d_p,
-                                      d_rho);
-    const FieldsItem *d = p->stage.put(fi);
-    if (!d) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
+    const FieldsItem *d = nullptr;
+    FieldsItem fi{};
+    if ((st = stage_fields(p, model, d_P, d_Bx, d_By, d_Bz, d_p, d_rho, &d, &fi))) return st;
     if ((st = flush_staging(p, s))) return st;
     Program pg;
-    Launch L{};
-    L.kind = Launch::kFields;
-    L.items = d;
-    L.ntiles = fi.ntx * fi.nty * fi.ntz;
-    L.prof = MHS_PROF_FIELDS;
-    L.bytes = 48.0 * (double)nx * ny * nz;
-    pg.launches.push_back(L);
+    pg.launches.push_back(fields_launch(p, d, fi));
     return run_program(p, pg, s);
 }
 

@@ -158,6 +158,11 @@ struct FieldsItem {
     int32_t ntx, nty, ntz;
     int32_t tile_base;
     int32_t kz;
+    // launched ahead of the host's status read: the recovery runs only once
+    // this solve has converged with P holding its iterate (null: always)
+    const SolveState *gate;
+    int32_t gate_odd; // -1: P always holds it; 0/1: only after an even/odd count of cycles
+    int32_t pad;
 };
 
 // Diagnostics of an equilibrium (current density, force-balance and

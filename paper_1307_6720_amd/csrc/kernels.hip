@@ -1641,6 +1641,10 @@ __global__ __launch_bounds__(kFThreads) void k_fields(const FieldsItem *__restri
     __shared__ double SB[3 * BSLOT];
     const int tile = xcd_tile();
     const FieldsItem *it = items + find_item(items, nitems, tile);
+    if (it->gate) {
+        const auto *g = gin<SolveState>(it->gate);
+        if (g->done != kConverged || (it->gate_odd >= 0 && ((g->checks - 1) & 1) != it->gate_odd)) return;
+    }
     const MHS_GLOBAL double *__restrict__ P = gin<double>(it->P);
     const int nx = it->nx, ny = it->ny, nz = it->nz;
     const int kz = it->kz;

@@ -4,6 +4,7 @@
 
 #include <chrono>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <string>
 #include <vector>
@@ -227,8 +228,10 @@ int next_batch(const SolveState &ss, const mhs_opts *o, int launched, int hint);
 // finished one.
 int hint_of(const mhs_plan *p, int kind, const mhs_opts *o);
 void record_cycles(mhs_plan *p, int kind, const mhs_opts *o, const SolveState &ss);
+// `overlap`, when given, runs once on the host after the first batch of
+// launches is enqueued (host work that overlaps the device's).
 int drive(mhs_plan *p, const Program &cycle, const SolveState *d_state, const mhs_opts *o, SolveState *out,
-          int *syncs, hipStream_t s, int kind);
+          int *syncs, hipStream_t s, int kind, const std::function<int()> *overlap = nullptr);
 double seconds_since(std::chrono::steady_clock::time_point t0);
 
 // Shapes and step kinds of a multigrid hierarchy (api.cpp).

@@ -247,6 +247,31 @@ class Plan:
             check(code)
         return info
 
+    def solve_equilibrium(self, bz0, model, P, out=None, opts2d=None, opts3d=None, raise_on_error=True):
+        """Equations (11) and (8) and the field recovery in one library call
+        (mhs_solve_equilibrium): the results of solve_boundary,
+        solve_interior and fields in turn, with fewer host round trips.
+        out: five tensors (Bx, By, Bz, p, rho), or None for no recovery.
+        Returns (info2d, info3d)."""
+        self._check(bz0, self.shape[1:], "bz0")
+        self._check(P, self.shape, "P")
+        if out is not None:
+            out = tuple(out)
+            if len(out) != 5:
+                raise ValueError("out must hold five tensors (Bx, By, Bz, p, rho)")
+            self._check_fields(out, ("Bx", "By", "Bz", "p", "rho"))
+        o2 = opts2d or make_opts()
+        o3 = opts3d or make_opts()
+        m = _ModelArgs.of(model)
+        i2, i3 = _lib.Info(), _lib.Info()
+        fp = [_ptr(t) for t in out] if out is not None else [None] * 5
+        with torch.cuda.device(self.device):
+            code = _lib.lib().mhs_solve_equilibrium(self.h, C.byref(m.c), _ptr(bz0), _ptr(P), *fp, C.byref(o2),
+                                                    C.byref(o3), C.byref(i2), C.byref(i3), _stream(self.device))
+        if raise_on_error:
+            check(code)
+        return i2, i3
+
     # ---- the general elliptic problem of Section 2.2 ---------------------------
     def solve_general(self, a, b, c, u, opts=None, raise_on_error=True):
         """a lap u + b u = c on the plan's 3D grid (per-node FP64 a, b, c of
@@ -469,12 +494,9 @@ def solve(plan: Plan, bz0, model, precision=PREC_FP64, rtol=1e-10, rtol2d=None, 
     else:
         P, F = out[0], tuple(out[1:]) if fields else None
     o2 = make_opts(PREC_FP64, rtol if rtol2d is None else rtol2d, max_cycles)
-    i2 = plan.solve_boundary(bz0, P, o2)
     o3 = make_opts(precision, rtol, max_cycles, inner_cycles=inner_cycles)
-    i3 = plan.solve_interior(model, P, o3)
-    if fields:
-        plan.fields(model, P, F)
-    else:
+    i2, i3 = plan.solve_equilibrium(bz0, model, P, F if fields else None, o2, o3)
+    if not fields:
         F = (None,) * 5
     return SolveResult(P, *F, i2.as_dict(), i3.as_dict())
 

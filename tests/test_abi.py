@@ -98,6 +98,8 @@ def test_null_arguments_rejected():
     L = _lib.lib()
     assert L.mhs_workspace_bytes(None, 1, None) == _lib.ERR_INVALID_ARG
     assert L.mhs_solve_boundary(None, None, None, None, None, None) == _lib.ERR_INVALID_ARG
+    assert L.mhs_solve_equilibrium(None, None, None, None, None, None, None, None, None, None, None, None, None,
+                                   None) == _lib.ERR_INVALID_ARG
     assert L.mhs_plan_destroy(None) == _lib.MHS_OK
     assert L.mhs_trace_field_lines(None, None, None, None, None, 1, 0.1, 1, 0.0, None, None, None,
                                    None) == _lib.ERR_INVALID_ARG

@@ -369,6 +369,116 @@ def test_mixed_start_from_twin_matches_fresh_plan():
         plan.close()
 
 
+def _three_calls(w, bz, prec, rtol=1e-10, **kw):
+    """Boundary, interior and fields as three calls on a fresh plan."""
+    plan = Plan(w.grid, PREC_FP64 | PREC_MIXED, device=DEV)
+    try:
+        P = torch.zeros(w.grid.shape, dtype=torch.float64, device=DEV)
+        F = tuple(torch.zeros_like(P) for _ in range(5))
+        i2 = plan.solve_boundary(bz, P, make_opts(rtol=1e-10))
+        i3 = plan.solve_interior(w.model, P, make_opts(prec, rtol=rtol, **kw), raise_on_error=False)
+        if i3.status == 0:
+            plan.fields(w.model, P, F)
+        torch.cuda.synchronize()
+        return P, F, i2, i3
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("prec", [PREC_FP64, PREC_MIXED])
+def test_equilibrium_call_equals_three_calls(prec):
+    """mhs_solve_equilibrium gives bitwise the results of the boundary,
+    interior and fields calls made one after the other: on a plan's first
+    call, on repeats (where the recovery enqueued behind the converging batch
+    is the one that runs), and with no recovery requested."""
+    w = synth.workload("mhs-129", dims=(65, 65, 65))
+    bz = torch.from_numpy(w.bz0).to(DEV)
+    P0, F0, i2a, i3a = _three_calls(w, bz, prec)
+    plan = Plan(w.grid, PREC_FP64 | PREC_MIXED, device=DEV)
+    try:
+        for rep in range(3):
+            P = torch.zeros(w.grid.shape, dtype=torch.float64, device=DEV)
+            F = tuple(torch.full_like(P, 7.0) for _ in range(5))
+            i2, i3 = plan.solve_equilibrium(bz, w.model, P, F, make_opts(rtol=1e-10), make_opts(prec, rtol=1e-10))
+            torch.cuda.synchronize()
+            assert (i2.cycles, i3.cycles) == (i2a.cycles, i3a.cycles)
+            assert torch.equal(P, P0)
+            for a, b in zip(F, F0):
+                assert torch.equal(a, b)
+        P = torch.zeros(w.grid.shape, dtype=torch.float64, device=DEV)
+        plan.solve_equilibrium(bz, w.model, P, None, make_opts(rtol=1e-10), make_opts(prec, rtol=1e-10))
+        torch.cuda.synchronize()
+        assert torch.equal(P, P0)
+    finally:
+        plan.close()
+
+
+def test_equilibrium_call_when_the_count_differs_from_the_last():
+    """After a mixed solve of an odd number of steps the next one starts
+    from P's twin; when its count is even (none for a zero magnetogram, two
+    under a cap) the recovery gated on P holding the iterate does not run
+    and the call recovers the fields after the copy back (or, capped, stops
+    with the copied iterate in P).  A base solve that does not converge ends
+    the call with the interior untouched, and the model prepared meanwhile
+    is uploaded by the next call."""
+    w = synth.workload("mhs-129", dims=(65, 65, 65))
+    bz = torch.from_numpy(w.bz0).to(DEV)
+    zero = torch.zeros_like(bz)
+    for rtol in (1e-10, 1e-9, 1e-11, 1e-8, 1e-12):
+        P0, F0, _, i3a = _three_calls(w, bz, PREC_MIXED, rtol)
+        if i3a.cycles % 2 == 1 and i3a.cycles > 2:
+            break
+    else:
+        pytest.fail("no tolerance gave an odd step count")
+    Pz, Fz, _, iz = _three_calls(w, zero, PREC_MIXED, rtol)
+    assert iz.cycles == 0
+    Pc, _, _, ic = _three_calls(w, bz, PREC_MIXED, rtol, max_cycles=2)
+    assert ic.status == _lib.ERR_NO_CONVERGENCE
+    plan = Plan(w.grid, PREC_FP64 | PREC_MIXED, device=DEV)
+
+    def call(b, P, o2=None, **kw):
+        F = tuple(torch.full_like(P, 7.0) for _ in range(5))
+        i2, i3 = plan.solve_equilibrium(b, w.model, P, F, o2 or make_opts(rtol=1e-10),
+                                        make_opts(PREC_MIXED, rtol=rtol, **kw), raise_on_error=False)
+        torch.cuda.synchronize()
+        return F, i2, i3
+
+    try:
+        P = torch.zeros(w.grid.shape, dtype=torch.float64, device=DEV)
+        F, _, i3 = call(bz, P)
+        assert i3.cycles == i3a.cycles and torch.equal(P, P0)
+        P = torch.zeros_like(P)
+        F, _, i3 = call(zero, P)
+        assert i3.status == 0 and i3.cycles == 0 and torch.equal(P, Pz)
+        for a, b in zip(F, Fz):
+            assert torch.equal(a, b)
+        call(bz, torch.zeros_like(P))  # the odd count again
+        P = torch.zeros_like(P)
+        _, _, i3 = call(bz, P, max_cycles=2)
+        assert i3.status == _lib.ERR_NO_CONVERGENCE and torch.equal(P, Pc)
+        # a base solve capped at one cycle: the interior planes keep their values
+        fresh = Plan(w.grid, PREC_FP64 | PREC_MIXED, device=DEV)
+        try:
+            P = torch.full(w.grid.shape, 3.0, dtype=torch.float64, device=DEV)
+            F = tuple(torch.full_like(P, 7.0) for _ in range(5))
+            i2, _ = fresh.solve_equilibrium(bz, w.model, P, F, make_opts(rtol=1e-10, max_cycles=1),
+                                            make_opts(PREC_MIXED, rtol=rtol), raise_on_error=False)
+            torch.cuda.synchronize()
+            assert i2.status == _lib.ERR_NO_CONVERGENCE
+            assert bool((P[1:] == 3.0).all()) and all(bool((t == 7.0).all()) for t in F)
+            P = torch.zeros_like(P)
+            F = tuple(torch.zeros_like(P) for _ in range(5))
+            fresh.solve_equilibrium(bz, w.model, P, F, make_opts(rtol=1e-10), make_opts(PREC_MIXED, rtol=rtol))
+            torch.cuda.synchronize()
+            assert torch.equal(P, P0)
+            for a, b in zip(F, F0):
+                assert torch.equal(a, b)
+        finally:
+            fresh.close()
+    finally:
+        plan.close()
+
+
 def test_error_paths(plans):
     w = synth.workload("mhs-129", dims=(33, 33, 33))
     m = w.model
