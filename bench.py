@@ -748,7 +748,7 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
-        print("bench.py: this build measures one GPU only (the path has no multi-GPU sharding); "
+        print("bench.py: measures one GPU only (the path has no multi-GPU sharding); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
