@@ -875,7 +875,7 @@ void *add_cycle(Program &pg, Staging &st, const Hierarchy &h, int path, void *a0
 // r32 = -A u_out in FP32, and the norm check of u_out.  The inner FP32
 // cycles that produce the next e follow it in the same program.
 void add_ir_step(Program &pg, Staging &st, const Hierarchy &h, const double *uin, double *uout, const void *e,
-                 float *r32, SolveState *state)
+                 float *r32, SolveState *state, bool zero_in)
 {
     const Level &l0 = h.lv[0];
     LevelItem it = level_item(h, 0, kF64);
@@ -896,11 +896,12 @@ void add_ir_step(Program &pg, Staging &st, const Hierarchy &h, const double *uin
     }
     Launch L{};
     L.kind = Launch::kIr3;
-    L.flags = e ? 1 : 0;
+    L.flags = (e ? 1 : 0) | (zero_in ? 2 : 0);
     L.items = d;
     L.ntiles = l0.ir_tiles();
     L.prof = MHS_PROF_REFINE;
-    L.bytes = (double)l0.N * (e ? 8.0 + 4.0 + 8.0 + 4.0 : 8.0 + 4.0);
+    // read u (not its interior with zero_in) and e, write u and r
+    L.bytes = (double)l0.N * ((zero_in ? 0.0 : 8.0) + (e ? 4.0 + 8.0 : 0.0) + 4.0);
     L.pre = true;
     pg.launches.push_back(L);
     add_finalize(pg, st, h.partials, l0.ir_tiles(), state);
@@ -934,6 +935,7 @@ FieldsItem fields_item(const mhs_plan *p, const mhs_model *model, const double *
     fi.tile_base = 0;
     fi.gate = nullptr;
     fi.gate_odd = -1;
+    fi.gate_min = 0;
     return fi;
 }
 
@@ -1018,7 +1020,7 @@ hipError_t exec_launch(const Launch &L, hipStream_t s)
     case Launch::kProlong3Z:
         return launch_prolong3_z((const LevelItem *)L.items, L.nitems, L.ntiles, L.dbl, s);
     case Launch::kIr3:
-        return launch_ir3((const LevelItem *)L.items, L.nitems, L.ntiles, L.flags != 0, s);
+        return launch_ir3((const LevelItem *)L.items, L.nitems, L.ntiles, (L.flags & 1) != 0, (L.flags & 2) != 0, s);
     case Launch::kBottom:
         return launch_bottom((const BottomItem *)L.items, L.nitems, L.lds, L.dbl, s);
     case Launch::kFinalize:
@@ -1627,6 +1629,10 @@ int solve_interior_on(mhs_plan *p, const mhs_model *model, double *d_P, const mh
     // same count ends in P with no copy
     const int hint = mixed ? hint_of(p, kSolve3DMixed, o) : 0;
     const bool swap = mixed && !o->warm_start && (hint & 1);
+    // mixed cold start: no interior is zeroed; the first two refinement
+    // steps read the start iterate's interior as zero (its boundary nodes
+    // only), and a solve that stops at step 0 zeroes P's interior after
+    const bool keep = mixed && !o->warm_start;
     PrepItem pi{};
     pi.P = d_P;
     pi.twin = T0;
@@ -1636,8 +1642,13 @@ int solve_interior_on(mhs_plan *p, const mhs_model *model, double *d_P, const mh
     pi.warm = o->warm_start;
     pi.faces = o->faces;
     pi.swap = swap ? 1 : 0;
+    pi.keep = keep ? 1 : 0;
     pi.n = N;
     const PrepItem *d_prep = p->stage.put(pi);
+    PrepItem pz = pi; // P's interior zeroed, faces as above
+    pz.swap = 0;
+    pz.keep = 0;
+    const PrepItem *d_zero = keep ? p->stage.put(pz) : nullptr;
     SolveState fin{};
     int syncs = 0;
     int inner_total = 0;
@@ -1647,12 +1658,13 @@ int solve_interior_on(mhs_plan *p, const mhs_model *model, double *d_P, const mh
     const FieldsItem *d_fgated = nullptr, *d_fplain = nullptr;
     FieldsItem fitem{};
     bool fields_done = false;
-    auto stage_fields_pair = [&](const SolveState *gate, int gate_odd) -> int {
+    auto stage_fields_pair = [&](const SolveState *gate, int gate_odd, int gate_min) -> int {
         int e = stage_fields(p, fr->model, d_P, fr->Bx, fr->By, fr->Bz, fr->p, fr->rho, &d_fplain, &fitem);
         if (e) return e;
         FieldsItem g = fitem;
         g.gate = gate;
         g.gate_odd = gate_odd;
+        g.gate_min = gate_min;
         d_fgated = p->stage.put(g);
         return d_fgated ? MHS_OK : fail(MHS_ERR_WORKSPACE, "staging area exhausted");
     };
@@ -1676,7 +1688,7 @@ int solve_interior_on(mhs_plan *p, const mhs_model *model, double *d_P, const mh
             cyc.launches.push_back(c);
         }
         if (!cyc.ok || !d_state || !d_prep) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
-        if (fr && (st = stage_fields_pair(d_state, -1))) return st;
+        if (fr && (st = stage_fields_pair(d_state, -1, 0))) return st;
         if ((st = flush_staging(p, s))) return st;
         HIPCHK(launch_prep3(d_prep, 1, prep3_threads(N), s));
         if ((st = drive_programs(
@@ -1703,22 +1715,26 @@ int solve_interior_on(mhs_plan *p, const mhs_model *model, double *d_P, const mh
             void *bb = (a == l0.u[kF32]) ? l0.t[kF32] : l0.u[kF32];
             ebuf = add_cycle(inner, p->stage, h, kF32, a, bb, r32, c == 0, false, o->nu1, o->nu2, d_state);
         }
-        Program first, odd, even;
-        add_ir_step(first, p->stage, h, U, nullptr, nullptr, r32, d_state);
+        Program first, second, odd, even;
+        add_ir_step(first, p->stage, h, U, nullptr, nullptr, r32, d_state, keep);
+        if (keep) add_ir_step(second, p->stage, h, U, V, ebuf, r32, d_state, true);
         add_ir_step(odd, p->stage, h, U, V, ebuf, r32, d_state);
         add_ir_step(even, p->stage, h, V, U, ebuf, r32, d_state);
-        for (Program *pg : {&first, &odd, &even})
-            pg->launches.insert(pg->launches.end(), inner.launches.begin(), inner.launches.end());
-        if (!first.ok || !odd.ok || !even.ok || !inner.ok || !d_state || !d_prep)
+        for (Program *pg : {&first, &second, &odd, &even})
+            if (pg != &second || keep) pg->launches.insert(pg->launches.end(), inner.launches.begin(), inner.launches.end());
+        if (!first.ok || !second.ok || !odd.ok || !even.ok || !inner.ok || !d_state || !d_prep || (keep && !d_zero))
             return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
-        // P holds the iterate after an odd count with swap, an even one without
-        if (fr && (st = stage_fields_pair(d_state, swap ? 1 : 0))) return st;
+        // P holds the iterate after an odd count with swap, an even one
+        // without (after a cold start, from step 1 on)
+        if (fr && (st = stage_fields_pair(d_state, swap ? 1 : 0, keep ? 1 : 0))) return st;
         if ((st = flush_staging(p, s))) return st;
         HIPCHK(launch_prep3(d_prep, 1, prep3_threads(N), s));
         SolveState ss{};
         if ((st = drive_programs(
                  p,
-                 [&](int step) -> const Program & { return step == 0 ? first : ((step & 1) ? odd : even); },
+                 [&](int step) -> const Program & {
+                     return step == 0 ? first : (step == 1 && keep) ? second : ((step & 1) ? odd : even);
+                 },
                  d_state, o, hint, &ss, &syncs, s, nullptr, fr ? &gated_fields : nullptr)))
             return st;
         fin = ss;
@@ -1728,8 +1744,11 @@ int solve_interior_on(mhs_plan *p, const mhs_model *model, double *d_P, const mh
         inner_total = steps * o->inner_cycles;
         // the iterate ends in V after an odd step count, else in U; when
         // that is the twin, the copy is stream-ordered like the rest of the
-        // solve's work
-        if (((steps & 1) ? V : U) == T0)
+        // solve's work.  A cold start stopped at step 0 never wrote an
+        // interior: P's is zeroed.
+        if (keep && steps == 0)
+            HIPCHK(launch_prep3(d_zero, 1, prep3_threads(N), s));
+        else if (((steps & 1) ? V : U) == T0)
             HIPCHK(launch_copy(T0, d_P, N, nullptr, s));
         else
             fields_done = true;

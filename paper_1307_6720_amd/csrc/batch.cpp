@@ -252,6 +252,9 @@ bool build_slot(const Slot &S, int i, SolveState *state, Staging &R, std::vector
             pi.warm = o.warm_start;
             pi.faces = o.faces;
             pi.swap = S.swap ? 1 : 0;
+            // a mixed cold start zeroes no interior (its first two steps
+            // read the start iterate's interior as zero)
+            pi.keep = (o.precision == MHS_PREC_MIXED && !o.warm_start) ? 1 : 0;
             pi.n = N;
             const PrepItem *d = R.put(pi);
             if (!d) return false;
@@ -293,7 +296,7 @@ bool build_slot(const Slot &S, int i, SolveState *state, Staging &R, std::vector
         const double *uin = (s == 0 || (s & 1)) ? U : V;
         double *uout = s == 0 ? nullptr : ((s & 1) ? V : U);
         Program ir;
-        add_ir_step(ir, R, h, uin, uout, s == 0 ? nullptr : ebuf, r32, state);
+        add_ir_step(ir, R, h, uin, uout, s == 0 ? nullptr : ebuf, r32, state, s <= 1 && !o.warm_start);
         if (!ir.ok || ir.launches.size() != 2) return false;
         tag_one(ir.launches[0], key_of(0, kPrologue, 1), i, out);
         tag_one(ir.launches[1], key_of(0, kPrologue, 2), i, out);
@@ -305,8 +308,25 @@ bool build_slot(const Slot &S, int i, SolveState *state, Staging &R, std::vector
     }
     if (S.phase == kFinish) {
         const int64_t N = (int64_t)p->h3.lv[0].N;
-        // the iterate ends in V after an odd step count, else in U
-        if (o.precision == MHS_PREC_MIXED && ((S.info[1].cycles & 1) != (S.swap ? 1 : 0))) {
+        // the iterate ends in V after an odd step count, else in U; a cold
+        // start that stopped at step 0 never wrote an interior: P's is zeroed
+        if (o.precision == MHS_PREC_MIXED && !o.warm_start && S.info[1].cycles == 0) {
+            PrepItem pi{};
+            pi.P = S.P;
+            pi.twin = (double *)p->h3.lv[0].t[kF64];
+            pi.nx = p->grid.nx;
+            pi.ny = p->grid.ny;
+            pi.nz = p->grid.nz;
+            pi.faces = o.faces;
+            pi.n = N;
+            const PrepItem *d = R.put(pi);
+            if (!d) return false;
+            Launch L{};
+            L.kind = Launch::kPrep3;
+            L.items = d;
+            L.n = prep3_threads(N);
+            tag_one(L, key_of(0, kPrologue, 0), i, out);
+        } else if (o.precision == MHS_PREC_MIXED && ((S.info[1].cycles & 1) != (S.swap ? 1 : 0))) {
             Launch c{};
             c.kind = Launch::kCopy;
             c.src = (const double *)p->h3.lv[0].t[kF64];

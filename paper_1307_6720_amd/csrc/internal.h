@@ -162,7 +162,7 @@ struct FieldsItem {
     // this solve has converged with P holding its iterate (null: always)
     const SolveState *gate;
     int32_t gate_odd; // -1: P always holds it; 0/1: only after an even/odd count of cycles
-    int32_t pad;
+    int32_t gate_min; // and only after at least this many cycles
 };
 
 // Diagnostics of an equilibrium (current density, force-balance and
@@ -201,6 +201,8 @@ struct PrepItem {
     int32_t warm;
     int32_t faces;      // 1: keep P's faces (2D: edges) as Dirichlet data
     int32_t swap;       // 3D: the zero interior goes to the twin, P's interior is left as it is
+    int32_t keep;       // 3D: no interior is written (the solve's first steps read it as zero)
+    int32_t pad;
     int64_t n;          // points covered
     int64_t base;       // first global thread of this item
 };
@@ -232,7 +234,9 @@ hipError_t launch_restrict2(const LevelItem *items, int nitems, int ntiles, bool
 // steps that keep x and y: one thread per node (ntiles = ceil(nodes / kThreads))
 hipError_t launch_restrict3_z(const LevelItem *items, int nitems, int ntiles, bool has_f, bool dbl, hipStream_t s);
 hipError_t launch_prolong3_z(const LevelItem *items, int nitems, int ntiles, bool dbl, hipStream_t s);
-hipError_t launch_ir3(const LevelItem *items, int nitems, int ntiles, bool has_e, hipStream_t s);
+// zero_in: the iterate's interior is read as zero (a cold start's first two
+// refinement steps; only its boundary nodes are loaded)
+hipError_t launch_ir3(const LevelItem *items, int nitems, int ntiles, bool has_e, bool zero_in, hipStream_t s);
 hipError_t launch_bottom(const BottomItem *items, int nitems, int lds_bytes, bool dbl, hipStream_t s);
 hipError_t launch_finalize(const FinalizeItem *items, int nitems, hipStream_t s);
 hipError_t launch_fields(const FieldsItem *items, int nitems, int ntiles, hipStream_t s);

@@ -1230,7 +1230,7 @@ constexpr int kIWY = kTY + 2;
 constexpr int kICells = kIWX * kIWY;
 constexpr int kIPer = (kICells + kThreads - 1) / kThreads;
 
-template <bool HAS_E>
+template <bool HAS_E, bool ZERO_IN>
 __global__ __launch_bounds__(kThreads) void k_ir3(const LevelItem *__restrict__ items, int nitems)
 {
     constexpr int D = kDepth;
@@ -1304,13 +1304,17 @@ __global__ __launch_bounds__(kThreads) void k_ir3(const LevelItem *__restrict__ 
     double pre[D][kIPer];
     float epre[D][HAS_E ? kIPer : 1];
     // unconditional clamped loads; the correction is added and out-of-array
-    // cells are zeroed when the plane is staged
+    // cells are zeroed when the plane is staged.  ZERO_IN: interior nodes
+    // of the iterate take an offset at the end of the plane, where the
+    // buffer load returns +0.0 without touching memory (the value a zeroed
+    // interior holds), so only boundary nodes are read.
     auto fetch = [&](int p, double(&dst)[kIPer], float(&edst)[HAS_E ? kIPer : 1]) {
         const auto ru = plane_rsrc(uin + sxy * (size_t)p, 8u * plane_elems);
         const auto re = plane_rsrc(e32 + sxy * (size_t)p, 4u * plane_elems);
+        const uint32_t skip = (ZERO_IN && p >= 1 && p <= nz - 2) ? st_int : 0u;
 #pragma unroll
         for (int r = 0; r < kIPer; ++r) {
-            dst[r] = bload<double>(ru, 8u * st_g[r]);
+            dst[r] = bload<double>(ru, ((skip >> r) & 1) ? 8u * plane_elems : 8u * st_g[r]);
             if constexpr (HAS_E) edst[r] = bload<float>(re, 4u * st_g[r]);
         }
     };
@@ -1643,7 +1647,9 @@ __global__ __launch_bounds__(kFThreads) void k_fields(const FieldsItem *__restri
     const FieldsItem *it = items + find_item(items, nitems, tile);
     if (it->gate) {
         const auto *g = gin<SolveState>(it->gate);
-        if (g->done != kConverged || (it->gate_odd >= 0 && ((g->checks - 1) & 1) != it->gate_odd)) return;
+        const int cycles = g->checks - 1;
+        if (g->done != kConverged || cycles < it->gate_min || (it->gate_odd >= 0 && (cycles & 1) != it->gate_odd))
+            return;
     }
     const MHS_GLOBAL double *__restrict__ P = gin<double>(it->P);
     const int nx = it->nx, ny = it->ny, nz = it->nz;
@@ -2101,6 +2107,8 @@ __device__ __forceinline__ int find_prep(const Item *items, int n, int64_t g)
 // P = 0 in the interior (step 1 of the procedure) unless warm-started, and
 // the twin's faces equal P's faces.  With `swap` (cold starts only) the
 // solve starts from the twin: its interior is zeroed and P's is not touched.
+// With `keep` no interior is written: the refinement steps that read the
+// start iterate take its interior as zero.
 __global__ __launch_bounds__(256) void k_prep3(const PrepItem *__restrict__ items, int nitems)
 {
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -2126,6 +2134,8 @@ __global__ __launch_bounds__(256) void k_prep3(const PrepItem *__restrict__ item
         } else if (side || k == nz - 1) {
             if (!it.faces) it.P[e] = 0.0;
             if (it.twin) it.twin[e] = it.faces ? it.P[e] : 0.0;
+        } else if (it.keep) {
+            // read as zero by the solve's first steps
         } else if (it.swap) {
             it.twin[e] = 0.0;
         } else if (!it.warm) {
@@ -2299,14 +2309,18 @@ hipError_t launch_restrict2(const LevelItem *items, int nitems, int ntiles, bool
     return hipGetLastError();
 }
 
-hipError_t launch_ir3(const LevelItem *items, int nitems, int ntiles, bool has_e, hipStream_t s)
+hipError_t launch_ir3(const LevelItem *items, int nitems, int ntiles, bool has_e, bool zero_in, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
     dim3 grid(ntiles), block(kThreads);
-    if (has_e)
-        hipLaunchKernelGGL((k_ir3<true>), grid, block, 0, s, items, nitems);
+    if (has_e && zero_in)
+        hipLaunchKernelGGL((k_ir3<true, true>), grid, block, 0, s, items, nitems);
+    else if (has_e)
+        hipLaunchKernelGGL((k_ir3<true, false>), grid, block, 0, s, items, nitems);
+    else if (zero_in)
+        hipLaunchKernelGGL((k_ir3<false, true>), grid, block, 0, s, items, nitems);
     else
-        hipLaunchKernelGGL((k_ir3<false>), grid, block, 0, s, items, nitems);
+        hipLaunchKernelGGL((k_ir3<false, false>), grid, block, 0, s, items, nitems);
     return hipGetLastError();
 }
 

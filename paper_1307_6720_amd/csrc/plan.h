@@ -196,8 +196,9 @@ int status_of(int32_t done);
 void add_finalize(Program &pg, Staging &st, const double *partials, int n, SolveState *state);
 void *add_cycle(Program &pg, Staging &st, const Hierarchy &h, int path, void *a0, void *b0, const void *f0,
                 bool first_zero, bool first_norm, int nu1, int nu2, SolveState *state);
+// zero_in: uin's interior is read as zero (see launch_ir3)
 void add_ir_step(Program &pg, Staging &st, const Hierarchy &h, const double *uin, double *uout, const void *e,
-                 float *r32, SolveState *state);
+                 float *r32, SolveState *state, bool zero_in = false);
 FieldsItem fields_item(const mhs_plan *p, const mhs_model *model, const double *tab, const double *P, double *Bx,
                        double *By, double *Bz, double *pr, double *rho);
 hipError_t exec_launch(const Launch &L, hipStream_t s);

@@ -479,6 +479,47 @@ def test_equilibrium_call_when_the_count_differs_from_the_last():
         plan.close()
 
 
+@pytest.mark.parametrize("faces_given", [False, True])
+def test_mixed_cold_start_equals_warm_start_from_zero(faces_given):
+    """A cold mixed solve zeroes no interior: its first two refinement steps
+    load only the boundary nodes of the start iterate and take its interior
+    as zero.  Its result equals that of a warm start from an iterate whose
+    interior is zero (which reads every node), whatever the caller's P held
+    before; a cold solve that stops at step 0 (zero data) zeroes P's
+    interior itself."""
+    w = synth.workload("mhs-129", dims=(65, 65, 65))
+    bz = torch.from_numpy(w.bz0).to(DEV)
+    plan = Plan(w.grid, PREC_FP64 | PREC_MIXED, device=DEV)
+    try:
+        base = torch.zeros(w.grid.shape, dtype=torch.float64, device=DEV)
+        if faces_given:
+            gen = torch.Generator(device="cpu").manual_seed(5)
+            faces = torch.rand(w.grid.shape, generator=gen, dtype=torch.float64).to(DEV)
+            faces[1:-1, 1:-1, 1:-1] = 0.0
+            base.copy_(faces)
+        plan.solve_boundary(bz, base, make_opts(rtol=1e-10, faces_given=faces_given))
+        torch.cuda.synchronize()
+        warm = base.clone()
+        iw = plan.solve_interior(w.model, warm, make_opts(PREC_MIXED, rtol=1e-10, warm_start=True,
+                                                          faces_given=faces_given))
+        for rep in range(2):  # the second starts from the twin (odd or even count alike)
+            cold = base.clone()
+            cold[1:-1, 1:-1, 1:-1] = 5.0  # what the caller's P held: never read
+            ic = plan.solve_interior(w.model, cold, make_opts(PREC_MIXED, rtol=1e-10, faces_given=faces_given))
+            torch.cuda.synchronize()
+            assert ic.cycles == iw.cycles
+            assert torch.equal(cold, warm)
+        zero = torch.zeros_like(bz)
+        P = torch.full(w.grid.shape, 5.0, dtype=torch.float64, device=DEV)
+        plan.solve_boundary(zero, P, make_opts(rtol=1e-10))
+        i3 = plan.solve_interior(w.model, P, make_opts(PREC_MIXED, rtol=1e-10))
+        torch.cuda.synchronize()
+        assert i3.cycles == 0
+        assert bool((P == 0.0).all())
+    finally:
+        plan.close()
+
+
 def test_error_paths(plans):
     w = synth.workload("mhs-129", dims=(33, 33, 33))
     m = w.model
