@@ -1643,11 +1643,12 @@ int solve_interior_on(mhs_plan *p, const mhs_model *model, double *d_P, const mh
     pi.faces = o->faces;
     pi.swap = swap ? 1 : 0;
     pi.keep = keep ? 1 : 0;
-    pi.n = N;
+    pi.n = keep ? prep3_faces(pi.nx, pi.ny, pi.nz) : N;
     const PrepItem *d_prep = p->stage.put(pi);
     PrepItem pz = pi; // P's interior zeroed, faces as above
     pz.swap = 0;
     pz.keep = 0;
+    pz.n = N;
     const PrepItem *d_zero = keep ? p->stage.put(pz) : nullptr;
     SolveState fin{};
     int syncs = 0;
@@ -1690,7 +1691,7 @@ int solve_interior_on(mhs_plan *p, const mhs_model *model, double *d_P, const mh
         if (!cyc.ok || !d_state || !d_prep) return fail(MHS_ERR_WORKSPACE, "staging area exhausted");
         if (fr && (st = stage_fields_pair(d_state, -1, 0))) return st;
         if ((st = flush_staging(p, s))) return st;
-        HIPCHK(launch_prep3(d_prep, 1, prep3_threads(N), s));
+        HIPCHK(launch_prep3(d_prep, 1, prep3_threads(pi.n), s));
         if ((st = drive_programs(
                  p, [&](int) -> const Program & { return cyc; }, d_state, o, hint_of(p, kSolve3D64, o), &fin, &syncs,
                  s, nullptr, fr ? &gated_fields : nullptr)))
@@ -1728,7 +1729,7 @@ int solve_interior_on(mhs_plan *p, const mhs_model *model, double *d_P, const mh
         // without (after a cold start, from step 1 on)
         if (fr && (st = stage_fields_pair(d_state, swap ? 1 : 0, keep ? 1 : 0))) return st;
         if ((st = flush_staging(p, s))) return st;
-        HIPCHK(launch_prep3(d_prep, 1, prep3_threads(N), s));
+        HIPCHK(launch_prep3(d_prep, 1, prep3_threads(pi.n), s));
         SolveState ss{};
         if ((st = drive_programs(
                  p,

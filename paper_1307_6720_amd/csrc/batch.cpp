@@ -255,13 +255,13 @@ bool build_slot(const Slot &S, int i, SolveState *state, Staging &R, std::vector
             // a mixed cold start zeroes no interior (its first two steps
             // read the start iterate's interior as zero)
             pi.keep = (o.precision == MHS_PREC_MIXED && !o.warm_start) ? 1 : 0;
-            pi.n = N;
+            pi.n = pi.keep ? prep3_faces(pi.nx, pi.ny, pi.nz) : N;
             const PrepItem *d = R.put(pi);
             if (!d) return false;
             Launch L{};
             L.kind = Launch::kPrep3;
             L.items = d;
-            L.n = prep3_threads(N); // threads (base of the merged launch counts threads)
+            L.n = prep3_threads(pi.n); // threads (base of the merged launch counts threads)
             tag_one(L, key_of(0, kPrologue, 0), i, out);
         }
         if (o.precision == MHS_PREC_FP64) {

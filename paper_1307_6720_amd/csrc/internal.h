@@ -201,7 +201,8 @@ struct PrepItem {
     int32_t warm;
     int32_t faces;      // 1: keep P's faces (2D: edges) as Dirichlet data
     int32_t swap;       // 3D: the zero interior goes to the twin, P's interior is left as it is
-    int32_t keep;       // 3D: no interior is written (the solve's first steps read it as zero)
+    int32_t keep;       // 3D: no interior is written (the solve's first steps read it as zero);
+                        // the item covers the boundary nodes only (n = prep3_faces)
     int32_t pad;
     int64_t n;          // points covered
     int64_t base;       // first global thread of this item
@@ -245,6 +246,11 @@ hipError_t launch_trace(const TraceItem &item, hipStream_t s);
 // 3D preparation: nodes per thread, and the threads an item of n nodes takes
 constexpr int kPrepNodes = 4;
 inline int64_t prep3_threads(int64_t n) { return (n + kPrepNodes - 1) / kPrepNodes; }
+// boundary nodes of an nx x ny x nz grid (planes 0 and nz - 1, the rings between)
+inline int64_t prep3_faces(int nx, int ny, int nz)
+{
+    return 2 * (int64_t)nx * ny + (int64_t)(nz - 2) * (2 * (int64_t)nx + 2 * (int64_t)(ny - 2));
+}
 hipError_t launch_prep3(const PrepItem *items, int nitems, int64_t nthreads, hipStream_t s);
 hipError_t launch_prep2(const PrepItem *items, int nitems, int64_t nthreads, hipStream_t s);
 hipError_t launch_copy(const double *src, double *dst, int64_t n, const SolveState *skip,

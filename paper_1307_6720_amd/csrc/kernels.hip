@@ -2116,6 +2116,46 @@ __global__ __launch_bounds__(256) void k_prep3(const PrepItem *__restrict__ item
     const int64_t e0 = (g - it.base) * kPrepNodes;
     if (e0 >= it.n) return;
     const int nx = it.nx, ny = it.ny, nz = it.nz;
+    if (it.keep) {
+        // only the boundary nodes: planes 0 and nz - 1, then the ring of
+        // every plane between (rows j = 0 and ny - 1, columns i = 0 and
+        // nx - 1); it.n counts them
+        const uint32_t pl = (uint32_t)nx * (uint32_t)ny, ring = 2u * (uint32_t)nx + 2u * (uint32_t)(ny - 2);
+#pragma unroll
+        for (int q = 0; q < kPrepNodes; ++q) {
+            const int64_t fq = e0 + q;
+            if (fq >= it.n) break;
+            const uint32_t f = (uint32_t)fq;
+            int i, j, k;
+            if (f < 2u * pl) {
+                const uint32_t a = f < pl ? f : f - pl;
+                k = f < pl ? 0 : nz - 1;
+                j = (int)(a / (uint32_t)nx);
+                i = (int)(a - (uint32_t)j * (uint32_t)nx);
+            } else {
+                const uint32_t b = f - 2u * pl, kk = b / ring, r = b - kk * ring;
+                k = 1 + (int)kk;
+                if (r < 2u * (uint32_t)nx) {
+                    j = r < (uint32_t)nx ? 0 : ny - 1;
+                    i = (int)(r < (uint32_t)nx ? r : r - (uint32_t)nx);
+                } else {
+                    const uint32_t c = r - 2u * (uint32_t)nx;
+                    i = c < (uint32_t)(ny - 2) ? 0 : nx - 1;
+                    j = 1 + (int)(c < (uint32_t)(ny - 2) ? c : c - (uint32_t)(ny - 2));
+                }
+            }
+            const int64_t e = (int64_t)i + (int64_t)nx * ((int64_t)j + (int64_t)ny * k);
+            const bool side = (i == 0 || i == nx - 1 || j == 0 || j == ny - 1);
+            if (k == 0) {
+                if (side && !it.faces) it.P[e] = 0.0;
+                if (it.twin) it.twin[e] = (side && !it.faces) ? 0.0 : it.P[e];
+            } else {
+                if (!it.faces) it.P[e] = 0.0;
+                if (it.twin) it.twin[e] = it.faces ? it.P[e] : 0.0;
+            }
+        }
+        return;
+    }
     // kPrepNodes consecutive nodes per thread: the divisions for the first,
     // then stepping along x (32-bit index arithmetic: a plan's grids have
     // fewer than 2^31 nodes)
@@ -2134,8 +2174,6 @@ __global__ __launch_bounds__(256) void k_prep3(const PrepItem *__restrict__ item
         } else if (side || k == nz - 1) {
             if (!it.faces) it.P[e] = 0.0;
             if (it.twin) it.twin[e] = it.faces ? it.P[e] : 0.0;
-        } else if (it.keep) {
-            // read as zero by the solve's first steps
         } else if (it.swap) {
             it.twin[e] = 0.0;
         } else if (!it.warm) {
