@@ -350,30 +350,56 @@ int coarse_inverse(const Hierarchy &h, const std::vector<double> &coef, double c
 // Smallest eigenvalue of -[(1 - xi(z)) (d2x + d2y) + d2z] on the interior
 // unknowns of level l (the operator of (8) without the alpha^2 term).  The
 // operator separates: an in-plane sine mode of eigenvalue lam turns it into
-// the symmetric tridiagonal -d2z + lam diag(1 - xi_k), whose eigenvalues
+// the symmetric tridiagonal T = -d2z + lam diag(1 - xi_k), whose eigenvalues
 // grow with lam (1 - xi > 0), so the minimum sits at the smallest in-plane
-// eigenvalue.  That tridiagonal eigenvalue is bracketed with Sturm counts
-// (the number of negative pivots of T - x I), three points per pass.
-double level_lambda_min(const Hierarchy &h, int l, const double *xi, const double len[3])
-{
-    const Level &lv = h.lv[l];
-    auto lam1 = [](double hh, double length) {
-        const double s = std::sin(3.14159265358979323846 * hh / (2.0 * length));
-        return 4.0 / (hh * hh) * s * s;
-    };
-    const double lxy = lam1(lv.h[0], len[0]) + lam1(lv.h[1], len[1]);
-    const int m = lv.n[2] - 2;
-    const double iz2 = 1.0 / (lv.h[2] * lv.h[2]);
-    std::vector<double> a((size_t)m);
-    double hi = 0.0;
-    for (int q = 0; q < m; ++q) {
-        a[(size_t)q] = 2.0 * iz2 + (1.0 - xi[(size_t)(q + 1) << lv.zs]) * lxy;
-        hi = q == 0 ? a[0] : std::min(hi, a[(size_t)q]); // Rayleigh quotient of a unit vector
+// eigenvalue.  T = iz2 K + D with K = tridiag(-1, 2, -1) and D diagonal, so
+// Weyl's inequality puts its smallest eigenvalue at or above
+// iz2 mu1 + min D (mu1 = 4 sin^2(pi / (2 (m + 1))), the smallest of K), and
+// the Rayleigh quotient of K's first eigenvector at or below
+// iz2 mu1 + (its weighted mean of D): a bracket that is exact for constant
+// xi.  Passes of Sturm counts (the number of negative pivots of T - x I) at
+// three points narrow it by four; callers narrow it only as far as their
+// decisions need.
+struct LambdaBracket {
+    std::vector<double> a;
+    double b2 = 0.0, lo = 0.0, hi = 0.0;
+    int m = 0;
+    LambdaBracket(const Hierarchy &h, int l, const double *xi, const double len[3])
+    {
+        const Level &lv = h.lv[l];
+        auto lam1 = [](double hh, double length) {
+            const double s = std::sin(3.14159265358979323846 * hh / (2.0 * length));
+            return 4.0 / (hh * hh) * s * s;
+        };
+        const double lxy = lam1(lv.h[0], len[0]) + lam1(lv.h[1], len[1]);
+        m = lv.n[2] - 2;
+        const double iz2 = 1.0 / (lv.h[2] * lv.h[2]);
+        const double sk = std::sin(3.14159265358979323846 / (2.0 * (m + 1)));
+        const double base = iz2 * 4.0 * sk * sk;
+        a.resize((size_t)m);
+        double dmin = 0.0, amin = 0.0, wsum = 0.0, wd = 0.0;
+        for (int q = 0; q < m; ++q) {
+            const double d = (1.0 - xi[(size_t)(q + 1) << lv.zs]) * lxy;
+            a[(size_t)q] = 2.0 * iz2 + d;
+            dmin = q == 0 ? d : std::min(dmin, d);
+            amin = q == 0 ? a[0] : std::min(amin, a[(size_t)q]); // Rayleigh quotient of a unit vector
+            const double v = std::sin(3.14159265358979323846 * (q + 1) / (m + 1));
+            wsum += v * v;
+            wd += v * v * d;
+        }
+        b2 = iz2 * iz2;
+        // a relative margin of 1e-12 keeps the rounded bounds outside
+        lo = std::max(0.0, (base + dmin) * (1.0 - 1e-12));
+        hi = std::min(amin, (base + wd / wsum) * (1.0 + 1e-12));
+        if (!(hi > lo)) hi = lo * (1.0 + 1e-12) + 1e-300;
     }
-    const double b2 = iz2 * iz2;
-    // whether some eigenvalue lies below each of three points: three
-    // independent pivot recurrences in one pass, so their divisions overlap
-    auto below3 = [&](const double x[3], bool out[3]) {
+    bool fine() const { return !(hi - lo > 1e-14 * hi); }
+    // one pass: three pivot recurrences (their divisions overlap) decide in
+    // which quarter of [lo, hi] the smallest eigenvalue lies
+    void pass()
+    {
+        const double w = hi - lo;
+        const double x[3] = {lo + 0.25 * w, lo + 0.5 * w, lo + 0.75 * w};
         double d[3] = {1.0, 1.0, 1.0};
         int cnt[3] = {0, 0, 0};
         for (int q = 0; q < m; ++q) {
@@ -384,29 +410,30 @@ double level_lambda_min(const Hierarchy &h, int l, const double *xi, const doubl
                 d[c] = v;
             }
         }
-        for (int c = 0; c < 3; ++c) out[c] = cnt[c] >= 1;
-    };
-    // quartersection of [lo, hi]: the smallest eigenvalue stays in it, lo
-    // below it, until the bracket is 1e-14 of hi wide
-    double lo = 0.0;
-    for (int it = 0; it < 100 && hi - lo > 1e-14 * hi; ++it) {
-        const double w = hi - lo;
-        const double x[3] = {lo + 0.25 * w, lo + 0.5 * w, lo + 0.75 * w};
-        bool b[3];
-        below3(x, b);
-        if (b[0]) {
+        if (cnt[0] >= 1) {
             hi = x[0];
-        } else if (b[1]) {
+        } else if (cnt[1] >= 1) {
             lo = x[0];
             hi = x[1];
-        } else if (b[2]) {
+        } else if (cnt[2] >= 1) {
             lo = x[1];
             hi = x[2];
         } else {
             lo = x[2];
         }
     }
-    return lo;
+    // narrowed to 1e-14 of hi: lo is then the smallest eigenvalue
+    double value()
+    {
+        for (int it = 0; it < 100 && !fine(); ++it) pass();
+        return lo;
+    }
+};
+
+double level_lambda_min(const Hierarchy &h, int l, const double *xi, const double len[3])
+{
+    LambdaBracket b(h, l, xi, len);
+    return b.value();
 }
 
 // Use levels 0..L-1 of a hierarchy: the bottom solver starts at the first
@@ -451,17 +478,37 @@ int model_depth(const Hierarchy &h, const mhs_grid &g, const mhs_model *model, i
 {
     const double len[3] = {g.lx, g.ly, g.lz};
     const double a2 = model->alpha * model->alpha;
+    // each comparison narrows the brackets until it is decided by them, or
+    // both are at 1e-14 width and their lower ends decide it
+    LambdaBracket b0(h, 0, model->xi, len);
+    if (lambda0) *lambda0 = b0.value();
+    while (!(b0.lo > a2) && !(b0.hi <= a2) && !b0.fine()) b0.pass();
+    if (!(a2 < b0.lo))
+        return fail(MHS_ERR_INDEFINITE, "alpha^2 = %g is not below the smallest eigenvalue %g of (8) on the grid", a2,
+                    b0.value());
     int L = h.Lgeo;
-    double gap0 = 0.0;
-    for (int l = 0; l < h.Lgeo; ++l) {
-        const double lmin = level_lambda_min(h, l, model->xi, len);
-        if (l == 0) {
-            if (lambda0) *lambda0 = lmin;
-            if (!(a2 < lmin))
-                return fail(MHS_ERR_INDEFINITE, "alpha^2 = %g is not below the smallest eigenvalue %g of (8) on the grid",
-                            a2, lmin);
-            gap0 = lmin - a2;
-        } else if (!(lmin - a2 >= kResonanceRatio * gap0)) {
+    for (int l = 1; l < h.Lgeo; ++l) {
+        LambdaBracket bl(h, l, model->xi, len);
+        bool stop;
+        for (;;) {
+            if (bl.lo - a2 >= kResonanceRatio * (b0.hi - a2)) {
+                stop = false;
+                break;
+            }
+            if (bl.hi - a2 < kResonanceRatio * (b0.lo - a2)) {
+                stop = true;
+                break;
+            }
+            if (bl.fine() && b0.fine()) {
+                stop = !(bl.lo - a2 >= kResonanceRatio * (b0.lo - a2));
+                break;
+            }
+            if (!bl.fine() && (b0.fine() || (bl.hi - bl.lo) / bl.hi >= (b0.hi - b0.lo) / b0.hi))
+                bl.pass();
+            else
+                b0.pass();
+        }
+        if (stop) {
             L = l;
             break;
         }
