@@ -72,6 +72,53 @@ def test_model_check_matches_oracle_eigenvalues(name):
     assert depth >= 2
 
 
+def test_model_check_decisions_near_their_thresholds():
+    """The host narrows each level's eigenvalue bracket only as far as its
+    comparison needs; its decisions must be those of the exact eigenvalues
+    (oracle) also where alpha^2 sits just inside or outside a threshold:
+    definiteness (alpha^2 against lambda_0) and the resonance rule
+    (lambda_l - alpha^2 against half of lambda_0 - alpha^2), for constant,
+    exponential and random xi profiles."""
+    rng = np.random.default_rng(11)
+    for n in (17, 33):
+        grid = synth.make_grid(n)
+        z = np.linspace(0.0, 1.0, n)
+        for t in range(6):
+            kind = t % 3
+            if kind == 0:
+                xi = np.full(n, rng.uniform(0.0, 0.95))
+            elif kind == 1:
+                xi = rng.uniform(0.0, 0.95) * np.exp(-z / rng.uniform(0.1, 1.0))
+            else:
+                xi = rng.uniform(0.0, 0.95, n)
+            lv = _levels(grid, xi)
+            a2s = [0.0, lv[0] * (1 - 1e-7), lv[0] * (1 + 1e-7)]
+            for l in range(1, len(lv)):
+                t2 = 2 * lv[l] - lv[0]  # lambda_l - a2 = (lambda_0 - a2) / 2
+                if t2 > 0:
+                    a2s += [t2 * (1 - 1e-7), t2 * (1 + 1e-7)]
+            for a2 in a2s:
+                m = synth.Model(np.sqrt(a2), xi, np.zeros(n), np.ones(n), np.ones(n))
+                if not a2 < lv[0]:
+                    with pytest.raises(_lib.MHSError) as e:
+                        check_model(grid, m)
+                    assert e.value.code == _lib.ERR_INDEFINITE
+                    continue
+                want = next((l for l, x in enumerate(lv) if l and x - a2 < 0.5 * (lv[0] - a2)), len(lv))
+                # the coarsest grid kept must have at most as many unknowns
+                # as the largest level of at most 512 (its dense inverse)
+                sizes = [((n - 1) // 2 ** l - 1) ** 3 for l in range(len(lv))]
+                cap = max(u for u in sizes[1:] if u <= 512)
+                if want < 2 or sizes[want - 1] > cap:
+                    with pytest.raises(_lib.MHSError) as e:
+                        check_model(grid, m)
+                    assert e.value.code == _lib.ERR_INDEFINITE
+                    continue
+                lam, depth = check_model(grid, m)
+                assert depth == want, (n, kind, a2)
+                assert abs(lam - lv[0]) <= 1e-12 * lv[0]
+
+
 def test_model_check_errors():
     w = synth.paper_workload("paper-xi1")
     m = w.model
